@@ -1,0 +1,28 @@
+"""Shared test helpers: turn a workload description into oracle objects."""
+import numpy as np
+
+import oracle
+from workloads import Workload
+
+
+def oracle_lattice(w: Workload) -> "oracle.Lattice":
+    return oracle.Lattice(w.L, w.cell, w.frac, w.periodic, w.mu)
+
+
+def oracle_model(w: Workload) -> "oracle.Model":
+    lat = oracle_lattice(w)
+    K = None
+    if w.K != 0.0:
+        K = np.full((w.n_sub, 1), w.K)
+        Kax = np.tile(np.asarray(w.K_axis, np.float64), (w.n_sub, 1))
+    else:
+        Kax = None
+    return oracle.Model(lat, n_shells=w.n_shells, J_shell=w.J_shell, D_shell=w.D_shell, K=K,
+                        K_axis=Kax, B=w.B, dipolar=w.dipolar)
+
+
+def max_rel(a, b):
+    """max |a - b| / max |b| over all elements."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

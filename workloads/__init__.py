@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs and workload descriptions.
+
+This module holds no arithmetic of the method: it only draws the initial spin
+states (NumPy PCG64 streams) and lists the lattice/model parameters of the
+benchmark workloads as plain data.  Both the HIP path's tests and the oracle's
+tests take their inputs from here, so that the two sides see identical bits.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+
+# ---------------------------------------------------------------- spin states
+def random_sphere(N: int, seed: int) -> np.ndarray:
+    """Uniform random unit vectors, shape (3, N): z ~ U[-1,1], phi ~ U[0,2pi)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    z = g.uniform(-1.0, 1.0, N)
+    phi = g.uniform(0.0, 2.0 * np.pi, N)
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return np.ascontiguousarray(np.stack([r * np.cos(phi), r * np.sin(phi), z]))
+
+
+def fm_tilt(N: int, seed: int, eps: float = 0.1) -> np.ndarray:
+    """Ferromagnet along +z plus a seeded Gaussian tilt: (eps gx, eps gy, 1)/norm."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    gx = g.standard_normal(N)
+    gy = g.standard_normal(N)
+    v = np.stack([eps * gx, eps * gy, np.ones(N)])
+    return np.ascontiguousarray(v / np.sqrt((v * v).sum(0)))
+
+
+def uniform_state(N: int, direction=(0.0, 0.0, 1.0)) -> np.ndarray:
+    d = np.asarray(direction, np.float64)
+    d = d / np.linalg.norm(d)
+    return np.ascontiguousarray(np.repeat(d[:, None], N, axis=1))
+
+
+def hopfion_texture(L: Sequence[int], R0: Optional[float] = None, width: Optional[float] = None,
+                    center_offset=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Toroidal Hopf-map-like seed texture of Hopf index 1 on an L^3 simple
+    cubic grid, shape (3, N).  The core circle of radius R0 (default L/6) lies
+    in the xy plane through the centre; rho is the distance to that circle,
+    Theta = pi * max(0, 1 - rho/width) (width defaults to R0),
+    Phi = azimuth + poloidal angle; spins far from the torus point along +z."""
+    Lx, Ly, Lz = (int(v) for v in L)
+    R0 = float(min(Lx, Ly, Lz)) / 6.0 if R0 is None else float(R0)
+    w = R0 if width is None else float(width)
+    cx = (Lx - 1) / 2.0 + center_offset[0]
+    cy = (Ly - 1) / 2.0 + center_offset[1]
+    cz = (Lz - 1) / 2.0 + center_offset[2]
+    z, y, x = np.meshgrid(np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    X, Y, Z = x - cx, y - cy, z - cz
+    rxy = np.sqrt(X * X + Y * Y)
+    rho = np.sqrt((rxy - R0) ** 2 + Z * Z)
+    theta = np.pi * np.clip(1.0 - rho / w, 0.0, 1.0)
+    phi = np.arctan2(Y, X) + np.arctan2(Z, rxy - R0)
+    S = np.stack([np.cos(phi) * np.sin(theta), np.sin(phi) * np.sin(theta), np.cos(theta)])
+    return np.ascontiguousarray(S.reshape(3, -1))
+
+
+# ---------------------------------------------------------------- workloads
+SC_CELL = ((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0))
+
+
+@dataclass
+class Workload:
+    """Lattice + Hamiltonian + dynamics parameters of one benchmark case."""
+    name: str
+    L: tuple
+    n_sub: int = 1
+    frac: tuple = ((0.0, 0.0, 0.0),)
+    cell: tuple = SC_CELL
+    periodic: tuple = (1, 1, 1)
+    mu: tuple = (1.0,)
+    J_shell: tuple = (1.0,)
+    D_shell: Optional[tuple] = None
+    K: float = 0.0
+    K_axis: tuple = (0.0, 0.0, 1.0)
+    B: tuple = (0.0, 0.0, 0.0)
+    dipolar: int = 0
+    alpha: float = 0.1
+    dt_fs: float = 0.1
+    T_K: float = 0.0
+    n_steps: int = 100
+    init: str = "random"
+    init_seed: int = 1
+    philox_seed: int = 1001
+    field_prec: str = "fp64"
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return int(self.n_sub * self.L[0] * self.L[1] * self.L[2])
+
+    @property
+    def n_shells(self) -> int:
+        return len(self.J_shell)
+
+    def initial_state(self) -> np.ndarray:
+        if self.init == "random":
+            return random_sphere(self.N, self.init_seed)
+        if self.init == "fm_tilt":
+            return fm_tilt(self.N, self.init_seed)
+        if self.init == "fm":
+            return uniform_state(self.N)
+        raise ValueError(self.init)
+
+    def scaled(self, L) -> "Workload":
+        """Same physics on a different lattice size (parity-test sizes)."""
+        d = dict(self.__dict__)
+        d["L"] = tuple(int(v) for v in L)
+        return Workload(**d)
+
+
+def sc_nn_fp64(L=(32, 32, 32)) -> Workload:
+    """sc 32^3, NN J = 1 meV, K = 0.1 meV along z, deterministic Heun,
+    alpha 0.1, dt 0.1 fs, 100 steps, FP64 throughout."""
+    return Workload(name="sc32_nn_fp64_heun", L=L, J_shell=(1.0,), K=0.1, alpha=0.1, dt_fs=0.1,
+                    T_K=0.0, n_steps=100, init="random", init_seed=1, philox_seed=1001,
+                    field_prec="fp64")
+
+
+BCC_FRAC = ((0.0, 0.0, 0.0), (0.5, 0.5, 0.5))
+
+
+def bcc_5shell_stochastic(L=(128, 128, 128)) -> Workload:
+    """bcc as two sublattices, shells 1-5 J = 1.33, 0.75, -0.05, -0.10, 0.07
+    meV, K = 0.005 meV along z, FM + tilt start, stochastic Heun at 300 K,
+    alpha 0.05, dt 0.1 fs, FP32 field / FP64 state, 1000 steps."""
+    return Workload(name="bcc128_5shell_stochastic_mixed", L=L, n_sub=2, frac=BCC_FRAC,
+                    mu=(1.0, 1.0), J_shell=(1.33, 0.75, -0.05, -0.10, 0.07), K=0.005,
+                    alpha=0.05, dt_fs=0.1, T_K=300.0, n_steps=1000, init="fm_tilt",
+                    init_seed=2, philox_seed=1002, field_prec="fp32")
+
+
+def sc_chiral_dipolar(L=(256, 256, 256)) -> Workload:
+    """sc 256^3 chiral magnet, a = 0.4 nm, mu = 2, J = 1 meV, bulk DMI 0.3 meV
+    along bonds, B = 0.5 T along z, open boundaries, dipolar via zero-padded FFT."""
+    a = 0.4
+    return Workload(name="sc256_chiral_dipolar_field", L=L, cell=((a, 0, 0), (0, a, 0), (0, 0, a)),
+                    periodic=(0, 0, 0), mu=(2.0,), J_shell=(1.0,), D_shell=(0.3,),
+                    B=(0.0, 0.0, 0.5), dipolar=1, init="random", init_seed=3, philox_seed=1003,
+                    field_prec="fp32")
+
+
+def sc_billion(L=(1024, 1024, 1024)) -> Workload:
+    """sc 1024^3, J = 1 meV NN, K = 0.1 meV, stochastic Heun at 50 K, alpha 0.1,
+    dt 0.1 fs, 100 steps, FP64 state with FP32 field."""
+    return Workload(name="sc1024_nn_stochastic_mixed", L=L, J_shell=(1.0,), K=0.1, alpha=0.1,
+                    dt_fs=0.1, T_K=50.0, n_steps=100, init="random", init_seed=4,
+                    philox_seed=1004, field_prec="fp32")
+
+
+def sc_frustrated_gneb(L=(48, 48, 48), shells="paper4") -> Workload:
+    """Frustrated sc exchange for the hopfion GNEB workload, open boundaries.
+    shells='config3': J1 = 1.0, J2 = -0.164, J3 = -0.082 meV;
+    shells='paper4': J1 = 1 meV with the four-shell ratios 0.188, -0.274, -0.161."""
+    J = (1.0, -0.164, -0.082) if shells == "config3" else (1.0, 0.188, -0.274, -0.161)
+    return Workload(name="sc_frustrated_gneb", L=L, periodic=(0, 0, 0), J_shell=J,
+                    init="hopfion", init_seed=5, field_prec="fp64")
+
+
+WORKLOADS = {
+    "sc32_nn_fp64_heun": sc_nn_fp64,
+    "bcc128_5shell_stochastic_mixed": bcc_5shell_stochastic,
+    "sc256_chiral_dipolar_field": sc_chiral_dipolar,
+    "sc1024_nn_stochastic_mixed": sc_billion,
+    "sc_frustrated_gneb": sc_frustrated_gneb,
+}
