@@ -1,0 +1,197 @@
+/*
+ * spx.h -- C ABI of the MI355X-native spin-field / LLG-Heun / GNEB library
+ * (libspx.so), implementing the hot path of the atomistic spin method of
+ * arXiv 2605.26016 ("SpinX").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function is extern "C", never throws and returns an spx_status.
+ *    On a non-OK status spx_last_error() returns a thread-local message.
+ *  - Pointers marked [dev] are device pointers (e.g. torch.Tensor.data_ptr()
+ *    of a CUDA/HIP tensor); pointers marked [host] are host memory, read only
+ *    during the call.  The caller owns every [dev] buffer it passes in and
+ *    keeps it alive until the stream has reached the enqueued work.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it; no call synchronises the device unless its
+ *    comment says so.
+ *  - Spin states are structure-of-arrays FP64 planes S[3][N] (x plane, then
+ *    y, then z), one unit vector per site.  The site index is
+ *        i = x + Lx * (y + Ly * (z + Lz * a)),
+ *    a = sublattice, (x, y, z) = unit cell (Methods, sublattice channels
+ *    S_a(R)).  N = n_sub * Lx * Ly * Lz; 64-bit indexing throughout.
+ *  - Units: spins dimensionless, reduced fields b and energies in meV,
+ *    external field in tesla, time step in fs, temperature in K, lengths in nm,
+ *    moments mu in Bohr magnetons (Methods, moment and unit conventions).
+ *  - Argument errors are reported synchronously.  A device fault raised by
+ *    earlier work surfaces at a later call as SPX_ERR_HIP.
+ *  - A handle is used from one host thread at a time.  Results are
+ *    deterministic for given inputs and seed: no atomics feed any result.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPX_ABI_VERSION 1
+
+typedef enum {
+    SPX_OK = 0,
+    SPX_ERR_INVALID_ARG = 1,   /* bad descriptor, size or pointer */
+    SPX_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
+    SPX_ERR_OUT_OF_MEMORY = 3, /* device allocation failed */
+    SPX_ERR_HIP = 4,           /* HIP runtime error (incl. faults of earlier work) */
+    SPX_ERR_FFT = 5,           /* hipFFT error */
+    SPX_ERR_BAD_HANDLE = 6     /* NULL, destroyed or foreign handle */
+} spx_status;
+
+/* Precision of the short-range field evaluation.  The spin state, the Heun
+ * integration and every reduction stay FP64 in all modes (Methods, mixed
+ * precision: fp32 field, fp64 state). */
+typedef enum {
+    SPX_FP64 = 0,      /* FP64 neighbours, couplings and accumulation; b is double */
+    SPX_FP32 = 1,      /* neighbours rounded to FP32, FP32 couplings and accumulation; b is float */
+    SPX_BF16_MFMA = 2, /* dense-window MFMA: BF16 operands, FP32 accumulation; b is float */
+    SPX_FP16_MFMA = 3  /* dense-window MFMA: FP16 operands, FP32 accumulation; b is float */
+} spx_precision;
+
+typedef struct spx_ham spx_ham;   /* opaque Hamiltonian + workspace */
+typedef struct spx_gneb spx_gneb; /* opaque batched GNEB object */
+
+/* Lattice: n_sub sublattices at fractional positions in a Bravais cell,
+ * dims[k] cells along lattice vector k, periodic[k] = 1 wraps that axis,
+ * 0 leaves it open (missing neighbours contribute nothing: the truncation
+ * rule for finite supercells, Methods, backend representations). */
+typedef struct {
+    int32_t n_sub;
+    int32_t dims[3];
+    int32_t periodic[3];
+    double cell[9];          /* [host] lattice vectors as rows, nm */
+    const double *sub_frac;  /* [host] [n_sub][3] fractional positions */
+    const double *mu;        /* [host] [n_sub] moment magnitudes, mu_B */
+} spx_lattice_desc;
+
+/* Hamiltonian H = H_bil + H_Z + H_ani + H_dip (Methods, total Hamiltonian).
+ * Bilinear couplings come either from shells or from an explicit bond list:
+ *  - shells: neighbour distances over all sublattice pairs, ascending, equal
+ *    within 1e-9 of the longest lattice vector, form shells 1..n_shells;
+ *    each directed bond of shell s gets J_ij = J_shell[s] I + [D]_x with
+ *    D_ij = D_shell[s] * (r_j - r_i)/|r_j - r_i| (D_shell may be NULL), the
+ *    antisymmetric DMI matrix of the Methods' bilinear tensor;
+ *  - bonds (n_bonds > 0 overrides shells): directed bonds a <- b at cell
+ *    offset delta with a full 3x3 row-major tensor J^{ab}(delta) in meV, used
+ *    as b_a(R) += J S_b(R + delta).  The caller supplies both directions
+ *    (J_ji = J_ij^T) if the pair energy is to be symmetric.
+ * Anisotropy: n_aniso axes per sublattice, H = -sum K (S.n)^2.
+ * Zeeman: H = -sum mu mu_B B.S.  Dipolar (dipolar = 1): open-boundary
+ * H_dip = -(mu0/4pi) mu_B^2 sum_{i<j} mu_i mu_j [3(S_i.r)(S_j.r) - S_i.S_j]/r^3
+ * evaluated by zero-padded FFT; needs n_sub = 1 and all axes open. */
+typedef struct {
+    int32_t n_shells;
+    const double *J_shell;     /* [host] [n_shells] meV */
+    const double *D_shell;     /* [host] [n_shells] meV, or NULL */
+    int32_t n_bonds;
+    const int32_t *bond_ab;    /* [host] [n_bonds][2] target a, source b */
+    const int32_t *bond_delta; /* [host] [n_bonds][3] cell offset */
+    const double *bond_J;      /* [host] [n_bonds][9] meV */
+    int32_t n_aniso;
+    const double *K;           /* [host] [n_sub][n_aniso] meV */
+    const double *K_axis;      /* [host] [n_sub][n_aniso][3] unit vectors */
+    double B_ext[3];           /* tesla */
+    int32_t dipolar;           /* 0 off, 1 on */
+} spx_model_desc;
+
+/* backend: 0 auto, 1 sparse stencil, 2 dense-window MFMA (needs a BF16/FP16
+ * field_prec).  autotune: 0 off, 1 time candidate launch shapes at setup and
+ * keep the fastest (cached per shape key in tune_cache_path if non-NULL). */
+typedef struct {
+    int32_t field_prec;        /* spx_precision */
+    int32_t backend;
+    int32_t autotune;
+    const char *tune_cache_path;
+} spx_options;
+
+/* Build the kernel tables (directed bonds grouped per target sublattice, see
+ * the Methods' sublattice convolution b_a(R) = sum_b sum_delta K_ab(delta)
+ * S_b(R + delta)), allocate the library-owned workspace (Heun predictor and
+ * ping-pong states, reduction scratch, dipolar FFT plans and the dipole
+ * spectrum) and return a handle.  Synchronous.  Errors: INVALID_ARG for bad
+ * descriptors, OUT_OF_MEMORY, UNSUPPORTED for dipolar with n_sub > 1 or a
+ * periodic axis, FFT for plan failures. */
+spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_desc *model,
+                                 const spx_options *opts, void *stream, spx_ham **out);
+spx_status spx_destroy_hamiltonian(spx_ham *h);
+
+/* Reduced effective field (Methods, reduced field b = -dH/dS in meV):
+ * b_i = sum_j J_ij S_j + 2 sum_l K_l (S_i.n_l) n_l + mu_i mu_B B + b_dip,i.
+ * S: [dev] double[3][N].  b: [dev] [3][N] of double (field_prec SPX_FP64) or
+ * float (all other precisions). */
+spx_status spx_eval_field(spx_ham *h, const double *S, void *b, void *stream);
+
+/* Energy E = -sum_i S_i.(b_bil/2 + b_ani/2 + b_dip/2 + b_Z), which equals
+ * the unordered pair form of the Methods' Hamiltonian.  E: [dev] one double.
+ * terms: [dev] double[5] = bilinear, Zeeman, anisotropy, dipolar, total, or
+ * NULL.  Fixed-order two-level FP64 reduction (deterministic). */
+spx_status spx_energy(spx_ham *h, const double *S, double *E, double *terms, void *stream);
+
+/* Stochastic/deterministic LLG (Methods, atomistic spin dynamics):
+ * dS/dt = -gamma/(1+alpha^2) [S x B + alpha S x (S x B)], B = b/(mu mu_B)
+ * plus, for temperature_K > 0, the thermal field sigma_i eta_i^n with
+ * sigma_i = sqrt(2 alpha k_B T / (gamma mu_i mu_B dt)) (stochastic LLG).
+ * Each step is the normalised Heun scheme: S~ = N[S + dt f(S)],
+ * S' = N[S + dt/2 (f(S) + f(S~))], the same eta in both stages.
+ * eta_i^n comes from one Philox4x32-10 block with key (seed lo, seed hi) and
+ * counter (i lo, i hi ^ tag, n lo, n hi), n = step0 + k for the k-th step;
+ * uniforms u = (x + 1/2) 2^-32; Box-Muller on (u0,u1) gives eta_x, eta_y and
+ * on (u2,u3) gives eta_z.  gamma = 0 selects 1.76085963023e11 rad/(s T).
+ * S is updated in place ([dev] double[3][N]). */
+typedef struct {
+    double alpha;
+    double dt_fs;
+    double temperature_K;
+    double gamma;        /* rad/(s T); 0 = CODATA electron value */
+    uint64_t seed;
+    uint64_t step0;
+    uint32_t tag;        /* noise stream tag (ensembles); 0 by default */
+    int32_t n_steps;
+} spx_llg_params;
+
+spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, void *stream);
+
+/* The thermal-noise normals eta_i^n the Heun kernels use for (seed, step,
+ * tag), written as [dev] double[3][N] for N sites.  Test hook of the RNG
+ * stream; no handle needed. */
+spx_status spx_thermal_noise(uint64_t seed, uint64_t step, uint32_t tag, int64_t N, double *eta,
+                             void *stream);
+
+/* Raw Philox4x32-10 blocks (Salmon et al., SC'11) for n counters:
+ * ctr [dev] uint32[n][4], key [dev] uint32[n][2] -> out [dev] uint32[n][4]. */
+spx_status spx_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out,
+                             void *stream);
+
+/* Introspection of a handle (host values; synchronous). */
+typedef struct {
+    int64_t n_sites;
+    int32_t n_bonds;           /* directed bonds in the table */
+    int32_t field_prec;
+    int32_t backend;           /* 1 stencil, 2 MFMA */
+    int32_t radius[3];         /* max |delta| per axis over the table */
+    int32_t dipolar;
+    int64_t workspace_bytes;   /* library-owned device memory */
+} spx_ham_info;
+spx_status spx_get_info(spx_ham *h, spx_ham_info *info);
+
+/* Copy the directed-bond table out (host arrays sized n_bonds): target a,
+ * source b, offset delta[3], tensor J[9]. */
+spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, double *bond_J);
+
+const char *spx_last_error(void);
+int32_t spx_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPX_H */

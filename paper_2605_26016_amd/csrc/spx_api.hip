@@ -1,0 +1,556 @@
+// spx_api.hip -- host runtime and C ABI of libspx.so: descriptor validation,
+// neighbour-shell enumeration into directed-bond kernel tables, workspace
+// management, and dispatch of the field / energy / Heun kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/spx.h"
+#include "spx_ext.hpp"
+#include "spx_internal.hpp"
+
+using namespace spx;
+
+// ---------------------------------------------------------------- errors
+namespace {
+thread_local std::string g_last_error;
+
+spx_status fail(spx_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+spx_status hip_fail(hipError_t e, const char *where) {
+    return fail(SPX_ERR_HIP, std::string(where) + ": " + hipGetErrorName(e) + " (" +
+                                 hipGetErrorString(e) + ")");
+}
+
+std::mutex g_reg_mu;
+std::unordered_set<const void *> g_handles;
+
+void reg_add(const void *p) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_handles.insert(p);
+}
+bool reg_has(const void *p) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    return p != nullptr && g_handles.count(p) != 0;
+}
+void reg_del(const void *p) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_handles.erase(p);
+}
+}  // namespace
+
+namespace spx {
+void register_handle(const void *p) { reg_add(p); }
+bool handle_alive(const void *p) { return reg_has(p); }
+void unregister_handle(const void *p) { reg_del(p); }
+spx_status set_error(spx_status s, const std::string &msg) { return fail(s, msg); }
+spx_status set_hip_error(hipError_t e, const char *where) { return hip_fail(e, where); }
+}  // namespace spx
+
+// ---------------------------------------------------------------- shells
+namespace {
+
+struct HostBond {
+    int a, b, d[3];
+    double J[9];
+};
+
+double norm3(const double v[3]) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+// Smallest spacing between lattice planes: volume / largest face area.
+double plane_spacing(const double c[9]) {
+    const double *a0 = c, *a1 = c + 3, *a2 = c + 6;
+    auto cross = [](const double *u, const double *v, double *w) {
+        w[0] = u[1] * v[2] - u[2] * v[1];
+        w[1] = u[2] * v[0] - u[0] * v[2];
+        w[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    double f01[3], f12[3], f20[3];
+    cross(a0, a1, f01);
+    cross(a1, a2, f12);
+    cross(a2, a0, f20);
+    const double vol = std::fabs(a0[0] * f12[0] + a0[1] * f12[1] + a0[2] * f12[2]);
+    const double area = std::max(norm3(f01), std::max(norm3(f12), norm3(f20)));
+    return vol / area;
+}
+
+// Bond vector r = (delta + f_b - f_a) . cell for source b at cell offset delta.
+void bond_vector(const double c[9], const double *fa, const double *fb, int dx, int dy, int dz,
+                 double r[3]) {
+    const double u = dx + fb[0] - fa[0], v = dy + fb[1] - fa[1], w = dz + fb[2] - fa[2];
+    for (int k = 0; k < 3; ++k) r[k] = u * c[k] + v * c[3 + k] + w * c[6 + k];
+}
+
+// Directed bonds of the first n_shells distance shells.  Candidate offsets are
+// gathered in a box that grows until it provably contains every vector up to
+// the last shell radius (|delta_k| <= rho / spacing + 1 for |r| <= rho).
+spx_status enumerate_shell_bonds(const spx_lattice_desc &lat, const spx_model_desc &m,
+                                 std::vector<HostBond> &out) {
+    const int ns = lat.n_sub;
+    double longest = 0.0;
+    for (int k = 0; k < 3; ++k) longest = std::max(longest, norm3(lat.cell + 3 * k));
+    const double tol = 1e-9 * longest;
+    const double h = plane_spacing(lat.cell);
+    if (!(h > 0.0)) return fail(SPX_ERR_INVALID_ARG, "lattice vectors are degenerate");
+    std::vector<double> shells;
+    for (int M = 1; M <= 64; M *= 2) {
+        std::vector<double> d;
+        for (int a = 0; a < ns; ++a)
+            for (int b = 0; b < ns; ++b)
+                for (int dz = -M; dz <= M; ++dz)
+                    for (int dy = -M; dy <= M; ++dy)
+                        for (int dx = -M; dx <= M; ++dx) {
+                            double r[3];
+                            bond_vector(lat.cell, lat.sub_frac + 3 * a, lat.sub_frac + 3 * b, dx, dy, dz, r);
+                            const double n = norm3(r);
+                            if (n > tol) d.push_back(n);
+                        }
+        std::sort(d.begin(), d.end());
+        shells.clear();
+        for (double v : d) {
+            if (shells.empty() || v - shells.back() > tol) shells.push_back(v);
+            if ((int)shells.size() == m.n_shells) break;
+        }
+        if ((int)shells.size() == m.n_shells && shells.back() <= (M - 1) * h) break;
+        shells.clear();
+    }
+    if ((int)shells.size() != m.n_shells) return fail(SPX_ERR_INVALID_ARG, "shell enumeration did not converge");
+    const int R = (int)std::ceil(shells.back() / h) + 1;
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b)
+            for (int dz = -R; dz <= R; ++dz)
+                for (int dy = -R; dy <= R; ++dy)
+                    for (int dx = -R; dx <= R; ++dx) {
+                        double r[3];
+                        bond_vector(lat.cell, lat.sub_frac + 3 * a, lat.sub_frac + 3 * b, dx, dy, dz, r);
+                        const double n = norm3(r);
+                        if (n <= tol) continue;
+                        int s = -1;
+                        for (int k = 0; k < m.n_shells; ++k)
+                            if (std::fabs(n - shells[k]) <= tol) { s = k; break; }
+                        if (s < 0) continue;
+                        const double J = m.J_shell[s];
+                        const double D = m.D_shell ? m.D_shell[s] : 0.0;
+                        if (J == 0.0 && D == 0.0) continue;
+                        // J_ij = J I + DMI matrix of D_ij = D r/|r| (Methods, bilinear tensor)
+                        const double Dx = D * r[0] / n, Dy = D * r[1] / n, Dz = D * r[2] / n;
+                        HostBond hb{a, b, {dx, dy, dz}, {J, Dz, -Dy, -Dz, J, Dx, Dy, -Dx, J}};
+                        out.push_back(hb);
+                    }
+    return SPX_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- handle
+struct spx_ham {
+    spx_lattice_desc lat{};
+    std::vector<double> frac, mu;
+    int field_prec = 0;
+    int backend = 1;
+    std::vector<HostBond> bonds;
+    Grid grid{};
+    Onsite onsite{};
+    BondTable tab{};
+    int radius[3] = {0, 0, 0};
+    // device allocations
+    int4 *d_geo = nullptr;
+    float *d_Jf = nullptr;
+    double *d_Jd = nullptr;
+    double *d_St = nullptr;      // Heun predictor state
+    double *d_Sp = nullptr;      // Heun ping-pong state
+    double *d_partial = nullptr; // energy partials
+    int64_t ws_bytes = 0;
+    DipolarPlan *dip = nullptr;  // dipolar FFT workspace (NULL when off)
+    float *d_bdip0 = nullptr, *d_bdip1 = nullptr;
+};
+
+namespace {
+
+template <typename T>
+spx_status dev_alloc(spx_ham *h, T **p, size_t count, const char *what) {
+    if (count == 0) { *p = nullptr; return SPX_OK; }
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(SPX_ERR_OUT_OF_MEMORY, std::string("hipMalloc failed for ") + what + " (" +
+                                               std::to_string(count * sizeof(T)) + " bytes)");
+    }
+    h->ws_bytes += (int64_t)(count * sizeof(T));
+    return SPX_OK;
+}
+
+void free_all(spx_ham *h) {
+    if (h->dip) destroy_dipolar(h->dip);
+    h->dip = nullptr;
+    for (void *p : {(void *)h->d_geo, (void *)h->d_Jf, (void *)h->d_Jd, (void *)h->d_St, (void *)h->d_Sp,
+                    (void *)h->d_partial, (void *)h->d_bdip0, (void *)h->d_bdip1})
+        if (p) (void)hipFree(p);
+    h->d_geo = nullptr;
+    h->d_Jf = nullptr;
+    h->d_Jd = nullptr;
+    h->d_St = h->d_Sp = h->d_partial = nullptr;
+    h->d_bdip0 = h->d_bdip1 = nullptr;
+}
+
+spx_status check_device() {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        return fail(SPX_ERR_HIP, "no HIP device available");
+    }
+    return SPX_OK;
+}
+
+}  // namespace
+
+namespace spx {
+spx_status get_ham_view(spx_ham *h, HamView &v) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    v.grid = h->grid;
+    v.tab = h->tab;
+    v.onsite = h->onsite;
+    v.field_prec = h->field_prec;
+    v.mu = h->mu.data();
+    v.dip = h->dip;
+    v.radius[0] = h->radius[0];
+    v.radius[1] = h->radius[1];
+    v.radius[2] = h->radius[2];
+    return SPX_OK;
+}
+}  // namespace spx
+
+extern "C" {
+
+int32_t spx_abi_version(void) { return SPX_ABI_VERSION; }
+
+const char *spx_last_error(void) { return g_last_error.c_str(); }
+
+spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_desc *model,
+                                 const spx_options *opts, void *stream, spx_ham **out) {
+    if (!out) return fail(SPX_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!lat || !model) return fail(SPX_ERR_INVALID_ARG, "lattice or model descriptor is NULL");
+    if (lat->n_sub < 1 || lat->n_sub > kMaxSub)
+        return fail(SPX_ERR_INVALID_ARG, "n_sub must be in [1, " + std::to_string(kMaxSub) + "]");
+    if (!lat->sub_frac || !lat->mu) return fail(SPX_ERR_INVALID_ARG, "sub_frac or mu is NULL");
+    int64_t M = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (lat->dims[k] < 1) return fail(SPX_ERR_INVALID_ARG, "dims must be >= 1");
+        if (lat->periodic[k] != 0 && lat->periodic[k] != 1)
+            return fail(SPX_ERR_INVALID_ARG, "periodic flags must be 0 or 1");
+        M *= lat->dims[k];
+    }
+    if (M > (int64_t)INT32_MAX) return fail(SPX_ERR_INVALID_ARG, "more than 2^31-1 cells per sublattice");
+    for (int a = 0; a < lat->n_sub; ++a)
+        if (!(lat->mu[a] > 0.0)) return fail(SPX_ERR_INVALID_ARG, "moments mu must be positive");
+    const int prec = opts ? opts->field_prec : SPX_FP64;
+    if (prec < SPX_FP64 || prec > SPX_FP16_MFMA) return fail(SPX_ERR_INVALID_ARG, "unknown field_prec");
+    const int backend_req = opts ? opts->backend : 0;
+    if (backend_req < 0 || backend_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown backend");
+    if (model->n_shells < 0 || model->n_bonds < 0 || model->n_aniso < 0)
+        return fail(SPX_ERR_INVALID_ARG, "negative counts in model descriptor");
+    if (model->n_shells > 0 && !model->J_shell) return fail(SPX_ERR_INVALID_ARG, "J_shell is NULL");
+    if (model->n_bonds > 0 && (!model->bond_ab || !model->bond_delta || !model->bond_J))
+        return fail(SPX_ERR_INVALID_ARG, "bond arrays are NULL");
+    if (model->n_aniso > kMaxAniso) return fail(SPX_ERR_INVALID_ARG, "too many anisotropy axes");
+    if (model->n_aniso > 0 && (!model->K || !model->K_axis))
+        return fail(SPX_ERR_INVALID_ARG, "K or K_axis is NULL");
+    if (model->dipolar != 0 && model->dipolar != 1) return fail(SPX_ERR_INVALID_ARG, "dipolar must be 0 or 1");
+    if (model->dipolar) {
+        if (lat->n_sub != 1) return fail(SPX_ERR_UNSUPPORTED, "dipolar FFT path needs n_sub = 1");
+        if (lat->periodic[0] || lat->periodic[1] || lat->periodic[2])
+            return fail(SPX_ERR_UNSUPPORTED, "dipolar FFT path is open-boundary only");
+    }
+    if (prec >= SPX_BF16_MFMA && backend_req == 1)
+        return fail(SPX_ERR_INVALID_ARG, "MFMA precisions need the dense backend");
+    if (prec >= SPX_BF16_MFMA)
+        return fail(SPX_ERR_UNSUPPORTED, "MFMA dense-window precisions are served by spx_dense_field");
+    spx_status s = check_device();
+    if (s != SPX_OK) return s;
+
+    spx_ham *h = new spx_ham();
+    h->lat = *lat;
+    h->frac.assign(lat->sub_frac, lat->sub_frac + 3 * lat->n_sub);
+    h->mu.assign(lat->mu, lat->mu + lat->n_sub);
+    h->lat.sub_frac = h->frac.data();
+    h->lat.mu = h->mu.data();
+    h->field_prec = prec;
+    h->backend = 1;
+
+    // bond table
+    if (model->n_bonds > 0) {
+        for (int p = 0; p < model->n_bonds; ++p) {
+            HostBond hb;
+            hb.a = model->bond_ab[2 * p];
+            hb.b = model->bond_ab[2 * p + 1];
+            if (hb.a < 0 || hb.a >= lat->n_sub || hb.b < 0 || hb.b >= lat->n_sub) {
+                delete h;
+                return fail(SPX_ERR_INVALID_ARG, "bond sublattice index out of range");
+            }
+            for (int k = 0; k < 3; ++k) hb.d[k] = model->bond_delta[3 * p + k];
+            for (int k = 0; k < 9; ++k) hb.J[k] = model->bond_J[9 * p + k];
+            h->bonds.push_back(hb);
+        }
+    } else if (model->n_shells > 0) {
+        s = enumerate_shell_bonds(h->lat, *model, h->bonds);
+        if (s != SPX_OK) { delete h; return s; }
+    }
+    std::stable_sort(h->bonds.begin(), h->bonds.end(), [](const HostBond &u, const HostBond &v) {
+        if (u.a != v.a) return u.a < v.a;
+        if (u.b != v.b) return u.b < v.b;
+        if (u.d[2] != v.d[2]) return u.d[2] < v.d[2];
+        if (u.d[1] != v.d[1]) return u.d[1] < v.d[1];
+        return u.d[0] < v.d[0];
+    });
+    const int nb = (int)h->bonds.size();
+    bool iso = true;
+    for (const HostBond &hb : h->bonds) {
+        const double *J = hb.J;
+        if (J[1] != 0 || J[2] != 0 || J[3] != 0 || J[5] != 0 || J[6] != 0 || J[7] != 0 || J[0] != J[4] ||
+            J[0] != J[8])
+            iso = false;
+        for (int k = 0; k < 3; ++k) h->radius[k] = std::max(h->radius[k], std::abs(hb.d[k]));
+    }
+    // grid
+    Grid &g = h->grid;
+    g.Lx = lat->dims[0];
+    g.Ly = lat->dims[1];
+    g.Lz = lat->dims[2];
+    for (int k = 0; k < 3; ++k) g.per[k] = lat->periodic[k];
+    g.n_sub = lat->n_sub;
+    g.M = (int)M;
+    g.N = M * lat->n_sub;
+    g.wrap_general = 0;
+    for (int k = 0; k < 3; ++k)
+        if (h->radius[k] > lat->dims[k]) g.wrap_general = 1;
+    // on-site terms
+    Onsite &os = h->onsite;
+    std::memset(&os, 0, sizeof(os));
+    os.n_aniso = model->n_aniso;
+    for (int a = 0; a < lat->n_sub; ++a) {
+        for (int l = 0; l < model->n_aniso; ++l) {
+            os.K[a][l] = model->K[a * model->n_aniso + l];
+            for (int c = 0; c < 3; ++c) os.axis[a][l][c] = model->K_axis[3 * (a * model->n_aniso + l) + c];
+        }
+        for (int c = 0; c < 3; ++c) os.bz[a][c] = lat->mu[a] * kMuB * model->B_ext[c];
+    }
+    // device tables
+    std::vector<int4> geo(nb);
+    std::vector<float> Jf(iso ? nb : 9 * nb);
+    std::vector<double> Jd(iso ? nb : 9 * nb);
+    BondTable &tb = h->tab;
+    std::memset(&tb, 0, sizeof(tb));
+    tb.iso = iso ? 1 : 0;
+    for (int a = 0, p = 0; a <= kMaxSub; ++a) {
+        while (p < nb && h->bonds[p].a < a) ++p;
+        tb.start[a] = p;
+    }
+    for (int p = 0; p < nb; ++p) {
+        const HostBond &hb = h->bonds[p];
+        geo[p] = make_int4(hb.b, hb.d[0], hb.d[1], hb.d[2]);
+        if (iso) {
+            Jd[p] = hb.J[0];
+            Jf[p] = (float)hb.J[0];
+        } else {
+            for (int k = 0; k < 9; ++k) {
+                Jd[9 * p + k] = hb.J[k];
+                Jf[9 * p + k] = (float)hb.J[k];
+            }
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n3 = (size_t)3 * (size_t)g.N;
+    if ((s = dev_alloc(h, &h->d_geo, std::max(nb, 1), "bond geometry")) != SPX_OK ||
+        (s = dev_alloc(h, &h->d_Jf, std::max<size_t>(Jf.size(), 1), "couplings fp32")) != SPX_OK ||
+        (s = dev_alloc(h, &h->d_Jd, std::max<size_t>(Jd.size(), 1), "couplings fp64")) != SPX_OK ||
+        (s = dev_alloc(h, &h->d_St, n3, "Heun predictor state")) != SPX_OK ||
+        (s = dev_alloc(h, &h->d_Sp, n3, "Heun ping-pong state")) != SPX_OK ||
+        (s = dev_alloc(h, &h->d_partial, (size_t)energy_partial_count(g) * 4, "energy partials")) != SPX_OK) {
+        free_all(h);
+        delete h;
+        return s;
+    }
+    hipError_t e = hipSuccess;
+    if (nb > 0) {
+        e = hipMemcpyAsync(h->d_geo, geo.data(), nb * sizeof(int4), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_Jf, Jf.data(), Jf.size() * sizeof(float), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_Jd, Jd.data(), Jd.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_all(h);
+        delete h;
+        return hip_fail(e, "spx_setup_hamiltonian: table upload");
+    }
+    tb.geo = h->d_geo;
+    tb.Jf = h->d_Jf;
+    tb.Jd = h->d_Jd;
+    if (model->dipolar) {
+        s = create_dipolar(lat->dims, lat->cell, lat->mu[0], st, &h->dip, &h->ws_bytes);
+        if (s == SPX_OK) s = dev_alloc(h, &h->d_bdip0, n3, "dipolar field");
+        if (s == SPX_OK) s = dev_alloc(h, &h->d_bdip1, n3, "dipolar field (predictor)");
+        if (s != SPX_OK) {
+            free_all(h);
+            delete h;
+            return s;
+        }
+    }
+    reg_add(h);
+    *out = h;
+    return SPX_OK;
+}
+
+spx_status spx_destroy_hamiltonian(spx_ham *h) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    reg_del(h);
+    (void)hipDeviceSynchronize();
+    free_all(h);
+    delete h;
+    return SPX_OK;
+}
+
+spx_status spx_get_info(spx_ham *h, spx_ham_info *info) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    if (!info) return fail(SPX_ERR_INVALID_ARG, "info is NULL");
+    info->n_sites = h->grid.N;
+    info->n_bonds = (int32_t)h->bonds.size();
+    info->field_prec = h->field_prec;
+    info->backend = h->backend;
+    for (int k = 0; k < 3; ++k) info->radius[k] = h->radius[k];
+    info->dipolar = h->dip ? 1 : 0;
+    info->workspace_bytes = h->ws_bytes;
+    return SPX_OK;
+}
+
+spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, double *bond_J) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    if (!bond_ab || !bond_delta || !bond_J) return fail(SPX_ERR_INVALID_ARG, "output array is NULL");
+    for (size_t p = 0; p < h->bonds.size(); ++p) {
+        const HostBond &hb = h->bonds[p];
+        bond_ab[2 * p] = hb.a;
+        bond_ab[2 * p + 1] = hb.b;
+        for (int k = 0; k < 3; ++k) bond_delta[3 * p + k] = hb.d[k];
+        for (int k = 0; k < 9; ++k) bond_J[9 * p + k] = hb.J[k];
+    }
+    return SPX_OK;
+}
+
+static spx_status dipolar_field(spx_ham *h, const double *S, float *bdip, hipStream_t st) {
+    return eval_dipolar(h->dip, S, bdip, st);
+}
+
+spx_status spx_eval_field(spx_ham *h, const double *S, void *b, void *stream) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    if (!S || !b) return fail(SPX_ERR_INVALID_ARG, "S or b is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const float *bdip = nullptr;
+    if (h->dip) {
+        spx_status s = dipolar_field(h, S, h->d_bdip0, st);
+        if (s != SPX_OK) return s;
+        bdip = h->d_bdip0;
+    }
+    hipError_t e = launch_field(h->field_prec, h->tab, h->grid, h->onsite, S, bdip, b, st);
+    if (e != hipSuccess) return hip_fail(e, "spx_eval_field");
+    return SPX_OK;
+}
+
+spx_status spx_energy(spx_ham *h, const double *S, double *E, double *terms, void *stream) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    if (!S || (!E && !terms)) return fail(SPX_ERR_INVALID_ARG, "S is NULL or no output given");
+    hipStream_t st = (hipStream_t)stream;
+    const float *bdip = nullptr;
+    if (h->dip) {
+        spx_status s = dipolar_field(h, S, h->d_bdip0, st);
+        if (s != SPX_OK) return s;
+        bdip = h->d_bdip0;
+    }
+    hipError_t e = launch_energy(h->field_prec, h->tab, h->grid, h->onsite, S, bdip, h->d_partial, E, terms, st);
+    if (e != hipSuccess) return hip_fail(e, "spx_energy");
+    return SPX_OK;
+}
+
+spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, void *stream) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    if (!S || !p) return fail(SPX_ERR_INVALID_ARG, "S or params is NULL");
+    if (p->n_steps < 0) return fail(SPX_ERR_INVALID_ARG, "n_steps < 0");
+    if (!(p->dt_fs > 0.0)) return fail(SPX_ERR_INVALID_ARG, "dt_fs must be positive");
+    if (!(p->alpha >= 0.0)) return fail(SPX_ERR_INVALID_ARG, "alpha must be >= 0");
+    if (!(p->temperature_K >= 0.0)) return fail(SPX_ERR_INVALID_ARG, "temperature must be >= 0");
+    if (p->temperature_K > 0.0 && p->alpha == 0.0)
+        return fail(SPX_ERR_INVALID_ARG, "a thermal bath needs alpha > 0");
+    if (p->n_steps == 0) return SPX_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const double gamma = (p->gamma > 0.0) ? p->gamma * 1e-15 : kGammaPerFs;  // rad/(fs T)
+    HeunConst hc;
+    std::memset(&hc, 0, sizeof(hc));
+    hc.dt = p->dt_fs;
+    hc.alpha = p->alpha;
+    hc.pre = -gamma / (1.0 + p->alpha * p->alpha);
+    hc.seed = p->seed;
+    hc.tag = p->tag;
+    hc.noise = p->temperature_K > 0.0 ? 1 : 0;
+    for (int a = 0; a < h->grid.n_sub; ++a) {
+        hc.inv_mumuB[a] = 1.0 / (h->mu[a] * kMuB);
+        hc.sigma[a] = hc.noise ? std::sqrt(2.0 * p->alpha * kKB * p->temperature_K /
+                                           (gamma * h->mu[a] * kMuB * p->dt_fs))
+                               : 0.0;
+    }
+    double *cur = S, *nxt = h->d_Sp;
+    for (int k = 0; k < p->n_steps; ++k) {
+        const uint64_t step = p->step0 + (uint64_t)k;
+        const float *bd0 = nullptr, *bd1 = nullptr;
+        if (h->dip) {
+            spx_status s = dipolar_field(h, cur, h->d_bdip0, st);
+            if (s != SPX_OK) return s;
+            bd0 = h->d_bdip0;
+        }
+        hipError_t e = launch_heun_predict(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, bd0,
+                                           h->d_St, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: predictor");
+        if (h->dip) {
+            spx_status s = dipolar_field(h, h->d_St, h->d_bdip1, st);
+            if (s != SPX_OK) return s;
+            bd1 = h->d_bdip1;
+        }
+        e = launch_heun_correct(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
+                                nxt, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: corrector");
+        std::swap(cur, nxt);
+    }
+    if (cur != S) {
+        hipError_t e = hipMemcpyAsync(S, cur, sizeof(double) * 3 * (size_t)h->grid.N, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: copy-back");
+    }
+    return SPX_OK;
+}
+
+spx_status spx_thermal_noise(uint64_t seed, uint64_t step, uint32_t tag, int64_t N, double *eta, void *stream) {
+    if (N < 0 || (N > 0 && !eta)) return fail(SPX_ERR_INVALID_ARG, "bad N or eta");
+    hipError_t e = launch_thermal_noise(seed, step, tag, N, eta, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "spx_thermal_noise");
+    return SPX_OK;
+}
+
+spx_status spx_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out, void *stream) {
+    if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(SPX_ERR_INVALID_ARG, "bad philox arguments");
+    hipError_t e = launch_philox(ctr, key, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "spx_philox4x32_10");
+    return SPX_OK;
+}
+
+}  // extern "C"

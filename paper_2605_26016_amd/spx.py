@@ -1,0 +1,295 @@
+"""ctypes binding of libspx.so (include/spx.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of libspx.so.  Device buffers are torch tensors on the GPU (or raw
+integer device pointers); streams default to torch's current stream.  Every
+function raises SpxError on a non-OK status, and importing the binding raises
+if the library has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspx.so")
+
+SPX_FP64, SPX_FP32, SPX_BF16_MFMA, SPX_FP16_MFMA = 0, 1, 2, 3
+PREC = {"fp64": SPX_FP64, "fp32": SPX_FP32, "bf16": SPX_BF16_MFMA, "fp16": SPX_FP16_MFMA}
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "HIP", 5: "FFT",
+          6: "BAD_HANDLE"}
+
+
+class SpxError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: SPX_ERR_{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class LatticeDesc(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("dims", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
+                ("cell", C.c_double * 9), ("sub_frac", C.POINTER(C.c_double)),
+                ("mu", C.POINTER(C.c_double))]
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("n_shells", C.c_int32), ("J_shell", C.POINTER(C.c_double)),
+                ("D_shell", C.POINTER(C.c_double)), ("n_bonds", C.c_int32),
+                ("bond_ab", C.POINTER(C.c_int32)), ("bond_delta", C.POINTER(C.c_int32)),
+                ("bond_J", C.POINTER(C.c_double)), ("n_aniso", C.c_int32),
+                ("K", C.POINTER(C.c_double)), ("K_axis", C.POINTER(C.c_double)),
+                ("B_ext", C.c_double * 3), ("dipolar", C.c_int32)]
+
+
+class Options(C.Structure):
+    _fields_ = [("field_prec", C.c_int32), ("backend", C.c_int32), ("autotune", C.c_int32),
+                ("tune_cache_path", C.c_char_p)]
+
+
+class LlgParams(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("dt_fs", C.c_double), ("temperature_K", C.c_double),
+                ("gamma", C.c_double), ("seed", C.c_uint64), ("step0", C.c_uint64),
+                ("tag", C.c_uint32), ("n_steps", C.c_int32)]
+
+
+class HamInfo(C.Structure):
+    _fields_ = [("n_sites", C.c_int64), ("n_bonds", C.c_int32), ("field_prec", C.c_int32),
+                ("backend", C.c_int32), ("radius", C.c_int32 * 3), ("dipolar", C.c_int32),
+                ("workspace_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libspx.so; raises if it is missing (build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -m paper_2605_26016_amd.build)")
+    L = C.CDLL(path)
+    vp, i32, i64, u64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_uint32, C.c_double
+    sigs = {
+        "spx_setup_hamiltonian": [C.POINTER(LatticeDesc), C.POINTER(ModelDesc), C.POINTER(Options), vp,
+                                  C.POINTER(vp)],
+        "spx_destroy_hamiltonian": [vp],
+        "spx_eval_field": [vp, vp, vp, vp],
+        "spx_energy": [vp, vp, vp, vp, vp],
+        "spx_llg_heun_step": [vp, vp, C.POINTER(LlgParams), vp],
+        "spx_thermal_noise": [u64, u64, u32, i64, vp, vp],
+        "spx_philox4x32_10": [vp, vp, i64, vp, vp],
+        "spx_get_info": [vp, C.POINTER(HamInfo)],
+        "spx_get_bonds": [vp, vp, vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.spx_last_error.restype = C.c_char_p
+    L.spx_last_error.argtypes = []
+    L.spx_abi_version.restype = C.c_int32
+    L.spx_abi_version.argtypes = []
+    _lib = L
+    _register_extensions(L)
+    return L
+
+
+_ext_registrars = []
+
+
+def _register_extensions(L):
+    for fn in _ext_registrars:
+        fn(L)
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise SpxError(status, where, last_error())
+
+
+def last_error() -> str:
+    return load().spx_last_error().decode()
+
+
+def abi_version() -> int:
+    return int(load().spx_abi_version())
+
+
+# ---------------------------------------------------------------- marshalling
+def _ptr(x) -> Optional[int]:
+    """Device pointer of a torch tensor (checked contiguous), an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("device buffers must be contiguous")
+        if x.device.type != "cuda":
+            raise ValueError("device buffers must live on the GPU")
+        return x.data_ptr()
+    raise TypeError(f"cannot take a device pointer of {type(x)}")
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class Hamiltonian:
+    """Owner of an spx_ham handle (destroyed with the object)."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+        self._info = None
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                load().spx_destroy_hamiltonian(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+    def destroy(self):
+        if self.handle:
+            _check(load().spx_destroy_hamiltonian(self.handle), "spx_destroy_hamiltonian")
+            self.handle = None
+
+    @property
+    def info(self) -> HamInfo:
+        if self._info is None:
+            self._info = get_info(self)
+        return self._info
+
+    @property
+    def N(self) -> int:
+        return int(self.info.n_sites)
+
+
+def setup_hamiltonian(dims: Sequence[int], cell=None, sub_frac=((0.0, 0.0, 0.0),), mu=(1.0,),
+                      periodic=(1, 1, 1), J_shell=None, D_shell=None, bonds=None, K=None,
+                      K_axis=None, B=(0.0, 0.0, 0.0), dipolar=0, field_prec="fp64", backend=0,
+                      autotune=0, tune_cache_path=None, stream=None) -> Hamiltonian:
+    """Wraps spx_setup_hamiltonian.  K: [n_sub][n_aniso] meV (or scalar applied
+    to every sublattice with one axis), K_axis: matching unit vectors.
+    bonds = (ab [n][2], delta [n][3], J [n][9]) overrides the shells."""
+    L = load()
+    frac = np.ascontiguousarray(np.asarray(sub_frac, np.float64).reshape(-1))
+    n_sub = len(frac) // 3
+    mu_a = np.ascontiguousarray(np.asarray(mu, np.float64).reshape(-1))
+    cell_a = np.asarray(np.eye(3) if cell is None else cell, np.float64).reshape(9)
+    lat = LatticeDesc()
+    lat.n_sub = n_sub
+    lat.dims[:] = [int(v) for v in dims]
+    lat.periodic[:] = [int(v) for v in periodic]
+    lat.cell[:] = list(cell_a)
+    lat.sub_frac = _dptr(frac)
+    lat.mu = _dptr(mu_a)
+    keep = [frac, mu_a]
+    m = ModelDesc()
+    if J_shell is not None:
+        Js = np.ascontiguousarray(np.asarray(J_shell, np.float64).reshape(-1))
+        keep.append(Js)
+        m.n_shells = len(Js)
+        m.J_shell = _dptr(Js)
+        if D_shell is not None:
+            Ds = np.ascontiguousarray(np.asarray(D_shell, np.float64).reshape(-1))
+            if len(Ds) != len(Js):
+                raise ValueError("D_shell must match J_shell")
+            keep.append(Ds)
+            m.D_shell = _dptr(Ds)
+    if bonds is not None:
+        ab, dl, Jb = bonds
+        ab = np.ascontiguousarray(np.asarray(ab, np.int32).reshape(-1))
+        dl = np.ascontiguousarray(np.asarray(dl, np.int32).reshape(-1))
+        Jb = np.ascontiguousarray(np.asarray(Jb, np.float64).reshape(-1))
+        keep += [ab, dl, Jb]
+        m.n_bonds = len(ab) // 2
+        m.bond_ab, m.bond_delta, m.bond_J = _iptr(ab), _iptr(dl), _dptr(Jb)
+    if K is not None:
+        Ka = np.asarray(K, np.float64)
+        if Ka.ndim == 0:
+            Ka = np.full((n_sub, 1), float(Ka))
+        Ka = np.ascontiguousarray(Ka.reshape(n_sub, -1))
+        ax = np.asarray((0.0, 0.0, 1.0) if K_axis is None else K_axis, np.float64)
+        if ax.size == 3:
+            ax = np.tile(ax, (n_sub, Ka.shape[1], 1))
+        ax = np.ascontiguousarray(ax.reshape(-1))
+        keep += [Ka, ax]
+        m.n_aniso = Ka.shape[1]
+        m.K, m.K_axis = _dptr(Ka.reshape(-1)), _dptr(ax)
+    m.B_ext[:] = [float(v) for v in B]
+    m.dipolar = int(dipolar)
+    o = Options()
+    o.field_prec = PREC[field_prec] if isinstance(field_prec, str) else int(field_prec)
+    o.backend = int(backend)
+    o.autotune = int(autotune)
+    o.tune_cache_path = None if tune_cache_path is None else tune_cache_path.encode()
+    h = C.c_void_p()
+    _check(L.spx_setup_hamiltonian(C.byref(lat), C.byref(m), C.byref(o), _stream(stream), C.byref(h)),
+           "spx_setup_hamiltonian")
+    return Hamiltonian(h.value, keep)
+
+
+def _h(h):
+    return h.handle if isinstance(h, Hamiltonian) else h
+
+
+def eval_field(h, S, b, stream=None):
+    _check(load().spx_eval_field(_h(h), _ptr(S), _ptr(b), _stream(stream)), "spx_eval_field")
+
+
+def energy(h, S, E, terms=None, stream=None):
+    _check(load().spx_energy(_h(h), _ptr(S), _ptr(E), _ptr(terms), _stream(stream)), "spx_energy")
+
+
+def llg_heun_step(h, S, alpha, dt_fs, temperature_K=0.0, gamma=0.0, seed=0, step0=0, tag=0,
+                  n_steps=1, stream=None):
+    p = LlgParams(float(alpha), float(dt_fs), float(temperature_K), float(gamma), int(seed),
+                  int(step0), int(tag), int(n_steps))
+    _check(load().spx_llg_heun_step(_h(h), _ptr(S), C.byref(p), _stream(stream)), "spx_llg_heun_step")
+
+
+def thermal_noise(seed, step, tag, N, eta, stream=None):
+    _check(load().spx_thermal_noise(int(seed), int(step), int(tag), int(N), _ptr(eta), _stream(stream)),
+           "spx_thermal_noise")
+
+
+def philox4x32_10(ctr, key, n, out, stream=None):
+    _check(load().spx_philox4x32_10(_ptr(ctr), _ptr(key), int(n), _ptr(out), _stream(stream)),
+           "spx_philox4x32_10")
+
+
+def get_info(h) -> HamInfo:
+    info = HamInfo()
+    _check(load().spx_get_info(_h(h), C.byref(info)), "spx_get_info")
+    return info
+
+
+def get_bonds(h):
+    info = get_info(h)
+    n = info.n_bonds
+    ab = np.zeros(2 * max(n, 1), np.int32)
+    dl = np.zeros(3 * max(n, 1), np.int32)
+    J = np.zeros(9 * max(n, 1), np.float64)
+    _check(load().spx_get_bonds(_h(h), ab.ctypes.data, dl.ctypes.data, J.ctypes.data), "spx_get_bonds")
+    return ab[:2 * n].reshape(n, 2), dl[:3 * n].reshape(n, 3), J[:9 * n].reshape(n, 3, 3)

@@ -26,3 +26,25 @@ def max_rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def gpu_hamiltonian(w: Workload, field_prec=None, **kw):
+    """libspx Hamiltonian for a workload (shell-defined couplings)."""
+    from paper_2605_26016_amd import spx
+    prec = field_prec or w.field_prec
+    K = w.K if w.K != 0.0 else None
+    return spx.setup_hamiltonian(w.L, cell=w.cell, sub_frac=w.frac, mu=w.mu, periodic=w.periodic,
+                                 J_shell=w.J_shell, D_shell=w.D_shell, K=K, K_axis=w.K_axis, B=w.B,
+                                 dipolar=w.dipolar, field_prec=prec, **kw)
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def require_gpu():
+    import pytest
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
