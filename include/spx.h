@@ -106,12 +106,21 @@ typedef struct {
 
 /* backend: 0 auto, 1 sparse stencil, 2 dense-window MFMA (needs a BF16/FP16
  * field_prec).  autotune: 0 off, 1 time candidate launch shapes at setup and
- * keep the fastest (cached per shape key in tune_cache_path if non-NULL). */
+ * keep the fastest (cached per shape key in tune_cache_path if non-NULL).
+ * stencil_engine: 0 auto, 1 gather kernel (any bond table), 2 z-marching LDS
+ * engine (bond tables that match a built-in shell shape: simple cubic shells
+ * 1, 1-3, 1-4; bcc shells 1-5).  zchunk: z planes per block of the z-march
+ * engine (0 = default 8).  heun_field: 0 auto, 1 the corrector recomputes
+ * the field of S^n, 2 the predictor stores the FP32 bilinear field of S^n
+ * for the corrector (FP32 field_prec only; identical results). */
 typedef struct {
     int32_t field_prec;        /* spx_precision */
     int32_t backend;
     int32_t autotune;
     const char *tune_cache_path;
+    int32_t stencil_engine;
+    int32_t zchunk;
+    int32_t heun_field;
 } spx_options;
 
 /* Build the kernel tables (directed bonds grouped per target sublattice, see
@@ -181,12 +190,26 @@ typedef struct {
     int32_t radius[3];         /* max |delta| per axis over the table */
     int32_t dipolar;
     int64_t workspace_bytes;   /* library-owned device memory */
+    int32_t stencil_engine;    /* 1 gather, 2 z-march */
+    int32_t shape;             /* z-march shell shape id, -1 if none */
+    int32_t zchunk;
+    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field */
 } spx_ham_info;
 spx_status spx_get_info(spx_ham *h, spx_ham_info *info);
 
 /* Copy the directed-bond table out (host arrays sized n_bonds): target a,
  * source b, offset delta[3], tensor J[9]. */
 spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, double *bond_J);
+
+/* Kernel timing instrumentation (Methods, performance measurements: device
+ * time of the hot kernels).  With enable = 1 every launch of the Heun
+ * predictor (kind 0), Heun corrector (kind 1) and field kernel (kind 2) on
+ * this handle is bracketed by a pair of hipEvents on the launch stream.
+ * spx_get_kernel_times synchronises on the recorded events and returns the
+ * number of launches and their summed duration in ms since the last query
+ * (then resets that kind).  enable = 0 stops recording. */
+spx_status spx_set_kernel_timing(spx_ham *h, int32_t enable);
+spx_status spx_get_kernel_times(spx_ham *h, int32_t kind, int64_t *count, double *total_ms);
 
 const char *spx_last_error(void);
 int32_t spx_abi_version(void);

@@ -173,6 +173,15 @@ struct spx_ham {
     int64_t ws_bytes = 0;
     DipolarPlan *dip = nullptr;  // dipolar FFT workspace (NULL when off)
     float *d_bdip0 = nullptr, *d_bdip1 = nullptr;
+    // z-march engine plan (valid when the bond table matches a shell shape)
+    ZPlan zp;
+    int engine = 1;          // 1 gather, 2 z-march
+    int heun_field = 1;      // 1 recompute, 2 stored FP32 field
+    float *d_bstore = nullptr;
+    // kernel timing: recorded (start, stop) event pairs per kind, and a pool
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[3];
+    std::vector<hipEvent_t> pool;
 };
 
 namespace {
@@ -191,12 +200,54 @@ spx_status dev_alloc(spx_ham *h, T **p, size_t count, const char *what) {
     return SPX_OK;
 }
 
+hipEvent_t pool_event(spx_ham *h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Brackets one kernel launch with events when timing is on.
+struct KernelTimer {
+    spx_ham *h;
+    int kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTimer(spx_ham *h_, int k, hipStream_t s) : h(h_), kind(k), st(s) {
+        if (!h->timing) return;
+        a = pool_event(h);
+        b = pool_event(h);
+        if (a && b) (void)hipEventRecord(a, st);
+    }
+    ~KernelTimer() {
+        if (!h->timing || !a || !b) return;
+        (void)hipEventRecord(b, st);
+        h->timed[kind].emplace_back(a, b);
+    }
+};
+
 void free_all(spx_ham *h) {
+    for (auto &v : h->timed)
+        for (auto &pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+    for (auto &v : h->timed) v.clear();
+    h->pool.clear();
     if (h->dip) destroy_dipolar(h->dip);
     h->dip = nullptr;
     for (void *p : {(void *)h->d_geo, (void *)h->d_Jf, (void *)h->d_Jd, (void *)h->d_St, (void *)h->d_Sp,
-                    (void *)h->d_partial, (void *)h->d_bdip0, (void *)h->d_bdip1})
+                    (void *)h->d_partial, (void *)h->d_bdip0, (void *)h->d_bdip1, (void *)h->d_bstore})
         if (p) (void)hipFree(p);
+    h->d_bstore = nullptr;
     h->d_geo = nullptr;
     h->d_Jf = nullptr;
     h->d_Jd = nullptr;
@@ -260,6 +311,14 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     if (prec < SPX_FP64 || prec > SPX_FP16_MFMA) return fail(SPX_ERR_INVALID_ARG, "unknown field_prec");
     const int backend_req = opts ? opts->backend : 0;
     if (backend_req < 0 || backend_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown backend");
+    const int engine_req = opts ? opts->stencil_engine : 0;
+    const int zchunk_req = opts ? opts->zchunk : 0;
+    const int hfield_req = opts ? opts->heun_field : 0;
+    if (engine_req < 0 || engine_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown stencil_engine");
+    if (zchunk_req < 0 || zchunk_req > 4096) return fail(SPX_ERR_INVALID_ARG, "zchunk out of range");
+    if (hfield_req < 0 || hfield_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
+    if (hfield_req == 2 && prec != SPX_FP32)
+        return fail(SPX_ERR_INVALID_ARG, "a stored Heun field needs field_prec SPX_FP32");
     if (model->n_shells < 0 || model->n_bonds < 0 || model->n_aniso < 0)
         return fail(SPX_ERR_INVALID_ARG, "negative counts in model descriptor");
     if (model->n_shells > 0 && !model->J_shell) return fail(SPX_ERR_INVALID_ARG, "J_shell is NULL");
@@ -400,6 +459,33 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     tb.geo = h->d_geo;
     tb.Jf = h->d_Jf;
     tb.Jd = h->d_Jd;
+    // z-march engine: match the bond table against the built-in shell shapes
+    {
+        std::vector<int> ba(nb), bb(nb), bd(3 * nb);
+        std::vector<double> bJ(9 * nb);
+        for (int p = 0; p < nb; ++p) {
+            ba[p] = h->bonds[p].a;
+            bb[p] = h->bonds[p].b;
+            for (int k = 0; k < 3; ++k) bd[3 * p + k] = h->bonds[p].d[k];
+            for (int k = 0; k < 9; ++k) bJ[9 * p + k] = h->bonds[p].J[k];
+        }
+        const bool have = nb > 0 && zmarch_plan(prec, lat->n_sub, ba.data(), bb.data(), bd.data(), bJ.data(), nb,
+                                                iso, h->zp);
+        if (engine_req == 2 && !have) {
+            free_all(h);
+            delete h;
+            return fail(SPX_ERR_UNSUPPORTED, "the bond table matches no z-march shell shape");
+        }
+        h->engine = (have && engine_req != 1) ? 2 : 1;
+        if (have && zchunk_req > 0) h->zp.zch = zchunk_req;
+        h->heun_field = 1;
+        if (h->engine == 2 && prec == SPX_FP32 && hfield_req != 1) h->heun_field = 2;
+        if (h->heun_field == 2 && (s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field")) != SPX_OK) {
+            free_all(h);
+            delete h;
+            return s;
+        }
+    }
     if (model->dipolar) {
         s = create_dipolar(lat->dims, lat->cell, lat->mu[0], st, &h->dip, &h->ws_bytes);
         if (s == SPX_OK) s = dev_alloc(h, &h->d_bdip0, n3, "dipolar field");
@@ -434,6 +520,10 @@ spx_status spx_get_info(spx_ham *h, spx_ham_info *info) {
     for (int k = 0; k < 3; ++k) info->radius[k] = h->radius[k];
     info->dipolar = h->dip ? 1 : 0;
     info->workspace_bytes = h->ws_bytes;
+    info->stencil_engine = h->engine;
+    info->shape = h->engine == 2 ? h->zp.kind : -1;
+    info->zchunk = h->engine == 2 ? h->zp.zch : 0;
+    info->heun_field = h->heun_field;
     return SPX_OK;
 }
 
@@ -464,7 +554,12 @@ spx_status spx_eval_field(spx_ham *h, const double *S, void *b, void *stream) {
         if (s != SPX_OK) return s;
         bdip = h->d_bdip0;
     }
-    hipError_t e = launch_field(h->field_prec, h->tab, h->grid, h->onsite, S, bdip, b, st);
+    hipError_t e;
+    {
+        KernelTimer kt(h, 2, st);
+        if (h->engine == 2) e = zmarch_field(h->zp, h->grid, h->onsite, S, bdip, b, st);
+        else e = launch_field(h->field_prec, h->tab, h->grid, h->onsite, S, bdip, b, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "spx_eval_field");
     return SPX_OK;
 }
@@ -519,16 +614,30 @@ spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, voi
             if (s != SPX_OK) return s;
             bd0 = h->d_bdip0;
         }
-        hipError_t e = launch_heun_predict(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, bd0,
-                                           h->d_St, st);
+        hipError_t e;
+        {
+            KernelTimer kt(h, 0, st);
+            if (h->engine == 2)
+                e = zmarch_predict(h->zp, h->grid, h->onsite, hc, step, cur, bd0, h->d_St,
+                                   h->heun_field == 2 ? h->d_bstore : nullptr, st);
+            else
+                e = launch_heun_predict(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, bd0, h->d_St, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: predictor");
         if (h->dip) {
             spx_status s = dipolar_field(h, h->d_St, h->d_bdip1, st);
             if (s != SPX_OK) return s;
             bd1 = h->d_bdip1;
         }
-        e = launch_heun_correct(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
-                                nxt, st);
+        {
+            KernelTimer kt(h, 1, st);
+            if (h->engine == 2)
+                e = zmarch_correct(h->zp, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
+                                   h->heun_field == 2 ? h->d_bstore : nullptr, nxt, st);
+            else
+                e = launch_heun_correct(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
+                                        nxt, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: corrector");
         std::swap(cur, nxt);
     }
@@ -536,6 +645,33 @@ spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, voi
         hipError_t e = hipMemcpyAsync(S, cur, sizeof(double) * 3 * (size_t)h->grid.N, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: copy-back");
     }
+    return SPX_OK;
+}
+
+spx_status spx_set_kernel_timing(spx_ham *h, int32_t enable) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    h->timing = enable != 0;
+    return SPX_OK;
+}
+
+spx_status spx_get_kernel_times(spx_ham *h, int32_t kind, int64_t *count, double *total_ms) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    if (kind < 0 || kind > 2 || !count || !total_ms) return fail(SPX_ERR_INVALID_ARG, "bad kind or output");
+    double tot = 0.0;
+    int64_t n = 0;
+    for (auto &pr : h->timed[kind]) {
+        hipError_t e = hipEventSynchronize(pr.second);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        if (e != hipSuccess) return hip_fail(e, "spx_get_kernel_times");
+        tot += ms;
+        ++n;
+        h->pool.push_back(pr.first);
+        h->pool.push_back(pr.second);
+    }
+    h->timed[kind].clear();
+    *count = n;
+    *total_ms = tot;
     return SPX_OK;
 }
 

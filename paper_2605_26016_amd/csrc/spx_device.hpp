@@ -98,11 +98,12 @@ __device__ __forceinline__ void llg_rhs(const double s[3], const double B[3], do
     f[2] = pre * (c2 + alpha * d2);
 }
 
+// N[v] = v/|v| with one reciprocal (within one rounding of three divisions).
 __device__ __forceinline__ void normalise3(double v[3]) {
-    const double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    v[0] /= n;
-    v[1] /= n;
-    v[2] /= n;
+    const double inv = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] *= inv;
+    v[1] *= inv;
+    v[2] *= inv;
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -129,21 +130,23 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
 // Three standard normals for site i at step n: one Philox block with
 // counter (i lo, i hi ^ tag, n lo, n hi) and key (seed lo, seed hi), uniforms
 // (x + 1/2) 2^-32, Box-Muller on (u0,u1) -> (eta_x, eta_y), (u2,u3) -> eta_z.
+// The angle 2 pi u is evaluated as sincospi(2u): 2u is exact, so no argument
+// reduction by pi is needed; this agrees with cos(2 pi u) to a few ulp.
 __device__ __forceinline__ void thermal_eta(uint64_t seed, uint64_t step, uint32_t tag, uint64_t site,
                                             double eta[3]) {
     uint32_t c0 = (uint32_t)site, c1 = (uint32_t)(site >> 32) ^ tag;
     uint32_t c2 = (uint32_t)step, c3 = (uint32_t)(step >> 32);
     philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
     const double sc = 2.3283064365386963e-10;  // 2^-32
-    const double two_pi = 6.283185307179586;
     const double u0 = ((double)c0 + 0.5) * sc, u1 = ((double)c1 + 0.5) * sc;
     const double u2 = ((double)c2 + 0.5) * sc, u3 = ((double)c3 + 0.5) * sc;
     const double r0 = sqrt(-2.0 * log(u0));
     const double r1 = sqrt(-2.0 * log(u2));
-    const double t0 = two_pi * u1, t1 = two_pi * u3;
-    eta[0] = r0 * cos(t0);
-    eta[1] = r0 * sin(t0);
-    eta[2] = r1 * cos(t1);
+    double sn, cs;
+    sincospi(2.0 * u1, &sn, &cs);
+    eta[0] = r0 * cs;
+    eta[1] = r0 * sn;
+    eta[2] = r1 * cospi(2.0 * u3);
 }
 
 // Wavefront (64 lanes) sum of a double, result valid in lane 0.

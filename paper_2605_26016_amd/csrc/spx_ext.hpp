@@ -10,6 +10,7 @@
 
 #include "../../include/spx.h"
 #include "spx_internal.hpp"
+#include "spx_stencil.hpp"
 
 namespace spx {
 
@@ -41,5 +42,27 @@ spx_status create_dipolar(const int32_t dims[3], const double cell[9], double mu
 void destroy_dipolar(DipolarPlan *p);
 // b_dip (meV) of state S written as float[3][N].
 spx_status eval_dipolar(DipolarPlan *p, const double *S, float *bdip, hipStream_t st);
+
+// Z-march stencil engine (spx_stencil.hip): a runtime bond table matched
+// against a compile-time shell shape, with the couplings packed in shape order.
+struct ZPlan {
+    bool valid = false;
+    int kind = -1;
+    int prec = 0;   // 0 FP64, 1 FP32
+    int iso = 1;
+    int nw = 0;
+    int zch = 8;    // z planes per block
+    double wd[9 * kMaxShapeBonds];
+    float wf[9 * kMaxShapeBonds];
+};
+bool zmarch_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, const int *bond_d,
+                 const double *bond_J, int n_bonds, bool iso, ZPlan &zp);
+hipError_t zmarch_field(const ZPlan &zp, const Grid &g, const Onsite &os, const double *S, const float *bdip,
+                        void *b, hipStream_t st);
+hipError_t zmarch_predict(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
+                          const double *S, const float *bdip, double *St, float *bstore, hipStream_t st);
+hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
+                          const double *S, const double *St, const float *bdipS, const float *bdipT,
+                          const float *bload, double *out, hipStream_t st);
 
 }  // namespace spx

@@ -1,0 +1,443 @@
+// spx_stencil.hip -- z-marching LDS stencil engine for structured shell
+// patterns on gfx950: effective field, Heun predictor and Heun corrector.
+//
+// A 256-thread block owns a 64 x 8 column tile (64 lanes along x, 4 thread
+// rows of 2 y-sites each) and a chunk of z planes.  It streams input planes
+// z' upward: each plane (all sublattices, 3 components, with the x/y halo of
+// the shape) is loaded once from global memory -- periodic wrap or zero fill
+// at open faces done here, so the compute loop has no boundary logic -- into a
+// double-buffered LDS slot, converted to the compute type (float in mixed
+// mode).  Every bond (compile-time offset, runtime coupling) then pushes
+// J S_b(x+dx, y+dy, z') into a register accumulator of output plane z' - dz;
+// the accumulators of the D = dzhi - dzlo + 1 pending output planes form a
+// register ring that shifts by one slot per input plane, so every bond's slot
+// (dzhi - dz) is a compile-time register.  An output plane is final once its
+// highest input plane has been pushed; a single copy of the epilogue then adds
+// the on-site terms in FP64 and runs the Heun stage for each of its sites.
+#include <type_traits>
+#include <vector>
+
+#include "spx_device.hpp"
+#include "spx_ext.hpp"
+#include "spx_stencil.hpp"
+
+namespace spx {
+
+namespace {
+
+constexpr int kTX = 64;   // tile width in x (one wavefront per thread row)
+constexpr int kTYT = 4;   // thread rows per block
+constexpr int kYB = 2;    // y sites per thread
+constexpr int kTYE = kTYT * kYB;  // tile height in y
+constexpr int kThreads = kTX * kTYT;
+
+enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3 };
+
+template <typename T, int NW>
+struct ZWeights {
+    T w[NW];
+};
+
+struct ZArgs {
+    int Lx, Ly, Lz;
+    int per[3];
+    int M;
+    int64_t N;
+    int zch;
+    const double *S0;  // S^n (or the state of a field evaluation)
+    const double *S1;  // S~ (corrector)
+    double *out;       // S~ (predictor) or S^{n+1} (corrector)
+    void *bout;        // field output (field mode)
+    float *bstore;     // predictor: FP32 bilinear field of S^n (may be NULL)
+    const float *bload;  // stored-field corrector: that field
+    const float *bdip0, *bdip1;  // dipolar fields of S0 / S1 (may be NULL)
+    uint64_t step;
+};
+
+// Shape table as a static constant, so that every bond read in an unrolled
+// loop is a constant expression.
+template <int KIND>
+struct ShapeC {
+    static constexpr ShapeTable t = make_shape(KIND);
+};
+
+// Compile-time loop: f(std::integral_constant<int, k>) for k = 0 .. N-1.
+template <typename F, int... K>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, K...>) {
+    (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+__device__ __forceinline__ int zwrap(int c, int L, int per, bool &ok) {
+    if (c >= 0 && c < L) return c;
+    if (!per) { ok = false; return 0; }
+    c %= L;
+    return c < 0 ? c + L : c;
+}
+
+template <int KIND, typename T, bool ISO, int MODE>
+__global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunConst hc,
+                                                     ZWeights<T, (ISO ? 1 : 9) * make_shape(KIND).nb> W) {
+    constexpr int NSUB = ShapeC<KIND>::t.nsub, NB = ShapeC<KIND>::t.nb;
+    constexpr int RX = ShapeC<KIND>::t.rx, RY = ShapeC<KIND>::t.ry;
+    constexpr int DZLO = ShapeC<KIND>::t.dzlo, DZHI = ShapeC<KIND>::t.dzhi;
+    constexpr int D = DZHI - DZLO + 1;
+    constexpr int NIN = (MODE == ZM_CORRECT) ? 2 : 1;
+    constexpr int PW = kTX + 2 * RX, PH = kTYE + 2 * RY;
+    constexpr int PLANE = PW * PH;
+    __shared__ T lds[2][NIN][NSUB][3][PLANE];
+
+    const int tx = threadIdx.x & (kTX - 1);
+    const int ty = threadIdx.x / kTX;
+    const int x0 = blockIdx.x * kTX;
+    const int y0 = blockIdx.y * kTYE;
+    const int zs = blockIdx.z * g.zch;
+    const int nout = min(g.zch, g.Lz - zs);
+    const int nq = nout + D - 1;
+    const int64_t N = g.N;
+    // LDS inputs: the field of S0 (and of S1 for the recomputing corrector);
+    // the stored-field corrector needs only the field of S1 = S~
+    const double *src[2] = {MODE == ZM_CORRECT_STORED ? g.S1 : g.S0, g.S1};
+
+    T acc[D][kYB][NSUB][3][NIN];
+#pragma unroll
+    for (int s = 0; s < D; ++s)
+#pragma unroll
+        for (int yb = 0; yb < kYB; ++yb)
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int k = 0; k < NIN; ++k) acc[s][yb][a][c][k] = T(0);
+
+    // global -> LDS copy of input plane q (z = zs + DZLO + q) into buffer `buf`
+    auto load_plane = [&](int q, int buf) {
+        bool zok = true;
+        const int gz = zwrap(zs + DZLO + q, g.Lz, g.per[2], zok);
+        for (int idx = threadIdx.x; idx < NSUB * PLANE; idx += kThreads) {
+            const int sub = idx / PLANE;
+            const int r = idx - sub * PLANE;
+            const int cy = r / PW;
+            const int cx = r - cy * PW;
+            bool ok = zok;
+            const int gx = zwrap(x0 - RX + cx, g.Lx, g.per[0], ok);
+            const int gy = zwrap(y0 - RY + cy, g.Ly, g.per[1], ok);
+            const int64_t j = (int64_t)sub * g.M + gx + (int64_t)g.Lx * (gy + (int64_t)g.Ly * gz);
+#pragma unroll
+            for (int k = 0; k < NIN; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lds[buf][k][sub][c][r] = ok ? (T)src[k][c * N + j] : T(0);
+        }
+    };
+
+    // Epilogue of one site (sublattice a, row y, plane z) whose bilinear field
+    // sums are v[in][c].  One copy of this code serves every site of the
+    // thread: the caller selects the site's values from the register ring.
+    auto finish_site = [&](auto ac, int x, int y, int z, const T (&v)[NIN][3]) __attribute__((always_inline)) {
+        constexpr int a = decltype(ac)::value;
+        const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
+        const double sv[3] = {g.S0[i], g.S0[N + i], g.S0[2 * N + i]};
+        double ba[3];
+        aniso_field(os, a, sv, ba);
+        if constexpr (MODE == ZM_FIELD) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double b = (double)v[0][c] + ba[c] + os.bz[a][c];
+                if (g.bdip0) b += (double)g.bdip0[c * N + i];
+                ((T *)g.bout)[c * N + i] = (T)b;
+            }
+        } else if constexpr (MODE == ZM_PREDICT) {
+            double B[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (g.bstore) g.bstore[c * N + i] = (float)v[0][c];
+                double b = (double)v[0][c] + ba[c] + os.bz[a][c];
+                if (g.bdip0) b += (double)g.bdip0[c * N + i];
+                B[c] = b * hc.inv_mumuB[a];
+            }
+            if (hc.noise) {
+                double eta[3];
+                thermal_eta(hc.seed, g.step, hc.tag, (uint64_t)i, eta);
+                const double sg = hc.sigma[a];
+                B[0] += sg * eta[0];
+                B[1] += sg * eta[1];
+                B[2] += sg * eta[2];
+            }
+            double f[3];
+            llg_rhs(sv, B, hc.pre, hc.alpha, f);
+            double p[3] = {sv[0] + hc.dt * f[0], sv[1] + hc.dt * f[1], sv[2] + hc.dt * f[2]};
+            normalise3(p);
+            g.out[i] = p[0];
+            g.out[N + i] = p[1];
+            g.out[2 * N + i] = p[2];
+        } else {
+            const double st[3] = {g.S1[i], g.S1[N + i], g.S1[2 * N + i]};
+            double bt[3];
+            aniso_field(os, a, st, bt);
+            double B0[3], B1[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double bil0, bil1;
+                if constexpr (MODE == ZM_CORRECT) {
+                    bil0 = (double)v[0][c];
+                    bil1 = (double)v[NIN - 1][c];
+                } else {
+                    bil0 = (double)g.bload[c * N + i];
+                    bil1 = (double)v[0][c];
+                }
+                double v0 = bil0 + ba[c] + os.bz[a][c];
+                double v1 = bil1 + bt[c] + os.bz[a][c];
+                if (g.bdip0) v0 += (double)g.bdip0[c * N + i];
+                if (g.bdip1) v1 += (double)g.bdip1[c * N + i];
+                B0[c] = v0 * hc.inv_mumuB[a];
+                B1[c] = v1 * hc.inv_mumuB[a];
+            }
+            if (hc.noise) {
+                double eta[3];
+                thermal_eta(hc.seed, g.step, hc.tag, (uint64_t)i, eta);
+                const double sg = hc.sigma[a];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    B0[c] += sg * eta[c];
+                    B1[c] += sg * eta[c];
+                }
+            }
+            double f0[3], f1[3];
+            llg_rhs(sv, B0, hc.pre, hc.alpha, f0);
+            llg_rhs(st, B1, hc.pre, hc.alpha, f1);
+            const double hdt = 0.5 * hc.dt;
+            double p[3] = {sv[0] + hdt * (f0[0] + f1[0]), sv[1] + hdt * (f0[1] + f1[1]),
+                           sv[2] + hdt * (f0[2] + f1[2])};
+            normalise3(p);
+            g.out[i] = p[0];
+            g.out[N + i] = p[1];
+            g.out[2 * N + i] = p[2];
+        }
+    };
+
+    // acc[k] holds output plane o = q - (D-1) + k after input plane q has been
+    // pushed; input plane q feeds slot k = dzhi - dz of every bond.
+    load_plane(0, 0);
+    __syncthreads();
+    for (int q = 0; q < nq; ++q) {
+        const int buf = q & 1;
+        if (q + 1 < nq) load_plane(q + 1, buf ^ 1);
+        static_for<NB>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int kb = decltype(kc)::value;
+            constexpr ZBond bd = ShapeC<KIND>::t.bonds[kb];
+            constexpr int slot = DZHI - bd.dz;
+            static_for<kYB>([&](auto ybc) __attribute__((always_inline)) {
+                constexpr int yb = decltype(ybc)::value;
+                const int off = (ty * kYB + yb + bd.dy + RY) * PW + tx + bd.dx + RX;
+                static_for<NIN>([&](auto inc) __attribute__((always_inline)) {
+                    constexpr int in = decltype(inc)::value;
+                    const T s0 = lds[buf][in][bd.b][0][off];
+                    const T s1 = lds[buf][in][bd.b][1][off];
+                    const T s2 = lds[buf][in][bd.b][2][off];
+                    if constexpr (ISO) {
+                        const T J = W.w[kb];
+                        acc[slot][yb][bd.a][0][in] += J * s0;
+                        acc[slot][yb][bd.a][1][in] += J * s1;
+                        acc[slot][yb][bd.a][2][in] += J * s2;
+                    } else {
+                        const T *J = &W.w[9 * kb];
+                        acc[slot][yb][bd.a][0][in] += J[0] * s0 + J[1] * s1 + J[2] * s2;
+                        acc[slot][yb][bd.a][1][in] += J[3] * s0 + J[4] * s1 + J[5] * s2;
+                        acc[slot][yb][bd.a][2][in] += J[6] * s0 + J[7] * s1 + J[8] * s2;
+                    }
+                });
+            });
+        });
+        // output plane q - (D-1) (slot 0) has received all of its inputs
+        const int o = q - (D - 1);
+        if (o >= 0 && o < nout) {
+            const int x = x0 + tx;
+            // sublattices unrolled (the on-site tables are indexed by a at
+            // compile time), rows by a runtime loop with register selects
+            static_for<NSUB>([&](auto ac) __attribute__((always_inline)) {
+                constexpr int a = decltype(ac)::value;
+                // rows go through one copy of the epilogue: row yb's sums are
+                // always in fin[0], shifted down after each row
+                T fin[kYB][NIN][3];
+#pragma unroll
+                for (int yb = 0; yb < kYB; ++yb)
+#pragma unroll
+                    for (int in = 0; in < NIN; ++in)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) fin[yb][in][c] = acc[0][yb][a][c][in];
+#pragma unroll 1
+                for (int yb = 0; yb < kYB; ++yb) {
+                    const int y = y0 + ty * kYB + yb;
+                    if (x < g.Lx && y < g.Ly) finish_site(ac, x, y, zs + o, fin[0]);
+#pragma unroll
+                    for (int k = 0; k + 1 < kYB; ++k)
+#pragma unroll
+                        for (int in = 0; in < NIN; ++in)
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) fin[k][in][c] = fin[k + 1][in][c];
+                }
+            });
+        }
+        // rotate the ring: slot k <- k+1, the top slot starts a new plane
+#pragma unroll
+        for (int k = 0; k + 1 < D; ++k)
+#pragma unroll
+            for (int yb = 0; yb < kYB; ++yb)
+#pragma unroll
+                for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int in = 0; in < NIN; ++in) acc[k][yb][a][c][in] = acc[k + 1][yb][a][c][in];
+#pragma unroll
+        for (int yb = 0; yb < kYB; ++yb)
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int in = 0; in < NIN; ++in) acc[D - 1][yb][a][c][in] = T(0);
+        __syncthreads();
+    }
+}
+
+template <int KIND, typename T, bool ISO, int MODE>
+hipError_t launch_kind(const ZPlan &zp, const ZArgs &a, const Onsite &os, const HeunConst &hc, hipStream_t st) {
+    constexpr int NB = make_shape(KIND).nb;
+    constexpr int NW = (ISO ? 1 : 9) * NB;
+    ZWeights<T, NW> W;
+    for (int k = 0; k < NW; ++k) W.w[k] = (T)(sizeof(T) == 4 ? (double)zp.wf[k] : zp.wd[k]);
+    dim3 grid((unsigned)((a.Lx + kTX - 1) / kTX), (unsigned)((a.Ly + kTYE - 1) / kTYE),
+              (unsigned)((a.Lz + a.zch - 1) / a.zch));
+    k_zmarch<KIND, T, ISO, MODE><<<grid, kThreads, 0, st>>>(a, os, hc, W);
+    return hipGetLastError();
+}
+
+template <typename T, bool ISO, int MODE>
+hipError_t launch_mode(const ZPlan &zp, const ZArgs &a, const Onsite &os, const HeunConst &hc, hipStream_t st) {
+    switch (zp.kind) {
+    case SHAPE_SC_NN: return launch_kind<SHAPE_SC_NN, T, ISO, MODE>(zp, a, os, hc, st);
+    case SHAPE_SC_3SH:
+        if constexpr (ISO) return launch_kind<SHAPE_SC_3SH, T, ISO, MODE>(zp, a, os, hc, st);
+        break;
+    case SHAPE_SC_4SH:
+        if constexpr (ISO) return launch_kind<SHAPE_SC_4SH, T, ISO, MODE>(zp, a, os, hc, st);
+        break;
+    case SHAPE_BCC_5SH:
+        if constexpr (ISO && sizeof(T) == 4) return launch_kind<SHAPE_BCC_5SH, T, ISO, MODE>(zp, a, os, hc, st);
+        break;
+    default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int MODE>
+hipError_t launch_any(const ZPlan &zp, const ZArgs &a, const Onsite &os, const HeunConst &hc, hipStream_t st) {
+    if (zp.prec == 0) {
+        if (zp.iso) return launch_mode<double, true, MODE>(zp, a, os, hc, st);
+        return launch_mode<double, false, MODE>(zp, a, os, hc, st);
+    }
+    if (zp.iso) return launch_mode<float, true, MODE>(zp, a, os, hc, st);
+    return launch_mode<float, false, MODE>(zp, a, os, hc, st);
+}
+
+ZArgs make_args(const ZPlan &zp, const Grid &g) {
+    ZArgs a{};
+    a.Lx = g.Lx;
+    a.Ly = g.Ly;
+    a.Lz = g.Lz;
+    for (int k = 0; k < 3; ++k) a.per[k] = g.per[k];
+    a.M = g.M;
+    a.N = g.N;
+    a.zch = zp.zch;
+    return a;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host planning
+bool zmarch_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, const int *bond_d,
+                 const double *bond_J, int n_bonds, bool iso, ZPlan &zp) {
+    zp = ZPlan{};
+    if (prec != 0 && prec != 1) return false;
+    for (int kind = 0; kind < SHAPE_COUNT; ++kind) {
+        const ShapeTable t = make_shape(kind);
+        if (t.nsub != n_sub) continue;
+        // supported instantiations (LDS budget): tensors only on SC_NN, FP64 not on bcc
+        if (!iso && kind != SHAPE_SC_NN) continue;
+        if (prec == 0 && kind == SHAPE_BCC_5SH) continue;
+        const int nw = (iso ? 1 : 9) * t.nb;
+        std::vector<double> w(nw, 0.0);
+        bool ok = true;
+        for (int p = 0; p < n_bonds && ok; ++p) {
+            int hit = -1;
+            for (int k = 0; k < t.nb; ++k) {
+                const ZBond &z = t.bonds[k];
+                if (z.a == bond_a[p] && z.b == bond_b[p] && z.dx == bond_d[3 * p] && z.dy == bond_d[3 * p + 1] &&
+                    z.dz == bond_d[3 * p + 2]) {
+                    hit = k;
+                    break;
+                }
+            }
+            if (hit < 0) { ok = false; break; }
+            if (iso) w[hit] += bond_J[9 * p];
+            else
+                for (int e = 0; e < 9; ++e) w[9 * hit + e] += bond_J[9 * p + e];
+        }
+        if (!ok) continue;
+        zp.kind = kind;
+        zp.prec = prec;
+        zp.iso = iso ? 1 : 0;
+        zp.nw = nw;
+        for (int k = 0; k < nw; ++k) {
+            zp.wd[k] = w[k];
+            zp.wf[k] = (float)w[k];
+        }
+        zp.zch = 8;
+        zp.valid = true;
+        return true;
+    }
+    return false;
+}
+
+hipError_t zmarch_field(const ZPlan &zp, const Grid &g, const Onsite &os, const double *S, const float *bdip,
+                        void *b, hipStream_t st) {
+    ZArgs a = make_args(zp, g);
+    a.S0 = S;
+    a.bout = b;
+    a.bdip0 = bdip;
+    HeunConst hc{};
+    return launch_any<ZM_FIELD>(zp, a, os, hc, st);
+}
+
+hipError_t zmarch_predict(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
+                          const double *S, const float *bdip, double *St, float *bstore, hipStream_t st) {
+    ZArgs a = make_args(zp, g);
+    a.S0 = S;
+    a.out = St;
+    a.bdip0 = bdip;
+    a.bstore = bstore;
+    a.step = step;
+    return launch_any<ZM_PREDICT>(zp, a, os, hc, st);
+}
+
+hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
+                          const double *S, const double *St, const float *bdipS, const float *bdipT,
+                          const float *bload, double *out, hipStream_t st) {
+    ZArgs a = make_args(zp, g);
+    a.S0 = S;
+    a.S1 = St;
+    a.out = out;
+    a.bdip0 = bdipS;
+    a.bdip1 = bdipT;
+    a.bload = bload;
+    a.step = step;
+    if (bload) return launch_any<ZM_CORRECT_STORED>(zp, a, os, hc, st);
+    return launch_any<ZM_CORRECT>(zp, a, os, hc, st);
+}
+
+}  // namespace spx

@@ -1,0 +1,82 @@
+// spx_stencil.hpp -- compile-time stencil shapes for the z-marching LDS
+// stencil engine (spx_stencil.hip), shared with the host code that matches a
+// runtime bond table against them.
+//
+// A shape is the set of directed bonds (target a, source b, cell offset
+// dx, dy, dz) of one structured neighbour pattern (the "structured sparse
+// shell" kernels of the sparse backend, Methods: backend representations).
+// The couplings stay runtime values; only the offsets are compile-time, which
+// lets the kernel address LDS with immediate offsets and share neighbour
+// loads between bonds.
+#pragma once
+
+namespace spx {
+
+struct ZBond {
+    int a, b, dx, dy, dz;
+};
+
+enum ShapeKind { SHAPE_SC_NN = 0, SHAPE_SC_3SH = 1, SHAPE_SC_4SH = 2, SHAPE_BCC_5SH = 3, SHAPE_COUNT = 4 };
+
+constexpr int kMaxShapeBonds = 128;
+
+struct ShapeTable {
+    int nsub;
+    int nb;
+    ZBond bonds[kMaxShapeBonds];
+    int rx, ry, dzlo, dzhi;
+};
+
+// Squared bond length in units where the cubic cell edge is 2 (so bcc body
+// centres are integer): r2 = |2 (delta + f_b - f_a)|^2.
+constexpr int shape_r2(int kind, int a, int b, int dx, int dy, int dz) {
+    int ox = 2 * dx, oy = 2 * dy, oz = 2 * dz;
+    if (kind == SHAPE_BCC_5SH) {
+        const int s = (b - a);  // body centre at (1,1,1) in these units
+        ox += s;
+        oy += s;
+        oz += s;
+    }
+    return ox * ox + oy * oy + oz * oz;
+}
+
+// Membership of a bond in the shape, by squared length (shell radii).
+constexpr bool shape_has(int kind, int r2) {
+    switch (kind) {
+    case SHAPE_SC_NN: return r2 == 4;                                   // shell 1
+    case SHAPE_SC_3SH: return r2 == 4 || r2 == 8 || r2 == 12;           // shells 1-3
+    case SHAPE_SC_4SH: return r2 == 4 || r2 == 8 || r2 == 12 || r2 == 16;  // shells 1-4
+    case SHAPE_BCC_5SH: return r2 == 3 || r2 == 4 || r2 == 8 || r2 == 11 || r2 == 12;  // shells 1-5
+    default: return false;
+    }
+}
+
+constexpr int shape_nsub(int kind) { return kind == SHAPE_BCC_5SH ? 2 : 1; }
+
+// Bonds ordered by (a, dz, b, dy, dx).
+constexpr ShapeTable make_shape(int kind) {
+    ShapeTable t{};
+    t.nsub = shape_nsub(kind);
+    t.nb = 0;
+    t.rx = t.ry = 0;
+    t.dzlo = 0;
+    t.dzhi = 0;
+    for (int a = 0; a < t.nsub; ++a)
+        for (int dz = -2; dz <= 2; ++dz)
+            for (int b = 0; b < t.nsub; ++b)
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        const int r2 = shape_r2(kind, a, b, dx, dy, dz);
+                        if (r2 == 0 || !shape_has(kind, r2)) continue;
+                        t.bonds[t.nb] = ZBond{a, b, dx, dy, dz};
+                        t.nb++;
+                        const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+                        if (ax > t.rx) t.rx = ax;
+                        if (ay > t.ry) t.ry = ay;
+                        if (dz < t.dzlo) t.dzlo = dz;
+                        if (dz > t.dzhi) t.dzhi = dz;
+                    }
+    return t;
+}
+
+}  // namespace spx

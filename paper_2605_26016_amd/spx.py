@@ -46,7 +46,8 @@ class ModelDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("field_prec", C.c_int32), ("backend", C.c_int32), ("autotune", C.c_int32),
-                ("tune_cache_path", C.c_char_p)]
+                ("tune_cache_path", C.c_char_p), ("stencil_engine", C.c_int32), ("zchunk", C.c_int32),
+                ("heun_field", C.c_int32)]
 
 
 class LlgParams(C.Structure):
@@ -58,7 +59,8 @@ class LlgParams(C.Structure):
 class HamInfo(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_bonds", C.c_int32), ("field_prec", C.c_int32),
                 ("backend", C.c_int32), ("radius", C.c_int32 * 3), ("dipolar", C.c_int32),
-                ("workspace_bytes", C.c_int64)]
+                ("workspace_bytes", C.c_int64), ("stencil_engine", C.c_int32), ("shape", C.c_int32),
+                ("zchunk", C.c_int32), ("heun_field", C.c_int32)]
 
 
 _lib = None
@@ -85,6 +87,8 @@ def load(path: str = LIB_PATH):
         "spx_philox4x32_10": [vp, vp, i64, vp, vp],
         "spx_get_info": [vp, C.POINTER(HamInfo)],
         "spx_get_bonds": [vp, vp, vp, vp],
+        "spx_set_kernel_timing": [vp, i32],
+        "spx_get_kernel_times": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -188,7 +192,8 @@ class Hamiltonian:
 def setup_hamiltonian(dims: Sequence[int], cell=None, sub_frac=((0.0, 0.0, 0.0),), mu=(1.0,),
                       periodic=(1, 1, 1), J_shell=None, D_shell=None, bonds=None, K=None,
                       K_axis=None, B=(0.0, 0.0, 0.0), dipolar=0, field_prec="fp64", backend=0,
-                      autotune=0, tune_cache_path=None, stream=None) -> Hamiltonian:
+                      autotune=0, tune_cache_path=None, stencil_engine=0, zchunk=0, heun_field=0,
+                      stream=None) -> Hamiltonian:
     """Wraps spx_setup_hamiltonian.  K: [n_sub][n_aniso] meV (or scalar applied
     to every sublattice with one axis), K_axis: matching unit vectors.
     bonds = (ab [n][2], delta [n][3], J [n][9]) overrides the shells."""
@@ -244,6 +249,9 @@ def setup_hamiltonian(dims: Sequence[int], cell=None, sub_frac=((0.0, 0.0, 0.0),
     o.backend = int(backend)
     o.autotune = int(autotune)
     o.tune_cache_path = None if tune_cache_path is None else tune_cache_path.encode()
+    o.stencil_engine = int(stencil_engine)
+    o.zchunk = int(zchunk)
+    o.heun_field = int(heun_field)
     h = C.c_void_p()
     _check(L.spx_setup_hamiltonian(C.byref(lat), C.byref(m), C.byref(o), _stream(stream), C.byref(h)),
            "spx_setup_hamiltonian")
@@ -293,3 +301,19 @@ def get_bonds(h):
     J = np.zeros(9 * max(n, 1), np.float64)
     _check(load().spx_get_bonds(_h(h), ab.ctypes.data, dl.ctypes.data, J.ctypes.data), "spx_get_bonds")
     return ab[:2 * n].reshape(n, 2), dl[:3 * n].reshape(n, 3), J[:9 * n].reshape(n, 3, 3)
+
+
+KERNEL_KINDS = {"heun_predict": 0, "heun_correct": 1, "field": 2}
+
+
+def set_kernel_timing(h, enable=True):
+    _check(load().spx_set_kernel_timing(_h(h), int(bool(enable))), "spx_set_kernel_timing")
+
+
+def get_kernel_times(h, kind):
+    """(launch count, summed duration in ms) of one kernel kind since the last query."""
+    k = KERNEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+    n = C.c_int64()
+    t = C.c_double()
+    _check(load().spx_get_kernel_times(_h(h), k, C.byref(n), C.byref(t)), "spx_get_kernel_times")
+    return int(n.value), float(t.value)

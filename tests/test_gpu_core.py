@@ -28,9 +28,9 @@ def _gpu():
     print("GPU:", torch.cuda.get_device_name(0), flush=True)
 
 
-def gpu_field(w, S, prec=None):
+def gpu_field(w, S, prec=None, **kw):
     import torch
-    h = gpu_hamiltonian(w, field_prec=prec)
+    h = gpu_hamiltonian(w, field_prec=prec, **kw)
     dt = torch.float64 if (prec or w.field_prec) == "fp64" else torch.float32
     b = torch.empty((3, w.N), dtype=dt, device="cuda")
     from paper_2605_26016_amd import spx
@@ -57,12 +57,33 @@ FIELD_CASES = [
 ]
 
 
+# engine: 1 = table-driven gather kernel, 0 = auto (z-march LDS engine when
+# the bond table matches a built-in shell shape), plus a small z chunk that
+# puts block boundaries inside the lattice
+ENGINES = [dict(stencil_engine=1), dict(stencil_engine=0), dict(stencil_engine=0, zchunk=3)]
+
+
+@pytest.mark.parametrize("eng", ENGINES, ids=["gather", "auto", "auto_z3"])
 @pytest.mark.parametrize("name,w,prec,tol", FIELD_CASES, ids=[c[0] for c in FIELD_CASES])
-def test_field_parity(name, w, prec, tol):
+def test_field_parity(name, w, prec, tol, eng):
     S = random_sphere(w.N, 31)
     ref = oracle.field(oracle_model(w), S)
-    got = gpu_field(w, S, prec)
+    got = gpu_field(w, S, prec, **eng)
     assert max_rel(got, ref) <= tol, (name, max_rel(got, ref))
+
+
+def test_zmarch_engine_selected_for_shell_shapes():
+    from paper_2605_26016_amd import spx
+    for w, prec, shape in ((sc_nn_fp64((8, 8, 8)), "fp64", 0), (bcc_5shell_stochastic((8, 8, 8)), "fp32", 3),
+                           (Workload(name="t", L=(8, 8, 8), J_shell=(1.0, 0.2, 0.1)), "fp64", 1),
+                           (Workload(name="t", L=(8, 8, 8), J_shell=(1.0, 0.2, 0.1, 0.3)), "fp32", 2),
+                           (Workload(name="t", L=(8, 8, 8), J_shell=(1.0,), D_shell=(0.3,)), "fp32", 0)):
+        info = spx.get_info(gpu_hamiltonian(w, field_prec=prec))
+        assert info.stencil_engine == 2 and info.shape == shape, (w.J_shell, info.shape)
+    w = Workload(name="t", L=(8, 8, 8), J_shell=(1.0, 0.2), D_shell=(0.3, 0.1))
+    assert spx.get_info(gpu_hamiltonian(w, field_prec="fp32")).stencil_engine == 1
+    with pytest.raises(spx.SpxError):
+        gpu_hamiltonian(w, field_prec="fp32", stencil_engine=2)
 
 
 def test_bond_table_matches_oracle():
@@ -127,10 +148,10 @@ def test_energy_parity(name, w, prec, tol):
     assert E2.item() == E.item()
 
 
-def gpu_heun(w, S, prec, **kw):
+def gpu_heun(w, S, prec, setup=None, **kw):
     import torch
     from paper_2605_26016_amd import spx
-    h = gpu_hamiltonian(w, field_prec=prec)
+    h = gpu_hamiltonian(w, field_prec=prec, **(setup or {}))
     St = to_dev(S)
     spx.llg_heun_step(h, St, **kw)
     torch.cuda.synchronize()
@@ -150,17 +171,32 @@ HEUN_CASES = [
 ]
 
 
+HEUN_SETUPS = [dict(stencil_engine=1), dict(stencil_engine=0, heun_field=1),
+               dict(stencil_engine=0, heun_field=0, zchunk=3)]
+
+
+@pytest.mark.parametrize("setup", HEUN_SETUPS, ids=["gather", "zmarch_recompute", "auto_z3"])
 @pytest.mark.parametrize("name,w,prec,extra,tol", HEUN_CASES, ids=[c[0] for c in HEUN_CASES])
-def test_heun_parity(name, w, prec, extra, tol):
+def test_heun_parity(name, w, prec, extra, tol, setup):
     S = w.initial_state() if w.init != "random" else random_sphere(w.N, 51)
     n = extra["n_steps"]
     ref = oracle.heun(oracle_model(w), S, alpha=w.alpha, dt_fs=w.dt_fs, T_K=w.T_K, seed=w.philox_seed,
                       step0=17, n_steps=n)
-    got = gpu_heun(w, S, prec, alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed,
-                   step0=17, n_steps=n)
+    got = gpu_heun(w, S, prec, setup=setup, alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K,
+                   seed=w.philox_seed, step0=17, n_steps=n)
     err = np.max(np.abs(got - ref))
     assert err <= tol * n, (name, err)
     assert np.max(np.abs(np.sqrt((got * got).sum(0)) - 1.0)) < 1e-14
+
+
+def test_heun_stored_field_equals_recompute():
+    # the stored FP32 field of S^n is bit-identical to recomputing it
+    w = bcc_5shell_stochastic((10, 9, 7))
+    S = w.initial_state()
+    kw = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed, step0=0, n_steps=3)
+    a = gpu_heun(w, S, "fp32", setup=dict(heun_field=1), **kw)
+    b = gpu_heun(w, S, "fp32", setup=dict(heun_field=2), **kw)
+    assert np.array_equal(a, b)
 
 
 def test_heun_resume_and_determinism():
