@@ -201,6 +201,59 @@ spx_status spx_get_info(spx_ham *h, spx_ham_info *info);
  * source b, offset delta[3], tensor J[9]. */
 spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, double *bond_J);
 
+/* ---- Batched geodesic nudged elastic band (Methods, minimum-energy paths) --
+ * One object holds n_inst independent paths ("instances"), each with its own
+ * Hamiltonian (field_prec SPX_FP64, no dipolar term) and n_img[k] >= 3 images
+ * stored in the caller's buffer images[k] ([dev] double[n_img][3][N_k]),
+ * updated in place; images 0 and n_img-1 are pinned.  Every iteration runs
+ * for all unconverged instances in one set of persistent launches:
+ *   F_i   = b_i - (b_i.S_i) S_i        (projected -grad H, meV per spin)
+ *   tau   = improved (energy-weighted upwind) tangent from Y_n+1 - Y_n and
+ *           Y_n - Y_n-1, projected per spin, normalised over the image
+ *   F     = F - (F.tau)tau + k (d(Y_n,Y_n+1) - d(Y_n-1,Y_n)) tau     (GNEB)
+ *   F     = F - 2 (F.tau)tau on the highest-energy movable image (climbing)
+ *   d     = geodesic distance [sum_i angle(S_i, S'_i)^2]^(1/2)
+ * followed by velocity projection over all movable images of the instance
+ * (v <- (v.F/F.F) F if v.F > 0 else 0; v += (dt/m) F) and the exponential-map
+ * retraction S <- cos|u| S + sin|u| u/|u| with u = P_perp(dt v).
+ * ci_mode: 0 no climbing image, 1 climbing image switched on once max |F|
+ * < ci_on_below, 2 from the start.  An instance stops (and is frozen) once
+ * max |F| < tol_force (and, for ci_mode 1, the climbing image is on);
+ * tol_force = 0 never stops.  Deterministic, fixed-order reductions. */
+typedef struct {
+    double spring_k;     /* meV / rad^2 */
+    double vp_dt;        /* velocity-projection time step */
+    double vp_mass;
+    int32_t ci_mode;
+    double ci_on_below;  /* meV */
+    double tol_force;    /* meV */
+} spx_gneb_params;
+
+/* Validates the instances and allocates the library-owned ping-pong images,
+ * velocities, forces and reduction scratch (synchronous).  The caller's
+ * images are the starting path. */
+spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *images, const int32_t *n_img,
+                           const spx_gneb_params *p, void *stream, spx_gneb **out);
+spx_status spx_gneb_destroy(spx_gneb *g);
+/* Initial path (method 0: geodesic): image n at t = n/(n_img-1) on every
+ * spin's great circle between the two end images; antiparallel end spins
+ * rotate about normalize(S_A x e_k), e_k the Cartesian axis least aligned with
+ * S_A (first on ties).  Resets velocities, counters and the climbing switch. */
+spx_status spx_gneb_init_path(spx_gneb *g, int32_t method, void *stream);
+/* n_iter iterations for every unconverged instance (captured once as a
+ * hipGraph and replayed).  On return the caller's buffers hold the state. */
+spx_status spx_gneb_step(spx_gneb *g, int32_t n_iter, void *stream);
+/* Per-instance statistics after the last iteration (synchronises): energies
+ * E[n_img] (meV), distances dist[n_img-1], max |F| per spin over movable images
+ * (meV, the force of the last iteration before its update), climbing-image
+ * index (-1 if none), climbing switch, iterations run, converged flag.  Any
+ * output pointer may be NULL (host memory). */
+spx_status spx_gneb_get_stats(spx_gneb *g, int32_t inst, double *E, double *dist, double *max_force,
+                              int32_t *ci_index, int32_t *ci_on, int32_t *iterations, int32_t *converged,
+                              void *stream);
+/* 1 (default): replay one captured hipGraph per iteration; 0: direct launches. */
+spx_status spx_gneb_set_graph(spx_gneb *g, int32_t enable);
+
 /* Kernel timing instrumentation (Methods, performance measurements: device
  * time of the hot kernels).  With enable = 1 every launch of the Heun
  * predictor (kind 0), Heun corrector (kind 1) and field kernel (kind 2) on

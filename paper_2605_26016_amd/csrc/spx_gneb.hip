@@ -1,0 +1,713 @@
+// spx_gneb.hip -- batched geodesic nudged elastic band (GNEB) with velocity
+// projection and the exponential-map retraction, for many images of many
+// ragged lattices in one set of persistent launches (Methods, static
+// optimisation and minimum-energy paths).
+//
+// Work decomposition: every (instance, image, 256-site tile) is one item of a
+// flat list; each per-site pass is one grid-stride launch over the items of
+// all instances.  One iteration is
+//   pass A  (all images)      field, energy, projected force F, distance terms
+//   reduce  (per image)       E_n, d(Y_n, Y_n+1)^2           fixed order
+//   scalars (per instance)    climbing image, tangent weights
+//   pass B  (movable images)  tangent tau, dots tau.tau F.tau v.tau v.F F.F
+//   reduce  (per image)
+//   scalars (per instance)    c_n, VP projection v.F/F.F from image sums
+//   pass C  (movable images)  F_gneb = F + c_n tau^, VP velocity, exp-map step
+//   reduce + scalars          max |F_gneb|, CI switch, convergence, buffer flip
+// All per-instance control state lives on the device, so an iteration needs
+// no host synchronisation and can be captured once in a hipGraph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "spx_device.hpp"
+#include "spx_ext.hpp"
+
+namespace spx {
+namespace {
+
+constexpr int kGB = 256;  // sites per item / threads per block
+
+// per-image statistics
+enum { IS_E = 0, IS_D2, IS_TT, IS_FT, IS_VT, IS_VF, IS_FF, IS_COEF, IS_TN, IS_WP, IS_WM, IS_N };
+// per-instance state
+enum { ST_PROJ = 0, ST_MAXF, ST_CI, ST_CION, ST_ITER, ST_DONE, ST_CUR, ST_N };
+
+struct GInst {
+    Grid g;
+    BondTable tb;
+    const Onsite *os;     // device copy
+    int n_img;
+    int item0;            // first item (all images) of this instance
+    int items_per_img;
+    double *Y[2];         // image buffers [n_img][3][N]; Y[0] is the caller's
+    double *V;            // velocities
+    double *F;            // projected physical force, then nothing else
+    double *img;          // [n_img][IS_N]
+    double *st;           // [ST_N]
+    double k, dt, mass, ci_on_below, tol;
+    int ci_mode;
+};
+
+struct GItem {
+    int inst, img, site0, pad;
+};
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kGB / 64; ++k) t += red[k];
+    return t;  // valid in thread 0
+}
+
+__device__ __forceinline__ double block_max(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kGB / 64; ++k) t = fmax(t, red[k]);
+    return t;
+}
+
+__device__ __forceinline__ void ld3(const double *p, int64_t N, int64_t i, double v[3]) {
+    v[0] = p[i];
+    v[1] = p[N + i];
+    v[2] = p[2 * N + i];
+}
+
+// geodesic angle atan2(|a x b|, a.b) (= arccos(a.b), accurate near 0 and pi)
+__device__ __forceinline__ double angle3(const double a[3], const double b[3]) {
+    const double c0 = a[1] * b[2] - a[2] * b[1];
+    const double c1 = a[2] * b[0] - a[0] * b[2];
+    const double c2 = a[0] * b[1] - a[1] * b[0];
+    return atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+}
+
+// ---------------------------------------------------------------- pass A
+__global__ __launch_bounds__(kGB) void k_gneb_a(const GInst *__restrict__ inst, const GItem *__restrict__ items,
+                                                int n_items, double *__restrict__ partial) {
+    __shared__ double red[kGB / 64];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const GItem itm = items[it];
+        const GInst &G = inst[itm.inst];
+        double e = 0.0, d2 = 0.0;
+        const bool active = G.st[ST_DONE] == 0.0;
+        if (active) {
+            const int cur = (int)G.st[ST_CUR];
+            const int64_t N = G.g.N;
+            const int64_t t = (int64_t)itm.site0 + threadIdx.x;
+            if (t < N) {
+                const double *S = G.Y[cur] + (int64_t)itm.img * 3 * N;
+                const int a = (int)(t / G.g.M);
+                int x, y, z;
+                site_xyz(G.g, (int)(t - (int64_t)a * G.g.M), x, y, z);
+                double acc[1][3];
+                const double *const src[1] = {S};
+                if (G.tb.iso) bil_sum<double, true, 1>(G.tb, G.g, a, x, y, z, src, acc);
+                else bil_sum<double, false, 1>(G.tb, G.g, a, x, y, z, src, acc);
+                double s[3], ba[3];
+                ld3(S, N, t, s);
+                aniso_field(*G.os, a, s, ba);
+                double b[3];
+                double sb = 0, sz = 0, sa = 0;
+                for (int c = 0; c < 3; ++c) {
+                    b[c] = acc[0][c] + ba[c] + G.os->bz[a][c];
+                    sb += s[c] * acc[0][c];
+                    sz += s[c] * G.os->bz[a][c];
+                    sa += s[c] * ba[c];
+                }
+                e = -0.5 * sb - sz - 0.5 * sa;
+                if (itm.img > 0 && itm.img < G.n_img - 1) {
+                    const double bs = b[0] * s[0] + b[1] * s[1] + b[2] * s[2];
+                    double *F = G.F + (int64_t)itm.img * 3 * N;
+                    for (int c = 0; c < 3; ++c) F[c * N + t] = b[c] - bs * s[c];
+                }
+                if (itm.img < G.n_img - 1) {
+                    double s2[3];
+                    ld3(S + 3 * N, N, t, s2);
+                    const double th = angle3(s, s2);
+                    d2 = th * th;
+                }
+            }
+        }
+        const double es = block_sum(e, red);
+        const double ds = block_sum(d2, red);
+        if (threadIdx.x == 0) {
+            partial[(size_t)it * 2] = es;
+            partial[(size_t)it * 2 + 1] = ds;
+        }
+    }
+}
+
+// per-image fixed-order reduction of `nv` partial values per item into
+// img[IS_base + v]; one block per (instance, image) with a flat index
+__global__ __launch_bounds__(kGB) void k_gneb_reduce(const GInst *__restrict__ inst, const int2 *__restrict__ imgs,
+                                                     const double *__restrict__ partial, int nv, int base,
+                                                     int only_movable) {
+    __shared__ double red[kGB / 64];
+    const int2 ii = imgs[blockIdx.x];
+    const GInst &G = inst[ii.x];
+    if (G.st[ST_DONE] != 0.0) return;
+    if (only_movable && (ii.y == 0 || ii.y == G.n_img - 1)) return;
+    const int first = G.item0 + ii.y * G.items_per_img;
+    for (int v = 0; v < nv; ++v) {
+        double s = 0.0;
+        for (int k = threadIdx.x; k < G.items_per_img; k += kGB) s += partial[(size_t)(first + k) * nv + v];
+        const double t = block_sum(s, red);
+        if (threadIdx.x == 0) G.img[ii.y * IS_N + base + v] = t;
+    }
+}
+
+// climbing image and tangent weights (Henkelman-Jonsson improved tangent)
+__global__ void k_gneb_scalars1(const GInst *__restrict__ inst, int n_inst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    const GInst &G = inst[k];
+    if (G.st[ST_DONE] != 0.0) return;
+    double *im = G.img;
+    int ci = -1;
+    if (G.ci_mode == 2 || (G.ci_mode == 1 && G.st[ST_CION] != 0.0)) {
+        for (int n = 1; n + 1 < G.n_img; ++n)
+            if (ci < 0 || im[n * IS_N + IS_E] > im[ci * IS_N + IS_E]) ci = n;
+    }
+    G.st[ST_CI] = (double)ci;
+    for (int n = 1; n + 1 < G.n_img; ++n) {
+        const double Ep = im[(n + 1) * IS_N + IS_E], Em = im[(n - 1) * IS_N + IS_E], E0 = im[n * IS_N + IS_E];
+        double wp, wm;
+        if (Ep > E0 && E0 > Em) { wp = 1.0; wm = 0.0; }
+        else if (Ep < E0 && E0 < Em) { wp = 0.0; wm = 1.0; }
+        else {
+            const double dmax = fmax(fabs(Ep - E0), fabs(Em - E0));
+            const double dmin = fmin(fabs(Ep - E0), fabs(Em - E0));
+            if (Ep > Em) { wp = dmax; wm = dmin; } else { wp = dmin; wm = dmax; }
+        }
+        im[n * IS_N + IS_WP] = wp;
+        im[n * IS_N + IS_WM] = wm;
+    }
+}
+
+// tangent of image n at site t (projected on the tangent plane, unnormalised)
+__device__ __forceinline__ void tangent_at(const GInst &G, const double *S, int64_t N, int64_t t, double wp,
+                                           double wm, const double s[3], double tau[3]) {
+    double sp[3], sm[3];
+    ld3(S + 3 * N, N, t, sp);
+    ld3(S - 3 * N, N, t, sm);
+    for (int c = 0; c < 3; ++c) tau[c] = wp * (sp[c] - s[c]) + wm * (s[c] - sm[c]);
+    const double ts = tau[0] * s[0] + tau[1] * s[1] + tau[2] * s[2];
+    for (int c = 0; c < 3; ++c) tau[c] -= ts * s[c];
+}
+
+// ---------------------------------------------------------------- pass B
+__global__ __launch_bounds__(kGB) void k_gneb_b(const GInst *__restrict__ inst, const GItem *__restrict__ items,
+                                                int n_items, double *__restrict__ partial) {
+    __shared__ double red[kGB / 64];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const GItem itm = items[it];
+        const GInst &G = inst[itm.inst];
+        double v5[5] = {0, 0, 0, 0, 0};
+        const bool movable = itm.img > 0 && itm.img < G.n_img - 1;
+        if (G.st[ST_DONE] == 0.0 && movable) {
+            const int64_t N = G.g.N;
+            const int64_t t = (int64_t)itm.site0 + threadIdx.x;
+            if (t < N) {
+                const int cur = (int)G.st[ST_CUR];
+                const double *S = G.Y[cur] + (int64_t)itm.img * 3 * N;
+                const double *im = G.img + itm.img * IS_N;
+                double s[3], tau[3], f[3], v[3];
+                ld3(S, N, t, s);
+                tangent_at(G, S, N, t, im[IS_WP], im[IS_WM], s, tau);
+                ld3(G.F + (int64_t)itm.img * 3 * N, N, t, f);
+                ld3(G.V + (int64_t)itm.img * 3 * N, N, t, v);
+                for (int c = 0; c < 3; ++c) {
+                    v5[0] += tau[c] * tau[c];
+                    v5[1] += f[c] * tau[c];
+                    v5[2] += v[c] * tau[c];
+                    v5[3] += v[c] * f[c];
+                    v5[4] += f[c] * f[c];
+                }
+            }
+        }
+        for (int q = 0; q < 5; ++q) {
+            const double r = block_sum(v5[q], red);
+            if (threadIdx.x == 0) partial[(size_t)it * 5 + q] = r;
+        }
+    }
+}
+
+// GNEB coefficients c_n and the VP projection from the image sums:
+// F_gneb = F + c_n tau^, c_n = -2 F.tau^ on the climbing image, else
+// -F.tau^ + k (d_n - d_{n-1});  v.F_gneb and F_gneb.F_gneb follow in closed form.
+__global__ void k_gneb_scalars2(const GInst *__restrict__ inst, int n_inst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    const GInst &G = inst[k];
+    if (G.st[ST_DONE] != 0.0) return;
+    double *im = G.img;
+    const int ci = (int)G.st[ST_CI];
+    double P = 0.0, Q = 0.0;
+    for (int n = 1; n + 1 < G.n_img; ++n) {
+        double *r = im + n * IS_N;
+        const double tn = sqrt(r[IS_TT]);
+        r[IS_TN] = tn;
+        const double ft = tn > 0.0 ? r[IS_FT] / tn : 0.0;
+        const double vt = tn > 0.0 ? r[IS_VT] / tn : 0.0;
+        double c;
+        if (n == ci) c = -2.0 * ft;
+        else c = -ft + G.k * (sqrt(im[n * IS_N + IS_D2]) - sqrt(im[(n - 1) * IS_N + IS_D2]));
+        if (!(tn > 0.0)) c = 0.0;
+        r[IS_COEF] = c;
+        P += r[IS_VF] + c * vt;
+        Q += r[IS_FF] + 2.0 * c * ft + c * c;
+    }
+    G.st[ST_PROJ] = (P > 0.0 && Q > 0.0) ? P / Q : 0.0;
+}
+
+// ---------------------------------------------------------------- pass C
+__global__ __launch_bounds__(kGB) void k_gneb_c(const GInst *__restrict__ inst, const GItem *__restrict__ items,
+                                                int n_items, double *__restrict__ partial) {
+    __shared__ double red[kGB / 64];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const GItem itm = items[it];
+        const GInst &G = inst[itm.inst];
+        double fm = 0.0;
+        const bool movable = itm.img > 0 && itm.img < G.n_img - 1;
+        if (G.st[ST_DONE] == 0.0 && movable) {
+            const int64_t N = G.g.N;
+            const int64_t t = (int64_t)itm.site0 + threadIdx.x;
+            if (t < N) {
+                const int cur = (int)G.st[ST_CUR];
+                const int64_t off = (int64_t)itm.img * 3 * N;
+                const double *S = G.Y[cur] + off;
+                const double *im = G.img + itm.img * IS_N;
+                double s[3], tau[3], f[3];
+                ld3(S, N, t, s);
+                tangent_at(G, S, N, t, im[IS_WP], im[IS_WM], s, tau);
+                ld3(G.F + off, N, t, f);
+                const double tn = im[IS_TN], c = im[IS_COEF];
+                const double proj = G.st[ST_PROJ];
+                double u[3];
+                double f2 = 0.0;
+                for (int q = 0; q < 3; ++q) {
+                    const double th = tn > 0.0 ? tau[q] / tn : 0.0;
+                    const double ft = f[q] + c * th;
+                    f2 += ft * ft;
+                    const double v = proj * ft + (G.dt / G.mass) * ft;
+                    G.V[off + q * N + t] = v;
+                    u[q] = G.dt * v;
+                }
+                fm = sqrt(f2);
+                const double us = u[0] * s[0] + u[1] * s[1] + u[2] * s[2];
+                for (int q = 0; q < 3; ++q) u[q] -= us * s[q];
+                // exponential map cos|u| S + sin|u| u/|u|, then renormalise
+                const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                double o[3];
+                if (un == 0.0) {
+                    o[0] = s[0]; o[1] = s[1]; o[2] = s[2];
+                } else {
+                    const double cs = cos(un), sn = sin(un) / un;
+                    for (int q = 0; q < 3; ++q) o[q] = cs * s[q] + sn * u[q];
+                    normalise3(o);
+                }
+                double *Sn = G.Y[cur ^ 1] + off;
+                for (int q = 0; q < 3; ++q) Sn[q * N + t] = o[q];
+            }
+        }
+        const double r = block_max(fm, red);
+        if (threadIdx.x == 0) partial[it] = r;
+    }
+}
+
+// max |F_gneb| per instance, climbing-image switch, convergence, buffer flip
+__global__ __launch_bounds__(kGB) void k_gneb_finish(const GInst *__restrict__ inst, const double *__restrict__ partial) {
+    __shared__ double red[kGB / 64];
+    const GInst &G = inst[blockIdx.x];
+    if (G.st[ST_DONE] != 0.0) return;
+    const int first = G.item0 + G.items_per_img;               // image 1
+    const int count = (G.n_img - 2) * G.items_per_img;         // movable images
+    double m = 0.0;
+    for (int k = threadIdx.x; k < count; k += kGB) m = fmax(m, partial[first + k]);
+    const double mx = block_max(m, red);
+    if (threadIdx.x == 0) {
+        G.st[ST_MAXF] = mx;
+        G.st[ST_ITER] += 1.0;
+        G.st[ST_CUR] = 1.0 - G.st[ST_CUR];
+        const bool ci_ready = G.ci_mode != 1 || G.st[ST_CION] != 0.0;
+        if (G.ci_mode == 1 && G.st[ST_CION] == 0.0 && mx < G.ci_on_below) G.st[ST_CION] = 1.0;
+        if (G.tol > 0.0 && mx < G.tol && ci_ready) G.st[ST_DONE] = 1.0;
+    }
+}
+
+// bring the state back to the caller's buffer Y[0] (after an odd number of flips)
+__global__ __launch_bounds__(kGB) void k_gneb_copyback(const GInst *__restrict__ inst, const GItem *__restrict__ items,
+                                                       int n_items) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const GItem itm = items[it];
+        const GInst &G = inst[itm.inst];
+        if (G.st[ST_CUR] == 0.0) continue;
+        const int64_t N = G.g.N;
+        const int64_t t = (int64_t)itm.site0 + threadIdx.x;
+        if (t >= N) continue;
+        const int64_t off = (int64_t)itm.img * 3 * N;
+        for (int q = 0; q < 3; ++q) G.Y[0][off + q * N + t] = G.Y[1][off + q * N + t];
+    }
+}
+
+__global__ void k_gneb_cur_reset(const GInst *__restrict__ inst, int n_inst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_inst) inst[k].st[ST_CUR] = 0.0;
+}
+
+// Geodesic initial path from the end images of Y[0]: image n at t = n/(n_img-1)
+// on each spin's great circle; antiparallel pairs rotate about
+// normalize(S_A x e_k), e_k the Cartesian axis least aligned with S_A.  Also
+// copies the end images into Y[1] and clears the velocities.
+__global__ __launch_bounds__(kGB) void k_gneb_geodesic(const GInst *__restrict__ inst, const GItem *__restrict__ items,
+                                                       int n_items) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const GItem itm = items[it];
+        const GInst &G = inst[itm.inst];
+        const int64_t N = G.g.N;
+        const int64_t t = (int64_t)itm.site0 + threadIdx.x;
+        if (t >= N) continue;
+        const int64_t off = (int64_t)itm.img * 3 * N;
+        const int last = G.n_img - 1;
+        double a[3], b[3], p[3];
+        ld3(G.Y[0], N, t, a);
+        ld3(G.Y[0] + (int64_t)last * 3 * N, N, t, b);
+        if (itm.img == 0 || itm.img == last) {
+            const double *src = itm.img == 0 ? a : b;
+            for (int q = 0; q < 3; ++q) p[q] = src[q];
+        } else {
+            const double tt = (double)itm.img / (double)last;
+            const double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+            double w[3] = {b[0] - dot * a[0], b[1] - dot * a[1], b[2] - dot * a[2]};
+            const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+            double e[3], ang;
+            bool same = false;
+            if (wn < 1e-10) {
+                if (dot > 0) {
+                    same = true;
+                    ang = 0.0;
+                    e[0] = e[1] = e[2] = 0.0;
+                } else {
+                    int kx = 0;
+                    double best = fabs(a[0]);
+                    if (fabs(a[1]) < best) { best = fabs(a[1]); kx = 1; }
+                    if (fabs(a[2]) < best) { kx = 2; }
+                    double ek[3] = {0, 0, 0};
+                    ek[kx] = 1.0;
+                    double ax[3] = {a[1] * ek[2] - a[2] * ek[1], a[2] * ek[0] - a[0] * ek[2], a[0] * ek[1] - a[1] * ek[0]};
+                    const double an = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+                    for (int q = 0; q < 3; ++q) ax[q] /= an;
+                    e[0] = ax[1] * a[2] - ax[2] * a[1];
+                    e[1] = ax[2] * a[0] - ax[0] * a[2];
+                    e[2] = ax[0] * a[1] - ax[1] * a[0];
+                    ang = M_PI;
+                }
+            } else {
+                for (int q = 0; q < 3; ++q) e[q] = w[q] / wn;
+                ang = atan2(wn, dot);
+            }
+            if (same) {
+                for (int q = 0; q < 3; ++q) p[q] = a[q];
+            } else {
+                const double cs = cos(tt * ang), sn = sin(tt * ang);
+                for (int q = 0; q < 3; ++q) p[q] = cs * a[q] + sn * e[q];
+                normalise3(p);
+            }
+        }
+        for (int q = 0; q < 3; ++q) {
+            G.Y[0][off + q * N + t] = p[q];
+            G.Y[1][off + q * N + t] = p[q];
+            G.V[off + q * N + t] = 0.0;
+        }
+    }
+}
+
+// per-instance state reset (iteration counter, CI switch, convergence)
+__global__ void k_gneb_reset(const GInst *__restrict__ inst, int n_inst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    for (int q = 0; q < ST_N; ++q) inst[k].st[q] = 0.0;
+    inst[k].st[ST_CI] = -1.0;
+}
+
+unsigned grid_for(int n_items) {
+    return (unsigned)std::max(1, std::min(n_items, 8192));
+}
+
+}  // namespace
+}  // namespace spx
+
+using namespace spx;
+
+struct spx_gneb {
+    int n_inst = 0;
+    std::vector<GInst> hinst;
+    std::vector<int> n_img;
+    std::vector<double *> caller;
+    GInst *d_inst = nullptr;
+    GItem *d_items = nullptr;
+    int n_items = 0;
+    int2 *d_imgs = nullptr;   // (instance, image) of every image
+    int n_imgs = 0;
+    double *d_partial = nullptr;
+    std::vector<void *> owned;  // library allocations
+    hipGraphExec_t graph = nullptr;
+    hipStream_t graph_stream = nullptr;
+    int use_graph = 1;
+};
+
+namespace {
+
+spx_status gneb_alloc(spx_gneb *g, void **p, size_t bytes, const char *what) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return set_error(SPX_ERR_OUT_OF_MEMORY, std::string("hipMalloc failed for ") + what);
+    }
+    g->owned.push_back(*p);
+    return SPX_OK;
+}
+
+void gneb_free(spx_gneb *g) {
+    if (g->graph) (void)hipGraphExecDestroy(g->graph);
+    for (void *p : g->owned) (void)hipFree(p);
+    g->owned.clear();
+}
+
+// Enqueue one GNEB iteration (all instances) on stream st.
+hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
+    const unsigned gi = grid_for(g->n_items);
+    k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0);
+    k_gneb_scalars1<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
+    k_gneb_b<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 5, IS_TT, 1);
+    k_gneb_scalars2<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
+    k_gneb_c<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
+    k_gneb_finish<<<g->n_inst, kGB, 0, st>>>(g->d_inst, g->d_partial);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *images, const int32_t *n_img,
+                           const spx_gneb_params *p, void *stream, spx_gneb **out) {
+    if (!out) return set_error(SPX_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!H || !images || !n_img || !p || n_inst < 1) return set_error(SPX_ERR_INVALID_ARG, "bad GNEB arguments");
+    if (!(p->vp_dt > 0.0) || !(p->vp_mass > 0.0) || !(p->spring_k >= 0.0))
+        return set_error(SPX_ERR_INVALID_ARG, "vp_dt, vp_mass must be > 0 and spring_k >= 0");
+    if (p->ci_mode < 0 || p->ci_mode > 2) return set_error(SPX_ERR_INVALID_ARG, "ci_mode must be 0, 1 or 2");
+    hipStream_t st = (hipStream_t)stream;
+    spx_gneb *g = new spx_gneb();
+    g->n_inst = n_inst;
+    std::vector<GItem> items;
+    std::vector<int2> imgs;
+    std::vector<Onsite> onsites(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        HamView v;
+        spx_status s = get_ham_view(H[k], v);
+        if (s != SPX_OK) { delete g; return s; }
+        if (v.field_prec != SPX_FP64) {
+            delete g;
+            return set_error(SPX_ERR_INVALID_ARG, "GNEB needs Hamiltonians with field_prec SPX_FP64");
+        }
+        if (v.dip) {
+            delete g;
+            return set_error(SPX_ERR_UNSUPPORTED, "GNEB with the dipolar term is not supported");
+        }
+        if (n_img[k] < 3 || !images[k]) {
+            delete g;
+            return set_error(SPX_ERR_INVALID_ARG, "each GNEB instance needs >= 3 images and a buffer");
+        }
+        GInst gi{};
+        gi.g = v.grid;
+        gi.tb = v.tab;
+        gi.n_img = n_img[k];
+        gi.items_per_img = (int)((v.grid.N + kGB - 1) / kGB);
+        gi.item0 = (int)items.size();
+        gi.k = p->spring_k;
+        gi.dt = p->vp_dt;
+        gi.mass = p->vp_mass;
+        gi.ci_mode = p->ci_mode;
+        gi.ci_on_below = p->ci_on_below;
+        gi.tol = p->tol_force;
+        onsites[k] = v.onsite;
+        for (int n = 0; n < n_img[k]; ++n) {
+            imgs.push_back(make_int2(k, n));
+            for (int b = 0; b < gi.items_per_img; ++b) items.push_back(GItem{k, n, b * kGB, 0});
+        }
+        g->hinst.push_back(gi);
+        g->n_img.push_back(n_img[k]);
+        g->caller.push_back(images[k]);
+    }
+    if (items.size() > (size_t)INT32_MAX / 8) {
+        delete g;
+        return set_error(SPX_ERR_INVALID_ARG, "too many GNEB work items");
+    }
+    g->n_items = (int)items.size();
+    g->n_imgs = (int)imgs.size();
+    spx_status s = SPX_OK;
+    Onsite *d_os = nullptr;
+    s = gneb_alloc(g, (void **)&d_os, sizeof(Onsite) * n_inst, "GNEB on-site tables");
+    for (int k = 0; k < n_inst && s == SPX_OK; ++k) {
+        GInst &gi = g->hinst[k];
+        const size_t n3 = (size_t)3 * gi.g.N * gi.n_img;
+        gi.os = d_os + k;
+        gi.Y[0] = images[k];
+        if ((s = gneb_alloc(g, (void **)&gi.Y[1], n3 * sizeof(double), "GNEB image buffer")) != SPX_OK) break;
+        if ((s = gneb_alloc(g, (void **)&gi.V, n3 * sizeof(double), "GNEB velocities")) != SPX_OK) break;
+        if ((s = gneb_alloc(g, (void **)&gi.F, n3 * sizeof(double), "GNEB forces")) != SPX_OK) break;
+        if ((s = gneb_alloc(g, (void **)&gi.img, sizeof(double) * IS_N * gi.n_img, "GNEB image stats")) != SPX_OK) break;
+        if ((s = gneb_alloc(g, (void **)&gi.st, sizeof(double) * ST_N, "GNEB state")) != SPX_OK) break;
+    }
+    if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_inst, sizeof(GInst) * n_inst, "GNEB instances");
+    if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_items, sizeof(GItem) * items.size(), "GNEB items");
+    if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_imgs, sizeof(int2) * imgs.size(), "GNEB image list");
+    if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_partial, sizeof(double) * 5 * items.size(), "GNEB partials");
+    if (s != SPX_OK) {
+        gneb_free(g);
+        delete g;
+        return s;
+    }
+    hipError_t e = hipMemcpyAsync(d_os, onsites.data(), sizeof(Onsite) * n_inst, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->d_inst, g->hinst.data(), sizeof(GInst) * n_inst, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->d_items, items.data(), sizeof(GItem) * items.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->d_imgs, imgs.data(), sizeof(int2) * imgs.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        k_gneb_reset<<<(n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, n_inst);
+        e = hipGetLastError();
+    }
+    // both buffers start from the caller's images, velocities at rest
+    for (int k = 0; k < n_inst && e == hipSuccess; ++k) {
+        const GInst &gi = g->hinst[k];
+        const size_t bytes = sizeof(double) * 3 * gi.g.N * gi.n_img;
+        e = hipMemcpyAsync(gi.Y[1], gi.Y[0], bytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemsetAsync(gi.V, 0, bytes, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        gneb_free(g);
+        delete g;
+        return set_hip_error(e, "spx_gneb_create");
+    }
+    register_handle(g);
+    *out = g;
+    return SPX_OK;
+}
+
+spx_status spx_gneb_destroy(spx_gneb *g) {
+    if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
+    unregister_handle(g);
+    (void)hipDeviceSynchronize();
+    gneb_free(g);
+    delete g;
+    return SPX_OK;
+}
+
+spx_status spx_gneb_init_path(spx_gneb *g, int32_t method, void *stream) {
+    if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
+    if (method != 0) return set_error(SPX_ERR_INVALID_ARG, "method must be 0 (geodesic)");
+    hipStream_t st = (hipStream_t)stream;
+    k_gneb_reset<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
+    k_gneb_geodesic<<<grid_for(g->n_items), kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(e, "spx_gneb_init_path");
+    return SPX_OK;
+}
+
+spx_status spx_gneb_step(spx_gneb *g, int32_t n_iter, void *stream) {
+    if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
+    if (n_iter < 0) return set_error(SPX_ERR_INVALID_ARG, "n_iter < 0");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (g->use_graph && n_iter > 1) {
+        if (!g->graph || g->graph_stream != st) {
+            if (g->graph) (void)hipGraphExecDestroy(g->graph);
+            g->graph = nullptr;
+            hipGraph_t graph;
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = enqueue_iteration(g, st);
+                e = hipStreamEndCapture(st, &graph);
+                if (e == hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) {
+                e = hipGraphInstantiate(&g->graph, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+            }
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                g->graph = nullptr;
+                g->use_graph = 0;  // fall back to direct launches
+                e = hipSuccess;
+            } else {
+                g->graph_stream = st;
+            }
+        }
+    }
+    for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
+        if (g->graph) e = hipGraphLaunch(g->graph, st);
+        else e = enqueue_iteration(g, st);
+    }
+    if (e == hipSuccess) {
+        k_gneb_copyback<<<grid_for(g->n_items), kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items);
+        k_gneb_cur_reset<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return set_hip_error(e, "spx_gneb_step");
+    return SPX_OK;
+}
+
+spx_status spx_gneb_get_stats(spx_gneb *g, int32_t inst, double *E, double *dist, double *max_force,
+                              int32_t *ci_index, int32_t *ci_on, int32_t *iterations, int32_t *converged,
+                              void *stream) {
+    if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
+    if (inst < 0 || inst >= g->n_inst) return set_error(SPX_ERR_INVALID_ARG, "instance out of range");
+    hipStream_t st = (hipStream_t)stream;
+    const GInst &gi = g->hinst[inst];
+    std::vector<double> im(IS_N * gi.n_img), s(ST_N);
+    hipError_t e = hipMemcpyAsync(im.data(), gi.img, sizeof(double) * im.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.data(), gi.st, sizeof(double) * ST_N, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_hip_error(e, "spx_gneb_get_stats");
+    for (int n = 0; n < gi.n_img; ++n) {
+        if (E) E[n] = im[n * IS_N + IS_E];
+        if (dist && n + 1 < gi.n_img) dist[n] = std::sqrt(im[n * IS_N + IS_D2]);
+    }
+    if (max_force) *max_force = s[ST_MAXF];
+    if (ci_index) *ci_index = (int32_t)s[ST_CI];
+    if (ci_on) *ci_on = (int32_t)s[ST_CION];
+    if (iterations) *iterations = (int32_t)s[ST_ITER];
+    if (converged) *converged = (int32_t)s[ST_DONE];
+    return SPX_OK;
+}
+
+spx_status spx_gneb_set_graph(spx_gneb *g, int32_t enable) {
+    if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
+    g->use_graph = enable ? 1 : 0;
+    if (!enable && g->graph) {
+        (void)hipGraphExecDestroy(g->graph);
+        g->graph = nullptr;
+    }
+    return SPX_OK;
+}
+
+}  // extern "C"

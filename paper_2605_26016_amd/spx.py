@@ -56,6 +56,11 @@ class LlgParams(C.Structure):
                 ("tag", C.c_uint32), ("n_steps", C.c_int32)]
 
 
+class GnebParams(C.Structure):
+    _fields_ = [("spring_k", C.c_double), ("vp_dt", C.c_double), ("vp_mass", C.c_double),
+                ("ci_mode", C.c_int32), ("ci_on_below", C.c_double), ("tol_force", C.c_double)]
+
+
 class HamInfo(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_bonds", C.c_int32), ("field_prec", C.c_int32),
                 ("backend", C.c_int32), ("radius", C.c_int32 * 3), ("dipolar", C.c_int32),
@@ -88,6 +93,13 @@ def load(path: str = LIB_PATH):
         "spx_get_info": [vp, C.POINTER(HamInfo)],
         "spx_get_bonds": [vp, vp, vp, vp],
         "spx_set_kernel_timing": [vp, i32],
+        "spx_gneb_create": [C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(C.c_int32), C.POINTER(GnebParams),
+                            vp, C.POINTER(vp)],
+        "spx_gneb_destroy": [vp],
+        "spx_gneb_init_path": [vp, i32, vp],
+        "spx_gneb_step": [vp, i32, vp],
+        "spx_gneb_get_stats": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
+        "spx_gneb_set_graph": [vp, i32],
         "spx_get_kernel_times": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
     for name, args in sigs.items():
@@ -317,3 +329,62 @@ def get_kernel_times(h, kind):
     t = C.c_double()
     _check(load().spx_get_kernel_times(_h(h), k, C.byref(n), C.byref(t)), "spx_get_kernel_times")
     return int(n.value), float(t.value)
+
+
+# ---------------------------------------------------------------- GNEB
+class Gneb:
+    """Owner of an spx_gneb handle; keeps the Hamiltonians and image buffers alive."""
+
+    def __init__(self, handle, hams, images, n_img):
+        self.handle = handle
+        self.hams = list(hams)
+        self.images = list(images)
+        self.n_img = list(n_img)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                load().spx_gneb_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def gneb_create(hams, images, spring_k=1.0, vp_dt=0.1, vp_mass=1.0, ci_mode=1, ci_on_below=1e-2,
+                tol_force=0.0, stream=None) -> Gneb:
+    """images: list of device tensors [n_img][3][N_k] (updated in place)."""
+    n = len(hams)
+    H = (C.c_void_p * n)(*[_h(h) for h in hams])
+    Y = (C.c_void_p * n)(*[_ptr(y) for y in images])
+    n_img = [int(y.shape[0]) for y in images]
+    NI = (C.c_int32 * n)(*n_img)
+    p = GnebParams(float(spring_k), float(vp_dt), float(vp_mass), int(ci_mode), float(ci_on_below),
+                   float(tol_force))
+    g = C.c_void_p()
+    _check(load().spx_gneb_create(H, n, Y, NI, C.byref(p), _stream(stream), C.byref(g)), "spx_gneb_create")
+    return Gneb(g.value, hams, images, n_img)
+
+
+def gneb_init_path(g, method=0, stream=None):
+    _check(load().spx_gneb_init_path(g.handle, int(method), _stream(stream)), "spx_gneb_init_path")
+
+
+def gneb_step(g, n_iter=1, stream=None):
+    _check(load().spx_gneb_step(g.handle, int(n_iter), _stream(stream)), "spx_gneb_step")
+
+
+def gneb_set_graph(g, enable=True):
+    _check(load().spx_gneb_set_graph(g.handle, int(bool(enable))), "spx_gneb_set_graph")
+
+
+def gneb_get_stats(g, inst=0, stream=None):
+    n = g.n_img[inst]
+    E = np.zeros(n)
+    d = np.zeros(max(n - 1, 1))
+    mf = C.c_double()
+    ci, con, iters, conv = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().spx_gneb_get_stats(g.handle, int(inst), E.ctypes.data, d.ctypes.data, C.byref(mf),
+                                     C.byref(ci), C.byref(con), C.byref(iters), C.byref(conv),
+                                     _stream(stream)), "spx_gneb_get_stats")
+    return {"E": E, "dist": d[:n - 1], "max_force": mf.value, "ci_index": ci.value, "ci_on": con.value,
+            "iterations": iters.value, "converged": conv.value}
