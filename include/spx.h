@@ -254,6 +254,11 @@ spx_status spx_gneb_get_stats(spx_gneb *g, int32_t inst, double *E, double *dist
 /* 1 (default): replay one captured hipGraph per iteration; 0: direct launches. */
 spx_status spx_gneb_set_graph(spx_gneb *g, int32_t enable);
 
+/* Lane-layout check of the 32x32x16 MFMA used by the dense backend:
+ * D = A B for A [32][16], B [16][32], D [32][32] ([dev] row-major float),
+ * operands rounded to BF16 (prec 2) or FP16 (prec 3).  Test hook. */
+spx_status spx_mfma_probe(int32_t prec, const float *A, const float *B, float *D, void *stream);
+
 /* Kernel timing instrumentation (Methods, performance measurements: device
  * time of the hot kernels).  With enable = 1 every launch of the Heun
  * predictor (kind 0), Heun corrector (kind 1) and field kernel (kind 2) on

@@ -173,6 +173,7 @@ struct spx_ham {
     int64_t ws_bytes = 0;
     DipolarPlan *dip = nullptr;  // dipolar FFT workspace (NULL when off)
     float *d_bdip0 = nullptr, *d_bdip1 = nullptr;
+    DensePlan *dense = nullptr;  // dense-window MFMA backend
     // z-march engine plan (valid when the bond table matches a shell shape)
     ZPlan zp;
     int engine = 1;          // 1 gather, 2 z-march
@@ -234,6 +235,8 @@ struct KernelTimer {
 };
 
 void free_all(spx_ham *h) {
+    if (h->dense) dense_destroy(h->dense);
+    h->dense = nullptr;
     for (auto &v : h->timed)
         for (auto &pr : v) {
             (void)hipEventDestroy(pr.first);
@@ -335,8 +338,10 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     }
     if (prec >= SPX_BF16_MFMA && backend_req == 1)
         return fail(SPX_ERR_INVALID_ARG, "MFMA precisions need the dense backend");
-    if (prec >= SPX_BF16_MFMA)
-        return fail(SPX_ERR_UNSUPPORTED, "MFMA dense-window precisions are served by spx_dense_field");
+    if (backend_req == 2 && prec < SPX_BF16_MFMA)
+        return fail(SPX_ERR_INVALID_ARG, "the dense MFMA backend needs field_prec SPX_BF16_MFMA or SPX_FP16_MFMA");
+    if (prec >= SPX_BF16_MFMA && model->dipolar)
+        return fail(SPX_ERR_UNSUPPORTED, "the dense MFMA backend has no dipolar term");
     spx_status s = check_device();
     if (s != SPX_OK) return s;
 
@@ -469,8 +474,17 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
             for (int k = 0; k < 3; ++k) bd[3 * p + k] = h->bonds[p].d[k];
             for (int k = 0; k < 9; ++k) bJ[9 * p + k] = h->bonds[p].J[k];
         }
-        const bool have = nb > 0 && zmarch_plan(prec, lat->n_sub, ba.data(), bb.data(), bd.data(), bJ.data(), nb,
-                                                iso, h->zp);
+        if (prec >= SPX_BF16_MFMA) {
+            std::string why;
+            if (!dense_plan(prec, lat->n_sub, ba.data(), bb.data(), bd.data(), bJ.data(), nb, &h->dense, st, why)) {
+                free_all(h);
+                delete h;
+                return fail(SPX_ERR_UNSUPPORTED, why);
+            }
+            h->backend = 2;
+        }
+        const bool have = prec < SPX_BF16_MFMA && nb > 0 &&
+                          zmarch_plan(prec, lat->n_sub, ba.data(), bb.data(), bd.data(), bJ.data(), nb, iso, h->zp);
         if (engine_req == 2 && !have) {
             free_all(h);
             delete h;
@@ -557,7 +571,8 @@ spx_status spx_eval_field(spx_ham *h, const double *S, void *b, void *stream) {
     hipError_t e;
     {
         KernelTimer kt(h, 2, st);
-        if (h->engine == 2) e = zmarch_field(h->zp, h->grid, h->onsite, S, bdip, b, st);
+        if (h->dense) e = dense_field(h->dense, h->grid, h->onsite, S, (float *)b, st);
+        else if (h->engine == 2) e = zmarch_field(h->zp, h->grid, h->onsite, S, bdip, b, st);
         else e = launch_field(h->field_prec, h->tab, h->grid, h->onsite, S, bdip, b, st);
     }
     if (e != hipSuccess) return hip_fail(e, "spx_eval_field");
@@ -574,7 +589,9 @@ spx_status spx_energy(spx_ham *h, const double *S, double *E, double *terms, voi
         if (s != SPX_OK) return s;
         bdip = h->d_bdip0;
     }
-    hipError_t e = launch_energy(h->field_prec, h->tab, h->grid, h->onsite, S, bdip, h->d_partial, E, terms, st);
+    // the dense MFMA backend evaluates energies with the FP32 gather kernel
+    const int eprec = h->field_prec >= SPX_BF16_MFMA ? SPX_FP32 : h->field_prec;
+    hipError_t e = launch_energy(eprec, h->tab, h->grid, h->onsite, S, bdip, h->d_partial, E, terms, st);
     if (e != hipSuccess) return hip_fail(e, "spx_energy");
     return SPX_OK;
 }
@@ -588,6 +605,7 @@ spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, voi
     if (!(p->temperature_K >= 0.0)) return fail(SPX_ERR_INVALID_ARG, "temperature must be >= 0");
     if (p->temperature_K > 0.0 && p->alpha == 0.0)
         return fail(SPX_ERR_INVALID_ARG, "a thermal bath needs alpha > 0");
+    if (h->dense) return fail(SPX_ERR_UNSUPPORTED, "Heun integration runs on the sparse stencil backend");
     if (p->n_steps == 0) return SPX_OK;
     hipStream_t st = (hipStream_t)stream;
     const double gamma = (p->gamma > 0.0) ? p->gamma * 1e-15 : kGammaPerFs;  // rad/(fs T)

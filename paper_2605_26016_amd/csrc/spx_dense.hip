@@ -1,0 +1,251 @@
+// spx_dense.hip -- dense-window sublattice convolution on the gfx950 matrix
+// cores (MFMA, BF16 or FP16 operands, FP32 accumulation): the "dense
+// convolution backend" of the Methods (compact regular kernels), for a
+// single-sublattice kernel K^{ab}(delta) filling a 7^3 window.
+//
+// GEMM mapping (v_mfma_f32_32x32x16_{bf16,f16}):
+//   M = 32 output rows y (one z plane),
+//   N = 32 columns = 3 field components x 10 consecutive output x + 2 pad,
+//   K = 16 consecutive input x' of one (beta, dy, dz) run,
+// so the x-direction band of the kernel sits in the weight operand B
+// (a 16 x 32 Toeplitz slice per run, 41 % of its MACs useful) and every input
+// value is read once per run from LDS.  147 MFMAs (49 (dy,dz) x 3 beta) per
+// 320 output sites.  Weight fragments are built on the host in lane order.
+// Operands are scaled by powers of two before rounding (exact) and the
+// product scale is undone in FP32: BF16 weights so that max|K| lies in [1,2);
+// FP16 weights so that max|K| lies in [2^12, 2^13) and spins by 2^10, which
+// keeps the small far-field couplings and spin components out of FP16's
+// subnormal range.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "spx_device.hpp"
+#include "spx_ext.hpp"
+
+namespace spx {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kDX = 10;   // output x per tile
+constexpr int kDY = 32;   // output y per tile (MFMA rows)
+constexpr int kDZ = 8;    // output z per block (2 per wave)
+constexpr int kR = 3;     // window radius
+constexpr int kIX = 16;   // input x per run (kDX + 2 kR)
+constexpr int kIY = kDY + 2 * kR;
+constexpr int kIZ = kDZ + 2 * kR;
+constexpr int kRuns = 49 * 3;
+
+// one MFMA in the requested operand type; a, b are 8 raw 16-bit values
+template <bool BF16>
+__device__ __forceinline__ f32x16 mfma32(s16x8 a, s16x8 b, f32x16 c) {
+    if constexpr (BF16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+}
+
+template <bool BF16>
+__device__ __forceinline__ short to16(float v) {
+    if constexpr (BF16) return __builtin_bit_cast(short, (__bf16)v);
+    else return __builtin_bit_cast(short, (_Float16)v);
+}
+
+// Operand layout of the 32x32x16 MFMA (one wavefront): lane l holds
+//   A[row = l % 32][k = 8 (l / 32) + j],  B[k = 8 (l / 32) + j][col = l % 32],
+//   j = 0..7, and accumulator r of lane l is D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+__device__ __forceinline__ int d_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S, float *__restrict__ b,
+                                                    const s16x8 *__restrict__ wfrag, float kscale, float in_scale,
+                                                    Grid g, Onsite os) {
+    __shared__ __attribute__((aligned(16))) short tile[3][kIZ][kIY][kIX];
+    const int x0 = blockIdx.x * kDX, y0 = blockIdx.y * kDY, z0 = blockIdx.z * kDZ;
+    const int64_t N = g.N;
+    // stage the input tile (zero outside open faces, wrapped on periodic axes)
+    for (int idx = threadIdx.x; idx < kIZ * kIY * kIX; idx += 256) {
+        const int xx = idx % kIX, yy = (idx / kIX) % kIY, zz = idx / (kIX * kIY);
+        bool ok = true;
+        const int gx = wrap_coord(x0 - kR + xx, g.Lx, g.per[0], 1, ok);
+        const int gy = wrap_coord(y0 - kR + yy, g.Ly, g.per[1], 1, ok);
+        const int gz = wrap_coord(z0 - kR + zz, g.Lz, g.per[2], 1, ok);
+        const int64_t j = gx + (int64_t)g.Lx * (gy + (int64_t)g.Ly * gz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tile[c][zz][yy][xx] = to16<BF16>(ok ? (float)S[c * N + j] * in_scale : 0.0f);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int zl0 = 2 * wave;  // this wave's two output planes
+    f32x16 acc0 = {}, acc1 = {};
+    const int arow = lane & 31, ak = 8 * (lane >> 5);
+    for (int run = 0; run < kRuns; ++run) {
+        const int beta = run % 3, dyz = run / 3;
+        const int dy = dyz % 7 - kR, dz = dyz / 7 - kR;
+        const s16x8 bf = wfrag[run * 64 + lane];
+        const s16x8 a0 = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + dz + kR][arow + dy + kR][ak]);
+        const s16x8 a1 = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + 1 + dz + kR][arow + dy + kR][ak]);
+        acc0 = mfma32<BF16>(a0, bf, acc0);
+        acc1 = mfma32<BF16>(a1, bf, acc1);
+    }
+    // epilogue: column -> (component, x), row -> y; on-site terms in FP64
+    const int col = lane & 31;
+    if (col >= 3 * kDX) return;
+    const int alpha = col / kDX, x = x0 + col % kDX;
+    if (x >= g.Lx) return;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int z = z0 + zl0 + p;
+        if (z >= g.Lz) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int y = y0 + d_row(lane, r);
+            if (y >= g.Ly) continue;
+            const int64_t i = x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
+            const float v = (p == 0 ? acc0[r] : acc1[r]) * kscale;
+            const double s[3] = {S[i], S[N + i], S[2 * N + i]};
+            double ba[3];
+            aniso_field(os, 0, s, ba);
+            b[alpha * N + i] = (float)((double)v + ba[alpha] + os.bz[0][alpha]);
+        }
+    }
+}
+
+// Layout probe: D = A B for one 32x32x16 MFMA, A [32][16], B [16][32], D [32][32]
+// row-major FP32 (values exactly representable in the operand type).
+template <bool BF16>
+__global__ void k_mfma_probe(const float *__restrict__ A, const float *__restrict__ B, float *__restrict__ D) {
+    const int lane = threadIdx.x;
+    s16x8 a, bb;
+    for (int j = 0; j < 8; ++j) {
+        a[j] = to16<BF16>(A[(lane & 31) * 16 + 8 * (lane >> 5) + j]);
+        bb[j] = to16<BF16>(B[(8 * (lane >> 5) + j) * 32 + (lane & 31)]);
+    }
+    f32x16 acc = {};
+    acc = mfma32<BF16>(a, bb, acc);
+    for (int r = 0; r < 16; ++r) D[d_row(lane, r) * 32 + (lane & 31)] = acc[r];
+}
+
+}  // namespace
+
+struct DensePlan {
+    short *d_frag = nullptr;  // [kRuns][64 lanes][8]
+    float kscale = 1.0f;      // 1 / (weight scale * input scale)
+    float in_scale = 1.0f;
+    int bf16 = 1;
+};
+
+// Host: dense 7^3 window from a single-sublattice bond table (all |delta| <= 3).
+bool dense_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, const int *bond_d, const double *bond_J,
+                int n_bonds, DensePlan **out, hipStream_t st, std::string &why) {
+    *out = nullptr;
+    if (n_sub != 1) { why = "dense window needs n_sub = 1"; return false; }
+    std::vector<double> K(343 * 9, 0.0);
+    for (int p = 0; p < n_bonds; ++p) {
+        (void)bond_a;
+        (void)bond_b;
+        const int dx = bond_d[3 * p], dy = bond_d[3 * p + 1], dz = bond_d[3 * p + 2];
+        if (std::abs(dx) > kR || std::abs(dy) > kR || std::abs(dz) > kR) {
+            why = "a bond lies outside the 7^3 dense window";
+            return false;
+        }
+        const int w = (dz + kR) * 49 + (dy + kR) * 7 + (dx + kR);
+        for (int e = 0; e < 9; ++e) K[w * 9 + e] += bond_J[9 * p + e];
+    }
+    double kmax = 0.0;
+    for (double v : K) kmax = std::max(kmax, std::fabs(v));
+    if (kmax == 0.0) kmax = 1.0;
+    const bool bf = prec == 2;
+    // power-of-two scales: BF16 max|K| -> [1,2); FP16 max|K| -> [2^12, 2^13), spins x 2^10
+    const int ke = (int)std::floor(std::log2(kmax));
+    const double wscale = std::ldexp(1.0, (bf ? 0 : 12) - ke);
+    const double in_scale = bf ? 1.0 : 1024.0;
+    std::vector<short> frag((size_t)kRuns * 64 * 8, 0);
+    auto enc = [&](double v) -> short {
+        const float f = (float)(v * wscale);
+        if (bf) {
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            const uint32_t lsb = (u >> 16) & 1u;  // round to nearest even
+            u += 0x7FFFu + lsb;
+            return (short)(u >> 16);
+        }
+        const _Float16 h = (_Float16)f;
+        short s;
+        std::memcpy(&s, &h, 2);
+        return s;
+    };
+    for (int run = 0; run < kRuns; ++run) {
+        const int beta = run % 3, dyz = run / 3;
+        const int dy = dyz % 7 - kR, dz = dyz / 7 - kR;
+        for (int lane = 0; lane < 64; ++lane) {
+            const int col = lane & 31;
+            for (int j = 0; j < 8; ++j) {
+                const int xin = 8 * (lane >> 5) + j;       // input x within the run
+                double v = 0.0;
+                if (col < 3 * kDX) {
+                    const int alpha = col / kDX, xs = col % kDX;
+                    const int dx = xin - kR - xs;
+                    if (dx >= -kR && dx <= kR) {
+                        const int w = (dz + kR) * 49 + (dy + kR) * 7 + (dx + kR);
+                        v = K[w * 9 + alpha * 3 + beta];
+                    }
+                }
+                frag[((size_t)run * 64 + lane) * 8 + j] = enc(v);
+            }
+        }
+    }
+    DensePlan *p = new DensePlan();
+    p->kscale = (float)(1.0 / (wscale * in_scale));
+    p->in_scale = (float)in_scale;
+    p->bf16 = bf ? 1 : 0;
+    if (hipMalloc((void **)&p->d_frag, frag.size() * sizeof(short)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        why = "hipMalloc failed for MFMA weight fragments";
+        return false;
+    }
+    if (hipMemcpyAsync(p->d_frag, frag.data(), frag.size() * sizeof(short), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p->d_frag);
+        delete p;
+        why = "upload of MFMA weight fragments failed";
+        return false;
+    }
+    *out = p;
+    return true;
+}
+
+void dense_destroy(DensePlan *p) {
+    if (!p) return;
+    if (p->d_frag) (void)hipFree(p->d_frag);
+    delete p;
+}
+
+hipError_t dense_field(const DensePlan *p, const Grid &g, const Onsite &os, const double *S, float *b, hipStream_t st) {
+    dim3 grid((unsigned)((g.Lx + kDX - 1) / kDX), (unsigned)((g.Ly + kDY - 1) / kDY), (unsigned)((g.Lz + kDZ - 1) / kDZ));
+    if (p->bf16)
+        k_dense_mfma<true><<<grid, 256, 0, st>>>(S, b, (const s16x8 *)p->d_frag, p->kscale, p->in_scale, g, os);
+    else
+        k_dense_mfma<false><<<grid, 256, 0, st>>>(S, b, (const s16x8 *)p->d_frag, p->kscale, p->in_scale, g, os);
+    return hipGetLastError();
+}
+
+}  // namespace spx
+
+extern "C" spx_status spx_mfma_probe(int32_t prec, const float *A, const float *B, float *D, void *stream) {
+    if (!A || !B || !D || (prec != 2 && prec != 3)) return spx::set_error(SPX_ERR_INVALID_ARG, "bad probe arguments");
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == 2) spx::k_mfma_probe<true><<<1, 64, 0, st>>>(A, B, D);
+    else spx::k_mfma_probe<false><<<1, 64, 0, st>>>(A, B, D);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return spx::set_hip_error(e, "spx_mfma_probe");
+    return SPX_OK;
+}

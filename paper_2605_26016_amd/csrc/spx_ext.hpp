@@ -65,4 +65,11 @@ hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, cons
                           const double *S, const double *St, const float *bdipS, const float *bdipT,
                           const float *bload, double *out, hipStream_t st);
 
+// Dense-window MFMA field (spx_dense.hip).
+struct DensePlan;
+bool dense_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, const int *bond_d, const double *bond_J,
+                int n_bonds, DensePlan **out, hipStream_t st, std::string &why);
+void dense_destroy(DensePlan *p);
+hipError_t dense_field(const DensePlan *p, const Grid &g, const Onsite &os, const double *S, float *b, hipStream_t st);
+
 }  // namespace spx

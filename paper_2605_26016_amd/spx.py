@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "spx_gneb_step": [vp, i32, vp],
         "spx_gneb_get_stats": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "spx_gneb_set_graph": [vp, i32],
+        "spx_mfma_probe": [i32, vp, vp, vp, vp],
         "spx_get_kernel_times": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
     for name, args in sigs.items():
@@ -388,3 +389,8 @@ def gneb_get_stats(g, inst=0, stream=None):
                                      _stream(stream)), "spx_gneb_get_stats")
     return {"E": E, "dist": d[:n - 1], "max_force": mf.value, "ci_index": ci.value, "ci_on": con.value,
             "iterations": iters.value, "converged": conv.value}
+
+
+def mfma_probe(prec, A, B, D, stream=None):
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    _check(load().spx_mfma_probe(p, _ptr(A), _ptr(B), _ptr(D), _stream(stream)), "spx_mfma_probe")

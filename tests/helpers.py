@@ -48,3 +48,46 @@ def require_gpu():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+
+
+def k7_table(J=1.0, D=0.3, mu=2.0, a=0.4, dip=True):
+    """Coupling table of the dense 7^3 window used for the MFMA comparison:
+    J + bulk DMI (D along the bond) on the 6 nearest-neighbour offsets and,
+    when dip is True, the dipole tensor (mu0/4pi) mu_B^2 mu^2 (3 rr - 1)/r^3 on
+    every other offset of the window.  Returns (ab, delta, J9) bond arrays."""
+    import oracle as _o
+    pref = _o.constants()[3] * mu * mu
+    ab, dl, Js = [], [], []
+    for dz in range(-3, 4):
+        for dy in range(-3, 4):
+            for dx in range(-3, 4):
+                if dx == dy == dz == 0:
+                    continue
+                r = np.array([dx, dy, dz], float) * a
+                rn = np.linalg.norm(r)
+                u = r / rn
+                T = np.zeros((3, 3))
+                if abs(dx) + abs(dy) + abs(dz) == 1:
+                    Dv = D * u
+                    T = J * np.eye(3) + np.array([[0, Dv[2], -Dv[1]], [-Dv[2], 0, Dv[0]], [Dv[1], -Dv[0], 0]])
+                elif dip:
+                    T = pref * (3 * np.outer(u, u) - np.eye(3)) / rn ** 3
+                else:
+                    continue
+                ab.append((0, 0))
+                dl.append((dx, dy, dz))
+                Js.append(T)
+    return np.array(ab, np.int32), np.array(dl, np.int32), np.array(Js)
+
+
+def round_bf16(x):
+    """FP64 -> FP32 (nearest even) -> BF16 (nearest even), returned as FP64."""
+    f = np.asarray(x, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_fp16(x):
+    """FP64 -> FP32 (nearest even) -> FP16 (nearest even), returned as FP64."""
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
