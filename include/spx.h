@@ -60,6 +60,7 @@ typedef enum {
 
 typedef struct spx_ham spx_ham;   /* opaque Hamiltonian + workspace */
 typedef struct spx_gneb spx_gneb; /* opaque batched GNEB object */
+typedef struct spx_net spx_net;   /* opaque learned-path-corrector workspace */
 
 /* Lattice: n_sub sublattices at fractional positions in a Bravais cell,
  * dims[k] cells along lattice vector k, periodic[k] = 1 wraps that axis,
@@ -235,11 +236,15 @@ typedef struct {
 spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *images, const int32_t *n_img,
                            const spx_gneb_params *p, void *stream, spx_gneb **out);
 spx_status spx_gneb_destroy(spx_gneb *g);
-/* Initial path (method 0: geodesic): image n at t = n/(n_img-1) on every
+/* Initial path.  method 0 (geodesic): image n at t = n/(n_img-1) on every
  * spin's great circle between the two end images; antiparallel end spins
  * rotate about normalize(S_A x e_k), e_k the Cartesian axis least aligned with
- * S_A (first on ties).  Resets velocities, counters and the climbing switch. */
-spx_status spx_gneb_init_path(spx_gneb *g, int32_t method, void *stream);
+ * S_A (first on ties).  method 1 (learned): the geodesic path, then every
+ * movable image corrected by the network (spx_net_forward) with parameters
+ * `params` ([dev] float[spx_net_nparams()]); net and params are ignored for
+ * method 0.  Lattices must be single-sublattice for method 1.  Resets
+ * velocities, counters and the climbing switch. */
+spx_status spx_gneb_init_path(spx_gneb *g, int32_t method, spx_net *net, const float *params, void *stream);
 /* n_iter iterations for every unconverged instance (captured once as a
  * hipGraph and replayed).  On return the caller's buffers hold the state. */
 spx_status spx_gneb_step(spx_gneb *g, int32_t n_iter, void *stream);
@@ -253,6 +258,33 @@ spx_status spx_gneb_get_stats(spx_gneb *g, int32_t inst, double *E, double *dist
                               void *stream);
 /* 1 (default): replay one captured hipGraph per iteration; 0: direct launches. */
 spx_status spx_gneb_set_graph(spx_gneb *g, int32_t enable);
+
+/* ---- Learned initial-path corrector (spec extension; the paper only
+ * names machine-learning interfaces).  A 3^3 convolution network with
+ * channels 10 -> 16 -> 16 -> 16 -> 3, zero padding and SiLU between layers,
+ * FP32 parameters packed layer by layer as W[cout][cin][kz][ky][kx] then
+ * bias[cout].  Input channels per image: geodesic guess S_g (3), end images
+ * S_A (3), S_B (3), reaction coordinate t (1); the output u is projected on
+ * the tangent plane of S_g and applied by the exponential map
+ * S_hat = cos|u| S_g + sin|u| u/|u| (the Methods' retraction).
+ * Arrays: S_g, S_A, S_B, S_hat, S_star [dev] double[batch][3][P] for lattices
+ * dims = (Lx, Ly, Lz), P = Lx Ly Lz (single sublattice, open faces as zero
+ * padding); t [dev] float[batch]. */
+int64_t spx_net_nparams(void);
+/* channels must be {10, 16, 16, 16, 3} (or NULL); the workspace grows with use. */
+spx_status spx_net_create(const int32_t *channels, spx_net **out);
+spx_status spx_net_destroy(spx_net *net);
+spx_status spx_net_forward(spx_net *net, const float *params, const int32_t *dims, int32_t batch, const double *Sg,
+                           const double *SA, const double *SB, const float *t, double *Shat, void *stream);
+/* Gradient of loss = mean over batch and sites of |S_hat - S_star|^2 with
+ * respect to every parameter, written to grad ([dev] float, overwritten);
+ * loss ([dev] double) may be NULL.  Deterministic fixed-order reductions. */
+spx_status spx_net_backward(spx_net *net, const float *params, const int32_t *dims, int32_t batch, const double *Sg,
+                            const double *SA, const double *SB, const float *t, const double *Sstar, float *grad,
+                            double *loss, void *stream);
+/* Adam (Kingma & Ba) on n FP32 parameters at step >= 1 (bias-corrected). */
+spx_status spx_net_adam_step(float *params, const float *grad, float *m, float *v, int64_t n, int64_t step,
+                             double lr, double b1, double b2, double eps, void *stream);
 
 /* Lane-layout check of the 32x32x16 MFMA used by the dense backend:
  * D = A B for A [32][16], B [16][32], D [32][32] ([dev] row-major float),

@@ -72,4 +72,10 @@ bool dense_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, const
 void dense_destroy(DensePlan *p);
 hipError_t dense_field(const DensePlan *p, const Grid &g, const Onsite &os, const double *S, float *b, hipStream_t st);
 
+// Learned path corrector (spx_net.hip).
+spx_status net_apply(spx_net *net, const float *params, const int32_t dims[3], int32_t batch, const double *Sg,
+                     const double *SA, const double *SB, int shared_ends, const float *t, double *Shat,
+                     hipStream_t st);
+bool net_alive(spx_net *net);
+
 }  // namespace spx

@@ -463,6 +463,8 @@ struct spx_gneb {
     int n_imgs = 0;
     double *d_partial = nullptr;
     std::vector<void *> owned;  // library allocations
+    float *d_tvals = nullptr;   // reaction coordinates for the learned init
+    int max_img = 0;
     hipGraphExec_t graph = nullptr;
     hipStream_t graph_stream = nullptr;
     int use_graph = 1;
@@ -579,6 +581,8 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_items, sizeof(GItem) * items.size(), "GNEB items");
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_imgs, sizeof(int2) * imgs.size(), "GNEB image list");
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_partial, sizeof(double) * 5 * items.size(), "GNEB partials");
+    for (int k = 0; k < n_inst; ++k) g->max_img = std::max(g->max_img, n_img[k]);
+    if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_tvals, sizeof(float) * g->max_img * n_inst, "GNEB t values");
     if (s != SPX_OK) {
         gneb_free(g);
         delete g;
@@ -622,14 +626,39 @@ spx_status spx_gneb_destroy(spx_gneb *g) {
     return SPX_OK;
 }
 
-spx_status spx_gneb_init_path(spx_gneb *g, int32_t method, void *stream) {
+spx_status spx_gneb_init_path(spx_gneb *g, int32_t method, spx_net *net, const float *params, void *stream) {
     if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
-    if (method != 0) return set_error(SPX_ERR_INVALID_ARG, "method must be 0 (geodesic)");
+    if (method != 0 && method != 1) return set_error(SPX_ERR_INVALID_ARG, "method must be 0 (geodesic) or 1 (learned)");
+    if (method == 1) {
+        if (!net_alive(net) || !params) return set_error(SPX_ERR_INVALID_ARG, "learned init needs a network and parameters");
+        for (const GInst &gi : g->hinst)
+            if (gi.g.n_sub != 1) return set_error(SPX_ERR_UNSUPPORTED, "learned init needs single-sublattice lattices");
+    }
     hipStream_t st = (hipStream_t)stream;
     k_gneb_reset<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
     k_gneb_geodesic<<<grid_for(g->n_items), kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_hip_error(e, "spx_gneb_init_path");
+    if (method == 1) {
+        for (int k = 0; k < g->n_inst; ++k) {
+            const GInst &gi = g->hinst[k];
+            const int nm = gi.n_img - 2;
+            const int64_t N = gi.g.N;
+            std::vector<float> tv(nm);
+            for (int n = 0; n < nm; ++n) tv[n] = (float)(n + 1) / (float)(gi.n_img - 1);
+            float *d_t = g->d_tvals + (size_t)k * g->max_img;
+            e = hipMemcpyAsync(d_t, tv.data(), sizeof(float) * nm, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return set_hip_error(e, "spx_gneb_init_path (learned)");
+            const int32_t dims[3] = {gi.g.Lx, gi.g.Ly, gi.g.Lz};
+            double *Sg = gi.Y[0] + 3 * N;  // images 1 .. n_img-2, corrected in place
+            spx_status s = net_apply(net, params, dims, nm, Sg, gi.Y[0], gi.Y[0] + (int64_t)(gi.n_img - 1) * 3 * N, 1,
+                                     d_t, Sg, st);
+            if (s != SPX_OK) return s;
+            e = hipMemcpyAsync(gi.Y[1] + 3 * N, Sg, sizeof(double) * 3 * N * nm, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return set_hip_error(e, "spx_gneb_init_path (learned)");
+        }
+    }
     return SPX_OK;
 }
 

@@ -1,0 +1,498 @@
+// spx_net.hip -- the learned GNEB initial-path corrector: a 4-layer 3^3
+// convolution network (10 -> 16 -> 16 -> 16 -> 3 channels, zero padding,
+// SiLU between layers) with hand-written FP32 forward, backward and Adam
+// kernels.  Input per image: the geodesic guess S_g, the two end images S_A,
+// S_B and the reaction coordinate t (10 channels); output u (3 channels) is
+// projected on the tangent plane of S_g and applied by the exponential map
+// S_hat = exp_{S_g}(P u) (the retraction of the Methods' minimum-energy-path
+// section).  Training loss: mean over images and sites of |S_hat - S*|^2.
+//
+// Activations are [batch][channel][z][y][x] FP32.  Convolutions are direct:
+// a 256-thread block owns an 8 x 8 x 4 output tile, stages the (10 x 10 x 6)
+// input halo tile of every input channel in LDS (SiLU applied on load) and
+// reads the weights through the scalar cache (uniform over the block).  The
+// input gradient is the same convolution with transposed, flipped weights;
+// weight gradients use one (out, in) channel pair per thread over the block's
+// sites, then a fixed-order reduction over blocks (deterministic).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "spx_device.hpp"
+#include "spx_ext.hpp"
+
+namespace spx {
+namespace {
+
+constexpr int kTXn = 8, kTYn = 8, kTZn = 4;  // output tile
+constexpr int kHX = kTXn + 2, kHY = kTYn + 2, kHZ = kTZn + 2;
+constexpr int kHalo = kHX * kHY * kHZ;
+constexpr int kNT = 256;
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+struct NetDims {
+    int Lx, Ly, Lz;
+    int64_t P;
+};
+
+__device__ __forceinline__ void tile_origin(const NetDims &d, int &x0, int &y0, int &z0) {
+    const int nbx = (d.Lx + kTXn - 1) / kTXn;
+    x0 = (blockIdx.x % nbx) * kTXn;
+    y0 = (blockIdx.x / nbx) * kTYn;
+    z0 = blockIdx.y * kTZn;
+}
+
+// Stage CIN input channels of image blockIdx.z with a 1-cell zero halo.
+template <int CIN, bool SILU_IN>
+__device__ __forceinline__ void stage_tile(const float *__restrict__ in, const NetDims &d, int x0, int y0, int z0,
+                                           float (*tile)[kHalo]) {
+    const float *src = in + (int64_t)blockIdx.z * CIN * d.P;
+    for (int idx = threadIdx.x; idx < CIN * kHalo; idx += kNT) {
+        const int ci = idx / kHalo, r = idx - ci * kHalo;
+        const int hx = r % kHX, hy = (r / kHX) % kHY, hz = r / (kHX * kHY);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        float v = 0.0f;
+        if (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.Lx && gy < d.Ly && gz < d.Lz) {
+            v = src[ci * d.P + gx + (int64_t)d.Lx * (gy + (int64_t)d.Ly * gz)];
+            if (SILU_IN) v = silu(v);
+        }
+        tile[ci][r] = v;
+    }
+}
+
+// out[co] = bias[co] + sum_ci sum_k W[co][ci][k] a[ci](p + k - 1)   (bias may be NULL)
+// MUL_GRAD: the result is multiplied by silu'(zmul) (input-gradient pass).
+template <int CIN, int COUT, bool SILU_IN, bool MUL_GRAD>
+__global__ __launch_bounds__(kNT) void k_conv(const float *__restrict__ in, const float *__restrict__ W,
+                                              const float *__restrict__ bias, const float *__restrict__ zmul,
+                                              float *__restrict__ out, NetDims d) {
+    __shared__ float tile[CIN][kHalo];
+    int x0, y0, z0;
+    tile_origin(d, x0, y0, z0);
+    stage_tile<CIN, SILU_IN>(in, d, x0, y0, z0, tile);
+    __syncthreads();
+    const int tx = threadIdx.x % kTXn, ty = (threadIdx.x / kTXn) % kTYn, tz = threadIdx.x / (kTXn * kTYn);
+    float acc[COUT];
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) acc[co] = bias ? bias[co] : 0.0f;
+    for (int ci = 0; ci < CIN; ++ci) {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+            const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+            const float v = tile[ci][(tx + kx) + kHX * ((ty + ky) + kHY * (tz + kz))];
+#pragma unroll
+            for (int co = 0; co < COUT; ++co) acc[co] += W[(co * CIN + ci) * 27 + k] * v;
+        }
+    }
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    if (x >= d.Lx || y >= d.Ly || z >= d.Lz) return;
+    const int64_t p = x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z);
+    float *dst = out + (int64_t)blockIdx.z * COUT * d.P;
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) {
+        float v = acc[co];
+        if (MUL_GRAD) v *= silu_grad(zmul[(int64_t)blockIdx.z * COUT * d.P + co * d.P + p]);
+        dst[co * d.P + p] = v;
+    }
+}
+
+// Wt[ci][co][k] = W[co][ci][26 - k]: weights of the input-gradient convolution.
+__global__ void k_transpose_flip(const float *__restrict__ W, float *__restrict__ Wt, int cin, int cout) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cin * cout * 27) return;
+    const int k = i % 27, co = (i / 27) % cout, ci = i / (27 * cout);
+    Wt[i] = W[(co * cin + ci) * 27 + (26 - k)];
+}
+
+// Per-block weight/bias gradient partials:
+//   dW[co][ci][k] = sum_p g[co](p) a[ci](p + k - 1),  db[co] = sum_p g[co](p)
+// over the block's output tile; partial[blk][COUT*CIN*27 + COUT].
+template <int CIN, int COUT, bool SILU_IN>
+__global__ __launch_bounds__(kNT) void k_conv_wgrad(const float *__restrict__ in, const float *__restrict__ g,
+                                                    float *__restrict__ partial, NetDims d) {
+    __shared__ float tile[CIN][kHalo];
+    __shared__ float gt[COUT][kTXn * kTYn * kTZn];
+    int x0, y0, z0;
+    tile_origin(d, x0, y0, z0);
+    stage_tile<CIN, SILU_IN>(in, d, x0, y0, z0, tile);
+    const float *gsrc = g + (int64_t)blockIdx.z * COUT * d.P;
+    for (int idx = threadIdx.x; idx < COUT * kNT; idx += kNT) {
+        const int co = idx / kNT, s = idx % kNT;
+        const int x = x0 + s % kTXn, y = y0 + (s / kTXn) % kTYn, z = z0 + s / (kTXn * kTYn);
+        float v = 0.0f;
+        if (x < d.Lx && y < d.Ly && z < d.Lz) v = gsrc[co * d.P + x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z)];
+        gt[co][s] = v;
+    }
+    __syncthreads();
+    const int nw = COUT * CIN * 27 + COUT;
+    const size_t blk = (size_t)blockIdx.z * gridDim.x * gridDim.y + (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    float *dst = partial + blk * nw;
+    const int t = threadIdx.x;
+    if (t < COUT * CIN) {
+        const int co = t / CIN, ci = t % CIN;
+        float acc[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) acc[k] = 0.0f;
+        for (int s = 0; s < kNT; ++s) {
+            const float gv = gt[co][s];
+            const int sx = s % kTXn, sy = (s / kTXn) % kTYn, sz = s / (kTXn * kTYn);
+#pragma unroll
+            for (int k = 0; k < 27; ++k) {
+                const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+                acc[k] += gv * tile[ci][(sx + kx) + kHX * ((sy + ky) + kHY * (sz + kz))];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 27; ++k) dst[(co * CIN + ci) * 27 + k] = acc[k];
+    }
+    if (t < COUT) {
+        float sb = 0.0f;
+        for (int s = 0; s < kNT; ++s) sb += gt[t][s];
+        dst[COUT * CIN * 27 + t] = sb;
+    }
+}
+
+// Fixed-order sum of n_blk partial vectors of length nw.
+__global__ void k_sum_partials(const float *__restrict__ partial, int n_blk, int nw, float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    float s = 0.0f;
+    for (int b = 0; b < n_blk; ++b) s += partial[(size_t)b * nw + i];
+    out[i] = s;
+}
+
+// Network input: channels (S_g, S_A, S_B, t) as FP32.
+// ab_stride: 3P for per-image end images, 0 when all images share them.
+__global__ void k_net_input(const double *__restrict__ Sg, const double *__restrict__ SA,
+                            const double *__restrict__ SB, const float *__restrict__ t, float *__restrict__ x,
+                            int64_t P, int64_t ab_stride) {
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const int b = blockIdx.y;
+    if (p >= P) return;
+    float *xb = x + (int64_t)b * 10 * P;
+    const int64_t o = (int64_t)b * 3 * P, oab = (int64_t)b * ab_stride;
+    for (int c = 0; c < 3; ++c) {
+        xb[c * P + p] = (float)Sg[o + c * P + p];
+        xb[(3 + c) * P + p] = (float)SA[oab + c * P + p];
+        xb[(6 + c) * P + p] = (float)SB[oab + c * P + p];
+    }
+    xb[9 * P + p] = t[b];
+}
+
+// S_hat = exp_{S_g}(P_perp u) (FP64); with S* also the loss partial per block
+// and d loss / d u for the backward pass (loss = mean over batch and sites).
+__global__ __launch_bounds__(kNT) void k_net_head(const float *__restrict__ u, const double *__restrict__ Sg,
+                                                  const double *__restrict__ Sstar, double *__restrict__ Shat,
+                                                  float *__restrict__ gu, double *__restrict__ loss_part, int64_t P,
+                                                  double inv_count) {
+    __shared__ double red[kNT / 64];
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const int b = blockIdx.y;
+    double l = 0.0;
+    if (p < P) {
+        const int64_t o = (int64_t)b * 3 * P;
+        double s[3], r[3];
+        for (int c = 0; c < 3; ++c) {
+            s[c] = Sg[o + c * P + p];
+            r[c] = (double)u[o + c * P + p];
+        }
+        const double rs = r[0] * s[0] + r[1] * s[1] + r[2] * s[2];
+        double w[3] = {r[0] - rs * s[0], r[1] - rs * s[1], r[2] - rs * s[2]};
+        const double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        double sinc, c2;  // sin(th)/th, (cos th - sinc)/th^2 with series near 0
+        if (th < 1e-4) {
+            const double t2 = th * th;
+            sinc = 1.0 - t2 / 6.0 + t2 * t2 / 120.0;
+            c2 = -1.0 / 3.0 + t2 / 30.0;
+        } else {
+            sinc = sin(th) / th;
+            c2 = (cos(th) - sinc) / (th * th);
+        }
+        const double ct = cos(th);
+        double h[3] = {ct * s[0] + sinc * w[0], ct * s[1] + sinc * w[1], ct * s[2] + sinc * w[2]};
+        normalise3(h);
+        if (Shat)
+            for (int c = 0; c < 3; ++c) Shat[o + c * P + p] = h[c];
+        if (Sstar) {
+            double gs[3];
+            for (int c = 0; c < 3; ++c) {
+                const double dlt = h[c] - Sstar[o + c * P + p];
+                l += dlt * dlt;
+                gs[c] = 2.0 * dlt * inv_count;
+            }
+            const double ug = w[0] * gs[0] + w[1] * gs[1] + w[2] * gs[2];
+            const double sg = s[0] * gs[0] + s[1] * gs[1] + s[2] * gs[2];
+            double gw[3];
+            for (int c = 0; c < 3; ++c) gw[c] = sinc * gs[c] + c2 * ug * w[c] - sinc * sg * w[c];
+            const double gws = gw[0] * s[0] + gw[1] * s[1] + gw[2] * s[2];
+            for (int c = 0; c < 3; ++c) gu[o + c * P + p] = (float)(gw[c] - gws * s[c]);
+        }
+    }
+    if (loss_part) {
+        const double t = wave_sum(l);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0;
+            for (int w = 0; w < kNT / 64; ++w) a += red[w];
+            loss_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = a;
+        }
+    }
+}
+
+__global__ void k_loss_final(const double *__restrict__ part, int n, double scale, double *__restrict__ loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *loss = s * scale;
+}
+
+// Adam (Kingma & Ba) on n parameters, step t >= 1.
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+constexpr int kC[5] = {10, 16, 16, 16, 3};
+
+struct NetWork {
+    int64_t cap_P = 0;
+    int cap_B = 0;
+    float *x = nullptr, *z[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *g[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *wt = nullptr;        // transposed weights of one layer
+    float *part = nullptr;      // weight-gradient partials
+    size_t part_cap = 0;
+    double *lpart = nullptr;
+    size_t lpart_cap = 0;
+};
+
+}  // namespace spx
+
+using namespace spx;
+
+struct spx_net {
+    NetWork w;
+};
+
+namespace {
+
+int64_t net_nparams() {
+    int64_t n = 0;
+    for (int l = 0; l < 4; ++l) n += (int64_t)kC[l + 1] * kC[l] * 27 + kC[l + 1];
+    return n;
+}
+int64_t layer_off(int l) {
+    int64_t n = 0;
+    for (int q = 0; q < l; ++q) n += (int64_t)kC[q + 1] * kC[q] * 27 + kC[q + 1];
+    return n;
+}
+
+void net_free(NetWork &w) {
+    for (void *p : {(void *)w.x, (void *)w.z[0], (void *)w.z[1], (void *)w.z[2], (void *)w.z[3], (void *)w.g[0],
+                    (void *)w.g[1], (void *)w.g[2], (void *)w.g[3], (void *)w.wt, (void *)w.part, (void *)w.lpart})
+        if (p) (void)hipFree(p);
+    w = NetWork{};
+}
+
+spx_status net_reserve(NetWork &w, int64_t P, int B, bool train) {
+    if (P <= w.cap_P && B <= w.cap_B && (!train || w.g[0])) return SPX_OK;
+    net_free(w);
+    auto al = [](void **p, size_t bytes) {
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return false;
+        }
+        return true;
+    };
+    bool ok = al((void **)&w.x, sizeof(float) * 10 * P * B);
+    for (int l = 0; l < 4 && ok; ++l) ok = al((void **)&w.z[l], sizeof(float) * kC[l + 1] * P * B);
+    for (int l = 0; l < 4 && ok && train; ++l) ok = al((void **)&w.g[l], sizeof(float) * kC[l + 1] * P * B);
+    if (ok && train) ok = al((void **)&w.wt, sizeof(float) * 16 * 16 * 27);
+    if (!ok) {
+        net_free(w);
+        return set_error(SPX_ERR_OUT_OF_MEMORY, "hipMalloc failed for network activations");
+    }
+    w.cap_P = P;
+    w.cap_B = B;
+    return SPX_OK;
+}
+
+dim3 conv_grid(const NetDims &d, int B) {
+    const int nbx = (d.Lx + kTXn - 1) / kTXn, nby = (d.Ly + kTYn - 1) / kTYn;
+    return dim3((unsigned)(nbx * nby), (unsigned)((d.Lz + kTZn - 1) / kTZn), (unsigned)B);
+}
+
+// forward through the four layers; z[l] are pre-activations
+hipError_t net_forward_layers(NetWork &w, const float *params, const NetDims &d, int B, hipStream_t st) {
+    const dim3 gr = conv_grid(d, B);
+    const float *W0 = params + layer_off(0), *W1 = params + layer_off(1);
+    const float *W2 = params + layer_off(2), *W3 = params + layer_off(3);
+    k_conv<10, 16, false, false><<<gr, kNT, 0, st>>>(w.x, W0, W0 + 16 * 10 * 27, nullptr, w.z[0], d);
+    k_conv<16, 16, true, false><<<gr, kNT, 0, st>>>(w.z[0], W1, W1 + 16 * 16 * 27, nullptr, w.z[1], d);
+    k_conv<16, 16, true, false><<<gr, kNT, 0, st>>>(w.z[1], W2, W2 + 16 * 16 * 27, nullptr, w.z[2], d);
+    k_conv<16, 3, true, false><<<gr, kNT, 0, st>>>(w.z[2], W3, W3 + 3 * 16 * 27, nullptr, w.z[3], d);
+    return hipGetLastError();
+}
+
+spx_status check_dims(const int32_t *dims, int32_t batch, NetDims &d) {
+    if (!dims || dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || batch < 1)
+        return set_error(SPX_ERR_INVALID_ARG, "bad network dims or batch");
+    d.Lx = dims[0];
+    d.Ly = dims[1];
+    d.Lz = dims[2];
+    d.P = (int64_t)dims[0] * dims[1] * dims[2];
+    if (d.P * batch > ((int64_t)1 << 31)) return set_error(SPX_ERR_INVALID_ARG, "network batch too large");
+    return SPX_OK;
+}
+
+}  // namespace
+
+namespace spx {
+// used by the GNEB learned initial path
+spx_status net_apply(spx_net *net, const float *params, const int32_t dims[3], int32_t batch, const double *Sg,
+                     const double *SA, const double *SB, int shared_ends, const float *t, double *Shat,
+                     hipStream_t st) {
+    NetDims d;
+    spx_status s = check_dims(dims, batch, d);
+    if (s != SPX_OK) return s;
+    if ((s = net_reserve(net->w, d.P, batch, false)) != SPX_OK) return s;
+    const dim3 pg((unsigned)((d.P + kNT - 1) / kNT), (unsigned)batch);
+    k_net_input<<<pg, kNT, 0, st>>>(Sg, SA, SB, t, net->w.x, d.P, shared_ends ? 0 : 3 * d.P);
+    hipError_t e = net_forward_layers(net->w, params, d, batch, st);
+    if (e == hipSuccess) {
+        k_net_head<<<pg, kNT, 0, st>>>(net->w.z[3], Sg, nullptr, Shat, nullptr, nullptr, d.P, 0.0);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return set_hip_error(e, "network forward");
+    return SPX_OK;
+}
+bool net_alive(spx_net *net) { return handle_alive(net); }
+}  // namespace spx
+
+extern "C" {
+
+int64_t spx_net_nparams(void) { return net_nparams(); }
+
+spx_status spx_net_create(const int32_t *channels, spx_net **out) {
+    if (!out) return set_error(SPX_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (channels)
+        for (int l = 0; l < 5; ++l)
+            if (channels[l] != kC[l])
+                return set_error(SPX_ERR_UNSUPPORTED, "only the 10-16-16-16-3 network is built");
+    spx_net *n = new spx_net();
+    register_handle(n);
+    *out = n;
+    return SPX_OK;
+}
+
+spx_status spx_net_destroy(spx_net *net) {
+    if (!handle_alive(net)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_net handle");
+    unregister_handle(net);
+    (void)hipDeviceSynchronize();
+    net_free(net->w);
+    delete net;
+    return SPX_OK;
+}
+
+spx_status spx_net_forward(spx_net *net, const float *params, const int32_t *dims, int32_t batch, const double *Sg,
+                           const double *SA, const double *SB, const float *t, double *Shat, void *stream) {
+    if (!handle_alive(net)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_net handle");
+    if (!params || !Sg || !SA || !SB || !t || !Shat) return set_error(SPX_ERR_INVALID_ARG, "NULL argument");
+    return net_apply(net, params, dims, batch, Sg, SA, SB, 0, t, Shat, (hipStream_t)stream);
+}
+
+spx_status spx_net_backward(spx_net *net, const float *params, const int32_t *dims, int32_t batch, const double *Sg,
+                            const double *SA, const double *SB, const float *t, const double *Sstar, float *grad,
+                            double *loss, void *stream) {
+    if (!handle_alive(net)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_net handle");
+    if (!params || !Sg || !SA || !SB || !t || !Sstar || !grad) return set_error(SPX_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    NetDims d;
+    spx_status s = check_dims(dims, batch, d);
+    if (s != SPX_OK) return s;
+    NetWork &w = net->w;
+    if ((s = net_reserve(w, d.P, batch, true)) != SPX_OK) return s;
+    const dim3 gr = conv_grid(d, batch);
+    const size_t n_blk = (size_t)gr.x * gr.y * gr.z;
+    const size_t need = n_blk * (16 * 16 * 27 + 16);
+    const dim3 pg((unsigned)((d.P + kNT - 1) / kNT), (unsigned)batch);
+    const size_t nl = (size_t)pg.x * pg.y;
+    if (need > w.part_cap) {
+        if (w.part) (void)hipFree(w.part);
+        if (hipMalloc((void **)&w.part, need * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            w.part = nullptr;
+            w.part_cap = 0;
+            return set_error(SPX_ERR_OUT_OF_MEMORY, "hipMalloc failed for gradient partials");
+        }
+        w.part_cap = need;
+    }
+    if (nl > w.lpart_cap) {
+        if (w.lpart) (void)hipFree(w.lpart);
+        if (hipMalloc((void **)&w.lpart, nl * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            w.lpart = nullptr;
+            w.lpart_cap = 0;
+            return set_error(SPX_ERR_OUT_OF_MEMORY, "hipMalloc failed for loss partials");
+        }
+        w.lpart_cap = nl;
+    }
+    k_net_input<<<pg, kNT, 0, st>>>(Sg, SA, SB, t, w.x, d.P, 3 * d.P);
+    hipError_t e = net_forward_layers(w, params, d, batch, st);
+    if (e != hipSuccess) return set_hip_error(e, "network backward (forward pass)");
+    const double inv_count = 1.0 / ((double)d.P * batch);
+    k_net_head<<<pg, kNT, 0, st>>>(w.z[3], Sg, Sstar, nullptr, w.g[3], w.lpart, d.P, inv_count);
+    if (loss) k_loss_final<<<1, 1, 0, st>>>(w.lpart, (int)nl, inv_count, loss);
+    // layer 4 (16 -> 3), 3 (16 -> 16), 2 (16 -> 16), 1 (10 -> 16)
+    for (int l = 3; l >= 0; --l) {
+        const int cin = kC[l], cout = kC[l + 1];
+        const int nw = cout * cin * 27 + cout;
+        const float *Wl = params + layer_off(l);
+        float *gl = grad + layer_off(l);
+        const float *ain = l == 0 ? w.x : w.z[l - 1];
+        if (l == 3) k_conv_wgrad<16, 3, true><<<gr, kNT, 0, st>>>(ain, w.g[3], w.part, d);
+        else if (l == 0) k_conv_wgrad<10, 16, false><<<gr, kNT, 0, st>>>(ain, w.g[0], w.part, d);
+        else k_conv_wgrad<16, 16, true><<<gr, kNT, 0, st>>>(ain, w.g[l], w.part, d);
+        k_sum_partials<<<(nw + 255) / 256, 256, 0, st>>>(w.part, (int)n_blk, nw, gl);
+        if (l > 0) {
+            // g_{l-1} = silu'(z_{l-1}) * conv(g_l, W^T flipped)
+            k_transpose_flip<<<(cin * cout * 27 + 255) / 256, 256, 0, st>>>(Wl, w.wt, cin, cout);
+            if (l == 3) k_conv<3, 16, false, true><<<gr, kNT, 0, st>>>(w.g[3], w.wt, nullptr, w.z[2], w.g[2], d);
+            else k_conv<16, 16, false, true><<<gr, kNT, 0, st>>>(w.g[l], w.wt, nullptr, w.z[l - 1], w.g[l - 1], d);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return set_hip_error(e, "network backward");
+    }
+    return SPX_OK;
+}
+
+spx_status spx_net_adam_step(float *params, const float *grad, float *m, float *v, int64_t n, int64_t step,
+                             double lr, double b1, double b2, double eps, void *stream) {
+    if (!params || !grad || !m || !v || n < 0 || step < 1) return set_error(SPX_ERR_INVALID_ARG, "bad Adam arguments");
+    const float c1 = (float)(1.0 - std::pow(b1, (double)step)), c2 = (float)(1.0 - std::pow(b2, (double)step));
+    k_adam<<<(unsigned)((n + kNT - 1) / kNT), kNT, 0, (hipStream_t)stream>>>(params, grad, m, v, n, (float)lr,
+                                                                            (float)b1, (float)b2, (float)eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(e, "spx_net_adam_step");
+    return SPX_OK;
+}
+
+}  // extern "C"

@@ -96,7 +96,12 @@ def load(path: str = LIB_PATH):
         "spx_gneb_create": [C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(C.c_int32), C.POINTER(GnebParams),
                             vp, C.POINTER(vp)],
         "spx_gneb_destroy": [vp],
-        "spx_gneb_init_path": [vp, i32, vp],
+        "spx_gneb_init_path": [vp, i32, vp, vp, vp],
+        "spx_net_create": [vp, C.POINTER(vp)],
+        "spx_net_destroy": [vp],
+        "spx_net_forward": [vp, vp, C.POINTER(C.c_int32), i32, vp, vp, vp, vp, vp, vp],
+        "spx_net_backward": [vp, vp, C.POINTER(C.c_int32), i32, vp, vp, vp, vp, vp, vp, vp, vp],
+        "spx_net_adam_step": [vp, vp, vp, vp, i64, i64, dbl, dbl, dbl, dbl, vp],
         "spx_gneb_step": [vp, i32, vp],
         "spx_gneb_get_stats": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "spx_gneb_set_graph": [vp, i32],
@@ -111,6 +116,8 @@ def load(path: str = LIB_PATH):
     L.spx_last_error.argtypes = []
     L.spx_abi_version.restype = C.c_int32
     L.spx_abi_version.argtypes = []
+    L.spx_net_nparams.restype = C.c_int64
+    L.spx_net_nparams.argtypes = []
     _lib = L
     _register_extensions(L)
     return L
@@ -366,8 +373,11 @@ def gneb_create(hams, images, spring_k=1.0, vp_dt=0.1, vp_mass=1.0, ci_mode=1, c
     return Gneb(g.value, hams, images, n_img)
 
 
-def gneb_init_path(g, method=0, stream=None):
-    _check(load().spx_gneb_init_path(g.handle, int(method), _stream(stream)), "spx_gneb_init_path")
+def gneb_init_path(g, method=0, net=None, params=None, stream=None):
+    """method 0: geodesic; method 1: geodesic corrected by the network `net`
+    with FP32 parameter tensor `params`."""
+    _check(load().spx_gneb_init_path(g.handle, int(method), None if net is None else net.handle, _ptr(params),
+                                     _stream(stream)), "spx_gneb_init_path")
 
 
 def gneb_step(g, n_iter=1, stream=None):
@@ -394,3 +404,46 @@ def gneb_get_stats(g, inst=0, stream=None):
 def mfma_probe(prec, A, B, D, stream=None):
     p = PREC[prec] if isinstance(prec, str) else int(prec)
     _check(load().spx_mfma_probe(p, _ptr(A), _ptr(B), _ptr(D), _stream(stream)), "spx_mfma_probe")
+
+
+# ---------------------------------------------------------------- learned corrector
+class Net:
+    """Owner of an spx_net workspace handle."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(load().spx_net_create(None, C.byref(h)), "spx_net_create")
+        self.handle = h.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                load().spx_net_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def net_nparams() -> int:
+    return int(load().spx_net_nparams())
+
+
+def _dims(dims):
+    return (C.c_int32 * 3)(*[int(v) for v in dims])
+
+
+def net_forward(net, params, dims, batch, Sg, SA, SB, t, Shat, stream=None):
+    _check(load().spx_net_forward(net.handle, _ptr(params), _dims(dims), int(batch), _ptr(Sg), _ptr(SA), _ptr(SB),
+                                  _ptr(t), _ptr(Shat), _stream(stream)), "spx_net_forward")
+
+
+def net_backward(net, params, dims, batch, Sg, SA, SB, t, Sstar, grad, loss=None, stream=None):
+    _check(load().spx_net_backward(net.handle, _ptr(params), _dims(dims), int(batch), _ptr(Sg), _ptr(SA), _ptr(SB),
+                                   _ptr(t), _ptr(Sstar), _ptr(grad), _ptr(loss), _stream(stream)),
+           "spx_net_backward")
+
+
+def net_adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    n = int(params.numel())
+    _check(load().spx_net_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, int(step), float(lr), float(b1),
+                                    float(b2), float(eps), _stream(stream)), "spx_net_adam_step")

@@ -1,0 +1,148 @@
+"""GPU parity of the learned path corrector (FP32 forward, backward, Adam and
+the learned GNEB initial path) against the FP64 oracle network.
+
+Tolerances (FP32 convolutions vs FP64): corrected images 1e-5 absolute per
+component; loss 1e-5 relative; gradients max|g - g_ref| <= 1e-4 max|g_ref|;
+Adam 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import require_gpu, to_dev
+from workloads import random_sphere
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def init_params(seed, scale=1.0):
+    """He-style random parameters for the 10-16-16-16-3 network (float32)."""
+    rng = np.random.default_rng(seed)
+    ch = oracle.NET_CHANNELS
+    out = []
+    for l in range(4):
+        fan = ch[l] * 27
+        out.append(rng.standard_normal(ch[l + 1] * ch[l] * 27) * scale * np.sqrt(2.0 / fan))
+        out.append(rng.standard_normal(ch[l + 1]) * 0.05)
+    return np.concatenate(out).astype(np.float32)
+
+
+def batch_case(L, B, seed):
+    P = L[0] * L[1] * L[2]
+    Sg = np.stack([random_sphere(P, seed + 3 * b) for b in range(B)])
+    SA = np.stack([random_sphere(P, seed + 3 * b + 1) for b in range(B)])
+    SB = np.stack([random_sphere(P, seed + 3 * b + 2) for b in range(B)])
+    Ss = np.stack([random_sphere(P, seed + 100 + b) for b in range(B)])
+    t = (np.arange(B, dtype=np.float32) + 1) / (B + 1)
+    return Sg, SA, SB, Ss, t
+
+
+def oracle_x(Sg, SA, SB, t):
+    P = Sg.shape[-1]
+    return np.concatenate([Sg, SA, SB, np.full((1, P), float(t))])
+
+
+@pytest.mark.parametrize("L,scale", [((9, 7, 5), 1.0), ((16, 8, 4), 1.0), ((9, 7, 5), 2.0)])
+def test_net_forward_matches_oracle(L, scale):
+    # FP32 convolutions: the corrected image differs from the FP64 oracle by
+    # about 1e-7 of the network output |u| per layer; the bound is 1e-5 for
+    # He-scaled weights (|u| ~ 1) and 1e-5 * max|u| beyond that
+    import torch
+    from paper_2605_26016_amd import spx
+    B = 3
+    p32 = init_params(1, scale=scale)
+    Sg, SA, SB, Ss, t = batch_case(L, B, 10)
+    net = spx.Net()
+    out = torch.zeros((B, 3, Sg.shape[-1]), dtype=torch.float64, device="cuda")
+    spx.net_forward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), out)
+    got = out.cpu().numpy()
+    p64 = p32.astype(np.float64)
+    for b in range(B):
+        raw = oracle.net_forward(L, p64, oracle_x(Sg[b], SA[b], SB[b], t[b]))
+        ref, _ = oracle.net_predict_loss(raw, Sg[b])
+        tol = 1e-5 * max(1.0, float(np.max(np.abs(raw))))
+        assert np.max(np.abs(got[b] - ref)) < tol, (b, np.max(np.abs(got[b] - ref)), tol)
+
+
+def test_net_backward_matches_oracle():
+    import torch
+    from paper_2605_26016_amd import spx
+    L = (7, 6, 5)
+    B = 2
+    p32 = init_params(2, scale=2.0)
+    Sg, SA, SB, Ss, t = batch_case(L, B, 20)
+    net = spx.Net()
+    n = spx.net_nparams()
+    assert n == oracle.net_nparams()
+    grad = torch.zeros(n, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    spx.net_backward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), to_dev(Ss), grad, loss)
+    g = grad.cpu().numpy().astype(np.float64)
+    p64 = p32.astype(np.float64)
+    ref = np.zeros(n)
+    lref = 0.0
+    for b in range(B):
+        lb, gb = oracle.net_backward(L, p64, oracle_x(Sg[b], SA[b], SB[b], t[b]), Sg[b], Ss[b])
+        ref += gb / B
+        lref += lb / B
+    assert abs(loss.item() - lref) <= 1e-5 * lref
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-4, err
+    # deterministic
+    grad2 = torch.zeros_like(grad)
+    spx.net_backward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), to_dev(Ss), grad2)
+    assert torch.equal(grad, grad2)
+
+
+def test_adam_matches_oracle():
+    import torch
+    from paper_2605_26016_amd import spx
+    rng = np.random.default_rng(3)
+    n = 1000
+    w = rng.standard_normal(n)
+    m = np.zeros(n)
+    v = np.zeros(n)
+    wd, md, vd = to_dev(w.astype(np.float32)), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    for step in range(1, 6):
+        g = rng.standard_normal(n)
+        oracle.adam(w, g, m, v, step, lr=1e-2)
+        spx.net_adam_step(wd, to_dev(g.astype(np.float32)), md, vd, step, lr=1e-2)
+    assert np.max(np.abs(wd.cpu().numpy() - w)) < 1e-5
+
+
+def test_learned_init_with_zero_net_is_geodesic_and_nonzero_matches_forward():
+    import torch
+    from paper_2605_26016_amd import spx
+    from tests.helpers import gpu_hamiltonian
+    from workloads import Workload
+    w = Workload(name="t", L=(6, 5, 4), periodic=(0, 0, 0), J_shell=(1.0, 0.188, -0.274, -0.161), field_prec="fp64")
+    A, Bv = random_sphere(w.N, 1), random_sphere(w.N, 2)
+    n_img = 6
+    Y = np.zeros((n_img, 3, w.N))
+    Y[0], Y[-1] = A, Bv
+    geo = oracle.geodesic_path(A, Bv, n_img)
+    net = spx.Net()
+    zero = torch.zeros(spx.net_nparams(), dtype=torch.float32, device="cuda")
+    Yd = to_dev(Y)
+    g = spx.gneb_create([gpu_hamiltonian(w)], [Yd])
+    spx.gneb_init_path(g, method=1, net=net, params=zero)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(Yd.cpu().numpy() - geo)) < 1e-13
+    p32 = init_params(5)
+    Yd2 = to_dev(Y)
+    g2 = spx.gneb_create([gpu_hamiltonian(w)], [Yd2])
+    spx.gneb_init_path(g2, method=1, net=net, params=to_dev(p32))
+    torch.cuda.synchronize()
+    got = Yd2.cpu().numpy()
+    p64 = p32.astype(np.float64)
+    for n in range(1, n_img - 1):
+        tn = np.float32(n / (n_img - 1))
+        raw = oracle.net_forward(w.L, p64, oracle_x(geo[n], A, Bv, tn))
+        ref, _ = oracle.net_predict_loss(raw, geo[n])
+        assert np.max(np.abs(got[n] - ref)) < 1e-5
+    assert np.array_equal(got[0], A) and np.array_equal(got[-1], Bv)
