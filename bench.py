@@ -81,6 +81,128 @@ def cpu_baseline(w, seconds: float):
             "sample": f"{steps} full Heun step(s) of the {w.N}-spin lattice, FP64 oracle, {el:.1f} s"}
 
 
+# GNEB algorithmic HBM bytes per spin-image-iteration of the three passes
+# (FP64, 24 B per spin vector): pass A reads S_n, S_n+1 and writes F (72 B);
+# pass B reads S_n-1, S_n, S_n+1, F, v (120 B); pass C reads S_n-1, S_n, S_n+1,
+# F and writes v, S' (144 B).  Neighbour reuse inside an image is on chip.
+GNEB_BYTES = 336
+
+
+def gneb_workload(args):
+    """Batched ragged GNEB throughput on 48^3, 64^3, 96^3 x 32 images (one
+    persistent launch set per pass), and the learned-versus-geodesic initial
+    path comparison on hopfion annihilation paths."""
+    import numpy as np
+    import torch
+
+    from paper_2605_26016_amd import pathinit, spx
+    from workloads import hopfion_texture, sc_frustrated_gneb, uniform_state
+
+    out = {"metric": "GNEB iterations to convergence, learned vs geodesic initial path; batched GNEB "
+                     "spin-image-iterations/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 (network f32)", "data": "synthetic (seeded hopfion textures)"}
+    # -- throughput: the config as given (3-shell model), seeded texture -> FM, 32 images each
+    sizes = (48, 64, 96)
+    hams, imgs = [], []
+    for L in sizes:
+        w = sc_frustrated_gneb((L, L, L), shells="config3")
+        h = spx.setup_hamiltonian(w.L, periodic=w.periodic, J_shell=w.J_shell, field_prec="fp64")
+        Y = torch.zeros((32, 3, w.N), dtype=torch.float64, device="cuda")
+        Y[0] = torch.from_numpy(hopfion_texture(w.L)).cuda()
+        Y[-1] = torch.from_numpy(uniform_state(w.N)).cuda()
+        hams.append(h)
+        imgs.append(Y)
+    g = spx.gneb_create(hams, imgs, ci_mode=1, ci_on_below=1e-2, tol_force=0.0)
+    spx.gneb_init_path(g)
+    spx.gneb_step(g, 5)
+    torch.cuda.synchronize()
+    n_it = args.steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    spx.gneb_step(g, n_it)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    spin_images = sum(32 * L ** 3 for L in sizes)
+    rate = spin_images * n_it / (ms / 1e3)
+    out.update({"value": rate, "unit": "spin-image-iterations/s", "steps": n_it, "warmup": 5,
+                "ms_per_step": ms / n_it,
+                "roofline": {"bound": "hbm", "achieved": rate * GNEB_BYTES / 1e9, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": rate * GNEB_BYTES / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                             "kernel": "GNEB iteration (passes A, B, C + reductions)",
+                             "bytes_per_spin_image_iteration": GNEB_BYTES}})
+    out["config"] = {"workload": "sc_frustrated_gneb", "lattices": [list((L, L, L)) for L in sizes], "images": 32,
+                     "spin_images": spin_images, "shells_throughput": [1.0, -0.164, -0.082],
+                     "parallelism": "single GPU, ragged batch in one launch per pass"}
+    del g, hams, imgs
+    log(f"[bench] batched GNEB: {rate:.3e} spin-image-iterations/s")
+    if args.no_learned:
+        print(json.dumps(out), flush=True)
+        return
+    # -- learned vs geodesic initial path on hopfion annihilation paths
+    J4 = (1.0, 0.188, -0.274, -0.161)
+    L = args.gneb_L
+    n_img = 16
+    h = spx.setup_hamiltonian((L, L, L), periodic=(0, 0, 0), J_shell=J4, field_prec="fp64")
+    N = L ** 3
+    fm = torch.from_numpy(uniform_state(N)).cuda()
+
+    def endpoints(seeds):
+        st = []
+        for s in seeds:
+            rng = np.random.default_rng(s)
+            S = hopfion_texture((L, L, L), R0=L / 6 * (1 + 0.2 * rng.uniform(-1, 1)),
+                                width=L / 6 * (1 + 0.2 * rng.uniform(-1, 1)), center_offset=rng.uniform(-2, 2, 3))
+            st.append(torch.from_numpy(S).cuda())
+        rel, its, mf = pathinit.minimize(h, st, tol=2e-4, max_iter=30000, vp_dt=0.2)
+        keep = [r for r in rel if int((r[2] < 0).sum()) > 0]   # textures that survived relaxation
+        return keep, its, mf
+
+    def paths(A):
+        Ys = []
+        for a in A:
+            Y = torch.zeros((n_img, 3, N), dtype=torch.float64, device="cuda")
+            Y[0] = a
+            Y[-1] = fm
+            Ys.append(Y)
+        return Ys
+
+    t0 = time.perf_counter()
+    A_tr, its_tr, _ = endpoints(range(1000, 1000 + args.n_train))
+    Y_tr = paths(A_tr)
+    geo = [y.clone() for y in Y_tr]
+    gg = spx.gneb_create([h] * len(geo), geo)
+    spx.gneb_init_path(gg)
+    res_tr = pathinit.converge([h] * len(Y_tr), Y_tr, tol=1e-3, max_iter=args.max_iter, chunk=1000)
+    ok = [k for k in range(len(Y_tr)) if res_tr.converged[k]]
+    log(f"[bench] training paths: {len(ok)}/{len(Y_tr)} converged, median iterations "
+        f"{int(np.median(res_tr.iterations))}, {time.perf_counter() - t0:.1f} s")
+    data = pathinit.build_samples((L, L, L), [geo[k] for k in ok], [Y_tr[k] for k in ok])
+    p, net, hist = pathinit.train(data, epochs=args.epochs, batch=16, lr=2e-3)
+    log(f"[bench] trained: loss {hist[0]:.3e} -> {hist[-1]:.3e}, {time.perf_counter() - t0:.1f} s")
+    A_te, _, _ = endpoints(range(5000, 5000 + args.n_test))
+    Yp = paths(A_te)
+    Yl = [y.clone() for y in Yp]
+    rp = pathinit.converge([h] * len(Yp), Yp, tol=1e-3, max_iter=args.max_iter, chunk=500)
+    rl = pathinit.converge([h] * len(Yl), Yl, tol=1e-3, max_iter=args.max_iter, chunk=500, method=1, net=net,
+                           params=p)
+    both = [k for k in range(len(Yp)) if rp.converged[k] and rl.converged[k]]
+    dbar = np.abs(rl.barrier - rp.barrier)
+    same = [k for k in both if dbar[k] <= 0.1]
+    it_p = float(np.mean(rp.iterations[same])) if same else float("nan")
+    it_l = float(np.mean(rl.iterations[same])) if same else float("nan")
+    out["learned_init"] = {
+        "model": "sc four-shell frustrated exchange J1 = 1 meV, J2/J1 = 0.188, J3/J1 = -0.274, J4/J1 = -0.161",
+        "lattice": [L, L, L], "images": n_img, "train_paths": len(ok), "test_paths": len(Yp),
+        "test_converged_both": len(both), "same_channel_within_0.1meV": len(same),
+        "iterations_geodesic": rp.iterations.tolist(), "iterations_learned": rl.iterations.tolist(),
+        "barrier_geodesic_meV": np.round(rp.barrier, 4).tolist(), "barrier_learned_meV": np.round(rl.barrier, 4).tolist(),
+        "mean_iterations_geodesic": it_p, "mean_iterations_learned": it_l,
+        "iteration_ratio_learned_over_geodesic": it_l / it_p if same else None,
+        "train_loss_first_last": [hist[0], hist[-1]], "seconds_total": time.perf_counter() - t0}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +211,12 @@ def main():
     ap.add_argument("--workload", default="bcc128_5shell_stochastic_mixed")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="GNEB workload: throughput only")
+    ap.add_argument("--gneb-L", type=int, default=32)
+    ap.add_argument("--n-train", type=int, default=48)
+    ap.add_argument("--n-test", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--max-iter", type=int, default=30000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -101,6 +229,10 @@ def main():
     from paper_2605_26016_amd import spx
     from workloads import WORKLOADS
 
+    if args.workload == "sc_frustrated_gneb":
+        torch.cuda.set_device(0)
+        gneb_workload(args)
+        return
     w = WORKLOADS[args.workload]()
     log(f"[bench] workload {w.name}: {w.N} spins, {args.warmup} warmup + {args.steps} timed Heun steps")
     torch.cuda.set_device(0)

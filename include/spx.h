@@ -218,7 +218,10 @@ spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, doub
  * (v <- (v.F/F.F) F if v.F > 0 else 0; v += (dt/m) F) and the exponential-map
  * retraction S <- cos|u| S + sin|u| u/|u| with u = P_perp(dt v).
  * ci_mode: 0 no climbing image, 1 climbing image switched on once max |F|
- * < ci_on_below, 2 from the start.  An instance stops (and is frozen) once
+ * < ci_on_below, 2 from the start, 3 static minimisation (Methods, static
+ * optimisation: velocity projection with the exponential-map retraction):
+ * no tangent, no springs, no climbing image, every movable image relaxes to a
+ * local minimum on its own (the end images are not used).  An instance stops (and is frozen) once
  * max |F| < tol_force (and, for ci_mode 1, the climbing image is on);
  * tol_force = 0 never stops.  Deterministic, fixed-order reductions. */
 typedef struct {

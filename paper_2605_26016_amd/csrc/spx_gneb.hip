@@ -182,6 +182,11 @@ __global__ void k_gneb_scalars1(const GInst *__restrict__ inst, int n_inst) {
     }
     G.st[ST_CI] = (double)ci;
     for (int n = 1; n + 1 < G.n_img; ++n) {
+        if (G.ci_mode == 3) {  // minimisation: no tangent, so no projection and no spring
+            im[n * IS_N + IS_WP] = 0.0;
+            im[n * IS_N + IS_WM] = 0.0;
+            continue;
+        }
         const double Ep = im[(n + 1) * IS_N + IS_E], Em = im[(n - 1) * IS_N + IS_E], E0 = im[n * IS_N + IS_E];
         double wp, wm;
         if (Ep > E0 && E0 > Em) { wp = 1.0; wm = 0.0; }
@@ -513,7 +518,7 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
     if (!H || !images || !n_img || !p || n_inst < 1) return set_error(SPX_ERR_INVALID_ARG, "bad GNEB arguments");
     if (!(p->vp_dt > 0.0) || !(p->vp_mass > 0.0) || !(p->spring_k >= 0.0))
         return set_error(SPX_ERR_INVALID_ARG, "vp_dt, vp_mass must be > 0 and spring_k >= 0");
-    if (p->ci_mode < 0 || p->ci_mode > 2) return set_error(SPX_ERR_INVALID_ARG, "ci_mode must be 0, 1 or 2");
+    if (p->ci_mode < 0 || p->ci_mode > 3) return set_error(SPX_ERR_INVALID_ARG, "ci_mode must be 0, 1, 2 or 3");
     hipStream_t st = (hipStream_t)stream;
     spx_gneb *g = new spx_gneb();
     g->n_inst = n_inst;

@@ -170,3 +170,19 @@ WORKLOADS = {
     "sc1024_nn_stochastic_mixed": sc_billion,
     "sc_frustrated_gneb": sc_frustrated_gneb,
 }
+
+
+def skyrmion_texture(L: Sequence[int], R: float, center=(0.0, 0.0), helicity: float = 0.5 * np.pi) -> np.ndarray:
+    """Isolated skyrmion seed in every xy layer of an L grid, shape (3, N):
+    core down, background +z, polar angle 2 atan(R / r), in-plane angle
+    azimuth + helicity (pi/2: Bloch type)."""
+    Lx, Ly, Lz = (int(v) for v in L)
+    cx = (Lx - 1) / 2.0 + center[0]
+    cy = (Ly - 1) / 2.0 + center[1]
+    z, y, x = np.meshgrid(np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    X, Y = x - cx, y - cy
+    r = np.sqrt(X * X + Y * Y)
+    theta = 2.0 * np.arctan2(R, r)
+    phi = np.arctan2(Y, X) + helicity
+    S = np.stack([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
+    return np.ascontiguousarray(S.reshape(3, -1))
