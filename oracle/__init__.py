@@ -70,7 +70,7 @@ def lib():
         L.or_thermal_eta.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_long, _dp]
         L.or_heun.restype = None
         L.or_heun.argtypes = model + [C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint64,
-                                      C.c_uint32, C.c_int, _dp]
+                                      C.c_uint32, C.c_uint64, C.c_int, _dp]
         L.or_image_distance.restype = C.c_double
         L.or_image_distance.argtypes = [C.c_long, _dp, _dp]
         L.or_geodesic_path.restype = None
@@ -248,11 +248,12 @@ def thermal_eta(seed, step, N, tag=0):
     return eta
 
 
-def heun(model: Model, S, alpha, dt_fs, T_K=0.0, seed=0, step0=0, n_steps=1, tag=0):
-    """n_steps normalised Heun steps (FP64) from S; returns the new state."""
+def heun(model: Model, S, alpha, dt_fs, T_K=0.0, seed=0, step0=0, n_steps=1, tag=0, site0=0):
+    """n_steps normalised Heun steps (FP64) from S; returns the new state.
+    site0 offsets the noise counters (a block of a larger lattice)."""
     S = _f64(S).copy()
     lib().or_heun(*model._args(), float(alpha), float(dt_fs), float(T_K), int(seed), int(step0),
-                  int(tag), int(n_steps), S)
+                  int(tag), int(site0), int(n_steps), S)
     return S
 
 

@@ -556,13 +556,20 @@ static void or_eta(uint64_t seed, uint64_t step, uint32_t tag, uint64_t site, do
     eta[2] = r1 * cos(t1);
 }
 
-void or_thermal_eta(uint64_t seed, uint64_t step, uint32_t tag, long N, double *eta /*[3][N]*/) {
+/* eta for sites site0 .. site0+N-1 (site0 > 0: a contiguous block of a
+   larger lattice, whose counters are the global site indices) */
+static void or_thermal_eta_at(uint64_t seed, uint64_t step, uint32_t tag, uint64_t site0, long N,
+                              double *eta) {
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) {
         double e[3];
-        or_eta(seed, step, tag, (uint64_t)i, e);
+        or_eta(seed, step, tag, site0 + (uint64_t)i, e);
         eta[i] = e[0]; eta[N + i] = e[1]; eta[2 * N + i] = e[2];
     }
+}
+
+void or_thermal_eta(uint64_t seed, uint64_t step, uint32_t tag, long N, double *eta /*[3][N]*/) {
+    or_thermal_eta_at(seed, step, tag, 0, N, eta);
 }
 
 /* ---- LLG + normalised Heun (Methods, atomistic spin dynamics) ----------- */
@@ -592,12 +599,15 @@ static void or_normalise(double v[3]) {
  * For T > 0 the thermal field sigma_i eta_i^n, sigma_i =
  * sqrt(2 alpha k_B T / (gamma mu_i mu_B dt)), is added to B in both stages
  * with the same eta (Stratonovich Heun); eta for step n = step0 + k.
+ * The noise counter of local site i is site0 + i (site0 = 0 for a whole
+ * lattice; a z-slab of a larger single-sublattice lattice passes the global
+ * index of its first site).
  */
 void or_heun(int n_sub, const int *L, const int *per, const double *cell9, const double *frac,
              int n_bonds, const int *b_a, const int *b_b, const int *b_delta, const double *b_J,
              int n_aniso, const double *K, const double *K_axis, const double *B3,
              const double *mu, int dipolar, double alpha, double dt_fs, double T_K,
-             uint64_t seed, uint64_t step0, uint32_t tag, int n_steps, double *S) {
+             uint64_t seed, uint64_t step0, uint32_t tag, uint64_t site0, int n_steps, double *S) {
     or_lat lt;
     or_model m;
     or_lat_fill(&lt, n_sub, L, per, cell9, frac);
@@ -610,7 +620,7 @@ void or_heun(int n_sub, const int *L, const int *per, const double *cell9, const
     double *eta = (double *)malloc(sizeof(double) * 3 * N);
     for (int k = 0; k < n_steps; ++k) {
         uint64_t step = step0 + (uint64_t)k;
-        if (T_K > 0.0) or_thermal_eta(seed, step, tag, N, eta);
+        if (T_K > 0.0) or_thermal_eta_at(seed, step, tag, site0, N, eta);
         /* predictor */
         or_field_total(&lt, &m, S, b);
         for (long i = 0; i < N; ++i) {
@@ -738,7 +748,8 @@ void or_geodesic_path(long N, const double *SA, const double *SB, int n_img, dou
  *   F_ci   = F - 2 (F.tau) tau                                  (climbing image)
  * VP over all movable images: v <- (v.F/F.F) F if v.F > 0 else 0;
  * v += (dt/m) F;  u = P_perp(dt v);  S <- exp_S(u).
- * ci_mode: 0 never, 1 switch on once max|F_gneb| < ci_on_below, 2 always.
+ * ci_mode: 0 never, 1 switch on once max|F_gneb| < ci_on_below, 2 always,
+ * 3 static minimisation of every movable image (no tangent: F_gneb = F).
  * *ci_on carries the switch between calls.  Outputs: energies E[n_img],
  * distances dist[n_img-1], max |F_gneb| per spin over movable images (before
  * the update), the climbing image index (-1 if none).
@@ -782,7 +793,8 @@ void or_gneb_iterate(int n_sub, const int *L, const int *per, const double *cell
         /* tangent weights (Henkelman & Jonsson improved tangent) */
         double wp, wm;
         double Ep = E[n + 1], Em = E[n - 1], E0 = E[n];
-        if (Ep > E0 && E0 > Em) { wp = 1.0; wm = 0.0; }
+        if (ci_mode == 3) { wp = 0.0; wm = 0.0; }
+        else if (Ep > E0 && E0 > Em) { wp = 1.0; wm = 0.0; }
         else if (Ep < E0 && E0 < Em) { wp = 0.0; wm = 1.0; }
         else {
             double dmax = fmax(fabs(Ep - E0), fabs(Em - E0));

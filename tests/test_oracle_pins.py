@@ -477,6 +477,29 @@ def test_gneb_coherent_rotation_block():
     assert abs(dist.sum() - math.sqrt(N) * math.pi) < 1e-6
 
 
+def test_gneb_minimisation_mode_relaxes_images_to_their_basins():
+    # static minimisation: images relax independently of springs and tangent;
+    # macrospin images with cos theta > -h fall into theta = 0, the others into pi
+    K, h = 1.0, 0.3
+    m = _sw_model(K, h)
+    SA = np.array([[0.0], [0.0], [-1.0]])
+    SB = np.array([[0.0], [0.0], [1.0]])
+    Y0 = oracle.geodesic_path(SA, SB, 9)
+    out = []
+    for k in (0.0, 7.0):
+        st = oracle.GnebState(Y0.copy(), k_spring=k, dt=0.2, mass=1.0, ci_mode=3)
+        for it in range(3000):
+            E, dist, fmax, ci = oracle.gneb_iterate(m, st)
+            if fmax < 1e-10:
+                break
+        assert ci == -1 and fmax < 1e-10
+        out.append(st.Y.copy())
+    np.testing.assert_array_equal(out[0], out[1])
+    for n in range(9):
+        want = 1.0 if Y0[n][2, 0] > -h else -1.0
+        assert abs(out[0][n][2, 0] - want) < 1e-9, n
+
+
 # ---------------------------------------------------------------- net
 def test_net_single_channel_conv_is_correlation():
     # one input / output channel, 3^3 kernel, zero padding == scipy correlate
@@ -546,3 +569,23 @@ def test_adam_first_step_is_lr_times_sign():
     v = np.zeros(3)
     oracle.adam(w, g, m, v, 1, lr=0.1)
     np.testing.assert_allclose(w, [0.9, -1.9, 2.9], atol=1e-6)
+
+
+def test_heun_site_offset_reproduces_a_slab_of_a_larger_lattice():
+    # a z-slab of a periodic-in-xy lattice advanced alone (open in z) with the
+    # noise counters offset by the slab's first global site equals the full
+    # lattice's step on the planes at least two away from the slab faces
+    w = Workload(name="t", L=(6, 5, 10), J_shell=(1.0,), K=0.1, alpha=0.1, dt_fs=0.5, T_K=50.0)
+    m = oracle_model(w)
+    S0 = random_sphere(w.N, 4)
+    full = oracle.heun(m, S0, alpha=0.1, dt_fs=0.5, T_K=50.0, seed=1004, step0=3, n_steps=1)
+    z0, nz, plane = 3, 6, 6 * 5
+    ws = Workload(name="t", L=(6, 5, nz), periodic=(1, 1, 0), J_shell=(1.0,), K=0.1)
+    slab = S0[:, z0 * plane:(z0 + nz) * plane]
+    got = oracle.heun(oracle_model(ws), slab, alpha=0.1, dt_fs=0.5, T_K=50.0, seed=1004, step0=3, n_steps=1,
+                      site0=z0 * plane)
+    inner = slice(2 * plane, (nz - 2) * plane)
+    np.testing.assert_array_equal(got[:, inner], full[:, (z0 + 2) * plane:(z0 + nz - 2) * plane])
+    # without the offset the noise differs
+    off = oracle.heun(oracle_model(ws), slab, alpha=0.1, dt_fs=0.5, T_K=50.0, seed=1004, step0=3, n_steps=1)
+    assert np.max(np.abs(off[:, inner] - got[:, inner])) > 1e-6
