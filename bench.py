@@ -31,7 +31,11 @@ METRIC = "spin updates/s (field+Heun), % HBM peak; GNEB iters learned vs plain i
 # state, 24 B per spin state): the predictor reads S and writes S~ (48 B), the
 # corrector reads S and S~ and writes S' (72 B); neighbour reuse is on chip.
 BYTES_PER_SPIN = {"heun_predict": 48, "heun_correct": 72}
-KERNEL_SOURCES = ["paper_2605_26016_amd/csrc/spx_kernels.hip", "paper_2605_26016_amd/csrc/spx_device.hpp"]
+KERNEL_SOURCES = ["paper_2605_26016_amd/csrc/spx_kernels.hip", "paper_2605_26016_amd/csrc/spx_device.hpp",
+                  "paper_2605_26016_amd/csrc/spx_stencil.hip", "paper_2605_26016_amd/csrc/spx_stencil.hpp",
+                  "paper_2605_26016_amd/csrc/spx_internal.hpp"]
+# corrector kernel name per stencil engine (1 gather, 2 z-march)
+CORRECT_KERNEL = {1: "k_heun_correct", 2: "k_zmarch (corrector instantiation)"}
 
 
 def log(*a):
@@ -139,26 +143,67 @@ def gneb_workload(args):
     if args.no_learned:
         print(json.dumps(out), flush=True)
         return
-    # -- learned vs geodesic initial path on hopfion annihilation paths
-    J4 = (1.0, 0.188, -0.274, -0.161)
-    L = args.gneb_L
-    n_img = 16
-    h = spx.setup_hamiltonian((L, L, L), periodic=(0, 0, 0), J_shell=J4, field_prec="fp64")
-    N = L ** 3
-    fm = torch.from_numpy(uniform_state(N)).cuda()
+    out["learned_init"] = {fam: learned_experiment(fam, args) for fam in args.families.split(",")}
+    print(json.dumps(out), flush=True)
 
-    def endpoints(seeds):
-        st = []
-        for s in seeds:
+
+def learned_experiment(family, args):
+    """Train the path corrector on GNEB-converged paths of one family and
+    compare GNEB from the learned and the geodesic initial path on held-out
+    end states.  hopfion: four-shell frustrated sc exchange (J1 = 1 meV,
+    J2/J1 = 0.188, J3/J1 = -0.274, J4/J1 = -0.161), open L^3, VP-relaxed
+    seeded hopfion -> FM.  skyrmion: sc monolayer film, J = 1 meV, bulk DMI
+    0.3 meV, B = 1.4 T, periodic in plane, relaxed seeded skyrmion -> FM,
+    trained on 32^2 and evaluated on a ragged batch of 48^2, 64^2, 96^2 films
+    with 32 images."""
+    import numpy as np
+    import torch
+
+    from paper_2605_26016_amd import pathinit, spx
+    from workloads import hopfion_texture, skyrmion_texture, uniform_state
+
+    t0 = time.perf_counter()
+    if family == "hopfion":
+        J = dict(J_shell=(1.0, 0.188, -0.274, -0.161))
+        Ltr = (args.gneb_L,) * 3
+        Lte = [Ltr]
+        per = (0, 0, 0)
+        n_tr_img, n_te_img = 16, 16
+        n_train, n_test = args.n_train, args.n_test
+
+        def seed_state(L, s):
             rng = np.random.default_rng(s)
-            S = hopfion_texture((L, L, L), R0=L / 6 * (1 + 0.2 * rng.uniform(-1, 1)),
-                                width=L / 6 * (1 + 0.2 * rng.uniform(-1, 1)), center_offset=rng.uniform(-2, 2, 3))
-            st.append(torch.from_numpy(S).cuda())
-        rel, its, mf = pathinit.minimize(h, st, tol=2e-4, max_iter=30000, vp_dt=0.2)
-        keep = [r for r in rel if int((r[2] < 0).sum()) > 0]   # textures that survived relaxation
-        return keep, its, mf
+            m = min(L) / 6
+            return hopfion_texture(L, R0=m * (1 + 0.2 * rng.uniform(-1, 1)), width=m * (1 + 0.2 * rng.uniform(-1, 1)),
+                                   center_offset=rng.uniform(-2, 2, 3))
+    else:
+        J = dict(J_shell=(1.0,), D_shell=(0.3,), B=(0.0, 0.0, 1.4))
+        Ltr = (32, 32, 1)
+        Lte = [(48, 48, 1), (64, 64, 1), (96, 96, 1)]
+        per = (1, 1, 0)
+        n_tr_img, n_te_img = 16, 32
+        n_train, n_test = args.n_train, 3 * max(1, args.n_test // 3)
 
-    def paths(A):
+        def seed_state(L, s):
+            rng = np.random.default_rng(s)
+            return skyrmion_texture(L, R=3.0 * (1 + 0.3 * rng.uniform(-1, 1)), center=tuple(rng.uniform(-3, 3, 2)))
+
+    hams = {}
+
+    def ham(L):
+        if L not in hams:
+            hams[L] = spx.setup_hamiltonian(L, periodic=per, field_prec="fp64", **J)
+        return hams[L]
+
+    def endpoints(L, seeds):
+        h = ham(L)
+        st = [torch.from_numpy(seed_state(L, s)).cuda() for s in seeds]
+        rel, _, _ = pathinit.minimize(h, st, tol=2e-4, max_iter=30000, vp_dt=0.2)
+        return [r for r in rel if int((r[2] < 0).sum()) > 0]   # textures that survived relaxation
+
+    def paths(L, A, n_img):
+        N = L[0] * L[1] * L[2]
+        fm = torch.from_numpy(uniform_state(N)).cuda()
         Ys = []
         for a in A:
             Y = torch.zeros((n_img, 3, N), dtype=torch.float64, device="cuda")
@@ -167,40 +212,42 @@ def gneb_workload(args):
             Ys.append(Y)
         return Ys
 
-    t0 = time.perf_counter()
-    A_tr, its_tr, _ = endpoints(range(1000, 1000 + args.n_train))
-    Y_tr = paths(A_tr)
+    A_tr = endpoints(Ltr, range(1000, 1000 + n_train))
+    Y_tr = paths(Ltr, A_tr, n_tr_img)
     geo = [y.clone() for y in Y_tr]
-    gg = spx.gneb_create([h] * len(geo), geo)
+    gg = spx.gneb_create([ham(Ltr)] * len(geo), geo)
     spx.gneb_init_path(gg)
-    res_tr = pathinit.converge([h] * len(Y_tr), Y_tr, tol=1e-3, max_iter=args.max_iter, chunk=1000)
+    res_tr = pathinit.converge([ham(Ltr)] * len(Y_tr), Y_tr, tol=1e-3, max_iter=args.max_iter, chunk=1000)
     ok = [k for k in range(len(Y_tr)) if res_tr.converged[k]]
-    log(f"[bench] training paths: {len(ok)}/{len(Y_tr)} converged, median iterations "
-        f"{int(np.median(res_tr.iterations))}, {time.perf_counter() - t0:.1f} s")
-    data = pathinit.build_samples((L, L, L), [geo[k] for k in ok], [Y_tr[k] for k in ok])
-    p, net, hist = pathinit.train(data, epochs=args.epochs, batch=16, lr=2e-3)
-    log(f"[bench] trained: loss {hist[0]:.3e} -> {hist[-1]:.3e}, {time.perf_counter() - t0:.1f} s")
-    A_te, _, _ = endpoints(range(5000, 5000 + args.n_test))
-    Yp = paths(A_te)
+    log(f"[bench] {family}: {len(ok)}/{len(Y_tr)} training paths converged (median "
+        f"{int(np.median(res_tr.iterations))} iterations), {time.perf_counter() - t0:.1f} s")
+    data = pathinit.build_samples(Ltr, [geo[k] for k in ok], [Y_tr[k] for k in ok])
+    p, net, hist = pathinit.train(data, epochs=args.epochs, batch=16, lr=1e-3)
+    log(f"[bench] {family}: trained, loss {hist[0]:.3e} -> {hist[-1]:.3e}, {time.perf_counter() - t0:.1f} s")
+    Hs, Yp = [], []
+    per_size = max(1, n_test // len(Lte))
+    for i, L in enumerate(Lte):
+        A = endpoints(L, range(5000 + 100 * i, 5000 + 100 * i + per_size))
+        Yp += paths(L, A, n_te_img)
+        Hs += [ham(L)] * len(A)
     Yl = [y.clone() for y in Yp]
-    rp = pathinit.converge([h] * len(Yp), Yp, tol=1e-3, max_iter=args.max_iter, chunk=500)
-    rl = pathinit.converge([h] * len(Yl), Yl, tol=1e-3, max_iter=args.max_iter, chunk=500, method=1, net=net,
-                           params=p)
+    rp = pathinit.converge(Hs, Yp, tol=1e-3, max_iter=args.max_iter, chunk=250)
+    rl = pathinit.converge(Hs, Yl, tol=1e-3, max_iter=args.max_iter, chunk=250, method=1, net=net, params=p)
     both = [k for k in range(len(Yp)) if rp.converged[k] and rl.converged[k]]
     dbar = np.abs(rl.barrier - rp.barrier)
     same = [k for k in both if dbar[k] <= 0.1]
-    it_p = float(np.mean(rp.iterations[same])) if same else float("nan")
-    it_l = float(np.mean(rl.iterations[same])) if same else float("nan")
-    out["learned_init"] = {
-        "model": "sc four-shell frustrated exchange J1 = 1 meV, J2/J1 = 0.188, J3/J1 = -0.274, J4/J1 = -0.161",
-        "lattice": [L, L, L], "images": n_img, "train_paths": len(ok), "test_paths": len(Yp),
-        "test_converged_both": len(both), "same_channel_within_0.1meV": len(same),
-        "iterations_geodesic": rp.iterations.tolist(), "iterations_learned": rl.iterations.tolist(),
-        "barrier_geodesic_meV": np.round(rp.barrier, 4).tolist(), "barrier_learned_meV": np.round(rl.barrier, 4).tolist(),
-        "mean_iterations_geodesic": it_p, "mean_iterations_learned": it_l,
-        "iteration_ratio_learned_over_geodesic": it_l / it_p if same else None,
-        "train_loss_first_last": [hist[0], hist[-1]], "seconds_total": time.perf_counter() - t0}
-    print(json.dumps(out), flush=True)
+    it_p = float(np.mean(rp.iterations[same])) if same else None
+    it_l = float(np.mean(rl.iterations[same])) if same else None
+    return {"lattice_train": list(Ltr), "lattices_test": [list(L) for L in Lte], "images_train": n_tr_img,
+            "images_test": n_te_img, "train_paths": len(ok), "test_paths": len(Yp),
+            "test_converged_both": len(both), "same_channel_within_0.1meV": len(same),
+            "iterations_geodesic": rp.iterations.tolist(), "iterations_learned": rl.iterations.tolist(),
+            "barrier_geodesic_meV": np.round(rp.barrier, 4).tolist(),
+            "barrier_learned_meV": np.round(rl.barrier, 4).tolist(),
+            "mean_iterations_geodesic_same_channel": it_p, "mean_iterations_learned_same_channel": it_l,
+            "iteration_ratio_learned_over_geodesic": (it_l / it_p) if same else None,
+            "max_barrier_difference_same_channel_meV": float(np.max(dbar[same])) if same else None,
+            "train_loss_first_last": [hist[0], hist[-1]], "seconds": time.perf_counter() - t0}
 
 
 def main():
@@ -211,11 +258,17 @@ def main():
     ap.add_argument("--workload", default="bcc128_5shell_stochastic_mixed")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (shared by repeated runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, run 4 plain device copies of 3N doubles (a known byte "
+                         "count for scaling hardware traffic counters)")
     ap.add_argument("--no-learned", action="store_true", help="GNEB workload: throughput only")
     ap.add_argument("--gneb-L", type=int, default=32)
-    ap.add_argument("--n-train", type=int, default=48)
+    ap.add_argument("--n-train", type=int, default=200)
     ap.add_argument("--n-test", type=int, default=12)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--families", default="skyrmion,hopfion")
     ap.add_argument("--max-iter", type=int, default=30000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -239,7 +292,11 @@ def main():
     stream = torch.cuda.current_stream()
     h = spx.setup_hamiltonian(w.L, cell=w.cell, sub_frac=w.frac, mu=w.mu, periodic=w.periodic,
                               J_shell=w.J_shell, D_shell=w.D_shell, K=(w.K if w.K else None),
-                              K_axis=w.K_axis, B=w.B, dipolar=w.dipolar, field_prec=w.field_prec)
+                              K_axis=w.K_axis, B=w.B, dipolar=w.dipolar, field_prec=w.field_prec,
+                              autotune=0 if args.no_autotune else 1, tune_cache_path=args.tune_cache)
+    info = spx.get_info(h)
+    log(f"[bench] engine {info.stencil_engine} shape {info.shape} zchunk {info.zchunk} "
+        f"heun_field {info.heun_field} tuned {info.tuned} ({info.tuned_step_us:.1f} us/step while tuning)")
     S = torch.from_numpy(w.initial_state()).cuda()
     params = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed)
     spx.llg_heun_step(h, S, step0=0, n_steps=args.warmup, **params)
@@ -277,9 +334,16 @@ def main():
     achieved = kernels[dom]["GBps_algorithmic"]
     traffic = measured_traffic(dom)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_heun_correct",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": CORRECT_KERNEL.get(info.stencil_engine, "k_heun_correct"),
             "bytes_per_launch_algorithmic": BYTES_PER_SPIN[dom] * w.N}
     step_bytes = sum(BYTES_PER_SPIN.values())
+    if args.calibrate_copy:
+        src = torch.empty_like(S).copy_(S)
+        dst = torch.empty_like(S)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 4 copies of {src.numel() * 8} bytes")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 CPU oracle on a bounded sample ...")
@@ -301,7 +365,8 @@ def main():
         "config": {"workload": w.name, "lattice": "bcc (2 sublattices)" if w.n_sub == 2 else "sc",
                    "cells": list(w.L), "spins": w.N, "shells": w.n_shells, "T_K": w.T_K,
                    "alpha": w.alpha, "dt_fs": w.dt_fs, "field_prec": w.field_prec,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "stencil_engine": info.stencil_engine,
+                   "zchunk": info.zchunk, "heun_field": info.heun_field},
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels,

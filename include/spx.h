@@ -111,9 +111,14 @@ typedef struct {
  * stencil_engine: 0 auto, 1 gather kernel (any bond table), 2 z-marching LDS
  * engine (bond tables that match a built-in shell shape: simple cubic shells
  * 1, 1-3, 1-4; bcc shells 1-5).  zchunk: z planes per block of the z-march
- * engine (0 = default 8).  heun_field: 0 auto, 1 the corrector recomputes
- * the field of S^n, 2 the predictor stores the FP32 bilinear field of S^n
- * for the corrector (FP32 field_prec only; identical results). */
+ * engine (0 = default 8).  heun_field (z-march engine; the gather engine
+ * always recomputes): 0 auto (3), 1 the
+ * corrector recomputes the field of S^n, 2 the predictor stores the FP32
+ * bilinear field of S^n for the corrector (FP32 field_prec only; results
+ * identical to 1), 3 the predictor stores the stage P = S^n + dt/2 f(S^n)
+ * and the step's noise (FP64, 48 bytes per spin of library memory), so the
+ * corrector evaluates f(S~) only (results equal to 1 up to the rounding of
+ * the regrouped sum S^n + dt/2 f(S^n) + dt/2 f(S~)). */
 typedef struct {
     int32_t field_prec;        /* spx_precision */
     int32_t backend;
@@ -171,6 +176,13 @@ typedef struct {
 
 spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, void *stream);
 
+/* Graph replay of the Heun loop (default on): for n_steps >= 4 the library
+ * captures two steps (S -> scratch -> S, the noise step read from a device
+ * counter that the graph advances) once per (state pointer, constants,
+ * stream) and replays it n_steps/2 times.  Off while kernels are timed and
+ * with the dipolar term.  Results are identical to direct launches. */
+spx_status spx_set_heun_graph(spx_ham *h, int32_t enable);
+
 /* The thermal-noise normals eta_i^n the Heun kernels use for (seed, step,
  * tag), written as [dev] double[3][N] for N sites.  Test hook of the RNG
  * stream; no handle needed. */
@@ -194,7 +206,10 @@ typedef struct {
     int32_t stencil_engine;    /* 1 gather, 2 z-march */
     int32_t shape;             /* z-march shell shape id, -1 if none */
     int32_t zchunk;
-    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field */
+    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field, 3 stored stage and noise */
+    int32_t tuned;             /* 1 if the autotuner chose zchunk / heun_field */
+    double tuned_step_us;      /* its timing of one Heun step (microseconds) */
+    int32_t heun_graph;        /* 1 once a captured Heun graph exists (replayed for runs of >= 4 steps) */
 } spx_ham_info;
 spx_status spx_get_info(spx_ham *h, spx_ham_info *info);
 

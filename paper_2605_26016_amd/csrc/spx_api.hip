@@ -177,8 +177,18 @@ struct spx_ham {
     // z-march engine plan (valid when the bond table matches a shell shape)
     ZPlan zp;
     int engine = 1;          // 1 gather, 2 z-march
-    int heun_field = 1;      // 1 recompute, 2 stored FP32 field
+    int heun_field = 1;      // 1 recompute, 2 stored FP32 field, 3 stored stage (P, eta)
     float *d_bstore = nullptr;
+    double *d_P = nullptr;   // heun_field 3: S^n + dt/2 f(S^n)
+    double *d_eta = nullptr; // heun_field 3: the step's thermal noise
+    // Heun graph replay: 2-step graph with a device step counter
+    uint64_t *d_step = nullptr;
+    hipGraphExec_t heun_graph = nullptr;
+    std::vector<unsigned char> graph_key;
+    hipStream_t cap_stream = nullptr;  // private capture stream
+    int use_graph = 1;
+    int tuned = 0;
+    double tune_us = 0.0;
     // kernel timing: recorded (start, stop) event pairs per kind, and a pool
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[3];
@@ -237,6 +247,12 @@ struct KernelTimer {
 void free_all(spx_ham *h) {
     if (h->dense) dense_destroy(h->dense);
     h->dense = nullptr;
+    if (h->heun_graph) (void)hipGraphExecDestroy(h->heun_graph);
+    h->heun_graph = nullptr;
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    h->cap_stream = nullptr;
+    if (h->d_step) (void)hipFree(h->d_step);
+    h->d_step = nullptr;
     for (auto &v : h->timed)
         for (auto &pr : v) {
             (void)hipEventDestroy(pr.first);
@@ -248,9 +264,11 @@ void free_all(spx_ham *h) {
     if (h->dip) destroy_dipolar(h->dip);
     h->dip = nullptr;
     for (void *p : {(void *)h->d_geo, (void *)h->d_Jf, (void *)h->d_Jd, (void *)h->d_St, (void *)h->d_Sp,
-                    (void *)h->d_partial, (void *)h->d_bdip0, (void *)h->d_bdip1, (void *)h->d_bstore})
+                    (void *)h->d_partial, (void *)h->d_bdip0, (void *)h->d_bdip1, (void *)h->d_bstore,
+                    (void *)h->d_P, (void *)h->d_eta})
         if (p) (void)hipFree(p);
     h->d_bstore = nullptr;
+    h->d_P = h->d_eta = nullptr;
     h->d_geo = nullptr;
     h->d_Jf = nullptr;
     h->d_Jd = nullptr;
@@ -286,6 +304,9 @@ spx_status get_ham_view(spx_ham *h, HamView &v) {
 }
 }  // namespace spx
 
+static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z, bool tune_field, hipStream_t st);
+static spx_status heun_buffers(spx_ham *h, int hf);
+
 extern "C" {
 
 int32_t spx_abi_version(void) { return SPX_ABI_VERSION; }
@@ -319,7 +340,7 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     const int hfield_req = opts ? opts->heun_field : 0;
     if (engine_req < 0 || engine_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown stencil_engine");
     if (zchunk_req < 0 || zchunk_req > 4096) return fail(SPX_ERR_INVALID_ARG, "zchunk out of range");
-    if (hfield_req < 0 || hfield_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
+    if (hfield_req < 0 || hfield_req > 3) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
     if (hfield_req == 2 && prec != SPX_FP32)
         return fail(SPX_ERR_INVALID_ARG, "a stored Heun field needs field_prec SPX_FP32");
     if (model->n_shells < 0 || model->n_bonds < 0 || model->n_aniso < 0)
@@ -493,8 +514,17 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
         h->engine = (have && engine_req != 1) ? 2 : 1;
         if (have && zchunk_req > 0) h->zp.zch = zchunk_req;
         h->heun_field = 1;
-        if (h->engine == 2 && prec == SPX_FP32 && hfield_req != 1) h->heun_field = 2;
-        if (h->heun_field == 2 && (s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field")) != SPX_OK) {
+        // stored stages exist in the z-march engine only; the gather engine recomputes
+        if (h->engine == 2) h->heun_field = hfield_req > 0 ? hfield_req : 3;
+        if ((s = heun_buffers(h, h->heun_field)) != SPX_OK) {
+            free_all(h);
+            delete h;
+            return s;
+        }
+    }
+    if (h->engine == 2 && opts && opts->autotune) {
+        s = autotune_heun(h, opts->tune_cache_path, zchunk_req == 0, hfield_req == 0, st);
+        if (s != SPX_OK) {
             free_all(h);
             delete h;
             return s;
@@ -538,6 +568,9 @@ spx_status spx_get_info(spx_ham *h, spx_ham_info *info) {
     info->shape = h->engine == 2 ? h->zp.kind : -1;
     info->zchunk = h->engine == 2 ? h->zp.zch : 0;
     info->heun_field = h->heun_field;
+    info->tuned = h->tuned;
+    info->tuned_step_us = h->tune_us;
+    info->heun_graph = h->heun_graph ? 1 : 0;
     return SPX_OK;
 }
 
@@ -556,6 +589,236 @@ spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, doub
 
 static spx_status dipolar_field(spx_ham *h, const double *S, float *bdip, hipStream_t st) {
     return eval_dipolar(h->dip, S, bdip, st);
+}
+
+__global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
+__global__ void k_add_u64(uint64_t *p, uint64_t v) { *p += v; }
+
+// One normalised Heun step cur -> nxt (predictor into d_St, then corrector).
+static spx_status enqueue_heun_step(spx_ham *h, const HeunConst &hc, uint64_t step, const double *cur, double *nxt,
+                                    hipStream_t st) {
+    const float *bd0 = nullptr, *bd1 = nullptr;
+    if (h->dip) {
+        spx_status s = dipolar_field(h, cur, h->d_bdip0, st);
+        if (s != SPX_OK) return s;
+        bd0 = h->d_bdip0;
+    }
+    hipError_t e;
+    {
+        KernelTimer kt(h, 0, st);
+        if (h->engine == 2)
+            e = zmarch_predict(h->zp, h->grid, h->onsite, hc, step, cur, bd0, h->d_St,
+                               h->heun_field == 2 ? h->d_bstore : nullptr, h->heun_field == 3 ? h->d_P : nullptr,
+                               (h->heun_field == 3 && hc.noise) ? h->d_eta : nullptr, st);
+        else
+            e = launch_heun_predict(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, bd0, h->d_St, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: predictor");
+    if (h->dip) {
+        spx_status s = dipolar_field(h, h->d_St, h->d_bdip1, st);
+        if (s != SPX_OK) return s;
+        bd1 = h->d_bdip1;
+    }
+    {
+        KernelTimer kt(h, 1, st);
+        if (h->engine == 2)
+            e = zmarch_correct(h->zp, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
+                               h->heun_field == 2 ? h->d_bstore : nullptr, h->heun_field == 3 ? h->d_P : nullptr,
+                               (h->heun_field == 3 && hc.noise) ? h->d_eta : nullptr, nxt, st);
+        else
+            e = launch_heun_correct(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1, nxt,
+                                    st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: corrector");
+    return SPX_OK;
+}
+
+__global__ void k_fill_up(double *S, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    S[i] = 0.0;
+    S[N + i] = 0.0;
+    S[2 * N + i] = 1.0;
+}
+
+// Buffers that Heun mode hf needs (allocated if missing): 2 the FP32 field
+// store, 3 the stage store P and the noise store.
+static spx_status heun_buffers(spx_ham *h, int hf) {
+    const size_t n3 = (size_t)3 * h->grid.N;
+    spx_status s = SPX_OK;
+    if (hf == 2 && !h->d_bstore) s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field");
+    if (s == SPX_OK && hf == 3 && !h->d_P) s = dev_alloc(h, &h->d_P, n3, "stored Heun stage");
+    if (s == SPX_OK && hf == 3 && !h->d_eta) s = dev_alloc(h, &h->d_eta, n3, "stored Heun noise");
+    return s;
+}
+
+// Frees the stores that the selected mode does not use.
+static void heun_buffers_trim(spx_ham *h) {
+    const int64_t n3 = 3 * h->grid.N;
+    if (h->heun_field != 2 && h->d_bstore) {
+        (void)hipFree(h->d_bstore);
+        h->d_bstore = nullptr;
+        h->ws_bytes -= (int64_t)sizeof(float) * n3;
+    }
+    if (h->heun_field != 3) {
+        for (double **p : {&h->d_P, &h->d_eta})
+            if (*p) {
+                (void)hipFree(*p);
+                *p = nullptr;
+                h->ws_bytes -= (int64_t)sizeof(double) * n3;
+            }
+    }
+}
+
+// Autotuner of the z-march engine: times stochastic Heun steps for every
+// candidate (z planes per block, stored or recomputed corrector field) on a
+// scratch state and keeps the fastest.  Results are cached per shape key
+// (shell shape, precision, sublattices, extents, boundary flags) as lines
+// "key zchunk heun_field microseconds" in cache_path when it is given.
+static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z, bool tune_field, hipStream_t st) {
+    const Grid &g = h->grid;
+    char key[160];
+    std::snprintf(key, sizeof(key), "shape%d_prec%d_sub%d_%dx%dx%d_per%d%d%d", h->zp.kind, h->field_prec, g.n_sub,
+                  g.Lx, g.Ly, g.Lz, g.per[0], g.per[1], g.per[2]);
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char k2[160];
+            int z, hf;
+            double us;
+            bool hit = false;
+            int cz = 0, chf = 0;
+            double cus = 0.0;
+            while (std::fscanf(f, "%159s %d %d %lf", k2, &z, &hf, &us) == 4)
+                if (std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && (hf == 1 || hf == 2)) {
+                    cz = z; chf = hf; cus = us; hit = true;   // the last matching line wins
+                }
+            std::fclose(f);
+            if (hit && !(chf == 2 && h->field_prec != SPX_FP32)) {
+                if (tune_z) h->zp.zch = cz;
+                if (tune_field) h->heun_field = chf;
+                h->tune_us = cus;
+                h->tuned = 1;
+                spx_status s = heun_buffers(h, h->heun_field);
+                heun_buffers_trim(h);
+                return s;
+            }
+        }
+    }
+    std::vector<int> zs;
+    if (tune_z) {
+        for (int z : {4, 8, 16, 32})
+            if (z <= g.Lz || zs.empty()) zs.push_back(z);
+    } else {
+        zs.push_back(h->zp.zch);
+    }
+    std::vector<int> hfs = {h->heun_field};
+    if (tune_field) {
+        hfs = {1, 3};
+        if (h->field_prec == SPX_FP32) hfs = {1, 2, 3};
+    }
+    for (int hf : hfs) {
+        spx_status s = heun_buffers(h, hf);
+        if (s != SPX_OK) return s;
+    }
+    double *tmp = nullptr;
+    spx_status s = dev_alloc(h, &tmp, (size_t)3 * g.N, "autotune scratch state");
+    if (s != SPX_OK) return s;
+    h->ws_bytes -= (int64_t)(sizeof(double) * 3 * g.N);
+    k_fill_up<<<(unsigned)((g.N + 255) / 256), 256, 0, st>>>(tmp, g.N);
+    HeunConst hc;
+    std::memset(&hc, 0, sizeof(hc));
+    hc.dt = 0.1;
+    hc.alpha = 0.1;
+    hc.pre = -kGammaPerFs / 1.01;
+    hc.seed = 1;
+    hc.noise = 1;
+    for (int a = 0; a < g.n_sub; ++a) {
+        hc.inv_mumuB[a] = 1.0 / (h->mu[a] * kMuB);
+        hc.sigma[a] = 100.0;
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best = 1e300;
+    int bz = h->zp.zch, bh = h->heun_field;
+    const int reps = 4;
+    for (int z : zs)
+        for (int hf : hfs) {
+            h->zp.zch = z;
+            h->heun_field = hf;
+            spx_status r = SPX_OK;
+            for (int k = 0; k < 2 && r == SPX_OK; ++k) r = enqueue_heun_step(h, hc, k, tmp, h->d_Sp, st);
+            (void)hipEventRecord(e0, st);
+            for (int k = 0; k < reps && r == SPX_OK; ++k)
+                r = enqueue_heun_step(h, hc, k, (k & 1) ? h->d_Sp : tmp, (k & 1) ? tmp : h->d_Sp, st);
+            (void)hipEventRecord(e1, st);
+            if (r != SPX_OK || hipEventSynchronize(e1) != hipSuccess) {
+                s = r != SPX_OK ? r : hip_fail(hipGetLastError(), "autotune");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double us = 1e3 * ms / reps;
+            if (us < best) { best = us; bz = z; bh = hf; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(tmp);
+    if (s != SPX_OK) return s;
+    h->zp.zch = bz;
+    h->heun_field = bh;
+    h->tuned = 1;
+    h->tune_us = best;
+    heun_buffers_trim(h);
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s %d %d %.3f\n", key, bz, bh, best);
+            std::fclose(f);
+        }
+    }
+    return SPX_OK;
+}
+
+// (Re)capture the 2-step Heun graph for state S, constants hc and stream st.
+static hipError_t heun_graph_prepare(spx_ham *h, HeunConst hc, double *S, hipStream_t st) {
+    if (!h->d_step) {
+        hipError_t e = hipMalloc((void **)&h->d_step, sizeof(uint64_t));
+        if (e != hipSuccess) return e;
+    }
+    hc.step_dev = h->d_step;
+    std::vector<unsigned char> key(sizeof(HeunConst) + sizeof(void *));
+    std::memcpy(key.data(), &hc, sizeof(HeunConst));
+    std::memcpy(key.data() + sizeof(HeunConst), &S, sizeof(void *));
+    if (h->heun_graph && key == h->graph_key) return hipSuccess;
+    if (h->heun_graph) (void)hipGraphExecDestroy(h->heun_graph);
+    h->heun_graph = nullptr;
+    // capture on a private stream: the caller's stream may be the legacy null
+    // stream, which cannot be captured; the graph is launched on st
+    if (!h->cap_stream) {
+        hipError_t e0 = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e0 != hipSuccess) return e0;
+    }
+    hipStream_t cs = h->cap_stream;
+    hipGraph_t graph;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    spx_status s1 = enqueue_heun_step(h, hc, 0, S, h->d_Sp, cs);
+    spx_status s2 = s1 == SPX_OK ? enqueue_heun_step(h, hc, 1, h->d_Sp, S, cs) : s1;
+    if (s2 == SPX_OK) k_add_u64<<<1, 1, 0, cs>>>(h->d_step, 2);
+    e = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess) return e;
+    if (s2 != SPX_OK) {
+        (void)hipGraphDestroy(graph);
+        return hipErrorUnknown;
+    }
+    e = hipGraphInstantiate(&h->heun_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        h->heun_graph = nullptr;
+        return e;
+    }
+    h->graph_key = key;
+    return hipSuccess;
 }
 
 spx_status spx_eval_field(spx_ham *h, const double *S, void *b, void *stream) {
@@ -623,46 +886,37 @@ spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, voi
                                            (gamma * h->mu[a] * kMuB * p->dt_fs))
                                : 0.0;
     }
+    // Graph replay: one captured 2-step graph (S -> Sp -> S) whose noise step
+    // comes from a device counter that the graph itself advances by 2.  Not
+    // used with the dipolar FFT path or while kernels are being timed.
+    int n_pairs = (h->use_graph && !h->dip && !h->timing && p->n_steps >= 4) ? p->n_steps / 2 : 0;
+    if (n_pairs > 0 && heun_graph_prepare(h, hc, S, st) != hipSuccess) {
+        (void)hipGetLastError();  // capture unsupported: direct launches from now on
+        h->use_graph = 0;
+        n_pairs = 0;
+    }
+    if (n_pairs > 0) {
+        k_set_u64<<<1, 1, 0, st>>>(h->d_step, p->step0);
+        hipError_t e = hipGetLastError();
+        for (int k = 0; k < n_pairs && e == hipSuccess; ++k) e = hipGraphLaunch(h->heun_graph, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: graph replay");
+    }
     double *cur = S, *nxt = h->d_Sp;
-    for (int k = 0; k < p->n_steps; ++k) {
-        const uint64_t step = p->step0 + (uint64_t)k;
-        const float *bd0 = nullptr, *bd1 = nullptr;
-        if (h->dip) {
-            spx_status s = dipolar_field(h, cur, h->d_bdip0, st);
-            if (s != SPX_OK) return s;
-            bd0 = h->d_bdip0;
-        }
-        hipError_t e;
-        {
-            KernelTimer kt(h, 0, st);
-            if (h->engine == 2)
-                e = zmarch_predict(h->zp, h->grid, h->onsite, hc, step, cur, bd0, h->d_St,
-                                   h->heun_field == 2 ? h->d_bstore : nullptr, st);
-            else
-                e = launch_heun_predict(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, bd0, h->d_St, st);
-        }
-        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: predictor");
-        if (h->dip) {
-            spx_status s = dipolar_field(h, h->d_St, h->d_bdip1, st);
-            if (s != SPX_OK) return s;
-            bd1 = h->d_bdip1;
-        }
-        {
-            KernelTimer kt(h, 1, st);
-            if (h->engine == 2)
-                e = zmarch_correct(h->zp, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
-                                   h->heun_field == 2 ? h->d_bstore : nullptr, nxt, st);
-            else
-                e = launch_heun_correct(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
-                                        nxt, st);
-        }
-        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: corrector");
+    for (int k = 2 * n_pairs; k < p->n_steps; ++k) {
+        spx_status s = enqueue_heun_step(h, hc, p->step0 + (uint64_t)k, cur, nxt, st);
+        if (s != SPX_OK) return s;
         std::swap(cur, nxt);
     }
     if (cur != S) {
         hipError_t e = hipMemcpyAsync(S, cur, sizeof(double) * 3 * (size_t)h->grid.N, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: copy-back");
     }
+    return SPX_OK;
+}
+
+spx_status spx_set_heun_graph(spx_ham *h, int32_t enable) {
+    if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    h->use_graph = enable ? 1 : 0;
     return SPX_OK;
 }
 

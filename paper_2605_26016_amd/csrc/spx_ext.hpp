@@ -60,10 +60,12 @@ bool zmarch_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, cons
 hipError_t zmarch_field(const ZPlan &zp, const Grid &g, const Onsite &os, const double *S, const float *bdip,
                         void *b, hipStream_t st);
 hipError_t zmarch_predict(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
-                          const double *S, const float *bdip, double *St, float *bstore, hipStream_t st);
+                          const double *S, const float *bdip, double *St, float *bstore, double *pstore,
+                          double *estore, hipStream_t st);
 hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
                           const double *S, const double *St, const float *bdipS, const float *bdipT,
-                          const float *bload, double *out, hipStream_t st);
+                          const float *bload, const double *pload, const double *eload, double *out,
+                          hipStream_t st);
 
 // Dense-window MFMA field (spx_dense.hip).
 struct DensePlan;

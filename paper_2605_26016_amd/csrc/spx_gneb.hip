@@ -471,7 +471,7 @@ struct spx_gneb {
     float *d_tvals = nullptr;   // reaction coordinates for the learned init
     int max_img = 0;
     hipGraphExec_t graph = nullptr;
-    hipStream_t graph_stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // library-owned capture stream (the caller's may be the null stream)
     int use_graph = 1;
 };
 
@@ -489,6 +489,9 @@ spx_status gneb_alloc(spx_gneb *g, void **p, size_t bytes, const char *what) {
 
 void gneb_free(spx_gneb *g) {
     if (g->graph) (void)hipGraphExecDestroy(g->graph);
+    g->graph = nullptr;
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    g->cap_stream = nullptr;
     for (void *p : g->owned) (void)hipFree(p);
     g->owned.clear();
 }
@@ -672,29 +675,27 @@ spx_status spx_gneb_step(spx_gneb *g, int32_t n_iter, void *stream) {
     if (n_iter < 0) return set_error(SPX_ERR_INVALID_ARG, "n_iter < 0");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    if (g->use_graph && n_iter > 1) {
-        if (!g->graph || g->graph_stream != st) {
-            if (g->graph) (void)hipGraphExecDestroy(g->graph);
-            g->graph = nullptr;
-            hipGraph_t graph;
-            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                hipError_t e2 = enqueue_iteration(g, st);
-                e = hipStreamEndCapture(st, &graph);
-                if (e == hipSuccess) e = e2;
-            }
+    if (g->use_graph && n_iter > 1 && !g->graph) {
+        // One iteration captured once on a private stream; the graph is then
+        // launched on whatever stream the caller passes.  Capture failure
+        // (graphs unsupported) leaves direct launches in place.
+        if (!g->cap_stream) e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+        hipGraph_t graph;
+        if (e == hipSuccess) e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = enqueue_iteration(g, g->cap_stream);
+            e = hipStreamEndCapture(g->cap_stream, &graph);
+            if (e == hipSuccess) e = e2;
             if (e == hipSuccess) {
                 e = hipGraphInstantiate(&g->graph, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
             }
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                g->graph = nullptr;
-                g->use_graph = 0;  // fall back to direct launches
-                e = hipSuccess;
-            } else {
-                g->graph_stream = st;
-            }
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            g->graph = nullptr;
+            g->use_graph = 0;
+            e = hipSuccess;
         }
     }
     for (int it = 0; it < n_iter && e == hipSuccess; ++it) {

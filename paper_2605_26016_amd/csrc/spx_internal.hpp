@@ -54,7 +54,14 @@ struct HeunConst {
     uint64_t seed;
     uint32_t tag;
     int noise;                     // 0: T = 0, no RNG calls
+    // optional device step counter (graph replay): the noise step is
+    // *step_dev + the kernel's step argument when step_dev is not NULL
+    const uint64_t *step_dev;
 };
+
+__device__ __forceinline__ uint64_t noise_step(const HeunConst &hc, uint64_t step) {
+    return hc.step_dev ? *hc.step_dev + step : step;
+}
 
 // ---- kernel launchers (spx_kernels.hip) ------------------------------------
 // field_prec: 0 FP64 (b double), 1 FP32 (b float).  bdip may be NULL.

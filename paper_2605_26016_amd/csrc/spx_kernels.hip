@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_heun_predict(BondTable tb, Grid g, O
     }
     if (hc.noise) {
         double eta[3];
-        thermal_eta(hc.seed, step, hc.tag, (uint64_t)i, eta);
+        thermal_eta(hc.seed, noise_step(hc, step), hc.tag, (uint64_t)i, eta);
         const double sg = hc.sigma[a];
         B[0] += sg * eta[0];
         B[1] += sg * eta[1];
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_heun_correct(BondTable tb, Grid g, O
     }
     if (hc.noise) {
         double eta[3];
-        thermal_eta(hc.seed, step, hc.tag, (uint64_t)i, eta);
+        thermal_eta(hc.seed, noise_step(hc, step), hc.tag, (uint64_t)i, eta);
         const double sg = hc.sigma[a];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

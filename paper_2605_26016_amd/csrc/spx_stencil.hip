@@ -31,7 +31,11 @@ constexpr int kYB = 2;    // y sites per thread
 constexpr int kTYE = kTYT * kYB;  // tile height in y
 constexpr int kThreads = kTX * kTYT;
 
-enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3 };
+// ZM_CORRECT: recompute the fields of S^n and S~; ZM_CORRECT_STORED: read the
+// predictor's FP32 bilinear field of S^n; ZM_CORRECT_P: read the predictor's
+// partial update P = S^n + dt/2 f(S^n) and its noise eta (FP64), so that the
+// corrector evaluates only f(S~).
+enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4 };
 
 template <typename T, int NW>
 struct ZWeights {
@@ -50,6 +54,9 @@ struct ZArgs {
     void *bout;        // field output (field mode)
     float *bstore;     // predictor: FP32 bilinear field of S^n (may be NULL)
     const float *bload;  // stored-field corrector: that field
+    double *pstore;    // predictor: P = S^n + dt/2 f(S^n) (may be NULL)
+    double *estore;    // predictor: eta of this step (may be NULL; T > 0 only)
+    const double *pload, *eload;  // ZM_CORRECT_P: P and eta
     const float *bdip0, *bdip1;  // dipolar fields of S0 / S1 (may be NULL)
     uint64_t step;
 };
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     const int64_t N = g.N;
     // LDS inputs: the field of S0 (and of S1 for the recomputing corrector);
     // the stored-field corrector needs only the field of S1 = S~
-    const double *src[2] = {MODE == ZM_CORRECT_STORED ? g.S1 : g.S0, g.S1};
+    const double *src[2] = {(MODE == ZM_CORRECT_STORED || MODE == ZM_CORRECT_P) ? g.S1 : g.S0, g.S1};
 
     T acc[D][kYB][NSUB][3][NIN];
 #pragma unroll
@@ -140,6 +147,32 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     auto finish_site = [&](auto ac, int x, int y, int z, const T (&v)[NIN][3]) __attribute__((always_inline)) {
         constexpr int a = decltype(ac)::value;
         const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
+        if constexpr (MODE == ZM_CORRECT_P) {
+            const double st[3] = {g.S1[i], g.S1[N + i], g.S1[2 * N + i]};
+            double bt[3];
+            aniso_field(os, a, st, bt);
+            double B1[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double v1 = (double)v[0][c] + bt[c] + os.bz[a][c];
+                if (g.bdip1) v1 += (double)g.bdip1[c * N + i];
+                B1[c] = v1 * hc.inv_mumuB[a];
+            }
+            if (hc.noise) {
+                const double sg = hc.sigma[a];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) B1[c] += sg * g.eload[c * N + i];
+            }
+            double f1[3];
+            llg_rhs(st, B1, hc.pre, hc.alpha, f1);
+            const double hdt = 0.5 * hc.dt;
+            double p[3] = {g.pload[i] + hdt * f1[0], g.pload[N + i] + hdt * f1[1], g.pload[2 * N + i] + hdt * f1[2]};
+            normalise3(p);
+            g.out[i] = p[0];
+            g.out[N + i] = p[1];
+            g.out[2 * N + i] = p[2];
+            return;
+        }
         const double sv[3] = {g.S0[i], g.S0[N + i], g.S0[2 * N + i]};
         double ba[3];
         aniso_field(os, a, sv, ba);
@@ -161,14 +194,25 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             }
             if (hc.noise) {
                 double eta[3];
-                thermal_eta(hc.seed, g.step, hc.tag, (uint64_t)i, eta);
+                thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)i, eta);
                 const double sg = hc.sigma[a];
                 B[0] += sg * eta[0];
                 B[1] += sg * eta[1];
                 B[2] += sg * eta[2];
+                if (g.estore) {
+                    g.estore[i] = eta[0];
+                    g.estore[N + i] = eta[1];
+                    g.estore[2 * N + i] = eta[2];
+                }
             }
             double f[3];
             llg_rhs(sv, B, hc.pre, hc.alpha, f);
+            if (g.pstore) {
+                const double hdt = 0.5 * hc.dt;
+                g.pstore[i] = sv[0] + hdt * f[0];
+                g.pstore[N + i] = sv[1] + hdt * f[1];
+                g.pstore[2 * N + i] = sv[2] + hdt * f[2];
+            }
             double p[3] = {sv[0] + hc.dt * f[0], sv[1] + hc.dt * f[1], sv[2] + hc.dt * f[2]};
             normalise3(p);
             g.out[i] = p[0];
@@ -198,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             }
             if (hc.noise) {
                 double eta[3];
-                thermal_eta(hc.seed, g.step, hc.tag, (uint64_t)i, eta);
+                thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)i, eta);
                 const double sg = hc.sigma[a];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -415,19 +459,23 @@ hipError_t zmarch_field(const ZPlan &zp, const Grid &g, const Onsite &os, const 
 }
 
 hipError_t zmarch_predict(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
-                          const double *S, const float *bdip, double *St, float *bstore, hipStream_t st) {
+                          const double *S, const float *bdip, double *St, float *bstore, double *pstore,
+                          double *estore, hipStream_t st) {
     ZArgs a = make_args(zp, g);
     a.S0 = S;
     a.out = St;
     a.bdip0 = bdip;
     a.bstore = bstore;
+    a.pstore = pstore;
+    a.estore = estore;
     a.step = step;
     return launch_any<ZM_PREDICT>(zp, a, os, hc, st);
 }
 
 hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
                           const double *S, const double *St, const float *bdipS, const float *bdipT,
-                          const float *bload, double *out, hipStream_t st) {
+                          const float *bload, const double *pload, const double *eload, double *out,
+                          hipStream_t st) {
     ZArgs a = make_args(zp, g);
     a.S0 = S;
     a.S1 = St;
@@ -435,7 +483,13 @@ hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, cons
     a.bdip0 = bdipS;
     a.bdip1 = bdipT;
     a.bload = bload;
+    a.pload = pload;
+    a.eload = eload;
     a.step = step;
+    if (pload) {
+        if (hc.noise && !eload) return hipErrorInvalidValue;
+        return launch_any<ZM_CORRECT_P>(zp, a, os, hc, st);
+    }
     if (bload) return launch_any<ZM_CORRECT_STORED>(zp, a, os, hc, st);
     return launch_any<ZM_CORRECT>(zp, a, os, hc, st);
 }

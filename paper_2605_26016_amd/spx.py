@@ -65,7 +65,8 @@ class HamInfo(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_bonds", C.c_int32), ("field_prec", C.c_int32),
                 ("backend", C.c_int32), ("radius", C.c_int32 * 3), ("dipolar", C.c_int32),
                 ("workspace_bytes", C.c_int64), ("stencil_engine", C.c_int32), ("shape", C.c_int32),
-                ("zchunk", C.c_int32), ("heun_field", C.c_int32)]
+                ("zchunk", C.c_int32), ("heun_field", C.c_int32), ("tuned", C.c_int32),
+                ("tuned_step_us", C.c_double), ("heun_graph", C.c_int32)]
 
 
 _lib = None
@@ -93,6 +94,7 @@ def load(path: str = LIB_PATH):
         "spx_get_info": [vp, C.POINTER(HamInfo)],
         "spx_get_bonds": [vp, vp, vp, vp],
         "spx_set_kernel_timing": [vp, i32],
+        "spx_set_heun_graph": [vp, i32],
         "spx_gneb_create": [C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(C.c_int32), C.POINTER(GnebParams),
                             vp, C.POINTER(vp)],
         "spx_gneb_destroy": [vp],
@@ -447,3 +449,7 @@ def net_adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
     n = int(params.numel())
     _check(load().spx_net_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, int(step), float(lr), float(b1),
                                     float(b2), float(eps), _stream(stream)), "spx_net_adam_step")
+
+
+def set_heun_graph(h, enable=True):
+    _check(load().spx_set_heun_graph(_h(h), int(bool(enable))), "spx_set_heun_graph")

@@ -172,10 +172,10 @@ HEUN_CASES = [
 
 
 HEUN_SETUPS = [dict(stencil_engine=1), dict(stencil_engine=0, heun_field=1),
-               dict(stencil_engine=0, heun_field=0, zchunk=3)]
+               dict(stencil_engine=0, heun_field=3), dict(stencil_engine=0, heun_field=0, zchunk=3)]
 
 
-@pytest.mark.parametrize("setup", HEUN_SETUPS, ids=["gather", "zmarch_recompute", "auto_z3"])
+@pytest.mark.parametrize("setup", HEUN_SETUPS, ids=["gather", "zmarch_recompute", "zmarch_stage", "auto_z3"])
 @pytest.mark.parametrize("name,w,prec,extra,tol", HEUN_CASES, ids=[c[0] for c in HEUN_CASES])
 def test_heun_parity(name, w, prec, extra, tol, setup):
     S = w.initial_state() if w.init != "random" else random_sphere(w.N, 51)
@@ -197,6 +197,14 @@ def test_heun_stored_field_equals_recompute():
     a = gpu_heun(w, S, "fp32", setup=dict(heun_field=1), **kw)
     b = gpu_heun(w, S, "fp32", setup=dict(heun_field=2), **kw)
     assert np.array_equal(a, b)
+    # the stored stage regroups S + dt/2 f0 + dt/2 f1: equal up to rounding
+    c = gpu_heun(w, S, "fp32", setup=dict(heun_field=3), **kw)
+    assert np.max(np.abs(a - c)) <= 1e-14
+    # deterministic case (no noise store)
+    kw["temperature_K"] = 0.0
+    a = gpu_heun(w, S, "fp32", setup=dict(heun_field=1), **kw)
+    c = gpu_heun(w, S, "fp32", setup=dict(heun_field=3), **kw)
+    assert np.max(np.abs(a - c)) <= 1e-14
 
 
 def test_heun_resume_and_determinism():
@@ -291,3 +299,48 @@ def test_dipolar_field_vs_numpy_fft_32():
     ref = dipolar_field_fft(L, w.cell, 2.0, S)
     got = gpu_field(w, S, "fp32")
     assert max_rel(got, ref) <= 1e-5
+
+
+def test_heun_graph_replay_is_bit_identical():
+    # captured 2-step graphs with a device step counter == direct launches
+    from paper_2605_26016_amd import spx
+    import torch
+    w = bcc_5shell_stochastic((10, 9, 8))
+    S0 = w.initial_state()
+    kw = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed)
+    for n in (10, 11):
+        ha = gpu_hamiltonian(w, field_prec="fp32")
+        hb = gpu_hamiltonian(w, field_prec="fp32")
+        spx.set_heun_graph(hb, False)
+        Sa, Sb = to_dev(S0), to_dev(S0)
+        spx.llg_heun_step(ha, Sa, step0=5, n_steps=n, **kw)
+        spx.llg_heun_step(ha, Sa, step0=5 + n, n_steps=n, **kw)   # graph reused, counter reset
+        spx.llg_heun_step(hb, Sb, step0=5, n_steps=2 * n, **kw)
+        torch.cuda.synchronize()
+        assert spx.get_info(ha).heun_graph == 1 and spx.get_info(hb).heun_graph == 0
+        assert torch.equal(Sa, Sb), n
+
+
+def test_autotuner_picks_candidate_and_caches(tmp_path):
+    from paper_2605_26016_amd import spx
+    import torch
+    w = bcc_5shell_stochastic((16, 16, 16))
+    cache = str(tmp_path / "tune.txt")
+    h = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache)
+    info = spx.get_info(h)
+    assert info.tuned == 1 and info.zchunk in (4, 8, 16) and info.heun_field in (1, 2, 3)
+    assert info.tuned_step_us > 0
+    lines = open(cache).read().split("\n")
+    assert any(l.startswith("shape3_prec1_sub2_16x16x16") for l in lines)
+    h2 = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache)
+    i2 = spx.get_info(h2)
+    assert (i2.zchunk, i2.heun_field) == (info.zchunk, info.heun_field)
+    # the z chunk does not change results (same Heun mode, other launch shape)
+    S0 = w.initial_state()
+    h3 = gpu_hamiltonian(w, field_prec="fp32", zchunk=3, heun_field=info.heun_field)
+    kw = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed, step0=0, n_steps=4)
+    Sa, Sb = to_dev(S0), to_dev(S0)
+    spx.llg_heun_step(h, Sa, **kw)
+    spx.llg_heun_step(h3, Sb, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(Sa, Sb)

@@ -1,0 +1,169 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark uses (z-march engine, autotuned), against the FP64 oracle on the
+same seeded inputs.
+
+  - bcc 128^3 (4,194,304 spins), 5 shells, stochastic Heun at 300 K, FP32
+    field / FP64 state: the whole lattice after one step, max |S - S_ref|
+    <= 1e-9 per component; a 10-step trajectory is reported and bounded
+    loosely (1e-7), since mixed precision diverges slowly by design.
+  - sc 1024^3 (1.07e9 spins), stochastic Heun at 50 K: one step on the GPU;
+    an interior z-slab of 8 planes is checked against the oracle run on the
+    slab plus a 2-plane halo on each side, with the noise counters of the
+    slab's global site indices (1e-9).
+  - sc 256^3 chiral magnet with open-boundary dipolar field: the FP32 field
+    (stencil + FFT dipolar) at 40 sampled sites (corners, face centres, the
+    body centre, random sites) against the FP64 field with the direct O(N^2)
+    dipolar sum (max-rel 1e-5), and the dipolar part alone (1e-5 of its own
+    scale).
+  - sc 32^3 FP64 deterministic Heun: 100 steps, 1e-11.
+  - frustrated sc 48^3 x 32 images, FP64 GNEB: three iterations, 1e-9.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import gpu_hamiltonian, max_rel, oracle_model, require_gpu, to_dev
+from workloads import (Workload, bcc_5shell_stochastic, hopfion_texture, random_sphere,
+                       random_sphere_device, sc_billion, sc_chiral_dipolar, sc_nn_fp64, uniform_state)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def heun_kw(w, **kw):
+    d = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed)
+    d.update(kw)
+    return d
+
+
+def test_bcc128_full_lattice_one_step_and_trajectory():
+    import torch
+    from paper_2605_26016_amd import spx
+    w = bcc_5shell_stochastic()
+    S0 = w.initial_state()
+    h = gpu_hamiltonian(w, autotune=1)
+    info = spx.get_info(h)
+    print(f"engine {info.stencil_engine} zchunk {info.zchunk} heun_field {info.heun_field}", flush=True)
+    S = to_dev(S0)
+    spx.llg_heun_step(h, S, **heun_kw(w, step0=0, n_steps=1))
+    got = S.cpu().numpy()
+    m = oracle_model(w)
+    ref = oracle.heun(m, S0, alpha=w.alpha, dt_fs=w.dt_fs, T_K=w.T_K, seed=w.philox_seed, step0=0, n_steps=1)
+    err1 = float(np.max(np.abs(got - ref)))
+    print(f"bcc128 one step: max |dS| = {err1:.3e}", flush=True)
+    assert err1 <= 1e-9
+    spx.llg_heun_step(h, S, **heun_kw(w, step0=1, n_steps=9))
+    got = S.cpu().numpy()
+    ref = oracle.heun(m, ref, alpha=w.alpha, dt_fs=w.dt_fs, T_K=w.T_K, seed=w.philox_seed, step0=1, n_steps=9)
+    err10 = float(np.max(np.abs(got - ref)))
+    print(f"bcc128 10 steps: max |dS| = {err10:.3e}", flush=True)
+    assert err10 <= 1e-7
+    torch.cuda.synchronize()
+
+
+def test_sc1024_interior_slab_one_step():
+    import torch
+    from paper_2605_26016_amd import spx
+    w = sc_billion()
+    Lx, Ly, Lz = w.L
+    plane = Lx * Ly
+    S = random_sphere_device(w.N, w.init_seed)
+    z0, nz, halo = 509, 8, 2
+    lo, hi = (z0 - halo) * plane, (z0 + nz + halo) * plane
+    slab0 = S[:, lo:hi].cpu().numpy()
+    h = gpu_hamiltonian(w, autotune=1)
+    info = spx.get_info(h)
+    print(f"sc1024: engine {info.stencil_engine} zchunk {info.zchunk} heun_field {info.heun_field} "
+          f"workspace {info.workspace_bytes / 2**30:.1f} GiB", flush=True)
+    spx.llg_heun_step(h, S, **heun_kw(w, step0=7, n_steps=1))
+    got = S[:, z0 * plane:(z0 + nz) * plane].cpu().numpy()
+    nrm = float((torch.sqrt((S * S).sum(0)) - 1.0).abs().max())
+    del S, h
+    torch.cuda.empty_cache()
+    ws = Workload(name="slab", L=(Lx, Ly, nz + 2 * halo), periodic=(1, 1, 0), J_shell=w.J_shell, K=w.K)
+    ref = oracle.heun(oracle_model(ws), slab0, alpha=w.alpha, dt_fs=w.dt_fs, T_K=w.T_K, seed=w.philox_seed,
+                      step0=7, n_steps=1, site0=lo)
+    err = float(np.max(np.abs(got - ref[:, halo * plane:(halo + nz) * plane])))
+    print(f"sc1024 slab: max |dS| = {err:.3e}, max ||S|-1| = {nrm:.2e}", flush=True)
+    assert err <= 1e-9
+    assert nrm <= 1e-14
+
+
+def sample_sites(L, n_random, seed):
+    Lx, Ly, Lz = L
+    pts = [(x, y, z) for x in (0, Lx - 1) for y in (0, Ly - 1) for z in (0, Lz - 1)]
+    cx, cy, cz = Lx // 2, Ly // 2, Lz // 2
+    pts += [(0, cy, cz), (Lx - 1, cy, cz), (cx, 0, cz), (cx, Ly - 1, cz), (cx, cy, 0), (cx, cy, Lz - 1),
+            (cx, cy, cz)]
+    rng = np.random.default_rng(seed)
+    pts += [tuple(int(v) for v in rng.integers(0, (Lx, Ly, Lz))) for _ in range(n_random)]
+    return np.array([x + Lx * (y + Ly * z) for x, y, z in pts], dtype=np.int64)
+
+
+def test_sc256_dipolar_field_at_sampled_sites():
+    import torch
+    from paper_2605_26016_amd import spx
+    w = sc_chiral_dipolar()
+    S0 = w.initial_state()
+    idx = sample_sites(w.L, 25, 7)
+    S = to_dev(S0)
+    b = torch.empty((3, w.N), dtype=torch.float32, device="cuda")
+    spx.eval_field(gpu_hamiltonian(w, field_prec="fp32"), S, b)
+    got = b[:, torch.from_numpy(idx).cuda()].double().cpu().numpy()
+    wd = sc_chiral_dipolar()
+    wd.J_shell, wd.D_shell, wd.B = (0.0,), None, (0.0, 0.0, 0.0)
+    spx.eval_field(gpu_hamiltonian(wd, field_prec="fp32"), S, b)
+    got_dip = b[:, torch.from_numpy(idx).cuda()].double().cpu().numpy()
+    del b, S
+    ws = sc_chiral_dipolar()
+    ws.dipolar = 0
+    short = oracle.field(oracle_model(ws), S0)[:, idx]
+    dip = oracle.dipolar_direct(oracle_model(w).lat, S0, idx)
+    ref = short + dip
+    e_tot, e_dip = max_rel(got, ref), max_rel(got_dip, dip)
+    print(f"sc256 dipolar: total max-rel {e_tot:.2e}, dipolar part {e_dip:.2e} "
+          f"(max |b_dip| {np.abs(dip).max():.3e} meV)", flush=True)
+    assert e_tot <= 1e-5
+    assert e_dip <= 1e-5
+
+
+def test_sc32_fp64_hundred_steps():
+    from paper_2605_26016_amd import spx
+    w = sc_nn_fp64()
+    S0 = w.initial_state()
+    S = to_dev(S0)
+    spx.llg_heun_step(gpu_hamiltonian(w, autotune=1), S, **heun_kw(w, step0=0, n_steps=w.n_steps))
+    ref = oracle.heun(oracle_model(w), S0, alpha=w.alpha, dt_fs=w.dt_fs, T_K=0.0, n_steps=w.n_steps)
+    err = float(np.max(np.abs(S.cpu().numpy() - ref)))
+    print(f"sc32 fp64 100 steps: max |dS| = {err:.3e}", flush=True)
+    assert err <= 1e-11
+
+
+def test_gneb_48cubed_32_images_iterations():
+    import torch
+    from paper_2605_26016_amd import spx
+    L = (48, 48, 48)
+    w = Workload(name="g", L=L, periodic=(0, 0, 0), J_shell=(1.0, 0.188, -0.274, -0.161), field_prec="fp64")
+    A = hopfion_texture(L)
+    B = uniform_state(w.N)
+    n_img = 32
+    Y0 = oracle.geodesic_path(A, B, n_img)
+    Yd = to_dev(Y0)
+    g = spx.gneb_create([gpu_hamiltonian(w)], [Yd], spring_k=1.0, vp_dt=0.05, vp_mass=1.0, ci_mode=1,
+                        ci_on_below=1e-2)
+    st = oracle.GnebState(Y0, k_spring=1.0, dt=0.05, mass=1.0, ci_mode=1, ci_on_below=1e-2)
+    m = oracle_model(w)
+    for it in range(3):
+        E, dist, fmax, ci = oracle.gneb_iterate(m, st)
+        spx.gneb_step(g, 1)
+        s = spx.gneb_get_stats(g)
+        err = float(np.max(np.abs(Yd.cpu().numpy() - st.Y)))
+        print(f"gneb 48^3 x 32 it {it}: max |dY| = {err:.3e}, max|F| {fmax:.3e}", flush=True)
+        assert err <= 1e-9
+        np.testing.assert_allclose(s["E"], E, rtol=1e-10, atol=1e-9)
+        assert abs(s["max_force"] - fmax) <= 1e-9 * max(1.0, fmax)
+    torch.cuda.synchronize()

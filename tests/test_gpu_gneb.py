@@ -57,7 +57,7 @@ def test_geodesic_init_matches_oracle():
     assert np.max(np.abs(Yd.cpu().numpy() - ref)) < 1e-13
 
 
-@pytest.mark.parametrize("ci_mode", [0, 1, 2])
+@pytest.mark.parametrize("ci_mode", [0, 1, 2, 3])
 def test_gneb_iterations_match_oracle(ci_mode):
     import torch
     from paper_2605_26016_amd import spx

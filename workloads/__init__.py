@@ -23,6 +23,26 @@ def random_sphere(N: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(np.stack([r * np.cos(phi), r * np.sin(phi), z]))
 
 
+def random_sphere_device(N: int, seed: int, device="cuda"):
+    """Uniform random unit vectors drawn on a torch device, shape (3, N),
+    FP64: z ~ U[-1,1], phi ~ U[0,2pi) from torch's seeded generator of that
+    device.  For lattices too large to draw on the host (1024^3 spins); the
+    same bits are then copied to whoever checks them."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    S = torch.empty((3, N), dtype=torch.float64, device=device)
+    z = S[2]
+    z.uniform_(-1.0, 1.0, generator=g)
+    phi = S[0]
+    phi.uniform_(0.0, 2.0 * np.pi, generator=g)
+    r = torch.sqrt(torch.clamp(1.0 - z * z, min=0.0))
+    S[1].copy_(torch.sin(phi)).mul_(r)
+    S[0].copy_(torch.cos(phi)).mul_(r)
+    del r
+    return S
+
+
 def fm_tilt(N: int, seed: int, eps: float = 0.1) -> np.ndarray:
     """Ferromagnet along +z plus a seeded Gaussian tilt: (eps gx, eps gy, 1)/norm."""
     g = np.random.Generator(np.random.PCG64(seed))
