@@ -31,6 +31,11 @@ METRIC = "spin updates/s (field+Heun), % HBM peak; GNEB iters learned vs plain i
 # state, 24 B per spin state): the predictor reads S and writes S~ (48 B), the
 # corrector reads S and S~ and writes S' (72 B); neighbour reuse is on chip.
 BYTES_PER_SPIN = {"heun_predict": 48, "heun_correct": 72}
+# field only: FP64 spin in, FP32 field out
+FIELD_BYTES = 36
+# dense 7^3 window of 3x3 blocks: 342 offsets x 9 multiply-adds x 2 flop
+DENSE_FLOP_PER_SITE = 6156
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 KERNEL_SOURCES = ["paper_2605_26016_amd/csrc/spx_kernels.hip", "paper_2605_26016_amd/csrc/spx_device.hpp",
                   "paper_2605_26016_amd/csrc/spx_stencil.hip", "paper_2605_26016_amd/csrc/spx_stencil.hpp",
                   "paper_2605_26016_amd/csrc/spx_internal.hpp"]
@@ -69,6 +74,12 @@ def cpu_baseline(w, seconds: float):
     repeated until about `seconds` of CPU work."""
     import oracle
     from tests.helpers import oracle_model
+    what = f"the {w.N}-spin lattice"
+    if w.N > 50_000_000:
+        # the full lattice does not fit the host's memory three times over:
+        # the same physics on 256^3 cells, per spin-step
+        w = w.scaled((256, 256, 256))
+        what = f"a {w.N}-spin (256^3) lattice of the same model"
     m = oracle_model(w)
     S = w.initial_state()
     steps = 0
@@ -82,7 +93,7 @@ def cpu_baseline(w, seconds: float):
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": w.N * steps / el, "unit": "spin-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} full Heun step(s) of the {w.N}-spin lattice, FP64 oracle, {el:.1f} s"}
+            "sample": f"{steps} full Heun step(s) of {what}, FP64 oracle, {el:.1f} s"}
 
 
 # GNEB algorithmic HBM bytes per spin-image-iteration of the three passes
@@ -140,11 +151,34 @@ def gneb_workload(args):
                      "parallelism": "single GPU, ragged batch in one launch per pass"}
     del g, hams, imgs
     log(f"[bench] batched GNEB: {rate:.3e} spin-image-iterations/s")
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_gneb_baseline(args.cpu_seconds)
     if args.no_learned:
         print(json.dumps(out), flush=True)
         return
     out["learned_init"] = {fam: learned_experiment(fam, args) for fam in args.families.split(",")}
     print(json.dumps(out), flush=True)
+
+
+def cpu_gneb_baseline(seconds):
+    """FP64 oracle GNEB iterations on the 48^3 x 32-image instance."""
+    import oracle
+    from tests.helpers import oracle_model
+    from workloads import hopfion_texture, sc_frustrated_gneb, uniform_state
+    w = sc_frustrated_gneb((48, 48, 48), shells="config3")
+    m = oracle_model(w)
+    st = oracle.GnebState(oracle.geodesic_path(hopfion_texture(w.L), uniform_state(w.N), 32), ci_mode=1,
+                          ci_on_below=1e-2)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.gneb_iterate(m, st)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or el * (n + 1) / n > 2.5 * seconds:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 32 * w.N * n / el, "unit": "spin-image-iterations/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} GNEB iteration(s) of the 48^3 x 32-image instance, FP64 oracle, {el:.1f} s"}
 
 
 def learned_experiment(family, args):
@@ -250,6 +284,254 @@ def learned_experiment(family, args):
             "train_loss_first_last": [hist[0], hist[-1]], "seconds": time.perf_counter() - t0}
 
 
+def heun_workload(args, w):
+    """Field + (stochastic) Heun throughput of one lattice workload."""
+    import numpy as np
+    import torch
+
+    from paper_2605_26016_amd import spx
+    from workloads import random_sphere_device
+
+    log(f"[bench] workload {w.name}: {w.N} spins, {args.warmup} warmup + {args.steps} timed Heun steps")
+    stream = torch.cuda.current_stream()
+    h = spx.setup_hamiltonian(w.L, cell=w.cell, sub_frac=w.frac, mu=w.mu, periodic=w.periodic,
+                              J_shell=w.J_shell, D_shell=w.D_shell, K=(w.K if w.K else None),
+                              K_axis=w.K_axis, B=w.B, dipolar=w.dipolar, field_prec=w.field_prec,
+                              autotune=0 if args.no_autotune else 1, tune_cache_path=args.tune_cache)
+    info = spx.get_info(h)
+    log(f"[bench] engine {info.stencil_engine} shape {info.shape} zchunk {info.zchunk} "
+        f"heun_field {info.heun_field} tuned {info.tuned} ({info.tuned_step_us:.1f} us/step while tuning), "
+        f"library workspace {info.workspace_bytes / 2**30:.2f} GiB")
+    if w.N > 200_000_000:
+        # too large to draw on the host in reasonable time: torch's seeded device generator
+        S = random_sphere_device(w.N, w.init_seed)
+        data = "synthetic (seeded uniform random start drawn on the device, Philox noise)"
+    else:
+        S = torch.from_numpy(w.initial_state()).cuda()
+        data = "synthetic (seeded start, Philox noise)" if w.T_K > 0 else "synthetic (seeded start)"
+    params = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed)
+    spx.llg_heun_step(h, S, step0=0, n_steps=args.warmup, **params)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    kinds = ("heun_predict", "heun_correct", "noise")
+    # small lattices are launch-bound: the timed region replays the captured
+    # Heun graphs and the per-kernel durations come from a second pass
+    small = w.N < 1_000_000
+    if not small:
+        spx.set_kernel_timing(h, True)
+    for k in kinds:
+        spx.get_kernel_times(h, k)  # reset
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    spx.llg_heun_step(h, S, step0=args.warmup, n_steps=args.steps, **params)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    if small:
+        spx.set_kernel_timing(h, True)
+        spx.llg_heun_step(h, S, step0=args.warmup + args.steps, n_steps=min(args.steps, 100), **params)
+        torch.cuda.synchronize()
+    spx.set_kernel_timing(h, False)
+    kt = {k: spx.get_kernel_times(h, k) for k in kinds}
+    log(f"[bench] timed region: {gpu_ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
+    t = max(gpu_ms / 1e3, 1e-12)
+    value = w.N * args.steps / t
+    nrm = torch.sqrt((S * S).sum(0))
+    assert float((nrm - 1).abs().max()) < 1e-12, "state left the unit sphere"
+    del nrm
+
+    kernels = {}
+    for k, (cnt, tot) in kt.items():
+        if cnt == 0:
+            continue
+        avg = tot / cnt / 1e3
+        kernels[k] = {"launches": cnt, "avg_us": avg * 1e6}
+        if k in BYTES_PER_SPIN:
+            kernels[k]["GBps_algorithmic"] = BYTES_PER_SPIN[k] * w.N / avg / 1e9
+    # the dominant kernel: the stage with the larger summed time
+    dom = max(("heun_predict", "heun_correct"), key=lambda k: kt[k][1])
+    achieved = kernels[dom]["GBps_algorithmic"]
+    kname = {("heun_predict", 2): "k_zmarch (predictor instantiation)",
+             ("heun_correct", 2): "k_zmarch (corrector instantiation)",
+             ("heun_predict", 1): "k_heun_predict", ("heun_correct", 1): "k_heun_correct"}
+    traffic = measured_traffic(dom)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kname.get((dom, info.stencil_engine), dom),
+            "bytes_per_spin_algorithmic": BYTES_PER_SPIN[dom],
+            "bytes_per_launch_algorithmic": BYTES_PER_SPIN[dom] * w.N,
+            "kernel_timing": "separate pass after the timed region (graph replay timed)" if small
+            else "HIP events around every launch inside the timed region"}
+    step_bytes = sum(BYTES_PER_SPIN.values())
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+        log(f"[bench] cpu oracle: {cpu['value']:.3e} spin-steps/s on {cpu['cores']} threads")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spin-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 field + f64 state" if w.field_prec == "fp32" else "f64",
+        "data": data,
+        "config": {"workload": w.name, "lattice": "bcc (2 sublattices)" if w.n_sub == 2 else "sc",
+                   "cells": list(w.L), "spins": w.N, "shells": w.n_shells, "T_K": w.T_K,
+                   "alpha": w.alpha, "dt_fs": w.dt_fs, "field_prec": w.field_prec,
+                   "parallelism": "single GPU", "stencil_engine": info.stencil_engine,
+                   "zchunk": info.zchunk, "heun_mode": info.heun_field},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "step_effective_GBps": step_bytes * w.N * args.steps / t / 1e9,
+        "hbm_frac_step": step_bytes * w.N * args.steps / t / 1e9 / HBM_PEAK_GBS,
+        "device": torch.cuda.get_device_name(0),
+    }
+    if args.calibrate_copy:
+        src = torch.empty_like(S).copy_(S)
+        dst = torch.empty_like(S)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 4 copies of {src.numel() * 8} bytes")
+        del src, dst
+    print(json.dumps(out), flush=True)
+
+
+def k7_couplings(J=1.0, D=0.3, mu=2.0, a=0.4):
+    """Dense 7^3 window of 3x3 couplings (meV) on simple cubic with lattice
+    constant a (nm): J + bulk DMI (D along the bond) on the six nearest
+    neighbours and the dipole tensor (mu0/4pi) mu_B^2 mu^2 (3 rr - 1)/r^3 on
+    every other offset (the near field a dense convolution would hold)."""
+    import numpy as np
+    pref = 1.0e-7 * 9.2740100783e-24 ** 2 / 1.602176634e-22 * 1.0e27 * mu * mu  # meV nm^3
+    ab, dl, Js = [], [], []
+    for dz in range(-3, 4):
+        for dy in range(-3, 4):
+            for dx in range(-3, 4):
+                if dx == dy == dz == 0:
+                    continue
+                r = np.array([dx, dy, dz], float) * a
+                rn = np.linalg.norm(r)
+                u = r / rn
+                if abs(dx) + abs(dy) + abs(dz) == 1:
+                    Dv = D * u
+                    T = J * np.eye(3) + np.array([[0, Dv[2], -Dv[1]], [-Dv[2], 0, Dv[0]], [Dv[1], -Dv[0], 0]])
+                else:
+                    T = pref * (3 * np.outer(u, u) - np.eye(3)) / rn ** 3
+                ab.append((0, 0))
+                dl.append((dx, dy, dz))
+                Js.append(T)
+    return np.array(ab, np.int32), np.array(dl, np.int32), np.array(Js)
+
+
+def field_workload(args, w):
+    """Field-only evaluations of the sc 256^3 chiral magnet: the FP32 stencil
+    (J + DMI + Zeeman), the stencil plus the zero-padded FFT dipolar field,
+    and the dense 7^3 window in BF16/FP16 MFMA and FP32 direct form against
+    its FP64 evaluation."""
+    import numpy as np
+    import torch
+
+    from paper_2605_26016_amd import spx
+
+    stream = torch.cuda.current_stream()
+    S = torch.from_numpy(w.initial_state()).cuda()
+    b32 = torch.empty((3, w.N), dtype=torch.float32, device="cuda")
+
+    def timed(h, out, reps):
+        spx.eval_field(h, S, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            spx.eval_field(h, S, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(args.steps, 1)
+    common = dict(cell=w.cell, mu=w.mu, periodic=w.periodic, B=w.B)
+    h = spx.setup_hamiltonian(w.L, J_shell=w.J_shell, D_shell=w.D_shell, dipolar=0, field_prec="fp32", **common)
+    ms_st = timed(h, b32, reps)
+    del h
+    h = spx.setup_hamiltonian(w.L, J_shell=w.J_shell, D_shell=w.D_shell, dipolar=1, field_prec="fp32", **common)
+    ms_dip = timed(h, b32, max(reps // 10, 2))
+    del h
+    log(f"[bench] stencil {ms_st * 1e3:.1f} us, stencil + dipolar FFT {ms_dip:.3f} ms")
+    ab, dl, J9 = k7_couplings(mu=w.mu[0], a=w.cell[0][0])
+    b64 = torch.empty((3, w.N), dtype=torch.float64, device="cuda")
+    h = spx.setup_hamiltonian(w.L, bonds=(ab, dl, J9), field_prec="fp64", **common)
+    ms64 = timed(h, b64, 2)
+    del h
+    ref_max = float(b64.abs().max())
+    dense = {}
+    for prec in ("bf16", "fp16", "fp32"):
+        h = spx.setup_hamiltonian(w.L, bonds=(ab, dl, J9), field_prec=prec, backend=2 if prec != "fp32" else 0,
+                                  **common)
+        ms = timed(h, b32, reps if prec != "fp32" else max(reps // 20, 2))
+        err = float((b32.double() - b64).abs().max()) / ref_max
+        dense[prec] = {"ms": ms, "fields_per_s": w.N / ms * 1e3,
+                       "TFLOPs_algorithmic": DENSE_FLOP_PER_SITE * w.N / ms / 1e9,
+                       "max_rel_error_vs_fp64": err}
+        log(f"[bench] K7 dense {prec}: {ms:.3f} ms, error vs FP64 {err:.2e}")
+        del h
+    dense["fp64_direct_ms"] = ms64
+    mf = dense["bf16"]
+    roof = {"bound": "mfma", "achieved": round(mf["TFLOPs_algorithmic"], 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(mf["TFLOPs_algorithmic"] / MFMA_BF16_PEAK_TFLOPS, 4),
+            "traffic": None, "kernel": "k_dense_mfma (BF16)",
+            "flop_per_site_algorithmic": DENSE_FLOP_PER_SITE}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_field_baseline(w, args.cpu_seconds)
+    out = {"metric": "field evaluations/s (sc 256^3 chiral magnet + dipolar FFT); dense 7^3 MFMA TFLOP/s",
+           "value": w.N / ms_dip * 1e3, "unit": "fields/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+           "ms_per_step": ms_dip, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 field (f64 state); dense window bf16/fp16 MFMA with f32 accumulation",
+           "data": "synthetic (seeded uniform random spins)",
+           "config": {"workload": w.name, "cells": list(w.L), "spins": w.N, "boundary": "open",
+                      "parallelism": "single GPU"},
+           "roofline": roof,
+           "stencil_only": {"ms": ms_st, "fields_per_s": w.N / ms_st * 1e3,
+                            "GBps_algorithmic": FIELD_BYTES * w.N / ms_st / 1e6,
+                            "hbm_frac": FIELD_BYTES * w.N / ms_st / 1e6 / HBM_PEAK_GBS},
+           "stencil_plus_dipolar_fft_ms": ms_dip, "dense_7cubed": dense, "cpu_baseline": cpu,
+           "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_field_baseline(w, seconds):
+    """FP64 oracle field (J + DMI + Zeeman, no dipolar) on the full lattice."""
+    import oracle
+    from tests.helpers import oracle_model
+    ws = w.scaled(w.L)
+    ws.dipolar = 0
+    m = oracle_model(ws)
+    S = ws.initial_state()
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.field(m, S)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or el * (n + 1) / n > 2.5 * seconds:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.N * n / el, "unit": "fields/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} full-lattice short-range field evaluation(s), FP64 oracle, {el:.1f} s (dipolar excluded)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,99 +564,13 @@ def main():
     from paper_2605_26016_amd import spx
     from workloads import WORKLOADS
 
-    if args.workload == "sc_frustrated_gneb":
-        torch.cuda.set_device(0)
-        gneb_workload(args)
-        return
-    w = WORKLOADS[args.workload]()
-    log(f"[bench] workload {w.name}: {w.N} spins, {args.warmup} warmup + {args.steps} timed Heun steps")
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    h = spx.setup_hamiltonian(w.L, cell=w.cell, sub_frac=w.frac, mu=w.mu, periodic=w.periodic,
-                              J_shell=w.J_shell, D_shell=w.D_shell, K=(w.K if w.K else None),
-                              K_axis=w.K_axis, B=w.B, dipolar=w.dipolar, field_prec=w.field_prec,
-                              autotune=0 if args.no_autotune else 1, tune_cache_path=args.tune_cache)
-    info = spx.get_info(h)
-    log(f"[bench] engine {info.stencil_engine} shape {info.shape} zchunk {info.zchunk} "
-        f"heun_field {info.heun_field} tuned {info.tuned} ({info.tuned_step_us:.1f} us/step while tuning)")
-    S = torch.from_numpy(w.initial_state()).cuda()
-    params = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed)
-    spx.llg_heun_step(h, S, step0=0, n_steps=args.warmup, **params)
-    torch.cuda.synchronize()
-    log("[bench] warmup done")
-
-    spx.set_kernel_timing(h, True)
-    for k in ("heun_predict", "heun_correct"):
-        spx.get_kernel_times(h, k)  # reset
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    spx.llg_heun_step(h, S, step0=args.warmup, n_steps=args.steps, **params)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    spx.set_kernel_timing(h, False)
-    kt = {k: spx.get_kernel_times(h, k) for k in ("heun_predict", "heun_correct")}
-    log(f"[bench] timed region: {gpu_ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
-    t = max(gpu_ms / 1e3, 1e-12)
-    value = w.N * args.steps / t
-    # sanity: the state stays on the unit sphere
-    nrm = torch.sqrt((S * S).sum(0))
-    assert float((nrm - 1).abs().max()) < 1e-12, "state left the unit sphere"
-
-    kernels = {}
-    for k, (cnt, tot) in kt.items():
-        avg = tot / max(cnt, 1) / 1e3
-        kernels[k] = {"launches": cnt, "avg_us": avg * 1e6,
-                      "GBps_algorithmic": BYTES_PER_SPIN[k] * w.N / avg / 1e9}
-    dom = "heun_correct"
-    achieved = kernels[dom]["GBps_algorithmic"]
-    traffic = measured_traffic(dom)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": CORRECT_KERNEL.get(info.stencil_engine, "k_heun_correct"),
-            "bytes_per_launch_algorithmic": BYTES_PER_SPIN[dom] * w.N}
-    step_bytes = sum(BYTES_PER_SPIN.values())
-    if args.calibrate_copy:
-        src = torch.empty_like(S).copy_(S)
-        dst = torch.empty_like(S)
-        for _ in range(4):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] copy calibration: 4 copies of {src.numel() * 8} bytes")
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] timing the FP64 CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(w, args.cpu_seconds)
-        log(f"[bench] cpu oracle: {cpu['value']:.3e} spin-steps/s on {cpu['cores']} threads")
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "spin-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": gpu_ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 field + f64 state" if w.field_prec == "fp32" else "f64",
-        "data": "synthetic (seeded FM + tilt start, Philox noise)",
-        "config": {"workload": w.name, "lattice": "bcc (2 sublattices)" if w.n_sub == 2 else "sc",
-                   "cells": list(w.L), "spins": w.N, "shells": w.n_shells, "T_K": w.T_K,
-                   "alpha": w.alpha, "dt_fs": w.dt_fs, "field_prec": w.field_prec,
-                   "parallelism": "single GPU", "stencil_engine": info.stencil_engine,
-                   "zchunk": info.zchunk, "heun_field": info.heun_field},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "kernels": kernels,
-        "step_effective_GBps": step_bytes * w.N * args.steps / t / 1e9,
-        "hbm_frac_step": step_bytes * w.N * args.steps / t / 1e9 / HBM_PEAK_GBS,
-        "device": torch.cuda.get_device_name(0),
-    }
-    print(json.dumps(out), flush=True)
+    if args.workload == "sc_frustrated_gneb":
+        gneb_workload(args)
+    elif args.workload == "sc256_chiral_dipolar_field":
+        field_workload(args, WORKLOADS[args.workload]())
+    else:
+        heun_workload(args, WORKLOADS[args.workload]())
 
 
 if __name__ == "__main__":

@@ -112,13 +112,17 @@ typedef struct {
  * engine (bond tables that match a built-in shell shape: simple cubic shells
  * 1, 1-3, 1-4; bcc shells 1-5).  zchunk: z planes per block of the z-march
  * engine (0 = default 8).  heun_field (z-march engine; the gather engine
- * always recomputes): 0 auto (3), 1 the
+ * always recomputes): 0 auto (3, or the autotuner's choice), 1 the
  * corrector recomputes the field of S^n, 2 the predictor stores the FP32
  * bilinear field of S^n for the corrector (FP32 field_prec only; results
  * identical to 1), 3 the predictor stores the stage P = S^n + dt/2 f(S^n)
  * and the step's noise (FP64, 48 bytes per spin of library memory), so the
  * corrector evaluates f(S~) only (results equal to 1 up to the rounding of
- * the regrouped sum S^n + dt/2 f(S^n) + dt/2 f(S~)). */
+ * the regrouped sum S^n + dt/2 f(S^n) + dt/2 f(S~)), 4 as 3 with the noise
+ * drawn by an elementwise pre-pass and read by both stages (same results
+ * as 3), 5 split: each stage is a stencil pass that stores the FP32
+ * bilinear field followed by an elementwise FP64 stage kernel (FP32
+ * field_prec only; same results as 3). */
 typedef struct {
     int32_t field_prec;        /* spx_precision */
     int32_t backend;
@@ -206,7 +210,7 @@ typedef struct {
     int32_t stencil_engine;    /* 1 gather, 2 z-march */
     int32_t shape;             /* z-march shell shape id, -1 if none */
     int32_t zchunk;
-    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field, 3 stored stage and noise */
+    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field, 3 stored stage and noise, 4 as 3 + noise pre-pass, 5 split */
     int32_t tuned;             /* 1 if the autotuner chose zchunk / heun_field */
     double tuned_step_us;      /* its timing of one Heun step (microseconds) */
     int32_t heun_graph;        /* 1 once a captured Heun graph exists (replayed for runs of >= 4 steps) */
@@ -311,8 +315,9 @@ spx_status spx_mfma_probe(int32_t prec, const float *A, const float *B, float *D
 
 /* Kernel timing instrumentation (Methods, performance measurements: device
  * time of the hot kernels).  With enable = 1 every launch of the Heun
- * predictor (kind 0), Heun corrector (kind 1) and field kernel (kind 2) on
- * this handle is bracketed by a pair of hipEvents on the launch stream.
+ * predictor (kind 0), Heun corrector (kind 1), field kernel (kind 2) and
+ * noise pre-pass (kind 3, Heun mode 4) on this handle is bracketed by a pair
+ * of hipEvents on the launch stream.
  * spx_get_kernel_times synchronises on the recorded events and returns the
  * number of launches and their summed duration in ms since the last query
  * (then resets that kind).  enable = 0 stops recording. */

@@ -191,7 +191,7 @@ struct spx_ham {
     double tune_us = 0.0;
     // kernel timing: recorded (start, stop) event pairs per kind, and a pool
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[3];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[4];
     std::vector<hipEvent_t> pool;
 };
 
@@ -340,9 +340,9 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     const int hfield_req = opts ? opts->heun_field : 0;
     if (engine_req < 0 || engine_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown stencil_engine");
     if (zchunk_req < 0 || zchunk_req > 4096) return fail(SPX_ERR_INVALID_ARG, "zchunk out of range");
-    if (hfield_req < 0 || hfield_req > 3) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
-    if (hfield_req == 2 && prec != SPX_FP32)
-        return fail(SPX_ERR_INVALID_ARG, "a stored Heun field needs field_prec SPX_FP32");
+    if (hfield_req < 0 || hfield_req > 5) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
+    if ((hfield_req == 2 || hfield_req == 5) && prec != SPX_FP32)
+        return fail(SPX_ERR_INVALID_ARG, "a stored FP32 Heun field needs field_prec SPX_FP32");
     if (model->n_shells < 0 || model->n_bonds < 0 || model->n_aniso < 0)
         return fail(SPX_ERR_INVALID_ARG, "negative counts in model descriptor");
     if (model->n_shells > 0 && !model->J_shell) return fail(SPX_ERR_INVALID_ARG, "J_shell is NULL");
@@ -604,12 +604,46 @@ static spx_status enqueue_heun_step(spx_ham *h, const HeunConst &hc, uint64_t st
         bd0 = h->d_bdip0;
     }
     hipError_t e;
+    if (h->engine == 2 && h->heun_field == 4 && hc.noise) {
+        KernelTimer kt(h, 3, st);
+        e = zmarch_noise(hc, step, h->grid.N, h->d_eta, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: noise");
+    }
+    if (h->engine == 2 && h->heun_field == 5) {
+        // split mode: stencil pass for the FP32 bilinear field, then the
+        // elementwise FP64 stage
+        {
+            KernelTimer kt(h, 0, st);
+            e = zmarch_bil(h->zp, h->grid, cur, h->d_bstore, st);
+            if (e == hipSuccess)
+                e = heun_split_pre(h->grid, h->onsite, hc, step, cur, h->d_bstore, bd0, h->d_St, h->d_P, h->d_eta, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: predictor");
+        if (h->dip) {
+            spx_status s = dipolar_field(h, h->d_St, h->d_bdip1, st);
+            if (s != SPX_OK) return s;
+            bd1 = h->d_bdip1;
+        }
+        {
+            KernelTimer kt(h, 1, st);
+            e = zmarch_bil(h->zp, h->grid, h->d_St, h->d_bstore, st);
+            if (e == hipSuccess)
+                e = heun_split_post(h->grid, h->onsite, hc, h->d_St, h->d_bstore, bd1, h->d_P, h->d_eta, nxt, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: corrector");
+        return SPX_OK;
+    }
     {
         KernelTimer kt(h, 0, st);
         if (h->engine == 2)
+        {
+            const int hf = h->heun_field;
+            const bool staged = hf >= 3;
             e = zmarch_predict(h->zp, h->grid, h->onsite, hc, step, cur, bd0, h->d_St,
-                               h->heun_field == 2 ? h->d_bstore : nullptr, h->heun_field == 3 ? h->d_P : nullptr,
-                               (h->heun_field == 3 && hc.noise) ? h->d_eta : nullptr, st);
+                               hf == 2 ? h->d_bstore : nullptr, staged ? h->d_P : nullptr,
+                               (hf == 3 && hc.noise) ? h->d_eta : nullptr, (hf == 4 && hc.noise) ? h->d_eta : nullptr,
+                               st);
+        }
         else
             e = launch_heun_predict(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, bd0, h->d_St, st);
     }
@@ -623,8 +657,8 @@ static spx_status enqueue_heun_step(spx_ham *h, const HeunConst &hc, uint64_t st
         KernelTimer kt(h, 1, st);
         if (h->engine == 2)
             e = zmarch_correct(h->zp, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
-                               h->heun_field == 2 ? h->d_bstore : nullptr, h->heun_field == 3 ? h->d_P : nullptr,
-                               (h->heun_field == 3 && hc.noise) ? h->d_eta : nullptr, nxt, st);
+                               h->heun_field == 2 ? h->d_bstore : nullptr, h->heun_field >= 3 ? h->d_P : nullptr,
+                               (h->heun_field >= 3 && hc.noise) ? h->d_eta : nullptr, nxt, st);
         else
             e = launch_heun_correct(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1, nxt,
                                     st);
@@ -646,21 +680,21 @@ __global__ void k_fill_up(double *S, int64_t N) {
 static spx_status heun_buffers(spx_ham *h, int hf) {
     const size_t n3 = (size_t)3 * h->grid.N;
     spx_status s = SPX_OK;
-    if (hf == 2 && !h->d_bstore) s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field");
-    if (s == SPX_OK && hf == 3 && !h->d_P) s = dev_alloc(h, &h->d_P, n3, "stored Heun stage");
-    if (s == SPX_OK && hf == 3 && !h->d_eta) s = dev_alloc(h, &h->d_eta, n3, "stored Heun noise");
+    if ((hf == 2 || hf == 5) && !h->d_bstore) s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field");
+    if (s == SPX_OK && hf >= 3 && !h->d_P) s = dev_alloc(h, &h->d_P, n3, "stored Heun stage");
+    if (s == SPX_OK && hf >= 3 && !h->d_eta) s = dev_alloc(h, &h->d_eta, n3, "stored Heun noise");
     return s;
 }
 
 // Frees the stores that the selected mode does not use.
 static void heun_buffers_trim(spx_ham *h) {
     const int64_t n3 = 3 * h->grid.N;
-    if (h->heun_field != 2 && h->d_bstore) {
+    if (h->heun_field != 2 && h->heun_field != 5 && h->d_bstore) {
         (void)hipFree(h->d_bstore);
         h->d_bstore = nullptr;
         h->ws_bytes -= (int64_t)sizeof(float) * n3;
     }
-    if (h->heun_field != 3) {
+    if (h->heun_field < 3) {
         for (double **p : {&h->d_P, &h->d_eta})
             if (*p) {
                 (void)hipFree(*p);
@@ -689,11 +723,11 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
             int cz = 0, chf = 0;
             double cus = 0.0;
             while (std::fscanf(f, "%159s %d %d %lf", k2, &z, &hf, &us) == 4)
-                if (std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && (hf == 1 || hf == 2)) {
+                if (std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && hf >= 1 && hf <= 5) {
                     cz = z; chf = hf; cus = us; hit = true;   // the last matching line wins
                 }
             std::fclose(f);
-            if (hit && !(chf == 2 && h->field_prec != SPX_FP32)) {
+            if (hit && !((chf == 2 || chf == 5) && h->field_prec != SPX_FP32)) {
                 if (tune_z) h->zp.zch = cz;
                 if (tune_field) h->heun_field = chf;
                 h->tune_us = cus;
@@ -713,8 +747,8 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
     }
     std::vector<int> hfs = {h->heun_field};
     if (tune_field) {
-        hfs = {1, 3};
-        if (h->field_prec == SPX_FP32) hfs = {1, 2, 3};
+        hfs = {1, 3, 4};
+        if (h->field_prec == SPX_FP32) hfs = {1, 2, 3, 4, 5};
     }
     for (int hf : hfs) {
         spx_status s = heun_buffers(h, hf);
@@ -928,7 +962,7 @@ spx_status spx_set_kernel_timing(spx_ham *h, int32_t enable) {
 
 spx_status spx_get_kernel_times(spx_ham *h, int32_t kind, int64_t *count, double *total_ms) {
     if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
-    if (kind < 0 || kind > 2 || !count || !total_ms) return fail(SPX_ERR_INVALID_ARG, "bad kind or output");
+    if (kind < 0 || kind > 3 || !count || !total_ms) return fail(SPX_ERR_INVALID_ARG, "bad kind or output");
     double tot = 0.0;
     int64_t n = 0;
     for (auto &pr : h->timed[kind]) {

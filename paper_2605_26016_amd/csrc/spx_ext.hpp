@@ -61,7 +61,14 @@ hipError_t zmarch_field(const ZPlan &zp, const Grid &g, const Onsite &os, const 
                         void *b, hipStream_t st);
 hipError_t zmarch_predict(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
                           const double *S, const float *bdip, double *St, float *bstore, double *pstore,
-                          double *estore, hipStream_t st);
+                          double *estore, const double *eload, hipStream_t st);
+hipError_t zmarch_noise(const HeunConst &hc, uint64_t step, int64_t N, double *eta, hipStream_t st);
+// split Heun mode: FP32 bilinear field pass + elementwise FP64 stages
+hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bil, hipStream_t st);
+hipError_t heun_split_pre(const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step, const double *S,
+                          const float *bil, const float *bdip, double *St, double *P, double *eta, hipStream_t st);
+hipError_t heun_split_post(const Grid &g, const Onsite &os, const HeunConst &hc, const double *St, const float *bil,
+                           const float *bdip, const double *P, const double *eta, double *out, hipStream_t st);
 hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
                           const double *S, const double *St, const float *bdipS, const float *bdipT,
                           const float *bload, const double *pload, const double *eload, double *out,

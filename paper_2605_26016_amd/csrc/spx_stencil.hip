@@ -1,12 +1,13 @@
 // spx_stencil.hip -- z-marching LDS stencil engine for structured shell
 // patterns on gfx950: effective field, Heun predictor and Heun corrector.
 //
-// A 256-thread block owns a 64 x 8 column tile (64 lanes along x, 4 thread
-// rows of 2 y-sites each) and a chunk of z planes.  It streams input planes
-// z' upward: each plane (all sublattices, 3 components, with the x/y halo of
-// the shape) is loaded once from global memory -- periodic wrap or zero fill
-// at open faces done here, so the compute loop has no boundary logic -- into a
-// double-buffered LDS slot, converted to the compute type (float in mixed
+// A block (512 threads by default) owns a 64 x 8 column tile (64 lanes along
+// x, one wavefront per y row) and a chunk of z planes.  It streams input
+// planes z' upward: each plane (all sublattices, 3 components, with the x/y
+// halo of the shape) is read once from global memory -- periodic wrap or zero
+// fill at open faces done here, so the compute loop has no boundary logic --
+// into registers while the previous plane is being computed, then written to
+// a double-buffered LDS slot, converted to the compute type (float in mixed
 // mode).  Every bond (compile-time offset, runtime coupling) then pushes
 // J S_b(x+dx, y+dy, z') into a register accumulator of output plane z' - dz;
 // the accumulators of the D = dzhi - dzlo + 1 pending output planes form a
@@ -25,9 +26,25 @@ namespace spx {
 
 namespace {
 
+// Tile shape and plane staging (compile-time; the defaults were the fastest
+// of the measured alternatives on the bcc 5-shell and sc NN workloads).
+#ifndef SPX_ZM_TYT
+#define SPX_ZM_TYT 8
+#endif
+#ifndef SPX_ZM_YB
+#define SPX_ZM_YB 1
+#endif
+#ifndef SPX_ZM_PREFETCH
+#define SPX_ZM_PREFETCH 1
+#endif
 constexpr int kTX = 64;   // tile width in x (one wavefront per thread row)
-constexpr int kTYT = 4;   // thread rows per block
-constexpr int kYB = 2;    // y sites per thread
+constexpr int kTYT = SPX_ZM_TYT;   // thread rows per block
+constexpr int kYB = SPX_ZM_YB;     // y sites per thread
+// 1: the next input plane is fetched into registers before the current
+// plane's compute and written to LDS after it (global latency overlapped);
+// single-input modes only (two staged inputs would double those registers)
+constexpr bool kPrefetch = SPX_ZM_PREFETCH != 0;
+
 constexpr int kTYE = kTYT * kYB;  // tile height in y
 constexpr int kThreads = kTX * kTYT;
 
@@ -35,7 +52,9 @@ constexpr int kThreads = kTX * kTYT;
 // predictor's FP32 bilinear field of S^n; ZM_CORRECT_P: read the predictor's
 // partial update P = S^n + dt/2 f(S^n) and its noise eta (FP64), so that the
 // corrector evaluates only f(S~).
-enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4 };
+// ZM_BIL: store only the FP32 bilinear field (the split Heun mode's stencil
+// pass; the Heun stages then run as elementwise kernels).
+enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4, ZM_BIL = 5 };
 
 template <typename T, int NW>
 struct ZWeights {
@@ -56,7 +75,7 @@ struct ZArgs {
     const float *bload;  // stored-field corrector: that field
     double *pstore;    // predictor: P = S^n + dt/2 f(S^n) (may be NULL)
     double *estore;    // predictor: eta of this step (may be NULL; T > 0 only)
-    const double *pload, *eload;  // ZM_CORRECT_P: P and eta
+    const double *pload, *eload;  // ZM_CORRECT_P: P and eta; predictor: eta if not NULL
     const float *bdip0, *bdip1;  // dipolar fields of S0 / S1 (may be NULL)
     uint64_t step;
 };
@@ -121,7 +140,47 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
                     for (int k = 0; k < NIN; ++k) acc[s][yb][a][c][k] = T(0);
 
-    // global -> LDS copy of input plane q (z = zs + DZLO + q) into buffer `buf`
+    // plane q (z = zs + DZLO + q) in two halves: fetch into registers, then
+    // commit to LDS buffer `buf`
+    constexpr int NLD = (NSUB * PLANE + kThreads - 1) / kThreads;
+    double pre[NLD][NIN][3];
+    auto fetch_plane = [&](int q) __attribute__((always_inline)) {
+        bool zok = true;
+        const int gz = zwrap(zs + DZLO + q, g.Lz, g.per[2], zok);
+#pragma unroll
+        for (int t = 0; t < NLD; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
+            if (idx < NSUB * PLANE) {
+                const int sub = idx / PLANE;
+                const int r = idx - sub * PLANE;
+                const int cy = r / PW;
+                const int cx = r - cy * PW;
+                bool ok = zok;
+                const int gx = zwrap(x0 - RX + cx, g.Lx, g.per[0], ok);
+                const int gy = zwrap(y0 - RY + cy, g.Ly, g.per[1], ok);
+                const int64_t j = (int64_t)sub * g.M + gx + (int64_t)g.Lx * (gy + (int64_t)g.Ly * gz);
+#pragma unroll
+                for (int k = 0; k < NIN; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) pre[t][k][c] = ok ? src[k][c * N + j] : 0.0;
+            }
+        }
+    };
+    auto commit_plane = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < NLD; ++t) {
+            const int idx = threadIdx.x + t * kThreads;
+            if (idx < NSUB * PLANE) {
+                const int sub = idx / PLANE;
+                const int r = idx - sub * PLANE;
+#pragma unroll
+                for (int k = 0; k < NIN; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) lds[buf][k][sub][c][r] = (T)pre[t][k][c];
+            }
+        }
+    };
+    // global -> LDS copy of input plane q into buffer `buf` in one pass
     auto load_plane = [&](int q, int buf) {
         bool zok = true;
         const int gz = zwrap(zs + DZLO + q, g.Lz, g.per[2], zok);
@@ -147,6 +206,11 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     auto finish_site = [&](auto ac, int x, int y, int z, const T (&v)[NIN][3]) __attribute__((always_inline)) {
         constexpr int a = decltype(ac)::value;
         const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
+        if constexpr (MODE == ZM_BIL) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g.bstore[c * N + i] = (float)v[0][c];
+            return;
+        }
         if constexpr (MODE == ZM_CORRECT_P) {
             const double st[3] = {g.S1[i], g.S1[N + i], g.S1[2 * N + i]};
             double bt[3];
@@ -194,7 +258,13 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             }
             if (hc.noise) {
                 double eta[3];
-                thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)i, eta);
+                if (g.eload) {
+                    eta[0] = g.eload[i];
+                    eta[1] = g.eload[N + i];
+                    eta[2] = g.eload[2 * N + i];
+                } else {
+                    thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)i, eta);
+                }
                 const double sg = hc.sigma[a];
                 B[0] += sg * eta[0];
                 B[1] += sg * eta[1];
@@ -265,11 +335,21 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 
     // acc[k] holds output plane o = q - (D-1) + k after input plane q has been
     // pushed; input plane q feeds slot k = dzhi - dz of every bond.
-    load_plane(0, 0);
+    if constexpr (kPrefetch && NIN == 1) {
+        fetch_plane(0);
+        commit_plane(0);
+    } else {
+        load_plane(0, 0);
+    }
     __syncthreads();
+#pragma unroll 1
     for (int q = 0; q < nq; ++q) {
         const int buf = q & 1;
-        if (q + 1 < nq) load_plane(q + 1, buf ^ 1);
+        if constexpr (kPrefetch && NIN == 1) {
+            if (q + 1 < nq) fetch_plane(q + 1);
+        } else {
+            if (q + 1 < nq) load_plane(q + 1, buf ^ 1);
+        }
         static_for<NB>([&](auto kc) __attribute__((always_inline)) {
             constexpr int kb = decltype(kc)::value;
             constexpr ZBond bd = ShapeC<KIND>::t.bonds[kb];
@@ -345,8 +425,101 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int in = 0; in < NIN; ++in) acc[D - 1][yb][a][c][in] = T(0);
+        if constexpr (kPrefetch && NIN == 1) {
+            if (q + 1 < nq) commit_plane(buf ^ 1);
+        }
         __syncthreads();
     }
+}
+
+// Thermal noise of one Heun step for every site (Heun mode 4: generated by
+// this elementwise pass, read by both stages).
+__global__ __launch_bounds__(256) void k_noise_pre(HeunConst hc, uint64_t step, int64_t N, double *__restrict__ eta) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    double e[3];
+    thermal_eta(hc.seed, noise_step(hc, step), hc.tag, (uint64_t)i, e);
+    eta[i] = e[0];
+    eta[N + i] = e[1];
+    eta[2 * N + i] = e[2];
+}
+
+// Split Heun stages (elementwise over the sites of sublattice blockIdx.y):
+// the bilinear field comes from the ZM_BIL pass, on-site terms and the
+// integration are FP64.
+// Predictor: S~ = N[S + dt f(S)], P = S + dt/2 f(S), eta stored for the corrector.
+__global__ __launch_bounds__(256) void k_heun_pre(int64_t M, int64_t N, Onsite os, HeunConst hc, uint64_t step,
+                                                  const double *__restrict__ S, const float *__restrict__ bil,
+                                                  const float *__restrict__ bdip, double *__restrict__ St,
+                                                  double *__restrict__ P, double *__restrict__ eta_out) {
+    const int a = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= M) return;
+    const int64_t i = (int64_t)a * M + t;
+    const double s[3] = {S[i], S[N + i], S[2 * N + i]};
+    double ba[3];
+    aniso_field(os, a, s, ba);
+    double B[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double v = (double)bil[c * N + i] + ba[c] + os.bz[a][c];
+        if (bdip) v += (double)bdip[c * N + i];
+        B[c] = v * hc.inv_mumuB[a];
+    }
+    if (hc.noise) {
+        double eta[3];
+        thermal_eta(hc.seed, noise_step(hc, step), hc.tag, (uint64_t)i, eta);
+        const double sg = hc.sigma[a];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            B[c] += sg * eta[c];
+            eta_out[c * N + i] = eta[c];
+        }
+    }
+    double f[3];
+    llg_rhs(s, B, hc.pre, hc.alpha, f);
+    const double hdt = 0.5 * hc.dt;
+    double p[3] = {s[0] + hc.dt * f[0], s[1] + hc.dt * f[1], s[2] + hc.dt * f[2]};
+    normalise3(p);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        P[c * N + i] = s[c] + hdt * f[c];
+        St[c * N + i] = p[c];
+    }
+}
+
+// Corrector: S' = N[P + dt/2 f(S~)] with the predictor's eta.
+__global__ __launch_bounds__(256) void k_heun_post(int64_t M, int64_t N, Onsite os, HeunConst hc,
+                                                   const double *__restrict__ St, const float *__restrict__ bil,
+                                                   const float *__restrict__ bdip, const double *__restrict__ P,
+                                                   const double *__restrict__ eta, double *__restrict__ out) {
+    const int a = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= M) return;
+    const int64_t i = (int64_t)a * M + t;
+    const double s[3] = {St[i], St[N + i], St[2 * N + i]};
+    double bt[3];
+    aniso_field(os, a, s, bt);
+    double B[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double v = (double)bil[c * N + i] + bt[c] + os.bz[a][c];
+        if (bdip) v += (double)bdip[c * N + i];
+        B[c] = v * hc.inv_mumuB[a];
+    }
+    if (hc.noise) {
+        const double sg = hc.sigma[a];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) B[c] += sg * eta[c * N + i];
+    }
+    double f[3];
+    llg_rhs(s, B, hc.pre, hc.alpha, f);
+    const double hdt = 0.5 * hc.dt;
+    double p[3] = {P[i] + hdt * f[0], P[N + i] + hdt * f[1], P[2 * N + i] + hdt * f[2]};
+    normalise3(p);
+    out[i] = p[0];
+    out[N + i] = p[1];
+    out[2 * N + i] = p[2];
 }
 
 template <int KIND, typename T, bool ISO, int MODE>
@@ -458,10 +631,41 @@ hipError_t zmarch_field(const ZPlan &zp, const Grid &g, const Onsite &os, const 
     return launch_any<ZM_FIELD>(zp, a, os, hc, st);
 }
 
+hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bil, hipStream_t st) {
+    if (zp.prec != 1) return hipErrorInvalidValue;
+    ZArgs a = make_args(zp, g);
+    a.S0 = S;
+    a.bstore = bil;
+    Onsite os{};
+    HeunConst hc{};
+    return launch_any<ZM_BIL>(zp, a, os, hc, st);
+}
+
+hipError_t heun_split_pre(const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step, const double *S,
+                          const float *bil, const float *bdip, double *St, double *P, double *eta, hipStream_t st) {
+    dim3 grid((unsigned)((g.M + 255) / 256), (unsigned)g.n_sub);
+    k_heun_pre<<<grid, 256, 0, st>>>(g.M, g.N, os, hc, step, S, bil, bdip, St, P, eta);
+    return hipGetLastError();
+}
+
+hipError_t heun_split_post(const Grid &g, const Onsite &os, const HeunConst &hc, const double *St, const float *bil,
+                           const float *bdip, const double *P, const double *eta, double *out, hipStream_t st) {
+    dim3 grid((unsigned)((g.M + 255) / 256), (unsigned)g.n_sub);
+    k_heun_post<<<grid, 256, 0, st>>>(g.M, g.N, os, hc, St, bil, bdip, P, eta, out);
+    return hipGetLastError();
+}
+
+hipError_t zmarch_noise(const HeunConst &hc, uint64_t step, int64_t N, double *eta, hipStream_t st) {
+    if (N <= 0) return hipSuccess;
+    k_noise_pre<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(hc, step, N, eta);
+    return hipGetLastError();
+}
+
 hipError_t zmarch_predict(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
                           const double *S, const float *bdip, double *St, float *bstore, double *pstore,
-                          double *estore, hipStream_t st) {
+                          double *estore, const double *eload, hipStream_t st) {
     ZArgs a = make_args(zp, g);
+    a.eload = eload;
     a.S0 = S;
     a.out = St;
     a.bdip0 = bdip;

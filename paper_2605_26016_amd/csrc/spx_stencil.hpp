@@ -53,7 +53,21 @@ constexpr bool shape_has(int kind, int r2) {
 
 constexpr int shape_nsub(int kind) { return kind == SHAPE_BCC_5SH ? 2 : 1; }
 
-// Bonds ordered by (a, dz, b, dy, dx).
+// Bonds are ordered by source position (b, dy, dx), then (a, dz), so that the
+// bonds reading one staged neighbour value are adjacent.
+constexpr void shape_add(ShapeTable &t, int kind, int a, int b, int dx, int dy, int dz) {
+    if (a >= t.nsub || b >= t.nsub) return;
+    const int r2 = shape_r2(kind, a, b, dx, dy, dz);
+    if (r2 == 0 || !shape_has(kind, r2)) return;
+    t.bonds[t.nb] = ZBond{a, b, dx, dy, dz};
+    t.nb++;
+    const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+    if (ax > t.rx) t.rx = ax;
+    if (ay > t.ry) t.ry = ay;
+    if (dz < t.dzlo) t.dzlo = dz;
+    if (dz > t.dzhi) t.dzhi = dz;
+}
+
 constexpr ShapeTable make_shape(int kind) {
     ShapeTable t{};
     t.nsub = shape_nsub(kind);
@@ -61,21 +75,11 @@ constexpr ShapeTable make_shape(int kind) {
     t.rx = t.ry = 0;
     t.dzlo = 0;
     t.dzhi = 0;
-    for (int a = 0; a < t.nsub; ++a)
-        for (int dz = -2; dz <= 2; ++dz)
-            for (int b = 0; b < t.nsub; ++b)
-                for (int dy = -2; dy <= 2; ++dy)
-                    for (int dx = -2; dx <= 2; ++dx) {
-                        const int r2 = shape_r2(kind, a, b, dx, dy, dz);
-                        if (r2 == 0 || !shape_has(kind, r2)) continue;
-                        t.bonds[t.nb] = ZBond{a, b, dx, dy, dz};
-                        t.nb++;
-                        const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
-                        if (ax > t.rx) t.rx = ax;
-                        if (ay > t.ry) t.ry = ay;
-                        if (dz < t.dzlo) t.dzlo = dz;
-                        if (dz > t.dzhi) t.dzhi = dz;
-                    }
+    for (int b = 0; b < 2; ++b)
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx)
+                for (int a = 0; a < 2; ++a)
+                    for (int dz = -2; dz <= 2; ++dz) shape_add(t, kind, a, b, dx, dy, dz);
     return t;
 }
 

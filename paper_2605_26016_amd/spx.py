@@ -325,7 +325,7 @@ def get_bonds(h):
     return ab[:2 * n].reshape(n, 2), dl[:3 * n].reshape(n, 3), J[:9 * n].reshape(n, 3, 3)
 
 
-KERNEL_KINDS = {"heun_predict": 0, "heun_correct": 1, "field": 2}
+KERNEL_KINDS = {"heun_predict": 0, "heun_correct": 1, "field": 2, "noise": 3}
 
 
 def set_kernel_timing(h, enable=True):

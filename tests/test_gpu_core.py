@@ -172,10 +172,12 @@ HEUN_CASES = [
 
 
 HEUN_SETUPS = [dict(stencil_engine=1), dict(stencil_engine=0, heun_field=1),
-               dict(stencil_engine=0, heun_field=3), dict(stencil_engine=0, heun_field=0, zchunk=3)]
+               dict(stencil_engine=0, heun_field=3), dict(stencil_engine=0, heun_field=4),
+               dict(stencil_engine=0, heun_field=0, zchunk=3)]
 
 
-@pytest.mark.parametrize("setup", HEUN_SETUPS, ids=["gather", "zmarch_recompute", "zmarch_stage", "auto_z3"])
+@pytest.mark.parametrize("setup", HEUN_SETUPS, ids=["gather", "zmarch_recompute", "zmarch_stage",
+                                                     "zmarch_noisepass", "auto_z3"])
 @pytest.mark.parametrize("name,w,prec,extra,tol", HEUN_CASES, ids=[c[0] for c in HEUN_CASES])
 def test_heun_parity(name, w, prec, extra, tol, setup):
     S = w.initial_state() if w.init != "random" else random_sphere(w.N, 51)
@@ -200,11 +202,19 @@ def test_heun_stored_field_equals_recompute():
     # the stored stage regroups S + dt/2 f0 + dt/2 f1: equal up to rounding
     c = gpu_heun(w, S, "fp32", setup=dict(heun_field=3), **kw)
     assert np.max(np.abs(a - c)) <= 1e-14
+    # the noise pre-pass draws the same numbers
+    d = gpu_heun(w, S, "fp32", setup=dict(heun_field=4), **kw)
+    assert np.array_equal(c, d)
+    # the split mode (stencil pass + elementwise stages) computes the same
+    e = gpu_heun(w, S, "fp32", setup=dict(heun_field=5), **kw)
+    assert np.array_equal(c, e)
     # deterministic case (no noise store)
     kw["temperature_K"] = 0.0
     a = gpu_heun(w, S, "fp32", setup=dict(heun_field=1), **kw)
     c = gpu_heun(w, S, "fp32", setup=dict(heun_field=3), **kw)
     assert np.max(np.abs(a - c)) <= 1e-14
+    e = gpu_heun(w, S, "fp32", setup=dict(heun_field=5), **kw)
+    assert np.array_equal(c, e)
 
 
 def test_heun_resume_and_determinism():
@@ -328,13 +338,16 @@ def test_autotuner_picks_candidate_and_caches(tmp_path):
     cache = str(tmp_path / "tune.txt")
     h = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache)
     info = spx.get_info(h)
-    assert info.tuned == 1 and info.zchunk in (4, 8, 16) and info.heun_field in (1, 2, 3)
+    assert info.tuned == 1 and info.zchunk in (4, 8, 16) and info.heun_field in (1, 2, 3, 4, 5)
     assert info.tuned_step_us > 0
     lines = open(cache).read().split("\n")
     assert any(l.startswith("shape3_prec1_sub2_16x16x16") for l in lines)
     h2 = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache)
     i2 = spx.get_info(h2)
     assert (i2.zchunk, i2.heun_field) == (info.zchunk, info.heun_field)
+    # the second setup read the cache instead of tuning again
+    assert sum(l.startswith("shape3_prec1_sub2_16x16x16") for l in open(cache).read().split("\n")) == 1
+    assert i2.tuned == 1 and i2.tuned_step_us == pytest.approx(info.tuned_step_us, abs=1e-3)
     # the z chunk does not change results (same Heun mode, other launch shape)
     S0 = w.initial_state()
     h3 = gpu_hamiltonian(w, field_prec="fp32", zchunk=3, heun_field=info.heun_field)
