@@ -152,6 +152,7 @@ def gneb_workload(args):
     del g, hams, imgs
     log(f"[bench] batched GNEB: {rate:.3e} spin-image-iterations/s")
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_gneb_baseline(args.cpu_seconds)
+    out["hbm_copy_GBps"] = copy_bandwidth()
     if args.no_learned:
         print(json.dumps(out), flush=True)
         return
@@ -358,6 +359,12 @@ def heun_workload(args, w):
     kname = {("heun_predict", 2): "k_zmarch (predictor instantiation)",
              ("heun_correct", 2): "k_zmarch (corrector instantiation)",
              ("heun_predict", 1): "k_heun_predict", ("heun_correct", 1): "k_heun_correct"}
+    if info.stencil_engine == 2 and info.heun_field >= 5:
+        # split predictor (modes 5, 6): one sweep = the bilinear-field stencil
+        # pass + the elementwise stage kernel, timed together
+        kname[("heun_predict", 2)] = "k_zmarch<ZM_BIL> + k_heun_pre (predictor sweep)"
+        if info.heun_field == 5:
+            kname[("heun_correct", 2)] = "k_zmarch<ZM_BIL> + k_heun_post (corrector sweep)"
     traffic = measured_traffic(dom)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -397,6 +404,7 @@ def heun_workload(args, w):
         "hbm_frac_step": step_bytes * w.N * args.steps / t / 1e9 / HBM_PEAK_GBS,
         "device": torch.cuda.get_device_name(0),
     }
+    out["hbm_copy_GBps"] = copy_bandwidth()
     if args.calibrate_copy:
         src = torch.empty_like(S).copy_(S)
         dst = torch.empty_like(S)
@@ -406,6 +414,26 @@ def heun_workload(args, w):
         log(f"[bench] copy calibration: 4 copies of {src.numel() * 8} bytes")
         del src, dst
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(nbytes=4 << 30, reps=5):
+    """Attainable HBM bandwidth: a plain device-to-device copy of 4 GiB (far
+    beyond the on-die caches), read + write bytes over the event-timed copy."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
 
 
 def k7_couplings(J=1.0, D=0.3, mu=2.0, a=0.4):
@@ -507,7 +535,7 @@ def field_workload(args, w):
                             "GBps_algorithmic": FIELD_BYTES * w.N / ms_st / 1e6,
                             "hbm_frac": FIELD_BYTES * w.N / ms_st / 1e6 / HBM_PEAK_GBS},
            "stencil_plus_dipolar_fft_ms": ms_dip, "dense_7cubed": dense, "cpu_baseline": cpu,
-           "device": torch.cuda.get_device_name(0)}
+           "hbm_copy_GBps": copy_bandwidth(), "device": torch.cuda.get_device_name(0)}
     print(json.dumps(out), flush=True)
 
 

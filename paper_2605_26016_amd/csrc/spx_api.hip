@@ -340,8 +340,8 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     const int hfield_req = opts ? opts->heun_field : 0;
     if (engine_req < 0 || engine_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown stencil_engine");
     if (zchunk_req < 0 || zchunk_req > 4096) return fail(SPX_ERR_INVALID_ARG, "zchunk out of range");
-    if (hfield_req < 0 || hfield_req > 5) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
-    if ((hfield_req == 2 || hfield_req == 5) && prec != SPX_FP32)
+    if (hfield_req < 0 || hfield_req > 6) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
+    if ((hfield_req == 2 || hfield_req >= 5) && prec != SPX_FP32)
         return fail(SPX_ERR_INVALID_ARG, "a stored FP32 Heun field needs field_prec SPX_FP32");
     if (model->n_shells < 0 || model->n_bonds < 0 || model->n_aniso < 0)
         return fail(SPX_ERR_INVALID_ARG, "negative counts in model descriptor");
@@ -609,9 +609,9 @@ static spx_status enqueue_heun_step(spx_ham *h, const HeunConst &hc, uint64_t st
         e = zmarch_noise(hc, step, h->grid.N, h->d_eta, st);
         if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: noise");
     }
-    if (h->engine == 2 && h->heun_field == 5) {
-        // split mode: stencil pass for the FP32 bilinear field, then the
-        // elementwise FP64 stage
+    if (h->engine == 2 && h->heun_field >= 5) {
+        // split predictor: stencil pass for the FP32 bilinear field, then the
+        // elementwise FP64 stage; corrector split (mode 5) or fused (mode 6)
         {
             KernelTimer kt(h, 0, st);
             e = zmarch_bil(h->zp, h->grid, cur, h->d_bstore, st);
@@ -626,9 +626,14 @@ static spx_status enqueue_heun_step(spx_ham *h, const HeunConst &hc, uint64_t st
         }
         {
             KernelTimer kt(h, 1, st);
-            e = zmarch_bil(h->zp, h->grid, h->d_St, h->d_bstore, st);
-            if (e == hipSuccess)
-                e = heun_split_post(h->grid, h->onsite, hc, h->d_St, h->d_bstore, bd1, h->d_P, h->d_eta, nxt, st);
+            if (h->heun_field == 5) {
+                e = zmarch_bil(h->zp, h->grid, h->d_St, h->d_bstore, st);
+                if (e == hipSuccess)
+                    e = heun_split_post(h->grid, h->onsite, hc, h->d_St, h->d_bstore, bd1, h->d_P, h->d_eta, nxt, st);
+            } else {
+                e = zmarch_correct(h->zp, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1, nullptr, h->d_P,
+                                   hc.noise ? h->d_eta : nullptr, nxt, st);
+            }
         }
         if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: corrector");
         return SPX_OK;
@@ -680,7 +685,7 @@ __global__ void k_fill_up(double *S, int64_t N) {
 static spx_status heun_buffers(spx_ham *h, int hf) {
     const size_t n3 = (size_t)3 * h->grid.N;
     spx_status s = SPX_OK;
-    if ((hf == 2 || hf == 5) && !h->d_bstore) s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field");
+    if ((hf == 2 || hf >= 5) && !h->d_bstore) s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field");
     if (s == SPX_OK && hf >= 3 && !h->d_P) s = dev_alloc(h, &h->d_P, n3, "stored Heun stage");
     if (s == SPX_OK && hf >= 3 && !h->d_eta) s = dev_alloc(h, &h->d_eta, n3, "stored Heun noise");
     return s;
@@ -689,7 +694,7 @@ static spx_status heun_buffers(spx_ham *h, int hf) {
 // Frees the stores that the selected mode does not use.
 static void heun_buffers_trim(spx_ham *h) {
     const int64_t n3 = 3 * h->grid.N;
-    if (h->heun_field != 2 && h->heun_field != 5 && h->d_bstore) {
+    if (h->heun_field != 2 && h->heun_field < 5 && h->d_bstore) {
         (void)hipFree(h->d_bstore);
         h->d_bstore = nullptr;
         h->ws_bytes -= (int64_t)sizeof(float) * n3;
@@ -723,11 +728,11 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
             int cz = 0, chf = 0;
             double cus = 0.0;
             while (std::fscanf(f, "%159s %d %d %lf", k2, &z, &hf, &us) == 4)
-                if (std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && hf >= 1 && hf <= 5) {
+                if (std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && hf >= 1 && hf <= 6) {
                     cz = z; chf = hf; cus = us; hit = true;   // the last matching line wins
                 }
             std::fclose(f);
-            if (hit && !((chf == 2 || chf == 5) && h->field_prec != SPX_FP32)) {
+            if (hit && !((chf == 2 || chf >= 5) && h->field_prec != SPX_FP32)) {
                 if (tune_z) h->zp.zch = cz;
                 if (tune_field) h->heun_field = chf;
                 h->tune_us = cus;
@@ -748,7 +753,7 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
     std::vector<int> hfs = {h->heun_field};
     if (tune_field) {
         hfs = {1, 3, 4};
-        if (h->field_prec == SPX_FP32) hfs = {1, 2, 3, 4, 5};
+        if (h->field_prec == SPX_FP32) hfs = {1, 2, 3, 4, 5, 6};
     }
     for (int hf : hfs) {
         spx_status s = heun_buffers(h, hf);

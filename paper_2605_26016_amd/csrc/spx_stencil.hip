@@ -106,7 +106,7 @@ __device__ __forceinline__ int zwrap(int c, int L, int per, bool &ok) {
 
 template <int KIND, typename T, bool ISO, int MODE>
 __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunConst hc,
-                                                     ZWeights<T, (ISO ? 1 : 9) * make_shape(KIND).nb> W) {
+                                                     ZWeights<T, ISO ? make_shape(KIND).nshell : 9 * make_shape(KIND).nb> W) {
     constexpr int NSUB = ShapeC<KIND>::t.nsub, NB = ShapeC<KIND>::t.nb;
     constexpr int RX = ShapeC<KIND>::t.rx, RY = ShapeC<KIND>::t.ry;
     constexpr int DZLO = ShapeC<KIND>::t.dzlo, DZHI = ShapeC<KIND>::t.dzhi;
@@ -140,43 +140,61 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
                     for (int k = 0; k < NIN; ++k) acc[s][yb][a][c][k] = T(0);
 
+    // Staged elements of a plane: thread t handles elements idx = t + k
+    // kThreads (k < NLD) of the (sublattice, halo row, halo column) grid.
+    // Their x/y source offsets and wrap/zero decisions do not depend on the
+    // plane and are computed once here; per plane only z is added.
+    constexpr int NLD = (NSUB * PLANE + kThreads - 1) / kThreads;
+    int64_t xy_off[NLD];
+    int lds_off[NLD];
+    unsigned xy_ok = 0;  // bit t: element valid and inside the lattice in x/y
+#pragma unroll
+    for (int t = 0; t < NLD; ++t) {
+        const int idx = threadIdx.x + t * kThreads;
+        xy_off[t] = 0;
+        lds_off[t] = 0;
+        if (idx < NSUB * PLANE) {
+            const int sub = idx / PLANE;
+            const int r = idx - sub * PLANE;
+            const int cy = r / PW;
+            const int cx = r - cy * PW;
+            bool ok = true;
+            const int gx = zwrap(x0 - RX + cx, g.Lx, g.per[0], ok);
+            const int gy = zwrap(y0 - RY + cy, g.Ly, g.per[1], ok);
+            xy_off[t] = (int64_t)sub * g.M + gx + (int64_t)g.Lx * gy;
+            lds_off[t] = sub * 3 * PLANE + r;
+            if (ok) xy_ok |= 1u << t;
+        }
+    }
+    const int64_t plane_stride = (int64_t)g.Lx * g.Ly;
+    T *const lds_flat = &lds[0][0][0][0][0];
+    constexpr int BUF_STRIDE = NIN * NSUB * 3 * PLANE, IN_STRIDE = NSUB * 3 * PLANE;
     // plane q (z = zs + DZLO + q) in two halves: fetch into registers, then
     // commit to LDS buffer `buf`
-    constexpr int NLD = (NSUB * PLANE + kThreads - 1) / kThreads;
     double pre[NLD][NIN][3];
     auto fetch_plane = [&](int q) __attribute__((always_inline)) {
         bool zok = true;
         const int gz = zwrap(zs + DZLO + q, g.Lz, g.per[2], zok);
+        const int64_t zoff = plane_stride * gz;
 #pragma unroll
         for (int t = 0; t < NLD; ++t) {
-            const int idx = threadIdx.x + t * kThreads;
-            if (idx < NSUB * PLANE) {
-                const int sub = idx / PLANE;
-                const int r = idx - sub * PLANE;
-                const int cy = r / PW;
-                const int cx = r - cy * PW;
-                bool ok = zok;
-                const int gx = zwrap(x0 - RX + cx, g.Lx, g.per[0], ok);
-                const int gy = zwrap(y0 - RY + cy, g.Ly, g.per[1], ok);
-                const int64_t j = (int64_t)sub * g.M + gx + (int64_t)g.Lx * (gy + (int64_t)g.Ly * gz);
+            const bool ok = zok && ((xy_ok >> t) & 1u);
+            const int64_t j = xy_off[t] + zoff;
 #pragma unroll
-                for (int k = 0; k < NIN; ++k)
+            for (int k = 0; k < NIN; ++k)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) pre[t][k][c] = ok ? src[k][c * N + j] : 0.0;
-            }
+                for (int c = 0; c < 3; ++c) pre[t][k][c] = ok ? src[k][c * N + j] : 0.0;
         }
     };
     auto commit_plane = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < NLD; ++t) {
-            const int idx = threadIdx.x + t * kThreads;
-            if (idx < NSUB * PLANE) {
-                const int sub = idx / PLANE;
-                const int r = idx - sub * PLANE;
+            if (NLD * kThreads == NSUB * PLANE || threadIdx.x + t * kThreads < NSUB * PLANE) {
 #pragma unroll
                 for (int k = 0; k < NIN; ++k)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) lds[buf][k][sub][c][r] = (T)pre[t][k][c];
+                    for (int c = 0; c < 3; ++c)
+                        lds_flat[buf * BUF_STRIDE + k * IN_STRIDE + c * PLANE + lds_off[t]] = (T)pre[t][k][c];
             }
         }
     };
@@ -184,19 +202,19 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     auto load_plane = [&](int q, int buf) {
         bool zok = true;
         const int gz = zwrap(zs + DZLO + q, g.Lz, g.per[2], zok);
-        for (int idx = threadIdx.x; idx < NSUB * PLANE; idx += kThreads) {
-            const int sub = idx / PLANE;
-            const int r = idx - sub * PLANE;
-            const int cy = r / PW;
-            const int cx = r - cy * PW;
-            bool ok = zok;
-            const int gx = zwrap(x0 - RX + cx, g.Lx, g.per[0], ok);
-            const int gy = zwrap(y0 - RY + cy, g.Ly, g.per[1], ok);
-            const int64_t j = (int64_t)sub * g.M + gx + (int64_t)g.Lx * (gy + (int64_t)g.Ly * gz);
+        const int64_t zoff = plane_stride * gz;
 #pragma unroll
-            for (int k = 0; k < NIN; ++k)
+        for (int t = 0; t < NLD; ++t) {
+            if (NLD * kThreads == NSUB * PLANE || threadIdx.x + t * kThreads < NSUB * PLANE) {
+                const bool ok = zok && ((xy_ok >> t) & 1u);
+                const int64_t j = xy_off[t] + zoff;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) lds[buf][k][sub][c][r] = ok ? (T)src[k][c * N + j] : T(0);
+                for (int k = 0; k < NIN; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        lds_flat[buf * BUF_STRIDE + k * IN_STRIDE + c * PLANE + lds_off[t]] =
+                            ok ? (T)src[k][c * N + j] : T(0);
+            }
         }
     };
 
@@ -363,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                     const T s1 = lds[buf][in][bd.b][1][off];
                     const T s2 = lds[buf][in][bd.b][2][off];
                     if constexpr (ISO) {
-                        const T J = W.w[kb];
+                        const T J = W.w[bd.shell];
                         acc[slot][yb][bd.a][0][in] += J * s0;
                         acc[slot][yb][bd.a][1][in] += J * s1;
                         acc[slot][yb][bd.a][2][in] += J * s2;
@@ -375,6 +393,26 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                     }
                 });
             });
+            // scheduling fence between source rows (b, dy): the pending sums
+            // are forced out and the next row's staged values are read after
+            // it, so only one row of staged values is live at a time (fewer
+            // registers, more resident waves)
+            if constexpr (kb + 1 < NB) {
+                constexpr ZBond nx = ShapeC<KIND>::t.bonds[kb + 1];
+                if constexpr (nx.b != bd.b || nx.dy != bd.dy) {
+#pragma unroll
+                    for (int s2 = 0; s2 < D; ++s2)
+#pragma unroll
+                        for (int yb = 0; yb < kYB; ++yb)
+#pragma unroll
+                            for (int a2 = 0; a2 < NSUB; ++a2)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                                    for (int in = 0; in < NIN; ++in) asm volatile("" : "+v"(acc[s2][yb][a2][c][in]));
+                    asm volatile("" ::: "memory");
+                }
+            }
         });
         // output plane q - (D-1) (slot 0) has received all of its inputs
         const int o = q - (D - 1);
@@ -525,7 +563,7 @@ __global__ __launch_bounds__(256) void k_heun_post(int64_t M, int64_t N, Onsite 
 template <int KIND, typename T, bool ISO, int MODE>
 hipError_t launch_kind(const ZPlan &zp, const ZArgs &a, const Onsite &os, const HeunConst &hc, hipStream_t st) {
     constexpr int NB = make_shape(KIND).nb;
-    constexpr int NW = (ISO ? 1 : 9) * NB;
+    constexpr int NW = ISO ? make_shape(KIND).nshell : 9 * NB;
     ZWeights<T, NW> W;
     for (int k = 0; k < NW; ++k) W.w[k] = (T)(sizeof(T) == 4 ? (double)zp.wf[k] : zp.wd[k]);
     dim3 grid((unsigned)((a.Lx + kTX - 1) / kTX), (unsigned)((a.Ly + kTYE - 1) / kTYE),
@@ -587,8 +625,10 @@ bool zmarch_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, cons
         // supported instantiations (LDS budget): tensors only on SC_NN, FP64 not on bcc
         if (!iso && kind != SHAPE_SC_NN) continue;
         if (prec == 0 && kind == SHAPE_BCC_5SH) continue;
-        const int nw = (iso ? 1 : 9) * t.nb;
-        std::vector<double> w(nw, 0.0);
+        // isotropic tables: one coupling per shell (every bond of a shell must
+        // carry the same J); tensor tables: one 3x3 block per bond
+        const int nwb = (iso ? 1 : 9) * t.nb;
+        std::vector<double> w(nwb, 0.0);
         bool ok = true;
         for (int p = 0; p < n_bonds && ok; ++p) {
             int hit = -1;
@@ -606,6 +646,19 @@ bool zmarch_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, cons
                 for (int e = 0; e < 9; ++e) w[9 * hit + e] += bond_J[9 * p + e];
         }
         if (!ok) continue;
+        int nw = nwb;
+        if (iso) {
+            std::vector<double> ws(t.nshell, 0.0);
+            std::vector<int> seen(t.nshell, 0);
+            for (int k = 0; k < t.nb && ok; ++k) {
+                const int sh = t.bonds[k].shell;
+                if (!seen[sh]) { ws[sh] = w[k]; seen[sh] = 1; }
+                else if (w[k] != ws[sh]) ok = false;
+            }
+            if (!ok) continue;
+            w = ws;
+            nw = t.nshell;
+        }
         zp.kind = kind;
         zp.prec = prec;
         zp.iso = iso ? 1 : 0;

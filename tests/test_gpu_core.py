@@ -82,6 +82,20 @@ def test_zmarch_engine_selected_for_shell_shapes():
         assert info.stencil_engine == 2 and info.shape == shape, (w.J_shell, info.shape)
     w = Workload(name="t", L=(8, 8, 8), J_shell=(1.0, 0.2), D_shell=(0.3, 0.1))
     assert spx.get_info(gpu_hamiltonian(w, field_prec="fp32")).stencil_engine == 1
+    # an isotropic nearest-neighbour table whose bonds of one shell differ in J
+    # is not shell-uniform: it runs on the gather engine, still exactly
+    import torch
+    deltas = np.array([(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)], np.int32)
+    Jb = np.array([np.eye(3) * v for v in (1.0, 1.0, 0.5, 0.5, 0.8, 0.8)])
+    ab = np.zeros((6, 2), np.int32)
+    hb = spx.setup_hamiltonian((6, 5, 4), J_shell=None, bonds=(ab, deltas, Jb), field_prec="fp64")
+    assert spx.get_info(hb).stencil_engine == 1
+    lat = oracle.Lattice((6, 5, 4), np.eye(3), [0, 0, 0])
+    mb = oracle.Model(lat, bonds=(ab[:, 0], ab[:, 1], deltas, Jb))
+    S = random_sphere(lat.N, 8)
+    bb = torch.empty((3, lat.N), dtype=torch.float64, device="cuda")
+    spx.eval_field(hb, to_dev(S), bb)
+    assert max_rel(bb.cpu().numpy(), oracle.field(mb, S)) < 1e-13
     with pytest.raises(spx.SpxError):
         gpu_hamiltonian(w, field_prec="fp32", stencil_engine=2)
 
@@ -208,6 +222,8 @@ def test_heun_stored_field_equals_recompute():
     # the split mode (stencil pass + elementwise stages) computes the same
     e = gpu_heun(w, S, "fp32", setup=dict(heun_field=5), **kw)
     assert np.array_equal(c, e)
+    f = gpu_heun(w, S, "fp32", setup=dict(heun_field=6), **kw)
+    assert np.array_equal(c, f)
     # deterministic case (no noise store)
     kw["temperature_K"] = 0.0
     a = gpu_heun(w, S, "fp32", setup=dict(heun_field=1), **kw)
@@ -215,6 +231,8 @@ def test_heun_stored_field_equals_recompute():
     assert np.max(np.abs(a - c)) <= 1e-14
     e = gpu_heun(w, S, "fp32", setup=dict(heun_field=5), **kw)
     assert np.array_equal(c, e)
+    f = gpu_heun(w, S, "fp32", setup=dict(heun_field=6), **kw)
+    assert np.array_equal(c, f)
 
 
 def test_heun_resume_and_determinism():
@@ -338,7 +356,7 @@ def test_autotuner_picks_candidate_and_caches(tmp_path):
     cache = str(tmp_path / "tune.txt")
     h = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache)
     info = spx.get_info(h)
-    assert info.tuned == 1 and info.zchunk in (4, 8, 16) and info.heun_field in (1, 2, 3, 4, 5)
+    assert info.tuned == 1 and info.zchunk in (4, 8, 16) and info.heun_field in (1, 2, 3, 4, 5, 6)
     assert info.tuned_step_us > 0
     lines = open(cache).read().split("\n")
     assert any(l.startswith("shape3_prec1_sub2_16x16x16") for l in lines)
