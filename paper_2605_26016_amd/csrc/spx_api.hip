@@ -176,6 +176,7 @@ struct spx_ham {
     DensePlan *dense = nullptr;  // dense-window MFMA backend
     // z-march engine plan (valid when the bond table matches a shell shape)
     ZPlan zp;
+    ZPlan zp64;  // FP64 plan of the same table for batched-image field passes (GNEB)
     int engine = 1;          // 1 gather, 2 z-march
     int heun_field = 1;      // 1 recompute, 2 stored FP32 field, 3 stored stage (P, eta)
     float *d_bstore = nullptr;
@@ -291,6 +292,7 @@ spx_status check_device() {
 namespace spx {
 spx_status get_ham_view(spx_ham *h, HamView &v) {
     if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    v.zp64 = h->zp64.valid ? &h->zp64 : nullptr;
     v.grid = h->grid;
     v.tab = h->tab;
     v.onsite = h->onsite;
@@ -506,6 +508,12 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
         }
         const bool have = prec < SPX_BF16_MFMA && nb > 0 &&
                           zmarch_plan(prec, lat->n_sub, ba.data(), bb.data(), bd.data(), bJ.data(), nb, iso, h->zp);
+        // an FP64 plan for the GNEB's batched field pass (FP64 arithmetic in
+        // every field precision), unless the gather engine was requested
+        if (nb > 0 && engine_req != 1) {
+            if (!zmarch_plan(0, lat->n_sub, ba.data(), bb.data(), bd.data(), bJ.data(), nb, iso, h->zp64))
+                h->zp64.valid = false;
+        }
         if (engine_req == 2 && !have) {
             free_all(h);
             delete h;

@@ -24,7 +24,9 @@ void unregister_handle(const void *p);
 struct DipolarPlan;
 
 // Read-only view of a Hamiltonian handle for other subsystems.
+struct ZPlan;
 struct HamView {
+    const ZPlan *zp64;  // FP64 z-march plan of the bond table (NULL if none or engine forced to gather)
     Grid grid;
     BondTable tab;
     Onsite onsite;
@@ -65,6 +67,11 @@ hipError_t zmarch_predict(const ZPlan &zp, const Grid &g, const Onsite &os, cons
 hipError_t zmarch_noise(const HeunConst &hc, uint64_t step, int64_t N, double *eta, hipStream_t st);
 // split Heun mode: FP32 bilinear field pass + elementwise FP64 stages
 hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bil, hipStream_t st);
+// Bilinear field of n_img images stacked as [n_img][3][N] (FP64 plan, FP64
+// output).  The source buffer is S0, or S0alt when *sel != 0 (a device flag);
+// nothing is done when *skip != 0 (skip may be NULL).
+hipError_t zmarch_bil_images(const ZPlan &zp, const Grid &g, int n_img, const double *S0, const double *S0alt,
+                             const double *sel, const double *skip, double *bil, hipStream_t st);
 hipError_t heun_split_pre(const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step, const double *S,
                           const float *bil, const float *bdip, double *St, double *P, double *eta, hipStream_t st);
 hipError_t heun_split_post(const Grid &g, const Onsite &os, const HeunConst &hc, const double *St, const float *bil,

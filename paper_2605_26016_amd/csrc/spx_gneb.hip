@@ -48,6 +48,9 @@ struct GInst {
     double *st;           // [ST_N]
     double k, dt, mass, ci_on_below, tol;
     int ci_mode;
+    // bilinear field of every image from the batched z-march pass
+    // ([n_img][3][N], FP64); NULL: pass A gathers the neighbours itself
+    const double *Bbil;
 };
 
 struct GItem {
@@ -112,9 +115,14 @@ __global__ __launch_bounds__(kGB) void k_gneb_a(const GInst *__restrict__ inst, 
                 int x, y, z;
                 site_xyz(G.g, (int)(t - (int64_t)a * G.g.M), x, y, z);
                 double acc[1][3];
-                const double *const src[1] = {S};
-                if (G.tb.iso) bil_sum<double, true, 1>(G.tb, G.g, a, x, y, z, src, acc);
-                else bil_sum<double, false, 1>(G.tb, G.g, a, x, y, z, src, acc);
+                if (G.Bbil) {
+                    const double *Bb = G.Bbil + (int64_t)itm.img * 3 * N;
+                    ld3(Bb, N, t, acc[0]);
+                } else {
+                    const double *const src[1] = {S};
+                    if (G.tb.iso) bil_sum<double, true, 1>(G.tb, G.g, a, x, y, z, src, acc);
+                    else bil_sum<double, false, 1>(G.tb, G.g, a, x, y, z, src, acc);
+                }
                 double s[3], ba[3];
                 ld3(S, N, t, s);
                 aniso_field(*G.os, a, s, ba);
@@ -473,6 +481,7 @@ struct spx_gneb {
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;  // library-owned capture stream (the caller's may be the null stream)
     int use_graph = 1;
+    std::vector<ZPlan> zplan;  // per instance: FP64 z-march plan (used when its Bbil is set)
 };
 
 namespace {
@@ -499,6 +508,13 @@ void gneb_free(spx_gneb *g) {
 // Enqueue one GNEB iteration (all instances) on stream st.
 hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
     const unsigned gi = grid_for(g->n_items);
+    for (int k = 0; k < g->n_inst; ++k) {
+        const GInst &G = g->hinst[k];
+        if (!G.Bbil) continue;
+        hipError_t e = zmarch_bil_images(g->zplan[k], G.g, G.n_img, G.Y[0], G.Y[1], G.st + ST_CUR, G.st + ST_DONE,
+                                         (double *)G.Bbil, st);
+        if (e != hipSuccess) return e;
+    }
     k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
     k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0);
     k_gneb_scalars1<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
@@ -557,6 +573,11 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         gi.ci_on_below = p->ci_on_below;
         gi.tol = p->tol_force;
         onsites[k] = v.onsite;
+        // the batched z-march field pass needs an FP64 plan and at most
+        // 65535 (image, z chunk) blocks in z
+        gi.Bbil = nullptr;
+        g->zplan.push_back(v.zp64 ? *v.zp64 : ZPlan{});
+        if (v.zp64) g->zplan.back().zch = 16;
         for (int n = 0; n < n_img[k]; ++n) {
             imgs.push_back(make_int2(k, n));
             for (int b = 0; b < gi.items_per_img; ++b) items.push_back(GItem{k, n, b * kGB, 0});
@@ -584,6 +605,11 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         if ((s = gneb_alloc(g, (void **)&gi.F, n3 * sizeof(double), "GNEB forces")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.img, sizeof(double) * IS_N * gi.n_img, "GNEB image stats")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.st, sizeof(double) * ST_N, "GNEB state")) != SPX_OK) break;
+        const ZPlan &zp = g->zplan[k];
+        const int64_t nz = (int64_t)((gi.g.Lz + zp.zch - 1) / zp.zch) * gi.n_img;
+        if (zp.valid && nz <= 65535) {
+            if ((s = gneb_alloc(g, (void **)&gi.Bbil, n3 * sizeof(double), "GNEB bilinear field")) != SPX_OK) break;
+        }
     }
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_inst, sizeof(GInst) * n_inst, "GNEB instances");
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_items, sizeof(GItem) * items.size(), "GNEB items");

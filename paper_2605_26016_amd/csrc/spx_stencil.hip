@@ -78,6 +78,13 @@ struct ZArgs {
     const double *pload, *eload;  // ZM_CORRECT_P: P and eta; predictor: eta if not NULL
     const float *bdip0, *bdip1;  // dipolar fields of S0 / S1 (may be NULL)
     uint64_t step;
+    // image batch (field modes): blockIdx.z = image * nzc + z chunk, images
+    // bstride elements apart; S0alt replaces S0 when *sel != 0; the whole
+    // launch is a no-op when *skip != 0
+    int nzc, nimg;
+    int64_t bstride;
+    const double *S0alt;
+    const double *sel, *skip;
 };
 
 // Shape table as a static constant, so that every bond read in an unrolled
@@ -120,13 +127,17 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     const int ty = threadIdx.x / kTX;
     const int x0 = blockIdx.x * kTX;
     const int y0 = blockIdx.y * kTYE;
-    const int zs = blockIdx.z * g.zch;
+    if (g.skip && *g.skip != 0.0) return;  // uniform over the grid
+    const int img = blockIdx.z / g.nzc;
+    const int zs = (blockIdx.z - img * g.nzc) * g.zch;
+    const int64_t boff = (int64_t)img * g.bstride;
     const int nout = min(g.zch, g.Lz - zs);
     const int nq = nout + D - 1;
     const int64_t N = g.N;
+    const double *S0 = ((g.sel && *g.sel != 0.0) ? g.S0alt : g.S0) + boff;
     // LDS inputs: the field of S0 (and of S1 for the recomputing corrector);
     // the stored-field corrector needs only the field of S1 = S~
-    const double *src[2] = {(MODE == ZM_CORRECT_STORED || MODE == ZM_CORRECT_P) ? g.S1 : g.S0, g.S1};
+    const double *src[2] = {(MODE == ZM_CORRECT_STORED || MODE == ZM_CORRECT_P) ? g.S1 : S0, g.S1};
 
     T acc[D][kYB][NSUB][3][NIN];
 #pragma unroll
@@ -225,8 +236,9 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         constexpr int a = decltype(ac)::value;
         const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
         if constexpr (MODE == ZM_BIL) {
+            T *const bo = (T *)g.bout + boff;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) g.bstore[c * N + i] = (float)v[0][c];
+            for (int c = 0; c < 3; ++c) bo[c * N + i] = v[0][c];
             return;
         }
         if constexpr (MODE == ZM_CORRECT_P) {
@@ -567,7 +579,7 @@ hipError_t launch_kind(const ZPlan &zp, const ZArgs &a, const Onsite &os, const 
     ZWeights<T, NW> W;
     for (int k = 0; k < NW; ++k) W.w[k] = (T)(sizeof(T) == 4 ? (double)zp.wf[k] : zp.wd[k]);
     dim3 grid((unsigned)((a.Lx + kTX - 1) / kTX), (unsigned)((a.Ly + kTYE - 1) / kTYE),
-              (unsigned)((a.Lz + a.zch - 1) / a.zch));
+              (unsigned)(a.nzc * a.nimg));
     k_zmarch<KIND, T, ISO, MODE><<<grid, kThreads, 0, st>>>(a, os, hc, W);
     return hipGetLastError();
 }
@@ -609,6 +621,8 @@ ZArgs make_args(const ZPlan &zp, const Grid &g) {
     a.M = g.M;
     a.N = g.N;
     a.zch = zp.zch;
+    a.nzc = (g.Lz + zp.zch - 1) / zp.zch;
+    a.nimg = 1;
     return a;
 }
 
@@ -688,7 +702,25 @@ hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bi
     if (zp.prec != 1) return hipErrorInvalidValue;
     ZArgs a = make_args(zp, g);
     a.S0 = S;
-    a.bstore = bil;
+    a.bout = bil;
+    Onsite os{};
+    HeunConst hc{};
+    return launch_any<ZM_BIL>(zp, a, os, hc, st);
+}
+
+hipError_t zmarch_bil_images(const ZPlan &zp, const Grid &g, int n_img, const double *S0, const double *S0alt,
+                             const double *sel, const double *skip, double *bil, hipStream_t st) {
+    if (zp.prec != 0 || n_img <= 0) return hipErrorInvalidValue;
+    ZArgs a = make_args(zp, g);
+    const int64_t gz = (int64_t)a.nzc * n_img;
+    if (gz > 65535) return hipErrorInvalidValue;
+    a.S0 = S0;
+    a.S0alt = S0alt ? S0alt : S0;
+    a.sel = sel;
+    a.skip = skip;
+    a.nimg = n_img;
+    a.bstride = 3 * g.N;
+    a.bout = bil;
     Onsite os{};
     HeunConst hc{};
     return launch_any<ZM_BIL>(zp, a, os, hc, st);

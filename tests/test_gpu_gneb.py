@@ -57,8 +57,10 @@ def test_geodesic_init_matches_oracle():
     assert np.max(np.abs(Yd.cpu().numpy() - ref)) < 1e-13
 
 
-@pytest.mark.parametrize("ci_mode", [0, 1, 2, 3])
-def test_gneb_iterations_match_oracle(ci_mode):
+@pytest.mark.parametrize("ci_mode,engine", [(0, 0), (1, 0), (2, 0), (3, 0), (1, 1)],
+                         ids=["mode0", "mode1", "mode2", "mode3", "mode1_gather"])
+def test_gneb_iterations_match_oracle(ci_mode, engine):
+    # engine 0: the batched z-march field pass; 1: pass A gathers neighbours
     import torch
     from paper_2605_26016_amd import spx
     w = frustrated((5, 4, 3))
@@ -67,7 +69,7 @@ def test_gneb_iterations_match_oracle(ci_mode):
     params = dict(spring_k=0.5, vp_dt=0.05, vp_mass=1.0, ci_mode=ci_mode, ci_on_below=10.0)
     Y0 = oracle.geodesic_path(A, B, n_img)
     Yd = to_dev(Y0)
-    g = spx.gneb_create([gpu_hamiltonian(w)], [Yd], **params)
+    g = spx.gneb_create([gpu_hamiltonian(w, stencil_engine=engine)], [Yd], **params)
     st = oracle.GnebState(Y0, k_spring=0.5, dt=0.05, mass=1.0, ci_mode=ci_mode, ci_on_below=10.0)
     m = oracle_model(w)
     for it in range(12):
