@@ -299,7 +299,7 @@ def dip_workload(L):
     return w
 
 
-@pytest.mark.parametrize("L", [(5, 4, 6), (8, 8, 8)])
+@pytest.mark.parametrize("L", [(5, 4, 6), (8, 8, 8), (1, 3, 2), (7, 1, 9), (4, 256, 3), (3, 4, 200)])
 def test_dipolar_field_vs_direct_sum(L):
     from paper_2605_26016_amd import spx  # noqa: F401
     w = dip_workload(L)
