@@ -69,9 +69,11 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S
     __shared__ __attribute__((aligned(16))) short tile[3][kIZ][kIY][kIX];
     const int x0 = blockIdx.x * kDX, y0 = blockIdx.y * kDY, z0 = blockIdx.z * kDZ;
     const int64_t N = g.N;
-    // stage the input tile (zero outside open faces, wrapped on periodic axes)
+    // stage the input tile (zero outside open faces, wrapped on periodic axes);
+    // kIX = 16 lanes per x run, so idx splits with shifts
     for (int idx = threadIdx.x; idx < kIZ * kIY * kIX; idx += 256) {
-        const int xx = idx % kIX, yy = (idx / kIX) % kIY, zz = idx / (kIX * kIY);
+        const int xx = idx & (kIX - 1), yz = idx >> 4;
+        const int yy = yz % kIY, zz = yz / kIY;
         bool ok = true;
         const int gx = wrap_coord(x0 - kR + xx, g.Lx, g.per[0], 1, ok);
         const int gy = wrap_coord(y0 - kR + yy, g.Ly, g.per[1], 1, ok);
@@ -85,14 +87,31 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S
     const int zl0 = 2 * wave;  // this wave's two output planes
     f32x16 acc0 = {}, acc1 = {};
     const int arow = lane & 31, ak = 8 * (lane >> 5);
-    for (int run = 0; run < kRuns; ++run) {
-        const int beta = run % 3, dyz = run / 3;
-        const int dy = dyz % 7 - kR, dz = dyz / 7 - kR;
-        const s16x8 bf = wfrag[run * 64 + lane];
-        const s16x8 a0 = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + dz + kR][arow + dy + kR][ak]);
-        const s16x8 a1 = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + 1 + dz + kR][arow + dy + kR][ak]);
-        acc0 = mfma32<BF16>(a0, bf, acc0);
-        acc1 = mfma32<BF16>(a1, bf, acc1);
+    // weight fragments stream from L2 in chunks of kChunk runs; the next
+    // chunk's loads are issued before the current chunk's MFMAs
+    constexpr int kChunk = 7;
+    static_assert(kRuns % kChunk == 0, "runs per chunk");
+    s16x8 bcur[kChunk], bnext[kChunk];
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) bcur[r] = wfrag[r * 64 + lane];
+#pragma unroll 1
+    for (int run0 = 0; run0 < kRuns; run0 += kChunk) {
+        if (run0 + kChunk < kRuns) {
+#pragma unroll
+            for (int r = 0; r < kChunk; ++r) bnext[r] = wfrag[(run0 + kChunk + r) * 64 + lane];
+        }
+#pragma unroll
+        for (int r = 0; r < kChunk; ++r) {
+            const int run = run0 + r;
+            const int beta = run % 3, dyz = run / 3;
+            const int dy = dyz % 7 - kR, dz = dyz / 7 - kR;
+            const s16x8 a0 = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + dz + kR][arow + dy + kR][ak]);
+            const s16x8 a1 = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + 1 + dz + kR][arow + dy + kR][ak]);
+            acc0 = mfma32<BF16>(a0, bcur[r], acc0);
+            acc1 = mfma32<BF16>(a1, bcur[r], acc1);
+        }
+#pragma unroll
+        for (int r = 0; r < kChunk; ++r) bcur[r] = bnext[r];
     }
     // epilogue: column -> (component, x), row -> y; on-site terms in FP64
     const int col = lane & 31;
@@ -109,9 +128,11 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S
             if (y >= g.Ly) continue;
             const int64_t i = x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
             const float v = (p == 0 ? acc0[r] : acc1[r]) * kscale;
-            const double s[3] = {S[i], S[N + i], S[2 * N + i]};
-            double ba[3];
-            aniso_field(os, 0, s, ba);
+            double ba[3] = {0.0, 0.0, 0.0};
+            if (os.n_aniso > 0) {  // the spin is read only when an anisotropy needs it
+                const double s[3] = {S[i], S[N + i], S[2 * N + i]};
+                aniso_field(os, 0, s, ba);
+            }
             b[alpha * N + i] = (float)((double)v + ba[alpha] + os.bz[0][alpha]);
         }
     }
