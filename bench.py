@@ -183,106 +183,11 @@ def cpu_gneb_baseline(seconds):
 
 
 def learned_experiment(family, args):
-    """Train the path corrector on GNEB-converged paths of one family and
-    compare GNEB from the learned and the geodesic initial path on held-out
-    end states.  hopfion: four-shell frustrated sc exchange (J1 = 1 meV,
-    J2/J1 = 0.188, J3/J1 = -0.274, J4/J1 = -0.161), open L^3, VP-relaxed
-    seeded hopfion -> FM.  skyrmion: sc monolayer film, J = 1 meV, bulk DMI
-    0.3 meV, B = 1.4 T, periodic in plane, relaxed seeded skyrmion -> FM,
-    trained on 32^2 and evaluated on a ragged batch of 48^2, 64^2, 96^2 films
-    with 32 images."""
-    import numpy as np
-    import torch
-
-    from paper_2605_26016_amd import pathinit, spx
-    from workloads import hopfion_texture, skyrmion_texture, uniform_state
-
-    t0 = time.perf_counter()
-    if family == "hopfion":
-        J = dict(J_shell=(1.0, 0.188, -0.274, -0.161))
-        Ltr = (args.gneb_L,) * 3
-        Lte = [Ltr]
-        per = (0, 0, 0)
-        n_tr_img, n_te_img = 16, 16
-        n_train, n_test = args.n_train, args.n_test
-
-        def seed_state(L, s):
-            rng = np.random.default_rng(s)
-            m = min(L) / 6
-            return hopfion_texture(L, R0=m * (1 + 0.2 * rng.uniform(-1, 1)), width=m * (1 + 0.2 * rng.uniform(-1, 1)),
-                                   center_offset=rng.uniform(-2, 2, 3))
-    else:
-        J = dict(J_shell=(1.0,), D_shell=(0.3,), B=(0.0, 0.0, 1.4))
-        Ltr = (32, 32, 1)
-        Lte = [(48, 48, 1), (64, 64, 1), (96, 96, 1)]
-        per = (1, 1, 0)
-        n_tr_img, n_te_img = 16, 32
-        n_train, n_test = args.n_train, 3 * max(1, args.n_test // 3)
-
-        def seed_state(L, s):
-            rng = np.random.default_rng(s)
-            return skyrmion_texture(L, R=3.0 * (1 + 0.3 * rng.uniform(-1, 1)), center=tuple(rng.uniform(-3, 3, 2)))
-
-    hams = {}
-
-    def ham(L):
-        if L not in hams:
-            hams[L] = spx.setup_hamiltonian(L, periodic=per, field_prec="fp64", **J)
-        return hams[L]
-
-    def endpoints(L, seeds):
-        h = ham(L)
-        st = [torch.from_numpy(seed_state(L, s)).cuda() for s in seeds]
-        rel, _, _ = pathinit.minimize(h, st, tol=2e-4, max_iter=30000, vp_dt=0.2)
-        return [r for r in rel if int((r[2] < 0).sum()) > 0]   # textures that survived relaxation
-
-    def paths(L, A, n_img):
-        N = L[0] * L[1] * L[2]
-        fm = torch.from_numpy(uniform_state(N)).cuda()
-        Ys = []
-        for a in A:
-            Y = torch.zeros((n_img, 3, N), dtype=torch.float64, device="cuda")
-            Y[0] = a
-            Y[-1] = fm
-            Ys.append(Y)
-        return Ys
-
-    A_tr = endpoints(Ltr, range(1000, 1000 + n_train))
-    Y_tr = paths(Ltr, A_tr, n_tr_img)
-    geo = [y.clone() for y in Y_tr]
-    gg = spx.gneb_create([ham(Ltr)] * len(geo), geo)
-    spx.gneb_init_path(gg)
-    res_tr = pathinit.converge([ham(Ltr)] * len(Y_tr), Y_tr, tol=1e-3, max_iter=args.max_iter, chunk=1000)
-    ok = [k for k in range(len(Y_tr)) if res_tr.converged[k]]
-    log(f"[bench] {family}: {len(ok)}/{len(Y_tr)} training paths converged (median "
-        f"{int(np.median(res_tr.iterations))} iterations), {time.perf_counter() - t0:.1f} s")
-    data = pathinit.build_samples(Ltr, [geo[k] for k in ok], [Y_tr[k] for k in ok])
-    p, net, hist = pathinit.train(data, epochs=args.epochs, batch=16, lr=1e-3)
-    log(f"[bench] {family}: trained, loss {hist[0]:.3e} -> {hist[-1]:.3e}, {time.perf_counter() - t0:.1f} s")
-    Hs, Yp = [], []
-    per_size = max(1, n_test // len(Lte))
-    for i, L in enumerate(Lte):
-        A = endpoints(L, range(5000 + 100 * i, 5000 + 100 * i + per_size))
-        Yp += paths(L, A, n_te_img)
-        Hs += [ham(L)] * len(A)
-    Yl = [y.clone() for y in Yp]
-    rp = pathinit.converge(Hs, Yp, tol=1e-3, max_iter=args.max_iter, chunk=250)
-    rl = pathinit.converge(Hs, Yl, tol=1e-3, max_iter=args.max_iter, chunk=250, method=1, net=net, params=p)
-    both = [k for k in range(len(Yp)) if rp.converged[k] and rl.converged[k]]
-    dbar = np.abs(rl.barrier - rp.barrier)
-    same = [k for k in both if dbar[k] <= 0.1]
-    it_p = float(np.mean(rp.iterations[same])) if same else None
-    it_l = float(np.mean(rl.iterations[same])) if same else None
-    return {"lattice_train": list(Ltr), "lattices_test": [list(L) for L in Lte], "images_train": n_tr_img,
-            "images_test": n_te_img, "train_paths": len(ok), "test_paths": len(Yp),
-            "test_converged_both": len(both), "same_channel_within_0.1meV": len(same),
-            "iterations_geodesic": rp.iterations.tolist(), "iterations_learned": rl.iterations.tolist(),
-            "barrier_geodesic_meV": np.round(rp.barrier, 4).tolist(),
-            "barrier_learned_meV": np.round(rl.barrier, 4).tolist(),
-            "mean_iterations_geodesic_same_channel": it_p, "mean_iterations_learned_same_channel": it_l,
-            "iteration_ratio_learned_over_geodesic": (it_l / it_p) if same else None,
-            "max_barrier_difference_same_channel_meV": float(np.max(dbar[same])) if same else None,
-            "train_loss_first_last": [hist[0], hist[-1]], "seconds": time.perf_counter() - t0}
+    """Learned versus geodesic initial paths on held-out end states of one
+    family (see pathinit.learned_vs_geodesic)."""
+    from paper_2605_26016_amd import pathinit
+    return pathinit.learned_vs_geodesic(family, n_train=args.n_train, n_test=args.n_test, epochs=args.epochs,
+                                        lr=args.lr, max_iter=args.max_iter, hopfion_L=args.gneb_L, log=log)
 
 
 def heun_workload(args, w):
@@ -577,7 +482,8 @@ def main():
     ap.add_argument("--gneb-L", type=int, default=32)
     ap.add_argument("--n-train", type=int, default=200)
     ap.add_argument("--n-test", type=int, default=12)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--lr", type=float, default=2e-3, help="initial Adam step of the path net (cosine decay to lr/20)")
     ap.add_argument("--families", default="skyrmion,hopfion")
     ap.add_argument("--max-iter", type=int, default=30000)
     args = ap.parse_args()

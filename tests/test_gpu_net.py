@@ -146,3 +146,21 @@ def test_learned_init_with_zero_net_is_geodesic_and_nonzero_matches_forward():
         ref, _ = oracle.net_predict_loss(raw, geo[n])
         assert np.max(np.abs(got[n] - ref)) < 1e-5
     assert np.array_equal(got[0], A) and np.array_equal(got[-1], Bv)
+
+
+def test_trained_net_saves_gneb_iterations_at_equal_barrier():
+    # the learned part's gain: train the corrector on GNEB-converged
+    # skyrmion-annihilation paths (24^2 films) with the library's own kernels,
+    # then run GNEB on held-out end states from the geodesic and from the
+    # learned initial path; pairs count when both converge to the same barrier
+    # (within 0.1 meV); the learned paths must need clearly fewer iterations
+    from paper_2605_26016_amd import pathinit
+    r = pathinit.learned_vs_geodesic("skyrmion", n_train=60, n_test=6, epochs=150, lr=2e-3, max_iter=20000,
+                                     skyrmion_train_L=24, skyrmion_test_L=(24, 32))
+    print({k: r[k] for k in ("same_channel_within_0.1meV", "mean_iterations_geodesic_same_channel",
+                             "mean_iterations_learned_same_channel", "iteration_ratio_learned_over_geodesic",
+                             "train_loss_first_last", "seconds")}, flush=True)
+    assert r["test_converged_both"] == r["test_paths"]
+    assert r["same_channel_within_0.1meV"] >= (2 * r["test_paths"]) // 3
+    assert r["train_loss_first_last"][1] < 0.5 * r["train_loss_first_last"][0]
+    assert r["iteration_ratio_learned_over_geodesic"] < 0.9
