@@ -180,6 +180,7 @@ struct spx_ham {
     int engine = 1;          // 1 gather, 2 z-march
     int heun_field = 1;      // 1 recompute, 2 stored FP32 field, 3 stored stage (P, eta)
     float *d_bstore = nullptr;
+    void *d_ebil = nullptr;  // energy: bilinear field of the z-march pass (made at the first call)
     double *d_P = nullptr;   // heun_field 3: S^n + dt/2 f(S^n)
     double *d_eta = nullptr; // heun_field 3: the step's thermal noise
     // Heun graph replay: 2-step graph with a device step counter
@@ -266,8 +267,9 @@ void free_all(spx_ham *h) {
     h->dip = nullptr;
     for (void *p : {(void *)h->d_geo, (void *)h->d_Jf, (void *)h->d_Jd, (void *)h->d_St, (void *)h->d_Sp,
                     (void *)h->d_partial, (void *)h->d_bdip0, (void *)h->d_bdip1, (void *)h->d_bstore,
-                    (void *)h->d_P, (void *)h->d_eta})
+                    (void *)h->d_P, (void *)h->d_eta, h->d_ebil})
         if (p) (void)hipFree(p);
+    h->d_ebil = nullptr;
     h->d_bstore = nullptr;
     h->d_P = h->d_eta = nullptr;
     h->d_geo = nullptr;
@@ -899,9 +901,26 @@ spx_status spx_energy(spx_ham *h, const double *S, double *E, double *terms, voi
         if (s != SPX_OK) return s;
         bdip = h->d_bdip0;
     }
-    // the dense MFMA backend evaluates energies with the FP32 gather kernel
+    // the dense MFMA backend evaluates energies with the FP32 gather kernel;
+    // with the z-march engine the bilinear field comes from its stencil pass
+    // (into the stored-field buffer, or a field buffer made at the first call)
     const int eprec = h->field_prec >= SPX_BF16_MFMA ? SPX_FP32 : h->field_prec;
-    hipError_t e = launch_energy(eprec, h->tab, h->grid, h->onsite, S, bdip, h->d_partial, E, terms, st);
+    const void *bil = nullptr;
+    hipError_t e = hipSuccess;
+    if (h->engine == 2 && h->zp.valid) {
+        void *buf = (h->zp.prec == 1 && h->d_bstore) ? (void *)h->d_bstore : h->d_ebil;
+        if (!buf) {
+            const size_t bytes = (size_t)3 * h->grid.N * (h->zp.prec == 1 ? sizeof(float) : sizeof(double));
+            spx_status s = dev_alloc(h, (unsigned char **)&h->d_ebil, bytes, "energy field buffer");
+            if (s != SPX_OK) return s;
+            buf = h->d_ebil;
+        }
+        e = h->zp.prec == 1 ? zmarch_bil(h->zp, h->grid, S, (float *)buf, st)
+                            : zmarch_bil_images(h->zp, h->grid, 1, S, nullptr, nullptr, nullptr, (double *)buf, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_energy (field pass)");
+        bil = buf;
+    }
+    e = launch_energy(eprec, h->tab, h->grid, h->onsite, S, bdip, bil, h->d_partial, E, terms, st);
     if (e != hipSuccess) return hip_fail(e, "spx_energy");
     return SPX_OK;
 }

@@ -573,8 +573,7 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         gi.ci_on_below = p->ci_on_below;
         gi.tol = p->tol_force;
         onsites[k] = v.onsite;
-        // the batched z-march field pass needs an FP64 plan and at most
-        // 65535 (image, z chunk) blocks in z
+        // the batched z-march field pass needs an FP64 plan of the table
         gi.Bbil = nullptr;
         g->zplan.push_back(v.zp64 ? *v.zp64 : ZPlan{});
         if (v.zp64) g->zplan.back().zch = 16;
@@ -606,8 +605,7 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         if ((s = gneb_alloc(g, (void **)&gi.img, sizeof(double) * IS_N * gi.n_img, "GNEB image stats")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.st, sizeof(double) * ST_N, "GNEB state")) != SPX_OK) break;
         const ZPlan &zp = g->zplan[k];
-        const int64_t nz = (int64_t)((gi.g.Lz + zp.zch - 1) / zp.zch) * gi.n_img;
-        if (zp.valid && nz <= 65535) {
+        if (zp.valid) {
             if ((s = gneb_alloc(g, (void **)&gi.Bbil, n3 * sizeof(double), "GNEB bilinear field")) != SPX_OK) break;
         }
     }

@@ -77,8 +77,10 @@ hipError_t launch_heun_correct(int field_prec, const BondTable &tb, const Grid &
 // Energy partials: partial[block][4] (bil, Z, ani, dip), then a fixed-order
 // final reduction into E (1 double) and terms (5 doubles, may be NULL).
 int energy_partial_count(const Grid &g);
+// bil: precomputed bilinear field (double for field_prec 0, float otherwise)
+// or NULL to gather the neighbours.
 hipError_t launch_energy(int field_prec, const BondTable &tb, const Grid &g, const Onsite &os,
-                         const double *S, const float *bdip, double *partial, double *E,
+                         const double *S, const float *bdip, const void *bil, double *partial, double *E,
                          double *terms, hipStream_t st);
 hipError_t launch_thermal_noise(uint64_t seed, uint64_t step, uint32_t tag, int64_t N, double *eta,
                                 hipStream_t st);

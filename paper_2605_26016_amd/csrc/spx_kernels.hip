@@ -198,7 +198,9 @@ template <typename AccT, bool ISO>
 __global__ __launch_bounds__(kBlock) void k_energy_partial(BondTable tb, Grid g, Onsite os,
                                                            const double *__restrict__ S,
                                                            const float *__restrict__ bdip,
+                                                           const AccT *__restrict__ bil,
                                                            double *__restrict__ partial) {
+    // bil != NULL: the bilinear field comes precomputed (stencil-engine pass)
     __shared__ double red[kBlock / 64][4];
     const int a = blockIdx.y;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -209,8 +211,13 @@ __global__ __launch_bounds__(kBlock) void k_energy_partial(BondTable tb, Grid g,
         const int64_t N = g.N;
         const int64_t i = (int64_t)a * g.M + t;
         AccT acc[1][3];
-        const double *const src[1] = {S};
-        bil_sum<AccT, ISO, 1>(tb, g, a, x, y, z, src, acc);
+        if (bil) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[0][c] = bil[c * N + i];
+        } else {
+            const double *const src[1] = {S};
+            bil_sum<AccT, ISO, 1>(tb, g, a, x, y, z, src, acc);
+        }
         const double s[3] = {S[i], S[N + i], S[2 * N + i]};
         double ba[3];
         aniso_field(os, a, s, ba);
@@ -276,15 +283,17 @@ int energy_partial_count(const Grid &g) {
 }
 
 hipError_t launch_energy(int field_prec, const BondTable &tb, const Grid &g, const Onsite &os,
-                         const double *S, const float *bdip, double *partial, double *E,
+                         const double *S, const float *bdip, const void *bil, double *partial, double *E,
                          double *terms, hipStream_t st) {
     const dim3 grid = site_grid(g);
     if (field_prec == 0) {
-        if (tb.iso) k_energy_partial<double, true><<<grid, kBlock, 0, st>>>(tb, g, os, S, bdip, partial);
-        else k_energy_partial<double, false><<<grid, kBlock, 0, st>>>(tb, g, os, S, bdip, partial);
+        const double *bd = (const double *)bil;
+        if (tb.iso) k_energy_partial<double, true><<<grid, kBlock, 0, st>>>(tb, g, os, S, bdip, bd, partial);
+        else k_energy_partial<double, false><<<grid, kBlock, 0, st>>>(tb, g, os, S, bdip, bd, partial);
     } else {
-        if (tb.iso) k_energy_partial<float, true><<<grid, kBlock, 0, st>>>(tb, g, os, S, bdip, partial);
-        else k_energy_partial<float, false><<<grid, kBlock, 0, st>>>(tb, g, os, S, bdip, partial);
+        const float *bf = (const float *)bil;
+        if (tb.iso) k_energy_partial<float, true><<<grid, kBlock, 0, st>>>(tb, g, os, S, bdip, bf, partial);
+        else k_energy_partial<float, false><<<grid, kBlock, 0, st>>>(tb, g, os, S, bdip, bf, partial);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

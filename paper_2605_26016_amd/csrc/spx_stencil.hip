@@ -44,6 +44,12 @@ constexpr int kYB = SPX_ZM_YB;     // y sites per thread
 // plane's compute and written to LDS after it (global latency overlapped);
 // single-input modes only (two staged inputs would double those registers)
 constexpr bool kPrefetch = SPX_ZM_PREFETCH != 0;
+// XCD-contiguous tile assignment: measured within +-2.5% of the default
+// round-robin order on the bcc and sc workloads, so left off.
+#ifndef SPX_ZM_XCD
+#define SPX_ZM_XCD 0
+#endif
+constexpr bool kXcdRemap = SPX_ZM_XCD != 0;
 
 constexpr int kTYE = kTYT * kYB;  // tile height in y
 constexpr int kThreads = kTX * kTYT;
@@ -125,11 +131,20 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 
     const int tx = threadIdx.x & (kTX - 1);
     const int ty = threadIdx.x / kTX;
-    const int x0 = blockIdx.x * kTX;
-    const int y0 = blockIdx.y * kTYE;
     if (g.skip && *g.skip != 0.0) return;  // uniform over the grid
-    const int img = blockIdx.z / g.nzc;
-    const int zs = (blockIdx.z - img * g.nzc) * g.zch;
+    // 1-D grid of (x tile, y tile, z chunk, image) tiles, x fastest.  Blocks
+    // are dealt to the 8 XCDs round-robin; with kXcdRemap each XCD instead
+    // gets one contiguous run of tiles, so tiles that share halo rows share
+    // that XCD's L2.
+    const unsigned nbx = (unsigned)((g.Lx + kTX - 1) / kTX), nby = (unsigned)((g.Ly + kTYE - 1) / kTYE);
+    const unsigned ntile = gridDim.x;
+    unsigned tile = blockIdx.x;
+    if (kXcdRemap && (ntile & 7u) == 0) tile = (tile & 7u) * (ntile >> 3) + (tile >> 3);
+    const int x0 = (int)(tile % nbx) * kTX;
+    const int y0 = (int)((tile / nbx) % nby) * kTYE;
+    const int zb = (int)(tile / (nbx * nby));
+    const int img = zb / g.nzc;
+    const int zs = (zb - img * g.nzc) * g.zch;
     const int64_t boff = (int64_t)img * g.bstride;
     const int nout = min(g.zch, g.Lz - zs);
     const int nq = nout + D - 1;
@@ -578,9 +593,9 @@ hipError_t launch_kind(const ZPlan &zp, const ZArgs &a, const Onsite &os, const 
     constexpr int NW = ISO ? make_shape(KIND).nshell : 9 * NB;
     ZWeights<T, NW> W;
     for (int k = 0; k < NW; ++k) W.w[k] = (T)(sizeof(T) == 4 ? (double)zp.wf[k] : zp.wd[k]);
-    dim3 grid((unsigned)((a.Lx + kTX - 1) / kTX), (unsigned)((a.Ly + kTYE - 1) / kTYE),
-              (unsigned)(a.nzc * a.nimg));
-    k_zmarch<KIND, T, ISO, MODE><<<grid, kThreads, 0, st>>>(a, os, hc, W);
+    const int64_t ntile = (int64_t)((a.Lx + kTX - 1) / kTX) * ((a.Ly + kTYE - 1) / kTYE) * a.nzc * a.nimg;
+    if (ntile > 0x7fffffff) return hipErrorInvalidValue;
+    k_zmarch<KIND, T, ISO, MODE><<<(unsigned)ntile, kThreads, 0, st>>>(a, os, hc, W);
     return hipGetLastError();
 }
 
@@ -712,8 +727,6 @@ hipError_t zmarch_bil_images(const ZPlan &zp, const Grid &g, int n_img, const do
                              const double *sel, const double *skip, double *bil, hipStream_t st) {
     if (zp.prec != 0 || n_img <= 0) return hipErrorInvalidValue;
     ZArgs a = make_args(zp, g);
-    const int64_t gz = (int64_t)a.nzc * n_img;
-    if (gz > 65535) return hipErrorInvalidValue;
     a.S0 = S0;
     a.S0alt = S0alt ? S0alt : S0;
     a.sel = sel;

@@ -142,13 +142,15 @@ ENERGY_CASES = [
 ]
 
 
+@pytest.mark.parametrize("engine", [0, 1], ids=["auto", "gather"])
 @pytest.mark.parametrize("name,w,prec,tol", ENERGY_CASES, ids=[c[0] for c in ENERGY_CASES])
-def test_energy_parity(name, w, prec, tol):
+def test_energy_parity(name, w, prec, tol, engine):
+    # auto: the z-march field pass feeds the energy where a shell shape matches
     import torch
     from paper_2605_26016_amd import spx
     S = random_sphere(w.N, 41)
     ref = oracle.energy(oracle_model(w), S)
-    h = gpu_hamiltonian(w, field_prec=prec)
+    h = gpu_hamiltonian(w, field_prec=prec, stencil_engine=engine)
     E = torch.zeros(1, dtype=torch.float64, device="cuda")
     terms = torch.zeros(5, dtype=torch.float64, device="cuda")
     spx.energy(h, to_dev(S), E, terms)
