@@ -4,12 +4,12 @@
 // single-sublattice kernel K^{ab}(delta) filling a 7^3 window.
 //
 // GEMM mapping (v_mfma_f32_32x32x16_{bf16,f16}):
-//   M = 32 output rows y (one z plane),
+//   M = 32 output rows y (one z plane; a wave owns 4 planes, a block 16),
 //   N = 32 columns = 3 field components x 10 consecutive output x + 2 pad,
 //   K = 16 consecutive input x' of one (beta, dy, dz) run,
 // so the x-direction band of the kernel sits in the weight operand B
 // (a 16 x 32 Toeplitz slice per run, 41 % of its MACs useful) and every input
-// value is read once per run from LDS.  147 MFMAs (49 (dy,dz) x 3 beta) per
+// value is read once per (dy, beta) row from LDS and feeds up to 4 MFMAs.  147 MFMAs (49 (dy,dz) x 3 beta) per
 // 320 output sites.  Weight fragments are built on the host in lane order.
 // Operands are scaled by powers of two before rounding (exact) and the
 // product scale is undone in FP32: BF16 weights so that max|K| lies in [1,2);
@@ -33,7 +33,10 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kDX = 10;   // output x per tile
 constexpr int kDY = 32;   // output y per tile (MFMA rows)
-constexpr int kDZ = 8;    // output z per block (2 per wave)
+constexpr int kPW = 4;    // output z planes per wave
+constexpr int kWaves = 4;
+constexpr int kDZ = kPW * kWaves;  // output z per block
+constexpr int kThreadsD = 64 * kWaves;
 constexpr int kR = 3;     // window radius
 constexpr int kIX = 16;   // input x per run (kDX + 2 kR)
 constexpr int kIY = kDY + 2 * kR;
@@ -63,7 +66,7 @@ __device__ __forceinline__ short to16(float v) {
 __device__ __forceinline__ int d_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S, float *__restrict__ b,
+__global__ __launch_bounds__(kThreadsD) void k_dense_mfma(const double *__restrict__ S, float *__restrict__ b,
                                                     const s16x8 *__restrict__ wfrag, float kscale, float in_scale,
                                                     Grid g, Onsite os) {
     __shared__ __attribute__((aligned(16))) short tile[3][kIZ][kIY][kIX];
@@ -71,7 +74,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S
     const int64_t N = g.N;
     // stage the input tile (zero outside open faces, wrapped on periodic axes);
     // kIX = 16 lanes per x run, so idx splits with shifts
-    for (int idx = threadIdx.x; idx < kIZ * kIY * kIX; idx += 256) {
+    for (int idx = threadIdx.x; idx < kIZ * kIY * kIX; idx += kThreadsD) {
         const int xx = idx & (kIX - 1), yz = idx >> 4;
         const int yy = yz % kIY, zz = yz / kIY;
         bool ok = true;
@@ -84,34 +87,38 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int zl0 = 2 * wave;  // this wave's two output planes
-    f32x16 acc0 = {}, acc1 = {};
+    const int zl0 = kPW * wave;  // this wave's output planes zl0 .. zl0 + kPW - 1
+    f32x16 acc[kPW];
+#pragma unroll
+    for (int p = 0; p < kPW; ++p) acc[p] = f32x16{};
     const int arow = lane & 31, ak = 8 * (lane >> 5);
-    // weight fragments stream from L2 in chunks of kChunk runs; the next
-    // chunk's loads are issued before the current chunk's MFMAs
-    constexpr int kChunk = 7;
-    static_assert(kRuns % kChunk == 0, "runs per chunk");
-    s16x8 bcur[kChunk], bnext[kChunk];
+    // Loop over the 21 (dy, beta) weight rows.  Each wave holds the 7 dz
+    // fragments of a row and streams the kPW + 6 input planes it touches:
+    // every A operand read from LDS feeds up to kPW MFMAs (one per output
+    // plane p, with dz = plane - p) and every weight fragment kPW MFMAs.
+    // The next row's weights are loaded while the current row computes.
+    auto run_of = [](int dyb, int dz) { return (dyb % 3) + 3 * ((dyb / 3) + 7 * dz); };
+    s16x8 bw[7], bn[7];
 #pragma unroll
-    for (int r = 0; r < kChunk; ++r) bcur[r] = wfrag[r * 64 + lane];
+    for (int dz = 0; dz < 7; ++dz) bw[dz] = wfrag[run_of(0, dz) * 64 + lane];
 #pragma unroll 1
-    for (int run0 = 0; run0 < kRuns; run0 += kChunk) {
-        if (run0 + kChunk < kRuns) {
+    for (int dyb = 0; dyb < 21; ++dyb) {
+        if (dyb + 1 < 21) {
 #pragma unroll
-            for (int r = 0; r < kChunk; ++r) bnext[r] = wfrag[(run0 + kChunk + r) * 64 + lane];
+            for (int dz = 0; dz < 7; ++dz) bn[dz] = wfrag[run_of(dyb + 1, dz) * 64 + lane];
+        }
+        const int beta = dyb % 3, dy = dyb / 3 - kR;
+#pragma unroll
+        for (int zi = 0; zi < kPW + 2 * kR; ++zi) {
+            const s16x8 a = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + zi][arow + dy + kR][ak]);
+#pragma unroll
+            for (int p = 0; p < kPW; ++p) {
+                const int dz = zi - p;  // 0..6  <->  offset dz - kR
+                if (dz >= 0 && dz < 7) acc[p] = mfma32<BF16>(a, bw[dz], acc[p]);
+            }
         }
 #pragma unroll
-        for (int r = 0; r < kChunk; ++r) {
-            const int run = run0 + r;
-            const int beta = run % 3, dyz = run / 3;
-            const int dy = dyz % 7 - kR, dz = dyz / 7 - kR;
-            const s16x8 a0 = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + dz + kR][arow + dy + kR][ak]);
-            const s16x8 a1 = *reinterpret_cast<const s16x8 *>(&tile[beta][zl0 + 1 + dz + kR][arow + dy + kR][ak]);
-            acc0 = mfma32<BF16>(a0, bcur[r], acc0);
-            acc1 = mfma32<BF16>(a1, bcur[r], acc1);
-        }
-#pragma unroll
-        for (int r = 0; r < kChunk; ++r) bcur[r] = bnext[r];
+        for (int dz = 0; dz < 7; ++dz) bw[dz] = bn[dz];
     }
     // epilogue: column -> (component, x), row -> y; on-site terms in FP64
     const int col = lane & 31;
@@ -119,7 +126,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S
     const int alpha = col / kDX, x = x0 + col % kDX;
     if (x >= g.Lx) return;
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < kPW; ++p) {
         const int z = z0 + zl0 + p;
         if (z >= g.Lz) continue;
 #pragma unroll
@@ -127,7 +134,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const double *__restrict__ S
             const int y = y0 + d_row(lane, r);
             if (y >= g.Ly) continue;
             const int64_t i = x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
-            const float v = (p == 0 ? acc0[r] : acc1[r]) * kscale;
+            const float v = acc[p][r] * kscale;
             double ba[3] = {0.0, 0.0, 0.0};
             if (os.n_aniso > 0) {  // the spin is read only when an anisotropy needs it
                 const double s[3] = {S[i], S[N + i], S[2 * N + i]};
@@ -253,9 +260,9 @@ void dense_destroy(DensePlan *p) {
 hipError_t dense_field(const DensePlan *p, const Grid &g, const Onsite &os, const double *S, float *b, hipStream_t st) {
     dim3 grid((unsigned)((g.Lx + kDX - 1) / kDX), (unsigned)((g.Ly + kDY - 1) / kDY), (unsigned)((g.Lz + kDZ - 1) / kDZ));
     if (p->bf16)
-        k_dense_mfma<true><<<grid, 256, 0, st>>>(S, b, (const s16x8 *)p->d_frag, p->kscale, p->in_scale, g, os);
+        k_dense_mfma<true><<<grid, kThreadsD, 0, st>>>(S, b, (const s16x8 *)p->d_frag, p->kscale, p->in_scale, g, os);
     else
-        k_dense_mfma<false><<<grid, 256, 0, st>>>(S, b, (const s16x8 *)p->d_frag, p->kscale, p->in_scale, g, os);
+        k_dense_mfma<false><<<grid, kThreadsD, 0, st>>>(S, b, (const s16x8 *)p->d_frag, p->kscale, p->in_scale, g, os);
     return hipGetLastError();
 }
 
