@@ -55,9 +55,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str, heun_mode: int, zchunk: int):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
-    was taken on the current kernel source (else None)."""
+    was taken on the current kernel source, on this workload and in this
+    launch configuration (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -65,6 +66,8 @@ def measured_traffic(kernel: str):
         d = json.load(f)
     e = d.get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    if (e.get("workload"), e.get("heun_mode"), e.get("zchunk")) != (workload, heun_mode, zchunk):
         return None
     return e.get("bytes_per_launch")
 
@@ -270,7 +273,7 @@ def heun_workload(args, w):
         kname[("heun_predict", 2)] = "k_zmarch<ZM_BIL> + k_heun_pre (predictor sweep)"
         if info.heun_field == 5:
             kname[("heun_correct", 2)] = "k_zmarch<ZM_BIL> + k_heun_post (corrector sweep)"
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, w.name, info.heun_field, info.zchunk)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname.get((dom, info.stencil_engine), dom),
@@ -309,6 +312,28 @@ def heun_workload(args, w):
         "hbm_frac_step": step_bytes * w.N * args.steps / t / 1e9 / HBM_PEAK_GBS,
         "device": torch.cuda.get_device_name(0),
     }
+    if small:
+        # the same steps with direct launches instead of the captured graph
+        spx.set_heun_graph(h, False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        spx.llg_heun_step(h, S, step0=args.warmup, n_steps=args.steps, **params)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        spx.set_heun_graph(h, True)
+        out["direct_launch_ms_per_step"] = e0.elapsed_time(e1) / args.steps
+    # energy of the final state (deterministic two-level reduction)
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    spx.energy(h, S, E)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        spx.energy(h, S, E)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out["energy"] = {"ms": e0.elapsed_time(e1) / 10, "meV_per_spin": float(E.item()) / w.N}
     out["hbm_copy_GBps"] = copy_bandwidth()
     if args.calibrate_copy:
         src = torch.empty_like(S).copy_(S)
@@ -439,9 +464,28 @@ def field_workload(args, w):
            "stencil_only": {"ms": ms_st, "fields_per_s": w.N / ms_st * 1e3,
                             "GBps_algorithmic": FIELD_BYTES * w.N / ms_st / 1e6,
                             "hbm_frac": FIELD_BYTES * w.N / ms_st / 1e6 / HBM_PEAK_GBS},
-           "stencil_plus_dipolar_fft_ms": ms_dip, "dense_7cubed": dense, "cpu_baseline": cpu,
+           "stencil_plus_dipolar_fft_ms": ms_dip,
+           "dipolar": dipolar_traffic(w.L, ms_dip - ms_st),
+           "dense_7cubed": dense, "cpu_baseline": cpu,
            "hbm_copy_GBps": copy_bandwidth(), "device": torch.cuda.get_device_name(0)}
     print(json.dumps(out), flush=True)
+
+
+def dipolar_traffic(L, ms):
+    """Contract bytes of one pruned dipolar evaluation (each array read or
+    written once per pass: pad, x-row R2C, y columns, fused z pass with the
+    dipole spectrum, inverse y, C2R, crop) and the rate they imply."""
+    Lx, Ly, Lz = L
+    P = [1 << (2 * v - 1).bit_length() for v in L]
+    H = P[0] // 2 + 1
+    rows = 3 * Ly * Lz
+    R, X = rows * P[0] * 4, rows * H * 8
+    Y = 3 * Lz * P[1] * H * 8
+    kern = 6 * P[2] * P[1] * H * 4
+    N = Lx * Ly * Lz
+    total = (3 * N * 8 + R) + (R + X) + (X + Y) + (Y + kern + Y) + (Y + X) + (X + R) + (3 * N * 4 * 2)
+    return {"ms": ms, "contract_bytes": total, "GBps": total / (ms / 1e3) / 1e9,
+            "hbm_frac": total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "padded": P}
 
 
 def cpu_field_baseline(w, seconds):

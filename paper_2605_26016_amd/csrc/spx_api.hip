@@ -828,16 +828,19 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
     return SPX_OK;
 }
 
-// (Re)capture the 2-step Heun graph for state S, constants hc and stream st.
-static hipError_t heun_graph_prepare(spx_ham *h, HeunConst hc, double *S, hipStream_t st) {
+// (Re)capture the Heun graph of gsteps (even) steps for state S, constants hc
+// and stream st.  Step k of the graph draws the noise of step *d_step + k; the
+// graph's last node advances d_step by gsteps.
+static hipError_t heun_graph_prepare(spx_ham *h, HeunConst hc, double *S, int gsteps, hipStream_t st) {
     if (!h->d_step) {
         hipError_t e = hipMalloc((void **)&h->d_step, sizeof(uint64_t));
         if (e != hipSuccess) return e;
     }
     hc.step_dev = h->d_step;
-    std::vector<unsigned char> key(sizeof(HeunConst) + sizeof(void *));
+    std::vector<unsigned char> key(sizeof(HeunConst) + sizeof(void *) + sizeof(int));
     std::memcpy(key.data(), &hc, sizeof(HeunConst));
     std::memcpy(key.data() + sizeof(HeunConst), &S, sizeof(void *));
+    std::memcpy(key.data() + sizeof(HeunConst) + sizeof(void *), &gsteps, sizeof(int));
     if (h->heun_graph && key == h->graph_key) return hipSuccess;
     if (h->heun_graph) (void)hipGraphExecDestroy(h->heun_graph);
     h->heun_graph = nullptr;
@@ -851,9 +854,11 @@ static hipError_t heun_graph_prepare(spx_ham *h, HeunConst hc, double *S, hipStr
     hipGraph_t graph;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    spx_status s1 = enqueue_heun_step(h, hc, 0, S, h->d_Sp, cs);
-    spx_status s2 = s1 == SPX_OK ? enqueue_heun_step(h, hc, 1, h->d_Sp, S, cs) : s1;
-    if (s2 == SPX_OK) k_add_u64<<<1, 1, 0, cs>>>(h->d_step, 2);
+    spx_status s2 = SPX_OK;
+    for (int k = 0; k < gsteps && s2 == SPX_OK; ++k)
+        s2 = (k & 1) ? enqueue_heun_step(h, hc, (uint64_t)k, h->d_Sp, S, cs)
+                     : enqueue_heun_step(h, hc, (uint64_t)k, S, h->d_Sp, cs);
+    if (s2 == SPX_OK) k_add_u64<<<1, 1, 0, cs>>>(h->d_step, (uint64_t)gsteps);
     e = hipStreamEndCapture(cs, &graph);
     if (e != hipSuccess) return e;
     if (s2 != SPX_OK) {
@@ -952,23 +957,27 @@ spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, voi
                                            (gamma * h->mu[a] * kMuB * p->dt_fs))
                                : 0.0;
     }
-    // Graph replay: one captured 2-step graph (S -> Sp -> S) whose noise step
-    // comes from a device counter that the graph itself advances by 2.  Not
-    // used with the dipolar FFT path or while kernels are being timed.
-    int n_pairs = (h->use_graph && !h->dip && !h->timing && p->n_steps >= 4) ? p->n_steps / 2 : 0;
-    if (n_pairs > 0 && heun_graph_prepare(h, hc, S, st) != hipSuccess) {
+    // Graph replay: one captured graph of gsteps steps (S -> Sp -> ... -> S)
+    // whose noise steps come from a device counter that the graph itself
+    // advances by gsteps; 16 steps per graph keep the counter node and the
+    // graph launch off the step time of small lattices.  The remaining steps
+    // are launched directly.  Not used with the dipolar FFT path or while
+    // kernels are being timed.
+    const int gsteps = p->n_steps >= 16 ? 16 : 2;
+    int n_graphs = (h->use_graph && !h->dip && !h->timing && p->n_steps >= 4) ? p->n_steps / gsteps : 0;
+    if (n_graphs > 0 && heun_graph_prepare(h, hc, S, gsteps, st) != hipSuccess) {
         (void)hipGetLastError();  // capture unsupported: direct launches from now on
         h->use_graph = 0;
-        n_pairs = 0;
+        n_graphs = 0;
     }
-    if (n_pairs > 0) {
+    if (n_graphs > 0) {
         k_set_u64<<<1, 1, 0, st>>>(h->d_step, p->step0);
         hipError_t e = hipGetLastError();
-        for (int k = 0; k < n_pairs && e == hipSuccess; ++k) e = hipGraphLaunch(h->heun_graph, st);
+        for (int k = 0; k < n_graphs && e == hipSuccess; ++k) e = hipGraphLaunch(h->heun_graph, st);
         if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: graph replay");
     }
     double *cur = S, *nxt = h->d_Sp;
-    for (int k = 2 * n_pairs; k < p->n_steps; ++k) {
+    for (int k = gsteps * n_graphs; k < p->n_steps; ++k) {
         spx_status s = enqueue_heun_step(h, hc, p->step0 + (uint64_t)k, cur, nxt, st);
         if (s != SPX_OK) return s;
         std::swap(cur, nxt);

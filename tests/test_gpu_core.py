@@ -332,13 +332,14 @@ def test_dipolar_field_vs_numpy_fft_32():
 
 
 def test_heun_graph_replay_is_bit_identical():
-    # captured 2-step graphs with a device step counter == direct launches
+    # captured graphs (2 steps, or 16 steps and direct launches for the rest)
+    # with a device step counter == direct launches
     from paper_2605_26016_amd import spx
     import torch
     w = bcc_5shell_stochastic((10, 9, 8))
     S0 = w.initial_state()
     kw = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed)
-    for n in (10, 11):
+    for n in (10, 11, 37):
         ha = gpu_hamiltonian(w, field_prec="fp32")
         hb = gpu_hamiltonian(w, field_prec="fp32")
         spx.set_heun_graph(hb, False)
