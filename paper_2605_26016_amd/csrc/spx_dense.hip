@@ -9,8 +9,9 @@
 //   K = 16 consecutive input x' of one (beta, dy, dz) run,
 // so the x-direction band of the kernel sits in the weight operand B
 // (a 16 x 32 Toeplitz slice per run, 41 % of its MACs useful) and every input
-// value is read once per (dy, beta) row from LDS and feeds up to 4 MFMAs.  147 MFMAs (49 (dy,dz) x 3 beta) per
-// 320 output sites.  Weight fragments are built on the host in lane order.
+// value is read once per (dy, beta) row from LDS and feeds up to 4 MFMAs:
+// 147 MFMAs (49 (dy,dz) x 3 beta) per 320 output sites.  Weight fragments are
+// built on the host in lane order.
 // Operands are scaled by powers of two before rounding (exact) and the
 // product scale is undone in FP32: BF16 weights so that max|K| lies in [1,2);
 // FP16 weights so that max|K| lies in [2^12, 2^13) and spins by 2^10, which
@@ -70,20 +71,69 @@ __global__ __launch_bounds__(kThreadsD) void k_dense_mfma(const double *__restri
                                                     const s16x8 *__restrict__ wfrag, float kscale, float in_scale,
                                                     Grid g, Onsite os) {
     __shared__ __attribute__((aligned(16))) short tile[3][kIZ][kIY][kIX];
-    const int x0 = blockIdx.x * kDX, y0 = blockIdx.y * kDY, z0 = blockIdx.z * kDZ;
+    // 1-D grid of tiles, x fastest.  Workgroups are dealt to the 8 XCDs in
+    // turn; each XCD is given a contiguous range of tiles instead, so tiles
+    // that share halo planes run on the same L2.
+    int x0, y0, z0;
+    {
+        const int nbx = (g.Lx + kDX - 1) / kDX, nby = (g.Ly + kDY - 1) / kDY;
+        const int T = (int)gridDim.x, b = (int)blockIdx.x;
+        const int q = T / 8, r = T % 8, k = b % 8;
+        const int t = k * q + min(k, r) + b / 8;
+        x0 = (t % nbx) * kDX;
+        y0 = ((t / nbx) % nby) * kDY;
+        z0 = (t / (nbx * nby)) * kDZ;
+    }
     const int64_t N = g.N;
-    // stage the input tile (zero outside open faces, wrapped on periodic axes);
-    // kIX = 16 lanes per x run, so idx splits with shifts
-    for (int idx = threadIdx.x; idx < kIZ * kIY * kIX; idx += kThreadsD) {
-        const int xx = idx & (kIX - 1), yz = idx >> 4;
-        const int yy = yz % kIY, zz = yz / kIY;
+    // Stage the input tile (zero outside open faces, wrapped on periodic
+    // axes).  The wrapped coordinate of each of the kIX + kIY + kIZ input
+    // lines is computed once (-1 outside an open face).  16 consecutive
+    // lanes then read the 16 x of one input line (one cache-line run per line
+    // and component), kU elements per thread at a time, with every global
+    // load of a batch issued before the first is consumed (masked sites load
+    // site 0 and store zero), so a block waits for memory a few times rather
+    // than once per element.
+    __shared__ int lines[kIX + kIY + kIZ];
+    if (threadIdx.x < kIX + kIY + kIZ) {
+        const int t = threadIdx.x;
+        const int ax = t < kIX ? 0 : (t < kIX + kIY ? 1 : 2);
+        const int c = ax == 0 ? x0 - kR + t : (ax == 1 ? y0 - kR + (t - kIX) : z0 - kR + (t - kIX - kIY));
+        const int L = ax == 0 ? g.Lx : (ax == 1 ? g.Ly : g.Lz);
         bool ok = true;
-        const int gx = wrap_coord(x0 - kR + xx, g.Lx, g.per[0], 1, ok);
-        const int gy = wrap_coord(y0 - kR + yy, g.Ly, g.per[1], 1, ok);
-        const int gz = wrap_coord(z0 - kR + zz, g.Lz, g.per[2], 1, ok);
-        const int64_t j = gx + (int64_t)g.Lx * (gy + (int64_t)g.Ly * gz);
+        const int w = wrap_coord(c, L, g.per[ax], 1, ok);
+        lines[t] = ok ? w : -1;
+    }
+    __syncthreads();
+    {
+        constexpr int kElems = kIZ * kIY * kIX;
+        constexpr int kU = 16;
+        const int *cx = lines, *cy = lines + kIX, *cz = lines + kIX + kIY;
+#pragma unroll 1
+        for (int e0 = threadIdx.x; e0 < kElems; e0 += kU * kThreadsD) {
+            double v[kU][3];
+            unsigned okm = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) tile[c][zz][yy][xx] = to16<BF16>(ok ? (float)S[c * N + j] * in_scale : 0.0f);
+            for (int u = 0; u < kU; ++u) {
+                const int q = min(e0 + u * kThreadsD, kElems - 1);
+                const int xx = q & (kIX - 1), yz = q / kIX;
+                const int gx = cx[xx], gy = cy[yz % kIY], gz = cz[yz / kIY];
+                const bool ok = (gx | gy | gz) >= 0;
+                okm |= (ok ? 1u : 0u) << u;
+                const int64_t j = ok ? gx + (int64_t)g.Lx * (gy + (int64_t)g.Ly * gz) : 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[u][c] = S[c * N + j];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int q = e0 + u * kThreadsD;
+                if (q >= kElems) break;
+                const int xx = q & (kIX - 1), yz = q / kIX;
+                const int yy = yz % kIY, zz = yz / kIY;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    tile[c][zz][yy][xx] = to16<BF16>((okm >> u) & 1u ? (float)v[u][c] * in_scale : 0.0f);
+            }
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -96,17 +146,19 @@ __global__ __launch_bounds__(kThreadsD) void k_dense_mfma(const double *__restri
     // fragments of a row and streams the kPW + 6 input planes it touches:
     // every A operand read from LDS feeds up to kPW MFMAs (one per output
     // plane p, with dz = plane - p) and every weight fragment kPW MFMAs.
-    // The next row's weights are loaded while the current row computes.
+    // The weights of the next row are loaded while the current row computes,
+    // into a second register set: rows alternate between the sets wA and wB,
+    // so no register copy (which would wait for the loads in flight) sits
+    // between a load and the row that consumes it.
     auto run_of = [](int dyb, int dz) { return (dyb % 3) + 3 * ((dyb / 3) + 7 * dz); };
-    s16x8 bw[7], bn[7];
+    // (the scheduling barrier keeps the loads ahead of the row they overlap:
+    // occupancy is set by LDS, so the registers they hold cost nothing)
+    auto load_row = [&](s16x8 (&w)[7], int dyb) {
 #pragma unroll
-    for (int dz = 0; dz < 7; ++dz) bw[dz] = wfrag[run_of(0, dz) * 64 + lane];
-#pragma unroll 1
-    for (int dyb = 0; dyb < 21; ++dyb) {
-        if (dyb + 1 < 21) {
-#pragma unroll
-            for (int dz = 0; dz < 7; ++dz) bn[dz] = wfrag[run_of(dyb + 1, dz) * 64 + lane];
-        }
+        for (int dz = 0; dz < 7; ++dz) w[dz] = wfrag[run_of(dyb, dz) * 64 + lane];
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto mfma_row = [&](const s16x8 (&w)[7], int dyb) {
         const int beta = dyb % 3, dy = dyb / 3 - kR;
 #pragma unroll
         for (int zi = 0; zi < kPW + 2 * kR; ++zi) {
@@ -114,12 +166,20 @@ __global__ __launch_bounds__(kThreadsD) void k_dense_mfma(const double *__restri
 #pragma unroll
             for (int p = 0; p < kPW; ++p) {
                 const int dz = zi - p;  // 0..6  <->  offset dz - kR
-                if (dz >= 0 && dz < 7) acc[p] = mfma32<BF16>(a, bw[dz], acc[p]);
+                if (dz >= 0 && dz < 7) acc[p] = mfma32<BF16>(a, w[dz], acc[p]);
             }
         }
-#pragma unroll
-        for (int dz = 0; dz < 7; ++dz) bw[dz] = bn[dz];
+    };
+    s16x8 wA[7], wB[7];
+    load_row(wA, 0);
+#pragma unroll 1
+    for (int dyb = 0; dyb < 20; dyb += 2) {
+        load_row(wB, dyb + 1);
+        mfma_row(wA, dyb);
+        load_row(wA, dyb + 2);
+        mfma_row(wB, dyb + 1);
     }
+    mfma_row(wA, 20);
     // epilogue: column -> (component, x), row -> y; on-site terms in FP64
     const int col = lane & 31;
     if (col >= 3 * kDX) return;
@@ -258,7 +318,8 @@ void dense_destroy(DensePlan *p) {
 }
 
 hipError_t dense_field(const DensePlan *p, const Grid &g, const Onsite &os, const double *S, float *b, hipStream_t st) {
-    dim3 grid((unsigned)((g.Lx + kDX - 1) / kDX), (unsigned)((g.Ly + kDY - 1) / kDY), (unsigned)((g.Lz + kDZ - 1) / kDZ));
+    const unsigned grid =
+        (unsigned)((g.Lx + kDX - 1) / kDX) * (unsigned)((g.Ly + kDY - 1) / kDY) * (unsigned)((g.Lz + kDZ - 1) / kDZ);
     if (p->bf16)
         k_dense_mfma<true><<<grid, kThreadsD, 0, st>>>(S, b, (const s16x8 *)p->d_frag, p->kscale, p->in_scale, g, os);
     else
