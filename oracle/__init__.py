@@ -79,8 +79,10 @@ def lib():
         L.or_gneb_iterate.argtypes = [C.c_int, _ip, _ip, _dp, _dp, C.c_int, _ip, _ip, _ip, _dp,
                                       C.c_int, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp, C.c_double,
                                       C.c_double, C.c_double, C.c_int, C.c_double,
-                                      C.POINTER(C.c_int), _dp, _dp, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int), C.c_void_p, _dp, _dp, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int)]
+        L.or_reparametrize.restype = None
+        L.or_reparametrize.argtypes = [C.c_long, C.c_int, _dp, C.c_void_p, _dp]
         L.or_net_nparams.restype = C.c_long
         L.or_net_nparams.argtypes = [_ip]
         L.or_net_forward.restype = None
@@ -270,15 +272,27 @@ def geodesic_path(SA, SB, n_img):
     return out
 
 
-class GnebState:
-    """Images, velocities and the climbing-image switch of one GNEB path."""
+def reparametrize(Y, alpha=None):
+    """The path Y [n_img][3][N] moved along the geodesic reaction coordinate to
+    the arc-length fractions alpha (None: equal spacing); end images kept."""
+    Y = _f64(Y)
+    out = np.zeros_like(Y)
+    a = None if alpha is None else _f64(alpha)
+    lib().or_reparametrize(Y.shape[-1], Y.shape[0], Y, _ptr(a), out)
+    return out
 
-    def __init__(self, images, k_spring=1.0, dt=0.1, mass=1.0, ci_mode=1, ci_on_below=1e-2):
+
+class GnebState:
+    """Images, velocities and the climbing-image switch of one GNEB path
+    (ci_mode 4: string method with target arc-length fractions alpha)."""
+
+    def __init__(self, images, k_spring=1.0, dt=0.1, mass=1.0, ci_mode=1, ci_on_below=1e-2, alpha=None):
         self.Y = _f64(images).copy()
         self.V = np.zeros_like(self.Y)
         self.k, self.dt, self.mass = k_spring, dt, mass
         self.ci_mode, self.ci_on_below = ci_mode, ci_on_below
         self.ci_on = C.c_int(0)
+        self.alpha = None if alpha is None else _f64(alpha)
 
 
 def gneb_iterate(model: Model, st: GnebState):
@@ -291,7 +305,8 @@ def gneb_iterate(model: Model, st: GnebState):
     ci = C.c_int(-1)
     args = model._args()[:-1]
     lib().or_gneb_iterate(*args, n_img, st.Y, st.V, st.k, st.dt, st.mass, st.ci_mode,
-                          st.ci_on_below, C.byref(st.ci_on), E, dist, C.byref(mf), C.byref(ci))
+                          st.ci_on_below, C.byref(st.ci_on), _ptr(st.alpha), E, dist, C.byref(mf),
+                          C.byref(ci))
     return E, dist[:n_img - 1], mf.value, ci.value
 
 

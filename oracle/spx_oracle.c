@@ -693,14 +693,41 @@ double or_image_distance(long N, const double *A, const double *B) {
 }
 
 /*
- * Geodesic initial path: image n of n_img lies at t = n/(n_img-1) on the great
- * circle from S_A to S_B, spin by spin:  S(t) = cos(t w) S_A + sin(t w) e,
- * e = unit tangent of S_B at S_A, w = angle(S_A, S_B).  If the tangent part
- * |S_B - (S_A.S_B) S_A| is below 1e-10 the spins are parallel (S(t) = S_A) or
- * antiparallel; for antiparallel spins the path is the rotation by w = pi about
- * the axis k = normalize(S_A x e_k), e_k the Cartesian axis least aligned with
- * S_A (first such axis on ties), so e = k x S_A.
+ * Point at fraction t of the great-circle arc from a to b (unit vectors):
+ * cos(t w) a + sin(t w) e, e = unit tangent of b at a, w = angle(a, b).  If
+ * the tangent part |b - (a.b) a| is below 1e-10 the spins are parallel (the
+ * point is a) or antiparallel; for antiparallel spins the arc is the rotation
+ * by w = pi about the axis k = normalize(a x e_k), e_k the Cartesian axis
+ * least aligned with a (first such axis on ties), so e = k x a.
  */
+static void or_geodesic_point(const double a[3], const double b[3], double t, double p[3]) {
+    double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    double w3[3] = {b[0] - dot * a[0], b[1] - dot * a[1], b[2] - dot * a[2]};
+    double wn = or_norm3(w3);
+    double e[3], ang;
+    if (wn < 1e-10) {
+        if (dot > 0) { p[0] = a[0]; p[1] = a[1]; p[2] = a[2]; return; }
+        int k = 0;
+        double best = fabs(a[0]);
+        if (fabs(a[1]) < best) { best = fabs(a[1]); k = 1; }
+        if (fabs(a[2]) < best) { best = fabs(a[2]); k = 2; }
+        double ek[3] = {0, 0, 0};
+        ek[k] = 1.0;
+        double ax[3];
+        or_cross(a, ek, ax);
+        or_normalise(ax);
+        or_cross(ax, a, e); /* rotation of a about ax by +90 degrees */
+        ang = M_PI;
+    } else {
+        for (int c = 0; c < 3; ++c) e[c] = w3[c] / wn;
+        ang = atan2(wn, dot);
+    }
+    for (int c = 0; c < 3; ++c) p[c] = cos(t * ang) * a[c] + sin(t * ang) * e[c];
+    or_normalise(p);
+}
+
+/* Geodesic initial path: image n of n_img lies at t = n/(n_img-1) on every
+   spin's great circle from S_A to S_B (or_geodesic_point). */
 void or_geodesic_path(long N, const double *SA, const double *SB, int n_img, double *out) {
     for (int n = 0; n < n_img; ++n) {
         double t = (n_img > 1) ? (double)n / (double)(n_img - 1) : 0.0;
@@ -708,33 +735,55 @@ void or_geodesic_path(long N, const double *SA, const double *SB, int n_img, dou
         for (long i = 0; i < N; ++i) {
             double a[3] = {SA[i], SA[N + i], SA[2 * N + i]};
             double b[3] = {SB[i], SB[N + i], SB[2 * N + i]};
-            double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-            double w3[3] = {b[0] - dot * a[0], b[1] - dot * a[1], b[2] - dot * a[2]};
-            double wn = or_norm3(w3);
-            double e[3], ang;
-            if (wn < 1e-10) {
-                if (dot > 0) { Y[i] = a[0]; Y[N + i] = a[1]; Y[2 * N + i] = a[2]; continue; }
-                int k = 0;
-                double best = fabs(a[0]);
-                if (fabs(a[1]) < best) { best = fabs(a[1]); k = 1; }
-                if (fabs(a[2]) < best) { best = fabs(a[2]); k = 2; }
-                double ek[3] = {0, 0, 0};
-                ek[k] = 1.0;
-                double ax[3];
-                or_cross(a, ek, ax);
-                or_normalise(ax);
-                or_cross(ax, a, e); /* rotation of a about ax by +90 degrees */
-                ang = M_PI;
-            } else {
-                for (int c = 0; c < 3; ++c) e[c] = w3[c] / wn;
-                ang = atan2(wn, dot);
-            }
             double p[3];
-            for (int c = 0; c < 3; ++c) p[c] = cos(t * ang) * a[c] + sin(t * ang) * e[c];
-            or_normalise(p);
+            or_geodesic_point(a, b, t, p);
             Y[i] = p[0]; Y[N + i] = p[1]; Y[2 * N + i] = p[2];
         }
     }
+}
+
+/*
+ * Reparameterisation along the geodesic reaction coordinate (Methods,
+ * minimum-energy paths: the string method's second step, and image
+ * redistribution).  The reaction coordinate of image n is the arc length
+ * s_n = sum_{m<n} d(Y_m, Y_m+1) with the geodesic image distance.  Image n of
+ * the new path sits at s*_n = alpha_n s_{n_img-1} (alpha NULL: alpha_n =
+ * n/(n_img-1), equal spacing): with k the last image with s_k <= s*_n (k <=
+ * n_img-2) and f = (s*_n - s_k)/(s_k+1 - s_k) (0 if that gap is 0), every spin
+ * of the new image is the point at fraction f of the great-circle arc from its
+ * value in Y_k to its value in Y_k+1.  The end images are kept.  in and out
+ * must not overlap.
+ */
+void or_reparametrize(long N, int n_img, const double *in, const double *alpha, double *out) {
+    const long img = 3 * N;
+    double *s = (double *)malloc(sizeof(double) * n_img);
+    s[0] = 0.0;
+    for (int n = 0; n + 1 < n_img; ++n) s[n + 1] = s[n] + or_image_distance(N, in + n * img, in + (n + 1) * img);
+    const double total = s[n_img - 1];
+    for (int n = 0; n < n_img; ++n) {
+        double *Y = out + (long)n * img;
+        if (n == 0 || n == n_img - 1) {
+            memcpy(Y, in + (long)n * img, sizeof(double) * img);
+            continue;
+        }
+        const double a = alpha ? alpha[n] : (double)n / (double)(n_img - 1);
+        const double target = a * total;
+        int k = 0;
+        while (k + 1 < n_img - 1 && s[k + 1] <= target) ++k;
+        const double gap = s[k + 1] - s[k];
+        double f = gap > 0.0 ? (target - s[k]) / gap : 0.0;
+        if (f < 0.0) f = 0.0;
+        if (f > 1.0) f = 1.0;
+        const double *Ya = in + (long)k * img, *Yb = in + (long)(k + 1) * img;
+        for (long i = 0; i < N; ++i) {
+            double pa[3] = {Ya[i], Ya[N + i], Ya[2 * N + i]};
+            double pb[3] = {Yb[i], Yb[N + i], Yb[2 * N + i]};
+            double p[3];
+            or_geodesic_point(pa, pb, f, p);
+            Y[i] = p[0]; Y[N + i] = p[1]; Y[2 * N + i] = p[2];
+        }
+    }
+    free(s);
 }
 
 /*
@@ -749,7 +798,13 @@ void or_geodesic_path(long N, const double *SA, const double *SB, int n_img, dou
  * VP over all movable images: v <- (v.F/F.F) F if v.F > 0 else 0;
  * v += (dt/m) F;  u = P_perp(dt v);  S <- exp_S(u).
  * ci_mode: 0 never, 1 switch on once max|F_gneb| < ci_on_below, 2 always,
- * 3 static minimisation of every movable image (no tangent: F_gneb = F).
+ * 3 static minimisation of every movable image (no tangent: F_gneb = F),
+ * 4 string method (Methods, minimum-energy paths): every movable image is
+ * displaced by its projected physical force, u = dt F, S <- exp_S(u), with no
+ * spring, no climbing image and no velocity memory, and the path is then
+ * reparameterised along the geodesic reaction coordinate to the spacing alpha
+ * (or_reparametrize; NULL: equal spacing); the reported force is the part of
+ * F perpendicular to the improved tangent, F - (F.tau)tau.
  * *ci_on carries the switch between calls.  Outputs: energies E[n_img],
  * distances dist[n_img-1], max |F_gneb| per spin over movable images (before
  * the update), the climbing image index (-1 if none).
@@ -760,7 +815,8 @@ void or_gneb_iterate(int n_sub, const int *L, const int *per, const double *cell
                      const double *K_axis, const double *B3, const double *mu, int n_img,
                      double *Y /* [n_img][3][N] */, double *V /* [n_img][3][N] */,
                      double k_spring, double dt, double mass, int ci_mode, double ci_on_below,
-                     int *ci_on, double *E, double *dist, double *max_force, int *ci_index) {
+                     int *ci_on, const double *alpha, double *E, double *dist, double *max_force,
+                     int *ci_index) {
     or_lat lt;
     or_model m;
     or_lat_fill(&lt, n_sub, L, per, cell9, frac);
@@ -782,6 +838,7 @@ void or_gneb_iterate(int n_sub, const int *L, const int *per, const double *cell
             if (ci < 0 || E[n] > E[ci]) ci = n;
     }
     double *tau = (double *)malloc(sizeof(double) * img);
+    double fperp = 0.0;
     for (int n = 1; n + 1 < n_img; ++n) {
         const double *S = Y + n * img, *Sp = Y + (n + 1) * img, *Sm = Y + (n - 1) * img;
         double *Fn = F + n * img;
@@ -818,8 +875,45 @@ void or_gneb_iterate(int n_sub, const int *L, const int *per, const double *cell
         }
         double coef;
         if (n == ci) coef = -2.0 * ft;
+        else if (ci_mode == 4) coef = -ft;
         else coef = -ft + k_spring * (dist[n] - dist[n - 1]);
+        if (ci_mode == 4) {
+            /* the string step uses F itself; only its perpendicular part is reported */
+            for (long i = 0; i < N; ++i) {
+                double f2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    double fp = Fn[c * N + i] + coef * tau[c * N + i];
+                    f2 += fp * fp;
+                }
+                if (sqrt(f2) > fperp) fperp = sqrt(f2);
+            }
+            continue;
+        }
         for (long k2 = 0; k2 < img; ++k2) Fn[k2] += coef * tau[k2];
+    }
+    if (ci_mode == 4) {
+        for (int n = 1; n + 1 < n_img; ++n) {
+            double *S = Y + n * img, *Vn = V + n * img;
+            const double *Fn = F + n * img;
+            for (long i = 0; i < N; ++i) {
+                double s[3] = {S[i], S[N + i], S[2 * N + i]};
+                double u[3], o[3];
+                for (int c = 0; c < 3; ++c) {
+                    u[c] = dt * Fn[c * N + i];
+                    Vn[c * N + i] = 0.0;
+                }
+                or_expmap(s, u, o);
+                S[i] = o[0]; S[N + i] = o[1]; S[2 * N + i] = o[2];
+            }
+        }
+        double *tmp = (double *)malloc(sizeof(double) * img * n_img);
+        or_reparametrize(N, n_img, Y, alpha, tmp);
+        memcpy(Y, tmp, sizeof(double) * img * n_img);
+        free(tmp);
+        *max_force = fperp;
+        *ci_index = -1;
+        free(b); free(F); free(tau);
+        return;
     }
     /* VP projection over all movable images */
     double vf = 0.0, ff = 0.0, fmaxv = 0.0;
