@@ -241,7 +241,13 @@ spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, doub
  * < ci_on_below, 2 from the start, 3 static minimisation (Methods, static
  * optimisation: velocity projection with the exponential-map retraction):
  * no tangent, no springs, no climbing image, every movable image relaxes to a
- * local minimum on its own (the end images are not used).  An instance stops (and is frozen) once
+ * local minimum on its own (the end images are not used); 4 string method
+ * (Methods, minimum-energy paths): every movable image is displaced by its
+ * projected physical force, u = vp_dt F, S <- exp_S(u), with no spring, no
+ * climbing image and no velocity memory (vp_mass and spring_k unused), and the
+ * path is then reparameterised along the geodesic reaction coordinate to the
+ * instance's arc-length spacing (spx_gneb_redistribute); the reported max |F|
+ * is that of F - (F.tau)tau.  An instance stops (and is frozen) once
  * max |F| < tol_force (and, for ci_mode 1, the climbing image is on);
  * tol_force = 0 never stops.  Deterministic, fixed-order reductions. */
 typedef struct {
@@ -279,6 +285,26 @@ spx_status spx_gneb_step(spx_gneb *g, int32_t n_iter, void *stream);
 spx_status spx_gneb_get_stats(spx_gneb *g, int32_t inst, double *E, double *dist, double *max_force,
                               int32_t *ci_index, int32_t *ci_on, int32_t *iterations, int32_t *converged,
                               void *stream);
+/* Target spacing of instance inst for reparameterisation (Methods,
+ * minimum-energy paths: image redistribution): alpha (host double[n_img]) are
+ * the images' fractions of the path's geodesic arc length, alpha[0] = 0,
+ * alpha[n_img-1] = 1, nondecreasing; the default is equal spacing n/(n_img-1).
+ * Synchronous.  SPX_ERR_INVALID_ARG for a bad instance or profile. */
+spx_status spx_gneb_set_spacing(spx_gneb *g, int32_t inst, const double *alpha, void *stream);
+/* Geodesic reparameterisation of every instance now (Methods, minimum-energy
+ * paths: the string method's second step, image redistribution): with s_n the
+ * cumulative geodesic distance d(Y_0,Y_1) + ... + d(Y_n-1,Y_n), movable image
+ * n moves to arc length alpha_n s_last, on each spin's great-circle arc
+ * between the two images that bracket it (fraction f of the arc from the last
+ * image k <= n_img-2 with s_k <= alpha_n s_last; antiparallel spins as in
+ * spx_gneb_init_path); end images are kept and velocities cleared.  Asynchronous;
+ * on completion the caller's buffers hold the new path. */
+spx_status spx_gneb_redistribute(spx_gneb *g, void *stream);
+/* Switch every instance to ci_mode (0 .. 4) and tol_force, e.g. from the
+ * string method to climbing-image GNEB on the relaxed path.  Clears the
+ * velocities, the iteration counters, the climbing switch and the converged
+ * flags (the paths are kept).  Synchronous. */
+spx_status spx_gneb_set_mode(spx_gneb *g, int32_t ci_mode, double tol_force, void *stream);
 /* 1 (default): replay one captured hipGraph per iteration; 0: direct launches. */
 spx_status spx_gneb_set_graph(spx_gneb *g, int32_t enable);
 

@@ -14,6 +14,10 @@
 //   scalars (per instance)    c_n, VP projection v.F/F.F from image sums
 //   pass C  (movable images)  F_gneb = F + c_n tau^, VP velocity, exp-map step
 //   reduce + scalars          max |F_gneb|, CI switch, convergence, buffer flip
+// and, for string-method instances (mode 4), the geodesic reparameterisation
+//   distances (all images)    d(Y_n, Y_n+1)^2 of the displaced path
+//   brackets  (per instance)  arc-length targets, bracketing image k, fraction f
+//   interpolation             every spin of image n on the arc Y_k -> Y_k+1
 // All per-instance control state lives on the device, so an iteration needs
 // no host synchronisation and can be captured once in a hipGraph.
 #include <algorithm>
@@ -30,9 +34,11 @@ namespace {
 constexpr int kGB = 256;  // sites per item / threads per block
 
 // per-image statistics
-enum { IS_E = 0, IS_D2, IS_TT, IS_FT, IS_VT, IS_VF, IS_FF, IS_COEF, IS_TN, IS_WP, IS_WM, IS_N };
-// per-instance state
-enum { ST_PROJ = 0, ST_MAXF, ST_CI, ST_CION, ST_ITER, ST_DONE, ST_CUR, ST_N };
+enum { IS_E = 0, IS_D2, IS_TT, IS_FT, IS_VT, IS_VF, IS_FF, IS_COEF, IS_TN, IS_WP, IS_WM, IS_RD2, IS_RK, IS_RF, IS_N };
+// per-instance state (ST_RDONE: the reparameterisation has seen ST_DONE)
+enum { ST_PROJ = 0, ST_MAXF, ST_CI, ST_CION, ST_ITER, ST_DONE, ST_CUR, ST_RDONE, ST_N };
+// mode of an instance (the ci_mode parameter)
+enum { MODE_STRING = 4 };
 
 struct GInst {
     Grid g;
@@ -48,6 +54,7 @@ struct GInst {
     double *st;           // [ST_N]
     double k, dt, mass, ci_on_below, tol;
     int ci_mode;
+    const double *alpha;  // target arc-length fractions of the images [n_img]
     // bilinear field of every image from the batched z-march pass
     // ([n_img][3][N], FP64); NULL: pass A gathers the neighbours itself
     const double *Bbil;
@@ -94,6 +101,43 @@ __device__ __forceinline__ double angle3(const double a[3], const double b[3]) {
     const double c1 = a[2] * b[0] - a[0] * b[2];
     const double c2 = a[0] * b[1] - a[1] * b[0];
     return atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+}
+
+// Point at fraction t of the great-circle arc from a to b (unit vectors):
+// cos(t w) a + sin(t w) e with e the unit tangent of b at a and w the angle
+// between them.  Parallel spins (tangent part below 1e-10, a.b > 0) give a;
+// antiparallel ones rotate by pi about normalize(a x e_k), e_k the Cartesian
+// axis least aligned with a (first on ties).
+__device__ __forceinline__ void geodesic_point(const double a[3], const double b[3], double t, double p[3]) {
+    const double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    double w[3] = {b[0] - dot * a[0], b[1] - dot * a[1], b[2] - dot * a[2]};
+    const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double e[3], ang;
+    if (wn < 1e-10) {
+        if (dot > 0) {
+            for (int q = 0; q < 3; ++q) p[q] = a[q];
+            return;
+        }
+        int kx = 0;
+        double best = fabs(a[0]);
+        if (fabs(a[1]) < best) { best = fabs(a[1]); kx = 1; }
+        if (fabs(a[2]) < best) { kx = 2; }
+        double ek[3] = {0, 0, 0};
+        ek[kx] = 1.0;
+        double ax[3] = {a[1] * ek[2] - a[2] * ek[1], a[2] * ek[0] - a[0] * ek[2], a[0] * ek[1] - a[1] * ek[0]};
+        const double an = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+        for (int q = 0; q < 3; ++q) ax[q] /= an;
+        e[0] = ax[1] * a[2] - ax[2] * a[1];
+        e[1] = ax[2] * a[0] - ax[0] * a[2];
+        e[2] = ax[0] * a[1] - ax[1] * a[0];
+        ang = M_PI;
+    } else {
+        for (int q = 0; q < 3; ++q) e[q] = w[q] / wn;
+        ang = atan2(wn, dot);
+    }
+    const double cs = cos(t * ang), sn = sin(t * ang);
+    for (int q = 0; q < 3; ++q) p[q] = cs * a[q] + sn * e[q];
+    normalise3(p);
 }
 
 // ---------------------------------------------------------------- pass A
@@ -159,13 +203,23 @@ __global__ __launch_bounds__(kGB) void k_gneb_a(const GInst *__restrict__ inst, 
 
 // per-image fixed-order reduction of `nv` partial values per item into
 // img[IS_base + v]; one block per (instance, image) with a flat index
+// Gates of the reparameterisation kernels: GATE_STRING runs them for string
+// instances that have not finished, GATE_ALL for every instance (an explicit
+// redistribution); the GNEB passes use GATE_ITER (unconverged instances).
+enum { GATE_ITER = 0, GATE_STRING = 1, GATE_ALL = 2 };
+__device__ __forceinline__ bool gate_open(const GInst &G, int gate) {
+    if (gate == GATE_ALL) return true;
+    if (gate == GATE_STRING) return G.ci_mode == MODE_STRING && G.st[ST_RDONE] == 0.0;
+    return G.st[ST_DONE] == 0.0;
+}
+
 __global__ __launch_bounds__(kGB) void k_gneb_reduce(const GInst *__restrict__ inst, const int2 *__restrict__ imgs,
                                                      const double *__restrict__ partial, int nv, int base,
-                                                     int only_movable) {
+                                                     int only_movable, int gate) {
     __shared__ double red[kGB / 64];
     const int2 ii = imgs[blockIdx.x];
     const GInst &G = inst[ii.x];
-    if (G.st[ST_DONE] != 0.0) return;
+    if (!gate_open(G, gate)) return;
     if (only_movable && (ii.y == 0 || ii.y == G.n_img - 1)) return;
     const int first = G.item0 + ii.y * G.items_per_img;
     for (int v = 0; v < nv; ++v) {
@@ -276,13 +330,14 @@ __global__ void k_gneb_scalars2(const GInst *__restrict__ inst, int n_inst) {
         const double vt = tn > 0.0 ? r[IS_VT] / tn : 0.0;
         double c;
         if (n == ci) c = -2.0 * ft;
+        else if (G.ci_mode == MODE_STRING) c = -ft;  // only the reported force is projected
         else c = -ft + G.k * (sqrt(im[n * IS_N + IS_D2]) - sqrt(im[(n - 1) * IS_N + IS_D2]));
         if (!(tn > 0.0)) c = 0.0;
         r[IS_COEF] = c;
         P += r[IS_VF] + c * vt;
         Q += r[IS_FF] + 2.0 * c * ft + c * c;
     }
-    G.st[ST_PROJ] = (P > 0.0 && Q > 0.0) ? P / Q : 0.0;
+    G.st[ST_PROJ] = (G.ci_mode != MODE_STRING && P > 0.0 && Q > 0.0) ? P / Q : 0.0;
 }
 
 // ---------------------------------------------------------------- pass C
@@ -310,17 +365,22 @@ __global__ __launch_bounds__(kGB) void k_gneb_c(const GInst *__restrict__ inst, 
                 const double proj = G.st[ST_PROJ];
                 double u[3];
                 double f2 = 0.0;
+                const bool string = G.ci_mode == MODE_STRING;
                 for (int q = 0; q < 3; ++q) {
                     const double th = tn > 0.0 ? tau[q] / tn : 0.0;
                     const double ft = f[q] + c * th;
                     f2 += ft * ft;
-                    const double v = proj * ft + (G.dt / G.mass) * ft;
+                    // string method: displacement by the projected physical
+                    // force itself, no velocity memory
+                    const double v = string ? 0.0 : proj * ft + (G.dt / G.mass) * ft;
                     G.V[off + q * N + t] = v;
-                    u[q] = G.dt * v;
+                    u[q] = string ? G.dt * f[q] : G.dt * v;
                 }
                 fm = sqrt(f2);
-                const double us = u[0] * s[0] + u[1] * s[1] + u[2] * s[2];
-                for (int q = 0; q < 3; ++q) u[q] -= us * s[q];
+                if (!string) {
+                    const double us = u[0] * s[0] + u[1] * s[1] + u[2] * s[2];
+                    for (int q = 0; q < 3; ++q) u[q] -= us * s[q];
+                }
                 // exponential map cos|u| S + sin|u| u/|u|, then renormalise
                 const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
                 double o[3];
@@ -401,43 +461,7 @@ __global__ __launch_bounds__(kGB) void k_gneb_geodesic(const GInst *__restrict__
             const double *src = itm.img == 0 ? a : b;
             for (int q = 0; q < 3; ++q) p[q] = src[q];
         } else {
-            const double tt = (double)itm.img / (double)last;
-            const double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-            double w[3] = {b[0] - dot * a[0], b[1] - dot * a[1], b[2] - dot * a[2]};
-            const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-            double e[3], ang;
-            bool same = false;
-            if (wn < 1e-10) {
-                if (dot > 0) {
-                    same = true;
-                    ang = 0.0;
-                    e[0] = e[1] = e[2] = 0.0;
-                } else {
-                    int kx = 0;
-                    double best = fabs(a[0]);
-                    if (fabs(a[1]) < best) { best = fabs(a[1]); kx = 1; }
-                    if (fabs(a[2]) < best) { kx = 2; }
-                    double ek[3] = {0, 0, 0};
-                    ek[kx] = 1.0;
-                    double ax[3] = {a[1] * ek[2] - a[2] * ek[1], a[2] * ek[0] - a[0] * ek[2], a[0] * ek[1] - a[1] * ek[0]};
-                    const double an = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-                    for (int q = 0; q < 3; ++q) ax[q] /= an;
-                    e[0] = ax[1] * a[2] - ax[2] * a[1];
-                    e[1] = ax[2] * a[0] - ax[0] * a[2];
-                    e[2] = ax[0] * a[1] - ax[1] * a[0];
-                    ang = M_PI;
-                }
-            } else {
-                for (int q = 0; q < 3; ++q) e[q] = w[q] / wn;
-                ang = atan2(wn, dot);
-            }
-            if (same) {
-                for (int q = 0; q < 3; ++q) p[q] = a[q];
-            } else {
-                const double cs = cos(tt * ang), sn = sin(tt * ang);
-                for (int q = 0; q < 3; ++q) p[q] = cs * a[q] + sn * e[q];
-                normalise3(p);
-            }
+            geodesic_point(a, b, (double)itm.img / (double)last, p);
         }
         for (int q = 0; q < 3; ++q) {
             G.Y[0][off + q * N + t] = p[q];
@@ -445,6 +469,101 @@ __global__ __launch_bounds__(kGB) void k_gneb_geodesic(const GInst *__restrict__
             G.V[off + q * N + t] = 0.0;
         }
     }
+}
+
+// ------------------------------------------ geodesic reparameterisation
+// d(Y_n, Y_n+1)^2 of the current buffer, per item (image n < n_img - 1)
+__global__ __launch_bounds__(kGB) void k_gneb_rdist(const GInst *__restrict__ inst, const GItem *__restrict__ items,
+                                                    int n_items, double *__restrict__ partial, int gate) {
+    __shared__ double red[kGB / 64];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const GItem itm = items[it];
+        const GInst &G = inst[itm.inst];
+        double d2 = 0.0;
+        if (gate_open(G, gate) && itm.img < G.n_img - 1) {
+            const int64_t N = G.g.N;
+            const int64_t t = (int64_t)itm.site0 + threadIdx.x;
+            if (t < N) {
+                const double *S = G.Y[(int)G.st[ST_CUR]] + (int64_t)itm.img * 3 * N;
+                double s[3], s2[3];
+                ld3(S, N, t, s);
+                ld3(S + 3 * N, N, t, s2);
+                const double th = angle3(s, s2);
+                d2 = th * th;
+            }
+        }
+        const double ds = block_sum(d2, red);
+        if (threadIdx.x == 0) partial[it] = ds;
+    }
+}
+
+// Arc-length coordinates s_n (cumulative distances), targets alpha_n s_last,
+// and for every movable image the last image k <= n_img - 2 with s_k <=
+// target and the fraction f = (target - s_k) / (s_k+1 - s_k) in [0, 1].
+__global__ void k_gneb_rscalars(const GInst *__restrict__ inst, int n_inst, int gate) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    const GInst &G = inst[k];
+    if (!gate_open(G, gate)) return;
+    double *im = G.img;
+    const int M = G.n_img;
+    double total = 0.0;
+    for (int n = 0; n + 1 < M; ++n) total += sqrt(im[n * IS_N + IS_RD2]);
+    for (int n = 1; n + 1 < M; ++n) {
+        const double target = G.alpha[n] * total;
+        int kk = 0;
+        double sk = 0.0, gap = sqrt(im[IS_RD2]);
+        while (kk + 1 < M - 1 && sk + gap <= target) {
+            sk += gap;
+            ++kk;
+            gap = sqrt(im[kk * IS_N + IS_RD2]);
+        }
+        double f = gap > 0.0 ? (target - sk) / gap : 0.0;
+        f = fmin(fmax(f, 0.0), 1.0);
+        im[n * IS_N + IS_RK] = (double)kk;
+        im[n * IS_N + IS_RF] = f;
+    }
+}
+
+// New path into the other buffer: movable image n at fraction f of every
+// spin's arc from Y_k to Y_k+1; end images copied; velocities cleared.
+__global__ __launch_bounds__(kGB) void k_gneb_reparam(const GInst *__restrict__ inst, const GItem *__restrict__ items,
+                                                      int n_items, int gate) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const GItem itm = items[it];
+        const GInst &G = inst[itm.inst];
+        if (!gate_open(G, gate)) continue;
+        const int64_t N = G.g.N;
+        const int64_t t = (int64_t)itm.site0 + threadIdx.x;
+        if (t >= N) continue;
+        const int cur = (int)G.st[ST_CUR];
+        const int64_t off = (int64_t)itm.img * 3 * N;
+        double p[3];
+        if (itm.img == 0 || itm.img == G.n_img - 1) {
+            ld3(G.Y[cur] + off, N, t, p);
+        } else {
+            const double *im = G.img + itm.img * IS_N;
+            const int kk = (int)im[IS_RK];
+            double a[3], b[3];
+            ld3(G.Y[cur] + (int64_t)kk * 3 * N, N, t, a);
+            ld3(G.Y[cur] + (int64_t)(kk + 1) * 3 * N, N, t, b);
+            geodesic_point(a, b, im[IS_RF], p);
+        }
+        double *Yn = G.Y[cur ^ 1] + off;
+        for (int q = 0; q < 3; ++q) {
+            Yn[q * N + t] = p[q];
+            G.V[off + q * N + t] = 0.0;
+        }
+    }
+}
+
+__global__ void k_gneb_rflip(const GInst *__restrict__ inst, int n_inst, int gate) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    const GInst &G = inst[k];
+    if (!gate_open(G, gate)) return;
+    G.st[ST_CUR] = 1.0 - G.st[ST_CUR];
+    if (gate == GATE_STRING) G.st[ST_RDONE] = G.st[ST_DONE];
 }
 
 // per-instance state reset (iteration counter, CI switch, convergence)
@@ -505,6 +624,18 @@ void gneb_free(spx_gneb *g) {
     g->owned.clear();
 }
 
+// Enqueue the geodesic reparameterisation of the instances the gate admits.
+hipError_t enqueue_reparam(spx_gneb *g, int gate, hipStream_t st) {
+    const unsigned gi = grid_for(g->n_items);
+    const unsigned gs = (unsigned)((g->n_inst + 63) / 64);
+    k_gneb_rdist<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial, gate);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, IS_RD2, 0, gate);
+    k_gneb_rscalars<<<gs, 64, 0, st>>>(g->d_inst, g->n_inst, gate);
+    k_gneb_reparam<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, gate);
+    k_gneb_rflip<<<gs, 64, 0, st>>>(g->d_inst, g->n_inst, gate);
+    return hipGetLastError();
+}
+
 // Enqueue one GNEB iteration (all instances) on stream st.
 hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
     const unsigned gi = grid_for(g->n_items);
@@ -516,13 +647,19 @@ hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
         if (e != hipSuccess) return e;
     }
     k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0, GATE_ITER);
     k_gneb_scalars1<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
     k_gneb_b<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 5, IS_TT, 1);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 5, IS_TT, 1, GATE_ITER);
     k_gneb_scalars2<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
     k_gneb_c<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
     k_gneb_finish<<<g->n_inst, kGB, 0, st>>>(g->d_inst, g->d_partial);
+    bool any_string = false;
+    for (const GInst &G : g->hinst) any_string = any_string || G.ci_mode == MODE_STRING;
+    if (any_string) {
+        hipError_t e = enqueue_reparam(g, GATE_STRING, st);
+        if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
 }
 
@@ -537,7 +674,7 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
     if (!H || !images || !n_img || !p || n_inst < 1) return set_error(SPX_ERR_INVALID_ARG, "bad GNEB arguments");
     if (!(p->vp_dt > 0.0) || !(p->vp_mass > 0.0) || !(p->spring_k >= 0.0))
         return set_error(SPX_ERR_INVALID_ARG, "vp_dt, vp_mass must be > 0 and spring_k >= 0");
-    if (p->ci_mode < 0 || p->ci_mode > 3) return set_error(SPX_ERR_INVALID_ARG, "ci_mode must be 0, 1, 2 or 3");
+    if (p->ci_mode < 0 || p->ci_mode > 4) return set_error(SPX_ERR_INVALID_ARG, "ci_mode must be 0 .. 4");
     hipStream_t st = (hipStream_t)stream;
     spx_gneb *g = new spx_gneb();
     g->n_inst = n_inst;
@@ -604,6 +741,7 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         if ((s = gneb_alloc(g, (void **)&gi.F, n3 * sizeof(double), "GNEB forces")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.img, sizeof(double) * IS_N * gi.n_img, "GNEB image stats")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.st, sizeof(double) * ST_N, "GNEB state")) != SPX_OK) break;
+        if ((s = gneb_alloc(g, (void **)&gi.alpha, sizeof(double) * gi.n_img, "GNEB image spacing")) != SPX_OK) break;
         const ZPlan &zp = g->zplan[k];
         if (zp.valid) {
             if ((s = gneb_alloc(g, (void **)&gi.Bbil, n3 * sizeof(double), "GNEB bilinear field")) != SPX_OK) break;
@@ -620,7 +758,16 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         delete g;
         return s;
     }
+    // equal arc-length spacing until spx_gneb_set_spacing says otherwise
+    std::vector<std::vector<double>> alpha0(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        alpha0[k].resize(n_img[k]);
+        for (int n = 0; n < n_img[k]; ++n) alpha0[k][n] = (double)n / (double)(n_img[k] - 1);
+    }
     hipError_t e = hipMemcpyAsync(d_os, onsites.data(), sizeof(Onsite) * n_inst, hipMemcpyHostToDevice, st);
+    for (int k = 0; k < n_inst && e == hipSuccess; ++k)
+        e = hipMemcpyAsync((void *)g->hinst[k].alpha, alpha0[k].data(), sizeof(double) * n_img[k],
+                           hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(g->d_inst, g->hinst.data(), sizeof(GInst) * n_inst, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -756,6 +903,61 @@ spx_status spx_gneb_get_stats(spx_gneb *g, int32_t inst, double *E, double *dist
     if (ci_on) *ci_on = (int32_t)s[ST_CION];
     if (iterations) *iterations = (int32_t)s[ST_ITER];
     if (converged) *converged = (int32_t)s[ST_DONE];
+    return SPX_OK;
+}
+
+spx_status spx_gneb_set_spacing(spx_gneb *g, int32_t inst, const double *alpha, void *stream) {
+    if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
+    if (inst < 0 || inst >= g->n_inst) return set_error(SPX_ERR_INVALID_ARG, "instance out of range");
+    if (!alpha) return set_error(SPX_ERR_INVALID_ARG, "alpha is NULL");
+    const GInst &gi = g->hinst[inst];
+    if (alpha[0] != 0.0 || alpha[gi.n_img - 1] != 1.0)
+        return set_error(SPX_ERR_INVALID_ARG, "alpha must start at 0 and end at 1");
+    for (int n = 0; n + 1 < gi.n_img; ++n)
+        if (!(alpha[n + 1] >= alpha[n])) return set_error(SPX_ERR_INVALID_ARG, "alpha must be nondecreasing");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync((void *)gi.alpha, alpha, sizeof(double) * gi.n_img, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_hip_error(e, "spx_gneb_set_spacing");
+    return SPX_OK;
+}
+
+spx_status spx_gneb_redistribute(spx_gneb *g, void *stream) {
+    if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = enqueue_reparam(g, GATE_ALL, st);
+    if (e == hipSuccess) {
+        k_gneb_copyback<<<grid_for(g->n_items), kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items);
+        k_gneb_cur_reset<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return set_hip_error(e, "spx_gneb_redistribute");
+    return SPX_OK;
+}
+
+spx_status spx_gneb_set_mode(spx_gneb *g, int32_t ci_mode, double tol_force, void *stream) {
+    if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
+    if (ci_mode < 0 || ci_mode > 4) return set_error(SPX_ERR_INVALID_ARG, "ci_mode must be 0 .. 4");
+    if (!(tol_force >= 0.0)) return set_error(SPX_ERR_INVALID_ARG, "tol_force must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    for (GInst &gi : g->hinst) {
+        gi.ci_mode = ci_mode;
+        gi.tol = tol_force;
+    }
+    // the iteration graph depends on whether any instance runs the string method
+    if (g->graph) (void)hipGraphExecDestroy(g->graph);
+    g->graph = nullptr;
+    hipError_t e = hipMemcpyAsync(g->d_inst, g->hinst.data(), sizeof(GInst) * g->n_inst, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        k_gneb_reset<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
+        e = hipGetLastError();
+    }
+    for (int k = 0; k < g->n_inst && e == hipSuccess; ++k) {
+        const GInst &gi = g->hinst[k];
+        e = hipMemsetAsync(gi.V, 0, sizeof(double) * 3 * gi.g.N * gi.n_img, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_hip_error(e, "spx_gneb_set_mode");
     return SPX_OK;
 }
 

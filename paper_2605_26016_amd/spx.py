@@ -107,6 +107,9 @@ def load(path: str = LIB_PATH):
         "spx_gneb_step": [vp, i32, vp],
         "spx_gneb_get_stats": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "spx_gneb_set_graph": [vp, i32],
+        "spx_gneb_set_spacing": [vp, i32, vp, vp],
+        "spx_gneb_redistribute": [vp, vp],
+        "spx_gneb_set_mode": [vp, i32, dbl, vp],
         "spx_mfma_probe": [i32, vp, vp, vp, vp],
         "spx_get_kernel_times": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
@@ -384,6 +387,23 @@ def gneb_init_path(g, method=0, net=None, params=None, stream=None):
 
 def gneb_step(g, n_iter=1, stream=None):
     _check(load().spx_gneb_step(g.handle, int(n_iter), _stream(stream)), "spx_gneb_step")
+
+
+def gneb_set_spacing(g, inst, alpha, stream=None):
+    """Target arc-length fractions of instance `inst` (alpha[0] = 0, alpha[-1] = 1)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    _check(load().spx_gneb_set_spacing(g.handle, int(inst), a.ctypes.data_as(C.c_void_p), _stream(stream)),
+           "spx_gneb_set_spacing")
+
+
+def gneb_redistribute(g, stream=None):
+    """Geodesic reparameterisation of every instance to its target spacing."""
+    _check(load().spx_gneb_redistribute(g.handle, _stream(stream)), "spx_gneb_redistribute")
+
+
+def gneb_set_mode(g, ci_mode, tol_force=0.0, stream=None):
+    """Switch every instance to ci_mode (0 .. 4) and tol_force; the paths are kept."""
+    _check(load().spx_gneb_set_mode(g.handle, int(ci_mode), float(tol_force), _stream(stream)), "spx_gneb_set_mode")
 
 
 def gneb_set_graph(g, enable=True):
