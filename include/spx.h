@@ -300,11 +300,11 @@ spx_status spx_gneb_set_spacing(spx_gneb *g, int32_t inst, const double *alpha, 
  * spx_gneb_init_path); end images are kept and velocities cleared.  Asynchronous;
  * on completion the caller's buffers hold the new path. */
 spx_status spx_gneb_redistribute(spx_gneb *g, void *stream);
-/* Switch every instance to ci_mode (0 .. 4) and tol_force, e.g. from the
- * string method to climbing-image GNEB on the relaxed path.  Clears the
- * velocities, the iteration counters, the climbing switch and the converged
- * flags (the paths are kept).  Synchronous. */
-spx_status spx_gneb_set_mode(spx_gneb *g, int32_t ci_mode, double tol_force, void *stream);
+/* New parameters for every instance (same rules as spx_gneb_create), e.g.
+ * from the string method to climbing-image GNEB on the relaxed path.  Clears
+ * the velocities, the iteration counters, the climbing switch and the
+ * converged flags (the paths are kept).  Synchronous. */
+spx_status spx_gneb_set_params(spx_gneb *g, const spx_gneb_params *p, void *stream);
 /* 1 (default): replay one captured hipGraph per iteration; 0: direct launches. */
 spx_status spx_gneb_set_graph(spx_gneb *g, int32_t enable);
 

@@ -935,14 +935,20 @@ spx_status spx_gneb_redistribute(spx_gneb *g, void *stream) {
     return SPX_OK;
 }
 
-spx_status spx_gneb_set_mode(spx_gneb *g, int32_t ci_mode, double tol_force, void *stream) {
+spx_status spx_gneb_set_params(spx_gneb *g, const spx_gneb_params *p, void *stream) {
     if (!handle_alive(g)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_gneb handle");
-    if (ci_mode < 0 || ci_mode > 4) return set_error(SPX_ERR_INVALID_ARG, "ci_mode must be 0 .. 4");
-    if (!(tol_force >= 0.0)) return set_error(SPX_ERR_INVALID_ARG, "tol_force must be >= 0");
+    if (!p) return set_error(SPX_ERR_INVALID_ARG, "params is NULL");
+    if (!(p->vp_dt > 0.0) || !(p->vp_mass > 0.0) || !(p->spring_k >= 0.0) || !(p->tol_force >= 0.0))
+        return set_error(SPX_ERR_INVALID_ARG, "vp_dt, vp_mass must be > 0; spring_k, tol_force >= 0");
+    if (p->ci_mode < 0 || p->ci_mode > 4) return set_error(SPX_ERR_INVALID_ARG, "ci_mode must be 0 .. 4");
     hipStream_t st = (hipStream_t)stream;
     for (GInst &gi : g->hinst) {
-        gi.ci_mode = ci_mode;
-        gi.tol = tol_force;
+        gi.k = p->spring_k;
+        gi.dt = p->vp_dt;
+        gi.mass = p->vp_mass;
+        gi.ci_mode = p->ci_mode;
+        gi.ci_on_below = p->ci_on_below;
+        gi.tol = p->tol_force;
     }
     // the iteration graph depends on whether any instance runs the string method
     if (g->graph) (void)hipGraphExecDestroy(g->graph);
@@ -957,7 +963,7 @@ spx_status spx_gneb_set_mode(spx_gneb *g, int32_t ci_mode, double tol_force, voi
         e = hipMemsetAsync(gi.V, 0, sizeof(double) * 3 * gi.g.N * gi.n_img, st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return set_hip_error(e, "spx_gneb_set_mode");
+    if (e != hipSuccess) return set_hip_error(e, "spx_gneb_set_params");
     return SPX_OK;
 }
 

@@ -109,7 +109,7 @@ def load(path: str = LIB_PATH):
         "spx_gneb_set_graph": [vp, i32],
         "spx_gneb_set_spacing": [vp, i32, vp, vp],
         "spx_gneb_redistribute": [vp, vp],
-        "spx_gneb_set_mode": [vp, i32, dbl, vp],
+        "spx_gneb_set_params": [vp, C.POINTER(GnebParams), vp],
         "spx_mfma_probe": [i32, vp, vp, vp, vp],
         "spx_get_kernel_times": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
@@ -401,13 +401,24 @@ def gneb_redistribute(g, stream=None):
     _check(load().spx_gneb_redistribute(g.handle, _stream(stream)), "spx_gneb_redistribute")
 
 
-def gneb_set_mode(g, ci_mode, tol_force=0.0, stream=None):
-    """Switch every instance to ci_mode (0 .. 4) and tol_force; the paths are kept."""
-    _check(load().spx_gneb_set_mode(g.handle, int(ci_mode), float(tol_force), _stream(stream)), "spx_gneb_set_mode")
+def gneb_set_params(g, spring_k=1.0, vp_dt=0.1, vp_mass=1.0, ci_mode=1, ci_on_below=1e-2, tol_force=0.0,
+                    stream=None):
+    """New parameters for every instance (the paths are kept; velocities,
+    counters and flags are cleared)."""
+    p = GnebParams(float(spring_k), float(vp_dt), float(vp_mass), int(ci_mode), float(ci_on_below),
+                   float(tol_force))
+    _check(load().spx_gneb_set_params(g.handle, C.byref(p), _stream(stream)), "spx_gneb_set_params")
 
 
 def gneb_set_graph(g, enable=True):
     _check(load().spx_gneb_set_graph(g.handle, int(bool(enable))), "spx_gneb_set_graph")
+
+
+def gneb_destroy(g):
+    """Release the library's buffers of g now (otherwise when g is collected)."""
+    if getattr(g, "handle", None):
+        _check(load().spx_gneb_destroy(g.handle), "spx_gneb_destroy")
+        g.handle = None
 
 
 def gneb_get_stats(g, inst=0, stream=None):

@@ -133,7 +133,7 @@ def test_string_then_climbing_image_on_a_transverse_field_macrospin():
     spx.gneb_step(g, 5000)
     s = spx.gneb_get_stats(g)
     assert s["converged"] == 1 and s["iterations"] < 5000
-    spx.gneb_set_mode(g, 2, tol_force=1e-9)
+    spx.gneb_set_params(g, spring_k=1.0, vp_dt=0.2, ci_mode=2, tol_force=1e-9)
     assert spx.gneb_get_stats(g)["iterations"] == 0
     spx.gneb_step(g, 20000)
     s = spx.gneb_get_stats(g)
@@ -154,4 +154,6 @@ def test_spacing_profile_is_validated():
     with pytest.raises(spx.SpxError):
         spx.gneb_set_spacing(g, 1, np.linspace(0, 1, 5))
     with pytest.raises(spx.SpxError):
-        spx.gneb_set_mode(g, 5)
+        spx.gneb_set_params(g, ci_mode=5)
+    with pytest.raises(spx.SpxError):
+        spx.gneb_set_params(g, vp_dt=0.0)
