@@ -104,6 +104,11 @@ def cpu_baseline(w, seconds: float):
 # pass B reads S_n-1, S_n, S_n+1, F, v (120 B); pass C reads S_n-1, S_n, S_n+1,
 # F and writes v, S' (144 B).  Neighbour reuse inside an image is on chip.
 GNEB_BYTES = 336
+# string method per spin-image: pass A 72 B; pass B without velocities 96 B;
+# pass C without velocities (read S_n-1, S_n, S_n+1, F, write S') 120 B; the
+# reparameterisation's distance pass (2 images per pair) 48 B and
+# interpolation (2 images read, 1 written) 72 B
+STRING_BYTES = 72 + 96 + 120 + 48 + 72
 
 
 def gneb_workload(args):
@@ -149,6 +154,21 @@ def gneb_workload(args):
                              "unit": "GB/s", "frac": rate * GNEB_BYTES / 1e9 / HBM_PEAK_GBS, "traffic": None,
                              "kernel": "GNEB iteration (passes A, B, C + reductions)",
                              "bytes_per_spin_image_iteration": GNEB_BYTES}})
+    # -- the string method on the same batch: force step + geodesic reparameterisation
+    spx.gneb_set_params(g, vp_dt=0.01, ci_mode=4, tol_force=0.0)
+    spx.gneb_step(g, 3)
+    torch.cuda.synchronize()
+    e0.record()
+    spx.gneb_step(g, n_it)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1)
+    rate_s = spin_images * n_it / (ms_s / 1e3)
+    out["string_method"] = {"ms_per_iteration": ms_s / n_it, "spin_image_iterations_per_s": rate_s,
+                            "bytes_per_spin_image_iteration": STRING_BYTES,
+                            "GBps_algorithmic": rate_s * STRING_BYTES / 1e9,
+                            "hbm_frac": rate_s * STRING_BYTES / 1e9 / HBM_PEAK_GBS}
+    log(f"[bench] string method: {rate_s:.3e} spin-image-iterations/s ({ms_s / n_it:.2f} ms per iteration)")
     out["config"] = {"workload": "sc_frustrated_gneb", "lattices": [list((L, L, L)) for L in sizes], "images": 32,
                      "spin_images": spin_images, "shells_throughput": [1.0, -0.164, -0.082],
                      "parallelism": "single GPU, ragged batch in one launch per pass"}

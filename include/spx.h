@@ -224,7 +224,7 @@ spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, doub
 
 /* ---- Batched geodesic nudged elastic band (Methods, minimum-energy paths) --
  * One object holds n_inst independent paths ("instances"), each with its own
- * Hamiltonian (field_prec SPX_FP64, no dipolar term) and n_img[k] >= 3 images
+ * Hamiltonian (field_prec SPX_FP64, no dipolar term) and 3 <= n_img[k] <= 4096 images
  * stored in the caller's buffer images[k] ([dev] double[n_img][3][N_k]),
  * updated in place; images 0 and n_img-1 are pinned.  Every iteration runs
  * for all unconverged instances in one set of persistent launches:

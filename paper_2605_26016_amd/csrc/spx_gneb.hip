@@ -32,9 +32,10 @@ namespace spx {
 namespace {
 
 constexpr int kGB = 256;  // sites per item / threads per block
+constexpr int kMaxImages = 4096;  // images per instance (arc-length table in LDS)
 
 // per-image statistics
-enum { IS_E = 0, IS_D2, IS_TT, IS_FT, IS_VT, IS_VF, IS_FF, IS_COEF, IS_TN, IS_WP, IS_WM, IS_RD2, IS_RK, IS_RF, IS_N };
+enum { IS_E = 0, IS_D2, IS_TT, IS_FT, IS_VT, IS_VF, IS_FF, IS_COEF, IS_TN, IS_WP, IS_WM, IS_RD2, IS_RK, IS_RF, IS_FM, IS_N };
 // per-instance state (ST_RDONE: the reparameterisation has seen ST_DONE)
 enum { ST_PROJ = 0, ST_MAXF, ST_CI, ST_CION, ST_ITER, ST_DONE, ST_CUR, ST_RDONE, ST_N };
 // mode of an instance (the ci_mode parameter)
@@ -215,7 +216,7 @@ __device__ __forceinline__ bool gate_open(const GInst &G, int gate) {
 
 __global__ __launch_bounds__(kGB) void k_gneb_reduce(const GInst *__restrict__ inst, const int2 *__restrict__ imgs,
                                                      const double *__restrict__ partial, int nv, int base,
-                                                     int only_movable, int gate) {
+                                                     int only_movable, int gate, int take_max) {
     __shared__ double red[kGB / 64];
     const int2 ii = imgs[blockIdx.x];
     const GInst &G = inst[ii.x];
@@ -224,43 +225,62 @@ __global__ __launch_bounds__(kGB) void k_gneb_reduce(const GInst *__restrict__ i
     const int first = G.item0 + ii.y * G.items_per_img;
     for (int v = 0; v < nv; ++v) {
         double s = 0.0;
-        for (int k = threadIdx.x; k < G.items_per_img; k += kGB) s += partial[(size_t)(first + k) * nv + v];
-        const double t = block_sum(s, red);
+        for (int k = threadIdx.x; k < G.items_per_img; k += kGB) {
+            const double x = partial[(size_t)(first + k) * nv + v];
+            s = take_max ? fmax(s, x) : s + x;
+        }
+        const double t = take_max ? block_max(s, red) : block_sum(s, red);
         if (threadIdx.x == 0) G.img[ii.y * IS_N + base + v] = t;
     }
 }
 
-// climbing image and tangent weights (Henkelman-Jonsson improved tangent)
-__global__ void k_gneb_scalars1(const GInst *__restrict__ inst, int n_inst) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_inst) return;
-    const GInst &G = inst[k];
+// climbing image and tangent weights (Henkelman-Jonsson improved tangent);
+// one block per instance, threads over the images
+__global__ __launch_bounds__(kGB) void k_gneb_scalars1(const GInst *__restrict__ inst) {
+    __shared__ double rv[kGB / 64];
+    __shared__ int ri[kGB / 64];
+    const GInst &G = inst[blockIdx.x];
     if (G.st[ST_DONE] != 0.0) return;
     double *im = G.img;
-    int ci = -1;
-    if (G.ci_mode == 2 || (G.ci_mode == 1 && G.st[ST_CION] != 0.0)) {
-        for (int n = 1; n + 1 < G.n_img; ++n)
-            if (ci < 0 || im[n * IS_N + IS_E] > im[ci * IS_N + IS_E]) ci = n;
-    }
-    G.st[ST_CI] = (double)ci;
-    for (int n = 1; n + 1 < G.n_img; ++n) {
-        if (G.ci_mode == 3) {  // minimisation: no tangent, so no projection and no spring
-            im[n * IS_N + IS_WP] = 0.0;
-            im[n * IS_N + IS_WM] = 0.0;
-            continue;
-        }
-        const double Ep = im[(n + 1) * IS_N + IS_E], Em = im[(n - 1) * IS_N + IS_E], E0 = im[n * IS_N + IS_E];
-        double wp, wm;
-        if (Ep > E0 && E0 > Em) { wp = 1.0; wm = 0.0; }
-        else if (Ep < E0 && E0 < Em) { wp = 0.0; wm = 1.0; }
-        else {
-            const double dmax = fmax(fabs(Ep - E0), fabs(Em - E0));
-            const double dmin = fmin(fabs(Ep - E0), fabs(Em - E0));
-            if (Ep > Em) { wp = dmax; wm = dmin; } else { wp = dmin; wm = dmax; }
+    const int M = G.n_img;
+    for (int n = 1 + (int)threadIdx.x; n < M - 1; n += kGB) {
+        double wp = 0.0, wm = 0.0;
+        if (G.ci_mode != 3) {  // minimisation: no tangent, so no projection and no spring
+            const double Ep = im[(n + 1) * IS_N + IS_E], Em = im[(n - 1) * IS_N + IS_E], E0 = im[n * IS_N + IS_E];
+            if (Ep > E0 && E0 > Em) { wp = 1.0; wm = 0.0; }
+            else if (Ep < E0 && E0 < Em) { wp = 0.0; wm = 1.0; }
+            else {
+                const double dmax = fmax(fabs(Ep - E0), fabs(Em - E0));
+                const double dmin = fmin(fabs(Ep - E0), fabs(Em - E0));
+                if (Ep > Em) { wp = dmax; wm = dmin; } else { wp = dmin; wm = dmax; }
+            }
         }
         im[n * IS_N + IS_WP] = wp;
         im[n * IS_N + IS_WM] = wm;
     }
+    // climbing image: the first movable image of highest energy
+    int ci = -1;
+    if (G.ci_mode == 2 || (G.ci_mode == 1 && G.st[ST_CION] != 0.0)) {
+        double best = 0.0;
+        for (int n = 1 + (int)threadIdx.x; n < M - 1; n += kGB) {
+            const double e = im[n * IS_N + IS_E];
+            if (ci < 0 || e > best) { best = e; ci = n; }
+        }
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_down(best, off, 64);
+            const int oi = __shfl_down(ci, off, 64);
+            if (oi >= 0 && (ci < 0 || ob > best || (ob == best && oi < ci))) { best = ob; ci = oi; }
+        }
+        if (lane == 0) { rv[w] = best; ri[w] = ci; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = 1; q < kGB / 64; ++q)
+                if (ri[q] >= 0 && (ci < 0 || rv[q] > best || (rv[q] == best && ri[q] < ci))) { best = rv[q]; ci = ri[q]; }
+        }
+    }
+    if (threadIdx.x == 0) G.st[ST_CI] = (double)ci;
 }
 
 // tangent of image n at site t (projected on the tangent plane, unnormalised)
@@ -294,7 +314,9 @@ __global__ __launch_bounds__(kGB) void k_gneb_b(const GInst *__restrict__ inst, 
                 ld3(S, N, t, s);
                 tangent_at(G, S, N, t, im[IS_WP], im[IS_WM], s, tau);
                 ld3(G.F + (int64_t)itm.img * 3 * N, N, t, f);
-                ld3(G.V + (int64_t)itm.img * 3 * N, N, t, v);
+                // (string method: the velocities stay zero and are not read)
+                if (G.ci_mode == MODE_STRING) v[0] = v[1] = v[2] = 0.0;
+                else ld3(G.V + (int64_t)itm.img * 3 * N, N, t, v);
                 for (int c = 0; c < 3; ++c) {
                     v5[0] += tau[c] * tau[c];
                     v5[1] += f[c] * tau[c];
@@ -314,15 +336,15 @@ __global__ __launch_bounds__(kGB) void k_gneb_b(const GInst *__restrict__ inst, 
 // GNEB coefficients c_n and the VP projection from the image sums:
 // F_gneb = F + c_n tau^, c_n = -2 F.tau^ on the climbing image, else
 // -F.tau^ + k (d_n - d_{n-1});  v.F_gneb and F_gneb.F_gneb follow in closed form.
-__global__ void k_gneb_scalars2(const GInst *__restrict__ inst, int n_inst) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_inst) return;
-    const GInst &G = inst[k];
+// One block per instance, threads over the images, fixed-order block sums.
+__global__ __launch_bounds__(kGB) void k_gneb_scalars2(const GInst *__restrict__ inst) {
+    __shared__ double red[kGB / 64];
+    const GInst &G = inst[blockIdx.x];
     if (G.st[ST_DONE] != 0.0) return;
     double *im = G.img;
     const int ci = (int)G.st[ST_CI];
     double P = 0.0, Q = 0.0;
-    for (int n = 1; n + 1 < G.n_img; ++n) {
+    for (int n = 1 + (int)threadIdx.x; n + 1 < G.n_img; n += kGB) {
         double *r = im + n * IS_N;
         const double tn = sqrt(r[IS_TT]);
         r[IS_TN] = tn;
@@ -337,7 +359,9 @@ __global__ void k_gneb_scalars2(const GInst *__restrict__ inst, int n_inst) {
         P += r[IS_VF] + c * vt;
         Q += r[IS_FF] + 2.0 * c * ft + c * c;
     }
-    G.st[ST_PROJ] = (G.ci_mode != MODE_STRING && P > 0.0 && Q > 0.0) ? P / Q : 0.0;
+    const double Ps = block_sum(P, red);
+    const double Qs = block_sum(Q, red);
+    if (threadIdx.x == 0) G.st[ST_PROJ] = (G.ci_mode != MODE_STRING && Ps > 0.0 && Qs > 0.0) ? Ps / Qs : 0.0;
 }
 
 // ---------------------------------------------------------------- pass C
@@ -373,7 +397,7 @@ __global__ __launch_bounds__(kGB) void k_gneb_c(const GInst *__restrict__ inst, 
                     // string method: displacement by the projected physical
                     // force itself, no velocity memory
                     const double v = string ? 0.0 : proj * ft + (G.dt / G.mass) * ft;
-                    G.V[off + q * N + t] = v;
+                    if (!string) G.V[off + q * N + t] = v;  // string method: V stays zero
                     u[q] = string ? G.dt * f[q] : G.dt * v;
                 }
                 fm = sqrt(f2);
@@ -400,15 +424,14 @@ __global__ __launch_bounds__(kGB) void k_gneb_c(const GInst *__restrict__ inst, 
     }
 }
 
-// max |F_gneb| per instance, climbing-image switch, convergence, buffer flip
-__global__ __launch_bounds__(kGB) void k_gneb_finish(const GInst *__restrict__ inst, const double *__restrict__ partial) {
+// max |F_gneb| per instance (from the per-image maxima), climbing-image
+// switch, convergence, buffer flip
+__global__ __launch_bounds__(kGB) void k_gneb_finish(const GInst *__restrict__ inst) {
     __shared__ double red[kGB / 64];
     const GInst &G = inst[blockIdx.x];
     if (G.st[ST_DONE] != 0.0) return;
-    const int first = G.item0 + G.items_per_img;               // image 1
-    const int count = (G.n_img - 2) * G.items_per_img;         // movable images
     double m = 0.0;
-    for (int k = threadIdx.x; k < count; k += kGB) m = fmax(m, partial[first + k]);
+    for (int n = 1 + (int)threadIdx.x; n + 1 < G.n_img; n += kGB) m = fmax(m, G.img[n * IS_N + IS_FM]);
     const double mx = block_max(m, red);
     if (threadIdx.x == 0) {
         G.st[ST_MAXF] = mx;
@@ -497,28 +520,30 @@ __global__ __launch_bounds__(kGB) void k_gneb_rdist(const GInst *__restrict__ in
     }
 }
 
-// Arc-length coordinates s_n (cumulative distances), targets alpha_n s_last,
-// and for every movable image the last image k <= n_img - 2 with s_k <=
-// target and the fraction f = (target - s_k) / (s_k+1 - s_k) in [0, 1].
-__global__ void k_gneb_rscalars(const GInst *__restrict__ inst, int n_inst, int gate) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_inst) return;
-    const GInst &G = inst[k];
+// Arc-length coordinates s_n (cumulative distances, summed in image order
+// in LDS), targets alpha_n s_last, and for every movable image the last image
+// k <= n_img - 2 with s_k <= target and the fraction f = (target - s_k) /
+// (s_k+1 - s_k) in [0, 1].  One block per instance, threads over the images.
+__global__ __launch_bounds__(kGB) void k_gneb_rscalars(const GInst *__restrict__ inst, int gate) {
+    __shared__ double sc[kMaxImages];
+    const GInst &G = inst[blockIdx.x];
     if (!gate_open(G, gate)) return;
     double *im = G.img;
     const int M = G.n_img;
-    double total = 0.0;
-    for (int n = 0; n + 1 < M; ++n) total += sqrt(im[n * IS_N + IS_RD2]);
-    for (int n = 1; n + 1 < M; ++n) {
+    for (int n = (int)threadIdx.x; n + 1 < M; n += kGB) sc[n + 1] = sqrt(im[n * IS_N + IS_RD2]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sc[0] = 0.0;
+        for (int n = 1; n < M; ++n) sc[n] += sc[n - 1];
+    }
+    __syncthreads();
+    const double total = sc[M - 1];
+    for (int n = 1 + (int)threadIdx.x; n + 1 < M; n += kGB) {
         const double target = G.alpha[n] * total;
         int kk = 0;
-        double sk = 0.0, gap = sqrt(im[IS_RD2]);
-        while (kk + 1 < M - 1 && sk + gap <= target) {
-            sk += gap;
-            ++kk;
-            gap = sqrt(im[kk * IS_N + IS_RD2]);
-        }
-        double f = gap > 0.0 ? (target - sk) / gap : 0.0;
+        while (kk + 1 < M - 1 && sc[kk + 1] <= target) ++kk;
+        const double gap = sc[kk + 1] - sc[kk];
+        double f = gap > 0.0 ? (target - sc[kk]) / gap : 0.0;
         f = fmin(fmax(f, 0.0), 1.0);
         im[n * IS_N + IS_RK] = (double)kk;
         im[n * IS_N + IS_RF] = f;
@@ -526,7 +551,9 @@ __global__ void k_gneb_rscalars(const GInst *__restrict__ inst, int n_inst, int 
 }
 
 // New path into the other buffer: movable image n at fraction f of every
-// spin's arc from Y_k to Y_k+1; end images copied; velocities cleared.
+// spin's arc from Y_k to Y_k+1; end images copied.  An explicit
+// redistribution clears the velocities; string-method instances never write
+// them (they stay zero from set-up or the last parameter change).
 __global__ __launch_bounds__(kGB) void k_gneb_reparam(const GInst *__restrict__ inst, const GItem *__restrict__ items,
                                                       int n_items, int gate) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -550,10 +577,9 @@ __global__ __launch_bounds__(kGB) void k_gneb_reparam(const GInst *__restrict__ 
             geodesic_point(a, b, im[IS_RF], p);
         }
         double *Yn = G.Y[cur ^ 1] + off;
-        for (int q = 0; q < 3; ++q) {
-            Yn[q * N + t] = p[q];
-            G.V[off + q * N + t] = 0.0;
-        }
+        for (int q = 0; q < 3; ++q) Yn[q * N + t] = p[q];
+        if (gate == GATE_ALL)
+            for (int q = 0; q < 3; ++q) G.V[off + q * N + t] = 0.0;
     }
 }
 
@@ -629,8 +655,8 @@ hipError_t enqueue_reparam(spx_gneb *g, int gate, hipStream_t st) {
     const unsigned gi = grid_for(g->n_items);
     const unsigned gs = (unsigned)((g->n_inst + 63) / 64);
     k_gneb_rdist<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial, gate);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, IS_RD2, 0, gate);
-    k_gneb_rscalars<<<gs, 64, 0, st>>>(g->d_inst, g->n_inst, gate);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, IS_RD2, 0, gate, 0);
+    k_gneb_rscalars<<<g->n_inst, kGB, 0, st>>>(g->d_inst, gate);
     k_gneb_reparam<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, gate);
     k_gneb_rflip<<<gs, 64, 0, st>>>(g->d_inst, g->n_inst, gate);
     return hipGetLastError();
@@ -647,13 +673,14 @@ hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
         if (e != hipSuccess) return e;
     }
     k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0, GATE_ITER);
-    k_gneb_scalars1<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0, GATE_ITER, 0);
+    k_gneb_scalars1<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
     k_gneb_b<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 5, IS_TT, 1, GATE_ITER);
-    k_gneb_scalars2<<<(g->n_inst + 63) / 64, 64, 0, st>>>(g->d_inst, g->n_inst);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 5, IS_TT, 1, GATE_ITER, 0);
+    k_gneb_scalars2<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
     k_gneb_c<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_finish<<<g->n_inst, kGB, 0, st>>>(g->d_inst, g->d_partial);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, IS_FM, 1, GATE_ITER, 1);
+    k_gneb_finish<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
     bool any_string = false;
     for (const GInst &G : g->hinst) any_string = any_string || G.ci_mode == MODE_STRING;
     if (any_string) {
@@ -693,9 +720,9 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
             delete g;
             return set_error(SPX_ERR_UNSUPPORTED, "GNEB with the dipolar term is not supported");
         }
-        if (n_img[k] < 3 || !images[k]) {
+        if (n_img[k] < 3 || n_img[k] > kMaxImages || !images[k]) {
             delete g;
-            return set_error(SPX_ERR_INVALID_ARG, "each GNEB instance needs >= 3 images and a buffer");
+            return set_error(SPX_ERR_INVALID_ARG, "each GNEB instance needs 3 .. 4096 images and a buffer");
         }
         GInst gi{};
         gi.g = v.grid;
