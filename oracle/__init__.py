@@ -81,6 +81,11 @@ def lib():
                                       C.c_double, C.c_double, C.c_int, C.c_double,
                                       C.POINTER(C.c_int), C.c_void_p, _dp, _dp, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int)]
+        L.or_mc_colouring.restype = C.c_int
+        L.or_mc_colouring.argtypes = [C.c_int, _ip, _ip, _dp, _dp, C.c_int, _ip, _ip, _ip, _dp, C.c_int, _ip]
+        L.or_mc_sweeps.restype = C.c_long
+        L.or_mc_sweeps.argtypes = model + [_dp, C.c_double, C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_int,
+                                           _ip]
         L.or_reparametrize.restype = None
         L.or_reparametrize.argtypes = [C.c_long, C.c_int, _dp, C.c_void_p, _dp]
         L.or_net_nparams.restype = C.c_long
@@ -270,6 +275,27 @@ def geodesic_path(SA, SB, n_img):
     out = np.zeros((n_img, 3, N))
     lib().or_geodesic_path(N, SA, SB, n_img, out)
     return out
+
+
+def mc_colouring(model: Model, cmax: int = 64):
+    """(C, coef) of the Monte Carlo colouring (x + ky y + kz z + o_a) mod C:
+    coef = (ky, kz, o_0 .. o_{n_sub-1}); C = 0 if none with C <= cmax."""
+    lt = model.lat
+    coef = np.zeros(2 + lt.n_sub, np.int32)
+    Cn = lib().or_mc_colouring(lt.n_sub, lt.L, lt.periodic, lt.cell, lt.frac, model.n_bonds, model.b_a,
+                               model.b_b, model.b_delta, model.b_J, int(cmax), coef)
+    return Cn, coef
+
+
+def mc_sweeps(model: Model, S, T_K, seed, sweep0=0, n_sweeps=1, method=0, colouring=None):
+    """n_sweeps heat-bath (method 0) or Metropolis (method 1) sweeps of S in
+    place; returns the number of accepted moves (-1: unsupported case)."""
+    if colouring is None:
+        colouring = mc_colouring(model)
+    Cn, coef = colouring
+    coef = _i32(coef)
+    return lib().or_mc_sweeps(*model._args(), S, float(T_K), int(seed), int(sweep0), int(n_sweeps), int(method),
+                              int(Cn), coef)
 
 
 def reparametrize(Y, alpha=None):

@@ -572,6 +572,196 @@ void or_thermal_eta(uint64_t seed, uint64_t step, uint32_t tag, long N, double *
     or_thermal_eta_at(seed, step, tag, 0, N, eta);
 }
 
+/* ---- Monte Carlo (Methods, Monte Carlo sampling) ------------------------ */
+static void or_cross(const double a[3], const double b[3], double c[3]);
+static void or_normalise(double v[3]);
+/*
+ * Colouring for parallel updates: site (x, y, z, a) gets the colour
+ * (x + ky y + kz z + o_a) mod C.  The colouring used is the smallest C >= 2,
+ * then the lexicographically smallest (ky, kz, o_1, ..., o_{n_sub-1}) with
+ * o_0 = 0 and every coefficient in [0, C), for which no two sites joined by a
+ * bond of the model share a colour (checked site by site on the lattice, with
+ * the bonds wrapped on periodic axes and dropped at open faces).  Returns C, or
+ * 0 if no colouring with C <= cmax exists; coef = (ky, kz, o_0 .. o_{n_sub-1}).
+ */
+static int or_colour_of(const or_lat *lt, long i, int C, const int *coef) {
+    const int Lx = lt->L[0], Ly = lt->L[1], Lz = lt->L[2];
+    int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), z = (int)((i / ((long)Lx * Ly)) % Lz);
+    int a = (int)(i / ((long)Lx * Ly * Lz));
+    long v = (long)x + (long)coef[0] * y + (long)coef[1] * z + coef[2 + a];
+    return (int)(((v % C) + C) % C);
+}
+
+static int or_colouring_valid(const or_lat *lt, const or_model *m, int C, const int *coef) {
+    const long N = or_nsites(lt);
+    const int Lx = lt->L[0], Ly = lt->L[1], Lz = lt->L[2];
+    for (long i = 0; i < N; ++i) {
+        int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), z = (int)((i / ((long)Lx * Ly)) % Lz);
+        int a = (int)(i / ((long)Lx * Ly * Lz));
+        int ci = or_colour_of(lt, i, C, coef);
+        for (int p = 0; p < m->n_bonds; ++p) {
+            if (m->b_a[p] != a) continue;
+            long j = or_bond_source(lt, x, y, z, m->b_b[p], m->b_delta + 3 * p);
+            if (j < 0) continue;
+            if (or_colour_of(lt, j, C, coef) == ci) return 0;
+        }
+    }
+    return 1;
+}
+
+int or_mc_colouring(int n_sub, const int *L, const int *per, const double *cell9, const double *frac,
+                    int n_bonds, const int *b_a, const int *b_b, const int *b_delta, const double *b_J,
+                    int cmax, int *coef) {
+    or_lat lt;
+    or_model m;
+    const double zero3[3] = {0, 0, 0};
+    or_lat_fill(&lt, n_sub, L, per, cell9, frac);
+    or_model_fill(&m, n_bonds, b_a, b_b, b_delta, b_J, 0, NULL, NULL, zero3, NULL, 0);
+    const int n_free = 2 + (n_sub - 1);   /* ky, kz, o_1 .. o_{n_sub-1} */
+    for (int C = 2; C <= cmax; ++C) {
+        long total = 1;
+        for (int k = 0; k < n_free; ++k) total *= C;
+        for (long t = 0; t < total; ++t) {
+            /* lexicographic order: ky most significant */
+            long r = t;
+            int digits[2 + 16];
+            for (int k = n_free - 1; k >= 0; --k) { digits[k] = (int)(r % C); r /= C; }
+            coef[0] = digits[0];
+            coef[1] = digits[1];
+            coef[2] = 0;
+            for (int a = 1; a < n_sub; ++a) coef[2 + a] = digits[1 + a];
+            if (or_colouring_valid(&lt, &m, C, coef)) return C;
+        }
+    }
+    return 0;
+}
+
+/* counter tag of the Monte Carlo random stream */
+#define OR_MC_TAG 0x4D430000u
+
+/* local energy of spin s apart from the bilinear and Zeeman part:
+   -sum_l K_l (s.n_l)^2 (Methods, on-site anisotropy) */
+static double or_aniso_energy(const or_model *m, int a, const double s[3]) {
+    double e = 0.0;
+    for (int l = 0; l < m->n_aniso; ++l) {
+        const double *n = m->K_axis + 3 * (a * m->n_aniso + l);
+        double sn = s[0] * n[0] + s[1] * n[1] + s[2] * n[2];
+        e -= m->K[a * m->n_aniso + l] * sn * sn;
+    }
+    return e;
+}
+
+/* Orthonormal frame (e1, e2) perpendicular to the unit vector e3: e1 =
+   normalize(e3 x a) with a the Cartesian axis least aligned with e3 (first on
+   ties), e2 = e3 x e1. */
+static void or_frame(const double e3[3], double e1[3], double e2[3]) {
+    int k = 0;
+    double best = fabs(e3[0]);
+    if (fabs(e3[1]) < best) { best = fabs(e3[1]); k = 1; }
+    if (fabs(e3[2]) < best) { best = fabs(e3[2]); k = 2; }
+    double ax[3] = {0, 0, 0};
+    ax[k] = 1.0;
+    or_cross(e3, ax, e1);
+    or_normalise(e1);
+    or_cross(e3, e1, e2);
+}
+
+/*
+ * Heat-bath draw (Methods, Monte Carlo sampling): S ~ exp(beta b.S) on the unit
+ * sphere.  With x = beta |b| the cosine to b has density proportional to
+ * exp(x c) on [-1, 1], sampled by inverting its distribution function,
+ * c = 1 + log1p((1 - u0) expm1(-2x)) / x (c = 2 u0 - 1 for x = 0), and the
+ * azimuth is 2 pi u1 in the frame of or_frame around b (around z for b = 0).
+ */
+static void or_heatbath_draw(const double b[3], double beta, double u0, double u1, double s[3]) {
+    double bn = or_norm3(b);
+    double x = beta * bn;
+    double c = (x > 0.0) ? 1.0 + log1p((1.0 - u0) * expm1(-2.0 * x)) / x : 2.0 * u0 - 1.0;
+    if (c > 1.0) c = 1.0;
+    if (c < -1.0) c = -1.0;
+    double e3[3] = {0.0, 0.0, 1.0};
+    if (bn > 0.0) for (int k = 0; k < 3; ++k) e3[k] = b[k] / bn;
+    double e1[3], e2[3];
+    or_frame(e3, e1, e2);
+    double st = sqrt(fmax(0.0, 1.0 - c * c));
+    double phi = 6.283185307179586 * u1;
+    double cp = cos(phi), sp = sin(phi);
+    for (int k = 0; k < 3; ++k) s[k] = c * e3[k] + st * (cp * e1[k] + sp * e2[k]);
+}
+
+/*
+ * n_sweeps Monte Carlo sweeps at temperature T_K (Methods, Monte Carlo
+ * sampling).  A sweep visits the colours 0 .. C-1 (or_mc_colouring); within a
+ * colour every site of that colour is updated once, in site order, against
+ * the local field of the other spins, b_i = sum_j J_ij S_j + mu_i mu_B B
+ * (no two sites of one colour interact, so the order inside a colour does not
+ * matter).  The random numbers of site i in sweep n are one Philox block with
+ * counter (i, tag, n) as for the thermal noise, tag OR_MC_TAG, uniforms
+ * (x + 1/2) 2^-32.
+ *   method 0, heat-bath: S_i drawn from exp(beta b_i.S) (u0, u1); the local
+ *            energy must be linear in S_i (no anisotropy).
+ *   method 1, Metropolis: trial S' uniform on the sphere (z = 2 u0 - 1,
+ *            azimuth 2 pi u1), dH = -(S' - S_i).b_i + E_ani(S') - E_ani(S_i),
+ *            accepted if u2 < exp(-beta dH).
+ * beta = 1 / (k_B T).  Returns the number of accepted moves (heat-bath: every
+ * draw), or -1 for an unsupported case (heat-bath with anisotropy, dipolar
+ * term, T <= 0).
+ */
+long or_mc_sweeps(int n_sub, const int *L, const int *per, const double *cell9, const double *frac,
+                  int n_bonds, const int *b_a, const int *b_b, const int *b_delta, const double *b_J,
+                  int n_aniso, const double *K, const double *K_axis, const double *B3, const double *mu,
+                  int dipolar, double *S, double T_K, uint64_t seed, uint64_t sweep0, int n_sweeps,
+                  int method, int C, const int *coef) {
+    or_lat lt;
+    or_model m;
+    or_lat_fill(&lt, n_sub, L, per, cell9, frac);
+    or_model_fill(&m, n_bonds, b_a, b_b, b_delta, b_J, n_aniso, K, K_axis, B3, mu, dipolar);
+    if (dipolar || !(T_K > 0.0) || (method == 0 && n_aniso > 0) || C < 2) return -1;
+    const long N = or_nsites(&lt);
+    const long per_sub = N / n_sub;
+    const double beta = 1.0 / (OR_K_B * T_K);
+    double *b = (double *)malloc(sizeof(double) * 3 * N);
+    double *bz = (double *)malloc(sizeof(double) * 3 * N);
+    or_field_zeeman(&lt, &m, bz);
+    long accepted = 0;
+    for (int n = 0; n < n_sweeps; ++n) {
+        const uint64_t sweep = sweep0 + (uint64_t)n;
+        for (int c = 0; c < C; ++c) {
+            or_field_bil(&lt, &m, S, b);
+            for (long i = 0; i < N; ++i) {
+                if (or_colour_of(&lt, i, C, coef) != c) continue;
+                double bi[3] = {b[i] + bz[i], b[N + i] + bz[N + i], b[2 * N + i] + bz[2 * N + i]};
+                double si[3] = {S[i], S[N + i], S[2 * N + i]};
+                uint32_t blk[4];
+                or_noise_block(seed, sweep, OR_MC_TAG, (uint64_t)i, blk);
+                double u0 = or_u01(blk[0]), u1 = or_u01(blk[1]), u2 = or_u01(blk[2]);
+                double sn[3];
+                if (method == 0) {
+                    or_heatbath_draw(bi, beta, u0, u1, sn);
+                    ++accepted;
+                } else {
+                    double z = 2.0 * u0 - 1.0, r = sqrt(fmax(0.0, 1.0 - z * z));
+                    double phi = 6.283185307179586 * u1;
+                    double tr[3] = {r * cos(phi), r * sin(phi), z};
+                    int a = (int)(i / per_sub);
+                    double dH = -((tr[0] - si[0]) * bi[0] + (tr[1] - si[1]) * bi[1] + (tr[2] - si[2]) * bi[2]) +
+                                or_aniso_energy(&m, a, tr) - or_aniso_energy(&m, a, si);
+                    if (u2 < exp(-beta * dH)) {
+                        sn[0] = tr[0]; sn[1] = tr[1]; sn[2] = tr[2];
+                        ++accepted;
+                    } else {
+                        sn[0] = si[0]; sn[1] = si[1]; sn[2] = si[2];
+                    }
+                }
+                S[i] = sn[0]; S[N + i] = sn[1]; S[2 * N + i] = sn[2];
+            }
+        }
+    }
+    free(b);
+    free(bz);
+    return accepted;
+}
+
 /* ---- LLG + normalised Heun (Methods, atomistic spin dynamics) ----------- */
 static void or_cross(const double a[3], const double b[3], double c[3]) {
     c[0] = a[1] * b[2] - a[2] * b[1];
