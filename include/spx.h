@@ -222,6 +222,45 @@ spx_status spx_get_info(spx_ham *h, spx_ham_info *info);
  * source b, offset delta[3], tensor J[9]. */
 spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, double *bond_J);
 
+/* ---- Monte Carlo sampling (Methods, Monte Carlo sampling) -----------------
+ * Heat-bath and Metropolis sweeps of the state S ([dev] double[3][N], in
+ * place) at temperature T, beta = 1/(k_B T), FP64 throughout.  The local field
+ * of site i is its bilinear field plus the Zeeman field, b_i = sum_j J_ij S_j
+ * + mu_i mu_B B (meV).  Sites are coloured by (x + ky y + kz z + o_a) mod C
+ * with the smallest C, then the lexicographically smallest (ky, kz, o_1 ..),
+ * for which no bond of the Hamiltonian joins two sites of one colour
+ * (spx_mc_colouring); a sweep updates the colours 0 .. C-1 in turn, all sites
+ * of a colour at once, one attempted update per spin.  Site i in sweep n draws
+ * one Philox4x32-10 block, counter (i lo, i hi ^ 0x4D430000, n lo, n hi), key
+ * (seed lo, seed hi), uniforms u_k = (x_k + 1/2) 2^-32.
+ *   method 0, heat-bath: S_i ~ exp(beta b_i.S); the cosine to b_i is
+ *     1 + log1p((1 - u0) expm1(-2x))/x, x = beta |b_i| (2 u0 - 1 for x = 0), the
+ *     azimuth 2 pi u1 around b_i in the frame e1 = normalize(b^ x e_k) (e_k the
+ *     Cartesian axis least aligned with b^), e2 = b^ x e1.  Needs a local energy
+ *     linear in the spin: SPX_ERR_UNSUPPORTED with anisotropy.
+ *   method 1, Metropolis: trial S' uniform on the sphere (z = 2 u0 - 1, azimuth
+ *     2 pi u1), dH = -(S' - S_i).b_i - sum_l K_l [(S'.n_l)^2 - (S_i.n_l)^2],
+ *     accepted if u2 < exp(-beta dH).
+ * SPX_ERR_UNSUPPORTED with the dipolar term or when no colouring with C <= 64
+ * exists; SPX_ERR_INVALID_ARG for T <= 0, n_sweeps < 0 or another method.
+ * `accepted` ([dev] uint64 or NULL) receives the number of accepted moves of
+ * the call (heat-bath: every draw).  Asynchronous. */
+typedef struct {
+    double temperature_K;
+    uint64_t seed;
+    uint64_t sweep0;     /* counter of the first sweep */
+    int32_t n_sweeps;
+    int32_t method;      /* 0 heat-bath, 1 Metropolis */
+} spx_mc_params;
+spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned long long *accepted, void *stream);
+/* The colouring used by spx_mc_sweep (searched on first use, synchronous):
+ * *n_colours = C, coef (host int32[2 + n_sub] or NULL) = (ky, kz, o_0 ..). */
+spx_status spx_mc_colouring(spx_ham *h, int32_t *n_colours, int32_t *coef);
+/* Total moment direction sum m = sum_i S_i (Methods, thermodynamic
+ * observables; reduced magnetisation m/N), m [dev] double[3], two-level
+ * fixed-order reduction.  Asynchronous. */
+spx_status spx_magnetization(spx_ham *h, const double *S, double *m, void *stream);
+
 /* ---- Batched geodesic nudged elastic band (Methods, minimum-energy paths) --
  * One object holds n_inst independent paths ("instances"), each with its own
  * Hamiltonian (field_prec SPX_FP64, no dipolar term) and 3 <= n_img[k] <= 4096 images

@@ -189,6 +189,7 @@ struct spx_ham {
     std::vector<unsigned char> graph_key;
     hipStream_t cap_stream = nullptr;  // private capture stream
     int use_graph = 1;
+    MCState *mc = nullptr;              // Monte Carlo colouring and scratch
     int tuned = 0;
     double tune_us = 0.0;
     // kernel timing: recorded (start, stop) event pairs per kind, and a pool
@@ -247,6 +248,8 @@ struct KernelTimer {
 };
 
 void free_all(spx_ham *h) {
+    if (h->mc) mc_destroy(h->mc);
+    h->mc = nullptr;
     if (h->dense) dense_destroy(h->dense);
     h->dense = nullptr;
     if (h->heun_graph) (void)hipGraphExecDestroy(h->heun_graph);
@@ -304,6 +307,7 @@ spx_status get_ham_view(spx_ham *h, HamView &v) {
     v.radius[0] = h->radius[0];
     v.radius[1] = h->radius[1];
     v.radius[2] = h->radius[2];
+    v.mc = &h->mc;
     return SPX_OK;
 }
 }  // namespace spx

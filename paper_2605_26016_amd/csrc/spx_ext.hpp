@@ -22,6 +22,9 @@ bool handle_alive(const void *p);
 void unregister_handle(const void *p);
 
 struct DipolarPlan;
+struct MCState;
+// Monte Carlo state of a Hamiltonian (spx_mc.hip): colouring and scratch.
+void mc_destroy(MCState *m);
 
 // Read-only view of a Hamiltonian handle for other subsystems.
 struct ZPlan;
@@ -34,6 +37,7 @@ struct HamView {
     const double *mu;
     DipolarPlan *dip;
     int radius[3];
+    MCState **mc;  // the handle's Monte Carlo state slot (created on first use)
 };
 spx_status get_ham_view(spx_ham *h, HamView &v);
 

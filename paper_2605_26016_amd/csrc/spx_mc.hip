@@ -1,0 +1,407 @@
+// spx_mc.hip -- heat-bath and Metropolis Monte Carlo with colour-based
+// parallel updates (Methods, Monte Carlo sampling), and the magnetisation sum
+// used by the thermodynamic observables (Methods, thermodynamic observables).
+//
+// Colouring: site (x, y, z, a) has colour (x + ky y + kz z + o_a) mod C.  The
+// host picks the smallest C >= 2, then the lexicographically smallest
+// (ky, kz, o_1 .. o_{n_sub-1}) (o_0 = 0, coefficients in [0, C)), such that no
+// bond joins two sites of one colour.  A bond (a <- b, delta) joins sites whose
+// coordinate difference along an axis is delta itself or, on a periodic
+// axis, a wrapped value of it; the set of differences the lattice realises is
+// enumerated per axis, so the test is exact for any extent.  One sweep is C
+// launches, one per colour; every site of the colour is updated in place
+// against the bilinear + Zeeman field of its neighbours, none of which is
+// being written in that launch.
+//
+// Random numbers: one Philox4x32-10 block per (site, sweep), counter
+// (i lo, i hi ^ tag, sweep lo, sweep hi), key (seed lo, seed hi), uniforms
+// (x + 1/2) 2^-32, tag kMcTag.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "spx_device.hpp"
+#include "spx_ext.hpp"
+
+namespace spx {
+
+struct MCState {
+    int C = 0;  // colours (0: not searched yet, -1: none found)
+    int ky = 0, kz = 0;
+    int o[kMaxSub] = {0};
+    unsigned long long *d_acc = nullptr;  // accepted-move counter of the last call
+    double *d_part = nullptr;             // magnetisation block partials [kMagBlocks][3]
+};
+
+void mc_destroy(MCState *m) {
+    if (!m) return;
+    if (m->d_acc) (void)hipFree(m->d_acc);
+    if (m->d_part) (void)hipFree(m->d_part);
+    delete m;
+}
+
+namespace {
+
+constexpr uint32_t kMcTag = 0x4D430000u;
+constexpr int kMcB = 256;
+constexpr int kMagBlocks = 1024;
+
+struct McColour {
+    int C, ky, kz;
+    int o[kMaxSub];
+};
+
+// Orthonormal frame (e1, e2) perpendicular to unit e3: e1 = normalize(e3 x a),
+// a the Cartesian axis least aligned with e3 (first on ties), e2 = e3 x e1.
+__device__ __forceinline__ void frame(const double e3[3], double e1[3], double e2[3]) {
+    int k = 0;
+    double best = fabs(e3[0]);
+    if (fabs(e3[1]) < best) { best = fabs(e3[1]); k = 1; }
+    if (fabs(e3[2]) < best) { k = 2; }
+    const double ax[3] = {k == 0 ? 1.0 : 0.0, k == 1 ? 1.0 : 0.0, k == 2 ? 1.0 : 0.0};
+    e1[0] = e3[1] * ax[2] - e3[2] * ax[1];
+    e1[1] = e3[2] * ax[0] - e3[0] * ax[2];
+    e1[2] = e3[0] * ax[1] - e3[1] * ax[0];
+    normalise3(e1);
+    e2[0] = e3[1] * e1[2] - e3[2] * e1[1];
+    e2[1] = e3[2] * e1[0] - e3[0] * e1[2];
+    e2[2] = e3[0] * e1[1] - e3[1] * e1[0];
+}
+
+// -sum_l K_l (s.n_l)^2
+__device__ __forceinline__ double aniso_energy(const Onsite &os, int a, const double s[3]) {
+    double e = 0.0;
+    for (int l = 0; l < os.n_aniso; ++l) {
+        const double *n = os.axis[a][l];
+        const double sn = s[0] * n[0] + s[1] * n[1] + s[2] * n[2];
+        e -= os.K[a][l] * sn * sn;
+    }
+    return e;
+}
+
+// One colour of one sweep.  Thread t covers x-slot j = t % J of row (y, z, a)
+// = t / J, J = ceil(Lx / C): the row's sites of colour c are x = x0 + C j.
+template <bool ISO, int METHOD>
+__global__ __launch_bounds__(kMcB) void k_mc_colour(double *__restrict__ S, BondTable tb, Grid g, Onsite os,
+                                                    McColour col, int c, double beta, uint64_t seed,
+                                                    uint64_t sweep, unsigned long long *__restrict__ acc) {
+    const int C = col.C;
+    const int J = (g.Lx + C - 1) / C;
+    const int64_t n_rows = (int64_t)g.Ly * g.Lz * g.n_sub;
+    const int64_t total = n_rows * J;
+    const int64_t N = g.N;
+    unsigned int accepted = 0;
+    for (int64_t t = (int64_t)blockIdx.x * kMcB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kMcB) {
+        const int j = (int)(t % J);
+        const int64_t row = t / J;
+        const int y = (int)(row % g.Ly);
+        const int z = (int)((row / g.Ly) % g.Lz);
+        const int a = (int)(row / ((int64_t)g.Ly * g.Lz));
+        int x0 = (c - col.ky * y - col.kz * z - col.o[a]) % C;
+        if (x0 < 0) x0 += C;
+        const int x = x0 + C * j;
+        if (x >= g.Lx) continue;
+        const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
+        double bl[1][3];
+        const double *const src[1] = {S};
+        bil_sum<double, ISO, 1>(tb, g, a, x, y, z, src, bl);
+        const double b[3] = {bl[0][0] + os.bz[a][0], bl[0][1] + os.bz[a][1], bl[0][2] + os.bz[a][2]};
+        uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32) ^ kMcTag;
+        uint32_t c2 = (uint32_t)sweep, c3 = (uint32_t)(sweep >> 32);
+        philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double sc = 2.3283064365386963e-10;  // 2^-32
+        const double u0 = ((double)c0 + 0.5) * sc, u1 = ((double)c1 + 0.5) * sc;
+        double sn[3];
+        if (METHOD == 0) {
+            // heat-bath: cos to b from the inverse distribution function of
+            // exp(x c) on [-1, 1], azimuth 2 pi u1 in the frame around b
+            const double bn = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+            const double xb = beta * bn;
+            double cth = xb > 0.0 ? 1.0 + log1p((1.0 - u0) * expm1(-2.0 * xb)) / xb : 2.0 * u0 - 1.0;
+            cth = fmin(fmax(cth, -1.0), 1.0);
+            double e3[3] = {0.0, 0.0, 1.0};
+            if (bn > 0.0)
+                for (int q = 0; q < 3; ++q) e3[q] = b[q] / bn;
+            double e1[3], e2[3];
+            frame(e3, e1, e2);
+            const double st = sqrt(fmax(0.0, 1.0 - cth * cth));
+            double sp, cp;
+            sincospi(2.0 * u1, &sp, &cp);
+            for (int q = 0; q < 3; ++q) sn[q] = cth * e3[q] + st * (cp * e1[q] + sp * e2[q]);
+            ++accepted;
+        } else {
+            // Metropolis: uniform trial direction, accepted if u2 < exp(-beta dH)
+            const double u2 = ((double)c2 + 0.5) * sc;
+            const double zt = 2.0 * u0 - 1.0, r = sqrt(fmax(0.0, 1.0 - zt * zt));
+            double sp, cp;
+            sincospi(2.0 * u1, &sp, &cp);
+            const double tr[3] = {r * cp, r * sp, zt};
+            double si[3];
+            si[0] = S[i];
+            si[1] = S[N + i];
+            si[2] = S[2 * N + i];
+            const double dH = -((tr[0] - si[0]) * b[0] + (tr[1] - si[1]) * b[1] + (tr[2] - si[2]) * b[2]) +
+                              aniso_energy(os, a, tr) - aniso_energy(os, a, si);
+            const bool ok = u2 < exp(-beta * dH);
+            for (int q = 0; q < 3; ++q) sn[q] = ok ? tr[q] : si[q];
+            accepted += ok ? 1u : 0u;
+        }
+        S[i] = sn[0];
+        S[N + i] = sn[1];
+        S[2 * N + i] = sn[2];
+    }
+    if (acc) {
+        // integer counts: the order of the atomic additions does not matter
+        unsigned int w = accepted;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_down(w, off, 64);
+        if ((threadIdx.x & 63) == 0 && w) atomicAdd(acc, (unsigned long long)w);
+    }
+}
+
+__global__ void k_mc_zero(unsigned long long *acc) { *acc = 0ull; }
+
+// sum_i S_i: block partials (grid-stride, fixed order), then one block
+__global__ __launch_bounds__(kMcB) void k_mag_partial(const double *__restrict__ S, int64_t N,
+                                                      double *__restrict__ part) {
+    __shared__ double red[3][kMcB / 64];
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kMcB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kMcB)
+        for (int q = 0; q < 3; ++q) m[q] += S[q * N + i];
+    for (int q = 0; q < 3; ++q) {
+        const double v = wave_sum(m[q]);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int k = 0; k < kMcB / 64; ++k) t += red[threadIdx.x][k];
+        part[blockIdx.x * 3 + threadIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kMcB) void k_mag_final(const double *__restrict__ part, int nb, double *__restrict__ m) {
+    __shared__ double red[3][kMcB / 64];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < nb; k += kMcB)
+        for (int q = 0; q < 3; ++q) v[q] += part[k * 3 + q];
+    for (int q = 0; q < 3; ++q) {
+        const double s = wave_sum(v[q]);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int k = 0; k < kMcB / 64; ++k) t += red[threadIdx.x][k];
+        m[threadIdx.x] = t;
+    }
+}
+
+// Coordinate differences that a bond offset d realises along an axis of
+// extent L: d itself where x + d stays inside, and on a periodic axis the
+// wrapped difference elsewhere.
+void realised(int d, int L, bool per, std::vector<int> &out) {
+    out.clear();
+    for (int x = 0; x < L; ++x) {
+        const int t = x + d;
+        int diff;
+        if (t >= 0 && t < L) diff = d;
+        else if (per) diff = (((t % L) + L) % L) - x;
+        else continue;
+        if (std::find(out.begin(), out.end(), diff) == out.end()) out.push_back(diff);
+    }
+}
+
+// The colouring (see the header); false if none with C <= cmax.
+bool find_colouring(const Grid &g, const std::vector<int> &ab, const std::vector<int> &dl, int cmax, McColour &out) {
+    const int nb = (int)ab.size() / 2;
+    struct Realised {
+        int a, b;
+        std::vector<int> dx, dy, dz;
+    };
+    std::vector<Realised> rb;
+    rb.reserve(nb);
+    for (int p = 0; p < nb; ++p) {
+        Realised r;
+        r.a = ab[2 * p];
+        r.b = ab[2 * p + 1];
+        realised(dl[3 * p], g.Lx, g.per[0] != 0, r.dx);
+        realised(dl[3 * p + 1], g.Ly, g.per[1] != 0, r.dy);
+        realised(dl[3 * p + 2], g.Lz, g.per[2] != 0, r.dz);
+        if (!r.dx.empty() && !r.dy.empty() && !r.dz.empty()) rb.push_back(std::move(r));
+    }
+    const int n_free = 2 + (g.n_sub - 1);
+    for (int C = 2; C <= cmax; ++C) {
+        long long total = 1;
+        for (int k = 0; k < n_free; ++k) total *= C;
+        int digits[2 + kMaxSub];
+        for (long long t = 0; t < total; ++t) {
+            long long r = t;
+            for (int k = n_free - 1; k >= 0; --k) {
+                digits[k] = (int)(r % C);
+                r /= C;
+            }
+            McColour col{};
+            col.C = C;
+            col.ky = digits[0];
+            col.kz = digits[1];
+            col.o[0] = 0;
+            for (int a = 1; a < g.n_sub; ++a) col.o[a] = digits[1 + a];
+            bool ok = true;
+            for (const Realised &r2 : rb) {
+                const int off = col.o[r2.b] - col.o[r2.a];
+                for (int dz : r2.dz) {
+                    for (int dy : r2.dy) {
+                        for (int dx : r2.dx) {
+                            const long long v = (long long)dx + (long long)col.ky * dy + (long long)col.kz * dz + off;
+                            if (((v % C) + C) % C == 0) { ok = false; break; }
+                        }
+                        if (!ok) break;
+                    }
+                    if (!ok) break;
+                }
+                if (!ok) break;
+            }
+            if (ok) {
+                out = col;
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
+// The handle's Monte Carlo state (scratch; the colouring is searched on
+// first use by mc_colouring).
+spx_status mc_state(const HamView &v, MCState **out) {
+    if (*v.mc) {
+        *out = *v.mc;
+        return SPX_OK;
+    }
+    MCState *m = new MCState();
+    if (hipMalloc((void **)&m->d_acc, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&m->d_part, sizeof(double) * 3 * kMagBlocks) != hipSuccess) {
+        (void)hipGetLastError();
+        mc_destroy(m);
+        return set_error(SPX_ERR_OUT_OF_MEMORY, "hipMalloc failed for Monte Carlo scratch");
+    }
+    *v.mc = m;
+    *out = m;
+    return SPX_OK;
+}
+
+spx_status mc_colouring(spx_ham *h, const HamView &v, MCState *m) {
+    if (m->C > 0) return SPX_OK;
+    if (m->C < 0) return set_error(SPX_ERR_UNSUPPORTED, "no colouring with at most 64 colours for this lattice");
+    spx_ham_info info;
+    spx_status s = spx_get_info(h, &info);
+    if (s != SPX_OK) return s;
+    const size_t nb = (size_t)std::max(info.n_bonds, 1);
+    std::vector<int32_t> ab(2 * nb), dl(3 * nb);
+    std::vector<double> J(9 * nb);
+    s = spx_get_bonds(h, ab.data(), dl.data(), J.data());
+    if (s != SPX_OK) return s;
+    std::vector<int> abi(ab.begin(), ab.begin() + 2 * (size_t)info.n_bonds);
+    std::vector<int> dli(dl.begin(), dl.begin() + 3 * (size_t)info.n_bonds);
+    McColour col{};
+    if (!find_colouring(v.grid, abi, dli, 64, col)) {
+        m->C = -1;
+        return set_error(SPX_ERR_UNSUPPORTED, "no colouring with at most 64 colours for this lattice");
+    }
+    m->C = col.C;
+    m->ky = col.ky;
+    m->kz = col.kz;
+    for (int a = 0; a < kMaxSub; ++a) m->o[a] = col.o[a];
+    return SPX_OK;
+}
+
+}  // namespace
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" {
+
+spx_status spx_mc_colouring(spx_ham *h, int32_t *n_colours, int32_t *coef) {
+    HamView v;
+    spx_status s = get_ham_view(h, v);
+    if (s != SPX_OK) return s;
+    if (!n_colours) return set_error(SPX_ERR_INVALID_ARG, "n_colours is NULL");
+    MCState *m = nullptr;
+    s = mc_state(v, &m);
+    if (s == SPX_OK) s = mc_colouring(h, v, m);
+    if (s != SPX_OK) return s;
+    *n_colours = m->C;
+    if (coef) {
+        coef[0] = m->ky;
+        coef[1] = m->kz;
+        for (int a = 0; a < v.grid.n_sub; ++a) coef[2 + a] = m->o[a];
+    }
+    return SPX_OK;
+}
+
+spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned long long *accepted, void *stream) {
+    HamView v;
+    spx_status s = get_ham_view(h, v);
+    if (s != SPX_OK) return s;
+    if (!S || !p) return set_error(SPX_ERR_INVALID_ARG, "S or params is NULL");
+    if (!(p->temperature_K > 0.0)) return set_error(SPX_ERR_INVALID_ARG, "temperature must be > 0");
+    if (p->n_sweeps < 0) return set_error(SPX_ERR_INVALID_ARG, "n_sweeps < 0");
+    if (p->method != 0 && p->method != 1) return set_error(SPX_ERR_INVALID_ARG, "method must be 0 or 1");
+    if (v.dip) return set_error(SPX_ERR_UNSUPPORTED, "Monte Carlo with the dipolar term is not supported");
+    if (p->method == 0 && v.onsite.n_aniso > 0)
+        return set_error(SPX_ERR_UNSUPPORTED, "heat-bath needs a local energy linear in the spin (no anisotropy)");
+    MCState *m = nullptr;
+    s = mc_state(v, &m);
+    if (s == SPX_OK) s = mc_colouring(h, v, m);
+    if (s != SPX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    McColour col{};
+    col.C = m->C;
+    col.ky = m->ky;
+    col.kz = m->kz;
+    for (int a = 0; a < kMaxSub; ++a) col.o[a] = m->o[a];
+    const double beta = 1.0 / (kKB * p->temperature_K);
+    unsigned long long *acc = accepted ? m->d_acc : nullptr;
+    if (acc) k_mc_zero<<<1, 1, 0, st>>>(acc);
+    const int64_t total = (int64_t)((v.grid.Lx + col.C - 1) / col.C) * v.grid.Ly * v.grid.Lz * v.grid.n_sub;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kMcB - 1) / kMcB, 65536));
+    const bool iso = v.tab.iso != 0;
+    for (int n = 0; n < p->n_sweeps; ++n) {
+        const uint64_t sweep = p->sweep0 + (uint64_t)n;
+        for (int c = 0; c < col.C; ++c) {
+            if (p->method == 0) {
+                if (iso) k_mc_colour<true, 0><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc);
+                else k_mc_colour<false, 0><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc);
+            } else {
+                if (iso) k_mc_colour<true, 1><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc);
+                else k_mc_colour<false, 1><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc);
+            }
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && accepted)
+        e = hipMemcpyAsync(accepted, m->d_acc, sizeof(unsigned long long), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return set_hip_error(e, "spx_mc_sweep");
+    return SPX_OK;
+}
+
+spx_status spx_magnetization(spx_ham *h, const double *S, double *m_out, void *stream) {
+    HamView v;
+    spx_status s = get_ham_view(h, v);
+    if (s != SPX_OK) return s;
+    if (!S || !m_out) return set_error(SPX_ERR_INVALID_ARG, "S or m is NULL");
+    MCState *m = nullptr;
+    s = mc_state(v, &m);
+    if (s != SPX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((v.grid.N + kMcB - 1) / kMcB, kMagBlocks));
+    k_mag_partial<<<nb, kMcB, 0, st>>>(S, v.grid.N, m->d_part);
+    k_mag_final<<<1, kMcB, 0, st>>>(m->d_part, nb, m_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(e, "spx_magnetization");
+    return SPX_OK;
+}
+
+}  // extern "C"

@@ -61,6 +61,11 @@ class GnebParams(C.Structure):
                 ("ci_mode", C.c_int32), ("ci_on_below", C.c_double), ("tol_force", C.c_double)]
 
 
+class McParams(C.Structure):
+    _fields_ = [("temperature_K", C.c_double), ("seed", C.c_uint64), ("sweep0", C.c_uint64),
+                ("n_sweeps", C.c_int32), ("method", C.c_int32)]
+
+
 class HamInfo(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_bonds", C.c_int32), ("field_prec", C.c_int32),
                 ("backend", C.c_int32), ("radius", C.c_int32 * 3), ("dipolar", C.c_int32),
@@ -107,6 +112,9 @@ def load(path: str = LIB_PATH):
         "spx_gneb_step": [vp, i32, vp],
         "spx_gneb_get_stats": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "spx_gneb_set_graph": [vp, i32],
+        "spx_mc_sweep": [vp, vp, C.POINTER(McParams), vp, vp],
+        "spx_mc_colouring": [vp, C.POINTER(C.c_int32), vp],
+        "spx_magnetization": [vp, vp, vp, vp],
         "spx_gneb_set_spacing": [vp, i32, vp, vp],
         "spx_gneb_redistribute": [vp, vp],
         "spx_gneb_set_params": [vp, C.POINTER(GnebParams), vp],
@@ -412,6 +420,30 @@ def gneb_set_params(g, spring_k=1.0, vp_dt=0.1, vp_mass=1.0, ci_mode=1, ci_on_be
 
 def gneb_set_graph(g, enable=True):
     _check(load().spx_gneb_set_graph(g.handle, int(bool(enable))), "spx_gneb_set_graph")
+
+
+MC_METHODS = {"heat_bath": 0, "metropolis": 1}
+
+
+def mc_sweep(h, S, temperature_K, seed, sweep0=0, n_sweeps=1, method="heat_bath", accepted=None, stream=None):
+    """n_sweeps heat-bath or Metropolis sweeps of the device state S in place;
+    `accepted` (device uint64 tensor of 1, optional) receives the accepted moves."""
+    m = MC_METHODS[method] if isinstance(method, str) else int(method)
+    p = McParams(float(temperature_K), int(seed), int(sweep0), int(n_sweeps), m)
+    _check(load().spx_mc_sweep(_h(h), _ptr(S), C.byref(p), _ptr(accepted), _stream(stream)), "spx_mc_sweep")
+
+
+def mc_colouring(h):
+    """(C, coef) with coef = (ky, kz, o_0 .. o_{n_sub-1})."""
+    nc = C.c_int32()
+    coef = np.zeros(2 + 8, np.int32)
+    _check(load().spx_mc_colouring(_h(h), C.byref(nc), coef.ctypes.data_as(C.c_void_p)), "spx_mc_colouring")
+    return nc.value, coef
+
+
+def magnetization(h, S, m, stream=None):
+    """m (device double tensor of 3) = sum_i S_i."""
+    _check(load().spx_magnetization(_h(h), _ptr(S), _ptr(m), _stream(stream)), "spx_magnetization")
 
 
 def gneb_destroy(g):

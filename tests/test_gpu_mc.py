@@ -1,0 +1,130 @@
+"""GPU Monte Carlo (spx_mc_sweep, spx_mc_colouring, spx_magnetization)
+against the FP64 oracle run with the same seeds and counters, plus the open
+Heisenberg chain's closed-form correlations at a size only the GPU reaches.
+
+Tolerances: colouring identical; after several sweeps the state agrees to
+1e-11 per component (both sides draw from the same Philox block in FP64; the
+library's log1p, expm1 and sincospi and the host's differ by a few ulp) and
+the accepted-move counts are equal; magnetisation 1e-12 relative; chain
+correlations within 4.5 standard errors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import gpu_hamiltonian, oracle_model, require_gpu, to_dev
+from workloads import Workload, bcc_5shell_stochastic, random_sphere
+
+pytestmark = pytest.mark.gpu
+
+K_B = 8.617333262e-2
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+CASES = {
+    "sc4": Workload(name="sc4", L=(4, 4, 4), J_shell=(1.0,), B=(0.0, 0.0, 2.0), field_prec="fp64"),
+    "sc5x4x4": Workload(name="sc5x4x4", L=(5, 4, 4), J_shell=(1.0,), field_prec="fp64"),
+    "chain": Workload(name="chain", L=(9, 1, 1), periodic=(0, 0, 0), J_shell=(1.0,), field_prec="fp64"),
+    "sc3shell_open": Workload(name="o", L=(5, 4, 3), periodic=(0, 0, 0), J_shell=(1.0, 0.5, -0.2),
+                              B=(1.0, 0.0, 0.5), field_prec="fp64"),
+    "bcc4": bcc_5shell_stochastic((4, 4, 4)),          # with uniaxial anisotropy: Metropolis only
+    "bcc6": bcc_5shell_stochastic((6, 6, 6)),
+}
+CASES["bcc4_noK"] = bcc_5shell_stochastic((4, 4, 4))
+CASES["bcc4_noK"].K = 0.0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_colouring_matches_the_oracle(name):
+    from paper_2605_26016_amd import spx
+    w = CASES[name]
+    C, coef = spx.mc_colouring(gpu_hamiltonian(w, field_prec="fp64"))
+    Co, coefo = oracle.mc_colouring(oracle_model(w))
+    assert C == Co
+    assert list(coef[:2 + w.n_sub]) == list(coefo)
+
+
+@pytest.mark.parametrize("name,method,T", [("sc4", 0, 80.0), ("sc5x4x4", 0, 40.0), ("sc3shell_open", 0, 30.0),
+                                           ("bcc4_noK", 0, 300.0), ("sc4", 1, 80.0), ("bcc4", 1, 600.0)])
+def test_sweeps_match_the_oracle(name, method, T):
+    import torch
+    from paper_2605_26016_amd import spx
+    w = CASES[name]
+    S0 = random_sphere(w.N, 17)
+    S = to_dev(S0)
+    acc = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    h = gpu_hamiltonian(w, field_prec="fp64")
+    spx.mc_sweep(h, S, T, seed=99, sweep0=5, n_sweeps=4, method=method, accepted=acc)
+    ref = S0.copy()
+    n_acc = oracle.mc_sweeps(oracle_model(w), ref, T, 99, sweep0=5, n_sweeps=4, method=method)
+    err = float(np.max(np.abs(S.cpu().numpy() - ref)))
+    assert err <= 1e-11, err
+    assert int(acc.cpu().item()) == n_acc
+    norms = np.linalg.norm(S.cpu().numpy(), axis=0)
+    assert np.max(np.abs(norms - 1.0)) < 1e-13
+
+
+def test_metropolis_with_anisotropy_matches_the_oracle():
+    import torch
+    from paper_2605_26016_amd import spx
+    w = Workload(name="a", L=(4, 4, 2), J_shell=(1.0,), K=0.7, K_axis=(0.0, 0.6, 0.8), B=(0.0, 1.0, 0.0),
+                 field_prec="fp64")
+    S0 = random_sphere(w.N, 23)
+    S = to_dev(S0)
+    acc = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    spx.mc_sweep(gpu_hamiltonian(w, field_prec="fp64"), S, 25.0, seed=5, n_sweeps=5, method="metropolis",
+                 accepted=acc)
+    ref = S0.copy()
+    n_acc = oracle.mc_sweeps(oracle_model(w), ref, 25.0, 5, n_sweeps=5, method=1)
+    assert float(np.max(np.abs(S.cpu().numpy() - ref))) <= 1e-11
+    assert int(acc.cpu().item()) == n_acc
+
+
+def test_magnetization_is_the_sum_of_spins():
+    import torch
+    from paper_2605_26016_amd import spx
+    w = Workload(name="m", L=(37, 21, 13), J_shell=(1.0,), field_prec="fp64")
+    S0 = random_sphere(w.N, 31)
+    m = torch.zeros(3, dtype=torch.float64, device="cuda")
+    spx.magnetization(gpu_hamiltonian(w, field_prec="fp64"), to_dev(S0), m)
+    ref = S0.sum(axis=1)
+    assert np.max(np.abs(m.cpu().numpy() - ref)) <= 1e-12 * w.N
+
+
+def test_open_chain_correlations_at_size():
+    # bond variables of the open classical Heisenberg chain are independent:
+    # <S_i.S_i+1> = L(beta J), <S_i.S_i+3> = L(beta J)^3
+    import torch
+    from paper_2605_26016_amd import spx
+    n, J, bj = 1 << 16, 1.0, 1.5
+    T = J / (bj * K_B)
+    w = Workload(name="chain", L=(n, 1, 1), periodic=(0, 0, 0), J_shell=(J,), field_prec="fp64")
+    h = gpu_hamiltonian(w, field_prec="fp64")
+    S = to_dev(random_sphere(n, 41))
+    spx.mc_sweep(h, S, T, seed=7, sweep0=0, n_sweeps=200)
+    c1, c3 = [], []
+    for k in range(20):
+        spx.mc_sweep(h, S, T, seed=7, sweep0=200 + 10 * k, n_sweeps=10)
+        c1.append(float((S[:, :-1] * S[:, 1:]).sum(0).mean()))
+        c3.append(float((S[:, :-3] * S[:, 3:]).sum(0).mean()))
+    L1 = 1.0 / np.tanh(bj) - 1.0 / bj
+    for c, ref in ((c1, L1), (c3, L1 ** 3)):
+        mu, se = np.mean(c), np.std(c, ddof=1) / np.sqrt(len(c))
+        assert abs(mu - ref) < 4.5 * se + 1e-4, (mu, ref, se)
+
+
+def test_refusals():
+    from paper_2605_26016_amd import spx
+    w = Workload(name="a", L=(4, 4, 4), J_shell=(1.0,), K=0.5, field_prec="fp64")
+    h = gpu_hamiltonian(w, field_prec="fp64")
+    S = to_dev(random_sphere(w.N, 1))
+    with pytest.raises(spx.SpxError):
+        spx.mc_sweep(h, S, 10.0, seed=1, method="heat_bath")
+    with pytest.raises(spx.SpxError):
+        spx.mc_sweep(h, S, 0.0, seed=1, method="metropolis")
+    with pytest.raises(spx.SpxError):
+        spx.mc_sweep(h, S, 10.0, seed=1, method=2)
