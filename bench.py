@@ -183,6 +183,84 @@ def gneb_workload(args):
     print(json.dumps(out), flush=True)
 
 
+# Monte Carlo per attempted update: the spin is read (as a neighbour) and
+# written once per sweep at the least
+MC_BYTES = 48
+MC_SHELLS = ((1.0,), (1.0, 0.3), (1.0, 0.3, 0.1), (1.0, 0.3, 0.1, 0.05), (1.0, 0.3, 0.1, 0.05, 0.02))
+
+
+def mc_workload(args):
+    """FP64 heat-bath and Metropolis Monte Carlo on sc 200^3 (Methods, Monte
+    Carlo sampling): attempted spin updates/s for 1 .. 5 exchange shells, and
+    the colour count each needs.  The headline value is heat-bath with one
+    shell."""
+    import torch
+
+    from paper_2605_26016_amd import spx
+    from workloads import random_sphere_device
+    L, T = 200, 500.0
+    N = L ** 3
+    S = random_sphere_device(N, 3)
+    n = max(1, args.steps)
+    table = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for J in MC_SHELLS:
+        h = spx.setup_hamiltonian((L, L, L), J_shell=J, field_prec="fp64", B=(0.0, 0.0, 1.0))
+        C, _ = spx.mc_colouring(h)
+        row = {"shells": len(J), "colours": C}
+        for method in ("heat_bath", "metropolis"):
+            spx.mc_sweep(h, S, T, seed=1, sweep0=0, n_sweeps=args.warmup if len(J) == 1 else 2, method=method)
+            torch.cuda.synchronize()
+            e0.record()
+            spx.mc_sweep(h, S, T, seed=1, sweep0=1000, n_sweeps=n if len(J) == 1 else max(1, n // 10),
+                         method=method)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / (n if len(J) == 1 else max(1, n // 10))
+            row[method] = {"ms_per_sweep": ms, "updates_per_s": N / (ms / 1e3)}
+        table.append(row)
+        log(f"[bench] MC {len(J)} shell(s), {C} colours: heat-bath {row['heat_bath']['updates_per_s']:.3e}, "
+            f"Metropolis {row['metropolis']['updates_per_s']:.3e} updates/s")
+        del h
+    head = table[0]["heat_bath"]
+    rate = head["updates_per_s"]
+    out = {"metric": "attempted spin updates/s (heat-bath Monte Carlo, FP64)", "value": rate,
+           "unit": "spin-updates/s", "n_gpus": 1, "steps": n, "warmup": args.warmup,
+           "ms_per_step": head["ms_per_sweep"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic (seeded random spins)",
+           "config": {"workload": "sc200_mc", "cells": [L, L, L], "spins": N, "T_K": T, "B_T": [0.0, 0.0, 1.0],
+                      "shells": [list(J) for J in MC_SHELLS], "parallelism": "single GPU"},
+           "roofline": {"bound": "hbm", "achieved": rate * MC_BYTES / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": rate * MC_BYTES / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_mc_colour (heat-bath, one shell, 2 colours)",
+                        "bytes_per_update_algorithmic": MC_BYTES},
+           "table": table}
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_mc_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_mc_baseline(seconds):
+    """The FP64 oracle's heat-bath sweeps on sc 48^3 (one shell)."""
+    import oracle
+    from tests.helpers import oracle_model
+    from workloads import Workload, random_sphere
+    w = Workload(name="mc", L=(48, 48, 48), J_shell=(1.0,), B=(0.0, 0.0, 1.0))
+    m = oracle_model(w)
+    S = random_sphere(w.N, 3)
+    col = oracle.mc_colouring(m)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.mc_sweeps(m, S, 500.0, 1, sweep0=n, n_sweeps=1, method=0, colouring=col)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or el * (n + 1) / n > 2.5 * seconds:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.N * n / el, "unit": "spin-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} heat-bath sweeps of sc 48^3 (one shell), {el:.1f} s"}
+
+
 def cpu_gneb_baseline(seconds):
     """FP64 oracle GNEB iterations on the 48^3 x 32-image instance."""
     import oracle
@@ -563,7 +641,9 @@ def main():
     from workloads import WORKLOADS
 
     torch.cuda.set_device(0)
-    if args.workload == "sc_frustrated_gneb":
+    if args.workload == "sc200_mc":
+        mc_workload(args)
+    elif args.workload == "sc_frustrated_gneb":
         gneb_workload(args)
     elif args.workload == "sc256_chiral_dipolar_field":
         field_workload(args, WORKLOADS[args.workload]())

@@ -32,12 +32,15 @@ struct MCState {
     int o[kMaxSub] = {0};
     unsigned long long *d_acc = nullptr;  // accepted-move counter of the last call
     double *d_part = nullptr;             // magnetisation block partials [kMagBlocks][3]
+    int64_t *d_off = nullptr;             // linear index offset of every bond (interior sites)
+    int rad[3] = {0, 0, 0};               // largest |delta| of the bonds along each axis
 };
 
 void mc_destroy(MCState *m) {
     if (!m) return;
     if (m->d_acc) (void)hipFree(m->d_acc);
     if (m->d_part) (void)hipFree(m->d_part);
+    if (m->d_off) (void)hipFree(m->d_off);
     delete m;
 }
 
@@ -82,10 +85,36 @@ __device__ __forceinline__ double aniso_energy(const Onsite &os, int a, const do
 
 // One colour of one sweep.  Thread t covers x-slot j = t % J of row (y, z, a)
 // = t / J, J = ceil(Lx / C): the row's sites of colour c are x = x0 + C j.
+// Bilinear field of an interior site (every neighbour inside the lattice):
+// neighbour j = i + off_p, no coordinate wrapping.
+template <bool ISO>
+__device__ __forceinline__ void bil_interior(const BondTable &tb, const int64_t *__restrict__ off, int64_t N, int a,
+                                             int64_t i, const double *__restrict__ S, double acc[3]) {
+    acc[0] = acc[1] = acc[2] = 0.0;
+    const int p0 = tb.start[a], p1 = tb.start[a + 1];
+#pragma unroll 4
+    for (int p = p0; p < p1; ++p) {
+        const int64_t j = i + off[p];
+        const double s0 = S[j], s1 = S[N + j], s2 = S[2 * N + j];
+        if constexpr (ISO) {
+            const double J = tb.Jd[p];
+            acc[0] += J * s0;
+            acc[1] += J * s1;
+            acc[2] += J * s2;
+        } else {
+            const double *Jp = tb.Jd + 9 * p;
+            acc[0] += Jp[0] * s0 + Jp[1] * s1 + Jp[2] * s2;
+            acc[1] += Jp[3] * s0 + Jp[4] * s1 + Jp[5] * s2;
+            acc[2] += Jp[6] * s0 + Jp[7] * s1 + Jp[8] * s2;
+        }
+    }
+}
+
 template <bool ISO, int METHOD>
 __global__ __launch_bounds__(kMcB) void k_mc_colour(double *__restrict__ S, BondTable tb, Grid g, Onsite os,
                                                     McColour col, int c, double beta, uint64_t seed,
-                                                    uint64_t sweep, unsigned long long *__restrict__ acc) {
+                                                    uint64_t sweep, unsigned long long *__restrict__ acc,
+                                                    const int64_t *__restrict__ off, int3 rad) {
     const int C = col.C;
     const int J = (g.Lx + C - 1) / C;
     const int64_t n_rows = (int64_t)g.Ly * g.Lz * g.n_sub;
@@ -104,8 +133,14 @@ __global__ __launch_bounds__(kMcB) void k_mc_colour(double *__restrict__ S, Bond
         if (x >= g.Lx) continue;
         const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
         double bl[1][3];
-        const double *const src[1] = {S};
-        bil_sum<double, ISO, 1>(tb, g, a, x, y, z, src, bl);
+        const bool interior = x >= rad.x && x < g.Lx - rad.x && y >= rad.y && y < g.Ly - rad.y && z >= rad.z &&
+                              z < g.Lz - rad.z;
+        if (interior) {
+            bil_interior<ISO>(tb, off, N, a, i, S, bl[0]);
+        } else {
+            const double *const src[1] = {S};
+            bil_sum<double, ISO, 1>(tb, g, a, x, y, z, src, bl);
+        }
         const double b[3] = {bl[0][0] + os.bz[a][0], bl[0][1] + os.bz[a][1], bl[0][2] + os.bz[a][2]};
         uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32) ^ kMcTag;
         uint32_t c2 = (uint32_t)sweep, c3 = (uint32_t)(sweep >> 32);
@@ -313,6 +348,23 @@ spx_status mc_colouring(spx_ham *h, const HamView &v, MCState *m) {
     m->ky = col.ky;
     m->kz = col.kz;
     for (int a = 0; a < kMaxSub; ++a) m->o[a] = col.o[a];
+    // linear offset of every bond, indexed like the device bond table (the
+    // host's bond order, grouped by target sublattice)
+    const Grid &g = v.grid;
+    std::vector<int64_t> off(std::max(info.n_bonds, 1), 0);
+    for (int p = 0; p < info.n_bonds; ++p) {
+        const int dx = dli[3 * p], dy = dli[3 * p + 1], dz = dli[3 * p + 2];
+        off[p] = (int64_t)(abi[2 * p + 1] - abi[2 * p]) * g.M + dx + (int64_t)g.Lx * (dy + (int64_t)g.Ly * dz);
+        m->rad[0] = std::max(m->rad[0], std::abs(dx));
+        m->rad[1] = std::max(m->rad[1], std::abs(dy));
+        m->rad[2] = std::max(m->rad[2], std::abs(dz));
+    }
+    if (hipMalloc((void **)&m->d_off, sizeof(int64_t) * off.size()) != hipSuccess ||
+        hipMemcpy(m->d_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        m->C = 0;
+        return set_error(SPX_ERR_OUT_OF_MEMORY, "Monte Carlo bond offsets");
+    }
     return SPX_OK;
 }
 
@@ -368,15 +420,16 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
     const int64_t total = (int64_t)((v.grid.Lx + col.C - 1) / col.C) * v.grid.Ly * v.grid.Lz * v.grid.n_sub;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kMcB - 1) / kMcB, 65536));
     const bool iso = v.tab.iso != 0;
+    const int3 rad = make_int3(m->rad[0], m->rad[1], m->rad[2]);
     for (int n = 0; n < p->n_sweeps; ++n) {
         const uint64_t sweep = p->sweep0 + (uint64_t)n;
         for (int c = 0; c < col.C; ++c) {
             if (p->method == 0) {
-                if (iso) k_mc_colour<true, 0><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc);
-                else k_mc_colour<false, 0><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc);
+                if (iso) k_mc_colour<true, 0><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
+                else k_mc_colour<false, 0><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
             } else {
-                if (iso) k_mc_colour<true, 1><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc);
-                else k_mc_colour<false, 1><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc);
+                if (iso) k_mc_colour<true, 1><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
+                else k_mc_colour<false, 1><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
             }
         }
     }
