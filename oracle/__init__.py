@@ -86,6 +86,10 @@ def lib():
         L.or_mc_sweeps.restype = C.c_long
         L.or_mc_sweeps.argtypes = model + [_dp, C.c_double, C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_int,
                                            _ip]
+        L.or_min_iterate.restype = None
+        L.or_min_iterate.argtypes = model + [_dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
+                                             C.c_double, C.c_double, C.c_double, C.c_double, _dp, _lp,
+                                             C.POINTER(C.c_double)]
         L.or_reparametrize.restype = None
         L.or_reparametrize.argtypes = [C.c_long, C.c_int, _dp, C.c_void_p, _dp]
         L.or_net_nparams.restype = C.c_long
@@ -296,6 +300,32 @@ def mc_sweeps(model: Model, S, T_K, seed, sweep0=0, n_sweeps=1, method=0, colour
     coef = _i32(coef)
     return lib().or_mc_sweeps(*model._args(), S, float(T_K), int(seed), int(sweep0), int(n_sweeps), int(method),
                               int(Cn), coef)
+
+
+MIN_METHODS = {"vp": 0, "bb": 1, "lbfgs": 2, "adam": 3}
+RETRACTIONS = {"exp": 0, "norm": 1}
+
+
+class MinState:
+    """State of a static minimiser run (velocities, moments, previous step and
+    force, L-BFGS history); zero at the start."""
+
+    def __init__(self, N, method="vp", retraction="exp", dt=0.1, mass=1.0, hist=5, beta1=0.9, beta2=0.999,
+                 eps=1e-8, max_step=0.0):
+        self.method = MIN_METHODS[method] if isinstance(method, str) else int(method)
+        self.retraction = RETRACTIONS[retraction] if isinstance(retraction, str) else int(retraction)
+        self.dt, self.mass, self.hist = float(dt), float(mass), int(hist)
+        self.beta1, self.beta2, self.eps, self.max_step = float(beta1), float(beta2), float(eps), float(max_step)
+        self.work = np.zeros((4 + 2 * self.hist) * 3 * N + self.hist)
+        self.ist = np.zeros(3, dtype=np.int64)
+
+
+def min_iterate(model: Model, S, st: MinState):
+    """One minimiser iteration of S in place; returns max |F| before the update."""
+    mf = C.c_double(0.0)
+    lib().or_min_iterate(*model._args(), S, st.method, st.retraction, st.dt, st.mass, st.hist, st.beta1,
+                         st.beta2, st.eps, st.max_step, st.work, st.ist, C.byref(mf))
+    return mf.value
 
 
 def reparametrize(Y, alpha=None):

@@ -1144,6 +1144,182 @@ void or_gneb_iterate(int n_sub, const int *L, const int *per, const double *cell
     free(b); free(F); free(tau);
 }
 
+/* ---- static minimisation (Methods, static optimisation and MEPs) -------- */
+/*
+ * One iteration of a static minimiser on the product of unit spheres.  The
+ * force F_i = b_i - (b_i.S_i) S_i is minus the tangent gradient G_i; max |F_i|
+ * (before the update) is returned in *max_force.  The step u_i is
+ *   method 0, velocity projection: P = sum v.F, Q = sum F.F over all spins;
+ *             v <- (P/Q) F (if P > 0, else 0) + (dt/mass) F;  u = dt v;
+ *   method 1, Barzilai-Borwein (BB1): alpha = sum s.s / sum s.y with
+ *             s = P(u_prev) and y = G - P(G_prev) (P: projection on the current
+ *             tangent planes), alpha = dt on the first iteration or when
+ *             sum s.y <= 0;  u = alpha F;
+ *   method 2, L-BFGS: the pair (s, y) above joins the history (at most hist
+ *             pairs, oldest dropped) when s.y > 0; the two-loop recursion from
+ *             q = G with the stored pairs projected on the current tangent
+ *             planes, initial scale gamma = s.y / y.y of the newest pair (dt
+ *             without pairs), gives r, and u = -r (u = dt F with no pairs);
+ *   method 3, Adam: m <- b1 m + (1 - b1) G, w <- b2 w + (1 - b2) G*G (per
+ *             Cartesian component), u = -dt m^ / (sqrt(w^) + eps) with the
+ *             bias corrections m^ = m / (1 - b1^t), w^ = w / (1 - b2^t), t the
+ *             iteration count from 1;
+ * then u_i is projected on the tangent plane of S_i, scaled down to
+ * |u_i| = max_step if longer (max_step > 0), and retracted:
+ *   retraction 0, exponential map: S <- cos|u| S + sin|u| u/|u| (then normalised);
+ *   retraction 1, normalised: S <- (S + u) / |S + u|.
+ * State (caller-owned, zero at the start): work = [V | W | Fp | Up | s_0 ..
+ * s_{hist-1} | y_0 .. y_{hist-1} | rho_0 .. rho_{hist-1}] (each block 3N
+ * doubles, rho hist doubles), ist = [iteration, pairs stored, newest slot].
+ */
+static double or_dot3N(long n3, const double *a, const double *b) {
+    double t = 0.0;
+    for (long k = 0; k < n3; ++k) t += a[k] * b[k];
+    return t;
+}
+
+/* x <- x - (x.S) S per spin */
+static void or_tangent(long N, const double *S, double *x) {
+    for (long i = 0; i < N; ++i) {
+        double d = x[i] * S[i] + x[N + i] * S[N + i] + x[2 * N + i] * S[2 * N + i];
+        for (int c = 0; c < 3; ++c) x[c * N + i] -= d * S[c * N + i];
+    }
+}
+
+void or_min_iterate(int n_sub, const int *L, const int *per, const double *cell9, const double *frac,
+                    int n_bonds, const int *b_a, const int *b_b, const int *b_delta, const double *b_J,
+                    int n_aniso, const double *K, const double *K_axis, const double *B3, const double *mu,
+                    int dipolar, double *S, int method, int retraction, double dt, double mass, int hist,
+                    double b1, double b2, double eps, double max_step, double *work, long *ist,
+                    double *max_force) {
+    or_lat lt;
+    or_model m;
+    or_lat_fill(&lt, n_sub, L, per, cell9, frac);
+    or_model_fill(&m, n_bonds, b_a, b_b, b_delta, b_J, n_aniso, K, K_axis, B3, mu, dipolar);
+    const long N = or_nsites(&lt), n3 = 3 * N;
+    double *V = work, *W = work + n3, *Fp = work + 2 * n3, *Up = work + 3 * n3;
+    double *Sh = work + 4 * n3, *Yh = work + (4 + hist) * n3, *rho = work + (4 + 2 * hist) * n3;
+    double *b = (double *)malloc(sizeof(double) * n3);
+    double *F = (double *)malloc(sizeof(double) * n3);
+    double *u = (double *)malloc(sizeof(double) * n3);
+    or_field_total(&lt, &m, S, b);
+    double fmax = 0.0;
+    for (long i = 0; i < N; ++i) {
+        double bs = b[i] * S[i] + b[N + i] * S[N + i] + b[2 * N + i] * S[2 * N + i];
+        double f2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            F[c * N + i] = b[c * N + i] - bs * S[c * N + i];
+            f2 += F[c * N + i] * F[c * N + i];
+        }
+        if (sqrt(f2) > fmax) fmax = sqrt(f2);
+    }
+    *max_force = fmax;
+    const long k = ist[0];
+    if (method == 0) {
+        double P = or_dot3N(n3, V, F), Q = or_dot3N(n3, F, F);
+        double proj = (P > 0.0 && Q > 0.0) ? P / Q : 0.0;
+        for (long q = 0; q < n3; ++q) {
+            V[q] = proj * F[q] + (dt / mass) * F[q];
+            u[q] = dt * V[q];
+        }
+    } else if (method == 1 || method == 2) {
+        /* s = P(u_prev), y = G - P(G_prev) = -F + P(F_prev) */
+        double *sv = (double *)malloc(sizeof(double) * n3);
+        double *yv = (double *)malloc(sizeof(double) * n3);
+        memcpy(sv, Up, sizeof(double) * n3);
+        memcpy(yv, Fp, sizeof(double) * n3);
+        or_tangent(N, S, sv);
+        or_tangent(N, S, yv);
+        for (long q = 0; q < n3; ++q) yv[q] -= F[q];
+        double ss = or_dot3N(n3, sv, sv), sy = or_dot3N(n3, sv, yv);
+        if (method == 1) {
+            double alpha = (k > 0 && sy > 0.0) ? ss / sy : dt;
+            for (long q = 0; q < n3; ++q) u[q] = alpha * F[q];
+        } else {
+            if (k > 0 && sy > 0.0) {
+                long slot = (ist[1] == 0) ? 0 : (ist[2] + 1) % hist;
+                memcpy(Sh + slot * n3, sv, sizeof(double) * n3);
+                memcpy(Yh + slot * n3, yv, sizeof(double) * n3);
+                rho[slot] = 1.0 / sy;
+                ist[2] = slot;
+                if (ist[1] < hist) ist[1] += 1;
+            }
+            const long np = ist[1];
+            if (np == 0) {
+                for (long q = 0; q < n3; ++q) u[q] = dt * F[q];
+            } else {
+                double *qv = (double *)malloc(sizeof(double) * n3);
+                double *py = (double *)malloc(sizeof(double) * n3);
+                double *ps = (double *)malloc(sizeof(double) * n3);
+                double *al = (double *)malloc(sizeof(double) * np);
+                for (long q = 0; q < n3; ++q) qv[q] = -F[q];
+                /* newest to oldest */
+                for (long t = 0; t < np; ++t) {
+                    long j = ((ist[2] - t) % hist + hist) % hist;
+                    memcpy(ps, Sh + j * n3, sizeof(double) * n3);
+                    memcpy(py, Yh + j * n3, sizeof(double) * n3);
+                    or_tangent(N, S, ps);
+                    or_tangent(N, S, py);
+                    al[t] = rho[j] * or_dot3N(n3, ps, qv);
+                    for (long q = 0; q < n3; ++q) qv[q] -= al[t] * py[q];
+                }
+                long jn = ist[2];
+                memcpy(ps, Sh + jn * n3, sizeof(double) * n3);
+                memcpy(py, Yh + jn * n3, sizeof(double) * n3);
+                or_tangent(N, S, ps);
+                or_tangent(N, S, py);
+                double gamma = or_dot3N(n3, ps, py) / or_dot3N(n3, py, py);
+                for (long q = 0; q < n3; ++q) qv[q] *= gamma;
+                /* oldest to newest */
+                for (long t = np - 1; t >= 0; --t) {
+                    long j = ((ist[2] - t) % hist + hist) % hist;
+                    memcpy(ps, Sh + j * n3, sizeof(double) * n3);
+                    memcpy(py, Yh + j * n3, sizeof(double) * n3);
+                    or_tangent(N, S, ps);
+                    or_tangent(N, S, py);
+                    double be = rho[j] * or_dot3N(n3, py, qv);
+                    for (long q = 0; q < n3; ++q) qv[q] += (al[t] - be) * ps[q];
+                }
+                for (long q = 0; q < n3; ++q) u[q] = -qv[q];
+                free(qv); free(py); free(ps); free(al);
+            }
+        }
+        free(sv); free(yv);
+    } else {
+        const double t = (double)(k + 1);
+        const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+        for (long q = 0; q < n3; ++q) {
+            double g = -F[q];
+            V[q] = b1 * V[q] + (1.0 - b1) * g;
+            W[q] = b2 * W[q] + (1.0 - b2) * g * g;
+            u[q] = -dt * (V[q] / c1) / (sqrt(W[q] / c2) + eps);
+        }
+    }
+    or_tangent(N, S, u);
+    for (long i = 0; i < N; ++i) {
+        double ui[3] = {u[i], u[N + i], u[2 * N + i]};
+        double un = or_norm3(ui);
+        if (max_step > 0.0 && un > max_step) {
+            for (int c = 0; c < 3; ++c) ui[c] *= max_step / un;
+            un = max_step;
+        }
+        double s3[3] = {S[i], S[N + i], S[2 * N + i]}, o[3];
+        if (retraction == 0) {
+            or_expmap(s3, ui, o);
+        } else {
+            for (int c = 0; c < 3; ++c) o[c] = s3[c] + ui[c];
+            or_normalise(o);
+        }
+        for (int c = 0; c < 3; ++c) {
+            S[c * N + i] = o[c];
+            Up[c * N + i] = ui[c];
+            Fp[c * N + i] = F[c * N + i];
+        }
+    }
+    ist[0] = k + 1;
+    free(b); free(F); free(u);
+}
+
 /* ---- learned path corrector: 3^3 conv net (forward / backward) ---------- */
 /*
  * Net: 4 layers of 3x3x3 convolutions with zero padding, channel counts
