@@ -261,6 +261,51 @@ spx_status spx_mc_colouring(spx_ham *h, int32_t *n_colours, int32_t *coef);
  * fixed-order reduction.  Asynchronous. */
 spx_status spx_magnetization(spx_ham *h, const double *S, double *m, void *stream);
 
+/* ---- Static minimisation (Methods, static optimisation) --------------------
+ * Minimisers on the product of unit spheres for the Hamiltonian's FP64 field
+ * (field_prec SPX_FP64).  The force F_i = b_i - (b_i.S_i) S_i is minus the
+ * tangent gradient G_i.  Per iteration the step u_i is
+ *   method 0, velocity projection: v <- (sum v.F / sum F.F) F (if sum v.F > 0,
+ *             else 0) + (dt/mass) F, u = dt v;
+ *   method 1, Barzilai-Borwein: u = alpha F, alpha = sum s.s / sum s.y with
+ *             s = P(u_prev), y = P(F_prev) - F (P: projection on the current
+ *             tangent planes); alpha = dt on the first iteration or if
+ *             sum s.y <= 0;
+ *   method 2, L-BFGS: (s, y) joins the history (the newest `history` pairs)
+ *             when s.y > 0; the two-loop recursion from q = G with the pairs
+ *             projected on the current tangent planes and the initial scale
+ *             s.y/y.y of the newest pair gives r, u = -r (u = dt F without pairs);
+ *   method 3, Adam: m <- beta1 m + (1-beta1) G, w <- beta2 w + (1-beta2) G*G
+ *             per Cartesian component, u = -dt m^/(sqrt(w^) + eps) with the
+ *             bias-corrected moments m^ = m/(1-beta1^t), w^ = w/(1-beta2^t);
+ * then u_i is projected on the tangent plane of S_i, cut to |u_i| = max_step if
+ * longer (max_step > 0), and retracted: retraction 0, exponential map
+ * S <- cos|u| S + sin|u| u/|u|; 1, normalised S <- (S + u)/|S + u|.
+ * The run stops (state frozen) after the first iteration whose max |F| (before
+ * its update) is below tol_force (0: never). */
+typedef struct {
+    int32_t method;       /* 0 VP, 1 BB, 2 L-BFGS, 3 Adam */
+    int32_t retraction;   /* 0 exponential map, 1 normalised */
+    double dt;            /* VP time step; BB/L-BFGS first step; Adam step (rad) */
+    double mass;          /* VP */
+    int32_t history;      /* L-BFGS pairs, 1 .. 32 */
+    double beta1, beta2, eps;  /* Adam */
+    double max_step;      /* largest rotation per spin and iteration (rad), 0 = none */
+    double tol_force;     /* meV */
+} spx_min_params;
+typedef struct spx_min spx_min;
+/* Allocates the minimiser state (velocities or moments, previous step and
+ * force, history), zeroed.  Synchronous. */
+spx_status spx_min_create(spx_ham *h, const spx_min_params *p, void *stream, spx_min **out);
+/* n_iter iterations of S ([dev] double[3][N], in place).  Asynchronous. */
+spx_status spx_min_step(spx_min *m, double *S, int32_t n_iter, void *stream);
+/* max |F| of the last iteration (meV, before its update), iterations run,
+ * converged flag (host outputs, any may be NULL).  Synchronises. */
+spx_status spx_min_get_stats(spx_min *m, double *max_force, int32_t *iterations, int32_t *converged, void *stream);
+/* Forget the state (velocities, moments, history, counters). */
+spx_status spx_min_reset(spx_min *m, void *stream);
+spx_status spx_min_destroy(spx_min *m);
+
 /* ---- Batched geodesic nudged elastic band (Methods, minimum-energy paths) --
  * One object holds n_inst independent paths ("instances"), each with its own
  * Hamiltonian (field_prec SPX_FP64, no dipolar term) and 3 <= n_img[k] <= 4096 images

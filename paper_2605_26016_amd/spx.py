@@ -66,6 +66,12 @@ class McParams(C.Structure):
                 ("n_sweeps", C.c_int32), ("method", C.c_int32)]
 
 
+class MinParams(C.Structure):
+    _fields_ = [("method", C.c_int32), ("retraction", C.c_int32), ("dt", C.c_double), ("mass", C.c_double),
+                ("history", C.c_int32), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("max_step", C.c_double), ("tol_force", C.c_double)]
+
+
 class HamInfo(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_bonds", C.c_int32), ("field_prec", C.c_int32),
                 ("backend", C.c_int32), ("radius", C.c_int32 * 3), ("dipolar", C.c_int32),
@@ -113,6 +119,11 @@ def load(path: str = LIB_PATH):
         "spx_gneb_get_stats": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "spx_gneb_set_graph": [vp, i32],
         "spx_mc_sweep": [vp, vp, C.POINTER(McParams), vp, vp],
+        "spx_min_create": [vp, C.POINTER(MinParams), vp, C.POINTER(vp)],
+        "spx_min_step": [vp, vp, i32, vp],
+        "spx_min_get_stats": [vp, vp, vp, vp, vp],
+        "spx_min_reset": [vp, vp],
+        "spx_min_destroy": [vp],
         "spx_mc_colouring": [vp, C.POINTER(C.c_int32), vp],
         "spx_magnetization": [vp, vp, vp, vp],
         "spx_gneb_set_spacing": [vp, i32, vp, vp],
@@ -420,6 +431,53 @@ def gneb_set_params(g, spring_k=1.0, vp_dt=0.1, vp_mass=1.0, ci_mode=1, ci_on_be
 
 def gneb_set_graph(g, enable=True):
     _check(load().spx_gneb_set_graph(g.handle, int(bool(enable))), "spx_gneb_set_graph")
+
+
+MIN_METHODS = {"vp": 0, "bb": 1, "lbfgs": 2, "adam": 3}
+RETRACTIONS = {"exp": 0, "norm": 1}
+
+
+class Minimizer:
+    """Owner of an spx_min handle (keeps its Hamiltonian alive)."""
+
+    def __init__(self, handle, ham):
+        self.handle = handle
+        self.ham = ham
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                load().spx_min_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def min_create(h, method="vp", retraction="exp", dt=0.1, mass=1.0, history=5, beta1=0.9, beta2=0.999,
+               eps=1e-8, max_step=0.0, tol_force=0.0, stream=None) -> Minimizer:
+    p = MinParams(MIN_METHODS[method] if isinstance(method, str) else int(method),
+                  RETRACTIONS[retraction] if isinstance(retraction, str) else int(retraction), float(dt),
+                  float(mass), int(history), float(beta1), float(beta2), float(eps), float(max_step),
+                  float(tol_force))
+    m = C.c_void_p()
+    _check(load().spx_min_create(_h(h), C.byref(p), _stream(stream), C.byref(m)), "spx_min_create")
+    return Minimizer(m.value, h)
+
+
+def min_step(m, S, n_iter=1, stream=None):
+    _check(load().spx_min_step(m.handle, _ptr(S), int(n_iter), _stream(stream)), "spx_min_step")
+
+
+def min_get_stats(m, stream=None):
+    mf = C.c_double()
+    it, conv = C.c_int32(), C.c_int32()
+    _check(load().spx_min_get_stats(m.handle, C.byref(mf), C.byref(it), C.byref(conv), _stream(stream)),
+           "spx_min_get_stats")
+    return {"max_force": mf.value, "iterations": it.value, "converged": conv.value}
+
+
+def min_reset(m, stream=None):
+    _check(load().spx_min_reset(m.handle, _stream(stream)), "spx_min_reset")
 
 
 MC_METHODS = {"heat_bath": 0, "metropolis": 1}
