@@ -239,6 +239,62 @@ def mc_workload(args):
     print(json.dumps(out), flush=True)
 
 
+# static minimiser iteration, per spin: field pass (24 B in, 24 B out) +
+# force pass (read S, b, u_prev, F_prev; write F) + update pass (read S, F;
+# write S, u, F_prev): 48 + 120 + 120 B, plus the L-BFGS two-loop passes
+MIN_BYTES = {"vp": 48 + 120 + 144, "bb": 48 + 120 + 120, "lbfgs": 48 + 120 + 120, "adam": 48 + 72 + 192}
+
+
+def min_workload(args):
+    """FP64 static minimisers on sc 200^3 with a fixed number of iterations
+    (Methods, static optimisation): spin-site updates/s (spins x iterations /
+    time) for 1 .. 5 exchange shells; the headline value is velocity
+    projection with one shell."""
+    import torch
+
+    from paper_2605_26016_amd import spx
+    from workloads import random_sphere_device
+    L = 200
+    N = L ** 3
+    n = max(1, args.steps // 10)
+    table = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for J in MC_SHELLS:
+        h = spx.setup_hamiltonian((L, L, L), J_shell=J, field_prec="fp64", K=0.1, B=(0.0, 0.0, 1.0))
+        row = {"shells": len(J)}
+        for method, kw in (("vp", dict(dt=0.1)), ("bb", dict(dt=0.02)), ("lbfgs", dict(dt=0.02, history=5)),
+                           ("adam", dict(dt=0.01))):
+            S = random_sphere_device(N, 3)
+            mn = spx.min_create(h, method=method, max_step=0.2, **kw)
+            spx.min_step(mn, S, 2)
+            torch.cuda.synchronize()
+            e0.record()
+            spx.min_step(mn, S, n)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / n
+            row[method] = {"ms_per_iteration": ms, "updates_per_s": N / (ms / 1e3)}
+            del mn, S
+        table.append(row)
+        log(f"[bench] minimisers, {len(J)} shell(s): " +
+            ", ".join(f"{k} {row[k]['updates_per_s']:.3e}" for k in ("vp", "bb", "lbfgs", "adam")))
+        del h
+    head = table[0]["vp"]
+    rate = head["updates_per_s"]
+    out = {"metric": "spin-site updates/s (static minimisation, fixed iterations, FP64)", "value": rate,
+           "unit": "spin-iterations/s", "n_gpus": 1, "steps": n, "warmup": 2,
+           "ms_per_step": head["ms_per_iteration"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded random spins)",
+           "config": {"workload": "sc200_min", "cells": [L, L, L], "spins": N, "K_meV": 0.1, "B_T": [0.0, 0.0, 1.0],
+                      "shells": [list(J) for J in MC_SHELLS], "parallelism": "single GPU"},
+           "roofline": {"bound": "hbm", "achieved": rate * MIN_BYTES["vp"] / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": rate * MIN_BYTES["vp"] / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "velocity-projection iteration (field, force, update)",
+                        "bytes_per_spin_iteration": MIN_BYTES["vp"]},
+           "table": table, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_mc_baseline(seconds):
     """The FP64 oracle's heat-bath sweeps on sc 48^3 (one shell)."""
     import oracle
@@ -643,6 +699,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "sc200_mc":
         mc_workload(args)
+    elif args.workload == "sc200_min":
+        min_workload(args)
     elif args.workload == "sc_frustrated_gneb":
         gneb_workload(args)
     elif args.workload == "sc256_chiral_dipolar_field":
