@@ -90,6 +90,14 @@ def lib():
         L.or_min_iterate.argtypes = model + [_dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
                                              C.c_double, C.c_double, C.c_double, C.c_double, _dp, _lp,
                                              C.POINTER(C.c_double)]
+        pl = [C.c_long, C.c_long, _lp, _lp, _dp, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, _dp]
+        L.or_pl_field.restype = None
+        L.or_pl_field.argtypes = pl + [_dp, _dp]
+        L.or_pl_energy.restype = None
+        L.or_pl_energy.argtypes = pl + [_dp, _dp]
+        L.or_pl_heun.restype = None
+        L.or_pl_heun.argtypes = pl + [C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint64, C.c_uint32,
+                                      C.c_int, _dp]
         L.or_reparametrize.restype = None
         L.or_reparametrize.argtypes = [C.c_long, C.c_int, _dp, C.c_void_p, _dp]
         L.or_net_nparams.restype = C.c_long
@@ -326,6 +334,49 @@ def min_iterate(model: Model, S, st: MinState):
     lib().or_min_iterate(*model._args(), S, st.method, st.retraction, st.dt, st.mass, st.hist, st.beta1,
                          st.beta2, st.eps, st.max_step, st.work, st.ist, C.byref(mf))
     return mf.value
+
+
+class PairList:
+    """Explicit couplings (pair-list backend): targets i, sources j, J per entry
+    (scalar, or [n][3][3] when tensor), per-site moments mu (None: 1),
+    per-site uniaxial anisotropy K with unit axes (None: none), field B (T)."""
+
+    def __init__(self, n_sites, i, j, J, mu=None, K=None, K_axis=None, B=(0.0, 0.0, 0.0)):
+        self.N = int(n_sites)
+        self.i = np.ascontiguousarray(i, dtype=np.int64)
+        self.j = np.ascontiguousarray(j, dtype=np.int64)
+        J = np.asarray(J, dtype=np.float64)
+        self.tensor = 1 if J.ndim == 3 else 0
+        self.J = np.ascontiguousarray(J.reshape(len(self.i), 9) if self.tensor else J)
+        self.mu = None if mu is None else _f64(mu)
+        self.K = None if K is None else _f64(K)
+        self.K_axis = None if K_axis is None else _f64(K_axis)
+        self.B = _f64(B)
+
+    def _args(self):
+        return (self.N, len(self.i), self.i, self.j, self.J, self.tensor, _ptr(self.mu), _ptr(self.K),
+                _ptr(self.K_axis), self.B)
+
+
+def pl_field(pl: PairList, S):
+    S = _f64(S)
+    b = np.zeros_like(S)
+    lib().or_pl_field(*pl._args(), S, b)
+    return b
+
+
+def pl_energy(pl: PairList, S):
+    S = _f64(S)
+    t = np.zeros(5)
+    lib().or_pl_energy(*pl._args(), S, t)
+    return t
+
+
+def pl_heun(pl: PairList, S, alpha, dt_fs, T_K=0.0, seed=0, step0=0, tag=0, n_steps=1):
+    S = _f64(S).copy()
+    lib().or_pl_heun(*pl._args(), float(alpha), float(dt_fs), float(T_K), int(seed), int(step0), int(tag),
+                     int(n_steps), S)
+    return S
 
 
 def reparametrize(Y, alpha=None):

@@ -1144,6 +1144,119 @@ void or_gneb_iterate(int n_sub, const int *L, const int *per, const double *cell
     free(b); free(F); free(tau);
 }
 
+/* ---- pair-list Hamiltonian (Methods, pair-list backend) ---------------- */
+/*
+ * Explicit couplings: entry p couples target site i_p to source site j_p with
+ * J_p (scalar, or 3x3 row-major if tensor).  Reduced bilinear field
+ *   b_i = sum_{p: i_p = i} J_p S_{j_p}
+ * (entries summed in list order), plus the site-resolved on-site terms: Zeeman
+ * mu_i mu_B B and uniaxial anisotropy 2 K_i (S_i.n_i) n_i.  mu NULL: all 1;
+ * K NULL: none.  Outputs b (total) and, if not NULL, b_bil.
+ */
+static void or_pl_fields(long N, long P, const long *ti, const long *sj, const double *J, int tensor,
+                         const double *mu, const double *K, const double *axis, const double *B3,
+                         const double *S, double *b, double *b_bil) {
+    double *bb = (double *)calloc((size_t)3 * N, sizeof(double));
+    for (long p = 0; p < P; ++p) {
+        const long i = ti[p], j = sj[p];
+        const double s[3] = {S[j], S[N + j], S[2 * N + j]};
+        if (tensor) {
+            const double *Jp = J + 9 * p;
+            for (int al = 0; al < 3; ++al)
+                bb[al * N + i] += Jp[3 * al] * s[0] + Jp[3 * al + 1] * s[1] + Jp[3 * al + 2] * s[2];
+        } else {
+            for (int al = 0; al < 3; ++al) bb[al * N + i] += J[p] * s[al];
+        }
+    }
+    for (long i = 0; i < N; ++i) {
+        const double m = mu ? mu[i] : 1.0;
+        double an[3] = {0, 0, 0};
+        if (K) {
+            const double *n = axis + 3 * i;
+            double sn = S[i] * n[0] + S[N + i] * n[1] + S[2 * N + i] * n[2];
+            for (int c = 0; c < 3; ++c) an[c] = 2.0 * K[i] * sn * n[c];
+        }
+        for (int c = 0; c < 3; ++c) {
+            b[c * N + i] = bb[c * N + i] + m * OR_MU_B * B3[c] + an[c];
+            if (b_bil) b_bil[c * N + i] = bb[c * N + i];
+        }
+    }
+    free(bb);
+}
+
+void or_pl_field(long N, long P, const long *ti, const long *sj, const double *J, int tensor, const double *mu,
+                 const double *K, const double *axis, const double *B3, const double *S, double *b) {
+    or_pl_fields(N, P, ti, sj, J, tensor, mu, K, axis, B3, S, b, NULL);
+}
+
+/* E terms [bilinear, Zeeman, anisotropy, dipolar (0), total]:
+   -1/2 sum S.b_bil, -sum mu mu_B B.S, -sum K (S.n)^2 */
+void or_pl_energy(long N, long P, const long *ti, const long *sj, const double *J, int tensor, const double *mu,
+                  const double *K, const double *axis, const double *B3, const double *S, double *terms) {
+    double *b = (double *)malloc(sizeof(double) * 3 * N);
+    double *bb = (double *)malloc(sizeof(double) * 3 * N);
+    or_pl_fields(N, P, ti, sj, J, tensor, mu, K, axis, B3, S, b, bb);
+    double eb = 0.0, ez = 0.0, ea = 0.0;
+    for (long i = 0; i < N; ++i) {
+        const double s[3] = {S[i], S[N + i], S[2 * N + i]};
+        const double m = mu ? mu[i] : 1.0;
+        eb += -0.5 * (s[0] * bb[i] + s[1] * bb[N + i] + s[2] * bb[2 * N + i]);
+        ez += -m * OR_MU_B * (s[0] * B3[0] + s[1] * B3[1] + s[2] * B3[2]);
+        if (K) {
+            const double *n = axis + 3 * i;
+            double sn = s[0] * n[0] + s[1] * n[1] + s[2] * n[2];
+            ea += -K[i] * sn * sn;
+        }
+    }
+    terms[0] = eb; terms[1] = ez; terms[2] = ea; terms[3] = 0.0; terms[4] = eb + ez + ea;
+    free(b);
+    free(bb);
+}
+
+static void or_llg_rhs(const double s[3], const double B[3], double alpha, double f[3]);
+
+/* n_steps normalised Heun steps with the pair-list field: the same algorithm
+   as or_heun (predictor, corrector, the same eta in both stages, noise
+   counter = site index), with the site's own moment mu_i. */
+void or_pl_heun(long N, long P, const long *ti, const long *sj, const double *J, int tensor, const double *mu,
+                const double *K, const double *axis, const double *B3, double alpha, double dt_fs, double T_K,
+                uint64_t seed, uint64_t step0, uint32_t tag, int n_steps, double *S) {
+    double *b = (double *)malloc(sizeof(double) * 3 * N);
+    double *f0 = (double *)malloc(sizeof(double) * 3 * N);
+    double *St = (double *)malloc(sizeof(double) * 3 * N);
+    double *eta = (double *)malloc(sizeof(double) * 3 * N);
+    for (int k = 0; k < n_steps; ++k) {
+        uint64_t step = step0 + (uint64_t)k;
+        if (T_K > 0.0) or_thermal_eta_at(seed, step, tag, 0, N, eta);
+        for (int stage = 0; stage < 2; ++stage) {
+            const double *X = stage == 0 ? S : St;
+            or_pl_fields(N, P, ti, sj, J, tensor, mu, K, axis, B3, X, b, NULL);
+            for (long i = 0; i < N; ++i) {
+                const double mu_i = mu ? mu[i] : 1.0;
+                double x[3] = {X[i], X[N + i], X[2 * N + i]};
+                double B[3];
+                for (int c = 0; c < 3; ++c) B[c] = b[c * N + i] / (mu_i * OR_MU_B);
+                if (T_K > 0.0) {
+                    double sig = sqrt(2.0 * alpha * OR_K_B * T_K / (OR_GAMMA * mu_i * OR_MU_B * dt_fs));
+                    for (int c = 0; c < 3; ++c) B[c] += sig * eta[c * N + i];
+                }
+                double f[3], p[3];
+                or_llg_rhs(x, B, alpha, f);
+                if (stage == 0) {
+                    for (int c = 0; c < 3; ++c) { f0[c * N + i] = f[c]; p[c] = S[c * N + i] + dt_fs * f[c]; }
+                    or_normalise(p);
+                    for (int c = 0; c < 3; ++c) St[c * N + i] = p[c];
+                } else {
+                    for (int c = 0; c < 3; ++c) p[c] = S[c * N + i] + 0.5 * dt_fs * (f0[c * N + i] + f[c]);
+                    or_normalise(p);
+                    for (int c = 0; c < 3; ++c) S[c * N + i] = p[c];
+                }
+            }
+        }
+    }
+    free(b); free(f0); free(St); free(eta);
+}
+
 /* ---- static minimisation (Methods, static optimisation and MEPs) -------- */
 /*
  * One iteration of a static minimiser on the product of unit spheres.  The
