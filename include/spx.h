@@ -199,12 +199,43 @@ spx_status spx_thermal_noise(uint64_t seed, uint64_t step, uint32_t tag, int64_t
 spx_status spx_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out,
                              void *stream);
 
+/* ---- Pair-list Hamiltonian (Methods, pair-list backend) --------------------
+ * For systems without translational symmetry (chemical disorder, defects,
+ * site-resolved couplings): entry p couples target site target[p] to source
+ * site source[p] with J[p] (meV; a scalar, or a row-major 3x3 block when
+ * tensor = 1), and the reduced bilinear field is
+ *   b_i = sum_{p: target[p] = i} J_p S_{source[p]},
+ * summed in list order, plus the site-resolved Zeeman mu_i mu_B B and uniaxial
+ * anisotropy 2 K_i (S_i.n_i) n_i.  The list is taken as given: reciprocal
+ * entries are the caller's to supply.  All arrays are host memory, copied at
+ * set-up; mu NULL means 1 everywhere, K NULL no anisotropy.  The handle works
+ * with spx_eval_field, spx_energy (terms: bilinear, Zeeman, anisotropy, 0,
+ * total), spx_llg_heun_step (per-site mu_i in B = b/(mu_i mu_B) and in the
+ * thermal field; noise counter = site index) and the minimisers; GNEB and
+ * Monte Carlo need a lattice (SPX_ERR_UNSUPPORTED).  field_prec SPX_FP64 or
+ * SPX_FP32 (neighbour spins and couplings rounded to float, FP32
+ * accumulation, on-site terms in FP64); other options are ignored.
+ * SPX_ERR_INVALID_ARG for sites out of range or non-positive moments. */
+typedef struct {
+    int64_t n_sites;
+    int64_t n_pairs;
+    const int64_t *target;     /* [n_pairs] i_p */
+    const int64_t *source;     /* [n_pairs] j_p */
+    const double *J;           /* [n_pairs] or [n_pairs][9] */
+    int32_t tensor;
+    const double *mu;          /* [n_sites] mu_B, or NULL */
+    const double *K;           /* [n_sites] meV, or NULL */
+    const double *K_axis;      /* [n_sites][3] unit axes (with K) */
+    double B_ext[3];           /* tesla */
+} spx_pairlist_desc;
+spx_status spx_setup_pairlist(const spx_pairlist_desc *d, const spx_options *opts, void *stream, spx_ham **out);
+
 /* Introspection of a handle (host values; synchronous). */
 typedef struct {
     int64_t n_sites;
     int32_t n_bonds;           /* directed bonds in the table */
     int32_t field_prec;
-    int32_t backend;           /* 1 stencil, 2 MFMA */
+    int32_t backend;           /* 1 stencil, 2 MFMA, 3 pair list */
     int32_t radius[3];         /* max |delta| per axis over the table */
     int32_t dipolar;
     int64_t workspace_bytes;   /* library-owned device memory */

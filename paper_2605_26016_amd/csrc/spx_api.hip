@@ -190,6 +190,8 @@ struct spx_ham {
     hipStream_t cap_stream = nullptr;  // private capture stream
     int use_graph = 1;
     MCState *mc = nullptr;              // Monte Carlo colouring and scratch
+    PairList *pl = nullptr;             // pair-list Hamiltonian (backend 3)
+    int64_t pl_pairs = 0;
     int tuned = 0;
     double tune_us = 0.0;
     // kernel timing: recorded (start, stop) event pairs per kind, and a pool
@@ -250,6 +252,8 @@ struct KernelTimer {
 void free_all(spx_ham *h) {
     if (h->mc) mc_destroy(h->mc);
     h->mc = nullptr;
+    if (h->pl) pl_destroy(h->pl);
+    h->pl = nullptr;
     if (h->dense) dense_destroy(h->dense);
     h->dense = nullptr;
     if (h->heun_graph) (void)hipGraphExecDestroy(h->heun_graph);
@@ -308,6 +312,7 @@ spx_status get_ham_view(spx_ham *h, HamView &v) {
     v.radius[1] = h->radius[1];
     v.radius[2] = h->radius[2];
     v.mc = &h->mc;
+    v.pl = h->pl;
     return SPX_OK;
 }
 }  // namespace spx
@@ -559,6 +564,36 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     return SPX_OK;
 }
 
+spx_status spx_setup_pairlist(const spx_pairlist_desc *d, const spx_options *opts, void *stream, spx_ham **out) {
+    if (!out) return fail(SPX_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(SPX_ERR_INVALID_ARG, "pair-list descriptor is NULL");
+    const int prec = opts ? opts->field_prec : SPX_FP64;
+    if (prec != SPX_FP64 && prec != SPX_FP32)
+        return fail(SPX_ERR_INVALID_ARG, "a pair list evaluates the field in SPX_FP64 or SPX_FP32");
+    hipStream_t st = (hipStream_t)stream;
+    PairList *pl = nullptr;
+    spx_status s = pl_create(d, prec, st, &pl);
+    if (s != SPX_OK) return s;
+    spx_ham *h = new spx_ham();
+    h->pl = pl;
+    h->pl_pairs = d->n_pairs;
+    h->field_prec = prec;
+    h->backend = 3;
+    h->engine = 1;
+    Grid &g = h->grid;
+    g.Lx = (int)d->n_sites;
+    g.Ly = g.Lz = 1;
+    g.per[0] = g.per[1] = g.per[2] = 0;
+    g.n_sub = 1;
+    g.M = (int)d->n_sites;
+    g.N = d->n_sites;
+    h->mu.assign(1, 1.0);
+    reg_add(h);
+    *out = h;
+    return SPX_OK;
+}
+
 spx_status spx_destroy_hamiltonian(spx_ham *h) {
     if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
     reg_del(h);
@@ -572,7 +607,7 @@ spx_status spx_get_info(spx_ham *h, spx_ham_info *info) {
     if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
     if (!info) return fail(SPX_ERR_INVALID_ARG, "info is NULL");
     info->n_sites = h->grid.N;
-    info->n_bonds = (int32_t)h->bonds.size();
+    info->n_bonds = h->pl ? (int32_t)std::min<int64_t>(h->pl_pairs, INT32_MAX) : (int32_t)h->bonds.size();
     info->field_prec = h->field_prec;
     info->backend = h->backend;
     for (int k = 0; k < 3; ++k) info->radius[k] = h->radius[k];
@@ -590,6 +625,7 @@ spx_status spx_get_info(spx_ham *h, spx_ham_info *info) {
 
 spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, double *bond_J) {
     if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
+    if (h->pl) return fail(SPX_ERR_UNSUPPORTED, "a pair-list Hamiltonian has no lattice bond table");
     if (!bond_ab || !bond_delta || !bond_J) return fail(SPX_ERR_INVALID_ARG, "output array is NULL");
     for (size_t p = 0; p < h->bonds.size(); ++p) {
         const HostBond &hb = h->bonds[p];
@@ -883,6 +919,12 @@ spx_status spx_eval_field(spx_ham *h, const double *S, void *b, void *stream) {
     if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
     if (!S || !b) return fail(SPX_ERR_INVALID_ARG, "S or b is NULL");
     hipStream_t st = (hipStream_t)stream;
+    if (h->pl) {
+        KernelTimer kt(h, 2, st);
+        hipError_t e = pl_field(h->pl, S, b, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_eval_field (pair list)");
+        return SPX_OK;
+    }
     const float *bdip = nullptr;
     if (h->dip) {
         spx_status s = dipolar_field(h, S, h->d_bdip0, st);
@@ -904,6 +946,11 @@ spx_status spx_energy(spx_ham *h, const double *S, double *E, double *terms, voi
     if (!reg_has(h)) return fail(SPX_ERR_BAD_HANDLE, "invalid spx_ham handle");
     if (!S || (!E && !terms)) return fail(SPX_ERR_INVALID_ARG, "S is NULL or no output given");
     hipStream_t st = (hipStream_t)stream;
+    if (h->pl) {
+        hipError_t e = pl_energy(h->pl, S, E, terms, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_energy (pair list)");
+        return SPX_OK;
+    }
     const float *bdip = nullptr;
     if (h->dip) {
         spx_status s = dipolar_field(h, S, h->d_bdip0, st);
@@ -947,6 +994,14 @@ spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, voi
     if (p->n_steps == 0) return SPX_OK;
     hipStream_t st = (hipStream_t)stream;
     const double gamma = (p->gamma > 0.0) ? p->gamma * 1e-15 : kGammaPerFs;  // rad/(fs T)
+    if (h->pl) {
+        const int noise = p->temperature_K > 0.0 ? 1 : 0;
+        const double sig0 = noise ? std::sqrt(2.0 * p->alpha * kKB * p->temperature_K / (gamma * kMuB * p->dt_fs)) : 0.0;
+        hipError_t e = pl_heun(h->pl, S, p->alpha, p->dt_fs, -gamma / (1.0 + p->alpha * p->alpha), sig0, p->seed,
+                               p->step0, p->tag, noise, p->n_steps, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step (pair list)");
+        return SPX_OK;
+    }
     HeunConst hc;
     std::memset(&hc, 0, sizeof(hc));
     hc.dt = p->dt_fs;

@@ -23,6 +23,14 @@ void unregister_handle(const void *p);
 
 struct DipolarPlan;
 struct MCState;
+struct PairList;
+// Pair-list Hamiltonian (spx_pairlist.hip).
+spx_status pl_create(const spx_pairlist_desc *d, int prec, hipStream_t st, PairList **out);
+void pl_destroy(PairList *p);
+hipError_t pl_field(const PairList *p, const double *S, void *b, hipStream_t st);
+hipError_t pl_energy(const PairList *p, const double *S, double *E, double *terms, hipStream_t st);
+hipError_t pl_heun(PairList *p, double *S, double alpha, double dt, double pre, double sig0, uint64_t seed,
+                   uint64_t step0, uint32_t tag, int noise, int n_steps, hipStream_t st);
 // Monte Carlo state of a Hamiltonian (spx_mc.hip): colouring and scratch.
 void mc_destroy(MCState *m);
 
@@ -38,6 +46,7 @@ struct HamView {
     DipolarPlan *dip;
     int radius[3];
     MCState **mc;  // the handle's Monte Carlo state slot (created on first use)
+    const PairList *pl;  // non-NULL for a pair-list Hamiltonian
 };
 spx_status get_ham_view(spx_ham *h, HamView &v);
 

@@ -720,6 +720,10 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
             delete g;
             return set_error(SPX_ERR_UNSUPPORTED, "GNEB with the dipolar term is not supported");
         }
+        if (v.pl) {
+            delete g;
+            return set_error(SPX_ERR_UNSUPPORTED, "GNEB needs a lattice Hamiltonian, not a pair list");
+        }
         if (n_img[k] < 3 || n_img[k] > kMaxImages || !images[k]) {
             delete g;
             return set_error(SPX_ERR_INVALID_ARG, "each GNEB instance needs 3 .. 4096 images and a buffer");

@@ -72,6 +72,12 @@ class MinParams(C.Structure):
                 ("max_step", C.c_double), ("tol_force", C.c_double)]
 
 
+class PairListDesc(C.Structure):
+    _fields_ = [("n_sites", C.c_int64), ("n_pairs", C.c_int64), ("target", C.c_void_p), ("source", C.c_void_p),
+                ("J", C.c_void_p), ("tensor", C.c_int32), ("mu", C.c_void_p), ("K", C.c_void_p),
+                ("K_axis", C.c_void_p), ("B_ext", C.c_double * 3)]
+
+
 class HamInfo(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_bonds", C.c_int32), ("field_prec", C.c_int32),
                 ("backend", C.c_int32), ("radius", C.c_int32 * 3), ("dipolar", C.c_int32),
@@ -119,6 +125,7 @@ def load(path: str = LIB_PATH):
         "spx_gneb_get_stats": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "spx_gneb_set_graph": [vp, i32],
         "spx_mc_sweep": [vp, vp, C.POINTER(McParams), vp, vp],
+        "spx_setup_pairlist": [C.POINTER(PairListDesc), C.POINTER(Options), vp, C.POINTER(vp)],
         "spx_min_create": [vp, C.POINTER(MinParams), vp, C.POINTER(vp)],
         "spx_min_step": [vp, vp, i32, vp],
         "spx_min_get_stats": [vp, vp, vp, vp, vp],
@@ -299,6 +306,37 @@ def setup_hamiltonian(dims: Sequence[int], cell=None, sub_frac=((0.0, 0.0, 0.0),
     h = C.c_void_p()
     _check(L.spx_setup_hamiltonian(C.byref(lat), C.byref(m), C.byref(o), _stream(stream), C.byref(h)),
            "spx_setup_hamiltonian")
+    return Hamiltonian(h.value, keep)
+
+
+def setup_pairlist(n_sites, target, source, J, mu=None, K=None, K_axis=None, B=(0.0, 0.0, 0.0),
+                   field_prec="fp64", stream=None) -> Hamiltonian:
+    """Pair-list Hamiltonian: entry p couples target[p] <- source[p] with J[p]
+    (scalar per entry, or [n][3][3] blocks); per-site moments mu, uniaxial
+    anisotropy K with unit axes K_axis (host arrays, copied)."""
+    L = load()
+    t = np.ascontiguousarray(target, dtype=np.int64)
+    so = np.ascontiguousarray(source, dtype=np.int64)
+    Ja = np.asarray(J, dtype=np.float64)
+    tensor = 1 if Ja.ndim == 3 else 0
+    Ja = np.ascontiguousarray(Ja.reshape(len(t), 9) if tensor else Ja.reshape(-1))
+    keep = [t, so, Ja]
+    d = PairListDesc()
+    d.n_sites, d.n_pairs = int(n_sites), len(t)
+    d.target, d.source, d.J = t.ctypes.data, so.ctypes.data, Ja.ctypes.data
+    d.tensor = tensor
+    for name, arr in (("mu", mu), ("K", K), ("K_axis", K_axis)):
+        if arr is None:
+            setattr(d, name, None)
+        else:
+            a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
+            keep.append(a)
+            setattr(d, name, a.ctypes.data)
+    d.B_ext[:] = [float(v) for v in B]
+    o = Options()
+    o.field_prec = PREC[field_prec] if isinstance(field_prec, str) else int(field_prec)
+    h = C.c_void_p()
+    _check(L.spx_setup_pairlist(C.byref(d), C.byref(o), _stream(stream), C.byref(h)), "spx_setup_pairlist")
     return Hamiltonian(h.value, keep)
 
 
