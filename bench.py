@@ -295,6 +295,73 @@ def min_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def pairlist_workload(args):
+    """The pair-list backend against the lattice engine on the same sc 200^3
+    nearest-neighbour model (the paper's backend comparison): field
+    evaluations/s and Heun spin-steps/s, FP64 and FP32 field.  The headline
+    value is the FP32-field pair-list Heun throughput."""
+    import numpy as np
+    import torch
+
+    from paper_2605_26016_amd import spx
+    from workloads import random_sphere_device
+    L = 200
+    N = L ** 3
+    idx = np.arange(N, dtype=np.int64)
+    x, y, z = idx % L, (idx // L) % L, idx // (L * L)
+    tgt, src = [], []
+    for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+        tgt.append(idx)
+        src.append((x + d[0]) % L + L * (((y + d[1]) % L) + L * ((z + d[2]) % L)))
+    tgt, src = np.concatenate(tgt), np.concatenate(src)
+    J = np.ones(len(tgt))
+    S0 = random_sphere_device(N, 3)
+    n = max(1, args.steps // 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    table = {}
+    for backend in ("pairlist", "lattice"):
+        for prec in ("fp64", "fp32"):
+            if backend == "pairlist":
+                h = spx.setup_pairlist(N, tgt, src, J, field_prec=prec)
+            else:
+                h = spx.setup_hamiltonian((L, L, L), J_shell=(1.0,), field_prec=prec)
+            b = torch.empty((3, N), dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
+            S = S0.clone()
+            ms_f = timed(lambda: spx.eval_field(h, S, b))
+            ms_h = timed(lambda: spx.llg_heun_step(h, S, alpha=0.1, dt_fs=0.1, temperature_K=0.0, n_steps=1))
+            table[f"{backend}_{prec}"] = {"field_ms": ms_f, "fields_per_s": N / (ms_f / 1e3), "heun_ms": ms_h,
+                                          "spin_steps_per_s": N / (ms_h / 1e3)}
+            log(f"[bench] {backend} {prec}: field {N / (ms_f / 1e3):.3e}/s, Heun {N / (ms_h / 1e3):.3e} spin-steps/s")
+            del h, b, S
+    head = table["pairlist_fp32"]
+    # pair-list field contract bytes per site: own spin 24 B, 6 sources (4 B
+    # index + 4 B FP32 coupling), row pointer 8 B, FP32 field out 12 B
+    pl_bytes = 24 + 6 * 8 + 8 + 12
+    out = {"metric": "spin updates/s (field+Heun), pair-list backend, sc 200^3 nearest neighbours",
+           "value": head["spin_steps_per_s"], "unit": "spin-steps/s", "n_gpus": 1, "steps": n, "warmup": 1,
+           "ms_per_step": head["heun_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 field (f64 state)", "data": "synthetic (seeded random spins)",
+           "config": {"workload": "sc200_pairlist", "cells": [L, L, L], "spins": N, "pairs": int(len(tgt)),
+                      "parallelism": "single GPU"},
+           "roofline": {"bound": "hbm", "achieved": head["fields_per_s"] * pl_bytes / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": head["fields_per_s"] * pl_bytes / 1e9 / HBM_PEAK_GBS,
+                        "traffic": None, "kernel": "k_pl_field<float> (pair-list FP32 field)",
+                        "bytes_per_site_algorithmic": pl_bytes},
+           "table": table, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_mc_baseline(seconds):
     """The FP64 oracle's heat-bath sweeps on sc 48^3 (one shell)."""
     import oracle
@@ -701,6 +768,8 @@ def main():
         mc_workload(args)
     elif args.workload == "sc200_min":
         min_workload(args)
+    elif args.workload == "sc200_pairlist":
+        pairlist_workload(args)
     elif args.workload == "sc_frustrated_gneb":
         gneb_workload(args)
     elif args.workload == "sc256_chiral_dipolar_field":

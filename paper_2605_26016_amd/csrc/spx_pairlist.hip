@@ -7,8 +7,8 @@
 //
 // Layout: the entries are sorted by target site into CSR rows (stable: a
 // site's entries keep their list order, which is the summation order), with
-// the sources and couplings in row order; per-site moments and anisotropies
-// are plain arrays.  One thread per target site gathers its row.  FP32 mode
+// the sources (32-bit) and couplings in row order; per-site moments and
+// anisotropies are plain arrays.  One thread per target site gathers its row.  FP32 mode
 // rounds every neighbour spin and coupling to float and accumulates in FP32,
 // with the on-site terms added in FP64 before the result is rounded.
 #include <algorithm>
@@ -28,7 +28,7 @@ struct PairList {
     bool has_K = false;
     double B[3] = {0, 0, 0};
     int64_t *row = nullptr;  // [N + 1]
-    int64_t *col = nullptr;  // [P] sources in row order
+    int32_t *col = nullptr;  // [P] sources in row order (sites < 2^31)
     double *Jd = nullptr;    // [P] or [P][9]
     float *Jf = nullptr;
     double *mu = nullptr;    // [N]
@@ -46,7 +46,8 @@ constexpr int kPlBlocks = 1024;
 
 struct PlView {
     int64_t N;
-    const int64_t *row, *col;
+    const int64_t *row;
+    const int32_t *col;
     const double *Jd;
     const float *Jf;
     const double *mu, *K, *axis;
@@ -252,13 +253,14 @@ spx_status pl_create(const spx_pairlist_desc *d, int prec, hipStream_t st, PairL
         ++row[d->target[p] + 1];
     }
     for (int64_t i = 0; i < N; ++i) row[i + 1] += row[i];
-    std::vector<int64_t> col(std::max<int64_t>(P, 1)), fill(row.begin(), row.end() - 1);
+    std::vector<int32_t> col(std::max<int64_t>(P, 1));
+    std::vector<int64_t> fill(row.begin(), row.end() - 1);
     const int nj = tensor ? 9 : 1;
     std::vector<double> Jd(std::max<int64_t>(P * nj, 1));
     std::vector<float> Jf(Jd.size());
     for (int64_t p = 0; p < P; ++p) {
         const int64_t q = fill[d->target[p]]++;
-        col[q] = d->source[p];
+        col[q] = (int32_t)d->source[p];
         for (int e = 0; e < nj; ++e) {
             Jd[q * nj + e] = d->J[p * nj + e];
             Jf[q * nj + e] = (float)d->J[p * nj + e];
@@ -288,7 +290,7 @@ spx_status pl_create(const spx_pairlist_desc *d, int prec, hipStream_t st, PairL
         pl->owned.push_back(*ptr);
         return true;
     };
-    bool ok = alloc((void **)&pl->row, sizeof(int64_t) * (N + 1)) && alloc((void **)&pl->col, sizeof(int64_t) * col.size()) &&
+    bool ok = alloc((void **)&pl->row, sizeof(int64_t) * (N + 1)) && alloc((void **)&pl->col, sizeof(int32_t) * col.size()) &&
               alloc((void **)&pl->Jd, sizeof(double) * Jd.size()) && alloc((void **)&pl->Jf, sizeof(float) * Jf.size()) &&
               alloc((void **)&pl->mu, sizeof(double) * N) && alloc((void **)&pl->St, sizeof(double) * 3 * N) &&
               alloc((void **)&pl->f0, sizeof(double) * 3 * N) && alloc((void **)&pl->part, sizeof(double) * 3 * kPlBlocks);
@@ -298,7 +300,7 @@ spx_status pl_create(const spx_pairlist_desc *d, int prec, hipStream_t st, PairL
         return set_error(SPX_ERR_OUT_OF_MEMORY, "hipMalloc failed for the pair list");
     }
     hipError_t e = hipMemcpyAsync(pl->row, row.data(), sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(pl->col, col.data(), sizeof(int64_t) * col.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(pl->col, col.data(), sizeof(int32_t) * col.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->Jd, Jd.data(), sizeof(double) * Jd.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->Jf, Jf.data(), sizeof(float) * Jf.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->mu, mu.data(), sizeof(double) * N, hipMemcpyHostToDevice, st);
