@@ -44,12 +44,6 @@ constexpr int kYB = SPX_ZM_YB;     // y sites per thread
 // plane's compute and written to LDS after it (global latency overlapped);
 // single-input modes only (two staged inputs would double those registers)
 constexpr bool kPrefetch = SPX_ZM_PREFETCH != 0;
-// XCD-contiguous tile assignment: measured within +-2.5% of the default
-// round-robin order on the bcc and sc workloads, so left off.
-#ifndef SPX_ZM_XCD
-#define SPX_ZM_XCD 0
-#endif
-constexpr bool kXcdRemap = SPX_ZM_XCD != 0;
 
 constexpr int kTYE = kTYT * kYB;  // tile height in y
 constexpr int kThreads = kTX * kTYT;
@@ -89,6 +83,9 @@ struct ZArgs {
     // launch is a no-op when *skip != 0
     int nzc, nimg;
     int64_t bstride;
+    // 1: tiles are dealt to the XCDs in contiguous runs (set by the launcher
+    // when every tile of the grid is resident at once)
+    int xcd;
     const double *S0alt;
     const double *sel, *skip;
 };
@@ -98,6 +95,94 @@ struct ZArgs {
 template <int KIND>
 struct ShapeC {
     static constexpr ShapeTable t = make_shape(KIND);
+};
+
+// Shared partial sums of an isotropic shape.  With one coupling per shell,
+// the bonds of one (target a, dz, shell) group all take the same J, so the
+// group's staged sources are summed first and multiplied once; groups with
+// the same source set (a shell's sources at dz and -dz, or two shells on
+// one set: on bcc the 2x2 box feeds the 1st and 4th shells) share one sum.
+// On the bcc 5-shell shape this turns 116 FMAs per component and input
+// plane into 32 adds and 28 FMAs.
+constexpr int kMaxSums = 48, kMaxMembers = 32, kMaxUses = 128;
+struct ZSum {
+    int n;                  // members (staged source positions)
+    int b[kMaxMembers], dx[kMaxMembers], dy[kMaxMembers];
+    int u0, nu;             // its uses: uses[u0 .. u0 + nu)
+};
+struct ZUse {
+    int a, dz, shell;
+};
+struct SumTable {
+    int nsum, nuse;
+    ZSum sums[kMaxSums];
+    ZUse uses[kMaxUses];
+    bool ok;                // false if the shape overflows the table
+};
+
+constexpr SumTable make_sums(int kind) {
+    const ShapeTable t = make_shape(kind);
+    SumTable st{};
+    st.ok = true;
+    // groups keyed by (a, dz, shell), members in bond order
+    int ng = 0;
+    int ga[kMaxUses] = {}, gdz[kMaxUses] = {}, gsh[kMaxUses] = {}, gn[kMaxUses] = {};
+    int gb[kMaxUses][kMaxMembers] = {}, gx[kMaxUses][kMaxMembers] = {}, gy[kMaxUses][kMaxMembers] = {};
+    for (int k = 0; k < t.nb; ++k) {
+        const ZBond &bd = t.bonds[k];
+        int g = 0;
+        while (g < ng && !(ga[g] == bd.a && gdz[g] == bd.dz && gsh[g] == bd.shell)) ++g;
+        if (g == ng) {
+            if (ng == kMaxUses) { st.ok = false; return st; }
+            ga[g] = bd.a;
+            gdz[g] = bd.dz;
+            gsh[g] = bd.shell;
+            gn[g] = 0;
+            ++ng;
+        }
+        if (gn[g] == kMaxMembers) { st.ok = false; return st; }
+        gb[g][gn[g]] = bd.b;
+        gx[g][gn[g]] = bd.dx;
+        gy[g][gn[g]] = bd.dy;
+        ++gn[g];
+    }
+    // one sum per distinct member list (bond order makes equal sets equal lists)
+    int gsum[kMaxUses] = {};
+    for (int g = 0; g < ng; ++g) {
+        int m = 0;
+        for (; m < st.nsum; ++m) {
+            const ZSum &z = st.sums[m];
+            bool same = z.n == gn[g];
+            for (int e = 0; same && e < z.n; ++e)
+                same = z.b[e] == gb[g][e] && z.dx[e] == gx[g][e] && z.dy[e] == gy[g][e];
+            if (same) break;
+        }
+        if (m == st.nsum) {
+            if (st.nsum == kMaxSums) { st.ok = false; return st; }
+            ZSum &z = st.sums[st.nsum++];
+            z.n = gn[g];
+            for (int e = 0; e < z.n; ++e) {
+                z.b[e] = gb[g][e];
+                z.dx[e] = gx[g][e];
+                z.dy[e] = gy[g][e];
+            }
+        }
+        gsum[g] = m;
+    }
+    // uses grouped by sum
+    for (int m = 0; m < st.nsum; ++m) {
+        st.sums[m].u0 = st.nuse;
+        for (int g = 0; g < ng; ++g)
+            if (gsum[g] == m) st.uses[st.nuse++] = ZUse{ga[g], gdz[g], gsh[g]};
+        st.sums[m].nu = st.nuse - st.sums[m].u0;
+    }
+    return st;
+}
+
+template <int KIND>
+struct SumC {
+    static constexpr SumTable t = make_sums(KIND);
+    static_assert(t.ok, "shape exceeds the partial-sum table");
 };
 
 // Compile-time loop: f(std::integral_constant<int, k>) for k = 0 .. N-1.
@@ -133,13 +218,13 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     const int ty = threadIdx.x / kTX;
     if (g.skip && *g.skip != 0.0) return;  // uniform over the grid
     // 1-D grid of (x tile, y tile, z chunk, image) tiles, x fastest.  Blocks
-    // are dealt to the 8 XCDs round-robin; with kXcdRemap each XCD instead
-    // gets one contiguous run of tiles, so tiles that share halo rows share
-    // that XCD's L2.
+    // are dealt to the 8 XCDs round-robin; with g.xcd each XCD instead gets
+    // one contiguous run of tiles, so the tiles that share halo rows and
+    // march through the same planes at the same time share that XCD's L2.
     const unsigned nbx = (unsigned)((g.Lx + kTX - 1) / kTX), nby = (unsigned)((g.Ly + kTYE - 1) / kTYE);
     const unsigned ntile = gridDim.x;
     unsigned tile = blockIdx.x;
-    if (kXcdRemap && (ntile & 7u) == 0) tile = (tile & 7u) * (ntile >> 3) + (tile >> 3);
+    if (g.xcd && (ntile & 7u) == 0) tile = (tile & 7u) * (ntile >> 3) + (tile >> 3);
     const int x0 = (int)(tile % nbx) * kTX;
     const int y0 = (int)((tile / nbx) % nby) * kTYE;
     const int zb = (int)(tile / (nbx * nby));
@@ -166,29 +251,89 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
                     for (int k = 0; k < NIN; ++k) acc[s][yb][a][c][k] = T(0);
 
-    // Staged elements of a plane: thread t handles elements idx = t + k
-    // kThreads (k < NLD) of the (sublattice, halo row, halo column) grid.
-    // Their x/y source offsets and wrap/zero decisions do not depend on the
-    // plane and are computed once here; per plane only z is added.
-    constexpr int NLD = (NSUB * PLANE + kThreads - 1) / kThreads;
+    // Per-site FP64 inputs of the epilogue other than the spin itself,
+    // fetched one march iteration before their use so that their latency
+    // hides behind a plane's stencil: CORRECT_P reads P and eta, PREDICT
+    // reads eta when the noise comes from a pre-pass.
+    constexpr bool kEpiPre = MODE == ZM_CORRECT_P || MODE == ZM_PREDICT;
+    constexpr int NE = MODE == ZM_CORRECT_P ? 6 : MODE == ZM_PREDICT ? 3 : 1;
+    double epi[kYB][NSUB][NE];
+    auto fetch_epi = [&](int o) __attribute__((always_inline)) {
+        if (o < 0 || o >= nout) return;  // uniform over the block
+        if (MODE == ZM_PREDICT && !(hc.noise && g.eload)) return;
+        const int x = x0 + tx;
+        static_for<NSUB>([&](auto ac) __attribute__((always_inline)) {
+            constexpr int a = decltype(ac)::value;
+#pragma unroll
+            for (int yb = 0; yb < kYB; ++yb) {
+                const int y = y0 + ty * kYB + yb;
+                if (x >= g.Lx || y >= g.Ly) continue;
+                const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * (zs + o));
+                double *e = epi[yb][a];
+                if constexpr (MODE == ZM_CORRECT_P) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) e[c] = g.pload[c * N + i];
+                    if (hc.noise)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) e[3 + c] = g.eload[c * N + i];
+                } else if constexpr (MODE == ZM_PREDICT) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) e[c] = g.eload[c * N + i];
+                }
+            }
+        });
+    };
+
+    // Staged elements of a plane.  Slots 0 .. NI-1 of thread (tx, ty) are
+    // its own interior sites (sublattice a, row yb), so the FP64 spins of the
+    // sites it finishes pass through its registers; slots NI .. NLD-1 hold
+    // the x/y halo ring, dealt over the block's threads.  The x/y source
+    // offsets and wrap/zero decisions do not depend on the plane and are
+    // computed once here; per plane only z is added.
+    constexpr int HS = PLANE - kTX * kTYE;  // halo elements per sublattice
+    constexpr int RX2 = 2 * RX > 0 ? 2 * RX : 1;
+    constexpr int NI = NSUB * kYB;
+    constexpr int NH = (NSUB * HS + kThreads - 1) / kThreads;
+    constexpr int NLD = NI + NH;
     int64_t xy_off[NLD];
     int lds_off[NLD];
-    unsigned xy_ok = 0;  // bit t: element valid and inside the lattice in x/y
+    unsigned xy_ok = 0;    // bit t: element inside the lattice in x/y (after wrap)
+    unsigned slot_ok = 0;  // bit t: slot t holds an element of the plane
 #pragma unroll
     for (int t = 0; t < NLD; ++t) {
-        const int idx = threadIdx.x + t * kThreads;
+        int sub, cy, cx;
+        bool have = true;
+        if (t < NI) {
+            sub = t / kYB;
+            cy = ty * kYB + t % kYB + RY;
+            cx = tx + RX;
+        } else {
+            const int h = threadIdx.x + (t - NI) * kThreads;
+            have = h < NSUB * HS;
+            sub = h / HS;
+            int m = h - sub * HS;
+            if (m < RY * PW) {  // rows above the tile
+                cy = m / PW;
+                cx = m - cy * PW;
+            } else if ((m -= RY * PW) < kTYE * 2 * RX) {  // left / right columns
+                cy = RY + m / RX2;
+                const int k = m - (cy - RY) * RX2;
+                cx = k < RX ? k : kTX + k;
+            } else {  // rows below the tile
+                m -= kTYE * 2 * RX;
+                cy = RY + kTYE + m / PW;
+                cx = m - (cy - RY - kTYE) * PW;
+            }
+        }
         xy_off[t] = 0;
         lds_off[t] = 0;
-        if (idx < NSUB * PLANE) {
-            const int sub = idx / PLANE;
-            const int r = idx - sub * PLANE;
-            const int cy = r / PW;
-            const int cx = r - cy * PW;
+        if (have) {
+            slot_ok |= 1u << t;
             bool ok = true;
             const int gx = zwrap(x0 - RX + cx, g.Lx, g.per[0], ok);
             const int gy = zwrap(y0 - RY + cy, g.Ly, g.per[1], ok);
             xy_off[t] = (int64_t)sub * g.M + gx + (int64_t)g.Lx * gy;
-            lds_off[t] = sub * 3 * PLANE + r;
+            lds_off[t] = sub * 3 * PLANE + cy * PW + cx;
             if (ok) xy_ok |= 1u << t;
         }
     }
@@ -198,6 +343,24 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // plane q (z = zs + DZLO + q) in two halves: fetch into registers, then
     // commit to LDS buffer `buf`
     double pre[NLD][NIN][3];
+    // FP64 spins of the thread's own sites for the last DZHI + 1 staged
+    // planes: own[0] holds the plane that the current iteration finishes
+    constexpr bool kOwn = kPrefetch && NIN == 1 && MODE != ZM_BIL;
+    double own[kOwn ? DZHI + 1 : 1][NI][3];
+    auto keep_own = [&]() __attribute__((always_inline)) {
+        if constexpr (kOwn) {
+#pragma unroll
+            for (int r = 0; r < DZHI; ++r)
+#pragma unroll
+                for (int k = 0; k < NI; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) own[r][k][c] = own[r + 1][k][c];
+#pragma unroll
+            for (int k = 0; k < NI; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) own[DZHI][k][c] = pre[k][0][c];
+        }
+    };
     auto fetch_plane = [&](int q) __attribute__((always_inline)) {
         bool zok = true;
         const int gz = zwrap(zs + DZLO + q, g.Lz, g.per[2], zok);
@@ -215,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     auto commit_plane = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < NLD; ++t) {
-            if (NLD * kThreads == NSUB * PLANE || threadIdx.x + t * kThreads < NSUB * PLANE) {
+            if (t < NI || ((slot_ok >> t) & 1u)) {
 #pragma unroll
                 for (int k = 0; k < NIN; ++k)
 #pragma unroll
@@ -231,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         const int64_t zoff = plane_stride * gz;
 #pragma unroll
         for (int t = 0; t < NLD; ++t) {
-            if (NLD * kThreads == NSUB * PLANE || threadIdx.x + t * kThreads < NSUB * PLANE) {
+            if (t < NI || ((slot_ok >> t) & 1u)) {
                 const bool ok = zok && ((xy_ok >> t) & 1u);
                 const int64_t j = xy_off[t] + zoff;
 #pragma unroll
@@ -247,7 +410,8 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // Epilogue of one site (sublattice a, row y, plane z) whose bilinear field
     // sums are v[in][c].  One copy of this code serves every site of the
     // thread: the caller selects the site's values from the register ring.
-    auto finish_site = [&](auto ac, int x, int y, int z, const T (&v)[NIN][3]) __attribute__((always_inline)) {
+    auto finish_site = [&](auto ac, int x, int y, int z, const T (&v)[NIN][3], const double (&e)[NE],
+                           const double (&so)[3]) __attribute__((always_inline)) {
         constexpr int a = decltype(ac)::value;
         const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
         if constexpr (MODE == ZM_BIL) {
@@ -257,7 +421,9 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             return;
         }
         if constexpr (MODE == ZM_CORRECT_P) {
-            const double st[3] = {g.S1[i], g.S1[N + i], g.S1[2 * N + i]};
+            double st[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) st[c] = kOwn ? so[c] : g.S1[c * N + i];
             double bt[3];
             aniso_field(os, a, st, bt);
             double B1[3];
@@ -270,19 +436,24 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             if (hc.noise) {
                 const double sg = hc.sigma[a];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) B1[c] += sg * g.eload[c * N + i];
+                for (int c = 0; c < 3; ++c) B1[c] += sg * e[3 + c];
             }
             double f1[3];
             llg_rhs(st, B1, hc.pre, hc.alpha, f1);
             const double hdt = 0.5 * hc.dt;
-            double p[3] = {g.pload[i] + hdt * f1[0], g.pload[N + i] + hdt * f1[1], g.pload[2 * N + i] + hdt * f1[2]};
+            double p[3] = {e[0] + hdt * f1[0], e[1] + hdt * f1[1], e[2] + hdt * f1[2]};
             normalise3(p);
             g.out[i] = p[0];
             g.out[N + i] = p[1];
             g.out[2 * N + i] = p[2];
             return;
         }
-        const double sv[3] = {g.S0[i], g.S0[N + i], g.S0[2 * N + i]};
+        // the spin of the state whose field this is (S^n): the thread's own
+        // staged value, except for the correctors that stage S~
+        constexpr bool kSvOwn = kOwn && (MODE == ZM_FIELD || MODE == ZM_PREDICT);
+        double sv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sv[c] = kSvOwn ? so[c] : g.S0[c * N + i];
         double ba[3];
         aniso_field(os, a, sv, ba);
         if constexpr (MODE == ZM_FIELD) {
@@ -304,9 +475,9 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             if (hc.noise) {
                 double eta[3];
                 if (g.eload) {
-                    eta[0] = g.eload[i];
-                    eta[1] = g.eload[N + i];
-                    eta[2] = g.eload[2 * N + i];
+                    eta[0] = e[0];
+                    eta[1] = e[1];
+                    eta[2] = e[2];
                 } else {
                     thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)i, eta);
                 }
@@ -334,7 +505,9 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             g.out[N + i] = p[1];
             g.out[2 * N + i] = p[2];
         } else {
-            const double st[3] = {g.S1[i], g.S1[N + i], g.S1[2 * N + i]};
+            double st[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) st[c] = (kOwn && MODE == ZM_CORRECT_STORED) ? so[c] : g.S1[c * N + i];
             double bt[3];
             aniso_field(os, a, st, bt);
             double B0[3], B1[3];
@@ -383,9 +556,11 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     if constexpr (kPrefetch && NIN == 1) {
         fetch_plane(0);
         commit_plane(0);
+        keep_own();
     } else {
         load_plane(0, 0);
     }
+    if constexpr (kEpiPre) fetch_epi(-(D - 1));
     __syncthreads();
 #pragma unroll 1
     for (int q = 0; q < nq; ++q) {
@@ -395,6 +570,56 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         } else {
             if (q + 1 < nq) load_plane(q + 1, buf ^ 1);
         }
+        if constexpr (ISO) {
+            // isotropic couplings: shared partial sums, then one FMA per use
+            constexpr int NSUM = SumC<KIND>::t.nsum;
+            static_for<NSUM>([&](auto kc) __attribute__((always_inline)) {
+                constexpr int ks = decltype(kc)::value;
+                constexpr ZSum sm = SumC<KIND>::t.sums[ks];
+                static_for<kYB>([&](auto ybc) __attribute__((always_inline)) {
+                    constexpr int yb = decltype(ybc)::value;
+                    static_for<NIN>([&](auto inc) __attribute__((always_inline)) {
+                        constexpr int in = decltype(inc)::value;
+                        T v[3] = {T(0), T(0), T(0)};
+                        static_for<sm.n>([&](auto mc) __attribute__((always_inline)) {
+                            constexpr int m = decltype(mc)::value;
+                            const int off = (ty * kYB + yb + sm.dy[m] + RY) * PW + tx + sm.dx[m] + RX;
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                const T sv = lds[buf][in][sm.b[m]][c][off];
+                                v[c] = m == 0 ? sv : v[c] + sv;
+                            }
+                        });
+                        static_for<sm.nu>([&](auto uc) __attribute__((always_inline)) {
+                            constexpr ZUse u = SumC<KIND>::t.uses[sm.u0 + decltype(uc)::value];
+                            constexpr int slot = DZHI - u.dz;
+                            const T J = W.w[u.shell];
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) acc[slot][yb][u.a][c][in] += J * v[c];
+                        });
+                    });
+                });
+                // scheduling fence where the next sum reads another source
+                // sublattice: sums over one sublattice share their staged
+                // reads, and only that sublattice's values are live at a time
+                if constexpr (ks + 1 < NSUM) {
+                    if constexpr (SumC<KIND>::t.sums[ks + 1].b[0] != sm.b[0]) {
+#pragma unroll
+                        for (int s2 = 0; s2 < D; ++s2)
+#pragma unroll
+                            for (int yb = 0; yb < kYB; ++yb)
+#pragma unroll
+                                for (int a2 = 0; a2 < NSUB; ++a2)
+#pragma unroll
+                                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                                        for (int in = 0; in < NIN; ++in)
+                                            asm volatile("" : "+v"(acc[s2][yb][a2][c][in]));
+                        asm volatile("" ::: "memory");
+                    }
+                }
+            });
+        } else {
         static_for<NB>([&](auto kc) __attribute__((always_inline)) {
             constexpr int kb = decltype(kc)::value;
             constexpr ZBond bd = ShapeC<KIND>::t.bonds[kb];
@@ -407,17 +632,10 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                     const T s0 = lds[buf][in][bd.b][0][off];
                     const T s1 = lds[buf][in][bd.b][1][off];
                     const T s2 = lds[buf][in][bd.b][2][off];
-                    if constexpr (ISO) {
-                        const T J = W.w[bd.shell];
-                        acc[slot][yb][bd.a][0][in] += J * s0;
-                        acc[slot][yb][bd.a][1][in] += J * s1;
-                        acc[slot][yb][bd.a][2][in] += J * s2;
-                    } else {
-                        const T *J = &W.w[9 * kb];
-                        acc[slot][yb][bd.a][0][in] += J[0] * s0 + J[1] * s1 + J[2] * s2;
-                        acc[slot][yb][bd.a][1][in] += J[3] * s0 + J[4] * s1 + J[5] * s2;
-                        acc[slot][yb][bd.a][2][in] += J[6] * s0 + J[7] * s1 + J[8] * s2;
-                    }
+                    const T *J = &W.w[9 * kb];
+                    acc[slot][yb][bd.a][0][in] += J[0] * s0 + J[1] * s1 + J[2] * s2;
+                    acc[slot][yb][bd.a][1][in] += J[3] * s0 + J[4] * s1 + J[5] * s2;
+                    acc[slot][yb][bd.a][2][in] += J[6] * s0 + J[7] * s1 + J[8] * s2;
                 });
             });
             // scheduling fence between source rows (b, dy): the pending sums
@@ -441,6 +659,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 }
             }
         });
+        }
         // output plane q - (D-1) (slot 0) has received all of its inputs
         const int o = q - (D - 1);
         if (o >= 0 && o < nout) {
@@ -452,22 +671,33 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 // rows go through one copy of the epilogue: row yb's sums are
                 // always in fin[0], shifted down after each row
                 T fin[kYB][NIN][3];
+                double ef[kYB][NE], sf[kYB][3];
 #pragma unroll
-                for (int yb = 0; yb < kYB; ++yb)
+                for (int yb = 0; yb < kYB; ++yb) {
 #pragma unroll
                     for (int in = 0; in < NIN; ++in)
 #pragma unroll
                         for (int c = 0; c < 3; ++c) fin[yb][in][c] = acc[0][yb][a][c][in];
+#pragma unroll
+                    for (int k = 0; k < NE; ++k) ef[yb][k] = kEpiPre ? epi[yb][a][k] : 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sf[yb][c] = kOwn ? own[0][a * kYB + yb][c] : 0.0;
+                }
 #pragma unroll 1
                 for (int yb = 0; yb < kYB; ++yb) {
                     const int y = y0 + ty * kYB + yb;
-                    if (x < g.Lx && y < g.Ly) finish_site(ac, x, y, zs + o, fin[0]);
+                    if (x < g.Lx && y < g.Ly) finish_site(ac, x, y, zs + o, fin[0], ef[0], sf[0]);
 #pragma unroll
-                    for (int k = 0; k + 1 < kYB; ++k)
+                    for (int k = 0; k + 1 < kYB; ++k) {
 #pragma unroll
                         for (int in = 0; in < NIN; ++in)
 #pragma unroll
                             for (int c = 0; c < 3; ++c) fin[k][in][c] = fin[k + 1][in][c];
+#pragma unroll
+                        for (int m = 0; m < NE; ++m) ef[k][m] = ef[k + 1][m];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) sf[k][c] = sf[k + 1][c];
+                    }
                 }
             });
         }
@@ -492,7 +722,11 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                     for (int in = 0; in < NIN; ++in) acc[D - 1][yb][a][c][in] = T(0);
         if constexpr (kPrefetch && NIN == 1) {
             if (q + 1 < nq) commit_plane(buf ^ 1);
+            keep_own();  // every iteration, so that own[0] stays aligned
         }
+        // the next iteration's output plane: its per-site inputs are in
+        // flight across the barrier and that iteration's stencil
+        if constexpr (kEpiPre) fetch_epi(q - D + 2);
         __syncthreads();
     }
 }
@@ -587,14 +821,35 @@ __global__ __launch_bounds__(256) void k_heun_post(int64_t M, int64_t N, Onsite 
     out[2 * N + i] = p[2];
 }
 
+// Compute units of the current device (queried once per process).
+int device_cus() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            return 0;
+        n = v;
+    }
+    return n;
+}
+
 template <int KIND, typename T, bool ISO, int MODE>
-hipError_t launch_kind(const ZPlan &zp, const ZArgs &a, const Onsite &os, const HeunConst &hc, hipStream_t st) {
+hipError_t launch_kind(const ZPlan &zp, const ZArgs &a0, const Onsite &os, const HeunConst &hc, hipStream_t st) {
     constexpr int NB = make_shape(KIND).nb;
     constexpr int NW = ISO ? make_shape(KIND).nshell : 9 * NB;
     ZWeights<T, NW> W;
     for (int k = 0; k < NW; ++k) W.w[k] = (T)(sizeof(T) == 4 ? (double)zp.wf[k] : zp.wd[k]);
-    const int64_t ntile = (int64_t)((a.Lx + kTX - 1) / kTX) * ((a.Ly + kTYE - 1) / kTYE) * a.nzc * a.nimg;
+    const int64_t ntile = (int64_t)((a0.Lx + kTX - 1) / kTX) * ((a0.Ly + kTYE - 1) / kTYE) * a0.nzc * a0.nimg;
     if (ntile > 0x7fffffff) return hipErrorInvalidValue;
+    // a grid whose tiles are all resident at once (two blocks per CU) gets
+    // the XCD-contiguous tile order: the x/y halo rows shared by concurrent
+    // neighbouring tiles are then fetched into one L2 once (measured: the
+    // bcc 128^3 bilinear pass fetches 2.25x fewer bytes).  Larger grids keep
+    // the round-robin order, which measured faster there.
+    ZArgs a = a0;
+    const int ncu = device_cus();
+    a.xcd = (ncu > 0 && ntile <= 2 * (int64_t)ncu) ? 1 : 0;
     k_zmarch<KIND, T, ISO, MODE><<<(unsigned)ntile, kThreads, 0, st>>>(a, os, hc, W);
     return hipGetLastError();
 }
