@@ -407,32 +407,28 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         }
     };
 
-    // Epilogue of one site (sublattice a, row y, plane z) whose bilinear field
-    // sums are v[in][c].  One copy of this code serves every site of the
-    // thread: the caller selects the site's values from the register ring.
-    auto finish_site = [&](auto ac, int x, int y, int z, const T (&v)[NIN][3], const double (&e)[NE],
-                           const double (&so)[3]) __attribute__((always_inline)) {
+    // Corrector epilogue of one site (sublattice a, index j) whose bilinear
+    // field sums are v[in][c].  One copy serves every site of the thread;
+    // the caller selects the site's values from the register rings.
+    auto finish_corr = [&](auto ac, int64_t j, const T (&v)[NIN][3], const double (&e)[NE], const double (&so)[3])
+                           __attribute__((always_inline)) {
         constexpr int a = decltype(ac)::value;
-        const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
-        if constexpr (MODE == ZM_BIL) {
-            T *const bo = (T *)g.bout + boff;
+        double st[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) bo[c * N + i] = v[0][c];
-            return;
+        for (int c = 0; c < 3; ++c) st[c] = (kOwn && MODE != ZM_CORRECT) ? so[c] : g.S1[c * N + j];
+        double bt[3];
+        aniso_field(os, a, st, bt);
+        double B1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v1 = (double)v[NIN - 1][c] + bt[c] + os.bz[a][c];
+            if (g.bdip1) v1 += (double)g.bdip1[c * N + j];
+            B1[c] = v1 * hc.inv_mumuB[a];
         }
+        const double hdt = 0.5 * hc.dt;
+        double pn[3];
         if constexpr (MODE == ZM_CORRECT_P) {
-            double st[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) st[c] = kOwn ? so[c] : g.S1[c * N + i];
-            double bt[3];
-            aniso_field(os, a, st, bt);
-            double B1[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double v1 = (double)v[0][c] + bt[c] + os.bz[a][c];
-                if (g.bdip1) v1 += (double)g.bdip1[c * N + i];
-                B1[c] = v1 * hc.inv_mumuB[a];
-            }
+            // P = S^n + dt/2 f(S^n) and eta come from the predictor
             if (hc.noise) {
                 const double sg = hc.sigma[a];
 #pragma unroll
@@ -440,97 +436,25 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             }
             double f1[3];
             llg_rhs(st, B1, hc.pre, hc.alpha, f1);
-            const double hdt = 0.5 * hc.dt;
-            double p[3] = {e[0] + hdt * f1[0], e[1] + hdt * f1[1], e[2] + hdt * f1[2]};
-            normalise3(p);
-            g.out[i] = p[0];
-            g.out[N + i] = p[1];
-            g.out[2 * N + i] = p[2];
-            return;
-        }
-        // the spin of the state whose field this is (S^n): the thread's own
-        // staged value, except for the correctors that stage S~
-        constexpr bool kSvOwn = kOwn && (MODE == ZM_FIELD || MODE == ZM_PREDICT);
-        double sv[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sv[c] = kSvOwn ? so[c] : g.S0[c * N + i];
-        double ba[3];
-        aniso_field(os, a, sv, ba);
-        if constexpr (MODE == ZM_FIELD) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double b = (double)v[0][c] + ba[c] + os.bz[a][c];
-                if (g.bdip0) b += (double)g.bdip0[c * N + i];
-                ((T *)g.bout)[c * N + i] = (T)b;
-            }
-        } else if constexpr (MODE == ZM_PREDICT) {
-            double B[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (g.bstore) g.bstore[c * N + i] = (float)v[0][c];
-                double b = (double)v[0][c] + ba[c] + os.bz[a][c];
-                if (g.bdip0) b += (double)g.bdip0[c * N + i];
-                B[c] = b * hc.inv_mumuB[a];
-            }
-            if (hc.noise) {
-                double eta[3];
-                if (g.eload) {
-                    eta[0] = e[0];
-                    eta[1] = e[1];
-                    eta[2] = e[2];
-                } else {
-                    thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)i, eta);
-                }
-                const double sg = hc.sigma[a];
-                B[0] += sg * eta[0];
-                B[1] += sg * eta[1];
-                B[2] += sg * eta[2];
-                if (g.estore) {
-                    g.estore[i] = eta[0];
-                    g.estore[N + i] = eta[1];
-                    g.estore[2 * N + i] = eta[2];
-                }
-            }
-            double f[3];
-            llg_rhs(sv, B, hc.pre, hc.alpha, f);
-            if (g.pstore) {
-                const double hdt = 0.5 * hc.dt;
-                g.pstore[i] = sv[0] + hdt * f[0];
-                g.pstore[N + i] = sv[1] + hdt * f[1];
-                g.pstore[2 * N + i] = sv[2] + hdt * f[2];
-            }
-            double p[3] = {sv[0] + hc.dt * f[0], sv[1] + hc.dt * f[1], sv[2] + hc.dt * f[2]};
-            normalise3(p);
-            g.out[i] = p[0];
-            g.out[N + i] = p[1];
-            g.out[2 * N + i] = p[2];
+            for (int c = 0; c < 3; ++c) pn[c] = e[c] + hdt * f1[c];
         } else {
-            double st[3];
+            double sv[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) st[c] = (kOwn && MODE == ZM_CORRECT_STORED) ? so[c] : g.S1[c * N + i];
-            double bt[3];
-            aniso_field(os, a, st, bt);
-            double B0[3], B1[3];
+            for (int c = 0; c < 3; ++c) sv[c] = g.S0[c * N + j];
+            double ba[3];
+            aniso_field(os, a, sv, ba);
+            double B0[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double bil0, bil1;
-                if constexpr (MODE == ZM_CORRECT) {
-                    bil0 = (double)v[0][c];
-                    bil1 = (double)v[NIN - 1][c];
-                } else {
-                    bil0 = (double)g.bload[c * N + i];
-                    bil1 = (double)v[0][c];
-                }
+                const double bil0 = MODE == ZM_CORRECT ? (double)v[0][c] : (double)g.bload[c * N + j];
                 double v0 = bil0 + ba[c] + os.bz[a][c];
-                double v1 = bil1 + bt[c] + os.bz[a][c];
-                if (g.bdip0) v0 += (double)g.bdip0[c * N + i];
-                if (g.bdip1) v1 += (double)g.bdip1[c * N + i];
+                if (g.bdip0) v0 += (double)g.bdip0[c * N + j];
                 B0[c] = v0 * hc.inv_mumuB[a];
-                B1[c] = v1 * hc.inv_mumuB[a];
             }
             if (hc.noise) {
                 double eta[3];
-                thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)i, eta);
+                thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)j, eta);
                 const double sg = hc.sigma[a];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -541,14 +465,111 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             double f0[3], f1[3];
             llg_rhs(sv, B0, hc.pre, hc.alpha, f0);
             llg_rhs(st, B1, hc.pre, hc.alpha, f1);
-            const double hdt = 0.5 * hc.dt;
-            double p[3] = {sv[0] + hdt * (f0[0] + f1[0]), sv[1] + hdt * (f0[1] + f1[1]),
-                           sv[2] + hdt * (f0[2] + f1[2])};
-            normalise3(p);
-            g.out[i] = p[0];
-            g.out[N + i] = p[1];
-            g.out[2 * N + i] = p[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pn[c] = sv[c] + hdt * (f0[c] + f1[c]);
         }
+        normalise3(pn);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g.out[c * N + j] = pn[c];
+    };
+
+    // Field / predictor epilogue of the thread's NSUB sites (one per
+    // sublattice) in row y of plane z, whose bilinear field sums are
+    // v[a][in][c].  The work runs phase
+    // by phase across the sites, with no branch inside a phase, so that the
+    // sites' independent FP64 and Philox chains interleave; sites outside
+    // the lattice (valid = false) compute on a clamped index and store nothing.
+    auto finish_row = [&](int x, int y, int z, bool valid, const T (&v)[NSUB][NIN][3],
+                          const double (&e)[NSUB][NE], const double (&so)[NSUB][3]) __attribute__((always_inline)) {
+        int64_t i[NSUB], ir[NSUB];
+#pragma unroll
+        for (int a = 0; a < NSUB; ++a) {
+            i[a] = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
+            ir[a] = valid ? i[a] : 0;
+        }
+        if constexpr (MODE == ZM_BIL) {
+            T *const bo = (T *)g.bout + boff;
+            if (valid)
+#pragma unroll
+                for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) bo[c * N + i[a]] = v[a][0][c];
+            return;
+        }
+        // field and predictor: phase by phase across the sites.  Optional
+        // per-site inputs are each gathered under one uniform branch
+        double d0[NSUB][3] = {};
+        if (g.bdip0)
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) d0[a][c] = (double)g.bdip0[c * N + ir[a]];
+        double eta[NSUB][3] = {};
+        if constexpr (MODE != ZM_FIELD) {
+            if (hc.noise) {
+                if (MODE == ZM_PREDICT && g.eload) {
+#pragma unroll
+                    for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) eta[a][c] = e[a][c];
+                } else {
+                    const uint64_t ns = noise_step(hc, g.step);
+#pragma unroll
+                    for (int a = 0; a < NSUB; ++a) thermal_eta(hc.seed, ns, hc.tag, (uint64_t)i[a], eta[a]);
+                }
+            }
+        }
+        double out[NSUB][3];
+        {
+            // the spin of the state whose field this is: the thread's own
+            // staged value
+            double sv[NSUB][3], ba[NSUB][3];
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sv[a][c] = kOwn ? so[a][c] : g.S0[c * N + ir[a]];
+                aniso_field(os, a, sv[a], ba[a]);
+            }
+            if constexpr (MODE == ZM_FIELD) {
+                if (valid)
+#pragma unroll
+                    for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            ((T *)g.bout)[c * N + i[a]] = (T)((double)v[a][0][c] + ba[a][c] + os.bz[a][c] + d0[a][c]);
+                return;
+            } else if constexpr (MODE == ZM_PREDICT) {
+                double f[NSUB][3];
+#pragma unroll
+                for (int a = 0; a < NSUB; ++a) {
+                    double B[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        B[c] = ((double)v[a][0][c] + ba[a][c] + os.bz[a][c] + d0[a][c]) * hc.inv_mumuB[a] +
+                               hc.sigma[a] * eta[a][c];
+                    llg_rhs(sv[a], B, hc.pre, hc.alpha, f[a]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) out[a][c] = sv[a][c] + hc.dt * f[a][c];
+                    normalise3(out[a]);
+                }
+                if (valid) {
+                    const double hdt = 0.5 * hc.dt;
+#pragma unroll
+                    for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            if (g.bstore) g.bstore[c * N + i[a]] = (float)v[a][0][c];
+                            if (g.estore && hc.noise) g.estore[c * N + i[a]] = eta[a][c];
+                            if (g.pstore) g.pstore[c * N + i[a]] = sv[a][c] + hdt * f[a][c];
+                        }
+                }
+            }
+        }
+        if (valid)
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) g.out[c * N + i[a]] = out[a][c];
     };
 
     // acc[k] holds output plane o = q - (D-1) + k after input plane q has been
@@ -602,8 +623,9 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 // scheduling fence where the next sum reads another source
                 // sublattice: sums over one sublattice share their staged
                 // reads, and only that sublattice's values are live at a time
+                // (after every sum when two states are staged)
                 if constexpr (ks + 1 < NSUM) {
-                    if constexpr (SumC<KIND>::t.sums[ks + 1].b[0] != sm.b[0]) {
+                    if constexpr (NIN == 2 || SumC<KIND>::t.sums[ks + 1].b[0] != sm.b[0]) {
 #pragma unroll
                         for (int s2 = 0; s2 < D; ++s2)
 #pragma unroll
@@ -662,14 +684,16 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         }
         // output plane q - (D-1) (slot 0) has received all of its inputs
         const int o = q - (D - 1);
+        constexpr bool kCorr = MODE == ZM_CORRECT_P || MODE == ZM_CORRECT || MODE == ZM_CORRECT_STORED;
+        if constexpr (kCorr) {
         if (o >= 0 && o < nout) {
             const int x = x0 + tx;
             // sublattices unrolled (the on-site tables are indexed by a at
             // compile time), rows by a runtime loop with register selects
             static_for<NSUB>([&](auto ac) __attribute__((always_inline)) {
                 constexpr int a = decltype(ac)::value;
-                // rows go through one copy of the epilogue: row yb's sums are
-                // always in fin[0], shifted down after each row
+                // rows go through one copy of the epilogue: row yb's values
+                // are always in slot 0, shifted down after each row
                 T fin[kYB][NIN][3];
                 double ef[kYB][NE], sf[kYB][3];
 #pragma unroll
@@ -686,7 +710,9 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll 1
                 for (int yb = 0; yb < kYB; ++yb) {
                     const int y = y0 + ty * kYB + yb;
-                    if (x < g.Lx && y < g.Ly) finish_site(ac, x, y, zs + o, fin[0], ef[0], sf[0]);
+                    if (x < g.Lx && y < g.Ly)
+                        finish_corr(ac, (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * (zs + o)), fin[0],
+                                    ef[0], sf[0]);
 #pragma unroll
                     for (int k = 0; k + 1 < kYB; ++k) {
 #pragma unroll
@@ -700,6 +726,46 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                     }
                 }
             });
+        }
+        } else {
+        if (o >= 0 && o < nout) {
+            const int x = x0 + tx;
+            // rows go through one copy of the epilogue: row yb's values are
+            // always in slot 0 of these arrays, shifted down after each row
+            T fin[kYB][NSUB][NIN][3];
+            double ef[kYB][NSUB][NE], sf[kYB][NSUB][3];
+#pragma unroll
+            for (int yb = 0; yb < kYB; ++yb)
+#pragma unroll
+                for (int a = 0; a < NSUB; ++a) {
+#pragma unroll
+                    for (int in = 0; in < NIN; ++in)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) fin[yb][a][in][c] = acc[0][yb][a][c][in];
+#pragma unroll
+                    for (int k = 0; k < NE; ++k) ef[yb][a][k] = kEpiPre ? epi[yb][a][k] : 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sf[yb][a][c] = kOwn ? own[0][a * kYB + yb][c] : 0.0;
+                }
+#pragma unroll 1
+            for (int yb = 0; yb < kYB; ++yb) {
+                const int y = y0 + ty * kYB + yb;
+                finish_row(x, y, zs + o, x < g.Lx && y < g.Ly, fin[0], ef[0], sf[0]);
+#pragma unroll
+                for (int k = 0; k + 1 < kYB; ++k)
+#pragma unroll
+                    for (int a = 0; a < NSUB; ++a) {
+#pragma unroll
+                        for (int in = 0; in < NIN; ++in)
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) fin[k][a][in][c] = fin[k + 1][a][in][c];
+#pragma unroll
+                        for (int m = 0; m < NE; ++m) ef[k][a][m] = ef[k + 1][a][m];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) sf[k][a][c] = sf[k + 1][a][c];
+                    }
+            }
+        }
         }
         // rotate the ring: slot k <- k+1, the top slot starts a new plane
 #pragma unroll
