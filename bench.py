@@ -488,7 +488,7 @@ def heun_workload(args, w):
     kname = {("heun_predict", 2): "k_zmarch (predictor instantiation)",
              ("heun_correct", 2): "k_zmarch (corrector instantiation)",
              ("heun_predict", 1): "k_heun_predict", ("heun_correct", 1): "k_heun_correct"}
-    if info.stencil_engine == 2 and info.heun_field >= 5:
+    if info.stencil_engine == 2 and info.heun_field in (5, 6):
         # split predictor (modes 5, 6): one sweep = the bilinear-field stencil
         # pass + the elementwise stage kernel, timed together
         kname[("heun_predict", 2)] = "k_zmarch<ZM_BIL> + k_heun_pre (predictor sweep)"

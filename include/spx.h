@@ -123,7 +123,10 @@ typedef struct {
  * as 3), 5 split: each stage is a stencil pass that stores the FP32
  * bilinear field followed by an elementwise FP64 stage kernel (FP32
  * field_prec only; same results as 3), 6 split predictor with the fused
- * stored-stage corrector of mode 3 (FP32 field_prec only; same results). */
+ * stored-stage corrector of mode 3 (FP32 field_prec only; same results), 7
+ * as 3 without the noise store: the corrector draws the step's noise again
+ * from the same Philox block (24 bytes per spin of library memory; same
+ * results as 3). */
 typedef struct {
     int32_t field_prec;        /* spx_precision */
     int32_t backend;
@@ -242,7 +245,7 @@ typedef struct {
     int32_t stencil_engine;    /* 1 gather, 2 z-march */
     int32_t shape;             /* z-march shell shape id, -1 if none */
     int32_t zchunk;
-    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field, 3 stored stage and noise, 4 as 3 + noise pre-pass, 5 split, 6 split predictor */
+    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field, 3 stored stage and noise, 4 as 3 + noise pre-pass, 5 split, 6 split predictor, 7 stored stage, noise drawn again */
     int32_t tuned;             /* 1 if the autotuner chose zchunk / heun_field */
     double tuned_step_us;      /* its timing of one Heun step (microseconds) */
     int32_t heun_graph;        /* 1 once a captured Heun graph exists (replayed for runs of >= 4 steps) */

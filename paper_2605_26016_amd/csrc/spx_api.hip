@@ -178,11 +178,11 @@ struct spx_ham {
     ZPlan zp;
     ZPlan zp64;  // FP64 plan of the same table for batched-image field passes (GNEB)
     int engine = 1;          // 1 gather, 2 z-march
-    int heun_field = 1;      // 1 recompute, 2 stored FP32 field, 3 stored stage (P, eta)
+    int heun_field = 1;      // 1 recompute, 2 stored FP32 field, 3 stored stage (P, eta), 7 stored P only
     float *d_bstore = nullptr;
     void *d_ebil = nullptr;  // energy: bilinear field of the z-march pass (made at the first call)
     double *d_P = nullptr;   // heun_field 3: S^n + dt/2 f(S^n)
-    double *d_eta = nullptr; // heun_field 3: the step's thermal noise
+    double *d_eta = nullptr; // heun_field 3, 4, 5, 6: the step's thermal noise
     // Heun graph replay: 2-step graph with a device step counter
     uint64_t *d_step = nullptr;
     hipGraphExec_t heun_graph = nullptr;
@@ -319,6 +319,8 @@ spx_status get_ham_view(spx_ham *h, HamView &v) {
 
 static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z, bool tune_field, hipStream_t st);
 static spx_status heun_buffers(spx_ham *h, int hf);
+// Heun modes of the z-march engine: 1 .. kMaxHeunMode (spx_options.heun_field)
+constexpr int kMaxHeunMode = 7;
 
 extern "C" {
 
@@ -353,8 +355,8 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     const int hfield_req = opts ? opts->heun_field : 0;
     if (engine_req < 0 || engine_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown stencil_engine");
     if (zchunk_req < 0 || zchunk_req > 4096) return fail(SPX_ERR_INVALID_ARG, "zchunk out of range");
-    if (hfield_req < 0 || hfield_req > 6) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
-    if ((hfield_req == 2 || hfield_req >= 5) && prec != SPX_FP32)
+    if (hfield_req < 0 || hfield_req > kMaxHeunMode) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
+    if ((hfield_req == 2 || hfield_req == 5 || hfield_req == 6) && prec != SPX_FP32)
         return fail(SPX_ERR_INVALID_ARG, "a stored FP32 Heun field needs field_prec SPX_FP32");
     if (model->n_shells < 0 || model->n_bonds < 0 || model->n_aniso < 0)
         return fail(SPX_ERR_INVALID_ARG, "negative counts in model descriptor");
@@ -476,7 +478,7 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
         (s = dev_alloc(h, &h->d_Jd, std::max<size_t>(Jd.size(), 1), "couplings fp64")) != SPX_OK ||
         (s = dev_alloc(h, &h->d_St, n3, "Heun predictor state")) != SPX_OK ||
         (s = dev_alloc(h, &h->d_Sp, n3, "Heun ping-pong state")) != SPX_OK ||
-        (s = dev_alloc(h, &h->d_partial, (size_t)energy_partial_count(g) * 4, "energy partials")) != SPX_OK) {
+        (s = dev_alloc(h, &h->d_partial, energy_partial_doubles(g), "energy partials")) != SPX_OK) {
         free_all(h);
         delete h;
         return s;
@@ -659,7 +661,7 @@ static spx_status enqueue_heun_step(spx_ham *h, const HeunConst &hc, uint64_t st
         e = zmarch_noise(hc, step, h->grid.N, h->d_eta, st);
         if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: noise");
     }
-    if (h->engine == 2 && h->heun_field >= 5) {
+    if (h->engine == 2 && (h->heun_field == 5 || h->heun_field == 6)) {
         // split predictor: stencil pass for the FP32 bilinear field, then the
         // elementwise FP64 stage; corrector split (mode 5) or fused (mode 6)
         {
@@ -713,7 +715,8 @@ static spx_status enqueue_heun_step(spx_ham *h, const HeunConst &hc, uint64_t st
         if (h->engine == 2)
             e = zmarch_correct(h->zp, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1,
                                h->heun_field == 2 ? h->d_bstore : nullptr, h->heun_field >= 3 ? h->d_P : nullptr,
-                               (h->heun_field >= 3 && hc.noise) ? h->d_eta : nullptr, nxt, st);
+                               (h->heun_field >= 3 && h->heun_field != 7 && hc.noise) ? h->d_eta : nullptr, nxt,
+                               st);
         else
             e = launch_heun_correct(h->field_prec, h->tab, h->grid, h->onsite, hc, step, cur, h->d_St, bd0, bd1, nxt,
                                     st);
@@ -735,27 +738,27 @@ __global__ void k_fill_up(double *S, int64_t N) {
 static spx_status heun_buffers(spx_ham *h, int hf) {
     const size_t n3 = (size_t)3 * h->grid.N;
     spx_status s = SPX_OK;
-    if ((hf == 2 || hf >= 5) && !h->d_bstore) s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field");
+    if ((hf == 2 || hf == 5 || hf == 6) && !h->d_bstore) s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field");
     if (s == SPX_OK && hf >= 3 && !h->d_P) s = dev_alloc(h, &h->d_P, n3, "stored Heun stage");
-    if (s == SPX_OK && hf >= 3 && !h->d_eta) s = dev_alloc(h, &h->d_eta, n3, "stored Heun noise");
+    if (s == SPX_OK && hf >= 3 && hf != 7 && !h->d_eta) s = dev_alloc(h, &h->d_eta, n3, "stored Heun noise");
     return s;
 }
 
 // Frees the stores that the selected mode does not use.
 static void heun_buffers_trim(spx_ham *h) {
     const int64_t n3 = 3 * h->grid.N;
-    if (h->heun_field != 2 && h->heun_field < 5 && h->d_bstore) {
+    if (h->heun_field != 2 && h->heun_field != 5 && h->heun_field != 6 && h->d_bstore) {
         (void)hipFree(h->d_bstore);
         h->d_bstore = nullptr;
         h->ws_bytes -= (int64_t)sizeof(float) * n3;
     }
-    if (h->heun_field < 3) {
-        for (double **p : {&h->d_P, &h->d_eta})
-            if (*p) {
-                (void)hipFree(*p);
-                *p = nullptr;
-                h->ws_bytes -= (int64_t)sizeof(double) * n3;
-            }
+    for (double **p : {&h->d_P, &h->d_eta}) {
+        const bool used = h->heun_field >= 3 && !(p == &h->d_eta && h->heun_field == 7);
+        if (!used && *p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+            h->ws_bytes -= (int64_t)sizeof(double) * n3;
+        }
     }
 }
 
@@ -778,11 +781,11 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
             int cz = 0, chf = 0;
             double cus = 0.0;
             while (std::fscanf(f, "%159s %d %d %lf", k2, &z, &hf, &us) == 4)
-                if (std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && hf >= 1 && hf <= 6) {
+                if (std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && hf >= 1 && hf <= kMaxHeunMode) {
                     cz = z; chf = hf; cus = us; hit = true;   // the last matching line wins
                 }
             std::fclose(f);
-            if (hit && !((chf == 2 || chf >= 5) && h->field_prec != SPX_FP32)) {
+            if (hit && !((chf == 2 || chf == 5 || chf == 6) && h->field_prec != SPX_FP32)) {
                 if (tune_z) h->zp.zch = cz;
                 if (tune_field) h->heun_field = chf;
                 h->tune_us = cus;
@@ -802,8 +805,8 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
     }
     std::vector<int> hfs = {h->heun_field};
     if (tune_field) {
-        hfs = {1, 3, 4};
-        if (h->field_prec == SPX_FP32) hfs = {1, 2, 3, 4, 5, 6};
+        hfs = {1, 3, 4, 7};
+        if (h->field_prec == SPX_FP32) hfs = {1, 2, 3, 4, 5, 6, 7};
     }
     for (int hf : hfs) {
         spx_status s = heun_buffers(h, hf);

@@ -77,6 +77,10 @@ hipError_t launch_heun_correct(int field_prec, const BondTable &tb, const Grid &
 // Energy partials: partial[block][4] (bil, Z, ani, dip), then a fixed-order
 // final reduction into E (1 double) and terms (5 doubles, may be NULL).
 int energy_partial_count(const Grid &g);
+// Second-level quadruples of the energy reduction, stored after the first level.
+constexpr int kEnergyL2 = 1024;
+// Doubles of the energy partial buffer (both levels).
+size_t energy_partial_doubles(const Grid &g);
 // bil: precomputed bilinear field (double for field_prec 0, float otherwise)
 // or NULL to gather the neighbours.
 hipError_t launch_energy(int field_prec, const BondTable &tb, const Grid &g, const Onsite &os,

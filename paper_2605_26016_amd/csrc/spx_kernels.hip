@@ -6,6 +6,8 @@
 // its table loads are uniform over a block and go through the scalar unit),
 // blockIdx.x * 256 + threadIdx.x is the site inside that sublattice, x fastest
 // (coalesced SoA loads of the three spin planes).
+#include <algorithm>
+
 #include "spx_device.hpp"
 
 namespace spx {
@@ -248,6 +250,31 @@ __global__ __launch_bounds__(kBlock) void k_energy_partial(BondTable tb, Grid g,
     }
 }
 
+// Middle level of the fixed-order reduction: block b sums partial quadruples
+// [b chunk, min(n, (b + 1) chunk)) into out[b][4], so that the one-block final
+// pass reads at most kEnergyL2 quadruples however large the lattice.
+__global__ __launch_bounds__(kBlock) void k_energy_reduce(const double *__restrict__ partial, int n, int chunk,
+                                                          double *__restrict__ out) {
+    __shared__ double red[kBlock / 64][4];
+    const int p0 = blockIdx.x * chunk, p1 = min(n, p0 + chunk);
+    double e[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = p0 + threadIdx.x; p < p1; p += kBlock)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] += partial[(size_t)p * 4 + k];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double v = wave_sum(e[k]);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) v += red[w][threadIdx.x];
+        out[(size_t)blockIdx.x * 4 + threadIdx.x] = v;
+    }
+}
+
 // Fixed-order final reduction of n partial quadruples by one block.
 __global__ __launch_bounds__(kBlock) void k_energy_final(const double *__restrict__ partial, int n,
                                                          double *__restrict__ E, double *__restrict__ terms) {
@@ -282,6 +309,8 @@ int energy_partial_count(const Grid &g) {
     return (int)(((g.M + kBlock - 1) / kBlock) * g.n_sub);
 }
 
+size_t energy_partial_doubles(const Grid &g) { return (size_t)4 * ((size_t)energy_partial_count(g) + kEnergyL2); }
+
 hipError_t launch_energy(int field_prec, const BondTable &tb, const Grid &g, const Onsite &os,
                          const double *S, const float *bdip, const void *bil, double *partial, double *E,
                          double *terms, hipStream_t st) {
@@ -297,7 +326,17 @@ hipError_t launch_energy(int field_prec, const BondTable &tb, const Grid &g, con
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_energy_final<<<1, kBlock, 0, st>>>(partial, energy_partial_count(g), E, terms);
+    const int n = energy_partial_count(g);
+    if (n <= 8 * kBlock) {
+        k_energy_final<<<1, kBlock, 0, st>>>(partial, n, E, terms);
+        return hipGetLastError();
+    }
+    // two levels: at most kEnergyL2 blocks of at least 8 kBlock quadruples
+    const int nb = (int)std::min<int64_t>(kEnergyL2, ((int64_t)n + 8 * kBlock - 1) / (8 * kBlock));
+    const int chunk = (int)(((int64_t)n + nb - 1) / nb);
+    double *mid = partial + (size_t)4 * n;
+    k_energy_reduce<<<nb, kBlock, 0, st>>>(partial, n, chunk, mid);
+    k_energy_final<<<1, kBlock, 0, st>>>(mid, nb, E, terms);
     return hipGetLastError();
 }
 

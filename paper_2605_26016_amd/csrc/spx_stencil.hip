@@ -50,8 +50,8 @@ constexpr int kThreads = kTX * kTYT;
 
 // ZM_CORRECT: recompute the fields of S^n and S~; ZM_CORRECT_STORED: read the
 // predictor's FP32 bilinear field of S^n; ZM_CORRECT_P: read the predictor's
-// partial update P = S^n + dt/2 f(S^n) and its noise eta (FP64), so that the
-// corrector evaluates only f(S~).
+// partial update P = S^n + dt/2 f(S^n) and its noise eta (FP64; or draw eta
+// again when it was not stored), so that the corrector evaluates only f(S~).
 // ZM_BIL: store only the FP32 bilinear field (the split Heun mode's stencil
 // pass; the Heun stages then run as elementwise kernels).
 enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4, ZM_BIL = 5 };
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 if constexpr (MODE == ZM_CORRECT_P) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) e[c] = g.pload[c * N + i];
-                    if (hc.noise)
+                    if (hc.noise && g.eload)
 #pragma unroll
                         for (int c = 0; c < 3; ++c) e[3 + c] = g.eload[c * N + i];
                 } else if constexpr (MODE == ZM_PREDICT) {
@@ -428,11 +428,19 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         const double hdt = 0.5 * hc.dt;
         double pn[3];
         if constexpr (MODE == ZM_CORRECT_P) {
-            // P = S^n + dt/2 f(S^n) and eta come from the predictor
+            // P = S^n + dt/2 f(S^n) comes from the predictor; eta too, or it
+            // is drawn again here (the same Philox block)
             if (hc.noise) {
+                double eta[3];
+                if (g.eload) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) eta[c] = e[3 + c];
+                } else {
+                    thermal_eta(hc.seed, noise_step(hc, g.step), hc.tag, (uint64_t)j, eta);
+                }
                 const double sg = hc.sigma[a];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) B1[c] += sg * e[3 + c];
+                for (int c = 0; c < 3; ++c) B1[c] += sg * eta[c];
             }
             double f1[3];
             llg_rhs(st, B1, hc.pre, hc.alpha, f1);
@@ -1109,10 +1117,7 @@ hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, cons
     a.pload = pload;
     a.eload = eload;
     a.step = step;
-    if (pload) {
-        if (hc.noise && !eload) return hipErrorInvalidValue;
-        return launch_any<ZM_CORRECT_P>(zp, a, os, hc, st);
-    }
+    if (pload) return launch_any<ZM_CORRECT_P>(zp, a, os, hc, st);  // eload NULL: noise drawn again
     if (bload) return launch_any<ZM_CORRECT_STORED>(zp, a, os, hc, st);
     return launch_any<ZM_CORRECT>(zp, a, os, hc, st);
 }

@@ -164,6 +164,29 @@ def test_energy_parity(name, w, prec, tol, engine):
     assert E2.item() == E.item()
 
 
+@pytest.mark.parametrize("L", [(128, 64, 128), (97, 101, 103)])
+def test_energy_two_level_reduction(L):
+    # more than 8 x 256 block partials: the sum goes through the middle level
+    # of the fixed-order reduction (several sites per middle block, a ragged
+    # last chunk for the odd extents)
+    import torch
+    from paper_2605_26016_amd import spx
+    w = Workload(name="e2", L=L, J_shell=(1.0, -0.3), D_shell=(0.2, 0.0), K=0.1, K_axis=(0.0, 0.0, 1.0),
+                 B=(0.0, 0.5, 2.0), field_prec="fp64")
+    S = random_sphere(w.N, 43)
+    ref = oracle.energy(oracle_model(w), S)
+    h = gpu_hamiltonian(w)
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    terms = torch.zeros(5, dtype=torch.float64, device="cuda")
+    spx.energy(h, to_dev(S), E, terms)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(terms.cpu().numpy() - ref)) <= 1e-12 * scale
+    assert abs(E.item() - ref[4]) <= 1e-12 * scale
+    E2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    spx.energy(h, to_dev(S), E2)
+    assert E2.item() == E.item()
+
+
 def gpu_heun(w, S, prec, setup=None, **kw):
     import torch
     from paper_2605_26016_amd import spx
@@ -189,11 +212,11 @@ HEUN_CASES = [
 
 HEUN_SETUPS = [dict(stencil_engine=1), dict(stencil_engine=0, heun_field=1),
                dict(stencil_engine=0, heun_field=3), dict(stencil_engine=0, heun_field=4),
-               dict(stencil_engine=0, heun_field=0, zchunk=3)]
+               dict(stencil_engine=0, heun_field=7), dict(stencil_engine=0, heun_field=0, zchunk=3)]
 
 
 @pytest.mark.parametrize("setup", HEUN_SETUPS, ids=["gather", "zmarch_recompute", "zmarch_stage",
-                                                     "zmarch_noisepass", "auto_z3"])
+                                                     "zmarch_noisepass", "zmarch_stage_redraw", "auto_z3"])
 @pytest.mark.parametrize("name,w,prec,extra,tol", HEUN_CASES, ids=[c[0] for c in HEUN_CASES])
 def test_heun_parity(name, w, prec, extra, tol, setup):
     S = w.initial_state() if w.init != "random" else random_sphere(w.N, 51)
@@ -226,6 +249,9 @@ def test_heun_stored_field_equals_recompute():
     assert np.array_equal(c, e)
     f = gpu_heun(w, S, "fp32", setup=dict(heun_field=6), **kw)
     assert np.array_equal(c, f)
+    # the corrector that draws the noise again gets the same numbers
+    g = gpu_heun(w, S, "fp32", setup=dict(heun_field=7), **kw)
+    assert np.array_equal(c, g)
     # deterministic case (no noise store)
     kw["temperature_K"] = 0.0
     a = gpu_heun(w, S, "fp32", setup=dict(heun_field=1), **kw)
@@ -235,6 +261,20 @@ def test_heun_stored_field_equals_recompute():
     assert np.array_equal(c, e)
     f = gpu_heun(w, S, "fp32", setup=dict(heun_field=6), **kw)
     assert np.array_equal(c, f)
+    g = gpu_heun(w, S, "fp32", setup=dict(heun_field=7), **kw)
+    assert np.array_equal(c, g)
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3, 4, 5, 6, 7])
+def test_autotuner_reads_every_mode_from_its_cache(tmp_path, mode):
+    # a cached choice of any Heun mode is taken as is, without tuning again
+    from paper_2605_26016_amd import spx
+    w = bcc_5shell_stochastic((16, 16, 16))
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"shape3_prec1_sub2_16x16x16_per111 8 {mode} 123.5\n")
+    info = spx.get_info(gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=str(cache)))
+    assert (info.tuned, info.zchunk, info.heun_field, info.tuned_step_us) == (1, 8, mode, 123.5)
+    assert cache.read_text().count("\n") == 1
 
 
 def test_heun_resume_and_determinism():
@@ -359,7 +399,7 @@ def test_autotuner_picks_candidate_and_caches(tmp_path):
     cache = str(tmp_path / "tune.txt")
     h = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache)
     info = spx.get_info(h)
-    assert info.tuned == 1 and info.zchunk in (4, 8, 16) and info.heun_field in (1, 2, 3, 4, 5, 6)
+    assert info.tuned == 1 and info.zchunk in (4, 8, 16) and info.heun_field in (1, 2, 3, 4, 5, 6, 7)
     assert info.tuned_step_us > 0
     lines = open(cache).read().split("\n")
     assert any(l.startswith("shape3_prec1_sub2_16x16x16") for l in lines)
