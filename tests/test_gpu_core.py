@@ -54,6 +54,15 @@ FIELD_CASES = [
                                      B=(0.1, -0.3, 0.5)), "fp64", 1e-13),
     ("sc_frustrated_open", Workload(name="t", L=(11, 10, 9), periodic=(0, 0, 0),
                                     J_shell=(1.0, 0.188, -0.274, -0.161)), "fp64", 1e-13),
+    # several 64 x 8 tiles with ragged x and y tails; tile counts divisible by
+    # 8 (XCD-contiguous tile order) at the default z chunk
+    ("sc3_fp32_multitile", Workload(name="t", L=(100, 20, 32), periodic=(1, 0, 1),
+                                    J_shell=(1.0, -0.3, 0.15), K=0.1, B=(0.2, 0.0, 0.4)), "fp32", 1e-5),
+    ("sc3_fp64_multitile", Workload(name="t", L=(100, 20, 32), periodic=(0, 1, 1),
+                                    J_shell=(1.0, -0.3, 0.15)), "fp64", 1e-13),
+    ("sc4_fp32_multitile", Workload(name="t", L=(70, 9, 16), periodic=(1, 1, 0),
+                                    J_shell=(1.0, 0.188, -0.274, -0.161)), "fp32", 1e-5),
+    ("bcc_fp32_multitile", bcc_5shell_stochastic((65, 17, 32)), "fp32", 1e-5),
 ]
 
 
@@ -204,6 +213,10 @@ HEUN_CASES = [
     ("bcc_stoch_fp32_1", bcc_5shell_stochastic((6, 5, 4)), "fp32", dict(n_steps=1), 1e-9),
     ("bcc_stoch_fp64_3", bcc_5shell_stochastic((6, 5, 4)), "fp64", dict(n_steps=3), 1e-12),
     ("sc_stoch_fp32_1", sc_billion((12, 11, 10)), "fp32", dict(n_steps=1), 1e-9),
+    ("bcc_stoch_fp32_multitile", bcc_5shell_stochastic((65, 17, 16)), "fp32", dict(n_steps=2), 1e-9),
+    ("sc3_stoch_fp32_multitile", Workload(name="t", L=(100, 20, 16), periodic=(1, 0, 1),
+                                          J_shell=(1.0, -0.3, 0.15), K=0.1, B=(0.2, 0.0, 0.4), T_K=300.0,
+                                          alpha=0.1, dt_fs=0.5, philox_seed=9), "fp32", dict(n_steps=2), 1e-9),
     ("dmi_zeeman_open_fp64", Workload(name="t", L=(7, 6, 5), periodic=(0, 0, 0), J_shell=(1.0,),
                                       D_shell=(0.3,), B=(0.0, 0.0, 0.5), mu=(2.0,), K=0.1, alpha=0.3,
                                       dt_fs=1.0, T_K=10.0, philox_seed=77), "fp64", dict(n_steps=2), 1e-12),
