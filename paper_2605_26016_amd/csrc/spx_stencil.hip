@@ -8,13 +8,20 @@
 // fill at open faces done here, so the compute loop has no boundary logic --
 // into registers while the previous plane is being computed, then written to
 // a double-buffered LDS slot, converted to the compute type (float in mixed
-// mode).  Every bond (compile-time offset, runtime coupling) then pushes
-// J S_b(x+dx, y+dy, z') into a register accumulator of output plane z' - dz;
-// the accumulators of the D = dzhi - dzlo + 1 pending output planes form a
-// register ring that shifts by one slot per input plane, so every bond's slot
-// (dzhi - dz) is a compile-time register.  An output plane is final once its
-// highest input plane has been pushed; a single copy of the epilogue then adds
-// the on-site terms in FP64 and runs the Heun stage for each of its sites.
+// mode).  Each thread stages its own interior sites first and keeps their
+// FP64 spins in a small register ring until its epilogue needs them.
+//
+// Every bond (compile-time offset, runtime coupling) pushes J S_b(x+dx, y+dy,
+// z') into a register accumulator of output plane z' - dz; with isotropic
+// shells the bonds that share J are summed first (shared partial sums, one
+// multiply per use).  The accumulators of the D = dzhi - dzlo + 1 pending
+// output planes form a register ring that shifts by one slot per input plane,
+// so every bond's slot (dzhi - dz) is a compile-time register.  An output
+// plane is final once its highest input plane has been pushed; one copy of
+// the epilogue then adds the on-site terms in FP64 and runs the Heun stage
+// for the thread's sites (the predictor across its sublattice sites phase by
+// phase, the correctors site by site), with the corrector's stored stage
+// fetched one plane ahead.
 #include <type_traits>
 #include <vector>
 
