@@ -83,6 +83,17 @@ hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bi
 // Bilinear field of n_img images stacked as [n_img][3][N] (FP64 plan, FP64
 // output).  The source buffer is S0, or S0alt when *sel != 0 (a device flag);
 // nothing is done when *skip != 0 (skip may be NULL).
+// Tiles of one image (x tiles x y tiles x z chunks) of the z-march engine.
+int zmarch_tiles(const ZPlan &zp, const Grid &g);
+// First GNEB pass fused into the FP64 z-march over the images of an instance
+// (buffer S0, or S0alt when *sel != 0; no-op when *skip != 0): writes the
+// projected force of interior images into F [n_img][3][N] and one (energy,
+// squared distance to the next image) partial per tile into
+// partial[(item0 + img items_per_img + tile) * 2 + {0, 1}].  Needs FP64 and
+// zmarch_tiles() <= items_per_img.
+hipError_t zmarch_gneb_a(const ZPlan &zp, const Grid &g, const Onsite &os, int n_img, const double *S0,
+                         const double *S0alt, const double *sel, const double *skip, double *F, double *partial,
+                         int item0, int items_per_img, hipStream_t st);
 hipError_t zmarch_bil_images(const ZPlan &zp, const Grid &g, int n_img, const double *S0, const double *S0alt,
                              const double *sel, const double *skip, double *bil, hipStream_t st);
 hipError_t heun_split_pre(const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step, const double *S,

@@ -7,6 +7,8 @@
 // flat list; each per-site pass is one grid-stride launch over the items of
 // all instances.  One iteration is
 //   pass A  (all images)      field, energy, projected force F, distance terms
+//                             (inside the z-march over the images when the
+//                             shell shape has one: one partial per tile)
 //   reduce  (per image)       E_n, d(Y_n, Y_n+1)^2           fixed order
 //   scalars (per instance)    climbing image, tangent weights
 //   pass B  (movable images)  tangent tau, dots tau.tau F.tau v.tau v.F F.F
@@ -59,6 +61,10 @@ struct GInst {
     // bilinear field of every image from the batched z-march pass
     // ([n_img][3][N], FP64); NULL: pass A gathers the neighbours itself
     const double *Bbil;
+    // > 0: pass A runs inside the z-march over the images, which leaves this
+    // many (energy, distance) partials per image (one per tile) in the
+    // image's first item slots; k_gneb_a then skips the instance
+    int zt_per_img;
 };
 
 struct GItem {
@@ -148,6 +154,7 @@ __global__ __launch_bounds__(kGB) void k_gneb_a(const GInst *__restrict__ inst, 
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const GItem itm = items[it];
         const GInst &G = inst[itm.inst];
+        if (G.zt_per_img > 0) continue;  // done by the fused z-march pass (uniform over the block)
         double e = 0.0, d2 = 0.0;
         const bool active = G.st[ST_DONE] == 0.0;
         if (active) {
@@ -216,16 +223,18 @@ __device__ __forceinline__ bool gate_open(const GInst &G, int gate) {
 
 __global__ __launch_bounds__(kGB) void k_gneb_reduce(const GInst *__restrict__ inst, const int2 *__restrict__ imgs,
                                                      const double *__restrict__ partial, int nv, int base,
-                                                     int only_movable, int gate, int take_max) {
+                                                     int only_movable, int gate, int take_max, int pass_a = 0) {
     __shared__ double red[kGB / 64];
     const int2 ii = imgs[blockIdx.x];
     const GInst &G = inst[ii.x];
     if (!gate_open(G, gate)) return;
     if (only_movable && (ii.y == 0 || ii.y == G.n_img - 1)) return;
     const int first = G.item0 + ii.y * G.items_per_img;
+    // the fused first pass leaves one partial per z-march tile
+    const int count = (pass_a && G.zt_per_img > 0) ? G.zt_per_img : G.items_per_img;
     for (int v = 0; v < nv; ++v) {
         double s = 0.0;
-        for (int k = threadIdx.x; k < G.items_per_img; k += kGB) {
+        for (int k = threadIdx.x; k < count; k += kGB) {
             const double x = partial[(size_t)(first + k) * nv + v];
             s = take_max ? fmax(s, x) : s + x;
         }
@@ -626,7 +635,8 @@ struct spx_gneb {
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;  // library-owned capture stream (the caller's may be the null stream)
     int use_graph = 1;
-    std::vector<ZPlan> zplan;  // per instance: FP64 z-march plan (used when its Bbil is set)
+    std::vector<ZPlan> zplan;  // per instance: FP64 z-march plan (used when its Bbil or zt_per_img is set)
+    std::vector<Onsite> hos;   // per instance: host copy of the on-site tables (fused first pass)
 };
 
 namespace {
@@ -667,13 +677,19 @@ hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
     const unsigned gi = grid_for(g->n_items);
     for (int k = 0; k < g->n_inst; ++k) {
         const GInst &G = g->hinst[k];
-        if (!G.Bbil) continue;
-        hipError_t e = zmarch_bil_images(g->zplan[k], G.g, G.n_img, G.Y[0], G.Y[1], G.st + ST_CUR, G.st + ST_DONE,
-                                         (double *)G.Bbil, st);
+        hipError_t e = hipSuccess;
+        if (G.zt_per_img > 0)
+            e = zmarch_gneb_a(g->zplan[k], G.g, g->hos[k], G.n_img, G.Y[0], G.Y[1], G.st + ST_CUR, G.st + ST_DONE,
+                              G.F, g->d_partial, G.item0, G.items_per_img, st);
+        else if (G.Bbil)
+            e = zmarch_bil_images(g->zplan[k], G.g, G.n_img, G.Y[0], G.Y[1], G.st + ST_CUR, G.st + ST_DONE,
+                                  (double *)G.Bbil, st);
         if (e != hipSuccess) return e;
     }
-    k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0, GATE_ITER, 0);
+    bool any_elementwise_a = false;  // an instance whose first pass is not fused into the z-march
+    for (const GInst &G : g->hinst) any_elementwise_a = any_elementwise_a || G.zt_per_img == 0;
+    if (any_elementwise_a) k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0, GATE_ITER, 0, 1);
     k_gneb_scalars1<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
     k_gneb_b<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
     k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 5, IS_TT, 1, GATE_ITER, 0);
@@ -741,6 +757,7 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         gi.ci_on_below = p->ci_on_below;
         gi.tol = p->tol_force;
         onsites[k] = v.onsite;
+        g->hos.push_back(v.onsite);
         // the batched z-march field pass needs an FP64 plan of the table
         gi.Bbil = nullptr;
         g->zplan.push_back(v.zp64 ? *v.zp64 : ZPlan{});
@@ -774,7 +791,10 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         if ((s = gneb_alloc(g, (void **)&gi.st, sizeof(double) * ST_N, "GNEB state")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.alpha, sizeof(double) * gi.n_img, "GNEB image spacing")) != SPX_OK) break;
         const ZPlan &zp = g->zplan[k];
-        if (zp.valid) {
+        gi.zt_per_img = 0;
+        if (zp.valid && zp.prec == 0 && zmarch_tiles(zp, gi.g) <= gi.items_per_img) {
+            gi.zt_per_img = zmarch_tiles(zp, gi.g);  // first pass fused into the z-march
+        } else if (zp.valid) {
             if ((s = gneb_alloc(g, (void **)&gi.Bbil, n3 * sizeof(double), "GNEB bilinear field")) != SPX_OK) break;
         }
     }

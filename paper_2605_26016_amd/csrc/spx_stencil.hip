@@ -61,7 +61,13 @@ constexpr int kThreads = kTX * kTYT;
 // again when it was not stored), so that the corrector evaluates only f(S~).
 // ZM_BIL: store only the FP32 bilinear field (the split Heun mode's stencil
 // pass; the Heun stages then run as elementwise kernels).
-enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4, ZM_BIL = 5 };
+// ZM_GNEB_A: over the images of a GNEB instance, the per-site work of the
+// first GNEB pass in the epilogue (energy terms, the force projected on the
+// tangent plane of the spin for interior images, the squared geodesic
+// distance to the next image), reduced to one (energy, distance) partial per
+// block in place of storing the field.
+enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4, ZM_BIL = 5,
+             ZM_GNEB_A = 6 };
 
 template <typename T, int NW>
 struct ZWeights {
@@ -95,6 +101,10 @@ struct ZArgs {
     int xcd;
     const double *S0alt;
     const double *sel, *skip;
+    // ZM_GNEB_A: forces [nimg][3][N], partials [(gitem0 + img gipi + tile) * 2 + {0,1}]
+    double *gF;
+    double *gpart;
+    int gitem0, gipi;
 };
 
 // Shape table as a static constant, so that every bond read in an unrolled
@@ -262,12 +272,13 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // fetched one march iteration before their use so that their latency
     // hides behind a plane's stencil: CORRECT_P reads P and eta, PREDICT
     // reads eta when the noise comes from a pre-pass.
-    constexpr bool kEpiPre = MODE == ZM_CORRECT_P || MODE == ZM_PREDICT;
-    constexpr int NE = MODE == ZM_CORRECT_P ? 6 : MODE == ZM_PREDICT ? 3 : 1;
+    constexpr bool kEpiPre = MODE == ZM_CORRECT_P || MODE == ZM_PREDICT || MODE == ZM_GNEB_A;
+    constexpr int NE = MODE == ZM_CORRECT_P ? 6 : (MODE == ZM_PREDICT || MODE == ZM_GNEB_A) ? 3 : 1;
     double epi[kYB][NSUB][NE];
     auto fetch_epi = [&](int o) __attribute__((always_inline)) {
         if (o < 0 || o >= nout) return;  // uniform over the block
         if (MODE == ZM_PREDICT && !(hc.noise && g.eload)) return;
+        if (MODE == ZM_GNEB_A && img >= g.nimg - 1) return;  // the last image has no successor
         const int x = x0 + tx;
         static_for<NSUB>([&](auto ac) __attribute__((always_inline)) {
             constexpr int a = decltype(ac)::value;
@@ -286,6 +297,10 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 } else if constexpr (MODE == ZM_PREDICT) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) e[c] = g.eload[c * N + i];
+                } else if constexpr (MODE == ZM_GNEB_A) {
+                    // the next image of the same buffer
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) e[c] = S0[g.bstride + c * N + i];
                 }
             }
         });
@@ -494,6 +509,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // by phase across the sites, with no branch inside a phase, so that the
     // sites' independent FP64 and Philox chains interleave; sites outside
     // the lattice (valid = false) compute on a clamped index and store nothing.
+    double gE = 0.0, gD = 0.0;  // ZM_GNEB_A: the thread's energy and squared-distance sums
     auto finish_row = [&](int x, int y, int z, bool valid, const T (&v)[NSUB][NIN][3],
                           const double (&e)[NSUB][NE], const double (&so)[NSUB][3]) __attribute__((always_inline)) {
         int64_t i[NSUB], ir[NSUB];
@@ -509,6 +525,41 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 for (int a = 0; a < NSUB; ++a)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) bo[c * N + i[a]] = v[a][0][c];
+            return;
+        }
+        if constexpr (MODE == ZM_GNEB_A) {
+            if (!valid) return;
+            const bool interior = img > 0 && img < g.nimg - 1;
+            const bool has_next = img < g.nimg - 1;
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a) {
+                double ba[3];
+                aniso_field(os, a, so[a], ba);
+                double b[3], sb = 0.0, sz = 0.0, sa = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double bil = (double)v[a][0][c];
+                    b[c] = bil + ba[c] + os.bz[a][c];
+                    sb += so[a][c] * bil;
+                    sz += so[a][c] * os.bz[a][c];
+                    sa += so[a][c] * ba[c];
+                }
+                gE += -0.5 * sb - sz - 0.5 * sa;
+                if (interior) {
+                    const double bs = b[0] * so[a][0] + b[1] * so[a][1] + b[2] * so[a][2];
+                    double *F = g.gF + boff;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) F[c * N + i[a]] = b[c] - bs * so[a][c];
+                }
+                if (has_next) {
+                    // geodesic angle atan2(|s x s'|, s.s')
+                    const double *p = so[a], *q = e[a];
+                    const double c0 = p[1] * q[2] - p[2] * q[1], c1 = p[2] * q[0] - p[0] * q[2],
+                                 c2 = p[0] * q[1] - p[1] * q[0];
+                    const double th = atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), p[0] * q[0] + p[1] * q[1] + p[2] * q[2]);
+                    gD += th * th;
+                }
+            }
             return;
         }
         // field and predictor: phase by phase across the sites.  Optional
@@ -810,6 +861,22 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         if constexpr (kEpiPre) fetch_epi(q - D + 2);
         __syncthreads();
     }
+    if constexpr (MODE == ZM_GNEB_A) {
+        // fixed-order block sums of the two statistics, one partial pair per tile
+        __shared__ double gred[2][kThreads / 64];
+        const double se = wave_sum(gE), sd = wave_sum(gD);
+        if ((threadIdx.x & 63) == 0) {
+            gred[0][threadIdx.x >> 6] = se;
+            gred[1][threadIdx.x >> 6] = sd;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            double t = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) t += gred[threadIdx.x][w];
+            const int tile_in_img = (int)tile - img * (int)(nbx * nby) * g.nzc;
+            g.gpart[((size_t)g.gitem0 + (size_t)img * g.gipi + tile_in_img) * 2 + threadIdx.x] = t;
+        }
+    }
 }
 
 // Thermal noise of one Heun step for every site (Heun mode 4: generated by
@@ -1057,6 +1124,30 @@ hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bi
     Onsite os{};
     HeunConst hc{};
     return launch_any<ZM_BIL>(zp, a, os, hc, st);
+}
+
+int zmarch_tiles(const ZPlan &zp, const Grid &g) {
+    return ((g.Lx + kTX - 1) / kTX) * ((g.Ly + kTYE - 1) / kTYE) * ((g.Lz + zp.zch - 1) / zp.zch);
+}
+
+hipError_t zmarch_gneb_a(const ZPlan &zp, const Grid &g, const Onsite &os, int n_img, const double *S0,
+                         const double *S0alt, const double *sel, const double *skip, double *F, double *partial,
+                         int item0, int items_per_img, hipStream_t st) {
+    if (zp.prec != 0 || n_img <= 0 || zmarch_tiles(zp, g) > items_per_img) return hipErrorInvalidValue;
+    ZArgs a = make_args(zp, g);
+    a.S0 = S0;
+    a.S0alt = S0alt ? S0alt : S0;
+    a.sel = sel;
+    a.skip = skip;
+    a.nimg = n_img;
+    a.bstride = 3 * g.N;
+    a.gF = F;
+    a.gpart = partial;
+    a.gitem0 = item0;
+    a.gipi = items_per_img;
+    HeunConst hc{};
+    if (zp.iso) return launch_mode<double, true, ZM_GNEB_A>(zp, a, os, hc, st);
+    return launch_mode<double, false, ZM_GNEB_A>(zp, a, os, hc, st);
 }
 
 hipError_t zmarch_bil_images(const ZPlan &zp, const Grid &g, int n_img, const double *S0, const double *S0alt,

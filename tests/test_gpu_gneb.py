@@ -147,3 +147,34 @@ def test_gneb_stoner_wohlfarth_barrier():
     Y = Yd.cpu().numpy()
     assert abs(Y[ci, 2, 0] - (-h)) < 1e-6
     assert abs((s["E"][ci] - s["E"][0]) - K * (1 - h) ** 2) < 1e-8
+
+
+def test_gneb_fused_and_stored_field_first_pass_match_oracle():
+    # one batch with both forms of the first pass: an instance of several
+    # z-march tiles per image with ragged x/y/z tails (the pass runs inside
+    # the z-march and leaves one partial per tile), and a thin column with
+    # more tiles per image than 256-site items (the z-march stores the field
+    # and the elementwise pass reads it)
+    import torch
+    from paper_2605_26016_amd import spx
+    cases = [(frustrated((70, 10, 20), periodic=(1, 0, 1)), 5, 21), (frustrated((2, 2, 40)), 4, 22)]
+    hams, bufs, refs = [], [], []
+    for w, n_img, seed in cases:
+        A, B = endpoints(w, seed)
+        Y0 = oracle.geodesic_path(A, B, n_img)
+        hams.append(gpu_hamiltonian(w))
+        bufs.append(to_dev(Y0))
+        refs.append((oracle_model(w), oracle.GnebState(Y0, k_spring=1.0, dt=0.05, mass=1.0, ci_mode=1,
+                                                        ci_on_below=3.0)))
+    g = spx.gneb_create(hams, bufs, spring_k=1.0, vp_dt=0.05, vp_mass=1.0, ci_mode=1, ci_on_below=3.0)
+    for it in range(8):
+        spx.gneb_step(g, 1)
+        torch.cuda.synchronize()
+        for k, (m, st) in enumerate(refs):
+            E, dist, fmax, ci = oracle.gneb_iterate(m, st)
+            got = bufs[k].cpu().numpy()
+            assert np.max(np.abs(got - st.Y)) <= 1e-9, (it, k, np.max(np.abs(got - st.Y)))
+            s = spx.gneb_get_stats(g, k)
+            np.testing.assert_allclose(s["E"], E, rtol=1e-10, atol=1e-12)
+            np.testing.assert_allclose(s["dist"], dist, rtol=1e-10, atol=1e-12)
+            assert s["ci_index"] == ci and s["iterations"] == it + 1
