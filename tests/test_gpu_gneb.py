@@ -150,14 +150,15 @@ def test_gneb_stoner_wohlfarth_barrier():
 
 
 def test_gneb_fused_and_stored_field_first_pass_match_oracle():
-    # one batch with both forms of the first pass: an instance of several
-    # z-march tiles per image with ragged x/y/z tails (the pass runs inside
-    # the z-march and leaves one partial per tile), and a thin column with
-    # more tiles per image than 256-site items (the z-march stores the field
-    # and the elementwise pass reads it)
+    # one batch with both forms of the first pass: instances of several
+    # z-march tiles per image with ragged x/y/z tails, periodic and open (the
+    # pass runs inside the z-march and leaves one partial per tile), and a
+    # thin column with more tiles per image than 256-site items (the z-march
+    # stores the field and the elementwise pass reads it)
     import torch
     from paper_2605_26016_amd import spx
-    cases = [(frustrated((70, 10, 20), periodic=(1, 0, 1)), 5, 21), (frustrated((2, 2, 40)), 4, 22)]
+    cases = [(frustrated((70, 10, 20), periodic=(1, 0, 1)), 5, 21), (frustrated((66, 9, 18)), 4, 23),
+             (frustrated((2, 2, 40)), 4, 22)]
     hams, bufs, refs = [], [], []
     for w, n_img, seed in cases:
         A, B = endpoints(w, seed)
