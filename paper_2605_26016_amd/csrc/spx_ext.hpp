@@ -83,6 +83,15 @@ hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bi
 // Bilinear field of n_img images stacked as [n_img][3][N] (FP64 plan, FP64
 // output).  The source buffer is S0, or S0alt when *sel != 0 (a device flag);
 // nothing is done when *skip != 0 (skip may be NULL).
+// Force pass of the static minimisers fused into the FP64 z-march field
+// evaluation of S (no-op when state[done_idx] != 0): writes F = b - (b.s) s
+// and one set of six partials per tile (max |F|, v.F, F.F, s.s, s.y, y.y of
+// the method) into partial[tile][6]; method 2 also writes the projected pair
+// into history slot state[cand_idx] of Sh / Yh.
+hipError_t zmarch_min_force(const ZPlan &zp, const Grid &g, const Onsite &os, const double *S, double *F,
+                            const double *V, const double *Up, const double *Fp, double *Sh, double *Yh,
+                            const double *state, int done_idx, int cand_idx, int method, double *partial,
+                            hipStream_t st);
 // Tiles of one image (x tiles x y tiles x z chunks) of the z-march engine.
 int zmarch_tiles(const ZPlan &zp, const Grid &g);
 // First GNEB pass fused into the FP64 z-march over the images of an instance

@@ -46,6 +46,7 @@ struct MinArgs {
     double *rho;     // [hist + 1]
     double *al;      // [hist]
     int nb;          // blocks of the elementwise passes
+    int npart;       // partial sets the scalar pass reduces (nb, or the z-march tiles of the fused force pass)
 };
 
 __device__ __forceinline__ double blk_sum(double v, double *red) {
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(kMinB) void k_min_scalars(MinArgs a) {
     if (a.st[MS_DONE] != 0.0) return;
     double v[kNP];
     for (int k = 0; k < kNP; ++k) v[k] = 0.0;
-    for (int bl = threadIdx.x; bl < a.nb; bl += kMinB) {
+    for (int bl = threadIdx.x; bl < a.npart; bl += kMinB) {
         const double *p = a.part + (size_t)bl * kNP;
         v[0] = fmax(v[0], p[0]);
         for (int k = 1; k < kNP; ++k) v[k] += p[k];
@@ -388,6 +389,13 @@ struct spx_min {
     MinArgs a{};
     double *b = nullptr;
     std::vector<void *> owned;
+    // the force pass runs inside the FP64 z-march field evaluation when the
+    // Hamiltonian has a z-march shape and no dipolar term
+    bool fused = false;
+    ZPlan zp;
+    Grid g{};
+    Onsite os{};
+    int ntile = 0;
 };
 
 namespace {
@@ -445,6 +453,15 @@ spx_status spx_min_create(spx_ham *h, const spx_min_params *p, void *stream, spx
     a.max_step = p->max_step;
     a.tol = p->tol_force;
     a.nb = (int)std::max<int64_t>(1, std::min<int64_t>((a.N + kMinB - 1) / kMinB, kMinBlocks));
+    a.npart = a.nb;
+    if (v.zp64 && !v.dip && !v.pl) {
+        m->fused = true;
+        m->zp = *v.zp64;
+        m->zp.zch = 16;
+        m->g = v.grid;
+        m->os = v.onsite;
+        m->ntile = zmarch_tiles(m->zp, v.grid);
+    }
     const size_t n3 = (size_t)3 * a.N;
     auto alloc = [&](double **ptr, size_t count) -> bool {
         if (hipMalloc((void **)ptr, sizeof(double) * std::max<size_t>(count, 1)) != hipSuccess) {
@@ -456,7 +473,7 @@ spx_status spx_min_create(spx_ham *h, const spx_min_params *p, void *stream, spx
     };
     bool ok = alloc(&m->b, n3) && alloc(&a.F, n3) && alloc(&a.V, n3) && alloc(&a.W, n3) && alloc(&a.Fp, n3) &&
               alloc(&a.Up, n3) && alloc(&a.q, n3) && alloc(&a.Sh, n3 * (a.hist + 1)) &&
-              alloc(&a.Yh, n3 * (a.hist + 1)) && alloc(&a.part, (size_t)kMinBlocks * kNP) && alloc(&a.st, MS_N) &&
+              alloc(&a.Yh, n3 * (a.hist + 1)) && alloc(&a.part, (size_t)std::max(kMinBlocks, m->ntile) * kNP) && alloc(&a.st, MS_N) &&
               alloc(&a.rho, a.hist + 1) && alloc(&a.al, a.hist);
     if (!ok) {
         min_free(m);
@@ -483,10 +500,19 @@ spx_status spx_min_step(spx_min *m, double *S, int32_t n_iter, void *stream) {
     const MinArgs &a = m->a;
     const unsigned nb = (unsigned)a.nb;
     for (int it = 0; it < n_iter; ++it) {
-        spx_status s = spx_eval_field(m->h, S, m->b, stream);
-        if (s != SPX_OK) return s;
-        k_min_force<<<nb, kMinB, 0, st>>>(a, S, m->b);
-        k_min_scalars<<<1, kMinB, 0, st>>>(a);
+        if (m->fused) {
+            hipError_t e = zmarch_min_force(m->zp, m->g, m->os, S, a.F, a.V, a.Up, a.Fp, a.Sh, a.Yh, a.st, MS_DONE,
+                                            MS_CAND, a.method, a.part, st);
+            if (e != hipSuccess) return set_hip_error(e, "spx_min_step: force pass");
+            MinArgs af = a;
+            af.npart = m->ntile;
+            k_min_scalars<<<1, kMinB, 0, st>>>(af);
+        } else {
+            spx_status s = spx_eval_field(m->h, S, m->b, stream);
+            if (s != SPX_OK) return s;
+            k_min_force<<<nb, kMinB, 0, st>>>(a, S, m->b);
+            k_min_scalars<<<1, kMinB, 0, st>>>(a);
+        }
         if (a.method == 2) {
             // t = hist only applies the last axpy of a full history
             for (int t = 0; t <= a.hist; ++t) {

@@ -66,8 +66,11 @@ constexpr int kThreads = kTX * kTYT;
 // tangent plane of the spin for interior images, the squared geodesic
 // distance to the next image), reduced to one (energy, distance) partial per
 // block in place of storing the field.
+// ZM_MIN_FORCE: the force pass of the static minimisers in the epilogue
+// (force projected on the spin's tangent plane, its max norm and the dot
+// products of the method), reduced to one partial set per block.
 enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4, ZM_BIL = 5,
-             ZM_GNEB_A = 6 };
+             ZM_GNEB_A = 6, ZM_MIN_FORCE = 7 };
 
 template <typename T, int NW>
 struct ZWeights {
@@ -105,6 +108,13 @@ struct ZArgs {
     double *gF;
     double *gpart;
     int gitem0, gipi;
+    // ZM_MIN_FORCE (force in gF, partials [tile][6] in gpart): the method's
+    // velocity (0) or previous step and force (1, 2), the L-BFGS history
+    // rings and the minimiser state (candidate slot)
+    const double *mV, *mUp, *mFp;
+    double *mSh, *mYh;
+    const double *mst;
+    int mmethod, mcand_idx;
 };
 
 // Shape table as a static constant, so that every bond read in an unrolled
@@ -272,13 +282,15 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // fetched one march iteration before their use so that their latency
     // hides behind a plane's stencil: CORRECT_P reads P and eta, PREDICT
     // reads eta when the noise comes from a pre-pass.
-    constexpr bool kEpiPre = MODE == ZM_CORRECT_P || MODE == ZM_PREDICT || MODE == ZM_GNEB_A;
-    constexpr int NE = MODE == ZM_CORRECT_P ? 6 : (MODE == ZM_PREDICT || MODE == ZM_GNEB_A) ? 3 : 1;
+    constexpr bool kEpiPre = MODE == ZM_CORRECT_P || MODE == ZM_PREDICT || MODE == ZM_GNEB_A || MODE == ZM_MIN_FORCE;
+    constexpr int NE = (MODE == ZM_CORRECT_P || MODE == ZM_MIN_FORCE) ? 6
+                       : (MODE == ZM_PREDICT || MODE == ZM_GNEB_A) ? 3 : 1;
     double epi[kYB][NSUB][NE];
     auto fetch_epi = [&](int o) __attribute__((always_inline)) {
         if (o < 0 || o >= nout) return;  // uniform over the block
         if (MODE == ZM_PREDICT && !(hc.noise && g.eload)) return;
         if (MODE == ZM_GNEB_A && img >= g.nimg - 1) return;  // the last image has no successor
+        if (MODE == ZM_MIN_FORCE && g.mmethod == 3) return;   // Adam reads nothing here
         const int x = x0 + tx;
         static_for<NSUB>([&](auto ac) __attribute__((always_inline)) {
             constexpr int a = decltype(ac)::value;
@@ -301,6 +313,17 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                     // the next image of the same buffer
 #pragma unroll
                     for (int c = 0; c < 3; ++c) e[c] = S0[g.bstride + c * N + i];
+                } else if constexpr (MODE == ZM_MIN_FORCE) {
+                    if (g.mmethod == 0) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) e[c] = g.mV[c * N + i];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            e[c] = g.mUp[c * N + i];
+                            e[3 + c] = g.mFp[c * N + i];
+                        }
+                    }
                 }
             }
         });
@@ -510,6 +533,8 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // sites' independent FP64 and Philox chains interleave; sites outside
     // the lattice (valid = false) compute on a clamped index and store nothing.
     double gE = 0.0, gD = 0.0;  // ZM_GNEB_A: the thread's energy and squared-distance sums
+    // ZM_MIN_FORCE: max |F|, v.F, F.F, s.s, s.y, y.y of the thread's sites
+    double mred[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     auto finish_row = [&](int x, int y, int z, bool valid, const T (&v)[NSUB][NIN][3],
                           const double (&e)[NSUB][NE], const double (&so)[NSUB][3]) __attribute__((always_inline)) {
         int64_t i[NSUB], ir[NSUB];
@@ -525,6 +550,61 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 for (int a = 0; a < NSUB; ++a)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) bo[c * N + i[a]] = v[a][0][c];
+            return;
+        }
+        if constexpr (MODE == ZM_MIN_FORCE) {
+            if (!valid) return;
+            const int method = g.mmethod;
+            const int cand = (int)g.mst[g.mcand_idx];
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a) {
+                const double *sp = so[a];
+                double ba[3];
+                aniso_field(os, a, sp, ba);
+                double b[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) b[c] = (double)v[a][0][c] + ba[c] + os.bz[a][c];
+                const double bs = b[0] * sp[0] + b[1] * sp[1] + b[2] * sp[2];
+                double f[3], f2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    f[c] = b[c] - bs * sp[c];
+                    f2 += f[c] * f[c];
+                    g.gF[c * N + i[a]] = f[c];
+                }
+                mred[0] = fmax(mred[0], sqrt(f2));
+                mred[2] += f2;
+                if (method == 0) {
+                    mred[1] += e[a][0] * f[0] + e[a][1] * f[1] + e[a][2] * f[2];
+                } else if (method == 1 || method == 2) {
+                    // step and force change, both projected on the tangent plane of s
+                    double sv[3], yv[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        sv[c] = e[a][c];
+                        yv[c] = e[a][3 + c];
+                    }
+                    const double ds = sv[0] * sp[0] + sv[1] * sp[1] + sv[2] * sp[2];
+                    const double dy = yv[0] * sp[0] + yv[1] * sp[1] + yv[2] * sp[2];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        sv[c] -= ds * sp[c];
+                        yv[c] -= dy * sp[c];
+                        yv[c] -= f[c];
+                    }
+                    mred[3] += sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
+                    mred[4] += sv[0] * yv[0] + sv[1] * yv[1] + sv[2] * yv[2];
+                    mred[5] += yv[0] * yv[0] + yv[1] * yv[1] + yv[2] * yv[2];
+                    if (method == 2) {
+                        double *Sj = g.mSh + (int64_t)cand * 3 * N, *Yj = g.mYh + (int64_t)cand * 3 * N;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            Sj[c * N + i[a]] = sv[c];
+                            Yj[c * N + i[a]] = yv[c];
+                        }
+                    }
+                }
+            }
             return;
         }
         if constexpr (MODE == ZM_GNEB_A) {
@@ -861,6 +941,28 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         if constexpr (kEpiPre) fetch_epi(q - D + 2);
         __syncthreads();
     }
+    if constexpr (MODE == ZM_MIN_FORCE) {
+        // fixed-order block reductions (the first a maximum), one set per tile
+        __shared__ double mr[6][kThreads / 64];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double v = mred[k];
+            if (k == 0) {
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+            } else {
+                v = wave_sum(v);
+            }
+            if ((threadIdx.x & 63) == 0) mr[k][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            const int k = threadIdx.x;
+            double t = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) t = k == 0 ? fmax(t, mr[k][w]) : t + mr[k][w];
+            g.gpart[(size_t)tile * 6 + k] = t;
+        }
+    }
     if constexpr (MODE == ZM_GNEB_A) {
         // fixed-order block sums of the two statistics, one partial pair per tile
         __shared__ double gred[2][kThreads / 64];
@@ -1124,6 +1226,29 @@ hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bi
     Onsite os{};
     HeunConst hc{};
     return launch_any<ZM_BIL>(zp, a, os, hc, st);
+}
+
+hipError_t zmarch_min_force(const ZPlan &zp, const Grid &g, const Onsite &os, const double *S, double *F,
+                            const double *V, const double *Up, const double *Fp, double *Sh, double *Yh,
+                            const double *state, int done_idx, int cand_idx, int method, double *partial,
+                            hipStream_t st) {
+    if (zp.prec != 0) return hipErrorInvalidValue;
+    ZArgs a = make_args(zp, g);
+    a.S0 = S;
+    a.skip = state + done_idx;  // the minimiser has converged: no-op
+    a.gF = F;
+    a.gpart = partial;
+    a.mV = V;
+    a.mUp = Up;
+    a.mFp = Fp;
+    a.mSh = Sh;
+    a.mYh = Yh;
+    a.mst = state;
+    a.mmethod = method;
+    a.mcand_idx = cand_idx;
+    HeunConst hc{};
+    if (zp.iso) return launch_mode<double, true, ZM_MIN_FORCE>(zp, a, os, hc, st);
+    return launch_mode<double, false, ZM_MIN_FORCE>(zp, a, os, hc, st);
 }
 
 int zmarch_tiles(const ZPlan &zp, const Grid &g) {

@@ -24,16 +24,25 @@ def _gpu():
     require_gpu()
 
 
+# the force pass runs inside the z-march field evaluation (one tile, or
+# several with ragged x/y/z tails) or, with the gather engine, as its own
+# pass after the field
+LATTICES = {"one_tile": ((5, 4, 3), 0), "multitile": ((70, 9, 18), 0), "gather": ((5, 4, 3), 1)}
+
+
+@pytest.mark.parametrize("lattice", list(LATTICES))
 @pytest.mark.parametrize("method", ["vp", "bb", "lbfgs", "adam"])
 @pytest.mark.parametrize("retraction", ["exp", "norm"])
-def test_iterations_match_the_oracle(method, retraction):
+def test_iterations_match_the_oracle(method, retraction, lattice):
     from paper_2605_26016_amd import spx
-    w = Workload(name="f", L=(5, 4, 3), periodic=(1, 0, 1), J_shell=(1.0, 0.188, -0.274), K=0.3,
+    L, engine = LATTICES[lattice]
+    w = Workload(name="f", L=L, periodic=(1, 0, 1), J_shell=(1.0, 0.188, -0.274), K=0.3,
                  K_axis=(0.0, 0.6, 0.8), B=(0.5, 0.0, 1.0), field_prec="fp64")
     S0 = random_sphere(w.N, 7)
     S = to_dev(S0)
     kw = dict(SETTINGS[method])
-    mn = spx.min_create(gpu_hamiltonian(w), method=method, retraction=retraction, max_step=0.3, **kw)
+    mn = spx.min_create(gpu_hamiltonian(w, stencil_engine=engine), method=method, retraction=retraction,
+                        max_step=0.3, **kw)
     hist = kw.pop("history", 5)
     st = oracle.MinState(w.N, method, retraction, max_step=0.3, hist=hist, **kw)
     ref = S0.copy()
