@@ -124,88 +124,6 @@ struct ShapeC {
     static constexpr ShapeTable t = make_shape(KIND);
 };
 
-// Shared partial sums of an isotropic shape.  With one coupling per shell,
-// the bonds of one (target a, dz, shell) group all take the same J, so the
-// group's staged sources are summed first and multiplied once; groups with
-// the same source set (a shell's sources at dz and -dz, or two shells on
-// one set: on bcc the 2x2 box feeds the 1st and 4th shells) share one sum.
-// On the bcc 5-shell shape this turns 116 FMAs per component and input
-// plane into 32 adds and 28 FMAs.
-constexpr int kMaxSums = 48, kMaxMembers = 32, kMaxUses = 128;
-struct ZSum {
-    int n;                  // members (staged source positions)
-    int b[kMaxMembers], dx[kMaxMembers], dy[kMaxMembers];
-    int u0, nu;             // its uses: uses[u0 .. u0 + nu)
-};
-struct ZUse {
-    int a, dz, shell;
-};
-struct SumTable {
-    int nsum, nuse;
-    ZSum sums[kMaxSums];
-    ZUse uses[kMaxUses];
-    bool ok;                // false if the shape overflows the table
-};
-
-constexpr SumTable make_sums(int kind) {
-    const ShapeTable t = make_shape(kind);
-    SumTable st{};
-    st.ok = true;
-    // groups keyed by (a, dz, shell), members in bond order
-    int ng = 0;
-    int ga[kMaxUses] = {}, gdz[kMaxUses] = {}, gsh[kMaxUses] = {}, gn[kMaxUses] = {};
-    int gb[kMaxUses][kMaxMembers] = {}, gx[kMaxUses][kMaxMembers] = {}, gy[kMaxUses][kMaxMembers] = {};
-    for (int k = 0; k < t.nb; ++k) {
-        const ZBond &bd = t.bonds[k];
-        int g = 0;
-        while (g < ng && !(ga[g] == bd.a && gdz[g] == bd.dz && gsh[g] == bd.shell)) ++g;
-        if (g == ng) {
-            if (ng == kMaxUses) { st.ok = false; return st; }
-            ga[g] = bd.a;
-            gdz[g] = bd.dz;
-            gsh[g] = bd.shell;
-            gn[g] = 0;
-            ++ng;
-        }
-        if (gn[g] == kMaxMembers) { st.ok = false; return st; }
-        gb[g][gn[g]] = bd.b;
-        gx[g][gn[g]] = bd.dx;
-        gy[g][gn[g]] = bd.dy;
-        ++gn[g];
-    }
-    // one sum per distinct member list (bond order makes equal sets equal lists)
-    int gsum[kMaxUses] = {};
-    for (int g = 0; g < ng; ++g) {
-        int m = 0;
-        for (; m < st.nsum; ++m) {
-            const ZSum &z = st.sums[m];
-            bool same = z.n == gn[g];
-            for (int e = 0; same && e < z.n; ++e)
-                same = z.b[e] == gb[g][e] && z.dx[e] == gx[g][e] && z.dy[e] == gy[g][e];
-            if (same) break;
-        }
-        if (m == st.nsum) {
-            if (st.nsum == kMaxSums) { st.ok = false; return st; }
-            ZSum &z = st.sums[st.nsum++];
-            z.n = gn[g];
-            for (int e = 0; e < z.n; ++e) {
-                z.b[e] = gb[g][e];
-                z.dx[e] = gx[g][e];
-                z.dy[e] = gy[g][e];
-            }
-        }
-        gsum[g] = m;
-    }
-    // uses grouped by sum
-    for (int m = 0; m < st.nsum; ++m) {
-        st.sums[m].u0 = st.nuse;
-        for (int g = 0; g < ng; ++g)
-            if (gsum[g] == m) st.uses[st.nuse++] = ZUse{ga[g], gdz[g], gsh[g]};
-        st.sums[m].nu = st.nuse - st.sums[m].u0;
-    }
-    return st;
-}
-
 template <int KIND>
 struct SumC {
     static constexpr SumTable t = make_sums(KIND);
