@@ -76,6 +76,9 @@ __device__ __forceinline__ void pl_bil(const PlView &v, const double *__restrict
     const int64_t N = v.N;
     AccT acc[3] = {AccT(0), AccT(0), AccT(0)};
     const int64_t p0 = v.row[i], p1 = v.row[i + 1];
+    // unrolled so that several entries' index loads, and then their spin
+    // loads, are in flight together instead of one dependent pair per entry
+#pragma unroll 4
     for (int64_t p = p0; p < p1; ++p) {
         const int64_t j = v.col[p];
         const AccT s0 = (AccT)S[j], s1 = (AccT)S[N + j], s2 = (AccT)S[2 * N + j];
