@@ -686,23 +686,27 @@ def field_workload(args, w):
                             "GBps_algorithmic": FIELD_BYTES * w.N / ms_st / 1e6,
                             "hbm_frac": FIELD_BYTES * w.N / ms_st / 1e6 / HBM_PEAK_GBS},
            "stencil_plus_dipolar_fft_ms": ms_dip,
-           "dipolar": dipolar_traffic(w.L, ms_dip - ms_st),
+           "dipolar": dipolar_traffic(w.L, ms_dip - ms_st, zsym=bool(
+               np.all(np.asarray(w.cell, np.float64).reshape(3, 3)[[0, 1, 2, 2], [2, 2, 0, 1]] == 0.0))),
            "dense_7cubed": dense, "cpu_baseline": cpu,
            "hbm_copy_GBps": copy_bandwidth(), "device": torch.cuda.get_device_name(0)}
     print(json.dumps(out), flush=True)
 
 
-def dipolar_traffic(L, ms):
+def dipolar_traffic(L, ms, zsym=True):
     """Contract bytes of one pruned dipolar evaluation (each array read or
     written once per pass: pad, x-row R2C, y columns, fused z pass with the
-    dipole spectrum, inverse y, C2R, crop) and the rate they imply."""
+    dipole spectrum, inverse y, C2R, crop) and the rate they imply.  With a
+    cell whose third vector is along z (zsym) the fused pass reads the
+    spectrum only for kz <= Pz / 2."""
     Lx, Ly, Lz = L
     P = [1 << (2 * v - 1).bit_length() for v in L]
     H = P[0] // 2 + 1
     rows = 3 * Ly * Lz
     R, X = rows * P[0] * 4, rows * H * 8
     Y = 3 * Lz * P[1] * H * 8
-    kern = 6 * P[2] * P[1] * H * 4
+    kz_read = P[2] // 2 + 1 if (zsym and P[2] == 512) else P[2]
+    kern = 6 * kz_read * P[1] * H * 4
     N = Lx * Ly * Lz
     total = (3 * N * 8 + R) + (R + X) + (X + Y) + (Y + kern + Y) + (Y + X) + (X + R) + (3 * N * 4 * 2)
     return {"ms": ms, "contract_bytes": total, "GBps": total / (ms / 1e3) / 1e9,

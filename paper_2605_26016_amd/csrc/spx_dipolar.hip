@@ -40,6 +40,11 @@ struct DipolarPlan {
     float2 *Y = nullptr;   // [3][Lz][Py][H] after the y transform
     float2 *Z = nullptr;   // [3][Pz][Py][H] full spectrum (Pz != 512; 512 uses the fused z pass)
     float *kern = nullptr; // [6][Pz][Py][H] real dipole spectrum xx, xy, xz, yy, yz, zz
+    // the third cell vector is along z and the first two have no z part: the
+    // sampled tensor is even (xx, xy, yy, zz) or odd (xz, yz) under dz -> -dz,
+    // so is its spectrum under kz -> Pz - kz, and the fused z pass reads only
+    // kz <= Pz / 2 (half the spectrum traffic)
+    bool zsym = false;
     float2 *tw_y = nullptr, *tw_z = nullptr;  // exp(-2 pi i k / P), k < P
     hipfftHandle fwd = 0, inv = 0;
     bool fwd_ok = false, inv_ok = false;
@@ -314,7 +319,8 @@ __global__ __launch_bounds__(kT512) void k_colfft512(const float2 *__restrict__ 
 // forward result sits in the thread that needs it for the inverse's first
 // pass (row c + 8 g + 64 h = 64 h + qin with qin = c + 8 g).
 __global__ __launch_bounds__(kT512) void k_zconv512(float2 *__restrict__ Y, const float *__restrict__ kern, int Lz,
-                                                    int64_t J, int64_t n_cplx, const float2 *__restrict__ tw512) {
+                                                    int64_t J, int64_t n_cplx, const float2 *__restrict__ tw512,
+                                                    int zsym) {
     __shared__ float2 lds[512 * kPitch];
     const int t = threadIdx.x;
     const int w = t & (kW512 - 1), q = t >> kW512Log;
@@ -335,9 +341,13 @@ __global__ __launch_bounds__(kT512) void k_zconv512(float2 *__restrict__ Y, cons
     if (col) {
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
-            const int64_t k = (int64_t)(qq + 64 * h) * J + j;
-            const float txx = kern[k], txy = kern[n_cplx + k], txz = kern[2 * n_cplx + k];
-            const float tyy = kern[3 * n_cplx + k], tyz = kern[4 * n_cplx + k], tzz = kern[5 * n_cplx + k];
+            // kz and 512 - kz read the same stored entries (sign flip for xz, yz)
+            const int kz = qq + 64 * h;
+            const bool mirror = zsym && kz > 256;
+            const float sgn = mirror ? -1.0f : 1.0f;
+            const int64_t k = (int64_t)(mirror ? 512 - kz : kz) * J + j;
+            const float txx = kern[k], txy = kern[n_cplx + k], txz = sgn * kern[2 * n_cplx + k];
+            const float tyy = kern[3 * n_cplx + k], tyz = sgn * kern[4 * n_cplx + k], tzz = kern[5 * n_cplx + k];
             const float2 sx = v[0][h], sy = v[1][h], sz = v[2][h];
             v[0][h] = make_float2(txx * sx.x + txy * sy.x + txz * sz.x, txx * sx.y + txy * sy.y + txz * sz.y);
             v[1][h] = make_float2(txy * sx.x + tyy * sy.x + tyz * sz.x, txy * sx.y + tyy * sy.y + tyz * sz.y);
@@ -459,6 +469,9 @@ spx_status create_dipolar(const int32_t dims[3], const double cell[9], double mu
     hipfftSetStream(dplan, st);
     const double pref = dipole_prefactor() * mu * mu / (double)n_real;
     const int comps[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    // z parity of the sampled tensor: no coupling of the z axis with x, y in the
+    // cell matrix (either storage order)
+    p->zsym = cell[2] == 0.0 && cell[5] == 0.0 && cell[6] == 0.0 && cell[7] == 0.0;
     for (int c = 0; c < 6 && s == SPX_OK && e == hipSuccess; ++c) {
         k_dipole_component<<<nblocks(n_real), kB, 0, st>>>(Lx, Ly, Lz, Px, Py, Pz, cell[0], cell[1], cell[2], cell[3],
                                                             cell[4], cell[5], cell[6], cell[7], cell[8], comps[c][0],
@@ -513,7 +526,7 @@ spx_status eval_dipolar(DipolarPlan *p, const double *S, float *bdip, hipStream_
         // z transform, product and inverse z transform in one pass over Y
         if (e == hipSuccess) {
             k_zconv512<<<(unsigned)((plane + kW512 - 1) / kW512), kT512, 0, st>>>(p->Y, p->kern, Lz, plane, p->n_cplx,
-                                                                                p->tw_z);
+                                                                                p->tw_z, p->zsym ? 1 : 0);
             e = hipGetLastError();
         }
     } else {
