@@ -371,6 +371,24 @@ def test_dipolar_field_vs_direct_sum(L):
     assert max_rel(got - got0, parts["dip"]) <= 2e-5
 
 
+@pytest.mark.parametrize("cell", [((0.4, 0.0, 0.0), (0.0, 0.4, 0.0), (0.0, 0.0, 0.5)),
+                                  ((0.4, 0.0, 0.0), (0.1, 0.4, 0.0), (0.05, 0.08, 0.4))],
+                         ids=["orthorhombic", "triclinic"])
+def test_dipolar_fused_z_pass_both_cell_kinds(cell):
+    # Lz = 150 pads to 512 in z: the fused z pass; an orthorhombic cell lets
+    # it read half the spectrum (even / odd in kz), a triclinic one does not
+    import dataclasses
+    w = dataclasses.replace(dip_workload((3, 4, 150)), cell=cell)
+    S = random_sphere(w.N, 62)
+    m = oracle_model(w)
+    ref = oracle.field(m, S)
+    got = gpu_field(w, S, "fp32")
+    assert max_rel(got, ref) <= 1e-5
+    w0 = dataclasses.replace(w, dipolar=0)
+    _, parts = oracle.field(m, S, terms=True)
+    assert max_rel(got - gpu_field(w0, S, "fp32"), parts["dip"]) <= 2e-5
+
+
 def test_dipolar_field_vs_numpy_fft_32():
     from oracle.dipolar_fft import dipolar_field_fft
     L = (32, 24, 20)
