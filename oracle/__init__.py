@@ -169,8 +169,12 @@ class Model:
             d = np.zeros(3 * max_bonds, np.int32)
             J = np.zeros(9 * max_bonds, np.float64)
             sh = np.zeros(max_bonds, np.int32)
-            Dp = None if D_shell is None else _f64(D_shell)
-            nb = lib().or_build_bonds(lat.n_sub, lat.cell, lat.frac, int(n_shells), _f64(J_shell),
+            Jp = _f64(J_shell).reshape(-1)
+            Dp = None if D_shell is None else _f64(D_shell).reshape(-1)
+            # the bond builder reads one J and one D per shell
+            if len(Jp) < n_shells or (Dp is not None and len(Dp) < n_shells):
+                raise ValueError("J_shell and D_shell need one entry per shell")
+            nb = lib().or_build_bonds(lat.n_sub, lat.cell, lat.frac, int(n_shells), Jp,
                                       _ptr(Dp), max_bonds, a, b, d, J, sh)
             if nb < 0:
                 raise RuntimeError("oracle bond enumeration failed")

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from tests.helpers import gpu_hamiltonian, max_rel, oracle_model, require_gpu, to_dev
-from tests.test_oracle_pairlist import disordered, lattice_to_pairlist
+from tests.test_oracle_pairlist import disordered, empty_list, lattice_to_pairlist
 from workloads import Workload, bcc_5shell_stochastic, random_sphere
 
 pytestmark = pytest.mark.gpu
@@ -84,6 +84,35 @@ def test_stochastic_heun_matches_the_oracle(prec, tol):
     spx.llg_heun_step(gpu_pl(pl, prec), S, temperature_K=200.0, **kw)
     ref = oracle.pl_heun(pl, S0, T_K=200.0, **kw)
     assert float(np.max(np.abs(S.cpu().numpy() - ref))) <= tol
+
+
+@pytest.mark.parametrize("kind", ["empty", "isolated_sites"])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_empty_list_and_sites_without_couplings(kind, prec, tol):
+    # an empty list leaves only the on-site terms; in the second list the
+    # couplings name only the first half of the sites, so the rest see
+    # on-site fields only
+    import torch
+    from paper_2605_26016_amd import spx
+    if kind == "empty":
+        pl = empty_list(N=301)
+    else:
+        pl0, _ = disordered(N=600, P=2000, seed=5)
+        keep = (pl0.i < 300) & (pl0.j < 300)
+        pl = oracle.PairList(pl0.N, pl0.i[keep], pl0.j[keep], pl0.J[keep].reshape(-1, 3, 3), mu=pl0.mu, K=pl0.K,
+                             K_axis=pl0.K_axis, B=pl0.B)
+    S0 = random_sphere(pl.N, 21)
+    assert max_rel(field(gpu_pl(pl, prec), S0, prec), oracle.pl_field(pl, S0)) <= tol
+    h = gpu_pl(pl, prec)
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    T = torch.zeros(5, dtype=torch.float64, device="cuda")
+    spx.energy(h, to_dev(S0), E, T)
+    np.testing.assert_allclose(T.cpu().numpy(), oracle.pl_energy(pl, S0), rtol=max(tol, 1e-12), atol=1e-9)
+    S = to_dev(S0)
+    kw = dict(alpha=0.05, dt_fs=0.1, seed=3, step0=0, n_steps=3)
+    spx.llg_heun_step(h, S, temperature_K=100.0, **kw)
+    ref = oracle.pl_heun(pl, S0, T_K=100.0, **kw)
+    assert float(np.max(np.abs(S.cpu().numpy() - ref))) <= (1e-11 if prec == "fp64" else 1e-8)
 
 
 def test_minimiser_on_a_pairlist_reaches_the_ground_state():

@@ -53,7 +53,7 @@ def lattice_to_pairlist(w):
     return oracle.PairList(w.N, ti, sj, np.array(J), mu=mu, K=K, K_axis=Kax, B=w.B)
 
 
-CASES = [Workload(name="sc", L=(4, 3, 5), periodic=(1, 0, 1), J_shell=(1.0, -0.3, 0.1), D_shell=(0.4,),
+CASES = [Workload(name="sc", L=(4, 3, 5), periodic=(1, 0, 1), J_shell=(1.0, -0.3, 0.1), D_shell=(0.4, 0.0, 0.0),
                   K=0.2, K_axis=(0.0, 0.6, 0.8), B=(1.0, -2.0, 0.5)),
          bcc_5shell_stochastic((3, 3, 3))]
 CASES[1].periodic = (1, 1, 0)
@@ -123,3 +123,26 @@ def test_disordered_heun_conserves_energy_without_damping():
         drift.append(abs(oracle.pl_energy(pl, X)[4] - E0))
     assert drift[0] < 1e-3 * abs(E0)
     assert drift[1] < drift[0] / 3.0                           # second order in dt
+
+
+def empty_list(N=37, seed=9):
+    rng = np.random.default_rng(seed)
+    ax = rng.normal(size=(N, 3))
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    mu, K = rng.uniform(0.5, 3.0, N), rng.uniform(-0.5, 0.5, N)
+    e = np.zeros(0, np.int64)
+    return oracle.PairList(N, e, e, np.zeros((0, 3, 3)), mu=mu, K=K, K_axis=ax, B=(0.3, -0.2, 1.1))
+
+
+def test_empty_list_field_and_energy_are_the_onsite_closed_forms():
+    # no couplings: each site sees its own Zeeman field mu muB B and the
+    # anisotropy field 2 K (a.S) a, and the energy is the sum of -mu muB B.S
+    # and -K (a.S)^2
+    pl = empty_list()
+    S = random_sphere(pl.N, 3)
+    proj = np.einsum("ci,ic->i", S, pl.K_axis.reshape(-1, 3))
+    want = MU_B * pl.mu[None, :] * pl.B[:, None] + 2.0 * pl.K[None, :] * proj[None, :] * pl.K_axis.reshape(-1, 3).T
+    assert np.max(np.abs(oracle.pl_field(pl, S) - want)) < 1e-14
+    t = oracle.pl_energy(pl, S)
+    assert abs(t[4] - (-np.sum(MU_B * pl.mu * (pl.B @ S)) - np.sum(pl.K * proj ** 2))) < 1e-12
+    assert t[0] == 0.0

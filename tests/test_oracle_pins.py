@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.helpers import max_rel, oracle_model
+from tests.helpers import max_rel, oracle_lattice, oracle_model
 from workloads import (BCC_FRAC, Workload, bcc_5shell_stochastic, fm_tilt, random_sphere,
                        sc_chiral_dipolar, uniform_state)
 
@@ -589,3 +589,11 @@ def test_heun_site_offset_reproduces_a_slab_of_a_larger_lattice():
     # without the offset the noise differs
     off = oracle.heun(oracle_model(ws), slab, alpha=0.1, dt_fs=0.5, T_K=50.0, seed=1004, step0=3, n_steps=1)
     assert np.max(np.abs(off[:, inner] - got[:, inner])) > 1e-6
+
+
+def test_model_rejects_shell_lists_shorter_than_the_shell_count():
+    lat = oracle_lattice(Workload(name="t", L=(3, 3, 3)))
+    with pytest.raises(ValueError):
+        oracle.Model(lat, n_shells=3, J_shell=(1.0, -0.3, 0.1), D_shell=(0.4,))
+    with pytest.raises(ValueError):
+        oracle.Model(lat, n_shells=2, J_shell=(1.0,))
