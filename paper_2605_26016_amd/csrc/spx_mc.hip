@@ -122,11 +122,25 @@ __global__ __launch_bounds__(kMcB) void k_mc_colour(double *__restrict__ S, Bond
     const int64_t N = g.N;
     unsigned int accepted = 0;
     for (int64_t t = (int64_t)blockIdx.x * kMcB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kMcB) {
-        const int j = (int)(t % J);
-        const int64_t row = t / J;
-        const int y = (int)(row % g.Ly);
-        const int z = (int)((row / g.Ly) % g.Lz);
-        const int a = (int)(row / ((int64_t)g.Ly * g.Lz));
+        // slot -> (j, y, z, a); 32-bit division when the slot count fits
+        // (every lattice below 2^32 slots), which is far cheaper than the
+        // 64-bit routine
+        int j, y, z, a;
+        if (total <= (int64_t)0xffffffffll) {
+            const uint32_t tt = (uint32_t)t, uJ = (uint32_t)J, uLy = (uint32_t)g.Ly, uLz = (uint32_t)g.Lz;
+            const uint32_t row = tt / uJ;
+            const uint32_t yz = row / uLy;
+            j = (int)(tt - row * uJ);
+            y = (int)(row - yz * uLy);
+            a = (int)(yz / uLz);
+            z = (int)(yz - (uint32_t)a * uLz);
+        } else {
+            const int64_t row = t / J;
+            j = (int)(t % J);
+            y = (int)(row % g.Ly);
+            z = (int)((row / g.Ly) % g.Lz);
+            a = (int)(row / ((int64_t)g.Ly * g.Lz));
+        }
         int x0 = (c - col.ky * y - col.kz * z - col.o[a]) % C;
         if (x0 < 0) x0 += C;
         const int x = x0 + C * j;
