@@ -97,3 +97,31 @@ def test_noise_and_philox_argument_checks(lib):
     assert lib.spx_thermal_noise(1, 2, 0, 10, None, None) == 1
     assert lib.spx_philox4x32_10(None, None, 3, None, None) == 1
     assert lib.spx_thermal_noise(1, 2, 0, 0, None, None) == 0
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # the Python package copied without libspx.so: every entry point must
+    # raise, never fall back to another implementation
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_2605_26016_amd")
+    dst = tmp_path / "paper_2605_26016_amd"
+    dst.mkdir()
+    for f in os.listdir(src):
+        if f.endswith(".py"):
+            shutil.copy(os.path.join(src, f), dst / f)
+    code = ("import numpy as np\n"
+            "from paper_2605_26016_amd import spx\n"
+            "for call in (lambda: spx.load(), lambda: spx.setup_hamiltonian((4, 4, 4), J_shell=(1.0,)),\n"
+            "             lambda: spx.abi_version()):\n"
+            "    try:\n"
+            "        call()\n"
+            "    except RuntimeError as e:\n"
+            "        assert 'missing' in str(e), e\n"
+            "    else:\n"
+            "        raise SystemExit('no error without the library')\n"
+            "print('ok')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=120,
+                       env={**os.environ, "PYTHONPATH": str(tmp_path)})
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
