@@ -34,6 +34,11 @@ CASES = {
     "bcc4": bcc_5shell_stochastic((4, 4, 4)),          # with uniaxial anisotropy: Metropolis only
     "bcc6": bcc_5shell_stochastic((6, 6, 6)),
 }
+# many blocks, interior sites and ragged colour rows: one shell (the
+# two-deep neighbour loop of heat-bath) and three shells (four-deep)
+CASES["sc_nn_37x21x13"] = Workload(name="nn", L=(37, 21, 13), J_shell=(1.0,), B=(0.0, 0.3, 1.0), field_prec="fp64")
+CASES["sc3shell_23x17x11"] = Workload(name="s3", L=(23, 17, 11), periodic=(1, 1, 0), J_shell=(1.0, 0.5, -0.2),
+                                      B=(1.0, 0.0, 0.5), field_prec="fp64")
 CASES["bcc4_noK"] = bcc_5shell_stochastic((4, 4, 4))
 CASES["bcc4_noK"].K = 0.0
 
@@ -49,7 +54,9 @@ def test_colouring_matches_the_oracle(name):
 
 
 @pytest.mark.parametrize("name,method,T", [("sc4", 0, 80.0), ("sc5x4x4", 0, 40.0), ("sc3shell_open", 0, 30.0),
-                                           ("bcc4_noK", 0, 300.0), ("sc4", 1, 80.0), ("bcc4", 1, 600.0)])
+                                           ("bcc4_noK", 0, 300.0), ("sc4", 1, 80.0), ("bcc4", 1, 600.0),
+                                           ("sc_nn_37x21x13", 0, 60.0), ("sc3shell_23x17x11", 0, 40.0),
+                                           ("sc_nn_37x21x13", 1, 60.0), ("sc3shell_23x17x11", 1, 40.0)])
 def test_sweeps_match_the_oracle(name, method, T):
     import torch
     from paper_2605_26016_amd import spx
