@@ -126,7 +126,14 @@ typedef struct {
  * stored-stage corrector of mode 3 (FP32 field_prec only; same results), 7
  * as 3 without the noise store: the corrector draws the step's noise again
  * from the same Philox block (24 bytes per spin of library memory; same
- * results as 3). */
+ * results as 3), 8 temporally fused: predictor and corrector in one pass
+ * that keeps the predicted state on chip and predicts a one-cell ring
+ * around each block's tile again, each site with its own noise, so the
+ * lattice is read and written once per step (single-sublattice simple cubic
+ * shells 1, any tensor, or shells 1-3 isotropic; no dipolar term; results
+ * equal to 3 up to the summation order of the bilinear sums).  heun_field 8
+ * on any other Hamiltonian fails with SPX_ERR_UNSUPPORTED; heun_field 0
+ * selects 8 where it applies (z chunk 64 unless zchunk is given), else 3. */
 typedef struct {
     int32_t field_prec;        /* spx_precision */
     int32_t backend;
@@ -185,9 +192,11 @@ typedef struct {
 spx_status spx_llg_heun_step(spx_ham *h, double *S, const spx_llg_params *p, void *stream);
 
 /* Graph replay of the Heun loop (default on): for n_steps >= 4 the library
- * captures two steps (S -> scratch -> S, the noise step read from a device
- * counter that the graph advances) once per (state pointer, constants,
- * stream) and replays it n_steps/2 times.  Off while kernels are timed and
+ * captures g steps (g = 16 when n_steps >= 16, else 2; S -> scratch -> S ...,
+ * the noise step read from a device counter that the graph's last node
+ * advances by g) once per (state pointer, constants, step count g) and
+ * replays it n_steps/g times on the caller's stream; the n_steps % g
+ * remaining steps are launched directly.  Off while kernels are timed and
  * with the dipolar term.  Results are identical to direct launches. */
 spx_status spx_set_heun_graph(spx_ham *h, int32_t enable);
 
@@ -245,7 +254,7 @@ typedef struct {
     int32_t stencil_engine;    /* 1 gather, 2 z-march */
     int32_t shape;             /* z-march shell shape id, -1 if none */
     int32_t zchunk;
-    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field, 3 stored stage and noise, 4 as 3 + noise pre-pass, 5 split, 6 split predictor, 7 stored stage, noise drawn again */
+    int32_t heun_field;        /* 1 recompute, 2 stored FP32 field, 3 stored stage and noise, 4 as 3 + noise pre-pass, 5 split, 6 split predictor, 7 stored stage, noise drawn again, 8 fused single pass */
     int32_t tuned;             /* 1 if the autotuner chose zchunk / heun_field */
     double tuned_step_us;      /* its timing of one Heun step (microseconds) */
     int32_t heun_graph;        /* 1 once a captured Heun graph exists (replayed for runs of >= 4 steps) */

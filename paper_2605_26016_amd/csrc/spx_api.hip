@@ -178,7 +178,8 @@ struct spx_ham {
     ZPlan zp;
     ZPlan zp64;  // FP64 plan of the same table for batched-image field passes (GNEB)
     int engine = 1;          // 1 gather, 2 z-march
-    int heun_field = 1;      // 1 recompute, 2 stored FP32 field, 3 stored stage (P, eta), 7 stored P only
+    bool fusable = false;    // the fused Heun step (mode 8) applies
+    int heun_field = 1;      // 1 recompute, 2 stored FP32 field, 3 stored stage (P, eta), 7 stored P only, 8 fused
     float *d_bstore = nullptr;
     void *d_ebil = nullptr;  // energy: bilinear field of the z-march pass (made at the first call)
     double *d_P = nullptr;   // heun_field 3: S^n + dt/2 f(S^n)
@@ -319,8 +320,10 @@ spx_status get_ham_view(spx_ham *h, HamView &v) {
 
 static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z, bool tune_field, hipStream_t st);
 static spx_status heun_buffers(spx_ham *h, int hf);
-// Heun modes of the z-march engine: 1 .. kMaxHeunMode (spx_options.heun_field)
-constexpr int kMaxHeunMode = 7;
+// Heun modes of the z-march engine: 1 .. kMaxHeunMode (spx_options.heun_field);
+// mode 8 is the temporally fused single-pass step
+constexpr int kMaxHeunMode = 8;
+constexpr int kHeunFused = 8;
 
 extern "C" {
 
@@ -535,8 +538,22 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
         h->engine = (have && engine_req != 1) ? 2 : 1;
         if (have && zchunk_req > 0) h->zp.zch = zchunk_req;
         h->heun_field = 1;
-        // stored stages exist in the z-march engine only; the gather engine recomputes
-        if (h->engine == 2) h->heun_field = hfield_req > 0 ? hfield_req : 3;
+        // the fused step needs a single-sublattice shape of range one cell and
+        // no dipolar term (whose FFT field is taken between the two stages)
+        const bool fusable = h->engine == 2 && !model->dipolar && fused_heun_supported(h->zp, h->grid);
+        h->fusable = fusable;
+        if (hfield_req == kHeunFused && !fusable) {
+            free_all(h);
+            delete h;
+            return fail(SPX_ERR_UNSUPPORTED, "the fused Heun step (heun_field 8) needs the z-march engine on a "
+                                             "single-sublattice shell shape of range one cell, without dipolar");
+        }
+        // stored stages exist in the z-march engine only; the gather engine
+        // recomputes.  Default: the fused step where it applies, else mode 3
+        if (h->engine == 2) {
+            h->heun_field = hfield_req > 0 ? hfield_req : (fusable ? kHeunFused : 3);
+            if (hfield_req == 0 && fusable && zchunk_req == 0) h->zp.zch = 64;
+        }
         if ((s = heun_buffers(h, h->heun_field)) != SPX_OK) {
             free_all(h);
             delete h;
@@ -656,6 +673,12 @@ static spx_status enqueue_heun_step(spx_ham *h, const HeunConst &hc, uint64_t st
         bd0 = h->d_bdip0;
     }
     hipError_t e;
+    if (h->engine == 2 && h->heun_field == kHeunFused) {
+        KernelTimer kt(h, 0, st);
+        e = heun_fused(h->zp, h->grid, h->onsite, hc, step, cur, nxt, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_llg_heun_step: fused step");
+        return SPX_OK;
+    }
     if (h->engine == 2 && h->heun_field == 4 && hc.noise) {
         KernelTimer kt(h, 3, st);
         e = zmarch_noise(hc, step, h->grid.N, h->d_eta, st);
@@ -739,8 +762,9 @@ static spx_status heun_buffers(spx_ham *h, int hf) {
     const size_t n3 = (size_t)3 * h->grid.N;
     spx_status s = SPX_OK;
     if ((hf == 2 || hf == 5 || hf == 6) && !h->d_bstore) s = dev_alloc(h, &h->d_bstore, n3, "stored Heun field");
-    if (s == SPX_OK && hf >= 3 && !h->d_P) s = dev_alloc(h, &h->d_P, n3, "stored Heun stage");
-    if (s == SPX_OK && hf >= 3 && hf != 7 && !h->d_eta) s = dev_alloc(h, &h->d_eta, n3, "stored Heun noise");
+    const bool staged = hf >= 3 && hf <= 7;
+    if (s == SPX_OK && staged && !h->d_P) s = dev_alloc(h, &h->d_P, n3, "stored Heun stage");
+    if (s == SPX_OK && staged && hf != 7 && !h->d_eta) s = dev_alloc(h, &h->d_eta, n3, "stored Heun noise");
     return s;
 }
 
@@ -753,7 +777,7 @@ static void heun_buffers_trim(spx_ham *h) {
         h->ws_bytes -= (int64_t)sizeof(float) * n3;
     }
     for (double **p : {&h->d_P, &h->d_eta}) {
-        const bool used = h->heun_field >= 3 && !(p == &h->d_eta && h->heun_field == 7);
+        const bool used = h->heun_field >= 3 && h->heun_field <= 7 && !(p == &h->d_eta && h->heun_field == 7);
         if (!used && *p) {
             (void)hipFree(*p);
             *p = nullptr;
@@ -785,7 +809,8 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
                     cz = z; chf = hf; cus = us; hit = true;   // the last matching line wins
                 }
             std::fclose(f);
-            if (hit && !((chf == 2 || chf == 5 || chf == 6) && h->field_prec != SPX_FP32)) {
+            if (hit && !((chf == 2 || chf == 5 || chf == 6) && h->field_prec != SPX_FP32) &&
+                !(chf == kHeunFused && !h->fusable)) {
                 if (tune_z) h->zp.zch = cz;
                 if (tune_field) h->heun_field = chf;
                 h->tune_us = cus;
@@ -796,17 +821,25 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
             }
         }
     }
-    std::vector<int> zs;
-    if (tune_z) {
-        for (int z : {4, 8, 16, 32})
+    // candidate z chunks: the two-sweep modes march short chunks; the fused
+    // step pays a four-plane pipeline fill per chunk, so it tries longer ones
+    auto zlist = [&](int hf) {
+        std::vector<int> zs;
+        if (!tune_z) {
+            zs.push_back(h->zp.zch);
+            return zs;
+        }
+        const std::vector<int> cand = hf == kHeunFused ? std::vector<int>{16, 32, 64, 128}
+                                                       : std::vector<int>{4, 8, 16, 32};
+        for (int z : cand)
             if (z <= g.Lz || zs.empty()) zs.push_back(z);
-    } else {
-        zs.push_back(h->zp.zch);
-    }
+        return zs;
+    };
     std::vector<int> hfs = {h->heun_field};
     if (tune_field) {
         hfs = {1, 3, 4, 7};
         if (h->field_prec == SPX_FP32) hfs = {1, 2, 3, 4, 5, 6, 7};
+        if (h->fusable) hfs.push_back(kHeunFused);
     }
     for (int hf : hfs) {
         spx_status s = heun_buffers(h, hf);
@@ -834,8 +867,8 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
     double best = 1e300;
     int bz = h->zp.zch, bh = h->heun_field;
     const int reps = 4;
-    for (int z : zs)
-        for (int hf : hfs) {
+    for (int hf : hfs)
+        for (int z : zlist(hf)) {
             h->zp.zch = z;
             h->heun_field = hf;
             spx_status r = SPX_OK;

@@ -109,6 +109,12 @@ hipError_t heun_split_pre(const Grid &g, const Onsite &os, const HeunConst &hc, 
                           const float *bil, const float *bdip, double *St, double *P, double *eta, hipStream_t st);
 hipError_t heun_split_post(const Grid &g, const Onsite &os, const HeunConst &hc, const double *St, const float *bil,
                            const float *bdip, const double *P, const double *eta, double *out, hipStream_t st);
+// Temporally fused Heun step (spx_fused.hip): predictor and corrector in one
+// z-march over the lattice, S -> out (out != S), for single-sublattice shell
+// shapes of range one cell (simple cubic shells 1 and, isotropic, 1-3).
+bool fused_heun_supported(const ZPlan &zp, const Grid &g);
+hipError_t heun_fused(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
+                      const double *S, double *out, hipStream_t st);
 hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
                           const double *S, const double *St, const float *bdipS, const float *bdipT,
                           const float *bload, const double *pload, const double *eload, double *out,

@@ -1,0 +1,173 @@
+"""GPU parity of the temporally fused Heun step (heun_field 8) against the
+FP64 CPU oracle, through the C ABI.
+
+The fused step predicts a one-cell ring around every block's tile again (with
+the noise of each site's own lattice index) and keeps the predicted state on
+chip, so the cases put block edges inside the lattice in every direction:
+several 62-column x tiles and 14-row (FP32) or 6-row (FP64) y tiles with
+ragged tails, z chunks of 3 and 64 planes, open, periodic and mixed faces,
+and lattices smaller than one tile (down to one site, where every neighbour
+is the site itself).
+
+Tolerances (as for the other Heun modes): one step from identical FP64 state
+max |S - S_ref| <= 1e-9 per component in mixed precision (FP32 field, FP64
+state) and 1e-12 in FP64, times the number of steps.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import gpu_hamiltonian, oracle_model, require_gpu, to_dev
+from workloads import Workload, random_sphere, sc_billion
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+    import torch
+    torch.cuda.init()
+
+
+def run_gpu(w, S, prec, n_steps, step0=17, graph=True, **setup):
+    import torch
+    from paper_2605_26016_amd import spx
+    h = gpu_hamiltonian(w, field_prec=prec, **setup)
+    if not graph:
+        spx.set_heun_graph(h, False)
+    St = to_dev(S)
+    spx.llg_heun_step(h, St, alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed,
+                      step0=step0, n_steps=n_steps)
+    torch.cuda.synchronize()
+    return St.cpu().numpy(), spx.get_info(h)
+
+
+def stoch(L, periodic=(1, 1, 1), **kw):
+    d = dict(name="t", L=L, periodic=periodic, J_shell=(1.0,), K=0.1, T_K=300.0, alpha=0.1, dt_fs=0.5,
+             philox_seed=1004)
+    d.update(kw)
+    return Workload(**d)
+
+
+FUSED_CASES = [
+    # name, workload, field precision, steps, tolerance per step
+    ("sc_fp32_multitile_periodic", stoch((130, 31, 20)), "fp32", 2, 1e-9),
+    ("sc_fp32_multitile_open", stoch((130, 31, 20), periodic=(0, 0, 0)), "fp32", 2, 1e-9),
+    ("sc_fp32_mixed_bc", stoch((70, 29, 11), periodic=(1, 0, 1)), "fp32", 3, 1e-9),
+    ("sc_fp32_exact_tiles", stoch((124, 28, 16)), "fp32", 2, 1e-9),
+    ("sc_fp64_multitile", stoch((70, 17, 9)), "fp64", 2, 1e-12),
+    ("sc_fp64_open_det", stoch((70, 17, 9), periodic=(0, 0, 0), T_K=0.0), "fp64", 3, 1e-12),
+    ("sc_one_site", stoch((1, 1, 1)), "fp64", 2, 1e-12),
+    ("sc_thin_periodic", stoch((2, 3, 1)), "fp32", 2, 1e-9),
+    ("sc_thin_open", stoch((1, 5, 7), periodic=(0, 0, 0)), "fp64", 2, 1e-12),
+    ("sc_dmi_zeeman_open_fp64", stoch((67, 15, 7), periodic=(0, 0, 0), D_shell=(0.3,), B=(0.0, 0.2, 0.5),
+                                      mu=(2.0,), K=0.1, K_axis=(0.6, 0.0, 0.8)), "fp64", 2, 1e-12),
+    ("sc_dmi_fp32", stoch((67, 30, 12), periodic=(1, 0, 1), D_shell=(0.3,), B=(0.0, 0.0, 0.5)), "fp32", 2, 1e-9),
+    ("sc3_fp32_multitile", stoch((100, 20, 16), periodic=(1, 0, 1), J_shell=(1.0, -0.3, 0.15),
+                                 B=(0.2, 0.0, 0.4)), "fp32", 2, 1e-9),
+    ("sc3_fp64_open", stoch((65, 13, 9), periodic=(0, 0, 0), J_shell=(1.0, -0.3, 0.15)), "fp64", 2, 1e-12),
+]
+
+
+@pytest.mark.parametrize("zchunk", [3, 64], ids=["z3", "z64"])
+@pytest.mark.parametrize("name,w,prec,n,tol", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+def test_fused_heun_parity(name, w, prec, n, tol, zchunk):
+    S = random_sphere(w.N, 61)
+    ref = oracle.heun(oracle_model(w), S, alpha=w.alpha, dt_fs=w.dt_fs, T_K=w.T_K, seed=w.philox_seed,
+                      step0=17, n_steps=n)
+    got, info = run_gpu(w, S, prec, n, heun_field=8, zchunk=zchunk)
+    assert info.heun_field == 8 and info.zchunk == zchunk
+    err = float(np.max(np.abs(got - ref)))
+    print(f"{name} z{zchunk}: max |dS| = {err:.3e}", flush=True)
+    assert err <= tol * n, (name, err)
+    assert np.max(np.abs(np.sqrt((got * got).sum(0)) - 1.0)) < 1e-14
+
+
+def test_fused_is_default_where_it_applies():
+    from paper_2605_26016_amd import spx
+    h = gpu_hamiltonian(stoch((40, 30, 20)), field_prec="fp32")
+    info = spx.get_info(h)
+    assert (info.heun_field, info.zchunk) == (8, 64)
+    # bcc (two sublattices) keeps the two-sweep stored-stage mode
+    wb = Workload(name="b", L=(8, 8, 8), cell=np.eye(3) * 0.287, frac=((0, 0, 0), (0.5, 0.5, 0.5)),
+                  mu=(1.0, 1.0), J_shell=(1.33, 0.75))
+    assert spx.get_info(gpu_hamiltonian(wb, field_prec="fp32")).heun_field == 3
+
+
+def test_fused_rejected_where_it_does_not_apply():
+    from paper_2605_26016_amd import spx
+    wb = Workload(name="b", L=(8, 8, 8), cell=np.eye(3) * 0.287, frac=((0, 0, 0), (0.5, 0.5, 0.5)),
+                  mu=(1.0, 1.0), J_shell=(1.33, 0.75))
+    with pytest.raises(spx.SpxError):
+        gpu_hamiltonian(wb, field_prec="fp32", heun_field=8)
+    # four sc shells reach two cells
+    with pytest.raises(spx.SpxError):
+        gpu_hamiltonian(stoch((16, 16, 16), J_shell=(1.0, 0.2, -0.3, -0.1)), field_prec="fp32", heun_field=8)
+    # the dipolar field is taken between the stages
+    wd = stoch((8, 8, 8), periodic=(0, 0, 0), dipolar=1, mu=(2.0,), cell=np.eye(3) * 0.4)
+    with pytest.raises(spx.SpxError):
+        gpu_hamiltonian(wd, field_prec="fp32", heun_field=8)
+    # the gather engine has no fused step
+    with pytest.raises(spx.SpxError):
+        gpu_hamiltonian(stoch((16, 16, 16)), field_prec="fp32", heun_field=8, stencil_engine=1)
+
+
+def test_fused_graph_replay_resume_and_determinism():
+    w = stoch((130, 31, 20))
+    S = random_sphere(w.N, 62)
+    a, _ = run_gpu(w, S, "fp32", 40, step0=5, graph=True, heun_field=8)
+    b, _ = run_gpu(w, S, "fp32", 40, step0=5, graph=False, heun_field=8)
+    assert np.array_equal(a, b)
+    c, _ = run_gpu(w, S, "fp32", 40, step0=5, graph=True, heun_field=8)
+    assert np.array_equal(a, c)
+    # 17 + 23 steps from the same counters give the same state
+    d, _ = run_gpu(w, S, "fp32", 17, step0=5, graph=True, heun_field=8)
+    e, _ = run_gpu(w, d, "fp32", 23, step0=22, graph=True, heun_field=8)
+    assert np.array_equal(a, e)
+
+
+def test_fused_matches_stored_stage_mode_fp64():
+    # same arithmetic as the stored-stage two-sweep mode up to the summation
+    # order of the FP64 bilinear sums
+    w = stoch((90, 20, 12), periodic=(1, 0, 1), J_shell=(1.0, -0.3, 0.15))
+    S = random_sphere(w.N, 63)
+    a, _ = run_gpu(w, S, "fp64", 4, heun_field=8)
+    b, _ = run_gpu(w, S, "fp64", 4, heun_field=3)
+    assert np.max(np.abs(a - b)) <= 1e-14
+
+
+def test_fused_sc1024_interior_slabs():
+    # the full sc 1024^3 stochastic workload in the benchmark's configuration:
+    # two 6-plane slabs, one across a z-chunk boundary (plane 512) and one
+    # ending next to the last plane, each checked against the oracle run on
+    # the slab plus a 2-plane halo with the slab's global noise counters
+    # (periodic z wrap is covered by the smaller lattices above)
+    import torch
+    from paper_2605_26016_amd import spx
+    from workloads import random_sphere_device
+    w = sc_billion()
+    Lx, Ly, Lz = w.L
+    plane = Lx * Ly
+    S = random_sphere_device(w.N, w.init_seed)
+    slabs = [(509, 6), (1016, 6)]
+    halo = 2
+    before = [S[:, (z0 - halo) * plane:(z0 + nz + halo) * plane].cpu().numpy() for z0, nz in slabs]
+    h = gpu_hamiltonian(w)
+    info = spx.get_info(h)
+    print(f"sc1024: heun_field {info.heun_field} zchunk {info.zchunk}", flush=True)
+    assert info.heun_field == 8
+    spx.llg_heun_step(h, S, alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed,
+                      step0=3, n_steps=1)
+    after = [S[:, z0 * plane:(z0 + nz) * plane].cpu().numpy() for z0, nz in slabs]
+    nrm = float((torch.sqrt((S * S).sum(0)) - 1.0).abs().max())
+    del S, h
+    torch.cuda.empty_cache()
+    assert nrm <= 1e-14
+    for (z0, nz), s0, got in zip(slabs, before, after):
+        ws = Workload(name="slab", L=(Lx, Ly, nz + 2 * halo), periodic=(1, 1, 0), J_shell=w.J_shell, K=w.K)
+        ref = oracle.heun(oracle_model(ws), s0, alpha=w.alpha, dt_fs=w.dt_fs, T_K=w.T_K, seed=w.philox_seed,
+                          step0=3, n_steps=1, site0=(z0 - halo) * plane)
+        err = float(np.max(np.abs(got - ref[:, halo * plane:(halo + nz) * plane])))
+        print(f"sc1024 fused slab z {z0}..{z0 + nz - 1}: max |dS| = {err:.3e}", flush=True)
+        assert err <= 1e-9
