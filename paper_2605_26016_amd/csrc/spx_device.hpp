@@ -4,6 +4,7 @@
 #pragma once
 
 #include "spx_internal.hpp"
+#include "spx_math.hpp"
 
 namespace spx {
 
@@ -98,9 +99,10 @@ __device__ __forceinline__ void llg_rhs(const double s[3], const double B[3], do
     f[2] = pre * (c2 + alpha * d2);
 }
 
-// N[v] = v/|v| with one reciprocal (within one rounding of three divisions).
+// N[v] = v/|v| with one reciprocal square root (about one ulp; the norm of a
+// spin update is close to 1).
 __device__ __forceinline__ void normalise3(double v[3]) {
-    const double inv = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double inv = rsqrt_pos(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     v[0] *= inv;
     v[1] *= inv;
     v[2] *= inv;
@@ -130,8 +132,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
 // Three standard normals for site i at step n: one Philox block with
 // counter (i lo, i hi ^ tag, n lo, n hi) and key (seed lo, seed hi), uniforms
 // (x + 1/2) 2^-32, Box-Muller on (u0,u1) -> (eta_x, eta_y), (u2,u3) -> eta_z.
-// The angle 2 pi u is evaluated as sincospi(2u): 2u is exact, so no argument
-// reduction by pi is needed; this agrees with cos(2 pi u) to a few ulp.
+// The angle 2 pi u is evaluated as sin/cos(pi t) of t = 2u: 2u is exact, so no
+// argument reduction by pi is needed.  The uniforms lie in [2^-33, 1 - 2^-33],
+// so -2 ln u is a positive normal number and the functions of spx_math.hpp
+// (about one ulp each) apply; the normals agree with a libm evaluation to a
+// few ulp.
 __device__ __forceinline__ void thermal_eta(uint64_t seed, uint64_t step, uint32_t tag, uint64_t site,
                                             double eta[3]) {
     uint32_t c0 = (uint32_t)site, c1 = (uint32_t)(site >> 32) ^ tag;
@@ -140,13 +145,14 @@ __device__ __forceinline__ void thermal_eta(uint64_t seed, uint64_t step, uint32
     const double sc = 2.3283064365386963e-10;  // 2^-32
     const double u0 = ((double)c0 + 0.5) * sc, u1 = ((double)c1 + 0.5) * sc;
     const double u2 = ((double)c2 + 0.5) * sc, u3 = ((double)c3 + 0.5) * sc;
-    const double r0 = sqrt(-2.0 * log(u0));
-    const double r1 = sqrt(-2.0 * log(u2));
-    double sn, cs;
-    sincospi(2.0 * u1, &sn, &cs);
+    const double r0 = sqrt_pos(-2.0 * log_pos(u0));
+    const double r1 = sqrt_pos(-2.0 * log_pos(u2));
+    double sn, cs, sn3, cs3;
+    sincospi_d(u1 + u1, sn, cs);
+    sincospi_d(u3 + u3, sn3, cs3);
     eta[0] = r0 * cs;
     eta[1] = r0 * sn;
-    eta[2] = r1 * cospi(2.0 * u3);
+    eta[2] = r1 * cs3;
 }
 
 // Wavefront (64 lanes) sum of a double, result valid in lane 0.

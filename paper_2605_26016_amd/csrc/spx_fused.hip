@@ -62,6 +62,39 @@ struct FArgs {
     uint64_t step;
 };
 
+// Integrator and on-site constants of the one sublattice, packed so that the
+// kernel keeps few of them in scalar registers.
+struct FConst {
+    double dt, hdt, pre, alpha, inv, sigma;
+    double bz[3];
+    double K2[kMaxAniso];     // 2 K_l
+    double ax[kMaxAniso][3];  // unit axes
+    int n_aniso;
+    int noise;
+    uint64_t seed;
+    uint32_t tag;
+    const uint64_t *step_dev;
+};
+
+// On-site field 2 K_l (s.n_l) n_l + Zeeman; NA = the number of anisotropy axes
+// (0 or 1), or -1 for up to kMaxAniso axes counted at run time.
+template <int NA>
+__device__ __forceinline__ void fused_onsite(const FConst &fc, const double s[3], double b[3]) {
+    b[0] = fc.bz[0];
+    b[1] = fc.bz[1];
+    b[2] = fc.bz[2];
+    constexpr int NL = NA < 0 ? kMaxAniso : NA;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        if (NA >= 0 || l < fc.n_aniso) {
+            const double c = fc.K2[l] * (s[0] * fc.ax[l][0] + s[1] * fc.ax[l][1] + s[2] * fc.ax[l][2]);
+            b[0] = fma(c, fc.ax[l][0], b[0]);
+            b[1] = fma(c, fc.ax[l][1], b[1]);
+            b[2] = fma(c, fc.ax[l][2], b[2]);
+        }
+    }
+}
+
 template <int KIND>
 struct FShape {
     static constexpr ShapeTable t = make_shape(KIND);
@@ -130,8 +163,8 @@ __device__ __forceinline__ void fused_bil(const T *const (&plane)[3], int at, in
     }
 }
 
-template <int KIND, typename T, bool ISO, int NW>
-__global__ __launch_bounds__(kFX *NW) void k_heun_fused(FArgs g, Onsite os, HeunConst hc,
+template <int KIND, typename T, bool ISO, int NW, int NA>
+__global__ __launch_bounds__(kFX *NW) void k_heun_fused(FArgs g, FConst fc,
                                                         FWeights<T, ISO ? make_shape(KIND).nshell
                                                                         : 9 * make_shape(KIND).nb> W) {
     static_assert(make_shape(KIND).nsub == 1 && make_shape(KIND).rx <= 1 && make_shape(KIND).ry <= 1 &&
@@ -217,62 +250,60 @@ __global__ __launch_bounds__(kFX *NW) void k_heun_fused(FArgs g, Onsite os, Heun
             for (int c = 0; c < 3; ++c) base[c * SPL + loff[1]] = (T)pre[1][c];
     };
 
-    // own FP64 S^n: ownA = plane L being predicted, ownB = plane L + 1
-    double ownA[3], ownB[3];
-    // corrector carry of the plane being corrected (A) and the next (B):
-    // P = S^n + dt/2 f(S^n), thermal field sigma eta, FP64 S~
-    double cPA[3], cHA[3], cTA[3], cPB[3], cHB[3], cTB[3];
+    // Registers that carry a plane from one iteration to a later one, in two
+    // sets used by alternate iterations (the loop below is unrolled by two):
+    //   own[j]: FP64 S^n of the thread's site, read by the predictor of
+    //     iteration k (plane k-1, set (k-1) & 1), then refilled with plane
+    //     k+1 from the fetch;
+    //   cP/cH/cT[j]: the corrector's P = S^n + dt/2 f(S^n), thermal field
+    //     sigma eta and FP64 S~ of plane L, read by the corrector of iteration
+    //     k (plane k-3) and then overwritten by the predictor (plane k-1), both
+    //     of parity (k-1) & 1.
+    double own[2][3];
+    double cP[2][3], cH[2][3], cT[2][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) cPA[c] = cHA[c] = cTA[c] = cPB[c] = cHB[c] = cTB[c] = 0.0;
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cP[j][c] = cH[j][c] = cT[j][c] = 0.0;
 
     fetch(0);
     commit(0);
     fetch(1);
     commit(1);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ownA[c] = pre[0][c];
+    for (int c = 0; c < 3; ++c) own[1][c] = pre[0][c];
     fetch(2);
     commit(2);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ownB[c] = pre[0][c];
+    for (int c = 0; c < 3; ++c) own[0][c] = pre[0][c];
     __syncthreads();
 
-    const double hdt = 0.5 * hc.dt;
-    const double inv = hc.inv_mumuB[0], sg = hc.sigma[0];
-    const uint64_t nstep = hc.noise ? noise_step(hc, g.step) : 0;
+    const uint64_t nstep = fc.noise ? (fc.step_dev ? *fc.step_dev + g.step : g.step) : 0;
     const int lastL = nz + 3;  // last S^n plane a predictor needs
-#pragma unroll 1
-    for (int k = 2; k <= nz + 4; ++k) {
+    auto iter = [&](int k, double (&oS)[3], double (&P)[3], double (&H)[3], double (&Tt)[3])
+                    __attribute__((always_inline)) {
         const bool more = k + 1 <= lastL;
         if (more) fetch(k + 1);
-        if (k >= 5) {
+        if (k >= 5 && corr) {
             // corrector of plane L = k - 3 (z = zs + k - 5)
             const int L = k - 3;
-            if (corr) {
-                const T *tp[3] = {&lt[(L - 1) & 3][0][0], &lt[L & 3][0][0], &lt[(L + 1) & 3][0][0]};
-                T bil[3];
-                fused_bil<KIND, T, ISO, kFX>(tp, row * kFX + lane, TPL, W, bil);
-                double bt[3];
-                aniso_field(os, 0, cTA, bt);
-                double B1[3];
+            const T *tp[3] = {&lt[(L - 1) & 3][0][0], &lt[L & 3][0][0], &lt[(L + 1) & 3][0][0]};
+            T bil[3];
+            fused_bil<KIND, T, ISO, kFX>(tp, row * kFX + lane, TPL, W, bil);
+            double bt[3];
+            fused_onsite<NA>(fc, Tt, bt);
+            double B1[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) B1[c] = ((double)bil[c] + bt[c] + os.bz[0][c]) * inv + cHA[c];
-                double f1[3];
-                llg_rhs(cTA, B1, hc.pre, hc.alpha, f1);
-                double pn[3];
+            for (int c = 0; c < 3; ++c) B1[c] = ((double)bil[c] + bt[c]) * fc.inv + H[c];
+            double f1[3];
+            llg_rhs(Tt, B1, fc.pre, fc.alpha, f1);
+            double pn[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) pn[c] = cPA[c] + hdt * f1[c];
-                normalise3(pn);
-                const int64_t i = cx + (int64_t)g.Lx * (cy + (int64_t)g.Ly * (zs + L - 2));
+            for (int c = 0; c < 3; ++c) pn[c] = P[c] + fc.hdt * f1[c];
+            normalise3(pn);
+            const int64_t i = cx + (int64_t)g.Lx * (cy + (int64_t)g.Ly * (zs + L - 2));
 #pragma unroll
-                for (int c = 0; c < 3; ++c) g.out[c * N + i] = pn[c];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            cPA[c] = cPB[c];
-            cHA[c] = cHB[c];
-            cTA[c] = cTB[c];
+            for (int c = 0; c < 3; ++c) g.out[c * N + i] = pn[c];
         }
         if (k <= lastL) {
             // predictor of plane L = k - 1 (z = zs + k - 3) over the whole region
@@ -283,44 +314,45 @@ __global__ __launch_bounds__(kFX *NW) void k_heun_fused(FArgs g, Onsite os, Heun
             T bil[3];
             fused_bil<KIND, T, ISO, kSW>(sp, (row + 1) * kSW + lane + 1, SPL, W, bil);
             double eta[3] = {0.0, 0.0, 0.0};
-            if (hc.noise) {
+            if (fc.noise) {
                 const int64_t i = px + (int64_t)g.Lx * (py + (int64_t)g.Ly * pz);
-                thermal_eta(hc.seed, nstep, hc.tag, (uint64_t)i, eta);
+                thermal_eta(fc.seed, nstep, fc.tag, (uint64_t)i, eta);
             }
             double ba[3];
-            aniso_field(os, 0, ownA, ba);
+            fused_onsite<NA>(fc, oS, ba);
             double B[3], f0[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                cHB[c] = sg * eta[c];
-                B[c] = ((double)bil[c] + ba[c] + os.bz[0][c]) * inv + cHB[c];
+                H[c] = fc.sigma * eta[c];
+                B[c] = ((double)bil[c] + ba[c]) * fc.inv + H[c];
             }
-            llg_rhs(ownA, B, hc.pre, hc.alpha, f0);
+            llg_rhs(oS, B, fc.pre, fc.alpha, f0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                cTB[c] = ownA[c] + hc.dt * f0[c];
-                cPB[c] = ownA[c] + hdt * f0[c];
+                Tt[c] = oS[c] + fc.dt * f0[c];
+                P[c] = oS[c] + fc.hdt * f0[c];
             }
-            normalise3(cTB);
+            normalise3(Tt);
             T *const tb = &lt[L & 3][0][0];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) tb[c * TPL + row * kFX + lane] = ok ? (T)cTB[c] : T(0);
+            for (int c = 0; c < 3; ++c) tb[c * TPL + row * kFX + lane] = ok ? (T)Tt[c] : T(0);
         }
         if (more) {
             commit(k + 1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                ownA[c] = ownB[c];
-                ownB[c] = pre[0][c];
-            }
+            for (int c = 0; c < 3; ++c) oS[c] = pre[0][c];
         }
         __syncthreads();
+    };
+#pragma unroll 1
+    for (int k = 2; k <= nz + 4; k += 2) {
+        iter(k, own[1], cP[1], cH[1], cT[1]);
+        if (k + 1 <= nz + 4) iter(k + 1, own[0], cP[0], cH[0], cT[0]);
     }
 }
 
 template <int KIND, typename T, bool ISO, int NW>
-hipError_t launch_fused_kind(const ZPlan &zp, const FArgs &a0, const Onsite &os, const HeunConst &hc,
-                             hipStream_t st) {
+hipError_t launch_fused_kind(const ZPlan &zp, const FArgs &a0, const FConst &fc, hipStream_t st) {
     constexpr int NWT = ISO ? make_shape(KIND).nshell : 9 * make_shape(KIND).nb;
     FWeights<T, NWT> W;
     for (int k = 0; k < NWT; ++k) W.w[k] = (T)(sizeof(T) == 4 ? (double)zp.wf[k] : zp.wd[k]);
@@ -330,7 +362,9 @@ hipError_t launch_fused_kind(const ZPlan &zp, const FArgs &a0, const Onsite &os,
     const int nzc = (a.Lz + a.zch - 1) / a.zch;
     const int64_t ntile = (int64_t)a.nbx * a.nby * nzc;
     if (ntile > 0x7fffffff) return hipErrorInvalidValue;
-    k_heun_fused<KIND, T, ISO, NW><<<(unsigned)ntile, kFX * NW, 0, st>>>(a, os, hc, W);
+    if (fc.n_aniso == 0) k_heun_fused<KIND, T, ISO, NW, 0><<<(unsigned)ntile, kFX * NW, 0, st>>>(a, fc, W);
+    else if (fc.n_aniso == 1) k_heun_fused<KIND, T, ISO, NW, 1><<<(unsigned)ntile, kFX * NW, 0, st>>>(a, fc, W);
+    else k_heun_fused<KIND, T, ISO, NW, -1><<<(unsigned)ntile, kFX * NW, 0, st>>>(a, fc, W);
     return hipGetLastError();
 }
 
@@ -338,11 +372,11 @@ hipError_t launch_fused_kind(const ZPlan &zp, const FArgs &a0, const Onsite &os,
 // 125 VGPRs: four waves per SIMD), 8 otherwise (FP64 planes take twice the
 // LDS; the 26-neighbour shape needs more than 128 VGPRs).
 template <typename T, bool ISO>
-hipError_t launch_fused_t(const ZPlan &zp, const FArgs &a, const Onsite &os, const HeunConst &hc, hipStream_t st) {
+hipError_t launch_fused_t(const ZPlan &zp, const FArgs &a, const FConst &fc, hipStream_t st) {
     switch (zp.kind) {
-    case SHAPE_SC_NN: return launch_fused_kind<SHAPE_SC_NN, T, ISO, sizeof(T) == 4 ? 16 : 8>(zp, a, os, hc, st);
+    case SHAPE_SC_NN: return launch_fused_kind<SHAPE_SC_NN, T, ISO, sizeof(T) == 4 ? 16 : 8>(zp, a, fc, st);
     case SHAPE_SC_3SH:
-        if constexpr (ISO) return launch_fused_kind<SHAPE_SC_3SH, T, ISO, 8>(zp, a, os, hc, st);
+        if constexpr (ISO) return launch_fused_kind<SHAPE_SC_3SH, T, ISO, 8>(zp, a, fc, st);
         break;
     default: break;
     }
@@ -370,12 +404,31 @@ hipError_t heun_fused(const ZPlan &zp, const Grid &g, const Onsite &os, const He
     a.S = S;
     a.out = out;
     a.step = step;
-    if (zp.prec == 0) {
-        if (zp.iso) return launch_fused_t<double, true>(zp, a, os, hc, st);
-        return launch_fused_t<double, false>(zp, a, os, hc, st);
+    FConst fc{};
+    fc.dt = hc.dt;
+    fc.hdt = 0.5 * hc.dt;
+    fc.pre = hc.pre;
+    fc.alpha = hc.alpha;
+    fc.inv = hc.inv_mumuB[0];
+    fc.sigma = hc.sigma[0];
+    fc.n_aniso = os.n_aniso;
+    for (int l = 0; l < os.n_aniso && l < kMaxAniso; ++l) {
+        fc.K2[l] = 2.0 * os.K[0][l];
+        for (int c = 0; c < 3; ++c) fc.ax[l][c] = os.axis[0][l][c];
     }
-    if (zp.iso) return launch_fused_t<float, true>(zp, a, os, hc, st);
-    return launch_fused_t<float, false>(zp, a, os, hc, st);
+    // the Zeeman term enters B = (b_bil + b_ani + b_Z) / (mu mu_B): it is
+    // carried in the on-site sum, added after the anisotropy
+    for (int c = 0; c < 3; ++c) fc.bz[c] = os.bz[0][c];
+    fc.noise = hc.noise;
+    fc.seed = hc.seed;
+    fc.tag = hc.tag;
+    fc.step_dev = hc.step_dev;
+    if (zp.prec == 0) {
+        if (zp.iso) return launch_fused_t<double, true>(zp, a, fc, st);
+        return launch_fused_t<double, false>(zp, a, fc, st);
+    }
+    if (zp.iso) return launch_fused_t<float, true>(zp, a, fc, st);
+    return launch_fused_t<float, false>(zp, a, fc, st);
 }
 
 }  // namespace spx

@@ -1,0 +1,33 @@
+"""Accuracy of the device elementary functions of the noise transform and the
+spin normalisation (paper_2605_26016_amd/csrc/spx_math.hpp), compiled for the
+CPU with g++ with the hardware estimates replaced by values carrying their
+stated 2^-23 relative error, against long-double libm over the Box-Muller
+arguments of ~4M Philox words (random, both ends of the u32 range, and the
+reduction boundaries) and 2M squared norms.  Bounds: log within 2 ulp, sqrt
+and 1/sqrt within 1 ulp (+ rounding slack), sin(pi t) and cos(pi t) within
+2^-52 absolute.  Together these keep the normals within a few ulp of the
+libm-based oracle (whose own 2 pi u rounding is of the same size)."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_noise_math_accuracy(tmp_path):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = tmp_path / "math_check"
+    subprocess.run([gxx, "-O2", "-std=c++17", "-ffp-contract=off", "-o", str(exe),
+                    os.path.join(HERE, "host", "math_check.cpp")], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    res = {ln.split()[0]: float(ln.split()[1]) for ln in out.strip().splitlines()}
+    print(res)
+    assert res["log"] <= 2.0
+    assert res["sqrt"] <= 1.01
+    assert res["rsqrt"] <= 1.01
+    assert res["sinpi_abs"] <= 2.0
+    assert res["cospi_abs"] <= 2.0
