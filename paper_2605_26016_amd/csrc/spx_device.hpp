@@ -99,6 +99,21 @@ __device__ __forceinline__ void llg_rhs(const double s[3], const double B[3], do
     f[2] = pre * (c2 + alpha * d2);
 }
 
+// The direction of the LLG right-hand side, S x B + alpha S x (S x B), so
+// that f = pre * llg_dir (pre folded into the step constants by callers that
+// only need dt f).
+__device__ __forceinline__ void llg_dir(const double s[3], const double B[3], double alpha, double g[3]) {
+    const double c0 = s[1] * B[2] - s[2] * B[1];
+    const double c1 = s[2] * B[0] - s[0] * B[2];
+    const double c2 = s[0] * B[1] - s[1] * B[0];
+    const double d0 = s[1] * c2 - s[2] * c1;
+    const double d1 = s[2] * c0 - s[0] * c2;
+    const double d2 = s[0] * c1 - s[1] * c0;
+    g[0] = c0 + alpha * d0;
+    g[1] = c1 + alpha * d1;
+    g[2] = c2 + alpha * d2;
+}
+
 // N[v] = v/|v| with one reciprocal square root (about one ulp; the norm of a
 // spin update is close to 1).
 __device__ __forceinline__ void normalise3(double v[3]) {
@@ -106,6 +121,12 @@ __device__ __forceinline__ void normalise3(double v[3]) {
     v[0] *= inv;
     v[1] *= inv;
     v[2] *= inv;
+}
+
+// Three-input exclusive or in one instruction (gfx950 v_bitop3_b32 with the
+// truth table of a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -118,8 +139,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -142,9 +163,9 @@ __device__ __forceinline__ void thermal_eta(uint64_t seed, uint64_t step, uint32
     uint32_t c0 = (uint32_t)site, c1 = (uint32_t)(site >> 32) ^ tag;
     uint32_t c2 = (uint32_t)step, c3 = (uint32_t)(step >> 32);
     philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double sc = 2.3283064365386963e-10;  // 2^-32
-    const double u0 = ((double)c0 + 0.5) * sc, u1 = ((double)c1 + 0.5) * sc;
-    const double u2 = ((double)c2 + 0.5) * sc, u3 = ((double)c3 + 0.5) * sc;
+    // (x + 1/2) 2^-32, exact (the sum has at most 33 significant bits)
+    const double u0 = ldexp((double)c0 + 0.5, -32), u1 = ldexp((double)c1 + 0.5, -32);
+    const double u2 = ldexp((double)c2 + 0.5, -32), u3 = ldexp((double)c3 + 0.5, -32);
     const double r0 = sqrt_pos(-2.0 * log_pos(u0));
     const double r1 = sqrt_pos(-2.0 * log_pos(u2));
     double sn, cs, sn3, cs3;

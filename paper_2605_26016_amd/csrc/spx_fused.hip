@@ -65,7 +65,8 @@ struct FArgs {
 // Integrator and on-site constants of the one sublattice, packed so that the
 // kernel keeps few of them in scalar registers.
 struct FConst {
-    double dt, hdt, pre, alpha, inv, sigma;
+    double dtp, hdtp;  // dt pre and dt/2 pre, pre = -gamma/(1 + alpha^2)
+    double alpha, inv, sigma;
     double bz[3];
     double K2[kMaxAniso];     // 2 K_l
     double ax[kMaxAniso][3];  // unit axes
@@ -295,11 +296,11 @@ __global__ __launch_bounds__(kFX *NW) void k_heun_fused(FArgs g, FConst fc,
             double B1[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) B1[c] = ((double)bil[c] + bt[c]) * fc.inv + H[c];
-            double f1[3];
-            llg_rhs(Tt, B1, fc.pre, fc.alpha, f1);
+            double g1[3];
+            llg_dir(Tt, B1, fc.alpha, g1);
             double pn[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) pn[c] = P[c] + fc.hdt * f1[c];
+            for (int c = 0; c < 3; ++c) pn[c] = P[c] + fc.hdtp * g1[c];
             normalise3(pn);
             const int64_t i = cx + (int64_t)g.Lx * (cy + (int64_t)g.Ly * (zs + L - 2));
 #pragma unroll
@@ -316,21 +317,28 @@ __global__ __launch_bounds__(kFX *NW) void k_heun_fused(FArgs g, FConst fc,
             double eta[3] = {0.0, 0.0, 0.0};
             if (fc.noise) {
                 const int64_t i = px + (int64_t)g.Lx * (py + (int64_t)g.Ly * pz);
-                thermal_eta(fc.seed, nstep, fc.tag, (uint64_t)i, eta);
+                // The key and step words are uniform.  Hiding them from the
+                // loop optimiser here keeps the per-round keys and the first
+                // round's product of the step word as scalar instructions in
+                // the loop; hoisted, their twenty-odd values spill into
+                // vector-lane storage and every use becomes a vector read.
+                uint64_t sd = fc.seed, ns = nstep;
+                asm volatile("" : "+s"(sd), "+s"(ns));
+                thermal_eta(sd, ns, fc.tag, (uint64_t)i, eta);
             }
             double ba[3];
             fused_onsite<NA>(fc, oS, ba);
-            double B[3], f0[3];
+            double B[3], g0[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 H[c] = fc.sigma * eta[c];
                 B[c] = ((double)bil[c] + ba[c]) * fc.inv + H[c];
             }
-            llg_rhs(oS, B, fc.pre, fc.alpha, f0);
+            llg_dir(oS, B, fc.alpha, g0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Tt[c] = oS[c] + fc.dt * f0[c];
-                P[c] = oS[c] + fc.hdt * f0[c];
+                Tt[c] = oS[c] + fc.dtp * g0[c];
+                P[c] = oS[c] + fc.hdtp * g0[c];
             }
             normalise3(Tt);
             T *const tb = &lt[L & 3][0][0];
@@ -405,9 +413,8 @@ hipError_t heun_fused(const ZPlan &zp, const Grid &g, const Onsite &os, const He
     a.out = out;
     a.step = step;
     FConst fc{};
-    fc.dt = hc.dt;
-    fc.hdt = 0.5 * hc.dt;
-    fc.pre = hc.pre;
+    fc.dtp = hc.dt * hc.pre;
+    fc.hdtp = 0.5 * hc.dt * hc.pre;
     fc.alpha = hc.alpha;
     fc.inv = hc.inv_mumuB[0];
     fc.sigma = hc.sigma[0];
