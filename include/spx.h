@@ -167,6 +167,21 @@ spx_status spx_eval_field(spx_ham *h, const double *S, void *b, void *stream);
  * NULL.  Fixed-order two-level FP64 reduction (deterministic). */
 spx_status spx_energy(spx_ham *h, const double *S, double *E, double *terms, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the energy
+ * and terms of spx_energy, with no allocation, synchronisation or memset in
+ * the call.  The neighbours are gathered per site and the partial sums go to
+ * a library-owned static device array of 4096 quadruples (128 KiB per
+ * device, looked up at the first call on each device): min(ceil(N / 256),
+ * 4096) blocks stride over the lattice, and one block adds their quadruples
+ * in a fixed order.  Results equal spx_energy's to FP64 rounding (another
+ * fixed summation order); deterministic.  Every quadruple read is written by
+ * the same call, so nothing is cleared between calls, and calls that overlap
+ * on one device (several streams) race on the array.  SPX_ERR_UNSUPPORTED for
+ * pair-list Hamiltonians and for the dipolar term; other errors as
+ * spx_energy. */
+spx_status spx_energy_noalloc(spx_ham *h, const double *S, double *E, double *terms, void *stream);
+
 /* Stochastic/deterministic LLG (Methods, atomistic spin dynamics):
  * dS/dt = -gamma/(1+alpha^2) [S x B + alpha S x (S x B)], B = b/(mu mu_B)
  * plus, for temperature_K > 0, the thermal field sigma_i eta_i^n with

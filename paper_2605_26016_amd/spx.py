@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
         "spx_destroy_hamiltonian": [vp],
         "spx_eval_field": [vp, vp, vp, vp],
         "spx_energy": [vp, vp, vp, vp, vp],
+        "spx_energy_noalloc": [vp, vp, vp, vp, vp],
         "spx_llg_heun_step": [vp, vp, C.POINTER(LlgParams), vp],
         "spx_thermal_noise": [u64, u64, u32, i64, vp, vp],
         "spx_philox4x32_10": [vp, vp, i64, vp, vp],
@@ -350,6 +351,12 @@ def eval_field(h, S, b, stream=None):
 
 def energy(h, S, E, terms=None, stream=None):
     _check(load().spx_energy(_h(h), _ptr(S), _ptr(E), _ptr(terms), _stream(stream)), "spx_energy")
+
+
+def energy_noalloc(h, S, E, terms=None, stream=None):
+    """spx_energy_noalloc: the same energy with no allocation in the call."""
+    _check(load().spx_energy_noalloc(_h(h), _ptr(S), _ptr(E), _ptr(terms), _stream(stream)),
+           "spx_energy_noalloc")
 
 
 def llg_heun_step(h, S, alpha, dt_fs, temperature_K=0.0, gamma=0.0, seed=0, step0=0, tag=0,
