@@ -31,6 +31,9 @@ METRIC = "spin updates/s (field+Heun), % HBM peak; GNEB iters learned vs plain i
 # state, 24 B per spin state): the predictor reads S and writes S~ (48 B), the
 # corrector reads S and S~ and writes S' (72 B); neighbour reuse is on chip.
 BYTES_PER_SPIN = {"heun_predict": 48, "heun_correct": 72}
+TWO_SWEEP_BYTES = 120
+# the temporally fused step reads S and writes S' once (predicted state on chip)
+BYTES_FUSED = 48
 # field only: FP64 spin in, FP32 field out
 FIELD_BYTES = 36
 # dense 7^3 window of 3x3 blocks: 342 offsets x 9 multiply-adds x 2 flop
@@ -38,7 +41,8 @@ DENSE_FLOP_PER_SITE = 6156
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 KERNEL_SOURCES = ["paper_2605_26016_amd/csrc/spx_kernels.hip", "paper_2605_26016_amd/csrc/spx_device.hpp",
                   "paper_2605_26016_amd/csrc/spx_stencil.hip", "paper_2605_26016_amd/csrc/spx_stencil.hpp",
-                  "paper_2605_26016_amd/csrc/spx_internal.hpp"]
+                  "paper_2605_26016_amd/csrc/spx_internal.hpp", "paper_2605_26016_amd/csrc/spx_fused.hip",
+                  "paper_2605_26016_amd/csrc/spx_math.hpp"]
 # corrector kernel name per stencil engine (1 gather, 2 z-march)
 CORRECT_KERNEL = {1: "k_heun_correct", 2: "k_zmarch (corrector instantiation)"}
 
@@ -103,7 +107,11 @@ def cpu_baseline(w, seconds: float):
 # (FP64, 24 B per spin vector): pass A reads S_n, S_n+1 and writes F (72 B);
 # pass B reads S_n-1, S_n, S_n+1, F, v (120 B); pass C reads S_n-1, S_n, S_n+1,
 # F and writes v, S' (144 B).  Neighbour reuse inside an image is on chip.
-GNEB_BYTES = 336
+GNEB_PASS_BYTES = 336
+# the per-iteration lower bound the roofline is scored against: the first pass
+# reads S_n, S_n+1 and writes F (72 B), one second pass reads S_n, S_n+-1, F, v
+# and writes S, v (168 B)
+GNEB_BYTES = 240
 # string method per spin-image: pass A 72 B; pass B without velocities 96 B;
 # pass C without velocities (read S_n-1, S_n, S_n+1, F, write S') 120 B; the
 # reparameterisation's distance pass (2 images per pair) 48 B and
@@ -153,7 +161,8 @@ def gneb_workload(args):
                 "roofline": {"bound": "hbm", "achieved": rate * GNEB_BYTES / 1e9, "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": rate * GNEB_BYTES / 1e9 / HBM_PEAK_GBS, "traffic": None,
                              "kernel": "GNEB iteration (passes A, B, C + reductions)",
-                             "bytes_per_spin_image_iteration": GNEB_BYTES}})
+                             "bytes_per_spin_image_iteration": GNEB_BYTES,
+                             "bytes_per_spin_image_iteration_of_the_passes": GNEB_PASS_BYTES}})
     # -- the string method on the same batch: force step + geodesic reparameterisation
     spx.gneb_set_params(g, vp_dt=0.01, ci_mode=4, tol_force=0.0)
     spx.gneb_step(g, 3)
@@ -414,15 +423,21 @@ def learned_experiment(family, args):
                                         lr=args.lr, max_iter=args.max_iter, hopfion_L=args.gneb_L, log=log)
 
 
-def heun_workload(args, w):
-    """Field + (stochastic) Heun throughput of one lattice workload."""
+def heun_workload(args, w, steps=None, warmup=None, cpu=True):
+    """Field + (stochastic) Heun throughput of one lattice workload; returns
+    the JSON record.  The timed region replays the library's captured Heun
+    graphs (the production path) and is bracketed by HIP events on the launch
+    stream; per-kernel durations come from a separate pass of direct launches
+    with events around every launch."""
     import numpy as np
     import torch
 
     from paper_2605_26016_amd import spx
     from workloads import random_sphere_device
 
-    log(f"[bench] workload {w.name}: {w.N} spins, {args.warmup} warmup + {args.steps} timed Heun steps")
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    log(f"[bench] workload {w.name}: {w.N} spins, {warmup} warmup + {steps} timed Heun steps")
     stream = torch.cuda.current_stream()
     h = spx.setup_hamiltonian(w.L, cell=w.cell, sub_frac=w.frac, mu=w.mu, periodic=w.periodic,
                               J_shell=w.J_shell, D_shell=w.D_shell, K=(w.K if w.K else None),
@@ -440,82 +455,96 @@ def heun_workload(args, w):
         S = torch.from_numpy(w.initial_state()).cuda()
         data = "synthetic (seeded start, Philox noise)" if w.T_K > 0 else "synthetic (seeded start)"
     params = dict(alpha=w.alpha, dt_fs=w.dt_fs, temperature_K=w.T_K, seed=w.philox_seed)
-    spx.llg_heun_step(h, S, step0=0, n_steps=args.warmup, **params)
+    spx.llg_heun_step(h, S, step0=0, n_steps=warmup, **params)
     torch.cuda.synchronize()
     log("[bench] warmup done")
+    fused = info.heun_field == 8
     kinds = ("heun_predict", "heun_correct", "noise")
-    # small lattices are launch-bound: the timed region replays the captured
-    # Heun graphs and the per-kernel durations come from a second pass
-    small = w.N < 1_000_000
-    if not small:
-        spx.set_kernel_timing(h, True)
-    for k in kinds:
-        spx.get_kernel_times(h, k)  # reset
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    spx.llg_heun_step(h, S, step0=args.warmup, n_steps=args.steps, **params)
+    spx.llg_heun_step(h, S, step0=warmup, n_steps=steps, **params)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    if small:
-        spx.set_kernel_timing(h, True)
-        spx.llg_heun_step(h, S, step0=args.warmup + args.steps, n_steps=min(args.steps, 100), **params)
-        torch.cuda.synchronize()
+    log(f"[bench] timed region: {gpu_ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
+    # per-kernel durations: a separate pass with events around every launch
+    spx.set_kernel_timing(h, True)
+    for k in kinds:
+        spx.get_kernel_times(h, k)  # reset
+    n_kt = min(steps, 10 if w.N > 100_000_000 else 100)
+    spx.llg_heun_step(h, S, step0=warmup + steps, n_steps=n_kt, **params)
+    torch.cuda.synchronize()
     spx.set_kernel_timing(h, False)
     kt = {k: spx.get_kernel_times(h, k) for k in kinds}
-    log(f"[bench] timed region: {gpu_ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
     t = max(gpu_ms / 1e3, 1e-12)
-    value = w.N * args.steps / t
+    value = w.N * steps / t
     nrm = torch.sqrt((S * S).sum(0))
     assert float((nrm - 1).abs().max()) < 1e-12, "state left the unit sphere"
     del nrm
 
+    bps = dict(BYTES_PER_SPIN)
+    if fused:
+        bps = {"heun_predict": BYTES_FUSED}  # kind 0 times the one fused launch
     kernels = {}
     for k, (cnt, tot) in kt.items():
         if cnt == 0:
             continue
         avg = tot / cnt / 1e3
-        kernels[k] = {"launches": cnt, "avg_us": avg * 1e6}
-        if k in BYTES_PER_SPIN:
-            kernels[k]["GBps_algorithmic"] = BYTES_PER_SPIN[k] * w.N / avg / 1e9
-    # the dominant kernel: the stage with the larger summed time
-    dom = max(("heun_predict", "heun_correct"), key=lambda k: kt[k][1])
-    achieved = kernels[dom]["GBps_algorithmic"]
-    kname = {("heun_predict", 2): "k_zmarch (predictor instantiation)",
-             ("heun_correct", 2): "k_zmarch (corrector instantiation)",
-             ("heun_predict", 1): "k_heun_predict", ("heun_correct", 1): "k_heun_correct"}
-    if info.stencil_engine == 2 and info.heun_field in (5, 6):
-        # split predictor (modes 5, 6): one sweep = the bilinear-field stencil
-        # pass + the elementwise stage kernel, timed together
-        kname[("heun_predict", 2)] = "k_zmarch<ZM_BIL> + k_heun_pre (predictor sweep)"
-        if info.heun_field == 5:
-            kname[("heun_correct", 2)] = "k_zmarch<ZM_BIL> + k_heun_post (corrector sweep)"
+        name = "heun_fused" if (fused and k == "heun_predict") else k
+        kernels[name] = {"launches": cnt, "avg_us": avg * 1e6}
+        if k in bps:
+            kernels[name]["GBps_algorithmic"] = bps[k] * w.N / avg / 1e9
+    if fused:
+        # one fused launch per step (plus one step-counter node per 16-step
+        # graph): the kernel's average duration over the timed region is the
+        # region divided by its launches
+        dom = "heun_fused"
+        avg_s = t / steps
+        achieved = BYTES_FUSED * w.N / avg_s / 1e9
+        kname = "k_heun_fused (predictor + corrector, one pass)"
+        timing = ("HIP events around the timed region of graph-replayed steps on the launch stream, "
+                  "one fused launch per step; per-launch events in a separate pass: "
+                  f"{kernels['heun_fused']['avg_us']:.1f} us")
+        bpl = BYTES_FUSED
+        step_bytes = BYTES_FUSED
+    else:
+        # the dominant kernel: the stage with the larger summed time in the
+        # per-launch pass
+        dom = max(("heun_predict", "heun_correct"), key=lambda k: kt[k][1])
+        achieved = kernels[dom]["GBps_algorithmic"]
+        kname = {("heun_predict", 2): "k_zmarch (predictor instantiation)",
+                 ("heun_correct", 2): "k_zmarch (corrector instantiation)",
+                 ("heun_predict", 1): "k_heun_predict", ("heun_correct", 1): "k_heun_correct"}
+        if info.stencil_engine == 2 and info.heun_field in (5, 6):
+            kname[("heun_predict", 2)] = "k_zmarch<ZM_BIL> + k_heun_pre (predictor sweep)"
+            if info.heun_field == 5:
+                kname[("heun_correct", 2)] = "k_zmarch<ZM_BIL> + k_heun_post (corrector sweep)"
+        kname = kname.get((dom, info.stencil_engine), dom)
+        timing = "HIP events around every launch in a separate pass of direct launches after the timed region"
+        bpl = BYTES_PER_SPIN[dom]
+        step_bytes = sum(BYTES_PER_SPIN.values())
     traffic = measured_traffic(dom, w.name, info.heun_field, info.zchunk)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kname.get((dom, info.stencil_engine), dom),
-            "bytes_per_spin_algorithmic": BYTES_PER_SPIN[dom],
-            "bytes_per_launch_algorithmic": BYTES_PER_SPIN[dom] * w.N,
-            "kernel_timing": "separate pass after the timed region (graph replay timed)" if small
-            else "HIP events around every launch inside the timed region"}
-    step_bytes = sum(BYTES_PER_SPIN.values())
-    cpu = None
-    if not args.no_cpu_baseline:
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+            "bytes_per_spin_algorithmic": bpl, "bytes_per_launch_algorithmic": bpl * w.N,
+            "kernel_timing": timing}
+    cpu_rec = None
+    if cpu and not args.no_cpu_baseline:
         log("[bench] timing the FP64 CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(w, args.cpu_seconds)
-        log(f"[bench] cpu oracle: {cpu['value']:.3e} spin-steps/s on {cpu['cores']} threads")
+        cpu_rec = cpu_baseline(w, args.cpu_seconds)
+        log(f"[bench] cpu oracle: {cpu_rec['value']:.3e} spin-steps/s on {cpu_rec['cores']} threads")
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "spin-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": gpu_ms / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": gpu_ms / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -527,23 +556,25 @@ def heun_workload(args, w):
                    "parallelism": "single GPU", "stencil_engine": info.stencil_engine,
                    "zchunk": info.zchunk, "heun_mode": info.heun_field},
         "roofline": roof,
-        "cpu_baseline": cpu,
+        "cpu_baseline": cpu_rec,
         "kernels": kernels,
-        "step_effective_GBps": step_bytes * w.N * args.steps / t / 1e9,
-        "hbm_frac_step": step_bytes * w.N * args.steps / t / 1e9 / HBM_PEAK_GBS,
+        "step_effective_GBps": step_bytes * w.N * steps / t / 1e9,
+        "hbm_frac_step": step_bytes * w.N * steps / t / 1e9 / HBM_PEAK_GBS,
+        # the rate against the two-sweep roofline (120 B per spin-step at 8 TB/s)
+        "two_sweep_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / TWO_SWEEP_BYTES),
         "device": torch.cuda.get_device_name(0),
     }
-    if small:
-        # the same steps with direct launches instead of the captured graph
-        spx.set_heun_graph(h, False)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        spx.llg_heun_step(h, S, step0=args.warmup, n_steps=args.steps, **params)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        spx.set_heun_graph(h, True)
-        out["direct_launch_ms_per_step"] = e0.elapsed_time(e1) / args.steps
+    # the same steps with direct launches instead of the captured graph
+    spx.set_heun_graph(h, False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_direct = min(steps, 20 if w.N > 100_000_000 else steps)
+    e0.record(stream)
+    spx.llg_heun_step(h, S, step0=warmup, n_steps=n_direct, **params)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    spx.set_heun_graph(h, True)
+    out["direct_launch_ms_per_step"] = e0.elapsed_time(e1) / n_direct
     # energy of the final state (deterministic two-level reduction)
     E = torch.zeros(1, dtype=torch.float64, device="cuda")
     spx.energy(h, S, E)
@@ -555,36 +586,59 @@ def heun_workload(args, w):
     e1.record(stream)
     torch.cuda.synchronize()
     out["energy"] = {"ms": e0.elapsed_time(e1) / 10, "meV_per_spin": float(E.item()) / w.N}
-    out["hbm_copy_GBps"] = copy_bandwidth()
     if args.calibrate_copy:
         src = torch.empty_like(S).copy_(S)
         dst = torch.empty_like(S)
         for _ in range(4):
-            dst.copy_(src)
+            spx.stream_probe(0, src, dst, src.numel() * 8)
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 4 copies of {src.numel() * 8} bytes")
         del src, dst
+    del S, h
+    torch.cuda.empty_cache()
+    return out
+
+
+def headline(args):
+    """The N = 1 line: the billion-spin sc 1024^3 stochastic workload, with the
+    bcc 128^3 five-shell workload as a secondary record (same metric)."""
+    from workloads import WORKLOADS
+    out = heun_workload(args, WORKLOADS["sc1024_nn_stochastic_mixed"]())
+    out["hbm_copy_GBps"] = copy_bandwidth()
+    sec = heun_workload(args, WORKLOADS["bcc128_5shell_stochastic_mixed"](), steps=max(args.steps, 200),
+                        warmup=max(args.warmup, 20), cpu=False)
+    keep = ("value", "unit", "steps", "warmup", "ms_per_step", "config", "roofline", "kernels",
+            "step_effective_GBps", "hbm_frac_step", "two_sweep_roofline_frac", "direct_launch_ms_per_step",
+            "energy")
+    out["secondary"] = {k: sec[k] for k in keep}
     print(json.dumps(out), flush=True)
 
 
 def copy_bandwidth(nbytes=4 << 30, reps=5):
-    """Attainable HBM bandwidth: a plain device-to-device copy of 4 GiB (far
-    beyond the on-die caches), read + write bytes over the event-timed copy."""
+    """Attainable HBM bandwidth from the library's streaming probe over 4 GiB
+    buffers (far beyond the on-die caches): copy (read + write bytes), read
+    only and write only, each event-timed over `reps` passes."""
     import torch
+
+    from paper_2605_26016_amd import spx
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    gbps = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    res = {}
+    for kind, name, mult in ((0, "copy", 2.0), (1, "read", 1.0), (2, "write", 1.0)):
+        spx.stream_probe(kind, a, b, nbytes)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            spx.stream_probe(kind, a, b, nbytes)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = round(mult * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
     del a, b
     torch.cuda.empty_cache()
-    return round(gbps, 1)
+    log(f"[bench] streaming probe over 4 GiB: copy {res['copy']} GB/s, read {res['read']} GB/s, "
+        f"write {res['write']} GB/s")
+    return res
 
 
 def k7_couplings(J=1.0, D=0.3, mu=2.0, a=0.4):
@@ -739,7 +793,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="bcc128_5shell_stochastic_mixed")
+    ap.add_argument("--workload", default="headline",
+                    help="headline (sc 1024^3 with bcc 128^3 as secondary), or one workload name")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
@@ -778,8 +833,12 @@ def main():
         gneb_workload(args)
     elif args.workload == "sc256_chiral_dipolar_field":
         field_workload(args, WORKLOADS[args.workload]())
+    elif args.workload == "headline":
+        headline(args)
     else:
-        heun_workload(args, WORKLOADS[args.workload]())
+        out = heun_workload(args, WORKLOADS[args.workload]())
+        out["hbm_copy_GBps"] = copy_bandwidth()
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -477,6 +477,14 @@ spx_status spx_net_backward(spx_net *net, const float *params, const int32_t *di
 spx_status spx_net_adam_step(float *params, const float *grad, float *m, float *v, int64_t n, int64_t step,
                              double lr, double b1, double b2, double eps, void *stream);
 
+/* Streaming probe of the attainable HBM bandwidth (measurement hook): 16-byte
+ * accesses over n_bytes (a multiple of 16; 16-byte aligned [dev] buffers),
+ * grid-stride with four accesses in flight per thread.  kind 0 copies src to
+ * dst, 1 only reads src (dst may be NULL; nothing is written unless the
+ * folded word hits a sentinel, in which case dst[0] gets 4 bytes), 2 only
+ * writes dst.  Asynchronous; time it with events on `stream`. */
+spx_status spx_stream_probe(int32_t kind, const void *src, void *dst, int64_t n_bytes, void *stream);
+
 /* Lane-layout check of the 32x32x16 MFMA used by the dense backend:
  * D = A B for A [32][16], B [16][32], D [32][32] ([dev] row-major float),
  * operands rounded to BF16 (prec 2) or FP16 (prec 3).  Test hook. */

@@ -1124,6 +1124,18 @@ spx_status spx_thermal_noise(uint64_t seed, uint64_t step, uint32_t tag, int64_t
     return SPX_OK;
 }
 
+spx_status spx_stream_probe(int32_t kind, const void *src, void *dst, int64_t n_bytes, void *stream) {
+    if (kind < 0 || kind > 2) return fail(SPX_ERR_INVALID_ARG, "spx_stream_probe: kind must be 0, 1 or 2");
+    if (n_bytes < 0 || n_bytes % 16 != 0) return fail(SPX_ERR_INVALID_ARG, "spx_stream_probe: n_bytes must be a multiple of 16");
+    if (n_bytes > 0 && ((kind != 2 && !src) || (kind != 1 && !dst)))
+        return fail(SPX_ERR_INVALID_ARG, "spx_stream_probe: missing buffer");
+    if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
+        return fail(SPX_ERR_INVALID_ARG, "spx_stream_probe: buffers must be 16-byte aligned");
+    hipError_t e = launch_stream(kind, src, dst, n_bytes / 16, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "spx_stream_probe");
+    return SPX_OK;
+}
+
 spx_status spx_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out, void *stream) {
     if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(SPX_ERR_INVALID_ARG, "bad philox arguments");
     hipError_t e = launch_philox(ctr, key, n, out, (hipStream_t)stream);

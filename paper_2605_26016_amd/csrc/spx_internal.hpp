@@ -88,6 +88,8 @@ hipError_t launch_energy(int field_prec, const BondTable &tb, const Grid &g, con
                          double *terms, hipStream_t st);
 hipError_t launch_thermal_noise(uint64_t seed, uint64_t step, uint32_t tag, int64_t N, double *eta,
                                 hipStream_t st);
+// Streaming bandwidth probe over n16 16-byte words (kind 0 copy, 1 read, 2 write).
+hipError_t launch_stream(int kind, const void *src, void *dst, int64_t n16, hipStream_t st);
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out,
                          hipStream_t st);
 

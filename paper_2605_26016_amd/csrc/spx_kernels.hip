@@ -373,6 +373,51 @@ __global__ __launch_bounds__(kBlock) void k_philox(const uint32_t *__restrict__ 
     out[4 * i + 3] = c3;
 }
 
+// Streaming probe of the attainable HBM bandwidth: 16-byte accesses, four
+// in flight per thread, grid-stride.  kind 0 copies src to dst, 1 reads src
+// (folded into a word that is stored only if it equals a sentinel, so the
+// loads stay and nothing is written), 2 fills dst.
+__global__ __launch_bounds__(256) void k_stream(int kind, const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                int64_t n) {
+    const int64_t st = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (kind == 0) {
+        for (; i + 3 * st < n; i += 4 * st) {
+            const uint4 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
+            dst[i] = a;
+            dst[i + st] = b;
+            dst[i + 2 * st] = c;
+            dst[i + 3 * st] = d;
+        }
+        for (; i < n; i += st) dst[i] = src[i];
+    } else if (kind == 1) {
+        uint32_t x = 0;
+        for (; i + 3 * st < n; i += 4 * st) {
+            const uint4 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
+            x ^= (a.x ^ a.y ^ a.z ^ a.w) + (b.x ^ b.y ^ b.z ^ b.w) + (c.x ^ c.y ^ c.z ^ c.w) + (d.x ^ d.y ^ d.z ^ d.w);
+        }
+        for (; i < n; i += st) x ^= src[i].x ^ src[i].y ^ src[i].z ^ src[i].w;
+        if (x == 0x9E3779B9u && dst) dst[0].x = x;
+    } else {
+        const uint4 v = make_uint4(0x3FF00000u, 0u, 0x3FF00000u, 0u);
+        for (; i + 3 * st < n; i += 4 * st) {
+            dst[i] = v;
+            dst[i + st] = v;
+            dst[i + 2 * st] = v;
+            dst[i + 3 * st] = v;
+        }
+        for (; i < n; i += st) dst[i] = v;
+    }
+}
+
+hipError_t launch_stream(int kind, const void *src, void *dst, int64_t n16, hipStream_t st) {
+    if (n16 <= 0) return hipSuccess;
+    const int64_t want = (n16 + 1023) / 1024;
+    const unsigned blocks = (unsigned)(want < 4096 ? want : 4096);
+    k_stream<<<blocks, 256, 0, st>>>(kind, (const uint4 *)src, (uint4 *)dst, n16);
+    return hipGetLastError();
+}
+
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);

@@ -138,6 +138,7 @@ def load(path: str = LIB_PATH):
         "spx_gneb_redistribute": [vp, vp],
         "spx_gneb_set_params": [vp, C.POINTER(GnebParams), vp],
         "spx_mfma_probe": [i32, vp, vp, vp, vp],
+        "spx_stream_probe": [i32, vp, vp, i64, vp],
         "spx_get_kernel_times": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
     for name, args in sigs.items():
@@ -619,3 +620,9 @@ def net_adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
 
 def set_heun_graph(h, enable=True):
     _check(load().spx_set_heun_graph(_h(h), int(bool(enable))), "spx_set_heun_graph")
+
+
+def stream_probe(kind, src, dst, n_bytes, stream=None):
+    """spx_stream_probe: kind 0 copy src -> dst, 1 read src, 2 write dst."""
+    _check(load().spx_stream_probe(int(kind), _ptr(src), _ptr(dst), int(n_bytes), _stream(stream)),
+           "spx_stream_probe")
