@@ -641,33 +641,6 @@ def copy_bandwidth(nbytes=4 << 30, reps=5):
     return res
 
 
-def k7_couplings(J=1.0, D=0.3, mu=2.0, a=0.4):
-    """Dense 7^3 window of 3x3 couplings (meV) on simple cubic with lattice
-    constant a (nm): J + bulk DMI (D along the bond) on the six nearest
-    neighbours and the dipole tensor (mu0/4pi) mu_B^2 mu^2 (3 rr - 1)/r^3 on
-    every other offset (the near field a dense convolution would hold)."""
-    import numpy as np
-    pref = 1.0e-7 * 9.2740100783e-24 ** 2 / 1.602176634e-22 * 1.0e27 * mu * mu  # meV nm^3
-    ab, dl, Js = [], [], []
-    for dz in range(-3, 4):
-        for dy in range(-3, 4):
-            for dx in range(-3, 4):
-                if dx == dy == dz == 0:
-                    continue
-                r = np.array([dx, dy, dz], float) * a
-                rn = np.linalg.norm(r)
-                u = r / rn
-                if abs(dx) + abs(dy) + abs(dz) == 1:
-                    Dv = D * u
-                    T = J * np.eye(3) + np.array([[0, Dv[2], -Dv[1]], [-Dv[2], 0, Dv[0]], [Dv[1], -Dv[0], 0]])
-                else:
-                    T = pref * (3 * np.outer(u, u) - np.eye(3)) / rn ** 3
-                ab.append((0, 0))
-                dl.append((dx, dy, dz))
-                Js.append(T)
-    return np.array(ab, np.int32), np.array(dl, np.int32), np.array(Js)
-
-
 def field_workload(args, w):
     """Field-only evaluations of the sc 256^3 chiral magnet: the FP32 stencil
     (J + DMI + Zeeman), the stencil plus the zero-padded FFT dipolar field,
@@ -702,7 +675,8 @@ def field_workload(args, w):
     ms_dip = timed(h, b32, max(reps // 10, 2))
     del h
     log(f"[bench] stencil {ms_st * 1e3:.1f} us, stencil + dipolar FFT {ms_dip:.3f} ms")
-    ab, dl, J9 = k7_couplings(mu=w.mu[0], a=w.cell[0][0])
+    from workloads import dense7_couplings
+    ab, dl, J9 = dense7_couplings(mu=w.mu[0], a=w.cell[0][0])
     b64 = torch.empty((3, w.N), dtype=torch.float64, device="cuda")
     h = spx.setup_hamiltonian(w.L, bonds=(ab, dl, J9), field_prec="fp64", **common)
     ms64 = timed(h, b64, 2)

@@ -153,6 +153,10 @@ typedef struct {
  * periodic axis, FFT for plan failures. */
 spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_desc *model,
                                  const spx_options *opts, void *stream, spx_ham **out);
+/* Frees everything the handle owns.  Synchronises the whole device first
+ * (hipDeviceSynchronize): work enqueued on any stream may still use the
+ * handle's tables and scratch, and the handle does not record the streams it
+ * was given. */
 spx_status spx_destroy_hamiltonian(spx_ham *h);
 
 /* Reduced effective field (Methods, reduced field b = -dH/dS in meV):
@@ -300,7 +304,7 @@ spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, doub
  *     2 pi u1), dH = -(S' - S_i).b_i - sum_l K_l [(S'.n_l)^2 - (S_i.n_l)^2],
  *     accepted if u2 < exp(-beta dH).
  * SPX_ERR_UNSUPPORTED with the dipolar term or when no colouring with C <= 64
- * exists; SPX_ERR_INVALID_ARG for T <= 0, n_sweeps < 0 or another method.
+ * is found (see spx_mc_find_colouring for the search's limits); SPX_ERR_INVALID_ARG for T <= 0, n_sweeps < 0 or another method.
  * `accepted` ([dev] uint64 or NULL) receives the number of accepted moves of
  * the call (heat-bath: every draw).  Asynchronous. */
 typedef struct {
@@ -314,6 +318,17 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
 /* The colouring used by spx_mc_sweep (searched on first use, synchronous):
  * *n_colours = C, coef (host int32[2 + n_sub] or NULL) = (ky, kz, o_0 ..). */
 spx_status spx_mc_colouring(spx_ham *h, int32_t *n_colours, int32_t *coef);
+/* The same colouring search on the host, without a handle or a device: a
+ * lattice of n_sub sublattices, dims/periodic [host] int32[3], n_bonds
+ * directed bonds (bond_ab [n][2] target, source; bond_delta [n][3]), colours
+ * 2 .. cmax.  SPX_ERR_UNSUPPORTED (and *n_colours = 0) when no colouring has
+ * at most cmax colours, when a bond joins a site to itself (same sublattice
+ * and every realised coordinate difference zero: no colouring exists), or
+ * when the candidates up to cmax exceed 2^26 before one is found (the search
+ * tries C^(n_sub+1) offset choices per C); the message says which. */
+spx_status spx_mc_find_colouring(int32_t n_sub, const int32_t *dims, const int32_t *periodic, int32_t n_bonds,
+                                 const int32_t *bond_ab, const int32_t *bond_delta, int32_t cmax, int32_t *n_colours,
+                                 int32_t *coef);
 /* Total moment direction sum m = sum_i S_i (Methods, thermodynamic
  * observables; reduced magnetisation m/N), m [dev] double[3], two-level
  * fixed-order reduction.  Asynchronous. */
@@ -362,6 +377,8 @@ spx_status spx_min_step(spx_min *m, double *S, int32_t n_iter, void *stream);
 spx_status spx_min_get_stats(spx_min *m, double *max_force, int32_t *iterations, int32_t *converged, void *stream);
 /* Forget the state (velocities, moments, history, counters). */
 spx_status spx_min_reset(spx_min *m, void *stream);
+/* Frees the minimiser's state.  Synchronises the whole device first (queued
+ * iterations may still use it). */
 spx_status spx_min_destroy(spx_min *m);
 
 /* ---- Batched geodesic nudged elastic band (Methods, minimum-energy paths) --
@@ -406,6 +423,9 @@ typedef struct {
  * images are the starting path. */
 spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *images, const int32_t *n_img,
                            const spx_gneb_params *p, void *stream, spx_gneb **out);
+/* Frees the library-owned images, velocities, forces, scratch and graphs.
+ * Synchronises the whole device first (queued iterations may still use
+ * them). */
 spx_status spx_gneb_destroy(spx_gneb *g);
 /* Initial path.  method 0 (geodesic): image n at t = n/(n_img-1) on every
  * spin's great circle between the two end images; antiparallel end spins
@@ -464,6 +484,8 @@ spx_status spx_gneb_set_graph(spx_gneb *g, int32_t enable);
 int64_t spx_net_nparams(void);
 /* channels must be {10, 16, 16, 16, 3} (or NULL); the workspace grows with use. */
 spx_status spx_net_create(const int32_t *channels, spx_net **out);
+/* Frees the workspace.  Synchronises the whole device first (queued passes
+ * may still use it). */
 spx_status spx_net_destroy(spx_net *net);
 spx_status spx_net_forward(spx_net *net, const float *params, const int32_t *dims, int32_t batch, const double *Sg,
                            const double *SA, const double *SB, const float *t, double *Shat, void *stream);

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "spx_device.hpp"
@@ -28,6 +29,7 @@ namespace spx {
 
 struct MCState {
     int C = 0;  // colours (0: not searched yet, -1: none found)
+    int C_fail = 0;  // why the search failed (a ColourResult)
     int ky = 0, kz = 0;
     int o[kMaxSub] = {0};
     unsigned long long *d_acc = nullptr;  // accepted-move counter of the last call
@@ -262,8 +264,18 @@ void realised(int d, int L, bool per, std::vector<int> &out) {
     }
 }
 
-// The colouring (see the header); false if none with C <= cmax.
-bool find_colouring(const Grid &g, const std::vector<int> &ab, const std::vector<int> &dl, int cmax, McColour &out) {
+// Candidate colourings tried at most, over all C (each candidate is checked
+// against the realised bonds until one joins two sites of one colour).
+constexpr long long kColourSearchBudget = 1LL << 26;
+
+enum ColourResult { COLOUR_FOUND = 1, COLOUR_NONE = 0, COLOUR_IMPOSSIBLE = -1, COLOUR_BUDGET = -2 };
+
+// The colouring (see the header).  COLOUR_NONE if none with C <= cmax,
+// COLOUR_IMPOSSIBLE if a bond joins a site to itself (same sublattice, every
+// realised difference zero on all three axes: no colouring separates them),
+// COLOUR_BUDGET if the candidates up to cmax exceed kColourSearchBudget
+// before one is found.
+int find_colouring(const Grid &g, const std::vector<int> &ab, const std::vector<int> &dl, int cmax, McColour &out) {
     const int nb = (int)ab.size() / 2;
     struct Realised {
         int a, b;
@@ -278,12 +290,18 @@ bool find_colouring(const Grid &g, const std::vector<int> &ab, const std::vector
         realised(dl[3 * p], g.Lx, g.per[0] != 0, r.dx);
         realised(dl[3 * p + 1], g.Ly, g.per[1] != 0, r.dy);
         realised(dl[3 * p + 2], g.Lz, g.per[2] != 0, r.dz);
-        if (!r.dx.empty() && !r.dy.empty() && !r.dz.empty()) rb.push_back(std::move(r));
+        if (r.dx.empty() || r.dy.empty() || r.dz.empty()) continue;
+        auto has0 = [](const std::vector<int> &v) { return std::find(v.begin(), v.end(), 0) != v.end(); };
+        if (r.a == r.b && has0(r.dx) && has0(r.dy) && has0(r.dz)) return COLOUR_IMPOSSIBLE;
+        rb.push_back(std::move(r));
     }
     const int n_free = 2 + (g.n_sub - 1);
+    long long spent = 0;
     for (int C = 2; C <= cmax; ++C) {
         long long total = 1;
         for (int k = 0; k < n_free; ++k) total *= C;
+        if (spent + total > kColourSearchBudget) return COLOUR_BUDGET;
+        spent += total;
         int digits[2 + kMaxSub];
         for (long long t = 0; t < total; ++t) {
             long long r = t;
@@ -314,11 +332,19 @@ bool find_colouring(const Grid &g, const std::vector<int> &ab, const std::vector
             }
             if (ok) {
                 out = col;
-                return true;
+                return COLOUR_FOUND;
             }
         }
     }
-    return false;
+    return COLOUR_NONE;
+}
+
+spx_status colour_error(int r, int cmax) {
+    if (r == COLOUR_IMPOSSIBLE)
+        return set_error(SPX_ERR_UNSUPPORTED, "no colouring exists: a bond joins a site to itself");
+    if (r == COLOUR_BUDGET)
+        return set_error(SPX_ERR_UNSUPPORTED, "colouring search stopped at 2^26 candidates without a result");
+    return set_error(SPX_ERR_UNSUPPORTED, "no colouring with at most " + std::to_string(cmax) + " colours");
 }
 
 // The handle's Monte Carlo state (scratch; the colouring is searched on
@@ -342,7 +368,7 @@ spx_status mc_state(const HamView &v, MCState **out) {
 
 spx_status mc_colouring(spx_ham *h, const HamView &v, MCState *m) {
     if (m->C > 0) return SPX_OK;
-    if (m->C < 0) return set_error(SPX_ERR_UNSUPPORTED, "no colouring with at most 64 colours for this lattice");
+    if (m->C < 0) return colour_error(m->C_fail, 64);
     spx_ham_info info;
     spx_status s = spx_get_info(h, &info);
     if (s != SPX_OK) return s;
@@ -354,9 +380,11 @@ spx_status mc_colouring(spx_ham *h, const HamView &v, MCState *m) {
     std::vector<int> abi(ab.begin(), ab.begin() + 2 * (size_t)info.n_bonds);
     std::vector<int> dli(dl.begin(), dl.begin() + 3 * (size_t)info.n_bonds);
     McColour col{};
-    if (!find_colouring(v.grid, abi, dli, 64, col)) {
+    const int r = find_colouring(v.grid, abi, dli, 64, col);
+    if (r != COLOUR_FOUND) {
         m->C = -1;
-        return set_error(SPX_ERR_UNSUPPORTED, "no colouring with at most 64 colours for this lattice");
+        m->C_fail = r;
+        return colour_error(r, 64);
     }
     m->C = col.C;
     m->ky = col.ky;
@@ -388,6 +416,39 @@ spx_status mc_colouring(spx_ham *h, const HamView &v, MCState *m) {
 using namespace spx;
 
 extern "C" {
+
+spx_status spx_mc_find_colouring(int32_t n_sub, const int32_t *dims, const int32_t *periodic, int32_t n_bonds,
+                                 const int32_t *bond_ab, const int32_t *bond_delta, int32_t cmax, int32_t *n_colours,
+                                 int32_t *coef) {
+    if (!dims || !periodic || !n_colours || (n_bonds > 0 && (!bond_ab || !bond_delta)))
+        return set_error(SPX_ERR_INVALID_ARG, "spx_mc_find_colouring: NULL argument");
+    if (n_sub < 1 || n_sub > kMaxSub || n_bonds < 0 || cmax < 2)
+        return set_error(SPX_ERR_INVALID_ARG, "spx_mc_find_colouring: n_sub in [1, 8], n_bonds >= 0, cmax >= 2");
+    Grid g{};
+    g.Lx = dims[0];
+    g.Ly = dims[1];
+    g.Lz = dims[2];
+    if (g.Lx < 1 || g.Ly < 1 || g.Lz < 1) return set_error(SPX_ERR_INVALID_ARG, "dims must be >= 1");
+    for (int k = 0; k < 3; ++k) g.per[k] = periodic[k] ? 1 : 0;
+    g.n_sub = n_sub;
+    std::vector<int> ab(bond_ab, bond_ab + 2 * (size_t)n_bonds), dl(bond_delta, bond_delta + 3 * (size_t)n_bonds);
+    for (int p = 0; p < n_bonds; ++p)
+        if (ab[2 * p] < 0 || ab[2 * p] >= n_sub || ab[2 * p + 1] < 0 || ab[2 * p + 1] >= n_sub)
+            return set_error(SPX_ERR_INVALID_ARG, "spx_mc_find_colouring: bond sublattice out of range");
+    McColour col{};
+    const int r = find_colouring(g, ab, dl, cmax, col);
+    if (r != COLOUR_FOUND) {
+        *n_colours = 0;
+        return colour_error(r, cmax);
+    }
+    *n_colours = col.C;
+    if (coef) {
+        coef[0] = col.ky;
+        coef[1] = col.kz;
+        for (int a = 0; a < n_sub; ++a) coef[2 + a] = col.o[a];
+    }
+    return SPX_OK;
+}
 
 spx_status spx_mc_colouring(spx_ham *h, int32_t *n_colours, int32_t *coef) {
     HamView v;

@@ -139,6 +139,7 @@ def load(path: str = LIB_PATH):
         "spx_gneb_set_params": [vp, C.POINTER(GnebParams), vp],
         "spx_mfma_probe": [i32, vp, vp, vp, vp],
         "spx_stream_probe": [i32, vp, vp, i64, vp],
+        "spx_mc_find_colouring": [i32, vp, vp, i32, vp, vp, i32, vp, vp],
         "spx_get_kernel_times": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
     for name, args in sigs.items():
@@ -626,3 +627,18 @@ def stream_probe(kind, src, dst, n_bytes, stream=None):
     """spx_stream_probe: kind 0 copy src -> dst, 1 read src, 2 write dst."""
     _check(load().spx_stream_probe(int(kind), _ptr(src), _ptr(dst), int(n_bytes), _stream(stream)),
            "spx_stream_probe")
+
+
+def mc_find_colouring(n_sub, dims, periodic, bond_ab, bond_delta, cmax=64):
+    """spx_mc_find_colouring (host only): (C, coef) of the Monte Carlo
+    colouring, or SpxError when there is none within the search's limits."""
+    L = load()
+    d = np.ascontiguousarray(np.asarray(dims, np.int32))
+    pr = np.ascontiguousarray(np.asarray(periodic, np.int32))
+    ab = np.ascontiguousarray(np.asarray(bond_ab, np.int32).reshape(-1))
+    dl = np.ascontiguousarray(np.asarray(bond_delta, np.int32).reshape(-1))
+    n = C.c_int32(0)
+    coef = np.zeros(2 + int(n_sub), np.int32)
+    _check(L.spx_mc_find_colouring(int(n_sub), _iptr(d), _iptr(pr), len(ab) // 2, _iptr(ab), _iptr(dl), int(cmax),
+                                   C.byref(n), _iptr(coef)), "spx_mc_find_colouring")
+    return int(n.value), coef

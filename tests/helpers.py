@@ -51,33 +51,9 @@ def require_gpu():
 
 
 def k7_table(J=1.0, D=0.3, mu=2.0, a=0.4, dip=True):
-    """Coupling table of the dense 7^3 window used for the MFMA comparison:
-    J + bulk DMI (D along the bond) on the 6 nearest-neighbour offsets and,
-    when dip is True, the dipole tensor (mu0/4pi) mu_B^2 mu^2 (3 rr - 1)/r^3 on
-    every other offset of the window.  Returns (ab, delta, J9) bond arrays."""
-    import oracle as _o
-    pref = _o.constants()[3] * mu * mu
-    ab, dl, Js = [], [], []
-    for dz in range(-3, 4):
-        for dy in range(-3, 4):
-            for dx in range(-3, 4):
-                if dx == dy == dz == 0:
-                    continue
-                r = np.array([dx, dy, dz], float) * a
-                rn = np.linalg.norm(r)
-                u = r / rn
-                T = np.zeros((3, 3))
-                if abs(dx) + abs(dy) + abs(dz) == 1:
-                    Dv = D * u
-                    T = J * np.eye(3) + np.array([[0, Dv[2], -Dv[1]], [-Dv[2], 0, Dv[0]], [Dv[1], -Dv[0], 0]])
-                elif dip:
-                    T = pref * (3 * np.outer(u, u) - np.eye(3)) / rn ** 3
-                else:
-                    continue
-                ab.append((0, 0))
-                dl.append((dx, dy, dz))
-                Js.append(T)
-    return np.array(ab, np.int32), np.array(dl, np.int32), np.array(Js)
+    """The dense 7^3 window's coupling table (workloads.dense7_couplings)."""
+    from workloads import dense7_couplings
+    return dense7_couplings(J=J, D=D, mu=mu, a=a, dipolar=dip)
 
 
 def round_bf16(x):

@@ -206,3 +206,37 @@ def skyrmion_texture(L: Sequence[int], R: float, center=(0.0, 0.0), helicity: fl
     phi = np.arctan2(Y, X) + helicity
     S = np.stack([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
     return np.ascontiguousarray(S.reshape(3, -1))
+
+
+# (mu0/4pi) mu_B^2 in meV nm^3 from the SI values (CODATA 2018 mu_B, exact e)
+DIPOLE_PREFACTOR_MEV_NM3 = 1.0e-7 * 9.2740100783e-24 ** 2 / 1.602176634e-22 * 1.0e27
+
+
+def dense7_couplings(J=1.0, D=0.3, mu=2.0, a=0.4, dipolar=True):
+    """Input coupling table of the dense 7^3 window (simple cubic, lattice
+    constant a nm, moment mu mu_B): J + bulk DMI (D along the bond) on the six
+    nearest-neighbour offsets and, when dipolar is True, the dipole tensor
+    (mu0/4pi) mu_B^2 mu^2 (3 r r - 1)/r^3 on every other offset of the window
+    (the near field a dense convolution holds).  Returns (ab [n][2],
+    delta [n][3], J [n][3][3]) in meV, offsets in (dz, dy, dx) loop order."""
+    pref = DIPOLE_PREFACTOR_MEV_NM3 * mu * mu
+    ab, dl, Js = [], [], []
+    for dz in range(-3, 4):
+        for dy in range(-3, 4):
+            for dx in range(-3, 4):
+                if dx == dy == dz == 0:
+                    continue
+                r = np.array([dx, dy, dz], float) * a
+                rn = np.linalg.norm(r)
+                u = r / rn
+                if abs(dx) + abs(dy) + abs(dz) == 1:
+                    Dv = D * u
+                    T = J * np.eye(3) + np.array([[0, Dv[2], -Dv[1]], [-Dv[2], 0, Dv[0]], [Dv[1], -Dv[0], 0]])
+                elif dipolar:
+                    T = pref * (3 * np.outer(u, u) - np.eye(3)) / rn ** 3
+                else:
+                    continue
+                ab.append((0, 0))
+                dl.append((dx, dy, dz))
+                Js.append(T)
+    return np.array(ab, np.int32), np.array(dl, np.int32), np.array(Js)
