@@ -994,11 +994,19 @@ spx_status spx_energy(spx_ham *h, const double *S, double *E, double *terms, voi
         bdip = h->d_bdip0;
     }
     // the dense MFMA backend evaluates energies with the FP32 gather kernel;
-    // with the z-march engine the bilinear field comes from its stencil pass
-    // (into the stored-field buffer, or a field buffer made at the first call)
+    // the z-march engine sums the energy terms in its epilogue, one quadruple
+    // per tile, when they fit the partial buffer (every lattice but very thin
+    // ones); otherwise its bilinear field pass feeds the gather energy kernel
     const int eprec = h->field_prec >= SPX_BF16_MFMA ? SPX_FP32 : h->field_prec;
     const void *bil = nullptr;
     hipError_t e = hipSuccess;
+    if (h->engine == 2 && h->zp.valid &&
+        (size_t)4 * ((size_t)zmarch_tiles(h->zp, h->grid) + kEnergyL2) <= energy_partial_doubles(h->grid)) {
+        e = zmarch_energy(h->zp, h->grid, h->onsite, S, bdip, h->d_partial, st);
+        if (e == hipSuccess) e = launch_energy_reduce(h->d_partial, zmarch_tiles(h->zp, h->grid), E, terms, st);
+        if (e != hipSuccess) return hip_fail(e, "spx_energy (z-march)");
+        return SPX_OK;
+    }
     if (h->engine == 2 && h->zp.valid) {
         void *buf = (h->zp.prec == 1 && h->d_bstore) ? (void *)h->d_bstore : h->d_ebil;
         if (!buf) {

@@ -78,6 +78,10 @@ hipError_t zmarch_predict(const ZPlan &zp, const Grid &g, const Onsite &os, cons
                           const double *S, const float *bdip, double *St, float *bstore, double *pstore,
                           double *estore, const double *eload, hipStream_t st);
 hipError_t zmarch_noise(const HeunConst &hc, uint64_t step, int64_t N, double *eta, hipStream_t st);
+// Energy terms of S in the z-march epilogue: one quadruple (bilinear, Zeeman,
+// anisotropy, dipolar) per tile into partial[zmarch_tiles()][4], fixed order.
+hipError_t zmarch_energy(const ZPlan &zp, const Grid &g, const Onsite &os, const double *S, const float *bdip,
+                         double *partial, hipStream_t st);
 // split Heun mode: FP32 bilinear field pass + elementwise FP64 stages
 hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bil, hipStream_t st);
 // Bilinear field of n_img images stacked as [n_img][3][N] (FP64 plan, FP64

@@ -83,6 +83,10 @@ constexpr int kEnergyL2 = 1024;
 size_t energy_partial_doubles(const Grid &g);
 // bil: precomputed bilinear field (double for field_prec 0, float otherwise)
 // or NULL to gather the neighbours.
+// The fixed-order reduction of n partial quadruples (a middle level of at most
+// kEnergyL2 blocks when n > 8 kBlock, written after them at partial + 4 n)
+// into E and terms.
+hipError_t launch_energy_reduce(double *partial, int n, double *E, double *terms, hipStream_t st);
 hipError_t launch_energy(int field_prec, const BondTable &tb, const Grid &g, const Onsite &os,
                          const double *S, const float *bdip, const void *bil, double *partial, double *E,
                          double *terms, hipStream_t st);

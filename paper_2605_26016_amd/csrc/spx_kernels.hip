@@ -326,7 +326,10 @@ hipError_t launch_energy(int field_prec, const BondTable &tb, const Grid &g, con
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int n = energy_partial_count(g);
+    return launch_energy_reduce(partial, energy_partial_count(g), E, terms, st);
+}
+
+hipError_t launch_energy_reduce(double *partial, int n, double *E, double *terms, hipStream_t st) {
     if (n <= 8 * kBlock) {
         k_energy_final<<<1, kBlock, 0, st>>>(partial, n, E, terms);
         return hipGetLastError();

@@ -69,8 +69,11 @@ constexpr int kThreads = kTX * kTYT;
 // ZM_MIN_FORCE: the force pass of the static minimisers in the epilogue
 // (force projected on the spin's tangent plane, its max norm and the dot
 // products of the method), reduced to one partial set per block.
+// ZM_ENERGY: the energy terms -S.b_bil/2, -S.b_Z, -S.b_ani/2, -S.b_dip/2 of the
+// thread's sites summed in the epilogue (the field is never stored), reduced
+// to one quadruple per tile in a fixed order.
 enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4, ZM_BIL = 5,
-             ZM_GNEB_A = 6, ZM_MIN_FORCE = 7 };
+             ZM_GNEB_A = 6, ZM_MIN_FORCE = 7, ZM_ENERGY = 8 };
 
 template <typename T, int NW>
 struct ZWeights {
@@ -451,6 +454,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // sites' independent FP64 and Philox chains interleave; sites outside
     // the lattice (valid = false) compute on a clamped index and store nothing.
     double gE = 0.0, gD = 0.0;  // ZM_GNEB_A: the thread's energy and squared-distance sums
+    double eE[4] = {0.0, 0.0, 0.0, 0.0};  // ZM_ENERGY: the thread's four energy terms
     // ZM_MIN_FORCE: max |F|, v.F, F.F, s.s, s.y, y.y of the thread's sites
     double mred[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     auto finish_row = [&](int x, int y, int z, bool valid, const T (&v)[NSUB][NIN][3],
@@ -522,6 +526,27 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                         }
                     }
                 }
+            }
+            return;
+        }
+        if constexpr (MODE == ZM_ENERGY) {
+            if (!valid) return;
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a) {
+                double ba[3];
+                aniso_field(os, a, so[a], ba);
+                double sb = 0.0, sz = 0.0, sa = 0.0, sd = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    sb += so[a][c] * (double)v[a][0][c];
+                    sz += so[a][c] * os.bz[a][c];
+                    sa += so[a][c] * ba[c];
+                    if (g.bdip0) sd += so[a][c] * (double)g.bdip0[c * N + i[a]];
+                }
+                eE[0] += -0.5 * sb;
+                eE[1] += -sz;
+                eE[2] += -0.5 * sa;
+                eE[3] += -0.5 * sd;
             }
             return;
         }
@@ -881,6 +906,21 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             g.gpart[(size_t)tile * 6 + k] = t;
         }
     }
+    if constexpr (MODE == ZM_ENERGY) {
+        // fixed-order block sums of the four terms, one quadruple per tile
+        __shared__ double ered[4][kThreads / 64];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double v = wave_sum(eE[k]);
+            if ((threadIdx.x & 63) == 0) ered[k][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double t = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) t += ered[threadIdx.x][w];
+            g.gpart[(size_t)tile * 4 + threadIdx.x] = t;
+        }
+    }
     if constexpr (MODE == ZM_GNEB_A) {
         // fixed-order block sums of the two statistics, one partial pair per tile
         __shared__ double gred[2][kThreads / 64];
@@ -1134,6 +1174,16 @@ hipError_t zmarch_field(const ZPlan &zp, const Grid &g, const Onsite &os, const 
     a.bdip0 = bdip;
     HeunConst hc{};
     return launch_any<ZM_FIELD>(zp, a, os, hc, st);
+}
+
+hipError_t zmarch_energy(const ZPlan &zp, const Grid &g, const Onsite &os, const double *S, const float *bdip,
+                         double *partial, hipStream_t st) {
+    ZArgs a = make_args(zp, g);
+    a.S0 = S;
+    a.bdip0 = bdip;
+    a.gpart = partial;
+    HeunConst hc{};
+    return launch_any<ZM_ENERGY>(zp, a, os, hc, st);
 }
 
 hipError_t zmarch_bil(const ZPlan &zp, const Grid &g, const double *S, float *bil, hipStream_t st) {

@@ -173,24 +173,33 @@ def test_energy_parity(name, w, prec, tol, engine):
     assert E2.item() == E.item()
 
 
-@pytest.mark.parametrize("L", [(128, 64, 128), (97, 101, 103)])
-def test_energy_two_level_reduction(L):
-    # more than 8 x 256 block partials: the sum goes through the middle level
-    # of the fixed-order reduction (several sites per middle block, a ragged
-    # last chunk for the odd extents)
+@pytest.mark.parametrize("L,setup", [((128, 64, 128), dict(stencil_engine=1)), ((97, 101, 103), dict(stencil_engine=1)),
+                                     ((256, 128, 64), dict(zchunk=1)), ((197, 81, 61), dict(zchunk=1, field_prec="fp32"))],
+                         ids=["gather_even", "gather_odd", "zmarch_4096_tiles", "zmarch_fp32_ragged"])
+def test_energy_two_level_reduction(L, setup):
+    # more than 8 x 256 partial quadruples (gather kernel: one per 256 sites;
+    # z-march energy epilogue: one per 64 x 8 x zchunk tile): the sum goes
+    # through the middle level of the fixed-order reduction (several
+    # quadruples per middle block, a ragged last chunk for the odd extents)
     import torch
     from paper_2605_26016_amd import spx
+    setup = dict(setup)
+    prec = setup.pop("field_prec", "fp64")
     w = Workload(name="e2", L=L, J_shell=(1.0, -0.3), D_shell=(0.2, 0.0), K=0.1, K_axis=(0.0, 0.0, 1.0),
-                 B=(0.0, 0.5, 2.0), field_prec="fp64")
+                 B=(0.0, 0.5, 2.0), field_prec=prec)
+    if "zchunk" in setup:
+        # an isotropic table (no DMI) has a z-march shape
+        w.D_shell = None
     S = random_sphere(w.N, 43)
     ref = oracle.energy(oracle_model(w), S)
-    h = gpu_hamiltonian(w)
+    h = gpu_hamiltonian(w, **setup)
+    tol = 1e-12 if prec == "fp64" else 1e-6
     E = torch.zeros(1, dtype=torch.float64, device="cuda")
     terms = torch.zeros(5, dtype=torch.float64, device="cuda")
     spx.energy(h, to_dev(S), E, terms)
     scale = np.max(np.abs(ref))
-    assert np.max(np.abs(terms.cpu().numpy() - ref)) <= 1e-12 * scale
-    assert abs(E.item() - ref[4]) <= 1e-12 * scale
+    assert np.max(np.abs(terms.cpu().numpy() - ref)) <= tol * scale
+    assert abs(E.item() - ref[4]) <= tol * scale
     E2 = torch.zeros(1, dtype=torch.float64, device="cuda")
     spx.energy(h, to_dev(S), E2)
     assert E2.item() == E.item()
