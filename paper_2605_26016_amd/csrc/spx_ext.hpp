@@ -98,15 +98,29 @@ hipError_t zmarch_min_force(const ZPlan &zp, const Grid &g, const Onsite &os, co
                             hipStream_t st);
 // Tiles of one image (x tiles x y tiles x z chunks) of the z-march engine.
 int zmarch_tiles(const ZPlan &zp, const Grid &g);
-// First GNEB pass fused into the FP64 z-march over the images of an instance
-// (buffer S0, or S0alt when *sel != 0; no-op when *skip != 0): writes the
-// projected force of interior images into F [n_img][3][N] and one (energy,
-// squared distance to the next image) partial per tile into
-// partial[(item0 + img items_per_img + tile) * 2 + {0, 1}].  Needs FP64 and
-// zmarch_tiles() <= items_per_img.
-hipError_t zmarch_gneb_a(const ZPlan &zp, const Grid &g, const Onsite &os, int n_img, const double *S0,
-                         const double *S0alt, const double *sel, const double *skip, double *F, double *partial,
-                         int item0, int items_per_img, hipStream_t st);
+// The two passes of a GNEB iteration that stores no force (see spx_stencil.hip
+// ZM_GNEB_A2 / ZM_GNEB_C2), over the images of one instance.  pass 0: every
+// image, eleven partials per tile into partial[(item0 + n items_per_img +
+// tile) * 11 + v] (energy, squared distance to the next image, a.a, a.b, b.b,
+// F.a, F.b, v.a, v.b, v.F, F.F); pass 1: interior images, the update into the
+// other buffer and velocities, one max |F_gneb| per tile into
+// partial[(item0 + n items_per_img + tile) * 11].  Reads the current buffer (Y0, or Y1
+// when *cur != 0); no-op when *done != 0.  FP64 plans only.
+struct GnebSlots {
+    int n, wp, wm, tn, coef, proj;
+};
+struct GnebPassArgs {
+    int n_img, item0, items_per_img;
+    double *Y0, *Y1, *V;
+    const double *cur, *done;
+    const double *img, *st;
+    GnebSlots slots;
+    double dt, mass;
+    int string;
+    double *partial;
+};
+hipError_t zmarch_gneb_pass(int pass, const ZPlan &zp, const Grid &g, const Onsite &os, const GnebPassArgs &ga,
+                            hipStream_t st);
 hipError_t zmarch_bil_images(const ZPlan &zp, const Grid &g, int n_img, const double *S0, const double *S0alt,
                              const double *sel, const double *skip, double *bil, hipStream_t st);
 hipError_t heun_split_pre(const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step, const double *S,

@@ -3,15 +3,32 @@
 // ragged lattices in one set of persistent launches (Methods, static
 // optimisation and minimum-energy paths).
 //
-// Work decomposition: every (instance, image, 256-site tile) is one item of a
-// flat list; each per-site pass is one grid-stride launch over the items of
-// all instances.  One iteration is
+// Instances whose bond table has a z-march shell shape run an iteration as
+// two passes of the stencil engine over their images, with no stored force:
+//   pass A2 (all images)      field, energy, distance to the next image and,
+//                             for interior images, the nine sums a.a, a.b,
+//                             b.b, F.a, F.b, v.a, v.b, v.F, F.F with a, b the
+//                             projected differences to the next and previous
+//                             image (the improved tangent is w+ a + w- b, so
+//                             its dot products follow from these once the
+//                             energy weights w+- are known); one set per tile
+//   reduce  (per image)       fixed order
+//   scalars (per instance)    climbing image, tangent weights
+//   scalars (per instance)    tau.tau, F.tau, v.tau, c_n, VP projection
+//   pass C2 (interior images) field again, F_gneb = F + c_n tau^, VP velocity,
+//                             exp-map step into the other buffer
+//   reduce + scalars          max |F_gneb|, CI switch, convergence, buffer flip
+// which moves 96 + 120 = 216 bytes per spin-image-iteration (pass A2 reads
+// S_n, S_n-1, S_n+1 and v; pass C2 reads S_n, S_n-1, S_n+1 and writes v, S').
+// Other instances (any bond table) use items: every (instance, image,
+// 256-site tile) is one item of a flat list and each per-site pass is one
+// grid-stride launch over the items of all instances:
 //   pass A  (all images)      field, energy, projected force F, distance terms
-//                             (inside the z-march over the images when the
-//                             shell shape has one: one partial per tile)
+//                             (the field from a batched z-march pass when the
+//                             table has an FP64 shape, else gathered)
 //   reduce  (per image)       E_n, d(Y_n, Y_n+1)^2           fixed order
 //   scalars (per instance)    climbing image, tangent weights
-//   pass B  (movable images)  tangent tau, dots tau.tau F.tau v.tau v.F F.F
+//   pass B  (movable images)  tangent tau, dots v.F F.F tau.tau F.tau v.tau
 //   reduce  (per image)
 //   scalars (per instance)    c_n, VP projection v.F/F.F from image sums
 //   pass C  (movable images)  F_gneb = F + c_n tau^, VP velocity, exp-map step
@@ -37,7 +54,14 @@ constexpr int kGB = 256;  // sites per item / threads per block
 constexpr int kMaxImages = 4096;  // images per instance (arc-length table in LDS)
 
 // per-image statistics
-enum { IS_E = 0, IS_D2, IS_TT, IS_FT, IS_VT, IS_VF, IS_FF, IS_COEF, IS_TN, IS_WP, IS_WM, IS_RD2, IS_RK, IS_RF, IS_FM, IS_N };
+// (the two-pass first pass fills IS_E .. IS_FF in this order; pass B fills
+// IS_VF .. IS_VT)
+enum { IS_E = 0, IS_D2, IS_AA, IS_AB, IS_BB, IS_FA, IS_FB, IS_VA, IS_VB, IS_VF, IS_FF, IS_TT, IS_FT, IS_VT, IS_COEF,
+       IS_TN, IS_WP, IS_WM, IS_RD2, IS_RK, IS_RF, IS_FM, IS_N };
+constexpr int kPassA2Values = IS_FF - IS_E + 1;
+// Partial values of item or tile k start at partial[k * kPS] for every pass,
+// so passes of different instances that run at the same time never overlap.
+constexpr int kPS = kPassA2Values;
 // per-instance state (ST_RDONE: the reparameterisation has seen ST_DONE)
 enum { ST_PROJ = 0, ST_MAXF, ST_CI, ST_CION, ST_ITER, ST_DONE, ST_CUR, ST_RDONE, ST_N };
 // mode of an instance (the ci_mode parameter)
@@ -61,9 +85,9 @@ struct GInst {
     // bilinear field of every image from the batched z-march pass
     // ([n_img][3][N], FP64); NULL: pass A gathers the neighbours itself
     const double *Bbil;
-    // > 0: pass A runs inside the z-march over the images, which leaves this
-    // many (energy, distance) partials per image (one per tile) in the
-    // image's first item slots; k_gneb_a then skips the instance
+    // > 0: the instance runs the two z-march passes, which leave one partial
+    // set per tile (this many per image) in the image's first item slots; the
+    // item passes skip it
     int zt_per_img;
 };
 
@@ -203,8 +227,8 @@ __global__ __launch_bounds__(kGB) void k_gneb_a(const GInst *__restrict__ inst, 
         const double es = block_sum(e, red);
         const double ds = block_sum(d2, red);
         if (threadIdx.x == 0) {
-            partial[(size_t)it * 2] = es;
-            partial[(size_t)it * 2 + 1] = ds;
+            partial[(size_t)it * kPS] = es;
+            partial[(size_t)it * kPS + 1] = ds;
         }
     }
 }
@@ -221,21 +245,27 @@ __device__ __forceinline__ bool gate_open(const GInst &G, int gate) {
     return G.st[ST_DONE] == 0.0;
 }
 
+// nv_items / nv_tiles: partial values per item of the item passes / per tile
+// of the two-pass instances (0: this reduction does not apply to them);
+// items_only: the pass reduced was an item pass for every instance.
 __global__ __launch_bounds__(kGB) void k_gneb_reduce(const GInst *__restrict__ inst, const int2 *__restrict__ imgs,
-                                                     const double *__restrict__ partial, int nv, int base,
-                                                     int only_movable, int gate, int take_max, int pass_a = 0) {
+                                                     const double *__restrict__ partial, int nv_items, int nv_tiles,
+                                                     int base, int only_movable, int gate, int take_max,
+                                                     int items_only) {
     __shared__ double red[kGB / 64];
     const int2 ii = imgs[blockIdx.x];
     const GInst &G = inst[ii.x];
     if (!gate_open(G, gate)) return;
     if (only_movable && (ii.y == 0 || ii.y == G.n_img - 1)) return;
+    const bool tiles = G.zt_per_img > 0 && !items_only;
+    const int nv = tiles ? nv_tiles : nv_items;
+    if (nv == 0) return;
     const int first = G.item0 + ii.y * G.items_per_img;
-    // the fused first pass leaves one partial per z-march tile
-    const int count = (pass_a && G.zt_per_img > 0) ? G.zt_per_img : G.items_per_img;
+    const int count = tiles ? G.zt_per_img : G.items_per_img;
     for (int v = 0; v < nv; ++v) {
         double s = 0.0;
         for (int k = threadIdx.x; k < count; k += kGB) {
-            const double x = partial[(size_t)(first + k) * nv + v];
+            const double x = partial[(size_t)(first + k) * kPS + v];
             s = take_max ? fmax(s, x) : s + x;
         }
         const double t = take_max ? block_max(s, red) : block_sum(s, red);
@@ -310,6 +340,7 @@ __global__ __launch_bounds__(kGB) void k_gneb_b(const GInst *__restrict__ inst, 
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const GItem itm = items[it];
         const GInst &G = inst[itm.inst];
+        if (G.zt_per_img > 0) continue;  // two-pass instance (uniform over the block)
         double v5[5] = {0, 0, 0, 0, 0};
         const bool movable = itm.img > 0 && itm.img < G.n_img - 1;
         if (G.st[ST_DONE] == 0.0 && movable) {
@@ -326,18 +357,19 @@ __global__ __launch_bounds__(kGB) void k_gneb_b(const GInst *__restrict__ inst, 
                 // (string method: the velocities stay zero and are not read)
                 if (G.ci_mode == MODE_STRING) v[0] = v[1] = v[2] = 0.0;
                 else ld3(G.V + (int64_t)itm.img * 3 * N, N, t, v);
+                // in the order of the image slots IS_VF, IS_FF, IS_TT, IS_FT, IS_VT
                 for (int c = 0; c < 3; ++c) {
-                    v5[0] += tau[c] * tau[c];
-                    v5[1] += f[c] * tau[c];
-                    v5[2] += v[c] * tau[c];
-                    v5[3] += v[c] * f[c];
-                    v5[4] += f[c] * f[c];
+                    v5[0] += v[c] * f[c];
+                    v5[1] += f[c] * f[c];
+                    v5[2] += tau[c] * tau[c];
+                    v5[3] += f[c] * tau[c];
+                    v5[4] += v[c] * tau[c];
                 }
             }
         }
         for (int q = 0; q < 5; ++q) {
             const double r = block_sum(v5[q], red);
-            if (threadIdx.x == 0) partial[(size_t)it * 5 + q] = r;
+            if (threadIdx.x == 0) partial[(size_t)it * kPS + q] = r;
         }
     }
 }
@@ -355,6 +387,13 @@ __global__ __launch_bounds__(kGB) void k_gneb_scalars2(const GInst *__restrict__
     double P = 0.0, Q = 0.0;
     for (int n = 1 + (int)threadIdx.x; n + 1 < G.n_img; n += kGB) {
         double *r = im + n * IS_N;
+        if (G.zt_per_img > 0) {
+            // two-pass instance: tau = w+ a + w- b
+            const double wp = r[IS_WP], wm = r[IS_WM];
+            r[IS_TT] = wp * wp * r[IS_AA] + 2.0 * wp * wm * r[IS_AB] + wm * wm * r[IS_BB];
+            r[IS_FT] = wp * r[IS_FA] + wm * r[IS_FB];
+            r[IS_VT] = wp * r[IS_VA] + wm * r[IS_VB];
+        }
         const double tn = sqrt(r[IS_TT]);
         r[IS_TN] = tn;
         const double ft = tn > 0.0 ? r[IS_FT] / tn : 0.0;
@@ -380,6 +419,7 @@ __global__ __launch_bounds__(kGB) void k_gneb_c(const GInst *__restrict__ inst, 
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const GItem itm = items[it];
         const GInst &G = inst[itm.inst];
+        if (G.zt_per_img > 0) continue;  // two-pass instance (uniform over the block)
         double fm = 0.0;
         const bool movable = itm.img > 0 && itm.img < G.n_img - 1;
         if (G.st[ST_DONE] == 0.0 && movable) {
@@ -429,7 +469,7 @@ __global__ __launch_bounds__(kGB) void k_gneb_c(const GInst *__restrict__ inst, 
             }
         }
         const double r = block_max(fm, red);
-        if (threadIdx.x == 0) partial[it] = r;
+        if (threadIdx.x == 0) partial[(size_t)it * kPS] = r;
     }
 }
 
@@ -525,7 +565,7 @@ __global__ __launch_bounds__(kGB) void k_gneb_rdist(const GInst *__restrict__ in
             }
         }
         const double ds = block_sum(d2, red);
-        if (threadIdx.x == 0) partial[it] = ds;
+        if (threadIdx.x == 0) partial[(size_t)it * kPS] = ds;
     }
 }
 
@@ -660,12 +700,34 @@ void gneb_free(spx_gneb *g) {
     g->owned.clear();
 }
 
+// Arguments of the two z-march passes of instance k.
+GnebPassArgs pass_args(const spx_gneb *g, int k) {
+    const GInst &G = g->hinst[k];
+    GnebPassArgs a{};
+    a.n_img = G.n_img;
+    a.item0 = G.item0;
+    a.items_per_img = G.items_per_img;
+    a.Y0 = G.Y[0];
+    a.Y1 = G.Y[1];
+    a.V = G.V;
+    a.cur = G.st + ST_CUR;
+    a.done = G.st + ST_DONE;
+    a.img = G.img;
+    a.st = G.st;
+    a.slots = GnebSlots{IS_N, IS_WP, IS_WM, IS_TN, IS_COEF, ST_PROJ};
+    a.dt = G.dt;
+    a.mass = G.mass;
+    a.string = G.ci_mode == MODE_STRING ? 1 : 0;
+    a.partial = g->d_partial;
+    return a;
+}
+
 // Enqueue the geodesic reparameterisation of the instances the gate admits.
 hipError_t enqueue_reparam(spx_gneb *g, int gate, hipStream_t st) {
     const unsigned gi = grid_for(g->n_items);
     const unsigned gs = (unsigned)((g->n_inst + 63) / 64);
     k_gneb_rdist<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial, gate);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, IS_RD2, 0, gate, 0);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, 1, IS_RD2, 0, gate, 0, 1);
     k_gneb_rscalars<<<g->n_inst, kGB, 0, st>>>(g->d_inst, gate);
     k_gneb_reparam<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, gate);
     k_gneb_rflip<<<gs, 64, 0, st>>>(g->d_inst, g->n_inst, gate);
@@ -673,29 +735,38 @@ hipError_t enqueue_reparam(spx_gneb *g, int gate, hipStream_t st) {
 }
 
 // Enqueue one GNEB iteration (all instances) on stream st.
+GnebPassArgs pass_args(const spx_gneb *g, int k);
+
 hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
     const unsigned gi = grid_for(g->n_items);
+    bool any_items = false;  // an instance that runs the item passes
     for (int k = 0; k < g->n_inst; ++k) {
         const GInst &G = g->hinst[k];
         hipError_t e = hipSuccess;
-        if (G.zt_per_img > 0)
-            e = zmarch_gneb_a(g->zplan[k], G.g, g->hos[k], G.n_img, G.Y[0], G.Y[1], G.st + ST_CUR, G.st + ST_DONE,
-                              G.F, g->d_partial, G.item0, G.items_per_img, st);
+        if (G.zt_per_img > 0) e = zmarch_gneb_pass(0, g->zplan[k], G.g, g->hos[k], pass_args(g, k), st);
         else if (G.Bbil)
             e = zmarch_bil_images(g->zplan[k], G.g, G.n_img, G.Y[0], G.Y[1], G.st + ST_CUR, G.st + ST_DONE,
                                   (double *)G.Bbil, st);
         if (e != hipSuccess) return e;
+        any_items = any_items || G.zt_per_img == 0;
     }
-    bool any_elementwise_a = false;  // an instance whose first pass is not fused into the z-march
-    for (const GInst &G : g->hinst) any_elementwise_a = any_elementwise_a || G.zt_per_img == 0;
-    if (any_elementwise_a) k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, IS_E, 0, GATE_ITER, 0, 1);
+    if (any_items) k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, kPassA2Values, IS_E, 0, GATE_ITER,
+                                             0, 0);
     k_gneb_scalars1<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
-    k_gneb_b<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 5, IS_TT, 1, GATE_ITER, 0);
+    if (any_items) {
+        k_gneb_b<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
+        k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 5, 0, IS_VF, 1, GATE_ITER, 0, 0);
+    }
     k_gneb_scalars2<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
-    k_gneb_c<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, IS_FM, 1, GATE_ITER, 1);
+    if (any_items) k_gneb_c<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
+    for (int k = 0; k < g->n_inst; ++k) {
+        const GInst &G = g->hinst[k];
+        if (G.zt_per_img == 0) continue;
+        hipError_t e = zmarch_gneb_pass(1, g->zplan[k], G.g, g->hos[k], pass_args(g, k), st);
+        if (e != hipSuccess) return e;
+    }
+    k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, 1, IS_FM, 1, GATE_ITER, 1, 0);
     k_gneb_finish<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
     bool any_string = false;
     for (const GInst &G : g->hinst) any_string = any_string || G.ci_mode == MODE_STRING;
@@ -786,22 +857,26 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         gi.Y[0] = images[k];
         if ((s = gneb_alloc(g, (void **)&gi.Y[1], n3 * sizeof(double), "GNEB image buffer")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.V, n3 * sizeof(double), "GNEB velocities")) != SPX_OK) break;
-        if ((s = gneb_alloc(g, (void **)&gi.F, n3 * sizeof(double), "GNEB forces")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.img, sizeof(double) * IS_N * gi.n_img, "GNEB image stats")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.st, sizeof(double) * ST_N, "GNEB state")) != SPX_OK) break;
         if ((s = gneb_alloc(g, (void **)&gi.alpha, sizeof(double) * gi.n_img, "GNEB image spacing")) != SPX_OK) break;
         const ZPlan &zp = g->zplan[k];
         gi.zt_per_img = 0;
+        gi.F = nullptr;
         if (zp.valid && zp.prec == 0 && zmarch_tiles(zp, gi.g) <= gi.items_per_img) {
-            gi.zt_per_img = zmarch_tiles(zp, gi.g);  // first pass fused into the z-march
-        } else if (zp.valid) {
-            if ((s = gneb_alloc(g, (void **)&gi.Bbil, n3 * sizeof(double), "GNEB bilinear field")) != SPX_OK) break;
+            gi.zt_per_img = zmarch_tiles(zp, gi.g);  // the two z-march passes; no stored force
+        } else {
+            if ((s = gneb_alloc(g, (void **)&gi.F, n3 * sizeof(double), "GNEB forces")) != SPX_OK) break;
+            if (zp.valid &&
+                (s = gneb_alloc(g, (void **)&gi.Bbil, n3 * sizeof(double), "GNEB bilinear field")) != SPX_OK)
+                break;
         }
     }
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_inst, sizeof(GInst) * n_inst, "GNEB instances");
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_items, sizeof(GItem) * items.size(), "GNEB items");
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_imgs, sizeof(int2) * imgs.size(), "GNEB image list");
-    if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_partial, sizeof(double) * 5 * items.size(), "GNEB partials");
+    if (s == SPX_OK)
+        s = gneb_alloc(g, (void **)&g->d_partial, sizeof(double) * kPassA2Values * items.size(), "GNEB partials");
     for (int k = 0; k < n_inst; ++k) g->max_img = std::max(g->max_img, n_img[k]);
     if (s == SPX_OK) s = gneb_alloc(g, (void **)&g->d_tvals, sizeof(float) * g->max_img * n_inst, "GNEB t values");
     if (s != SPX_OK) {

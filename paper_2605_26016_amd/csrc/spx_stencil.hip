@@ -61,19 +61,24 @@ constexpr int kThreads = kTX * kTYT;
 // again when it was not stored), so that the corrector evaluates only f(S~).
 // ZM_BIL: store only the FP32 bilinear field (the split Heun mode's stencil
 // pass; the Heun stages then run as elementwise kernels).
-// ZM_GNEB_A: over the images of a GNEB instance, the per-site work of the
-// first GNEB pass in the epilogue (energy terms, the force projected on the
-// tangent plane of the spin for interior images, the squared geodesic
-// distance to the next image), reduced to one (energy, distance) partial per
-// block in place of storing the field.
 // ZM_MIN_FORCE: the force pass of the static minimisers in the epilogue
 // (force projected on the spin's tangent plane, its max norm and the dot
 // products of the method), reduced to one partial set per block.
 // ZM_ENERGY: the energy terms -S.b_bil/2, -S.b_Z, -S.b_ani/2, -S.b_dip/2 of the
 // thread's sites summed in the epilogue (the field is never stored), reduced
 // to one quadruple per tile in a fixed order.
+// ZM_GNEB_A2 / ZM_GNEB_C2: the two passes of a GNEB iteration that keeps no
+// stored force.  A2 (every image): energy terms, squared distance to the next
+// image and, for interior images, the nine image sums from which the
+// improved tangent's dot products follow once its energy weights are known
+// (a = P(S_n+1 - S_n), b = P(S_n - S_n-1), P the projection on the spin's
+// tangent plane: a.a, a.b, b.b, F.a, F.b, v.a, v.b, v.F, F.F), eleven
+// partials per tile.  C2 (interior images): the force again from the field,
+// the tangent w+ a + w- b, the spring / climbing-image force, the velocity
+// projection step and the exponential-map retraction into the other image
+// buffer, the velocity store and max |F_gneb| per tile.
 enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4, ZM_BIL = 5,
-             ZM_GNEB_A = 6, ZM_MIN_FORCE = 7, ZM_ENERGY = 8 };
+             ZM_MIN_FORCE = 7, ZM_ENERGY = 8, ZM_GNEB_A2 = 9, ZM_GNEB_C2 = 10 };
 
 template <typename T, int NW>
 struct ZWeights {
@@ -107,7 +112,7 @@ struct ZArgs {
     int xcd;
     const double *S0alt;
     const double *sel, *skip;
-    // ZM_GNEB_A: forces [nimg][3][N], partials [(gitem0 + img gipi + tile) * 2 + {0,1}]
+    // ZM_MIN_FORCE: force [3][N]; partials of the modes that reduce per tile
     double *gF;
     double *gpart;
     int gitem0, gipi;
@@ -118,6 +123,17 @@ struct ZArgs {
     double *mSh, *mYh;
     const double *mst;
     int mmethod, mcand_idx;
+    // ZM_GNEB_A2 / C2: launch image k is image gimg0 + k of gntot; velocities
+    // gV [gntot][3][N]; C2 writes to O0, or O1 when *sel != 0; per-image
+    // scalars gims[n * gis.n + {wp, wm, tn, coef}], the VP projection at
+    // gst[gis.proj]; the VP step and mass; string method (no velocity)
+    int gimg0, gntot;
+    double *gV;
+    double *O0, *O1;
+    const double *gims, *gst;
+    GnebSlots gis;
+    double gdt, gmass;
+    int gstring;
 };
 
 // Shape table as a static constant, so that every bond read in an unrolled
@@ -178,7 +194,10 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     const int zb = (int)(tile / (nbx * nby));
     const int img = zb / g.nzc;
     const int zs = (zb - img * g.nzc) * g.zch;
-    const int64_t boff = (int64_t)img * g.bstride;
+    // image offset of the launch's image in its buffer (the GNEB second pass
+    // launches over the interior images only: launch image k is image
+    // gimg0 + k)
+    const int64_t boff = (int64_t)(img + g.gimg0) * g.bstride;
     const int nout = min(g.zch, g.Lz - zs);
     const int nq = nout + D - 1;
     const int64_t N = g.N;
@@ -203,14 +222,16 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // fetched one march iteration before their use so that their latency
     // hides behind a plane's stencil: CORRECT_P reads P and eta, PREDICT
     // reads eta when the noise comes from a pre-pass.
-    constexpr bool kEpiPre = MODE == ZM_CORRECT_P || MODE == ZM_PREDICT || MODE == ZM_GNEB_A || MODE == ZM_MIN_FORCE;
-    constexpr int NE = (MODE == ZM_CORRECT_P || MODE == ZM_MIN_FORCE) ? 6
-                       : (MODE == ZM_PREDICT || MODE == ZM_GNEB_A) ? 3 : 1;
+    constexpr bool kEpiPre = MODE == ZM_CORRECT_P || MODE == ZM_PREDICT || MODE == ZM_MIN_FORCE ||
+                             MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2;
+    constexpr int NE = (MODE == ZM_CORRECT_P || MODE == ZM_MIN_FORCE || MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2) ? 6
+                       : MODE == ZM_PREDICT ? 3 : 1;
+    // image of the launch in its instance (GNEB two-pass modes)
+    const int gimg = img + g.gimg0;
     double epi[kYB][NSUB][NE];
     auto fetch_epi = [&](int o) __attribute__((always_inline)) {
         if (o < 0 || o >= nout) return;  // uniform over the block
         if (MODE == ZM_PREDICT && !(hc.noise && g.eload)) return;
-        if (MODE == ZM_GNEB_A && img >= g.nimg - 1) return;  // the last image has no successor
         if (MODE == ZM_MIN_FORCE && g.mmethod == 3) return;   // Adam reads nothing here
         const int x = x0 + tx;
         static_for<NSUB>([&](auto ac) __attribute__((always_inline)) {
@@ -230,10 +251,14 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 } else if constexpr (MODE == ZM_PREDICT) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) e[c] = g.eload[c * N + i];
-                } else if constexpr (MODE == ZM_GNEB_A) {
-                    // the next image of the same buffer
+                } else if constexpr (MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2) {
+                    // the neighbouring images (zero where there is none)
+                    const bool nx = gimg < g.gntot - 1, pv = gimg > 0;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) e[c] = S0[g.bstride + c * N + i];
+                    for (int c = 0; c < 3; ++c) {
+                        e[c] = nx ? S0[g.bstride + c * N + i] : 0.0;
+                        e[3 + c] = pv ? S0[c * N + i - g.bstride] : 0.0;
+                    }
                 } else if constexpr (MODE == ZM_MIN_FORCE) {
                     if (g.mmethod == 0) {
 #pragma unroll
@@ -453,8 +478,18 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // by phase across the sites, with no branch inside a phase, so that the
     // sites' independent FP64 and Philox chains interleave; sites outside
     // the lattice (valid = false) compute on a clamped index and store nothing.
-    double gE = 0.0, gD = 0.0;  // ZM_GNEB_A: the thread's energy and squared-distance sums
     double eE[4] = {0.0, 0.0, 0.0, 0.0};  // ZM_ENERGY: the thread's four energy terms
+    // ZM_GNEB_C2: the thread's max |F_gneb|.  ZM_GNEB_A2: the thread's energy,
+    // squared distance and nine image sums (a.a, a.b, b.b, F.a, F.b, v.a, v.b,
+    // v.F, F.F) live in its own LDS column rather than in registers
+    double gX[1] = {0.0};
+    double *gacc = nullptr;  // [11][kThreads], ZM_GNEB_A2 only
+    if constexpr (MODE == ZM_GNEB_A2) {
+        __shared__ double gacc_lds[11 * kThreads];
+        gacc = gacc_lds;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) gacc[k * kThreads + threadIdx.x] = 0.0;
+    }
     // ZM_MIN_FORCE: max |F|, v.F, F.F, s.s, s.y, y.y of the thread's sites
     double mred[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     auto finish_row = [&](int x, int y, int z, bool valid, const T (&v)[NSUB][NIN][3],
@@ -529,6 +564,123 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             }
             return;
         }
+        if constexpr (MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2) {
+            if (!valid) return;
+            const bool interior = gimg > 0 && gimg < g.gntot - 1, has_next = gimg < g.gntot - 1;
+            const double *im = g.gims + (int64_t)gimg * g.gis.n;
+            double wp = 0.0, wm = 0.0, tn = 0.0, cf = 0.0, proj = 0.0;
+            if constexpr (MODE == ZM_GNEB_C2) {
+                wp = im[g.gis.wp];
+                wm = im[g.gis.wm];
+                tn = im[g.gis.tn];
+                cf = im[g.gis.coef];
+                proj = g.gst[g.gis.proj];
+            }
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a) {
+                const double *sp = so[a];
+                double ba[3];
+                aniso_field(os, a, sp, ba);
+                double b[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) b[c] = (double)v[a][0][c] + ba[c] + os.bz[a][c];
+                if constexpr (MODE == ZM_GNEB_A2) {
+                    double sb = 0.0, sz = 0.0, sa = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        sb += sp[c] * (double)v[a][0][c];
+                        sz += sp[c] * os.bz[a][c];
+                        sa += sp[c] * ba[c];
+                    }
+                    gacc[threadIdx.x] += -0.5 * sb - sz - 0.5 * sa;
+                    if (has_next) {
+                        const double *q = e[a];
+                        const double c0 = sp[1] * q[2] - sp[2] * q[1], c1 = sp[2] * q[0] - sp[0] * q[2],
+                                     c2 = sp[0] * q[1] - sp[1] * q[0];
+                        const double th =
+                            atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), sp[0] * q[0] + sp[1] * q[1] + sp[2] * q[2]);
+                        gacc[kThreads + threadIdx.x] += th * th;
+                    }
+                }
+                if (!interior) continue;
+                const double bs = b[0] * sp[0] + b[1] * sp[1] + b[2] * sp[2];
+                double F[3], ap[3], bp[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    F[c] = b[c] - bs * sp[c];
+                    ap[c] = e[a][c] - sp[c];
+                    bp[c] = sp[c] - e[a][3 + c];
+                }
+                const double as = ap[0] * sp[0] + ap[1] * sp[1] + ap[2] * sp[2];
+                const double bss = bp[0] * sp[0] + bp[1] * sp[1] + bp[2] * sp[2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    ap[c] -= as * sp[c];
+                    bp[c] -= bss * sp[c];
+                }
+                if constexpr (MODE == ZM_GNEB_A2) {
+                    // the velocity is read here rather than a plane ahead:
+                    // the registers matter more than its latency
+                    double vv[3] = {0.0, 0.0, 0.0};
+                    if (!g.gstring) {
+                        const double *V = g.gV + (int64_t)gimg * g.bstride;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) vv[c] = V[c * N + i[a]];
+                    }
+                    double d9[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        d9[0] += ap[c] * ap[c];
+                        d9[1] += ap[c] * bp[c];
+                        d9[2] += bp[c] * bp[c];
+                        d9[3] += F[c] * ap[c];
+                        d9[4] += F[c] * bp[c];
+                        d9[5] += vv[c] * ap[c];
+                        d9[6] += vv[c] * bp[c];
+                        d9[7] += vv[c] * F[c];
+                        d9[8] += F[c] * F[c];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) gacc[(2 + k) * kThreads + threadIdx.x] += d9[k];
+                } else {
+                    // F_gneb = F + c tau^, VP step, exponential map
+                    double u[3], vn[3], f2 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double tau = wp * ap[c] + wm * bp[c];
+                        const double th = tn > 0.0 ? tau / tn : 0.0;
+                        const double ft = F[c] + cf * th;
+                        f2 += ft * ft;
+                        vn[c] = g.gstring ? 0.0 : proj * ft + (g.gdt / g.gmass) * ft;
+                        u[c] = g.gstring ? g.gdt * F[c] : g.gdt * vn[c];
+                    }
+                    gX[0] = fmax(gX[0], sqrt(f2));
+                    if (!g.gstring) {
+                        double *V = g.gV + (int64_t)gimg * g.bstride;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) V[c * N + i[a]] = vn[c];
+                        const double us = u[0] * sp[0] + u[1] * sp[1] + u[2] * sp[2];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) u[c] -= us * sp[c];
+                    }
+                    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    double o[3];
+                    if (un == 0.0) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) o[c] = sp[c];
+                    } else {
+                        const double cs = cos(un), sn = sin(un) / un;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) o[c] = cs * sp[c] + sn * u[c];
+                        normalise3(o);
+                    }
+                    double *On = ((g.sel && *g.sel != 0.0) ? g.O1 : g.O0) + (int64_t)gimg * g.bstride;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) On[c * N + i[a]] = o[c];
+                }
+            }
+            return;
+        }
         if constexpr (MODE == ZM_ENERGY) {
             if (!valid) return;
 #pragma unroll
@@ -547,41 +699,6 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 eE[1] += -sz;
                 eE[2] += -0.5 * sa;
                 eE[3] += -0.5 * sd;
-            }
-            return;
-        }
-        if constexpr (MODE == ZM_GNEB_A) {
-            if (!valid) return;
-            const bool interior = img > 0 && img < g.nimg - 1;
-            const bool has_next = img < g.nimg - 1;
-#pragma unroll
-            for (int a = 0; a < NSUB; ++a) {
-                double ba[3];
-                aniso_field(os, a, so[a], ba);
-                double b[3], sb = 0.0, sz = 0.0, sa = 0.0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double bil = (double)v[a][0][c];
-                    b[c] = bil + ba[c] + os.bz[a][c];
-                    sb += so[a][c] * bil;
-                    sz += so[a][c] * os.bz[a][c];
-                    sa += so[a][c] * ba[c];
-                }
-                gE += -0.5 * sb - sz - 0.5 * sa;
-                if (interior) {
-                    const double bs = b[0] * so[a][0] + b[1] * so[a][1] + b[2] * so[a][2];
-                    double *F = g.gF + boff;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) F[c * N + i[a]] = b[c] - bs * so[a][c];
-                }
-                if (has_next) {
-                    // geodesic angle atan2(|s x s'|, s.s')
-                    const double *p = so[a], *q = e[a];
-                    const double c0 = p[1] * q[2] - p[2] * q[1], c1 = p[2] * q[0] - p[0] * q[2],
-                                 c2 = p[0] * q[1] - p[1] * q[0];
-                    const double th = atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), p[0] * q[0] + p[1] * q[1] + p[2] * q[2]);
-                    gD += th * th;
-                }
             }
             return;
         }
@@ -906,6 +1023,31 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             g.gpart[(size_t)tile * 6 + k] = t;
         }
     }
+    if constexpr (MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2) {
+        // fixed-order block sums (A2: energy, squared distance and the nine
+        // image sums) or maximum (C2: max |F_gneb|), one set per tile
+        constexpr int NV = MODE == ZM_GNEB_A2 ? 11 : 1;
+        __shared__ double gred[NV][kThreads / 64];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double v = MODE == ZM_GNEB_C2 ? gX[0] : gacc[k * kThreads + threadIdx.x];
+            if constexpr (MODE == ZM_GNEB_C2) {
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+            } else {
+                v = wave_sum(v);
+            }
+            if ((threadIdx.x & 63) == 0) gred[k][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < NV) {
+            double t = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w)
+                t = MODE == ZM_GNEB_C2 ? fmax(t, gred[threadIdx.x][w]) : t + gred[threadIdx.x][w];
+            const int tile_in_img = (int)tile - img * (int)(nbx * nby) * g.nzc;
+            g.gpart[((size_t)g.gitem0 + (size_t)gimg * g.gipi + tile_in_img) * 11 + threadIdx.x] = t;
+        }
+    }
     if constexpr (MODE == ZM_ENERGY) {
         // fixed-order block sums of the four terms, one quadruple per tile
         __shared__ double ered[4][kThreads / 64];
@@ -919,22 +1061,6 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             double t = 0.0;
             for (int w = 0; w < kThreads / 64; ++w) t += ered[threadIdx.x][w];
             g.gpart[(size_t)tile * 4 + threadIdx.x] = t;
-        }
-    }
-    if constexpr (MODE == ZM_GNEB_A) {
-        // fixed-order block sums of the two statistics, one partial pair per tile
-        __shared__ double gred[2][kThreads / 64];
-        const double se = wave_sum(gE), sd = wave_sum(gD);
-        if ((threadIdx.x & 63) == 0) {
-            gred[0][threadIdx.x >> 6] = se;
-            gred[1][threadIdx.x >> 6] = sd;
-        }
-        __syncthreads();
-        if (threadIdx.x < 2) {
-            double t = 0.0;
-            for (int w = 0; w < kThreads / 64; ++w) t += gred[threadIdx.x][w];
-            const int tile_in_img = (int)tile - img * (int)(nbx * nby) * g.nzc;
-            g.gpart[((size_t)g.gitem0 + (size_t)img * g.gipi + tile_in_img) * 2 + threadIdx.x] = t;
         }
     }
 }
@@ -1223,24 +1349,38 @@ int zmarch_tiles(const ZPlan &zp, const Grid &g) {
     return ((g.Lx + kTX - 1) / kTX) * ((g.Ly + kTYE - 1) / kTYE) * ((g.Lz + zp.zch - 1) / zp.zch);
 }
 
-hipError_t zmarch_gneb_a(const ZPlan &zp, const Grid &g, const Onsite &os, int n_img, const double *S0,
-                         const double *S0alt, const double *sel, const double *skip, double *F, double *partial,
-                         int item0, int items_per_img, hipStream_t st) {
-    if (zp.prec != 0 || n_img <= 0 || zmarch_tiles(zp, g) > items_per_img) return hipErrorInvalidValue;
+hipError_t zmarch_gneb_pass(int pass, const ZPlan &zp, const Grid &g, const Onsite &os, const GnebPassArgs &ga,
+                            hipStream_t st) {
+    if (zp.prec != 0 || ga.n_img < 3 || zmarch_tiles(zp, g) > ga.items_per_img) return hipErrorInvalidValue;
     ZArgs a = make_args(zp, g);
-    a.S0 = S0;
-    a.S0alt = S0alt ? S0alt : S0;
-    a.sel = sel;
-    a.skip = skip;
-    a.nimg = n_img;
     a.bstride = 3 * g.N;
-    a.gF = F;
-    a.gpart = partial;
-    a.gitem0 = item0;
-    a.gipi = items_per_img;
+    a.gntot = ga.n_img;
+    // the second pass runs over the interior images only
+    a.gimg0 = pass == 0 ? 0 : 1;
+    a.nimg = pass == 0 ? ga.n_img : ga.n_img - 2;
+    a.S0 = ga.Y0;
+    a.S0alt = ga.Y1;
+    a.sel = ga.cur;
+    a.skip = ga.done;
+    a.O0 = ga.Y1;
+    a.O1 = ga.Y0;
+    a.gV = ga.V;
+    a.gims = ga.img;
+    a.gst = ga.st;
+    a.gis = ga.slots;
+    a.gdt = ga.dt;
+    a.gmass = ga.mass;
+    a.gstring = ga.string;
+    a.gpart = ga.partial;
+    a.gitem0 = ga.item0;
+    a.gipi = ga.items_per_img;
     HeunConst hc{};
-    if (zp.iso) return launch_mode<double, true, ZM_GNEB_A>(zp, a, os, hc, st);
-    return launch_mode<double, false, ZM_GNEB_A>(zp, a, os, hc, st);
+    if (pass == 0) {
+        if (zp.iso) return launch_mode<double, true, ZM_GNEB_A2>(zp, a, os, hc, st);
+        return launch_mode<double, false, ZM_GNEB_A2>(zp, a, os, hc, st);
+    }
+    if (zp.iso) return launch_mode<double, true, ZM_GNEB_C2>(zp, a, os, hc, st);
+    return launch_mode<double, false, ZM_GNEB_C2>(zp, a, os, hc, st);
 }
 
 hipError_t zmarch_bil_images(const ZPlan &zp, const Grid &g, int n_img, const double *S0, const double *S0alt,

@@ -149,21 +149,22 @@ def test_gneb_stoner_wohlfarth_barrier():
     assert abs((s["E"][ci] - s["E"][0]) - K * (1 - h) ** 2) < 1e-8
 
 
-def test_gneb_fused_and_stored_field_first_pass_match_oracle():
-    # one batch with both forms of the first pass: instances of several
+def test_gneb_two_pass_and_item_instances_match_oracle():
+    # one batch with every form of the iteration: instances of several
     # z-march tiles per image with ragged x/y/z tails, periodic and open (the
-    # pass runs inside the z-march and leaves one partial per tile), and a
-    # thin column with more tiles per image than 256-site items (the z-march
-    # stores the field and the elementwise pass reads it)
+    # two z-march passes, one partial set per tile, no stored force), a thin
+    # column with more tiles per image than 256-site items (the z-march stores
+    # the field and the item passes read it), and a gather-engine instance
+    # (item passes that gather the neighbours); their passes run side by side
     import torch
     from paper_2605_26016_amd import spx
-    cases = [(frustrated((70, 10, 20), periodic=(1, 0, 1)), 5, 21), (frustrated((66, 9, 18)), 4, 23),
-             (frustrated((2, 2, 40)), 4, 22)]
+    cases = [(frustrated((70, 10, 20), periodic=(1, 0, 1)), 5, 21, {}), (frustrated((66, 9, 18)), 4, 23, {}),
+             (frustrated((2, 2, 40)), 4, 22, {}), (frustrated((5, 4, 3)), 5, 24, dict(stencil_engine=1))]
     hams, bufs, refs = [], [], []
-    for w, n_img, seed in cases:
+    for w, n_img, seed, setup in cases:
         A, B = endpoints(w, seed)
         Y0 = oracle.geodesic_path(A, B, n_img)
-        hams.append(gpu_hamiltonian(w))
+        hams.append(gpu_hamiltonian(w, **setup))
         bufs.append(to_dev(Y0))
         refs.append((oracle_model(w), oracle.GnebState(Y0, k_spring=1.0, dt=0.05, mass=1.0, ci_mode=1,
                                                         ci_on_below=3.0)))
