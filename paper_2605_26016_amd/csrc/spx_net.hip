@@ -115,7 +115,7 @@ __global__ void k_transpose_flip(const float *__restrict__ W, float *__restrict_
 // over the block's output tile; partial[blk][COUT*CIN*27 + COUT].
 template <int CIN, int COUT, bool SILU_IN>
 __global__ __launch_bounds__(kNT) void k_conv_wgrad(const float *__restrict__ in, const float *__restrict__ g,
-                                                    float *__restrict__ partial, NetDims d) {
+                                                    double *__restrict__ partial, NetDims d) {
     __shared__ float tile[CIN][kHalo];
     __shared__ float gt[COUT][kTXn * kTYn * kTZn];
     int x0, y0, z0;
@@ -132,39 +132,43 @@ __global__ __launch_bounds__(kNT) void k_conv_wgrad(const float *__restrict__ in
     __syncthreads();
     const int nw = COUT * CIN * 27 + COUT;
     const size_t blk = (size_t)blockIdx.z * gridDim.x * gridDim.y + (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-    float *dst = partial + blk * nw;
+    // FP64 accumulation: the product of two floats is exact in double, so the
+    // weight-gradient sums carry no FP32 rounding of their own (only that of
+    // the FP32 activations and back-propagated fields they multiply)
+    double *dst = partial + blk * nw;
     const int t = threadIdx.x;
     if (t < COUT * CIN) {
         const int co = t / CIN, ci = t % CIN;
-        float acc[27];
+        double acc[27];
 #pragma unroll
-        for (int k = 0; k < 27; ++k) acc[k] = 0.0f;
+        for (int k = 0; k < 27; ++k) acc[k] = 0.0;
         for (int s = 0; s < kNT; ++s) {
-            const float gv = gt[co][s];
+            const double gv = (double)gt[co][s];
             const int sx = s % kTXn, sy = (s / kTXn) % kTYn, sz = s / (kTXn * kTYn);
 #pragma unroll
             for (int k = 0; k < 27; ++k) {
                 const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-                acc[k] += gv * tile[ci][(sx + kx) + kHX * ((sy + ky) + kHY * (sz + kz))];
+                acc[k] = fma(gv, (double)tile[ci][(sx + kx) + kHX * ((sy + ky) + kHY * (sz + kz))], acc[k]);
             }
         }
 #pragma unroll
         for (int k = 0; k < 27; ++k) dst[(co * CIN + ci) * 27 + k] = acc[k];
     }
     if (t < COUT) {
-        float sb = 0.0f;
-        for (int s = 0; s < kNT; ++s) sb += gt[t][s];
+        double sb = 0.0;
+        for (int s = 0; s < kNT; ++s) sb += (double)gt[t][s];
         dst[COUT * CIN * 27 + t] = sb;
     }
 }
 
-// Fixed-order sum of n_blk partial vectors of length nw.
-__global__ void k_sum_partials(const float *__restrict__ partial, int n_blk, int nw, float *__restrict__ out) {
+// Fixed-order FP64 sum of n_blk partial vectors of length nw, rounded to
+// float once.
+__global__ void k_sum_partials(const double *__restrict__ partial, int n_blk, int nw, float *__restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nw) return;
-    float s = 0.0f;
+    double s = 0.0;
     for (int b = 0; b < n_blk; ++b) s += partial[(size_t)b * nw + i];
-    out[i] = s;
+    out[i] = (float)s;
 }
 
 // Network input: channels (S_g, S_A, S_B, t) as FP32.
@@ -276,7 +280,7 @@ struct NetWork {
     float *x = nullptr, *z[4] = {nullptr, nullptr, nullptr, nullptr};
     float *g[4] = {nullptr, nullptr, nullptr, nullptr};
     float *wt = nullptr;        // transposed weights of one layer
-    float *part = nullptr;      // weight-gradient partials
+    double *part = nullptr;     // weight-gradient partials (FP64)
     size_t part_cap = 0;
     double *lpart = nullptr;
     size_t lpart_cap = 0;
@@ -437,7 +441,7 @@ spx_status spx_net_backward(spx_net *net, const float *params, const int32_t *di
     const size_t nl = (size_t)pg.x * pg.y;
     if (need > w.part_cap) {
         if (w.part) (void)hipFree(w.part);
-        if (hipMalloc((void **)&w.part, need * sizeof(float)) != hipSuccess) {
+        if (hipMalloc((void **)&w.part, need * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             w.part = nullptr;
             w.part_cap = 0;

@@ -2,8 +2,10 @@
 the learned GNEB initial path) against the FP64 oracle network.
 
 Tolerances (FP32 convolutions vs FP64): corrected images 1e-5 absolute per
-component; loss 1e-5 relative; gradients max|g - g_ref| <= 1e-4 max|g_ref|;
-Adam 1e-6 relative.
+component; loss 1e-5 relative; gradients max|g - g_ref| <= 1e-5 max|g_ref|
+(weight-gradient sums accumulated in FP64; the FP32 activations and
+back-propagated fields carry about 1e-7 relative error each); Adam 1e-6
+relative.
 """
 import numpy as np
 import pytest
@@ -92,7 +94,8 @@ def test_net_backward_matches_oracle():
         lref += lb / B
     assert abs(loss.item() - lref) <= 1e-5 * lref
     err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
-    assert err <= 1e-4, err
+    print(f"gradient max-normalised error {err:.2e}", flush=True)
+    assert err <= 1e-5, err
     # deterministic
     grad2 = torch.zeros_like(grad)
     spx.net_backward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), to_dev(Ss), grad2)
