@@ -103,15 +103,14 @@ def cpu_baseline(w, seconds: float):
             "sample": f"{steps} full Heun step(s) of {what}, FP64 oracle, {el:.1f} s"}
 
 
-# GNEB algorithmic HBM bytes per spin-image-iteration of the three passes
-# (FP64, 24 B per spin vector): pass A reads S_n, S_n+1 and writes F (72 B);
-# pass B reads S_n-1, S_n, S_n+1, F, v (120 B); pass C reads S_n-1, S_n, S_n+1,
-# F and writes v, S' (144 B).  Neighbour reuse inside an image is on chip.
-GNEB_PASS_BYTES = 336
-# the per-iteration lower bound the roofline is scored against: the first pass
-# reads S_n, S_n+1 and writes F (72 B), one second pass reads S_n, S_n+-1, F, v
-# and writes S, v (168 B)
+# GNEB per spin-image-iteration, the lower bound the roofline is scored
+# against: a first pass reads S_n, S_n+1 and writes F (72 B), a second pass
+# reads S_n, S_n+-1, F, v and writes S, v (168 B)
 GNEB_BYTES = 240
+# what the library's two z-march passes move (no stored force): the first
+# reads S_n, S_n-1, S_n+1 and v (96 B), the second reads S_n, S_n-1, S_n+1, v
+# and writes v, S' (120 B)
+GNEB_PASS_BYTES = 216
 # string method per spin-image: pass A 72 B; pass B without velocities 96 B;
 # pass C without velocities (read S_n-1, S_n, S_n+1, F, write S') 120 B; the
 # reparameterisation's distance pass (2 images per pair) 48 B and
@@ -160,9 +159,28 @@ def gneb_workload(args):
                 "ms_per_step": ms / n_it,
                 "roofline": {"bound": "hbm", "achieved": rate * GNEB_BYTES / 1e9, "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": rate * GNEB_BYTES / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                             "kernel": "GNEB iteration (passes A, B, C + reductions)",
+                             "kernel": "GNEB iteration (two z-march passes + reductions)",
                              "bytes_per_spin_image_iteration": GNEB_BYTES,
-                             "bytes_per_spin_image_iteration_of_the_passes": GNEB_PASS_BYTES}})
+                             "bytes_per_spin_image_iteration_of_the_passes": GNEB_PASS_BYTES,
+                             "GBps_of_the_passes": rate * GNEB_PASS_BYTES / 1e9}})
+    log(f"[bench] batched GNEB: {rate:.3e} spin-image-iterations/s ({ms / n_it:.3f} ms per iteration)")
+    # -- the same three instances as three separate GNEB objects, one after
+    # another on the same stream (the unbatched path)
+    singles = [spx.gneb_create([h], [Y], ci_mode=1, ci_on_below=1e-2, tol_force=0.0) for h, Y in zip(hams, imgs)]
+    for gs in singles:
+        spx.gneb_step(gs, 5)
+    torch.cuda.synchronize()
+    e0.record()
+    for gs in singles:
+        spx.gneb_step(gs, n_it)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_1 = e0.elapsed_time(e1)
+    out["per_instance"] = {"ms_per_iteration": ms_1 / n_it, "spin_image_iterations_per_s": spin_images * n_it / (ms_1 / 1e3),
+                           "batched_speedup": ms_1 / ms,
+                           "what": "each lattice its own GNEB object, stepped one after another on one stream"}
+    log(f"[bench] per-instance GNEB: {ms_1 / n_it:.3f} ms per iteration (batched {ms / n_it:.3f} ms)")
+    del singles
     # -- the string method on the same batch: force step + geodesic reparameterisation
     spx.gneb_set_params(g, vp_dt=0.01, ci_mode=4, tol_force=0.0)
     spx.gneb_step(g, 3)
@@ -182,7 +200,6 @@ def gneb_workload(args):
                      "spin_images": spin_images, "shells_throughput": [1.0, -0.164, -0.082],
                      "parallelism": "single GPU, ragged batch in one launch per pass"}
     del g, hams, imgs
-    log(f"[bench] batched GNEB: {rate:.3e} spin-image-iterations/s")
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_gneb_baseline(args.cpu_seconds)
     out["hbm_copy_GBps"] = copy_bandwidth()
     if args.no_learned:

@@ -67,6 +67,7 @@ struct ZPlan {
     int iso = 1;
     int nw = 0;
     int zch = 8;    // z planes per block
+    int txw = 64;   // tile width in x (GNEB passes: 64, 32 or 16; others 64)
     double wd[9 * kMaxShapeBonds];
     float wf[9 * kMaxShapeBonds];
 };
@@ -98,6 +99,10 @@ hipError_t zmarch_min_force(const ZPlan &zp, const Grid &g, const Onsite &os, co
                             hipStream_t st);
 // Tiles of one image (x tiles x y tiles x z chunks) of the z-march engine.
 int zmarch_tiles(const ZPlan &zp, const Grid &g);
+// The same for the GNEB passes (256-thread blocks, tile width zp.txw), and
+// the width those passes should use on a lattice.
+int zmarch_gneb_tiles(const ZPlan &zp, const Grid &g);
+int zmarch_gneb_width(const ZPlan &zp, const Grid &g);
 // The two passes of a GNEB iteration that stores no force (see spx_stencil.hip
 // ZM_GNEB_A2 / ZM_GNEB_C2), over the images of one instance.  pass 0: every
 // image, eleven partials per tile into partial[(item0 + n items_per_img +

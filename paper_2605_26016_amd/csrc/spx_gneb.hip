@@ -863,9 +863,11 @@ spx_status spx_gneb_create(spx_ham *const *H, int32_t n_inst, double *const *ima
         const ZPlan &zp = g->zplan[k];
         gi.zt_per_img = 0;
         gi.F = nullptr;
-        if (zp.valid && zp.prec == 0 && zmarch_tiles(zp, gi.g) <= gi.items_per_img) {
-            gi.zt_per_img = zmarch_tiles(zp, gi.g);  // the two z-march passes; no stored force
+        if (zp.valid && zp.prec == 0) g->zplan[k].txw = zmarch_gneb_width(zp, gi.g);
+        if (zp.valid && zp.prec == 0 && zmarch_gneb_tiles(zp, gi.g) <= gi.items_per_img) {
+            gi.zt_per_img = zmarch_gneb_tiles(zp, gi.g);  // the two z-march passes; no stored force
         } else {
+            g->zplan[k].txw = 64;
             if ((s = gneb_alloc(g, (void **)&gi.F, n3 * sizeof(double), "GNEB forces")) != SPX_OK) break;
             if (zp.valid &&
                 (s = gneb_alloc(g, (void **)&gi.Bbil, n3 * sizeof(double), "GNEB bilinear field")) != SPX_OK)

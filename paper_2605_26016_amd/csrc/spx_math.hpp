@@ -17,6 +17,15 @@
 //     About one ulp.
 //   - sqrt_pos, rsqrt_pos: positive normal arguments; the hardware estimate
 //     (relative error near 2^-23) refined by Newton steps to about one ulp.
+//   - div_pos: a / b for b positive normal, about half an ulp.
+//   - atan2_nonneg: atan2(y, x) for y >= 0 (the angle between two vectors
+//     from |a x b| and a.b): the ratio min/max of |x|, y in [0, 1], reduced
+//     by pi/4 to |t| <= tan(pi/8), then twenty terms of the series of
+//     atan t (the next term is below 2^-56 of the result); quadrants by
+//     pi/2 - . and pi - . with pi split in two doubles.  About two ulp.
+//   - expmap_cs: cos r and sin(r)/r from z = r^2 (the exponential map on the
+//     sphere), as power series in z for z <= 1 (ten terms each, the next
+//     below 2^-60), else through sqrt_pos and sincospi_d.  A few ulp.
 // Each function states its argument range; nothing here checks it.
 //
 // A host build of this header (for the accuracy tests) may define SPX_MATH_FN,
@@ -96,6 +105,16 @@ SPX_MATH_FN double log_pos(double u) {
     return std::fma(de, kLn2Hi, std::fma(de, kLn2Lo, lnm));
 }
 
+// a / b, b positive normal: reciprocal refined by two Newton steps, then
+// one residual correction of the quotient.
+SPX_MATH_FN double div_pos(double a, double b) {
+    double r = SPX_EST_RCP(b);
+    r = std::fma(std::fma(-b, r, 1.0), r, r);
+    r = std::fma(std::fma(-b, r, 1.0), r, r);
+    const double q = a * r;
+    return std::fma(std::fma(-q, b, a), r, q);
+}
+
 // sin(pi t) and cos(pi t), |t| < 2^30.
 SPX_MATH_FN void sincospi_d(double t, double &sn, double &cs) {
     // Taylor coefficients (-1)^k pi^(2k+1)/(2k+1)! and (-1)^k pi^(2k)/(2k)!
@@ -134,6 +153,80 @@ SPX_MATH_FN void sincospi_d(double t, double &sn, double &cs) {
     const double b = (q & 1) ? sr : cr;
     sn = (q & 2) ? -a : a;
     cs = ((q + 1) & 2) ? -b : b;
+}
+
+
+// atan2(y, x) for y >= 0 and (x, y) != (0, 0); result in [0, pi].
+SPX_MATH_FN double atan2_nonneg(double y, double x) {
+    constexpr double kPi4Hi = 0x1.921fb54442d18p-1, kPi4Lo = 0x1.1a62633145c07p-55;
+    constexpr double kTanPi8 = 0x1.a827999fcef32p-2;  // sqrt 2 - 1
+    const double ax = std::fabs(x);
+    const double mx = std::fmax(ax, y), mn = std::fmin(ax, y);
+    // r = mn / mx in [0, 1]; above tan(pi/8), atan r = pi/4 + atan((r - 1)/(r + 1))
+    const bool big = mn > kTanPi8 * mx;
+    const double t = big ? div_pos(mn - mx, mn + mx) : div_pos(mn, mx);
+    const double z = t * t;
+    // atan t = t + t z sum_{k>=1} (-1)^k z^(k-1) / (2k + 1), k up to 19
+    double p = -1.0 / 39.0;
+    p = std::fma(p, z, 1.0 / 37.0);
+    p = std::fma(p, z, -1.0 / 35.0);
+    p = std::fma(p, z, 1.0 / 33.0);
+    p = std::fma(p, z, -1.0 / 31.0);
+    p = std::fma(p, z, 1.0 / 29.0);
+    p = std::fma(p, z, -1.0 / 27.0);
+    p = std::fma(p, z, 1.0 / 25.0);
+    p = std::fma(p, z, -1.0 / 23.0);
+    p = std::fma(p, z, 1.0 / 21.0);
+    p = std::fma(p, z, -1.0 / 19.0);
+    p = std::fma(p, z, 1.0 / 17.0);
+    p = std::fma(p, z, -1.0 / 15.0);
+    p = std::fma(p, z, 1.0 / 13.0);
+    p = std::fma(p, z, -1.0 / 11.0);
+    p = std::fma(p, z, 1.0 / 9.0);
+    p = std::fma(p, z, -1.0 / 7.0);
+    p = std::fma(p, z, 1.0 / 5.0);
+    p = std::fma(p, z, -1.0 / 3.0);
+    const double at = std::fma(t * z, p, t);
+    // angle of (mx, mn) in [0, pi/4]
+    double th = big ? kPi4Hi + (at + kPi4Lo) : at;
+    // the ratio was |x| / y: pi/2 - th
+    if (y > ax) th = (2.0 * kPi4Hi - th) + 2.0 * kPi4Lo;
+    // second quadrant: pi - th
+    if (x < 0.0) th = (4.0 * kPi4Hi - th) + 4.0 * kPi4Lo;
+    return th;
+}
+
+// cos r and sin(r) / r from z = r^2 >= 0.
+SPX_MATH_FN void expmap_cs(double z, double &cs, double &sc) {
+    if (z <= 1.0) {
+        // cos r = sum_k (-1)^k z^k / (2k)!, sin(r)/r = sum_k (-1)^k z^k / (2k+1)!, k <= 9
+        double c = 1.0 / 6402373705728000.0;  // 1/18!
+        c = std::fma(c, z, -1.0 / 20922789888000.0);
+        c = std::fma(c, z, 1.0 / 87178291200.0);
+        c = std::fma(c, z, -1.0 / 479001600.0);
+        c = std::fma(c, z, 1.0 / 3628800.0);
+        c = std::fma(c, z, -1.0 / 40320.0);
+        c = std::fma(c, z, 1.0 / 720.0);
+        c = std::fma(c, z, -1.0 / 24.0);
+        c = std::fma(c, z, 0.5);
+        cs = std::fma(-c, z, 1.0);
+        double q = 1.0 / 121645100408832000.0;  // 1/19!
+        q = std::fma(q, z, -1.0 / 355687428096000.0);
+        q = std::fma(q, z, 1.0 / 1307674368000.0);
+        q = std::fma(q, z, -1.0 / 6227020800.0);
+        q = std::fma(q, z, 1.0 / 39916800.0);
+        q = std::fma(q, z, -1.0 / 362880.0);
+        q = std::fma(q, z, 1.0 / 5040.0);
+        q = std::fma(q, z, -1.0 / 120.0);
+        q = std::fma(q, z, 1.0 / 6.0);
+        sc = std::fma(-q, z, 1.0);
+    } else {
+        constexpr double kInvPi = 0x1.45f306dc9c883p-2;
+        const double r = sqrt_pos(z);
+        double sn;
+        sincospi_d(r * kInvPi, sn, cs);
+        sc = div_pos(sn, r);
+    }
 }
 
 }  // namespace spx

@@ -52,8 +52,7 @@ constexpr int kYB = SPX_ZM_YB;     // y sites per thread
 // single-input modes only (two staged inputs would double those registers)
 constexpr bool kPrefetch = SPX_ZM_PREFETCH != 0;
 
-constexpr int kTYE = kTYT * kYB;  // tile height in y
-constexpr int kThreads = kTX * kTYT;
+constexpr int kThreads = kTX * kTYT;  // default block: kTX x kTYT threads, tile height kTYT kYB
 
 // ZM_CORRECT: recompute the fields of S^n and S~; ZM_CORRECT_STORED: read the
 // predictor's FP32 bilinear field of S^n; ZM_CORRECT_P: read the predictor's
@@ -79,6 +78,21 @@ constexpr int kThreads = kTX * kTYT;
 // buffer, the velocity store and max |F_gneb| per tile.
 enum ZMode { ZM_FIELD = 0, ZM_PREDICT = 1, ZM_CORRECT = 2, ZM_CORRECT_STORED = 3, ZM_CORRECT_P = 4, ZM_BIL = 5,
              ZM_MIN_FORCE = 7, ZM_ENERGY = 8, ZM_GNEB_A2 = 9, ZM_GNEB_C2 = 10 };
+
+// Block size of a mode on a shape.  The GNEB passes run 256-thread blocks
+// (two per CU at their register use) whose tile width is chosen per lattice
+// (zp.txw: 64 x 4, 32 x 8 or 16 x 16 sites, so that x extents such as 48 and
+// 96 fill every lane); the two-cell 4-shell shape needs all 256 registers
+// there and keeps the default block.  The other modes use the engine default
+// and 64-wide tiles.
+constexpr bool zm_gneb(int mode) { return mode == ZM_GNEB_A2 || mode == ZM_GNEB_C2; }
+constexpr int zm_block(int mode, int kind) { return zm_gneb(mode) && kind != SHAPE_SC_4SH ? 256 : kThreads; }
+
+// Tiles of one image for a block size and tile width.
+int zm_tiles(const Grid &g, int zch, int block, int txw) {
+    const int rows = block / txw * kYB;
+    return ((g.Lx + txw - 1) / txw) * ((g.Ly + rows - 1) / rows) * ((g.Lz + zch - 1) / zch);
+}
 
 template <typename T, int NW>
 struct ZWeights {
@@ -108,8 +122,10 @@ struct ZArgs {
     int nzc, nimg;
     int64_t bstride;
     // 1: tiles are dealt to the XCDs in contiguous runs (set by the launcher
-    // when every tile of the grid is resident at once)
+    // when every tile of the grid is resident at once, or with imgfast)
     int xcd;
+    // 1: the image index is the fastest of the tile decomposition
+    int imgfast;
     const double *S0alt;
     const double *sel, *skip;
     // ZM_MIN_FORCE: force [3][N]; partials of the modes that reduce per tile
@@ -166,9 +182,15 @@ __device__ __forceinline__ int zwrap(int c, int L, int per, bool &ok) {
     return c < 0 ? c + L : c;
 }
 
-template <int KIND, typename T, bool ISO, int MODE>
-__global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunConst hc,
-                                                     ZWeights<T, ISO ? make_shape(KIND).nshell : 9 * make_shape(KIND).nb> W) {
+template <int KIND, typename T, bool ISO, int MODE, int TXW>
+__global__ __launch_bounds__(zm_block(MODE, KIND)) void k_zmarch(ZArgs g, Onsite os, HeunConst hc,
+                                                           ZWeights<T, ISO ? make_shape(KIND).nshell : 9 * make_shape(KIND).nb> W) {
+    // block size and tile shape of this instantiation (they shadow the
+    // engine-wide defaults): TXW lanes along x, the other threads along y
+    constexpr int kThreads = zm_block(MODE, KIND);
+    constexpr int kTX = TXW;
+    constexpr int kTYE = kThreads / TXW * kYB;
+    static_assert(kThreads % TXW == 0 && (TXW & (TXW - 1)) == 0, "tile width: a power of two dividing the block");
     constexpr int NSUB = ShapeC<KIND>::t.nsub, NB = ShapeC<KIND>::t.nb;
     constexpr int RX = ShapeC<KIND>::t.rx, RY = ShapeC<KIND>::t.ry;
     constexpr int DZLO = ShapeC<KIND>::t.dzlo, DZHI = ShapeC<KIND>::t.dzhi;
@@ -185,15 +207,27 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // are dealt to the 8 XCDs round-robin; with g.xcd each XCD instead gets
     // one contiguous run of tiles, so the tiles that share halo rows and
     // march through the same planes at the same time share that XCD's L2.
+    // With g.imgfast the image index runs fastest instead, so that the
+    // launches of one spatial tile over all images are adjacent: with the
+    // contiguous XCD order they run together on one XCD, and the neighbouring
+    // images that each block reads besides its own come from that L2.
     const unsigned nbx = (unsigned)((g.Lx + kTX - 1) / kTX), nby = (unsigned)((g.Ly + kTYE - 1) / kTYE);
     const unsigned ntile = gridDim.x;
     unsigned tile = blockIdx.x;
     if (g.xcd && (ntile & 7u) == 0) tile = (tile & 7u) * (ntile >> 3) + (tile >> 3);
-    const int x0 = (int)(tile % nbx) * kTX;
-    const int y0 = (int)((tile / nbx) % nby) * kTYE;
-    const int zb = (int)(tile / (nbx * nby));
-    const int img = zb / g.nzc;
-    const int zs = (zb - img * g.nzc) * g.zch;
+    unsigned stile;  // spatial tile of the image: x tile + nbx (y tile + nby z chunk)
+    int img;
+    if (g.imgfast) {
+        img = (int)(tile % (unsigned)g.nimg);
+        stile = tile / (unsigned)g.nimg;
+    } else {
+        const unsigned per_img = nbx * nby * (unsigned)g.nzc;
+        img = (int)(tile / per_img);
+        stile = tile - (unsigned)img * per_img;
+    }
+    const int x0 = (int)(stile % nbx) * kTX;
+    const int y0 = (int)((stile / nbx) % nby) * kTYE;
+    const int zs = (int)(stile / (nbx * nby)) * g.zch;
     // image offset of the launch's image in its buffer (the GNEB second pass
     // launches over the interior images only: launch image k is image
     // gimg0 + k)
@@ -224,12 +258,34 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     // reads eta when the noise comes from a pre-pass.
     constexpr bool kEpiPre = MODE == ZM_CORRECT_P || MODE == ZM_PREDICT || MODE == ZM_MIN_FORCE ||
                              MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2;
-    constexpr int NE = (MODE == ZM_CORRECT_P || MODE == ZM_MIN_FORCE || MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2) ? 6
+    constexpr int NE = MODE == ZM_GNEB_A2 ? 9
+                       : (MODE == ZM_CORRECT_P || MODE == ZM_MIN_FORCE || MODE == ZM_GNEB_C2) ? 6
                        : MODE == ZM_PREDICT ? 3 : 1;
     // image of the launch in its instance (GNEB two-pass modes)
     const int gimg = img + g.gimg0;
-    double epi[kYB][NSUB][NE];
-    auto fetch_epi = [&](int o) __attribute__((always_inline)) {
+    // ZM_GNEB_C2: the image's tangent weights w+-, c_n / |tau| (the spring or
+    // climbing-image coefficient over the tangent norm) and the velocity
+    // factor (VP projection + dt / m), uniform over the block
+    double gwp = 0.0, gwm = 0.0, gcn = 0.0, gvf = 0.0;
+    if constexpr (MODE == ZM_GNEB_C2) {
+        const double *im = g.gims + (int64_t)gimg * g.gis.n;
+        gwp = im[g.gis.wp];
+        gwm = im[g.gis.wm];
+        const double tn = im[g.gis.tn];
+        gcn = tn > 0.0 ? im[g.gis.coef] / tn : 0.0;
+        gvf = g.gst[g.gis.proj] + g.gdt / g.gmass;
+    }
+    // kDeep: the staged plane and the epilogue inputs are fetched two march
+    // iterations ahead into two register sets, whose names stay static
+    // because the march loop is unrolled by two (passes whose iterations wait
+    // on memory longer than they compute; about 30 more registers, which the
+    // two-cell 4-shell shape does not have)
+    constexpr bool kDeep =
+        kPrefetch && NIN == 1 && (MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2) && KIND != SHAPE_SC_4SH;
+    constexpr int NSET = kDeep ? 2 : 1;
+    double epi[NSET][kYB][NSUB][NE];
+    auto fetch_epi = [&](int o, auto es) __attribute__((always_inline)) {
+        constexpr int E = decltype(es)::value;
         if (o < 0 || o >= nout) return;  // uniform over the block
         if (MODE == ZM_PREDICT && !(hc.noise && g.eload)) return;
         if (MODE == ZM_MIN_FORCE && g.mmethod == 3) return;   // Adam reads nothing here
@@ -241,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 const int y = y0 + ty * kYB + yb;
                 if (x >= g.Lx || y >= g.Ly) continue;
                 const int64_t i = (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * (zs + o));
-                double *e = epi[yb][a];
+                double *e = epi[E][yb][a];
                 if constexpr (MODE == ZM_CORRECT_P) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) e[c] = g.pload[c * N + i];
@@ -253,11 +309,17 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                     for (int c = 0; c < 3; ++c) e[c] = g.eload[c * N + i];
                 } else if constexpr (MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2) {
                     // the neighbouring images (zero where there is none)
+                    // and, for A2, the interior image's velocity
                     const bool nx = gimg < g.gntot - 1, pv = gimg > 0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         e[c] = nx ? S0[g.bstride + c * N + i] : 0.0;
                         e[3 + c] = pv ? S0[c * N + i - g.bstride] : 0.0;
+                    }
+                    if constexpr (MODE == ZM_GNEB_A2) {
+                        const bool vel = nx && pv && !g.gstring;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) e[6 + c] = vel ? g.gV[(int64_t)gimg * g.bstride + c * N + i] : 0.0;
                     }
                 } else if constexpr (MODE == ZM_MIN_FORCE) {
                     if (g.mmethod == 0) {
@@ -333,12 +395,13 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
     constexpr int BUF_STRIDE = NIN * NSUB * 3 * PLANE, IN_STRIDE = NSUB * 3 * PLANE;
     // plane q (z = zs + DZLO + q) in two halves: fetch into registers, then
     // commit to LDS buffer `buf`
-    double pre[NLD][NIN][3];
+    double pre[NSET][NLD][NIN][3];
     // FP64 spins of the thread's own sites for the last DZHI + 1 staged
     // planes: own[0] holds the plane that the current iteration finishes
     constexpr bool kOwn = kPrefetch && NIN == 1 && MODE != ZM_BIL;
     double own[kOwn ? DZHI + 1 : 1][NI][3];
-    auto keep_own = [&]() __attribute__((always_inline)) {
+    auto keep_own = [&](auto ps) __attribute__((always_inline)) {
+        constexpr int P = decltype(ps)::value;
         if constexpr (kOwn) {
 #pragma unroll
             for (int r = 0; r < DZHI; ++r)
@@ -349,10 +412,11 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
             for (int k = 0; k < NI; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) own[DZHI][k][c] = pre[k][0][c];
+                for (int c = 0; c < 3; ++c) own[DZHI][k][c] = pre[P][k][0][c];
         }
     };
-    auto fetch_plane = [&](int q) __attribute__((always_inline)) {
+    auto fetch_plane = [&](int q, auto ps) __attribute__((always_inline)) {
+        constexpr int P = decltype(ps)::value;
         bool zok = true;
         const int gz = zwrap(zs + DZLO + q, g.Lz, g.per[2], zok);
         const int64_t zoff = plane_stride * gz;
@@ -363,10 +427,11 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
             for (int k = 0; k < NIN; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) pre[t][k][c] = ok ? src[k][c * N + j] : 0.0;
+                for (int c = 0; c < 3; ++c) pre[P][t][k][c] = ok ? src[k][c * N + j] : 0.0;
         }
     };
-    auto commit_plane = [&](int buf) __attribute__((always_inline)) {
+    auto commit_plane = [&](int buf, auto ps) __attribute__((always_inline)) {
+        constexpr int P = decltype(ps)::value;
 #pragma unroll
         for (int t = 0; t < NLD; ++t) {
             if (t < NI || ((slot_ok >> t) & 1u)) {
@@ -374,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                 for (int k = 0; k < NIN; ++k)
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        lds_flat[buf * BUF_STRIDE + k * IN_STRIDE + c * PLANE + lds_off[t]] = (T)pre[t][k][c];
+                        lds_flat[buf * BUF_STRIDE + k * IN_STRIDE + c * PLANE + lds_off[t]] = (T)pre[P][t][k][c];
             }
         }
     };
@@ -567,15 +632,6 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         if constexpr (MODE == ZM_GNEB_A2 || MODE == ZM_GNEB_C2) {
             if (!valid) return;
             const bool interior = gimg > 0 && gimg < g.gntot - 1, has_next = gimg < g.gntot - 1;
-            const double *im = g.gims + (int64_t)gimg * g.gis.n;
-            double wp = 0.0, wm = 0.0, tn = 0.0, cf = 0.0, proj = 0.0;
-            if constexpr (MODE == ZM_GNEB_C2) {
-                wp = im[g.gis.wp];
-                wm = im[g.gis.wm];
-                tn = im[g.gis.tn];
-                cf = im[g.gis.coef];
-                proj = g.gst[g.gis.proj];
-            }
 #pragma unroll
             for (int a = 0; a < NSUB; ++a) {
                 const double *sp = so[a];
@@ -597,8 +653,9 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                         const double *q = e[a];
                         const double c0 = sp[1] * q[2] - sp[2] * q[1], c1 = sp[2] * q[0] - sp[0] * q[2],
                                      c2 = sp[0] * q[1] - sp[1] * q[0];
+                        const double cc = c0 * c0 + c1 * c1 + c2 * c2;
                         const double th =
-                            atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), sp[0] * q[0] + sp[1] * q[1] + sp[2] * q[2]);
+                            atan2_nonneg(cc > 0.0 ? sqrt_pos(cc) : 0.0, sp[0] * q[0] + sp[1] * q[1] + sp[2] * q[2]);
                         gacc[kThreads + threadIdx.x] += th * th;
                     }
                 }
@@ -619,14 +676,9 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
                     bp[c] -= bss * sp[c];
                 }
                 if constexpr (MODE == ZM_GNEB_A2) {
-                    // the velocity is read here rather than a plane ahead:
-                    // the registers matter more than its latency
-                    double vv[3] = {0.0, 0.0, 0.0};
-                    if (!g.gstring) {
-                        const double *V = g.gV + (int64_t)gimg * g.bstride;
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) vv[c] = V[c * N + i[a]];
-                    }
+                    // the velocity, fetched a plane ahead (zero for the
+                    // string method)
+                    const double vv[3] = {e[a][6], e[a][7], e[a][8]};
                     double d9[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -643,18 +695,18 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
                     for (int k = 0; k < 9; ++k) gacc[(2 + k) * kThreads + threadIdx.x] += d9[k];
                 } else {
-                    // F_gneb = F + c tau^, VP step, exponential map
+                    // F_gneb = F + c_n tau / |tau|, VP step, exponential map
                     double u[3], vn[3], f2 = 0.0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const double tau = wp * ap[c] + wm * bp[c];
-                        const double th = tn > 0.0 ? tau / tn : 0.0;
-                        const double ft = F[c] + cf * th;
+                        const double tau = gwp * ap[c] + gwm * bp[c];
+                        const double ft = F[c] + gcn * tau;
                         f2 += ft * ft;
-                        vn[c] = g.gstring ? 0.0 : proj * ft + (g.gdt / g.gmass) * ft;
+                        vn[c] = g.gstring ? 0.0 : gvf * ft;
                         u[c] = g.gstring ? g.gdt * F[c] : g.gdt * vn[c];
                     }
-                    gX[0] = fmax(gX[0], sqrt(f2));
+                    // max |F_gneb|^2 here, its square root once per tile
+                    gX[0] = fmax(gX[0], f2);
                     if (!g.gstring) {
                         double *V = g.gV + (int64_t)gimg * g.bstride;
 #pragma unroll
@@ -663,17 +715,17 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
                         for (int c = 0; c < 3; ++c) u[c] -= us * sp[c];
                     }
-                    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    // exp_S(u) = cos|u| S + (sin|u| / |u|) u, renormalised;
+                    // u = 0 leaves S as it is
+                    const double uz = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                    double cs, sc;
+                    expmap_cs(uz, cs, sc);
                     double o[3];
-                    if (un == 0.0) {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) o[c] = sp[c];
-                    } else {
-                        const double cs = cos(un), sn = sin(un) / un;
+                    for (int c = 0; c < 3; ++c) o[c] = cs * sp[c] + sc * u[c];
+                    normalise3(o);
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) o[c] = cs * sp[c] + sn * u[c];
-                        normalise3(o);
-                    }
+                    for (int c = 0; c < 3; ++c) o[c] = uz == 0.0 ? sp[c] : o[c];
                     double *On = ((g.sel && *g.sel != 0.0) ? g.O1 : g.O0) + (int64_t)gimg * g.bstride;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) On[c * N + i[a]] = o[c];
@@ -780,20 +832,40 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 
     // acc[k] holds output plane o = q - (D-1) + k after input plane q has been
     // pushed; input plane q feeds slot k = dzhi - dz of every bond.
+    // Register sets: with kDeep, iteration q stages plane q + 2 into set
+    // q & 1 and commits plane q + 1 from set (q + 1) & 1; the epilogue inputs
+    // of output plane o live in set o & 1.  Otherwise one set, one ahead.
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
     if constexpr (kPrefetch && NIN == 1) {
-        fetch_plane(0);
-        commit_plane(0);
-        keep_own();
+        fetch_plane(0, I0{});
+        commit_plane(0, I0{});
+        keep_own(I0{});
+        if constexpr (kDeep) {
+            if (1 < nq) fetch_plane(1, I1{});
+        }
     } else {
         load_plane(0, 0);
     }
-    if constexpr (kEpiPre) fetch_epi(-(D - 1));
+    if constexpr (kEpiPre) {
+        if constexpr (kDeep) {
+            fetch_epi(1 - D, std::integral_constant<int, (1 - D) & 1>{});
+            fetch_epi(2 - D, std::integral_constant<int, (2 - D) & 1>{});
+        } else {
+            fetch_epi(-(D - 1), I0{});
+        }
+    }
     __syncthreads();
-#pragma unroll 1
-    for (int q = 0; q < nq; ++q) {
-        const int buf = q & 1;
-        if constexpr (kPrefetch && NIN == 1) {
-            if (q + 1 < nq) fetch_plane(q + 1);
+    auto march = [&](int q, auto qp) __attribute__((always_inline)) {
+        // QP = q & 1 with kDeep, else 0
+        constexpr int QP = decltype(qp)::value;
+        // register set of this iteration's output plane o = q - (D - 1)
+        constexpr int ES = kDeep ? (QP ^ ((D - 1) & 1)) : 0;
+        const int buf = kDeep ? QP : (q & 1);
+        if constexpr (kDeep) {
+            if (q + 2 < nq) fetch_plane(q + 2, qp);
+        } else if constexpr (kPrefetch && NIN == 1) {
+            if (q + 1 < nq) fetch_plane(q + 1, I0{});
         } else {
             if (q + 1 < nq) load_plane(q + 1, buf ^ 1);
         }
@@ -909,7 +981,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
                         for (int c = 0; c < 3; ++c) fin[yb][in][c] = acc[0][yb][a][c][in];
 #pragma unroll
-                    for (int k = 0; k < NE; ++k) ef[yb][k] = kEpiPre ? epi[yb][a][k] : 0.0;
+                    for (int k = 0; k < NE; ++k) ef[yb][k] = kEpiPre ? epi[ES][yb][a][k] : 0.0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) sf[yb][c] = kOwn ? own[0][a * kYB + yb][c] : 0.0;
                 }
@@ -949,7 +1021,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
                         for (int c = 0; c < 3; ++c) fin[yb][a][in][c] = acc[0][yb][a][c][in];
 #pragma unroll
-                    for (int k = 0; k < NE; ++k) ef[yb][a][k] = kEpiPre ? epi[yb][a][k] : 0.0;
+                    for (int k = 0; k < NE; ++k) ef[yb][a][k] = kEpiPre ? epi[ES][yb][a][k] : 0.0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) sf[yb][a][c] = kOwn ? own[0][a * kYB + yb][c] : 0.0;
                 }
@@ -993,13 +1065,28 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
 #pragma unroll
                     for (int in = 0; in < NIN; ++in) acc[D - 1][yb][a][c][in] = T(0);
         if constexpr (kPrefetch && NIN == 1) {
-            if (q + 1 < nq) commit_plane(buf ^ 1);
-            keep_own();  // every iteration, so that own[0] stays aligned
+            constexpr int CP = kDeep ? (QP ^ 1) : 0;  // set holding plane q + 1
+            if (q + 1 < nq) commit_plane(buf ^ 1, std::integral_constant<int, CP>{});
+            keep_own(std::integral_constant<int, CP>{});  // every iteration, so that own[0] stays aligned
         }
-        // the next iteration's output plane: its per-site inputs are in
-        // flight across the barrier and that iteration's stencil
-        if constexpr (kEpiPre) fetch_epi(q - D + 2);
+        // the per-site inputs of a later output plane are in flight across
+        // the barrier and the next iteration's stencil (two of them with
+        // kDeep: output o + 2 reuses the set that o just released)
+        if constexpr (kEpiPre) {
+            if constexpr (kDeep) fetch_epi(q - D + 3, std::integral_constant<int, ES>{});
+            else fetch_epi(q - D + 2, I0{});
+        }
         __syncthreads();
+    };
+    if constexpr (kDeep) {
+#pragma unroll 1
+        for (int q = 0; q < nq; q += 2) {
+            march(q, I0{});
+            if (q + 1 < nq) march(q + 1, I1{});
+        }
+    } else {
+#pragma unroll 1
+        for (int q = 0; q < nq; ++q) march(q, I0{});
     }
     if constexpr (MODE == ZM_MIN_FORCE) {
         // fixed-order block reductions (the first a maximum), one set per tile
@@ -1030,7 +1117,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
         __shared__ double gred[NV][kThreads / 64];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            double v = MODE == ZM_GNEB_C2 ? gX[0] : gacc[k * kThreads + threadIdx.x];
+            double v = MODE == ZM_GNEB_C2 ? sqrt(gX[0]) : gacc[k * kThreads + threadIdx.x];
             if constexpr (MODE == ZM_GNEB_C2) {
 #pragma unroll
                 for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
@@ -1044,8 +1131,7 @@ __global__ __launch_bounds__(kThreads) void k_zmarch(ZArgs g, Onsite os, HeunCon
             double t = 0.0;
             for (int w = 0; w < kThreads / 64; ++w)
                 t = MODE == ZM_GNEB_C2 ? fmax(t, gred[threadIdx.x][w]) : t + gred[threadIdx.x][w];
-            const int tile_in_img = (int)tile - img * (int)(nbx * nby) * g.nzc;
-            g.gpart[((size_t)g.gitem0 + (size_t)gimg * g.gipi + tile_in_img) * 11 + threadIdx.x] = t;
+            g.gpart[((size_t)g.gitem0 + (size_t)gimg * g.gipi + stile) * 11 + threadIdx.x] = t;
         }
     }
     if constexpr (MODE == ZM_ENERGY) {
@@ -1168,13 +1254,14 @@ int device_cus() {
     return n;
 }
 
-template <int KIND, typename T, bool ISO, int MODE>
-hipError_t launch_kind(const ZPlan &zp, const ZArgs &a0, const Onsite &os, const HeunConst &hc, hipStream_t st) {
+template <int KIND, typename T, bool ISO, int MODE, int TXW>
+hipError_t launch_tile(const ZPlan &zp, const ZArgs &a0, const Onsite &os, const HeunConst &hc, hipStream_t st) {
     constexpr int NB = make_shape(KIND).nb;
     constexpr int NW = ISO ? make_shape(KIND).nshell : 9 * NB;
+    constexpr int kBlock = zm_block(MODE, KIND), kRows = kBlock / TXW * kYB;
     ZWeights<T, NW> W;
     for (int k = 0; k < NW; ++k) W.w[k] = (T)(sizeof(T) == 4 ? (double)zp.wf[k] : zp.wd[k]);
-    const int64_t ntile = (int64_t)((a0.Lx + kTX - 1) / kTX) * ((a0.Ly + kTYE - 1) / kTYE) * a0.nzc * a0.nimg;
+    const int64_t ntile = (int64_t)((a0.Lx + TXW - 1) / TXW) * ((a0.Ly + kRows - 1) / kRows) * a0.nzc * a0.nimg;
     if (ntile > 0x7fffffff) return hipErrorInvalidValue;
     // a grid whose tiles are all resident at once (two blocks per CU) gets
     // the XCD-contiguous tile order: the x/y halo rows shared by concurrent
@@ -1183,9 +1270,19 @@ hipError_t launch_kind(const ZPlan &zp, const ZArgs &a0, const Onsite &os, const
     // the round-robin order, which measured faster there.
     ZArgs a = a0;
     const int ncu = device_cus();
-    a.xcd = (ncu > 0 && ntile <= 2 * (int64_t)ncu) ? 1 : 0;
-    k_zmarch<KIND, T, ISO, MODE><<<(unsigned)ntile, kThreads, 0, st>>>(a, os, hc, W);
+    a.xcd = (a0.imgfast || (ncu > 0 && ntile <= 2 * (int64_t)ncu)) ? 1 : 0;
+    k_zmarch<KIND, T, ISO, MODE, TXW><<<(unsigned)ntile, kBlock, 0, st>>>(a, os, hc, W);
     return hipGetLastError();
+}
+
+template <int KIND, typename T, bool ISO, int MODE>
+hipError_t launch_kind(const ZPlan &zp, const ZArgs &a, const Onsite &os, const HeunConst &hc, hipStream_t st) {
+    if constexpr (zm_gneb(MODE)) {
+        if (zp.txw == 32) return launch_tile<KIND, T, ISO, MODE, 32>(zp, a, os, hc, st);
+        if (zp.txw == 16) return launch_tile<KIND, T, ISO, MODE, 16>(zp, a, os, hc, st);
+    }
+    if (zp.txw != kTX) return hipErrorInvalidValue;
+    return launch_tile<KIND, T, ISO, MODE, kTX>(zp, a, os, hc, st);
 }
 
 template <typename T, bool ISO, int MODE>
@@ -1345,13 +1442,30 @@ hipError_t zmarch_min_force(const ZPlan &zp, const Grid &g, const Onsite &os, co
     return launch_mode<double, false, ZM_MIN_FORCE>(zp, a, os, hc, st);
 }
 
-int zmarch_tiles(const ZPlan &zp, const Grid &g) {
-    return ((g.Lx + kTX - 1) / kTX) * ((g.Ly + kTYE - 1) / kTYE) * ((g.Lz + zp.zch - 1) / zp.zch);
+int zmarch_tiles(const ZPlan &zp, const Grid &g) { return zm_tiles(g, zp.zch, kThreads, kTX); }
+
+int zmarch_gneb_tiles(const ZPlan &zp, const Grid &g) {
+    return zm_tiles(g, zp.zch, zm_block(ZM_GNEB_A2, zp.kind), zp.txw);
+}
+
+int zmarch_gneb_width(const ZPlan &zp, const Grid &g) {
+    // the width with the fewest padded sites in x and y (the wider on ties)
+    int best = kTX;
+    int64_t area = -1;
+    for (int w = kTX; w >= 16; w >>= 1) {
+        const int rows = zm_block(ZM_GNEB_A2, zp.kind) / w * kYB;
+        const int64_t a = (int64_t)((g.Lx + w - 1) / w) * w * (((g.Ly + rows - 1) / rows) * rows);
+        if (area < 0 || a < area) {
+            area = a;
+            best = w;
+        }
+    }
+    return best;
 }
 
 hipError_t zmarch_gneb_pass(int pass, const ZPlan &zp, const Grid &g, const Onsite &os, const GnebPassArgs &ga,
                             hipStream_t st) {
-    if (zp.prec != 0 || ga.n_img < 3 || zmarch_tiles(zp, g) > ga.items_per_img) return hipErrorInvalidValue;
+    if (zp.prec != 0 || ga.n_img < 3 || zmarch_gneb_tiles(zp, g) > ga.items_per_img) return hipErrorInvalidValue;
     ZArgs a = make_args(zp, g);
     a.bstride = 3 * g.N;
     a.gntot = ga.n_img;
@@ -1374,6 +1488,7 @@ hipError_t zmarch_gneb_pass(int pass, const ZPlan &zp, const Grid &g, const Onsi
     a.gpart = ga.partial;
     a.gitem0 = ga.item0;
     a.gipi = ga.items_per_img;
+    a.imgfast = 1;
     HeunConst hc{};
     if (pass == 0) {
         if (zp.iso) return launch_mode<double, true, ZM_GNEB_A2>(zp, a, os, hc, st);

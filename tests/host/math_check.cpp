@@ -63,7 +63,66 @@ int main() {
                                  : ldexp(1.0 + ldexp((double)(rng() >> 11), -53), (int)(rng() % 200) - 100);
         mrsq = fmax(mrsq, ulp_err(spx::rsqrt_pos(v), 1.0L / sqrtl((long double)v)));
     }
+    // a / b over random magnitudes
+    double mdiv = 0;
+    for (int k = 0; k < 1000000; ++k) {
+        const double a = ldexp(1.0 + ldexp((double)(rng() >> 11), -53), (int)(rng() % 200) - 100) * ((k & 1) ? -1 : 1);
+        const double b = ldexp(1.0 + ldexp((double)(rng() >> 11), -53), (int)(rng() % 200) - 100);
+        mdiv = fmax(mdiv, ulp_err(spx::div_pos(a, b), (long double)a / (long double)b));
+    }
+    // angle between unit vectors from (|a x b|, a.b): random directions, pairs
+    // close together (angles down to 1e-9), nearly opposite, and the octant
+    // boundaries of the reduction
+    std::normal_distribution<double> nd;
+    double mang = 0;
+    long nang = 0;
+    auto check_angle = [&](double y, double x) {
+        mang = fmax(mang, ulp_err(spx::atan2_nonneg(y, x), atan2l((long double)y, (long double)x)));
+        ++nang;
+    };
+    for (int k = 0; k < 1000000; ++k) {
+        double a[3] = {nd(rng), nd(rng), nd(rng)}, b[3];
+        const double eps = (k % 4 == 0) ? 1.0 : ldexp(1.0, -(int)(rng() % 30));
+        for (int c = 0; c < 3; ++c) b[c] = ((k % 4 == 3) ? -a[c] : a[c]) + eps * nd(rng);
+        const double c0 = a[1] * b[2] - a[2] * b[1], c1 = a[2] * b[0] - a[0] * b[2], c2 = a[0] * b[1] - a[1] * b[0];
+        check_angle(sqrt(c0 * c0 + c1 * c1 + c2 * c2), a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+    }
+    const double tp8 = 0.41421356237309503;
+    for (int d = -2000; d <= 2000; ++d) {
+        const double r = tp8 + d * 1e-16, q = 1.0 + d * 1e-16;
+        check_angle(r, 1.0); check_angle(1.0, r); check_angle(r, -1.0); check_angle(1.0, -r);
+        check_angle(q, 1.0); check_angle(1.0, q); check_angle(q, -1.0);
+    }
+    check_angle(0.0, 1.0); check_angle(0.0, -1.0); check_angle(1.0, 0.0); check_angle(1.0, -0.0);
+    // cos r and sin(r)/r from z = r^2: steps of the exponential map (0 to a few rad)
+    // (series branch z <= 1: cos, and sin r / r relative; beyond: the
+    // absolute errors of cos r and r (sin r / r) = sin r, the terms of the
+    // retraction, in 2^-53 units)
+    double mcs = 0, msc = 0, mcs_far = 0, msn_far = 0;
+    for (int k = 0; k < 1000000; ++k) {
+        const double r = (k & 1) ? ldexp((double)(rng() >> 11), -53) * 4.0 : ldexp((double)(rng() >> 11), -53 - (int)(rng() % 40));
+        const double z = r * r;
+        double cs, sc;
+        spx::expmap_cs(z, cs, sc);
+        const long double rl = sqrtl((long double)z);
+        const double ecs = (double)(fabsl((long double)cs - cosl(rl)) / ldexpl(1.0L, -53));
+        if (z <= 1.0) {
+            mcs = fmax(mcs, ecs);
+            msc = fmax(msc, ulp_err(sc, rl == 0.0L ? 1.0L : sinl(rl) / rl));
+        } else {
+            mcs_far = fmax(mcs_far, ecs);
+            msn_far = fmax(msn_far, (double)(fabsl((long double)sc * rl - sinl(rl)) / ldexpl(1.0L, -53)));
+        }
+    }
+    {
+        double cs, sc;
+        spx::expmap_cs(0.0, cs, sc);
+        if (cs != 1.0 || sc != 1.0) mcs = INFINITY;
+    }
     std::printf("log %.3f %ld\nsqrt %.3f %ld\nsinpi_abs %.3f %ld\ncospi_abs %.3f %ld\nrsqrt %.3f 2000000\n", mlog, n, msq,
                 n, msin, n, mcos, n, mrsq);
+    std::printf("div %.3f 1000000\natan2 %.3f %ld\nexpmap_cos_abs %.3f 1000000\nexpmap_sinc %.3f 1000000\n", mdiv, mang,
+                nang, mcs, msc);
+    std::printf("expmap_far_cos_abs %.3f 1000000\nexpmap_far_sin_abs %.3f 1000000\n", mcs_far, msn_far);
     return 0;
 }

@@ -180,3 +180,41 @@ def test_gneb_two_pass_and_item_instances_match_oracle():
             np.testing.assert_allclose(s["E"], E, rtol=1e-10, atol=1e-12)
             np.testing.assert_allclose(s["dist"], dist, rtol=1e-10, atol=1e-12)
             assert s["ci_index"] == ci and s["iterations"] == it + 1
+
+
+def test_gneb_two_pass_tile_widths_match_oracle():
+    # three-shell instances (256-thread blocks) on lattices whose padded area
+    # is smallest at each tile width: 100 x 4 -> 64 x 4 tiles, 20 x 19 ->
+    # 32 x 8 tiles (ragged x and y), 14 x 30 -> 16 x 16 tiles (ragged x and
+    # y); odd image counts, so the image-fastest tile order wraps the XCD runs
+    # unevenly, open and periodic faces
+    import torch
+    from paper_2605_26016_amd import spx
+
+    def three(L, periodic):
+        return Workload(name="t", L=L, periodic=periodic, J_shell=(1.0, -0.164, -0.082), K=0.05,
+                        B=(0.0, 0.0, 0.3), field_prec="fp64")
+
+    cases = [(three((100, 4, 5), (1, 0, 1)), 5, 31), (three((20, 19, 7), (1, 1, 0)), 7, 32),
+             (three((14, 30, 5), (0, 0, 0)), 6, 33)]
+    hams, bufs, refs = [], [], []
+    for w, n_img, seed in cases:
+        A, B = endpoints(w, seed)
+        Y0 = oracle.geodesic_path(A, B, n_img)
+        hams.append(gpu_hamiltonian(w))
+        bufs.append(to_dev(Y0))
+        refs.append((oracle_model(w), oracle.GnebState(Y0, k_spring=1.0, dt=0.05, mass=1.0, ci_mode=1,
+                                                        ci_on_below=3.0)))
+    g = spx.gneb_create(hams, bufs, spring_k=1.0, vp_dt=0.05, vp_mass=1.0, ci_mode=1, ci_on_below=3.0)
+    for it in range(6):
+        spx.gneb_step(g, 1)
+        torch.cuda.synchronize()
+        for k, (m, st) in enumerate(refs):
+            E, dist, fmax, ci = oracle.gneb_iterate(m, st)
+            got = bufs[k].cpu().numpy()
+            err = float(np.max(np.abs(got - st.Y)))
+            assert err <= 1e-9, (it, k, err)
+            s = spx.gneb_get_stats(g, k)
+            np.testing.assert_allclose(s["E"], E, rtol=1e-10, atol=1e-12)
+            np.testing.assert_allclose(s["dist"], dist, rtol=1e-10, atol=1e-12)
+            assert s["ci_index"] == ci and s["iterations"] == it + 1

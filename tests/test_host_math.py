@@ -6,7 +6,13 @@ arguments of ~4M Philox words (random, both ends of the u32 range, and the
 reduction boundaries) and 2M squared norms.  Bounds: log within 2 ulp, sqrt
 and 1/sqrt within 1 ulp (+ rounding slack), sin(pi t) and cos(pi t) within
 2^-52 absolute.  Together these keep the normals within a few ulp of the
-libm-based oracle (whose own 2 pi u rounding is of the same size)."""
+libm-based oracle (whose own 2 pi u rounding is of the same size).
+
+The GNEB passes' functions are checked the same way: the quotient (half an
+ulp), the angle between two unit vectors from (|a x b|, a.b) over random,
+nearly parallel and nearly opposite pairs and the reduction's octant
+boundaries (3 ulp), and cos r, sin(r)/r of the exponential map from r^2
+(1.5 ulp up to r = 1, a few 2^-53 absolute up to r = 4)."""
 import os
 import shutil
 import subprocess
@@ -16,7 +22,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_noise_math_accuracy(tmp_path):
+def test_device_math_accuracy(tmp_path):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ not available")
@@ -31,3 +37,11 @@ def test_noise_math_accuracy(tmp_path):
     assert res["rsqrt"] <= 1.01
     assert res["sinpi_abs"] <= 2.0
     assert res["cospi_abs"] <= 2.0
+    # GNEB: image distances and the exponential-map retraction
+    assert res["div"] <= 0.51
+    assert res["atan2"] <= 3.0
+    assert res["expmap_cos_abs"] <= 1.5
+    assert res["expmap_sinc"] <= 1.5
+    # beyond |u| = 1 (up to 4 rad) the angle goes through u / pi in one rounding
+    assert res["expmap_far_cos_abs"] <= 8.0
+    assert res["expmap_far_sin_abs"] <= 8.0
