@@ -51,25 +51,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(paths=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in paths:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, heun_mode: int, zchunk: int):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
-    was taken on the current kernel source, on this workload and in this
-    launch configuration (else None)."""
+def measured_traffic(kernel: str, workload: str, heun_mode, zchunk):
+    """HBM bytes per launch (per iteration for the GNEB entry) from the
+    committed rocprofv3 --pmc summary, if it was taken on the current source
+    of the files it lists, on this workload and in this launch configuration
+    (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
     e = d.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash(e.get("sources", KERNEL_SOURCES)):
         return None
     if (e.get("workload"), e.get("heun_mode"), e.get("zchunk")) != (workload, heun_mode, zchunk):
         return None
@@ -158,7 +159,8 @@ def gneb_workload(args):
     out.update({"value": rate, "unit": "spin-image-iterations/s", "steps": n_it, "warmup": 5,
                 "ms_per_step": ms / n_it,
                 "roofline": {"bound": "hbm", "achieved": rate * GNEB_BYTES / 1e9, "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": rate * GNEB_BYTES / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                             "unit": "GB/s", "frac": rate * GNEB_BYTES / 1e9 / HBM_PEAK_GBS,
+                             "traffic": measured_traffic("gneb_iteration", "sc_frustrated_gneb", None, 16),
                              "kernel": "GNEB iteration (two z-march passes + reductions)",
                              "bytes_per_spin_image_iteration": GNEB_BYTES,
                              "bytes_per_spin_image_iteration_of_the_passes": GNEB_PASS_BYTES,
