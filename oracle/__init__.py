@@ -103,11 +103,11 @@ def lib():
         L.or_net_nparams.restype = C.c_long
         L.or_net_nparams.argtypes = [_ip]
         L.or_net_forward.restype = None
-        L.or_net_forward.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _dp, _dp, _dp, C.c_void_p]
+        L.or_net_forward.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp, _dp, _dp, C.c_void_p]
         L.or_net_predict_loss.restype = C.c_double
         L.or_net_predict_loss.argtypes = [C.c_long, _dp, _dp, C.c_void_p, C.c_void_p]
         L.or_net_backward.restype = C.c_double
-        L.or_net_backward.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _dp, _dp, _dp, _dp, _dp]
+        L.or_net_backward.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp, _dp, _dp, _dp, _dp]
         L.or_adam.restype = None
         L.or_adam.argtypes = [C.c_long, _dp, _dp, _dp, _dp, C.c_long, C.c_double, C.c_double,
                               C.c_double, C.c_double]
@@ -429,12 +429,14 @@ def net_nparams(ch=NET_CHANNELS):
     return lib().or_net_nparams(_i32(ch))
 
 
-def net_forward(L, params, x, ch=NET_CHANNELS, want_act=False):
+def net_forward(L, params, x, ch=NET_CHANNELS, want_act=False, dil=(1, 1, 1, 1)):
+    """Raw net output [c4][P] (and the pre-activations of every layer with
+    want_act) for input x [c0][P] on an L grid; dil: per-layer dilation."""
     Lx, Ly, Lz = (int(v) for v in L)
     P = Lx * Ly * Lz
     out = np.zeros((ch[4], P))
     act = np.zeros((sum(ch[1:]), P)) if want_act else None
-    lib().or_net_forward(Lx, Ly, Lz, _i32(ch), _f64(params), _f64(x), out, _ptr(act))
+    lib().or_net_forward(Lx, Ly, Lz, _i32(ch), _i32(dil), _f64(params), _f64(x), out, _ptr(act))
     return (out, act) if want_act else out
 
 
@@ -447,10 +449,10 @@ def net_predict_loss(raw, Sg, Sstar=None):
     return shat, loss
 
 
-def net_backward(L, params, x, Sg, Sstar, ch=NET_CHANNELS):
+def net_backward(L, params, x, Sg, Sstar, ch=NET_CHANNELS, dil=(1, 1, 1, 1)):
     Lx, Ly, Lz = (int(v) for v in L)
     g = np.zeros(net_nparams(ch))
-    loss = lib().or_net_backward(Lx, Ly, Lz, _i32(ch), _f64(params), _f64(x), _f64(Sg),
+    loss = lib().or_net_backward(Lx, Ly, Lz, _i32(ch), _i32(dil), _f64(params), _f64(x), _f64(Sg),
                                  _f64(Sstar), g)
     return loss, g
 

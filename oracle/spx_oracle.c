@@ -1436,11 +1436,16 @@ void or_min_iterate(int n_sub, const int *L, const int *per, const double *cell9
 /* ---- learned path corrector: 3^3 conv net (forward / backward) ---------- */
 /*
  * Net: 4 layers of 3x3x3 convolutions with zero padding, channel counts
- * c[0] -> c[1] -> c[2] -> c[3] -> c[4], SiLU after layers 1..3.
+ * c[0] -> c[1] -> c[2] -> c[3] -> c[4], SiLU after layers 1..3.  Layer l may
+ * be dilated by dil[l] (the dilated convolution of Yu & Koltun, ICLR 2016:
+ * tap k of the 3^3 kernel reads the input at offset (k - 1) dil[l] per axis);
+ * dil == NULL means 1 everywhere.
  * Activations are [C][Lz][Ly][Lx] planes.  Weights of layer l are
  * W[cout][cin][kz][ky][kx] followed by bias[cout], packed layer after layer.
  */
-static void or_conv3(int Lx, int Ly, int Lz, int cin, int cout, const double *W, const double *bias,
+static int or_dil(const int *dil, int l) { return dil ? dil[l] : 1; }
+
+static void or_conv3(int Lx, int Ly, int Lz, int cin, int cout, int d, const double *W, const double *bias,
                      const double *in, double *out) {
     const long P = (long)Lx * Ly * Lz;
 #pragma omp parallel for schedule(static)
@@ -1452,7 +1457,7 @@ static void or_conv3(int Lx, int Ly, int Lz, int cin, int cout, const double *W,
                 for (int kz = 0; kz < 3; ++kz)
                     for (int ky = 0; ky < 3; ++ky)
                         for (int kx = 0; kx < 3; ++kx) {
-                            int xx = x + kx - 1, yy = y + ky - 1, zz = z + kz - 1;
+                            int xx = x + (kx - 1) * d, yy = y + (ky - 1) * d, zz = z + (kz - 1) * d;
                             if (xx < 0 || yy < 0 || zz < 0 || xx >= Lx || yy >= Ly || zz >= Lz) continue;
                             acc += W[(((long)co * cin + ci) * 3 + kz) * 9 + ky * 3 + kx] *
                                    in[ci * P + xx + (long)Lx * (yy + (long)Ly * zz)];
@@ -1473,8 +1478,8 @@ long or_net_nparams(const int *c) {
 
 /* forward: input x [c0][P] -> raw output [c4][P]; pre-activations saved in
    `act` (layer outputs before SiLU, [c1+c2+c3+c4][P]) if non-NULL */
-void or_net_forward(int Lx, int Ly, int Lz, const int *c, const double *params, const double *x,
-                    double *out, double *act) {
+void or_net_forward(int Lx, int Ly, int Lz, const int *c, const int *dil, const double *params,
+                    const double *x, double *out, double *act) {
     const long P = (long)Lx * Ly * Lz;
     const double *cur = x;
     double *buf[4];
@@ -1483,7 +1488,7 @@ void or_net_forward(int Lx, int Ly, int Lz, const int *c, const double *params, 
         buf[l] = (double *)malloc(sizeof(double) * c[l + 1] * P);
         const double *W = w;
         const double *bias = w + (long)c[l + 1] * c[l] * 27;
-        or_conv3(Lx, Ly, Lz, c[l], c[l + 1], W, bias, cur, buf[l]);
+        or_conv3(Lx, Ly, Lz, c[l], c[l + 1], or_dil(dil, l), W, bias, cur, buf[l]);
         w = bias + c[l + 1];
         if (act) {
             long off = 0;
@@ -1531,14 +1536,14 @@ double or_net_predict_loss(long P, const double *raw, const double *Sg, const do
  * params), by the chain rule written out by hand: loss -> exp map -> tangent
  * projection -> conv layers / SiLU.  Returns the loss.
  */
-double or_net_backward(int Lx, int Ly, int Lz, const int *c, const double *params, const double *x,
-                       const double *Sg, const double *Sstar, double *grad) {
+double or_net_backward(int Lx, int Ly, int Lz, const int *c, const int *dil, const double *params,
+                       const double *x, const double *Sg, const double *Sstar, double *grad) {
     const long P = (long)Lx * Ly * Lz;
     long tot_act = 0;
     for (int l = 0; l < 4; ++l) tot_act += (long)c[l + 1] * P;
     double *act = (double *)malloc(sizeof(double) * tot_act);
     double *raw = (double *)malloc(sizeof(double) * 3 * P);
-    or_net_forward(Lx, Ly, Lz, c, params, x, raw, act);
+    or_net_forward(Lx, Ly, Lz, c, dil, params, x, raw, act);
     double loss = 0.0;
     /* d loss / d raw */
     double *g = (double *)malloc(sizeof(double) * 3 * P);
@@ -1587,7 +1592,7 @@ double or_net_backward(int Lx, int Ly, int Lz, const int *c, const double *param
     memset(grad, 0, sizeof(double) * wo);
     double *gout = g; /* gradient w.r.t. layer output (pre-activation for l=3) */
     for (int l = 3; l >= 0; --l) {
-        const int cin = c[l], cout = c[l + 1];
+        const int cin = c[l], cout = c[l + 1], d = or_dil(dil, l);
         const double *W = params + woff[l];
         double *gW = grad + woff[l];
         double *gb = gW + (long)cout * cin * 27;
@@ -1612,7 +1617,7 @@ double or_net_backward(int Lx, int Ly, int Lz, const int *c, const double *param
                             double s = 0.0;
                             for (long p = 0; p < P; ++p) {
                                 int x0 = (int)(p % Lx), y0 = (int)((p / Lx) % Ly), z0 = (int)(p / ((long)Lx * Ly));
-                                int xx = x0 + kx - 1, yy = y0 + ky - 1, zz = z0 + kz - 1;
+                                int xx = x0 + (kx - 1) * d, yy = y0 + (ky - 1) * d, zz = z0 + (kz - 1) * d;
                                 if (xx < 0 || yy < 0 || zz < 0 || xx >= Lx || yy >= Ly || zz >= Lz) continue;
                                 s += gout[co * P + p] * in[ci * P + xx + (long)Lx * (yy + (long)Ly * zz)];
                             }
@@ -1630,8 +1635,8 @@ double or_net_backward(int Lx, int Ly, int Lz, const int *c, const double *param
                         for (int kz = 0; kz < 3; ++kz)
                             for (int ky = 0; ky < 3; ++ky)
                                 for (int kx = 0; kx < 3; ++kx) {
-                                    /* output q = p - (k-1) used input p through tap k */
-                                    int xq = x0 - kx + 1, yq = y0 - ky + 1, zq = z0 - kz + 1;
+                                    /* output q = p - (k-1) d used input p through tap k */
+                                    int xq = x0 - (kx - 1) * d, yq = y0 - (ky - 1) * d, zq = z0 - (kz - 1) * d;
                                     if (xq < 0 || yq < 0 || zq < 0 || xq >= Lx || yq >= Ly || zq >= Lz) continue;
                                     s += W[(((long)co * cin + ci) * 3 + kz) * 9 + ky * 3 + kx] *
                                          gout[co * P + xq + (long)Lx * (yq + (long)Ly * zq)];

@@ -554,6 +554,65 @@ def test_net_backward_matches_finite_differences():
     assert abs(lf - loss) < 1e-14
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_net_dilated_layer_is_correlation_with_spread_kernel(d):
+    # a layer dilated by d equals scipy's correlation with the 3^3 kernel
+    # spread onto a (2d+1)^3 grid (taps at 0, d, 2d, zeros between), zero
+    # padding; the later layers see its SiLU output (checked as above)
+    from scipy.ndimage import correlate
+    rng = np.random.default_rng(5)
+    L = (9, 7, 8)
+    ch = (1, 1, 1, 1, 1)
+    n = oracle.net_nparams(ch)
+    p = np.zeros(n)
+    k1 = rng.standard_normal(27)
+    p[:27] = k1
+    p[27] = -0.5
+    x = rng.standard_normal((1, L[0] * L[1] * L[2]))
+    _, act = oracle.net_forward(L, p, x, ch=ch, want_act=True, dil=(d, 1, 1, 1))
+    big = np.zeros((2 * d + 1,) * 3)
+    big[::d, ::d, ::d] = k1.reshape(3, 3, 3)
+    ref = correlate(x.reshape(L[2], L[1], L[0]), big, mode="constant", cval=0.0) - 0.5
+    np.testing.assert_allclose(act[0], ref.reshape(-1), atol=1e-12)
+    # layer 2 dilated too: its pre-activation is the spread correlation of
+    # the SiLU of layer 1
+    p2 = p.copy()
+    k2 = rng.standard_normal(27)
+    p2[28:55] = k2
+    _, act2 = oracle.net_forward(L, p2, x, ch=ch, want_act=True, dil=(d, d + 1, 1, 1))
+    big2 = np.zeros((2 * (d + 1) + 1,) * 3)
+    big2[::d + 1, ::d + 1, ::d + 1] = k2.reshape(3, 3, 3)
+    silu = ref * (1 / (1 + np.exp(-ref)))
+    ref2 = correlate(silu, big2, mode="constant", cval=0.0)
+    np.testing.assert_allclose(act2[1], ref2.reshape(-1), atol=1e-12)
+
+
+def test_net_dilated_backward_matches_finite_differences():
+    rng = np.random.default_rng(6)
+    L = (7, 6, 5)
+    P = L[0] * L[1] * L[2]
+    ch = (10, 4, 4, 4, 3)
+    dil = (2, 1, 3, 1)
+    n = oracle.net_nparams(ch)
+    params = rng.standard_normal(n) * 0.2
+    Sg = random_sphere(P, 7)
+    Ss = random_sphere(P, 8)
+    x = np.concatenate([Sg, Ss, random_sphere(P, 9), np.full((1, P), 0.6)])
+    loss, g = oracle.net_backward(L, params, x, Sg, Ss, ch=ch, dil=dil)
+    h = 1e-6
+    for k in rng.choice(n, 40, replace=False):
+        pp, pm = params.copy(), params.copy()
+        pp[k] += h
+        pm[k] -= h
+        lp = oracle.net_predict_loss(oracle.net_forward(L, pp, x, ch=ch, dil=dil), Sg, Ss)[1]
+        lm = oracle.net_predict_loss(oracle.net_forward(L, pm, x, ch=ch, dil=dil), Sg, Ss)[1]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-9, (k, fd, g[k])
+    # dilation changes the result (the taps are not those of dilation 1)
+    l1, _ = oracle.net_backward(L, params, x, Sg, Ss, ch=ch)
+    assert abs(l1 - loss) > 1e-6
+
+
 def test_net_zero_output_returns_geodesic_guess():
     L = (3, 3, 3)
     P = 27
