@@ -438,8 +438,16 @@ def learned_experiment(family, args):
     """Learned versus geodesic initial paths on held-out end states of one
     family (see pathinit.learned_vs_geodesic)."""
     from paper_2605_26016_amd import pathinit
+    tr = None
+    if args.train_sizes:
+        tr = tuple((int(e.split(":")[0]), float(e.split(":")[1]) if ":" in e else 1.0)
+                   for e in args.train_sizes.split(","))
+    te = tuple(int(e) for e in args.test_sizes.split(",")) if args.test_sizes else None
+    dil = tuple(int(v) for v in args.dilation.split(",")) if args.dilation else None
     return pathinit.learned_vs_geodesic(family, n_train=args.n_train, n_test=args.n_test, epochs=args.epochs,
-                                        lr=args.lr, max_iter=args.max_iter, hopfion_L=args.gneb_L, log=log)
+                                        lr=args.lr, max_iter=args.max_iter, train_sizes=tr, test_sizes=te,
+                                        n_img_test=args.test_images, dilation=dil, endpoint_tol=args.endpoint_tol,
+                                        log=log)
 
 
 def heun_workload(args, w, steps=None, warmup=None, cpu=True):
@@ -796,7 +804,15 @@ def main():
                     help="after the timed region, run 4 plain device copies of 3N doubles (a known byte "
                          "count for scaling hardware traffic counters)")
     ap.add_argument("--no-learned", action="store_true", help="GNEB workload: throughput only")
-    ap.add_argument("--gneb-L", type=int, default=32)
+    ap.add_argument("--train-sizes", default=None,
+                    help="learned init: training lattice edges and shares, e.g. 48:0.8,64:0.2 "
+                         "(default: the family's own)")
+    ap.add_argument("--test-sizes", default=None, help="learned init: test lattice edges, e.g. 48,64,96")
+    ap.add_argument("--dilation", default=None,
+                    help="learned init: per-layer dilation of the network, e.g. 1,2,4,8 (default: the family's own)")
+    ap.add_argument("--test-images", type=int, default=32, help="learned init: images per test path")
+    ap.add_argument("--endpoint-tol", type=float, default=2e-4,
+                    help="learned init: max |F| (meV) of the relaxed end states")
     ap.add_argument("--n-train", type=int, default=200)
     ap.add_argument("--n-test", type=int, default=12)
     ap.add_argument("--epochs", type=int, default=150)

@@ -487,6 +487,13 @@ spx_status spx_net_create(const int32_t *channels, spx_net **out);
 /* Frees the workspace.  Synchronises the whole device first (queued passes
  * may still use it). */
 spx_status spx_net_destroy(spx_net *net);
+/* Per-layer dilation dil[4] (host int32, each 1 .. 64; default 1 1 1 1):
+ * tap k = (kx, ky, kz) of layer l reads the input at offset
+ * ((kx-1) dil[l], (ky-1) dil[l], (kz-1) dil[l]), zero outside the lattice, so
+ * the four layers see 1 + 2 (dil[0] + ... + dil[3]) cells per axis.  Applies
+ * to every later forward, backward and learned initial path of the net.
+ * SPX_ERR_INVALID_ARG for a value out of range. */
+spx_status spx_net_set_dilation(spx_net *net, const int32_t *dil);
 spx_status spx_net_forward(spx_net *net, const float *params, const int32_t *dims, int32_t batch, const double *Sg,
                            const double *SA, const double *SB, const float *t, double *Shat, void *stream);
 /* Gradient of loss = mean over batch and sites of |S_hat - S_star|^2 with

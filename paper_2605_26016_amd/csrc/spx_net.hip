@@ -14,6 +14,15 @@
 // input gradient is the same convolution with transposed, flipped weights;
 // weight gradients use one (out, in) channel pair per thread over the block's
 // sites, then a fixed-order reduction over blocks (deterministic).
+//
+// A layer may be dilated by d (tap k reads offset (k - 1) d per axis, which
+// widens the receptive field of the four layers from 9 to 1 + 2 (d1 + d2 +
+// d3 + d4) cells).  The sites of one phase (px, py, pz) in [0, d)^3, at
+// (px + d sx, py + d sy, pz + d sz), only read each other, so a dilated
+// layer runs as the same 3^3 tiles over every phase's sub-grid of
+// ceil(L / d) sites per axis: tiles stay in sub-grid coordinates and only
+// the global addressing is strided.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -39,24 +48,42 @@ __device__ __forceinline__ float silu_grad(float z) {
 struct NetDims {
     int Lx, Ly, Lz;
     int64_t P;
+    int dil;         // dilation of the layer
+    int Sx, Sy, Sz;  // sub-grid extents ceil(L / dil)
 };
 
-__device__ __forceinline__ void tile_origin(const NetDims &d, int &x0, int &y0, int &z0) {
-    const int nbx = (d.Lx + kTXn - 1) / kTXn;
-    x0 = (blockIdx.x % nbx) * kTXn;
-    y0 = (blockIdx.x / nbx) * kTYn;
-    z0 = blockIdx.y * kTZn;
+// Tile of this block: origin (x0, y0, z0) in sub-grid coordinates and the
+// phase (px, py, pz).  blockIdx.x = bx + nbx (by + nby (px + dil py)),
+// blockIdx.y = bz + nbz pz.
+struct NetTile {
+    int x0, y0, z0, px, py, pz;
+};
+__device__ __forceinline__ NetTile tile_origin(const NetDims &d) {
+    const int nbx = (d.Sx + kTXn - 1) / kTXn, nby = (d.Sy + kTYn - 1) / kTYn, nbz = (d.Sz + kTZn - 1) / kTZn;
+    NetTile t;
+    int r = blockIdx.x;
+    t.x0 = (r % nbx) * kTXn;
+    r /= nbx;
+    t.y0 = (r % nby) * kTYn;
+    r /= nby;
+    t.px = r % d.dil;
+    t.py = r / d.dil;
+    t.z0 = ((int)blockIdx.y % nbz) * kTZn;
+    t.pz = (int)blockIdx.y / nbz;
+    return t;
 }
 
-// Stage CIN input channels of image blockIdx.z with a 1-cell zero halo.
+// Stage CIN input channels of image blockIdx.z with a 1-cell zero halo (in
+// sub-grid cells: d sites in the lattice).
 template <int CIN, bool SILU_IN>
-__device__ __forceinline__ void stage_tile(const float *__restrict__ in, const NetDims &d, int x0, int y0, int z0,
+__device__ __forceinline__ void stage_tile(const float *__restrict__ in, const NetDims &d, const NetTile &t,
                                            float (*tile)[kHalo]) {
     const float *src = in + (int64_t)blockIdx.z * CIN * d.P;
     for (int idx = threadIdx.x; idx < CIN * kHalo; idx += kNT) {
         const int ci = idx / kHalo, r = idx - ci * kHalo;
         const int hx = r % kHX, hy = (r / kHX) % kHY, hz = r / (kHX * kHY);
-        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        const int gx = t.px + d.dil * (t.x0 + hx - 1), gy = t.py + d.dil * (t.y0 + hy - 1),
+                  gz = t.pz + d.dil * (t.z0 + hz - 1);
         float v = 0.0f;
         if (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.Lx && gy < d.Ly && gz < d.Lz) {
             v = src[ci * d.P + gx + (int64_t)d.Lx * (gy + (int64_t)d.Ly * gz)];
@@ -73,9 +100,8 @@ __global__ __launch_bounds__(kNT) void k_conv(const float *__restrict__ in, cons
                                               const float *__restrict__ bias, const float *__restrict__ zmul,
                                               float *__restrict__ out, NetDims d) {
     __shared__ float tile[CIN][kHalo];
-    int x0, y0, z0;
-    tile_origin(d, x0, y0, z0);
-    stage_tile<CIN, SILU_IN>(in, d, x0, y0, z0, tile);
+    const NetTile tl = tile_origin(d);
+    stage_tile<CIN, SILU_IN>(in, d, tl, tile);
     __syncthreads();
     const int tx = threadIdx.x % kTXn, ty = (threadIdx.x / kTXn) % kTYn, tz = threadIdx.x / (kTXn * kTYn);
     float acc[COUT];
@@ -90,7 +116,7 @@ __global__ __launch_bounds__(kNT) void k_conv(const float *__restrict__ in, cons
             for (int co = 0; co < COUT; ++co) acc[co] += W[(co * CIN + ci) * 27 + k] * v;
         }
     }
-    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    const int x = tl.px + d.dil * (tl.x0 + tx), y = tl.py + d.dil * (tl.y0 + ty), z = tl.pz + d.dil * (tl.z0 + tz);
     if (x >= d.Lx || y >= d.Ly || z >= d.Lz) return;
     const int64_t p = x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z);
     float *dst = out + (int64_t)blockIdx.z * COUT * d.P;
@@ -111,20 +137,20 @@ __global__ void k_transpose_flip(const float *__restrict__ W, float *__restrict_
 }
 
 // Per-block weight/bias gradient partials:
-//   dW[co][ci][k] = sum_p g[co](p) a[ci](p + k - 1),  db[co] = sum_p g[co](p)
+//   dW[co][ci][k] = sum_p g[co](p) a[ci](p + (k - 1) d),  db[co] = sum_p g[co](p)
 // over the block's output tile; partial[blk][COUT*CIN*27 + COUT].
 template <int CIN, int COUT, bool SILU_IN>
 __global__ __launch_bounds__(kNT) void k_conv_wgrad(const float *__restrict__ in, const float *__restrict__ g,
                                                     double *__restrict__ partial, NetDims d) {
     __shared__ float tile[CIN][kHalo];
     __shared__ float gt[COUT][kTXn * kTYn * kTZn];
-    int x0, y0, z0;
-    tile_origin(d, x0, y0, z0);
-    stage_tile<CIN, SILU_IN>(in, d, x0, y0, z0, tile);
+    const NetTile tl = tile_origin(d);
+    stage_tile<CIN, SILU_IN>(in, d, tl, tile);
     const float *gsrc = g + (int64_t)blockIdx.z * COUT * d.P;
     for (int idx = threadIdx.x; idx < COUT * kNT; idx += kNT) {
         const int co = idx / kNT, s = idx % kNT;
-        const int x = x0 + s % kTXn, y = y0 + (s / kTXn) % kTYn, z = z0 + s / (kTXn * kTYn);
+        const int x = tl.px + d.dil * (tl.x0 + s % kTXn), y = tl.py + d.dil * (tl.y0 + (s / kTXn) % kTYn),
+                  z = tl.pz + d.dil * (tl.z0 + s / (kTXn * kTYn));
         float v = 0.0f;
         if (x < d.Lx && y < d.Ly && z < d.Lz) v = gsrc[co * d.P + x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z)];
         gt[co][s] = v;
@@ -273,6 +299,7 @@ __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float
 }  // namespace
 
 constexpr int kC[5] = {10, 16, 16, 16, 3};
+constexpr int kMaxDilation = 64;
 
 struct NetWork {
     int64_t cap_P = 0;
@@ -292,6 +319,7 @@ using namespace spx;
 
 struct spx_net {
     NetWork w;
+    int dil[4] = {1, 1, 1, 1};  // per-layer dilation
 };
 
 namespace {
@@ -338,20 +366,33 @@ spx_status net_reserve(NetWork &w, int64_t P, int B, bool train) {
     return SPX_OK;
 }
 
+// The dims of layer l: the lattice with that layer's dilation.
+NetDims layer_dims(const NetDims &d, const int dil[4], int l) {
+    NetDims e = d;
+    e.dil = dil[l];
+    e.Sx = (d.Lx + e.dil - 1) / e.dil;
+    e.Sy = (d.Ly + e.dil - 1) / e.dil;
+    e.Sz = (d.Lz + e.dil - 1) / e.dil;
+    return e;
+}
+
+// Blocks of a layer: the tiles of one phase's sub-grid times the d^3 phases.
 dim3 conv_grid(const NetDims &d, int B) {
-    const int nbx = (d.Lx + kTXn - 1) / kTXn, nby = (d.Ly + kTYn - 1) / kTYn;
-    return dim3((unsigned)(nbx * nby), (unsigned)((d.Lz + kTZn - 1) / kTZn), (unsigned)B);
+    const int nbx = (d.Sx + kTXn - 1) / kTXn, nby = (d.Sy + kTYn - 1) / kTYn, nbz = (d.Sz + kTZn - 1) / kTZn;
+    return dim3((unsigned)(nbx * nby * d.dil * d.dil), (unsigned)(nbz * d.dil), (unsigned)B);
 }
 
 // forward through the four layers; z[l] are pre-activations
-hipError_t net_forward_layers(NetWork &w, const float *params, const NetDims &d, int B, hipStream_t st) {
-    const dim3 gr = conv_grid(d, B);
+hipError_t net_forward_layers(NetWork &w, const float *params, const NetDims &d, const int dil[4], int B,
+                              hipStream_t st) {
+    const NetDims d0 = layer_dims(d, dil, 0), d1 = layer_dims(d, dil, 1), d2 = layer_dims(d, dil, 2),
+                  d3 = layer_dims(d, dil, 3);
     const float *W0 = params + layer_off(0), *W1 = params + layer_off(1);
     const float *W2 = params + layer_off(2), *W3 = params + layer_off(3);
-    k_conv<10, 16, false, false><<<gr, kNT, 0, st>>>(w.x, W0, W0 + 16 * 10 * 27, nullptr, w.z[0], d);
-    k_conv<16, 16, true, false><<<gr, kNT, 0, st>>>(w.z[0], W1, W1 + 16 * 16 * 27, nullptr, w.z[1], d);
-    k_conv<16, 16, true, false><<<gr, kNT, 0, st>>>(w.z[1], W2, W2 + 16 * 16 * 27, nullptr, w.z[2], d);
-    k_conv<16, 3, true, false><<<gr, kNT, 0, st>>>(w.z[2], W3, W3 + 3 * 16 * 27, nullptr, w.z[3], d);
+    k_conv<10, 16, false, false><<<conv_grid(d0, B), kNT, 0, st>>>(w.x, W0, W0 + 16 * 10 * 27, nullptr, w.z[0], d0);
+    k_conv<16, 16, true, false><<<conv_grid(d1, B), kNT, 0, st>>>(w.z[0], W1, W1 + 16 * 16 * 27, nullptr, w.z[1], d1);
+    k_conv<16, 16, true, false><<<conv_grid(d2, B), kNT, 0, st>>>(w.z[1], W2, W2 + 16 * 16 * 27, nullptr, w.z[2], d2);
+    k_conv<16, 3, true, false><<<conv_grid(d3, B), kNT, 0, st>>>(w.z[2], W3, W3 + 3 * 16 * 27, nullptr, w.z[3], d3);
     return hipGetLastError();
 }
 
@@ -362,6 +403,10 @@ spx_status check_dims(const int32_t *dims, int32_t batch, NetDims &d) {
     d.Ly = dims[1];
     d.Lz = dims[2];
     d.P = (int64_t)dims[0] * dims[1] * dims[2];
+    d.dil = 1;
+    d.Sx = d.Lx;
+    d.Sy = d.Ly;
+    d.Sz = d.Lz;
     if (d.P * batch > ((int64_t)1 << 31)) return set_error(SPX_ERR_INVALID_ARG, "network batch too large");
     return SPX_OK;
 }
@@ -379,7 +424,7 @@ spx_status net_apply(spx_net *net, const float *params, const int32_t dims[3], i
     if ((s = net_reserve(net->w, d.P, batch, false)) != SPX_OK) return s;
     const dim3 pg((unsigned)((d.P + kNT - 1) / kNT), (unsigned)batch);
     k_net_input<<<pg, kNT, 0, st>>>(Sg, SA, SB, t, net->w.x, d.P, shared_ends ? 0 : 3 * d.P);
-    hipError_t e = net_forward_layers(net->w, params, d, batch, st);
+    hipError_t e = net_forward_layers(net->w, params, d, net->dil, batch, st);
     if (e == hipSuccess) {
         k_net_head<<<pg, kNT, 0, st>>>(net->w.z[3], Sg, nullptr, Shat, nullptr, nullptr, d.P, 0.0);
         e = hipGetLastError();
@@ -404,6 +449,16 @@ spx_status spx_net_create(const int32_t *channels, spx_net **out) {
     spx_net *n = new spx_net();
     register_handle(n);
     *out = n;
+    return SPX_OK;
+}
+
+spx_status spx_net_set_dilation(spx_net *net, const int32_t *dil) {
+    if (!handle_alive(net)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_net handle");
+    if (!dil) return set_error(SPX_ERR_INVALID_ARG, "dil is NULL");
+    for (int l = 0; l < 4; ++l)
+        if (dil[l] < 1 || dil[l] > kMaxDilation)
+            return set_error(SPX_ERR_INVALID_ARG, "each dilation must be 1 .. 64");
+    for (int l = 0; l < 4; ++l) net->dil[l] = dil[l];
     return SPX_OK;
 }
 
@@ -434,9 +489,14 @@ spx_status spx_net_backward(spx_net *net, const float *params, const int32_t *di
     if (s != SPX_OK) return s;
     NetWork &w = net->w;
     if ((s = net_reserve(w, d.P, batch, true)) != SPX_OK) return s;
-    const dim3 gr = conv_grid(d, batch);
-    const size_t n_blk = (size_t)gr.x * gr.y * gr.z;
-    const size_t need = n_blk * (16 * 16 * 27 + 16);
+    NetDims dl[4];
+    size_t max_blk = 0;
+    for (int l = 0; l < 4; ++l) {
+        dl[l] = layer_dims(d, net->dil, l);
+        const dim3 g = conv_grid(dl[l], batch);
+        max_blk = std::max(max_blk, (size_t)g.x * g.y * g.z);
+    }
+    const size_t need = max_blk * (16 * 16 * 27 + 16);
     const dim3 pg((unsigned)((d.P + kNT - 1) / kNT), (unsigned)batch);
     const size_t nl = (size_t)pg.x * pg.y;
     if (need > w.part_cap) {
@@ -460,7 +520,7 @@ spx_status spx_net_backward(spx_net *net, const float *params, const int32_t *di
         w.lpart_cap = nl;
     }
     k_net_input<<<pg, kNT, 0, st>>>(Sg, SA, SB, t, w.x, d.P, 3 * d.P);
-    hipError_t e = net_forward_layers(w, params, d, batch, st);
+    hipError_t e = net_forward_layers(w, params, d, net->dil, batch, st);
     if (e != hipSuccess) return set_hip_error(e, "network backward (forward pass)");
     const double inv_count = 1.0 / ((double)d.P * batch);
     k_net_head<<<pg, kNT, 0, st>>>(w.z[3], Sg, Sstar, nullptr, w.g[3], w.lpart, d.P, inv_count);
@@ -472,15 +532,19 @@ spx_status spx_net_backward(spx_net *net, const float *params, const int32_t *di
         const float *Wl = params + layer_off(l);
         float *gl = grad + layer_off(l);
         const float *ain = l == 0 ? w.x : w.z[l - 1];
-        if (l == 3) k_conv_wgrad<16, 3, true><<<gr, kNT, 0, st>>>(ain, w.g[3], w.part, d);
-        else if (l == 0) k_conv_wgrad<10, 16, false><<<gr, kNT, 0, st>>>(ain, w.g[0], w.part, d);
-        else k_conv_wgrad<16, 16, true><<<gr, kNT, 0, st>>>(ain, w.g[l], w.part, d);
+        const NetDims &d_l = dl[l];
+        const dim3 gr = conv_grid(d_l, batch);
+        const size_t n_blk = (size_t)gr.x * gr.y * gr.z;
+        if (l == 3) k_conv_wgrad<16, 3, true><<<gr, kNT, 0, st>>>(ain, w.g[3], w.part, d_l);
+        else if (l == 0) k_conv_wgrad<10, 16, false><<<gr, kNT, 0, st>>>(ain, w.g[0], w.part, d_l);
+        else k_conv_wgrad<16, 16, true><<<gr, kNT, 0, st>>>(ain, w.g[l], w.part, d_l);
         k_sum_partials<<<(nw + 255) / 256, 256, 0, st>>>(w.part, (int)n_blk, nw, gl);
         if (l > 0) {
             // g_{l-1} = silu'(z_{l-1}) * conv(g_l, W^T flipped)
             k_transpose_flip<<<(cin * cout * 27 + 255) / 256, 256, 0, st>>>(Wl, w.wt, cin, cout);
-            if (l == 3) k_conv<3, 16, false, true><<<gr, kNT, 0, st>>>(w.g[3], w.wt, nullptr, w.z[2], w.g[2], d);
-            else k_conv<16, 16, false, true><<<gr, kNT, 0, st>>>(w.g[l], w.wt, nullptr, w.z[l - 1], w.g[l - 1], d);
+            // the transposed convolution of layer l has layer l's dilation
+            if (l == 3) k_conv<3, 16, false, true><<<gr, kNT, 0, st>>>(w.g[3], w.wt, nullptr, w.z[2], w.g[2], d_l);
+            else k_conv<16, 16, false, true><<<gr, kNT, 0, st>>>(w.g[l], w.wt, nullptr, w.z[l - 1], w.g[l - 1], d_l);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return set_hip_error(e, "network backward");

@@ -38,9 +38,10 @@ class PathResult:
 
 
 def converge(hams, images, tol=1e-3, ci_on_below=1e-2, max_iter=20000, chunk=500, spring_k=1.0, vp_dt=0.1,
-             vp_mass=1.0, method=0, net=None, params=None) -> PathResult:
+             vp_mass=1.0, method=0, net=None, params=None, log=None, what="") -> PathResult:
     """Batched GNEB over all instances from the geodesic (method 0) or learned
-    (method 1) initial path until every instance has converged or max_iter."""
+    (method 1) initial path until every instance has converged or max_iter.
+    log: called with a progress line every 5000 iterations."""
     import time
     import torch
     g = spx.gneb_create(hams, images, spring_k=spring_k, vp_dt=vp_dt, vp_mass=vp_mass, ci_mode=1,
@@ -56,6 +57,9 @@ def converge(hams, images, tol=1e-3, ci_on_below=1e-2, max_iter=20000, chunk=500
         conv = [spx.gneb_get_stats(g, k)["converged"] for k in range(n)]
         if all(conv):
             break
+        if log and done % 5000 < chunk:
+            log(f"[path-init] {what}: {done} iterations, {sum(conv)}/{n} converged, "
+                f"{time.perf_counter() - t0:.0f} s")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     st = [spx.gneb_get_stats(g, k) for k in range(n)]
@@ -115,11 +119,16 @@ def build_samples(dims, geodesic_paths, converged_paths) -> PathData:
                     torch.stack(Ss).contiguous())
 
 
-def train(data: PathData, epochs=30, batch=16, lr=1e-3, seed=0, params=None, log=None, lr_final=None):
+def train(data, epochs=30, batch=16, lr=1e-3, seed=0, params=None, log=None, lr_final=None, dilation=(1, 1, 1, 1),
+          log_every=1):
     """Adam on the mean over images and sites of |S_hat - S*|^2; the step
-    size decays from lr to lr_final (default lr) on a cosine over the run."""
+    size decays from lr to lr_final (default lr) on a cosine over the run.
+    data: one PathData or a list of them (lattice sizes); every batch comes
+    from one of them, and an epoch visits every sample once in shuffled
+    batch order."""
     import torch
-    net = spx.Net()
+    sets = data if isinstance(data, (list, tuple)) else [data]
+    net = spx.Net(dilation=dilation)
     p = torch.from_numpy(init_params(seed) if params is None else params).cuda()
     n = p.numel()
     grad = torch.zeros(n, dtype=torch.float32, device="cuda")
@@ -127,17 +136,21 @@ def train(data: PathData, epochs=30, batch=16, lr=1e-3, seed=0, params=None, log
     v = torch.zeros_like(grad)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(seed)
-    ns = data.Sg.shape[0]
     step = 0
     hist = []
     lr_end = lr if lr_final is None else lr_final
-    n_steps = epochs * ((ns + batch - 1) // batch)
+    n_steps = epochs * sum((d.Sg.shape[0] + batch - 1) // batch for d in sets)
     for ep in range(epochs):
-        order = rng.permutation(ns)
+        plan = []
+        for k, d in enumerate(sets):
+            order = rng.permutation(d.Sg.shape[0])
+            plan += [(k, order[b0:b0 + batch]) for b0 in range(0, len(order), batch)]
+        rng.shuffle(plan)
         tot = 0.0
         nb = 0
-        for b0 in range(0, ns, batch):
-            idx = torch.from_numpy(order[b0:b0 + batch]).cuda()
+        for k, sel in plan:
+            data = sets[k]
+            idx = torch.from_numpy(sel).cuda()
             B = int(idx.numel())
             Sg = data.Sg.index_select(0, idx).contiguous()
             SA = data.SA.index_select(0, idx).contiguous()
@@ -151,7 +164,7 @@ def train(data: PathData, epochs=30, batch=16, lr=1e-3, seed=0, params=None, log
             tot += loss.item()
             nb += 1
         hist.append(tot / max(nb, 1))
-        if log:
+        if log and (ep % log_every == 0 or ep == epochs - 1):
             log(f"epoch {ep}: loss {hist[-1]:.4e}")
     return p, net, hist
 
@@ -176,20 +189,30 @@ def minimize(h, states, tol=1e-4, max_iter=20000, chunk=1000, vp_dt=0.1, vp_mass
     return [Y[1 + m].clone() for m in range(M)], s["iterations"], s["max_force"]
 
 
-def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max_iter=30000, hopfion_L=32,
-                        skyrmion_train_L=32, skyrmion_test_L=(48, 64, 96), log=None):
+def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max_iter=30000, train_sizes=None,
+                        test_sizes=None, n_img_train=16, n_img_test=32, dilation=None, endpoint_tol=2e-4,
+                        log=None):
     """Train the path corrector on GNEB-converged paths of one family and
     compare GNEB from the learned and the geodesic initial path on held-out
-    end states.  hopfion: four-shell frustrated sc exchange (J1 = 1 meV,
-    J2/J1 = 0.188, J3/J1 = -0.274, J4/J1 = -0.161), open L^3, VP-relaxed
-    seeded hopfion -> FM (16 images).  skyrmion: sc monolayer film, J = 1 meV,
-    bulk DMI 0.3 meV, B = 1.4 T, periodic in plane, relaxed seeded skyrmion ->
-    FM, trained on skyrmion_train_L^2 films (16 images) and evaluated on a
-    ragged batch of skyrmion_test_L^2 films (32 images).  Both GNEB runs use
-    the same optimiser settings; a pair counts when both converge to max |F| <
-    1e-3 meV with barriers within 0.1 meV (same channel).  End states are
-    drawn by the seeded texture generators (training seeds 1000.., test seeds
-    5000..)."""
+    end states.
+
+    hopfion: four-shell frustrated sc exchange (J1 = 1 meV, J2/J1 = 0.188,
+    J3/J1 = -0.274, J4/J1 = -0.161), open L^3, VP-relaxed seeded hopfion ->
+    FM; train_sizes default ((48, 0.8), (64, 0.2)): lattice edge and share of
+    the n_train training pairs; test on 48^3, 64^3 and 96^3.
+    skyrmion: sc monolayer film, J = 1 meV, bulk DMI 0.3 meV, B = 1.4 T,
+    periodic in plane, relaxed seeded skyrmion -> FM; trained on 32^2 films,
+    tested on 48^2, 64^2 and 96^2 films.
+
+    End states are relaxed by velocity projection to max |F| < endpoint_tol
+    (meV).  n_img_train images per training path, n_img_test per test path; the
+    test pairs are dealt evenly over test_sizes and run as one ragged batch.
+    dilation: per-layer dilation of the network (default (1, 2, 4, 8) for
+    hopfions, whose torus radius L/6 exceeds the 9-cell field of undilated
+    layers, and (1, 1, 1, 1) for skyrmion films).  Both GNEB runs use the same
+    optimiser settings; a pair counts when both converge to max |F| < 1e-3
+    meV with barriers within 0.1 meV (same channel).  End states are drawn by
+    the seeded texture generators (training seeds 1000.., test seeds 5000..)."""
     import time
 
     import torch
@@ -201,10 +224,13 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
     t0 = time.perf_counter()
     if family == "hopfion":
         J = dict(J_shell=(1.0, 0.188, -0.274, -0.161))
-        Ltr = (hopfion_L,) * 3
-        Lte = [Ltr]
         per = (0, 0, 0)
-        n_tr_img, n_te_img = 16, 16
+        train_sizes = train_sizes or ((48, 0.8), (64, 0.2))
+        test_sizes = test_sizes or (48, 64, 96)
+        dilation = dilation or (1, 2, 4, 8)
+
+        def lat(L):
+            return (L, L, L)
 
         def seed_state(L, s):
             rng = np.random.default_rng(s)
@@ -213,11 +239,13 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
                                    center_offset=rng.uniform(-2, 2, 3))
     else:
         J = dict(J_shell=(1.0,), D_shell=(0.3,), B=(0.0, 0.0, 1.4))
-        Ltr = (skyrmion_train_L, skyrmion_train_L, 1)
-        Lte = [(L, L, 1) for L in skyrmion_test_L]
         per = (1, 1, 0)
-        n_tr_img, n_te_img = 16, 32
-        n_test = len(Lte) * max(1, n_test // len(Lte))
+        train_sizes = train_sizes or ((32, 1.0),)
+        test_sizes = test_sizes or (48, 64, 96)
+        dilation = dilation or (1, 1, 1, 1)
+
+        def lat(L):
+            return (L, L, 1)
 
         def seed_state(L, s):
             rng = np.random.default_rng(s)
@@ -233,7 +261,7 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
     def endpoints(L, seeds):
         h = ham(L)
         st = [torch.from_numpy(seed_state(L, s)).cuda() for s in seeds]
-        rel, _, _ = minimize(h, st, tol=2e-4, max_iter=30000, vp_dt=0.2)
+        rel, _, _ = minimize(h, st, tol=endpoint_tol, max_iter=60000, vp_dt=0.2)
         return [r for r in rel if int((r[2] < 0).sum()) > 0]   # textures that survived relaxation
 
     def paths(L, A, n_img):
@@ -247,34 +275,57 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
             Ys.append(Y)
         return Ys
 
-    A_tr = endpoints(Ltr, range(1000, 1000 + n_train))
-    Y_tr = paths(Ltr, A_tr, n_tr_img)
-    geo = [y.clone() for y in Y_tr]
-    gg = spx.gneb_create([ham(Ltr)] * len(geo), geo)
-    spx.gneb_init_path(gg)
-    res_tr = converge([ham(Ltr)] * len(Y_tr), Y_tr, tol=1e-3, max_iter=max_iter, chunk=1000)
-    ok = [k for k in range(len(Y_tr)) if res_tr.converged[k]]
-    log(f"[path-init] {family}: {len(ok)}/{len(Y_tr)} training paths converged (median "
-        f"{int(np.median(res_tr.iterations))} iterations), {time.perf_counter() - t0:.1f} s")
-    data = build_samples(Ltr, [geo[k] for k in ok], [Y_tr[k] for k in ok])
-    p, net, hist = train(data, epochs=epochs, batch=16, lr=lr, lr_final=lr / 20)
+    # -- training data: converged paths per lattice size
+    sets, n_ok, its_tr, bar_tr = [], 0, [], []
+    for i, (edge, share) in enumerate(train_sizes):
+        L = lat(edge)
+        n_L = max(1, int(round(n_train * share)))
+        A_tr = endpoints(L, range(1000 + 2000 * i, 1000 + 2000 * i + n_L))
+        Y_tr = paths(L, A_tr, n_img_train)
+        geo = [y.clone() for y in Y_tr]
+        gg = spx.gneb_create([ham(L)] * len(geo), geo)
+        spx.gneb_init_path(gg)
+        del gg
+        res_tr = converge([ham(L)] * len(Y_tr), Y_tr, tol=1e-3, max_iter=max_iter, chunk=1000, log=log,
+                          what=f"{family} training {edge}")
+        ok = [k for k in range(len(Y_tr)) if res_tr.converged[k]]
+        n_ok += len(ok)
+        its_tr += res_tr.iterations.tolist()
+        bar_tr += np.round(res_tr.barrier, 4).tolist()
+        log(f"[path-init] {family} {L}: {len(ok)}/{len(Y_tr)} training paths converged (median "
+            f"{int(np.median(res_tr.iterations))} iterations, barriers {np.min(res_tr.barrier):.3f} .. "
+            f"{np.max(res_tr.barrier):.3f} meV), {time.perf_counter() - t0:.1f} s")
+        if ok:
+            sets.append(build_samples(L, [geo[k] for k in ok], [Y_tr[k] for k in ok]))
+        del Y_tr, geo
+    p, net, hist = train(sets, epochs=epochs, batch=16, lr=lr, lr_final=lr / 20, dilation=dilation,
+                         log=lambda m: log(f"[path-init] {family} {m}"), log_every=10)
     log(f"[path-init] {family}: trained, loss {hist[0]:.3e} -> {hist[-1]:.3e}, {time.perf_counter() - t0:.1f} s")
-    Hs, Yp = [], []
-    per_size = max(1, n_test // len(Lte))
-    for i, L in enumerate(Lte):
+    del sets
+    # -- held-out pairs on every test size, one ragged batch per initial path
+    Hs, Yp, size_of = [], [], []
+    per_size = max(1, n_test // len(test_sizes))
+    for i, edge in enumerate(test_sizes):
+        L = lat(edge)
         A = endpoints(L, range(5000 + 100 * i, 5000 + 100 * i + per_size))
-        Yp += paths(L, A, n_te_img)
+        Yp += paths(L, A, n_img_test)
         Hs += [ham(L)] * len(A)
+        size_of += [edge] * len(A)
     Yl = [y.clone() for y in Yp]
-    rp = converge(Hs, Yp, tol=1e-3, max_iter=max_iter, chunk=250)
-    rl = converge(Hs, Yl, tol=1e-3, max_iter=max_iter, chunk=250, method=1, net=net, params=p)
+    rp = converge(Hs, Yp, tol=1e-3, max_iter=max_iter, chunk=250, log=log, what=f"{family} test geodesic")
+    rl = converge(Hs, Yl, tol=1e-3, max_iter=max_iter, chunk=250, method=1, net=net, params=p, log=log,
+                  what=f"{family} test learned")
     both = [k for k in range(len(Yp)) if rp.converged[k] and rl.converged[k]]
     dbar = np.abs(rl.barrier - rp.barrier)
     same = [k for k in both if dbar[k] <= 0.1]
     it_p = float(np.mean(rp.iterations[same])) if same else None
     it_l = float(np.mean(rl.iterations[same])) if same else None
-    return {"lattice_train": list(Ltr), "lattices_test": [list(L) for L in Lte], "images_train": n_tr_img,
-            "images_test": n_te_img, "train_paths": len(ok), "test_paths": len(Yp),
+    log(f"[path-init] {family}: {len(same)}/{len(Yp)} test pairs in the same channel; iterations learned "
+        f"{it_l} vs geodesic {it_p}")
+    return {"lattices_train": [list(lat(e)) for e, _ in train_sizes], "train_share": [sh for _, sh in train_sizes],
+            "lattices_test": [list(lat(e)) for e in test_sizes], "test_lattice_edge": size_of,
+            "images_train": n_img_train, "images_test": n_img_test, "dilation": list(dilation),
+            "train_paths": n_ok, "train_iterations": its_tr, "train_barriers_meV": bar_tr, "test_paths": len(Yp),
             "test_converged_both": len(both), "same_channel_within_0.1meV": len(same),
             "iterations_geodesic": rp.iterations.tolist(), "iterations_learned": rl.iterations.tolist(),
             "barrier_geodesic_meV": np.round(rp.barrier, 4).tolist(),

@@ -119,6 +119,7 @@ def load(path: str = LIB_PATH):
         "spx_gneb_init_path": [vp, i32, vp, vp, vp],
         "spx_net_create": [vp, C.POINTER(vp)],
         "spx_net_destroy": [vp],
+        "spx_net_set_dilation": [vp, C.POINTER(C.c_int32)],
         "spx_net_forward": [vp, vp, C.POINTER(C.c_int32), i32, vp, vp, vp, vp, vp, vp],
         "spx_net_backward": [vp, vp, C.POINTER(C.c_int32), i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "spx_net_adam_step": [vp, vp, vp, vp, i64, i64, dbl, dbl, dbl, dbl, vp],
@@ -578,12 +579,16 @@ def mfma_probe(prec, A, B, D, stream=None):
 
 # ---------------------------------------------------------------- learned corrector
 class Net:
-    """Owner of an spx_net workspace handle."""
+    """Owner of an spx_net workspace handle; dilation: per-layer dilation of
+    the four 3^3 convolutions (spx_net_set_dilation)."""
 
-    def __init__(self):
+    def __init__(self, dilation=(1, 1, 1, 1)):
         h = C.c_void_p()
         _check(load().spx_net_create(None, C.byref(h)), "spx_net_create")
         self.handle = h.value
+        self.dilation = tuple(int(v) for v in dilation)
+        if self.dilation != (1, 1, 1, 1):
+            net_set_dilation(self, self.dilation)
 
     def __del__(self):
         if getattr(self, "handle", None):
@@ -592,6 +597,12 @@ class Net:
             except Exception:
                 pass
             self.handle = None
+
+
+def net_set_dilation(net, dil):
+    d = (C.c_int32 * 4)(*[int(v) for v in dil])
+    _check(load().spx_net_set_dilation(net.handle, d), "spx_net_set_dilation")
+    net.dilation = tuple(int(v) for v in dil)
 
 
 def net_nparams() -> int:

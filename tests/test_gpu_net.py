@@ -102,6 +102,74 @@ def test_net_backward_matches_oracle():
     assert torch.equal(grad, grad2)
 
 
+@pytest.mark.parametrize("L,dil", [((19, 13, 11), (1, 2, 4, 3)), ((12, 20, 9), (8, 4, 2, 1))],
+                         ids=["d1243", "d8421"])
+def test_net_dilated_forward_matches_oracle(L, dil):
+    # dilated layers run as 3^3 tiles over the phase sub-grids of ceil(L/d)
+    # sites: extents that are not multiples of d, sub-grids smaller than one
+    # 8 x 8 x 4 tile, and a dilation of 8 on a 9-site axis (phases with one
+    # and two sites)
+    import torch
+    from paper_2605_26016_amd import spx
+    B = 2
+    p32 = init_params(4, scale=1.5)
+    Sg, SA, SB, _, t = batch_case(L, B, 40)
+    P = L[0] * L[1] * L[2]
+    net = spx.Net(dilation=dil)
+    out = torch.zeros((B, 3, P), dtype=torch.float64, device="cuda")
+    spx.net_forward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    p64 = p32.astype(np.float64)
+    for b in range(B):
+        raw = oracle.net_forward(L, p64, oracle_x(Sg[b], SA[b], SB[b], t[b]), dil=dil)
+        ref, _ = oracle.net_predict_loss(raw, Sg[b])
+        err = float(np.max(np.abs(got[b] - ref)))
+        print(f"dilation {dil} image {b}: max |dS| {err:.2e}", flush=True)
+        assert err <= 1e-5 * max(1.0, float(np.max(np.abs(raw)))), err
+    # dilation 1 everywhere reproduces the undilated net
+    spx.net_set_dilation(net, (1, 1, 1, 1))
+    spx.net_forward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), out)
+    raw = oracle.net_forward(L, p64, oracle_x(Sg[0], SA[0], SB[0], t[0]))
+    ref, _ = oracle.net_predict_loss(raw, Sg[0])
+    assert np.max(np.abs(out[0].cpu().numpy() - ref)) <= 1e-5 * max(1.0, float(np.max(np.abs(raw))))
+
+
+def test_net_dilated_backward_matches_oracle():
+    import torch
+    from paper_2605_26016_amd import spx
+    L = (11, 9, 7)
+    B = 2
+    dil = (2, 1, 3, 2)
+    p32 = init_params(5, scale=2.0)
+    Sg, SA, SB, Ss, t = batch_case(L, B, 50)
+    net = spx.Net(dilation=dil)
+    n = spx.net_nparams()
+    grad = torch.zeros(n, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    spx.net_backward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), to_dev(Ss), grad, loss)
+    g = grad.cpu().numpy().astype(np.float64)
+    p64 = p32.astype(np.float64)
+    ref = np.zeros(n)
+    lref = 0.0
+    for b in range(B):
+        lb, gb = oracle.net_backward(L, p64, oracle_x(Sg[b], SA[b], SB[b], t[b]), Sg[b], Ss[b], dil=dil)
+        ref += gb / B
+        lref += lb / B
+    assert abs(loss.item() - lref) <= 1e-5 * lref
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    print(f"dilated gradient max-normalised error {err:.2e}", flush=True)
+    assert err <= 1e-5, err
+
+
+def test_net_dilation_is_validated():
+    from paper_2605_26016_amd import spx
+    net = spx.Net()
+    for bad in ((0, 1, 1, 1), (1, 1, 65, 1)):
+        with pytest.raises(spx.SpxError):
+            spx.net_set_dilation(net, bad)
+
+
 def test_adam_matches_oracle():
     import torch
     from paper_2605_26016_amd import spx
@@ -159,7 +227,8 @@ def test_trained_net_saves_gneb_iterations_at_equal_barrier():
     # (within 0.1 meV); the learned paths must need clearly fewer iterations
     from paper_2605_26016_amd import pathinit
     r = pathinit.learned_vs_geodesic("skyrmion", n_train=60, n_test=6, epochs=150, lr=2e-3, max_iter=20000,
-                                     skyrmion_train_L=24, skyrmion_test_L=(24, 32))
+                                     train_sizes=((24, 1.0),), test_sizes=(24, 32), n_img_test=32,
+                                     dilation=(1, 1, 1, 1))
     print({k: r[k] for k in ("same_channel_within_0.1meV", "mean_iterations_geodesic_same_channel",
                              "mean_iterations_learned_same_channel", "iteration_ratio_learned_over_geodesic",
                              "train_loss_first_last", "seconds")}, flush=True)
