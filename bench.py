@@ -36,6 +36,9 @@ TWO_SWEEP_BYTES = 120
 BYTES_FUSED = 48
 # field only: FP64 spin in, FP32 field out
 FIELD_BYTES = 36
+# MI355X vector FP32 peak (packed FP32 instructions: two FMAs per lane; the
+# library is built without them, which halves the rate it can reach)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 # dense 7^3 window of 3x3 blocks: 342 offsets x 9 multiply-adds x 2 flop
 DENSE_FLOP_PER_SITE = 6156
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -710,16 +713,24 @@ def field_workload(args, w):
     del h
     ref_max = float(b64.abs().max())
     dense = {}
-    for prec in ("bf16", "fp16", "fp32"):
-        h = spx.setup_hamiltonian(w.L, bonds=(ab, dl, J9), field_prec=prec, backend=2 if prec != "fp32" else 0,
-                                  **common)
-        ms = timed(h, b32, reps if prec != "fp32" else max(reps // 20, 2))
+    # bf16 / fp16: the MFMA window; fp32_direct: the FP32 direct window on the
+    # vector ALUs (the plain path the MFMA forms are compared with);
+    # fp32_gather: the generic gather kernel on the same bond table
+    for name, prec, backend in (("bf16", "bf16", 2), ("fp16", "fp16", 2), ("fp32_direct", "fp32", 2),
+                                ("fp32_gather", "fp32", 1)):
+        h = spx.setup_hamiltonian(w.L, bonds=(ab, dl, J9), field_prec=prec, backend=backend, **common)
+        ms = timed(h, b32, reps if name != "fp32_gather" else max(reps // 20, 2))
         err = float((b32.double() - b64).abs().max()) / ref_max
-        dense[prec] = {"ms": ms, "fields_per_s": w.N / ms * 1e3,
-                       "TFLOPs_algorithmic": DENSE_FLOP_PER_SITE * w.N / ms / 1e9,
+        tf = DENSE_FLOP_PER_SITE * w.N / ms / 1e9
+        dense[name] = {"ms": ms, "fields_per_s": w.N / ms * 1e3, "TFLOPs_algorithmic": tf,
                        "max_rel_error_vs_fp64": err}
-        log(f"[bench] K7 dense {prec}: {ms:.3f} ms, error vs FP64 {err:.2e}")
+        log(f"[bench] K7 dense {name}: {ms:.3f} ms, {tf:.1f} TFLOP/s, error vs FP64 {err:.2e}")
         del h
+    fd = dense["fp32_direct"]
+    fd["frac_of_fp32_peak"] = fd["TFLOPs_algorithmic"] / FP32_VECTOR_PEAK_TFLOPS
+    fd["frac_of_unpacked_fp32_peak"] = fd["TFLOPs_algorithmic"] / (FP32_VECTOR_PEAK_TFLOPS / 2)
+    for name in ("bf16", "fp16"):
+        dense[name]["speedup_over_fp32_direct"] = fd["ms"] / dense[name]["ms"]
     dense["fp64_direct_ms"] = ms64
     mf = dense["bf16"]
     roof = {"bound": "mfma", "achieved": round(mf["TFLOPs_algorithmic"], 2), "peak": MFMA_BF16_PEAK_TFLOPS,

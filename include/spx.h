@@ -105,8 +105,11 @@ typedef struct {
     int32_t dipolar;           /* 0 off, 1 on */
 } spx_model_desc;
 
-/* backend: 0 auto, 1 sparse stencil, 2 dense-window MFMA (needs a BF16/FP16
- * field_prec).  autotune: 0 off, 1 time candidate launch shapes at setup and
+/* backend: 0 auto, 1 sparse stencil, 2 dense 7^3 window (single sublattice,
+ * every bond within |delta| <= 3; no dipolar term; field evaluation only):
+ * field_prec SPX_BF16_MFMA / SPX_FP16_MFMA run it on the matrix cores,
+ * SPX_FP32 runs the direct FP32 convolution on the vector ALUs (Methods,
+ * backend representations: dense convolution).  autotune: 0 off, 1 time candidate launch shapes at setup and
  * keep the fastest (cached per shape key in tune_cache_path if non-NULL).
  * stencil_engine: 0 auto, 1 gather kernel (any bond table), 2 z-marching LDS
  * engine (bond tables that match a built-in shell shape: simple cubic shells
@@ -266,7 +269,7 @@ typedef struct {
     int64_t n_sites;
     int32_t n_bonds;           /* directed bonds in the table */
     int32_t field_prec;
-    int32_t backend;           /* 1 stencil, 2 MFMA, 3 pair list */
+    int32_t backend;           /* 1 stencil, 2 dense window (MFMA or FP32 direct), 3 pair list */
     int32_t radius[3];         /* max |delta| per axis over the table */
     int32_t dipolar;
     int64_t workspace_bytes;   /* library-owned device memory */

@@ -377,10 +377,12 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     }
     if (prec >= SPX_BF16_MFMA && backend_req == 1)
         return fail(SPX_ERR_INVALID_ARG, "MFMA precisions need the dense backend");
-    if (backend_req == 2 && prec < SPX_BF16_MFMA)
-        return fail(SPX_ERR_INVALID_ARG, "the dense MFMA backend needs field_prec SPX_BF16_MFMA or SPX_FP16_MFMA");
-    if (prec >= SPX_BF16_MFMA && model->dipolar)
-        return fail(SPX_ERR_UNSUPPORTED, "the dense MFMA backend has no dipolar term");
+    if (backend_req == 2 && prec != SPX_FP32 && prec < SPX_BF16_MFMA)
+        return fail(SPX_ERR_INVALID_ARG,
+                    "the dense backend needs field_prec SPX_FP32 (direct), SPX_BF16_MFMA or SPX_FP16_MFMA");
+    // the dense window: MFMA precisions, or FP32 with the dense backend requested
+    const bool want_dense = prec >= SPX_BF16_MFMA || backend_req == 2;
+    if (want_dense && model->dipolar) return fail(SPX_ERR_UNSUPPORTED, "the dense backend has no dipolar term");
     spx_status s = check_device();
     if (s != SPX_OK) return s;
 
@@ -513,7 +515,7 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
             for (int k = 0; k < 3; ++k) bd[3 * p + k] = h->bonds[p].d[k];
             for (int k = 0; k < 9; ++k) bJ[9 * p + k] = h->bonds[p].J[k];
         }
-        if (prec >= SPX_BF16_MFMA) {
+        if (want_dense) {
             std::string why;
             if (!dense_plan(prec, lat->n_sub, ba.data(), bb.data(), bd.data(), bJ.data(), nb, &h->dense, st, why)) {
                 free_all(h);

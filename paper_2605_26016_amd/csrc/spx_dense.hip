@@ -17,6 +17,15 @@
 // FP16 weights so that max|K| lies in [2^12, 2^13) and spins by 2^10, which
 // keeps the small far-field couplings and spin components out of FP16's
 // subnormal range.
+//
+// The plain FP32 path over the same window (k_dense_fp32) is a direct
+// convolution on the vector ALUs: a 128-thread block owns a 16 x 8 x 8
+// output tile and stages its 22 x 14 x 14 input region in LDS as float;
+// each thread computes the 8 outputs of one z column.  For each of the 49
+// (dx, dy) window columns it reads every input spin of its column once from
+// LDS and applies it, with the column's seven uniform 3x3 blocks (scalar
+// registers), to each of the up to seven outputs it reaches: 504 FMAs per
+// 42 LDS reads, 3087 per output.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -205,6 +214,120 @@ __global__ __launch_bounds__(kThreadsD) void k_dense_mfma(const double *__restri
     }
 }
 
+constexpr int kFX = 16, kFY = 8, kFZ = 8;  // FP32 direct: output tile, one thread per (x, y) column
+constexpr int kFT = kFX * kFY;
+constexpr int kFIX = kFX + 2 * kR, kFIY = kFY + 2 * kR, kFIZ = kFZ + 2 * kR;
+
+// b = sum_w K_w S(x + delta_w) over the 7^3 window (FP32 operands and
+// accumulation) + Zeeman + anisotropy (FP64), K [343][9] with w = (dz + 3)
+// 49 + (dy + 3) 7 + (dx + 3) and entries [alpha][beta].
+__global__ __launch_bounds__(kFT) void k_dense_fp32(const double *__restrict__ S, float *__restrict__ b,
+                                                    const float *__restrict__ K, Grid g, Onsite os) {
+    __shared__ float tile[3][kFIZ][kFIY][kFIX];
+    __shared__ int lines[kFIX + kFIY + kFIZ];
+    int x0, y0, z0;
+    {
+        // contiguous runs of tiles per XCD (tiles sharing halo planes share an L2)
+        const int nbx = (g.Lx + kFX - 1) / kFX, nby = (g.Ly + kFY - 1) / kFY;
+        const int T = (int)gridDim.x, bi = (int)blockIdx.x;
+        const int q = T / 8, r = T % 8, k = bi % 8;
+        const int t = k * q + min(k, r) + bi / 8;
+        x0 = (t % nbx) * kFX;
+        y0 = ((t / nbx) % nby) * kFY;
+        z0 = (t / (nbx * nby)) * kFZ;
+    }
+    const int64_t N = g.N;
+    // wrapped coordinate of each input line (-1 outside an open face)
+    if (threadIdx.x < kFIX + kFIY + kFIZ) {
+        const int t = threadIdx.x;
+        const int ax = t < kFIX ? 0 : (t < kFIX + kFIY ? 1 : 2);
+        const int c = ax == 0 ? x0 - kR + t : (ax == 1 ? y0 - kR + (t - kFIX) : z0 - kR + (t - kFIX - kFIY));
+        const int L = ax == 0 ? g.Lx : (ax == 1 ? g.Ly : g.Lz);
+        bool ok = true;
+        const int w = wrap_coord(c, L, g.per[ax], 1, ok);
+        lines[t] = ok ? w : -1;
+    }
+    __syncthreads();
+    {
+        constexpr int kElems = kFIZ * kFIY * kFIX;
+        constexpr int kU = 8;
+        const int *cx = lines, *cy = lines + kFIX, *cz = lines + kFIX + kFIY;
+#pragma unroll 1
+        for (int e0 = threadIdx.x; e0 < kElems; e0 += kU * kFT) {
+            double v[kU][3];
+            unsigned okm = 0;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int q = min(e0 + u * kFT, kElems - 1);
+                const int xx = q % kFIX, yz = q / kFIX;
+                const int gx = cx[xx], gy = cy[yz % kFIY], gz = cz[yz / kFIY];
+                const bool ok = (gx | gy | gz) >= 0;
+                okm |= (ok ? 1u : 0u) << u;
+                const int64_t j = ok ? gx + (int64_t)g.Lx * (gy + (int64_t)g.Ly * gz) : 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[u][c] = S[c * N + j];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int q = e0 + u * kFT;
+                if (q >= kElems) break;
+                const int xx = q % kFIX, yz = q / kFIX;
+                const int yy = yz % kFIY, zz = yz / kFIY;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) tile[c][zz][yy][xx] = (okm >> u) & 1u ? (float)v[u][c] : 0.0f;
+            }
+        }
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % kFX, ty = threadIdx.x / kFX;
+    float acc[kFZ][3];
+#pragma unroll
+    for (int o = 0; o < kFZ; ++o) acc[o][0] = acc[o][1] = acc[o][2] = 0.0f;
+#pragma unroll 1
+    for (int dyx = 0; dyx < 49; ++dyx) {
+        const int dy = dyx / 7, dx = dyx - 7 * dy;
+        float kk[7][9];  // uniform: the column's seven 3x3 blocks
+#pragma unroll
+        for (int dz = 0; dz < 7; ++dz)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) kk[dz][e] = K[(dz * 49 + dyx) * 9 + e];
+#pragma unroll
+        for (int zi = 0; zi < kFIZ; ++zi) {
+            const float s0 = tile[0][zi][ty + dy][tx + dx], s1 = tile[1][zi][ty + dy][tx + dx],
+                        s2 = tile[2][zi][ty + dy][tx + dx];
+            // input plane zi reaches output o = zi - dz through offset dz - 3
+#pragma unroll
+            for (int dz = 0; dz < 7; ++dz) {
+                const int o = zi - dz;
+                if (o >= 0 && o < kFZ) {
+                    // three FMAs per component chained on the accumulator
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        acc[o][a] = fmaf(kk[dz][3 * a], s0, acc[o][a]);
+                        acc[o][a] = fmaf(kk[dz][3 * a + 1], s1, acc[o][a]);
+                        acc[o][a] = fmaf(kk[dz][3 * a + 2], s2, acc[o][a]);
+                    }
+                }
+            }
+        }
+    }
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= g.Lx || y >= g.Ly) return;
+#pragma unroll
+    for (int o = 0; o < kFZ; ++o) {
+        const int z = z0 + o;
+        if (z >= g.Lz) break;
+        const int64_t i = x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z);
+        double ba[3] = {0.0, 0.0, 0.0};
+        if (os.n_aniso > 0) {
+            const double sv[3] = {S[i], S[N + i], S[2 * N + i]};
+            aniso_field(os, 0, sv, ba);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b[c * N + i] = (float)((double)acc[o][c] + ba[c] + os.bz[0][c]);
+    }
+}
+
 // Layout probe: D = A B for one 32x32x16 MFMA, A [32][16], B [16][32], D [32][32]
 // row-major FP32 (values exactly representable in the operand type).
 template <bool BF16>
@@ -223,10 +346,12 @@ __global__ void k_mfma_probe(const float *__restrict__ A, const float *__restric
 }  // namespace
 
 struct DensePlan {
-    short *d_frag = nullptr;  // [kRuns][64 lanes][8]
+    short *d_frag = nullptr;  // MFMA: [kRuns][64 lanes][8]
+    float *d_K = nullptr;     // FP32 direct: [343][9]
     float kscale = 1.0f;      // 1 / (weight scale * input scale)
     float in_scale = 1.0f;
     int bf16 = 1;
+    int direct = 0;           // 1: the FP32 direct kernel
 };
 
 // Host: dense 7^3 window from a single-sublattice bond table (all |delta| <= 3).
@@ -245,6 +370,32 @@ bool dense_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, const
         }
         const int w = (dz + kR) * 49 + (dy + kR) * 7 + (dx + kR);
         for (int e = 0; e < 9; ++e) K[w * 9 + e] += bond_J[9 * p + e];
+    }
+    if (prec == 1) {
+        // FP32 direct: the window table rounded to float once
+        std::vector<float> Kf(K.begin(), K.end());
+        DensePlan *p = new DensePlan();
+        p->direct = 1;
+        if (hipMalloc((void **)&p->d_K, Kf.size() * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            delete p;
+            why = "hipMalloc failed for the dense window table";
+            return false;
+        }
+        if (hipMemcpyAsync(p->d_K, Kf.data(), Kf.size() * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(p->d_K);
+            delete p;
+            why = "upload of the dense window table failed";
+            return false;
+        }
+        *out = p;
+        return true;
+    }
+    if (prec != 2 && prec != 3) {
+        why = "the dense window runs in FP32, BF16 MFMA or FP16 MFMA";
+        return false;
     }
     double kmax = 0.0;
     for (double v : K) kmax = std::max(kmax, std::fabs(v));
@@ -314,10 +465,17 @@ bool dense_plan(int prec, int n_sub, const int *bond_a, const int *bond_b, const
 void dense_destroy(DensePlan *p) {
     if (!p) return;
     if (p->d_frag) (void)hipFree(p->d_frag);
+    if (p->d_K) (void)hipFree(p->d_K);
     delete p;
 }
 
 hipError_t dense_field(const DensePlan *p, const Grid &g, const Onsite &os, const double *S, float *b, hipStream_t st) {
+    if (p->direct) {
+        const unsigned tiles = (unsigned)((g.Lx + kFX - 1) / kFX) * (unsigned)((g.Ly + kFY - 1) / kFY) *
+                               (unsigned)((g.Lz + kFZ - 1) / kFZ);
+        k_dense_fp32<<<tiles, kFT, 0, st>>>(S, b, p->d_K, g, os);
+        return hipGetLastError();
+    }
     const unsigned grid =
         (unsigned)((g.Lx + kDX - 1) / kDX) * (unsigned)((g.Ly + kDY - 1) / kDY) * (unsigned)((g.Lz + kDZ - 1) / kDZ);
     if (p->bf16)

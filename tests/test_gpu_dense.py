@@ -42,13 +42,13 @@ def test_mfma_lane_layout_probe(prec):
     assert np.array_equal(D.cpu().numpy(), A @ B)
 
 
-def dense_case(L, periodic, prec, seed=5):
+def dense_case(L, periodic, prec, seed=5, backend=2):
     import torch
     from paper_2605_26016_amd import spx
     ab, dl, J = k7_table()
     cell = np.eye(3) * 0.4
     h = spx.setup_hamiltonian(L, cell=cell, mu=(2.0,), periodic=periodic, bonds=(ab, dl, J), B=(0, 0, 0.5),
-                              field_prec=prec, backend=2 if prec in ("bf16", "fp16") else 0)
+                              field_prec=prec, backend=backend)
     lat = oracle.Lattice(L, cell, [0, 0, 0], periodic=periodic, mu=[2.0])
     N = lat.N
     S = random_sphere(N, seed)
@@ -86,8 +86,23 @@ def test_dense_mfma_matches_emulated_oracle(prec, rnd, bound, L, per):
     assert err <= bound
 
 
-def test_dense_fp32_direct_matches_fp64():
-    got, S, lat, (ab, dl, J) = dense_case((21, 18, 9), (0, 0, 0), "fp32")
+@pytest.mark.parametrize("L,periodic", [((21, 18, 9), (0, 0, 0)), ((37, 19, 17), (1, 0, 1)), ((5, 4, 3), (1, 1, 1)),
+                                        ((33, 8, 8), (0, 1, 0))],
+                         ids=["open", "mixed_ragged", "smaller_than_window", "exact_y_z_tiles"])
+def test_dense_fp32_direct_matches_fp64(L, periodic):
+    # the FP32 direct window (16 x 8 x 8 tiles): ragged tails on every axis,
+    # periodic wrap, and a lattice smaller than the window (periodic images
+    # of one site reached through several offsets); FP32 operands and
+    # accumulation over 343 offsets: 1e-5 of the largest field
+    got, S, lat, (ab, dl, J) = dense_case(L, periodic, "fp32")
+    ref = oracle.field(oracle.Model(lat, bonds=(ab[:, 0], ab[:, 1], dl, J), B=(0, 0, 0.5)), S)
+    err = max_rel(got, ref)
+    print(f"fp32 direct {L} {periodic}: max-rel error vs FP64 {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_dense_fp32_gather_matches_fp64():
+    got, S, lat, (ab, dl, J) = dense_case((21, 18, 9), (0, 0, 0), "fp32", backend=1)
     ref = oracle.field(oracle.Model(lat, bonds=(ab[:, 0], ab[:, 1], dl, J), B=(0, 0, 0.5)), S)
     assert max_rel(got, ref) <= 1e-5
 
