@@ -115,11 +115,11 @@ GNEB_BYTES = 240
 # reads S_n, S_n-1, S_n+1 and v (96 B), the second reads S_n, S_n-1, S_n+1, v
 # and writes v, S' (120 B)
 GNEB_PASS_BYTES = 216
-# string method per spin-image: pass A 72 B; pass B without velocities 96 B;
-# pass C without velocities (read S_n-1, S_n, S_n+1, F, write S') 120 B; the
-# reparameterisation's distance pass (2 images per pair) 48 B and
-# interpolation (2 images read, 1 written) 72 B
-STRING_BYTES = 72 + 96 + 120 + 48 + 72
+# string method per spin-image: the projection pass without velocities
+# (read S_n, S_n-1, S_n+1: 72 B), the update pass without velocities (read
+# S_n, S_n-1, S_n+1, write S': 96 B), the reparameterisation's distance pass
+# (2 images per pair: 48 B) and interpolation (2 images read, 1 written: 72 B)
+STRING_BYTES = 72 + 96 + 48 + 72
 
 
 def gneb_workload(args):
