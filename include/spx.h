@@ -145,6 +145,10 @@ typedef struct {
     int32_t stencil_engine;
     int32_t zchunk;
     int32_t heun_field;
+    /* rows (wavefronts) per block of the fused Heun step (heun_field 8) on
+     * the FP32 nearest-neighbour shape: 16 or 8; 0 = the autotuner's choice
+     * (16 without autotuning).  Other shapes use 8. */
+    int32_t tile_rows;
 } spx_options;
 
 /* Build the kernel tables (directed bonds grouped per target sublattice, see
@@ -280,6 +284,7 @@ typedef struct {
     int32_t tuned;             /* 1 if the autotuner chose zchunk / heun_field */
     double tuned_step_us;      /* its timing of one Heun step (microseconds) */
     int32_t heun_graph;        /* 1 once a captured Heun graph exists (replayed for runs of >= 4 steps) */
+    int32_t tile_rows;         /* rows per block of the fused Heun step (0 when heun_field != 8) */
 } spx_ham_info;
 spx_status spx_get_info(spx_ham *h, spx_ham_info *info);
 

@@ -358,6 +358,8 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
     const int hfield_req = opts ? opts->heun_field : 0;
     if (engine_req < 0 || engine_req > 2) return fail(SPX_ERR_INVALID_ARG, "unknown stencil_engine");
     if (zchunk_req < 0 || zchunk_req > 4096) return fail(SPX_ERR_INVALID_ARG, "zchunk out of range");
+    const int rows_req = opts ? opts->tile_rows : 0;
+    if (rows_req != 0 && rows_req != 8 && rows_req != 16) return fail(SPX_ERR_INVALID_ARG, "tile_rows must be 0, 8 or 16");
     if (hfield_req < 0 || hfield_req > kMaxHeunMode) return fail(SPX_ERR_INVALID_ARG, "unknown heun_field");
     if ((hfield_req == 2 || hfield_req == 5 || hfield_req == 6) && prec != SPX_FP32)
         return fail(SPX_ERR_INVALID_ARG, "a stored FP32 Heun field needs field_prec SPX_FP32");
@@ -539,6 +541,7 @@ spx_status spx_setup_hamiltonian(const spx_lattice_desc *lat, const spx_model_de
         }
         h->engine = (have && engine_req != 1) ? 2 : 1;
         if (have && zchunk_req > 0) h->zp.zch = zchunk_req;
+        if (have) h->zp.frows = rows_req;
         h->heun_field = 1;
         // the fused step needs a single-sublattice shape of range one cell and
         // no dipolar term (whose FFT field is taken between the two stages)
@@ -640,6 +643,7 @@ spx_status spx_get_info(spx_ham *h, spx_ham_info *info) {
     info->heun_field = h->heun_field;
     info->tuned = h->tuned;
     info->tuned_step_us = h->tune_us;
+    info->tile_rows = (h->engine == 2 && h->heun_field == kHeunFused) ? fused_rows(h->zp) : 0;
     info->heun_graph = h->heun_graph ? 1 : 0;
     return SPX_OK;
 }
@@ -798,23 +802,32 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
     char key[160];
     std::snprintf(key, sizeof(key), "shape%d_prec%d_sub%d_%dx%dx%d_per%d%d%d", h->zp.kind, h->field_prec, g.n_sub,
                   g.Lx, g.Ly, g.Lz, g.per[0], g.per[1], g.per[2]);
+    // cache lines: key, z chunk, Heun mode, microseconds per step, and the
+    // fused step's rows per block (0 for the other modes; lines without it
+    // read as 0)
+    const bool tune_rows = h->fusable && h->zp.kind == SHAPE_SC_NN && h->zp.prec == 1 && h->zp.frows == 0;
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "r")) {
-            char k2[160];
-            int z, hf;
+            char line[256], k2[160];
+            int z, hf, rows;
             double us;
             bool hit = false;
-            int cz = 0, chf = 0;
+            int cz = 0, chf = 0, crows = 0;
             double cus = 0.0;
-            while (std::fscanf(f, "%159s %d %d %lf", k2, &z, &hf, &us) == 4)
-                if (std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && hf >= 1 && hf <= kMaxHeunMode) {
-                    cz = z; chf = hf; cus = us; hit = true;   // the last matching line wins
+            while (std::fgets(line, sizeof(line), f)) {
+                rows = 0;
+                const int n = std::sscanf(line, "%159s %d %d %lf %d", k2, &z, &hf, &us, &rows);
+                if (n >= 4 && std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && hf >= 1 && hf <= kMaxHeunMode &&
+                    (rows == 0 || rows == 8 || rows == 16)) {
+                    cz = z; chf = hf; cus = us; crows = rows; hit = true;   // the last matching line wins
                 }
+            }
             std::fclose(f);
             if (hit && !((chf == 2 || chf == 5 || chf == 6) && h->field_prec != SPX_FP32) &&
                 !(chf == kHeunFused && !h->fusable)) {
                 if (tune_z) h->zp.zch = cz;
                 if (tune_field) h->heun_field = chf;
+                if (tune_rows && h->heun_field == kHeunFused && chf == kHeunFused && crows != 0) h->zp.frows = crows;
                 h->tune_us = cus;
                 h->tuned = 1;
                 spx_status s = heun_buffers(h, h->heun_field);
@@ -867,11 +880,18 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     double best = 1e300;
-    int bz = h->zp.zch, bh = h->heun_field;
+    int bz = h->zp.zch, bh = h->heun_field, brows = h->zp.frows;
     const int reps = 4;
+    // block shapes of the fused step: 16 or 8 rows (wavefronts) per block
+    auto rowlist = [&](int hf) {
+        if (hf == kHeunFused && tune_rows) return std::vector<int>{16, 8};
+        return std::vector<int>{h->zp.frows};
+    };
     for (int hf : hfs)
+        for (int rows : rowlist(hf))
         for (int z : zlist(hf)) {
             h->zp.zch = z;
+            h->zp.frows = rows;
             h->heun_field = hf;
             spx_status r = SPX_OK;
             for (int k = 0; k < 2 && r == SPX_OK; ++k) r = enqueue_heun_step(h, hc, k, tmp, h->d_Sp, st);
@@ -886,20 +906,21 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e0, e1);
             const double us = 1e3 * ms / reps;
-            if (us < best) { best = us; bz = z; bh = hf; }
+            if (us < best) { best = us; bz = z; bh = hf; brows = rows; }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(tmp);
     if (s != SPX_OK) return s;
     h->zp.zch = bz;
+    h->zp.frows = brows;
     h->heun_field = bh;
     h->tuned = 1;
     h->tune_us = best;
     heun_buffers_trim(h);
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %.3f\n", key, bz, bh, best);
+            std::fprintf(f, "%s %d %d %.3f %d\n", key, bz, bh, best, bh == kHeunFused ? fused_rows(h->zp) : 0);
             std::fclose(f);
         }
     }

@@ -68,6 +68,7 @@ struct ZPlan {
     int nw = 0;
     int zch = 8;    // z planes per block
     int txw = 64;   // tile width in x (GNEB passes: 64, 32 or 16; others 64)
+    int frows = 0;  // rows (wavefronts) per block of the fused Heun step, 0: 16 for FP32 NN, else 8
     double wd[9 * kMaxShapeBonds];
     float wf[9 * kMaxShapeBonds];
 };
@@ -136,6 +137,8 @@ hipError_t heun_split_post(const Grid &g, const Onsite &os, const HeunConst &hc,
 // z-march over the lattice, S -> out (out != S), for single-sublattice shell
 // shapes of range one cell (simple cubic shells 1 and, isotropic, 1-3).
 bool fused_heun_supported(const ZPlan &zp, const Grid &g);
+// Rows per block the fused step launches with for this plan (16 or 8).
+int fused_rows(const ZPlan &zp);
 hipError_t heun_fused(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,
                       const double *S, double *out, hipStream_t st);
 hipError_t zmarch_correct(const ZPlan &zp, const Grid &g, const Onsite &os, const HeunConst &hc, uint64_t step,

@@ -377,12 +377,18 @@ hipError_t launch_fused_kind(const ZPlan &zp, const FArgs &a0, const FConst &fc,
 }
 
 // Rows per block: 16 wavefronts for FP32 nearest neighbours (106 KB of LDS,
-// 125 VGPRs: four waves per SIMD), 8 otherwise (FP64 planes take twice the
-// LDS; the 26-neighbour shape needs more than 128 VGPRs).
+// 125 VGPRs: four waves per SIMD) or 8 (zp.frows, chosen by the autotuner);
+// 8 otherwise (FP64 planes take twice the LDS; the 26-neighbour shape needs
+// more than 128 VGPRs).
 template <typename T, bool ISO>
 hipError_t launch_fused_t(const ZPlan &zp, const FArgs &a, const FConst &fc, hipStream_t st) {
     switch (zp.kind) {
-    case SHAPE_SC_NN: return launch_fused_kind<SHAPE_SC_NN, T, ISO, sizeof(T) == 4 ? 16 : 8>(zp, a, fc, st);
+    case SHAPE_SC_NN:
+        if constexpr (sizeof(T) == 4) {
+            if (zp.frows == 8) return launch_fused_kind<SHAPE_SC_NN, T, ISO, 8>(zp, a, fc, st);
+            return launch_fused_kind<SHAPE_SC_NN, T, ISO, 16>(zp, a, fc, st);
+        }
+        return launch_fused_kind<SHAPE_SC_NN, T, ISO, 8>(zp, a, fc, st);
     case SHAPE_SC_3SH:
         if constexpr (ISO) return launch_fused_kind<SHAPE_SC_3SH, T, ISO, 8>(zp, a, fc, st);
         break;
@@ -392,6 +398,10 @@ hipError_t launch_fused_t(const ZPlan &zp, const FArgs &a, const FConst &fc, hip
 }
 
 }  // namespace
+
+int fused_rows(const ZPlan &zp) {
+    return (zp.kind == SHAPE_SC_NN && zp.prec == 1 && zp.frows != 8) ? 16 : 8;
+}
 
 bool fused_heun_supported(const ZPlan &zp, const Grid &g) {
     if (!zp.valid || g.n_sub != 1) return false;

@@ -47,7 +47,7 @@ class ModelDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("field_prec", C.c_int32), ("backend", C.c_int32), ("autotune", C.c_int32),
                 ("tune_cache_path", C.c_char_p), ("stencil_engine", C.c_int32), ("zchunk", C.c_int32),
-                ("heun_field", C.c_int32)]
+                ("heun_field", C.c_int32), ("tile_rows", C.c_int32)]
 
 
 class LlgParams(C.Structure):
@@ -83,7 +83,7 @@ class HamInfo(C.Structure):
                 ("backend", C.c_int32), ("radius", C.c_int32 * 3), ("dipolar", C.c_int32),
                 ("workspace_bytes", C.c_int64), ("stencil_engine", C.c_int32), ("shape", C.c_int32),
                 ("zchunk", C.c_int32), ("heun_field", C.c_int32), ("tuned", C.c_int32),
-                ("tuned_step_us", C.c_double), ("heun_graph", C.c_int32)]
+                ("tuned_step_us", C.c_double), ("heun_graph", C.c_int32), ("tile_rows", C.c_int32)]
 
 
 _lib = None
@@ -248,7 +248,7 @@ def setup_hamiltonian(dims: Sequence[int], cell=None, sub_frac=((0.0, 0.0, 0.0),
                       periodic=(1, 1, 1), J_shell=None, D_shell=None, bonds=None, K=None,
                       K_axis=None, B=(0.0, 0.0, 0.0), dipolar=0, field_prec="fp64", backend=0,
                       autotune=0, tune_cache_path=None, stencil_engine=0, zchunk=0, heun_field=0,
-                      stream=None) -> Hamiltonian:
+                      tile_rows=0, stream=None) -> Hamiltonian:
     """Wraps spx_setup_hamiltonian.  K: [n_sub][n_aniso] meV (or scalar applied
     to every sublattice with one axis), K_axis: matching unit vectors.
     bonds = (ab [n][2], delta [n][3], J [n][9]) overrides the shells."""
@@ -307,6 +307,7 @@ def setup_hamiltonian(dims: Sequence[int], cell=None, sub_frac=((0.0, 0.0, 0.0),
     o.stencil_engine = int(stencil_engine)
     o.zchunk = int(zchunk)
     o.heun_field = int(heun_field)
+    o.tile_rows = int(tile_rows)
     h = C.c_void_p()
     _check(L.spx_setup_hamiltonian(C.byref(lat), C.byref(m), C.byref(o), _stream(stream), C.byref(h)),
            "spx_setup_hamiltonian")

@@ -84,6 +84,44 @@ def test_fused_heun_parity(name, w, prec, n, tol, zchunk):
     assert np.max(np.abs(np.sqrt((got * got).sum(0)) - 1.0)) < 1e-14
 
 
+@pytest.mark.parametrize("name,w", [("sc_fp32_multitile_periodic", stoch((130, 31, 20))),
+                                    ("sc_fp32_mixed_bc", stoch((70, 29, 11), periodic=(1, 0, 1))),
+                                    ("sc_dmi_fp32", stoch((67, 30, 12), periodic=(1, 0, 1), D_shell=(0.3,),
+                                                          B=(0.0, 0.0, 0.5)))],
+                         ids=["periodic", "mixed_bc", "dmi"])
+def test_fused_eight_row_blocks_fp32(name, w):
+    # the autotuner's other block shape for FP32 nearest neighbours: 8 rows
+    # (6 corrector rows per tile) instead of 16
+    S = random_sphere(w.N, 64)
+    ref = oracle.heun(oracle_model(w), S, alpha=w.alpha, dt_fs=w.dt_fs, T_K=w.T_K, seed=w.philox_seed,
+                      step0=17, n_steps=2)
+    got, info = run_gpu(w, S, "fp32", 2, heun_field=8, zchunk=5, tile_rows=8)
+    assert (info.heun_field, info.tile_rows) == (8, 8)
+    err = float(np.max(np.abs(got - ref)))
+    print(f"{name} 8 rows: max |dS| = {err:.3e}", flush=True)
+    assert err <= 2e-9, (name, err)
+    got16, info16 = run_gpu(w, S, "fp32", 2, heun_field=8, zchunk=5, tile_rows=16)
+    assert info16.tile_rows == 16
+    assert float(np.max(np.abs(got16 - ref))) <= 2e-9
+
+
+def test_fused_tuner_searches_block_rows(tmp_path):
+    # with the fused step requested, the autotuner times 16- and 8-row blocks
+    # over its z chunks and records the winner in its cache; a second set-up
+    # reads it back
+    from paper_2605_26016_amd import spx
+    cache = str(tmp_path / "tune.txt")
+    w = stoch((96, 90, 40))
+    h = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache, heun_field=8)
+    info = spx.get_info(h)
+    assert info.tuned == 1 and info.heun_field == 8 and info.tile_rows in (8, 16)
+    line = open(cache).read().split("\n")[0].split()
+    assert int(line[2]) == 8 and int(line[4]) == info.tile_rows
+    h2 = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache, heun_field=8)
+    info2 = spx.get_info(h2)
+    assert (info2.zchunk, info2.heun_field, info2.tile_rows) == (info.zchunk, 8, info.tile_rows)
+
+
 def test_fused_is_default_where_it_applies():
     from paper_2605_26016_amd import spx
     h = gpu_hamiltonian(stoch((40, 30, 20)), field_prec="fp32")
