@@ -62,11 +62,12 @@ def kernel_source_hash(paths=KERNEL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, heun_mode, zchunk):
+def measured_traffic(kernel: str, workload: str, heun_mode, zchunk, tile_rows=0):
     """HBM bytes per launch (per iteration for the GNEB entry) from the
     committed rocprofv3 --pmc summary, if it was taken on the current source
     of the files it lists, on this workload and in this launch configuration
-    (else None)."""
+    (else None).  An entry holds one record per launch configuration it was
+    measured in ("configs": z chunk, Heun mode, fused rows, bytes)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -75,9 +76,12 @@ def measured_traffic(kernel: str, workload: str, heun_mode, zchunk):
     e = d.get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash(e.get("sources", KERNEL_SOURCES)):
         return None
-    if (e.get("workload"), e.get("heun_mode"), e.get("zchunk")) != (workload, heun_mode, zchunk):
+    if e.get("workload") != workload:
         return None
-    return e.get("bytes_per_launch")
+    for c in e.get("configs", [e]):
+        if (c.get("heun_mode"), c.get("zchunk"), c.get("tile_rows", 0)) == (heun_mode, zchunk, tile_rows or 0):
+            return c.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(w, seconds: float):
@@ -475,7 +479,8 @@ def heun_workload(args, w, steps=None, warmup=None, cpu=True):
                               autotune=0 if args.no_autotune else 1, tune_cache_path=args.tune_cache)
     info = spx.get_info(h)
     log(f"[bench] engine {info.stencil_engine} shape {info.shape} zchunk {info.zchunk} "
-        f"heun_field {info.heun_field} tuned {info.tuned} ({info.tuned_step_us:.1f} us/step while tuning), "
+        f"heun_field {info.heun_field} tile_rows {info.tile_rows} tuned {info.tuned} "
+        f"({info.tuned_step_us:.1f} us/step while tuning), "
         f"library workspace {info.workspace_bytes / 2**30:.2f} GiB")
     if w.N > 200_000_000:
         # too large to draw on the host in reasonable time: torch's seeded device generator
@@ -557,7 +562,7 @@ def heun_workload(args, w, steps=None, warmup=None, cpu=True):
         timing = "HIP events around every launch in a separate pass of direct launches after the timed region"
         bpl = BYTES_PER_SPIN[dom]
         step_bytes = sum(BYTES_PER_SPIN.values())
-    traffic = measured_traffic(dom, w.name, info.heun_field, info.zchunk)
+    traffic = measured_traffic(dom, w.name, info.heun_field, info.zchunk, info.tile_rows)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
             "bytes_per_spin_algorithmic": bpl, "bytes_per_launch_algorithmic": bpl * w.N,
@@ -584,7 +589,7 @@ def heun_workload(args, w, steps=None, warmup=None, cpu=True):
                    "cells": list(w.L), "spins": w.N, "shells": w.n_shells, "T_K": w.T_K,
                    "alpha": w.alpha, "dt_fs": w.dt_fs, "field_prec": w.field_prec,
                    "parallelism": "single GPU", "stencil_engine": info.stencil_engine,
-                   "zchunk": info.zchunk, "heun_mode": info.heun_field},
+                   "zchunk": info.zchunk, "heun_mode": info.heun_field, "tile_rows": info.tile_rows},
         "roofline": roof,
         "cpu_baseline": cpu_rec,
         "kernels": kernels,
