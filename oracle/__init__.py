@@ -106,6 +106,8 @@ def lib():
         L.or_net_forward.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp, _dp, _dp, C.c_void_p]
         L.or_net_predict_loss.restype = C.c_double
         L.or_net_predict_loss.argtypes = [C.c_long, _dp, _dp, C.c_void_p, C.c_void_p]
+        L.or_net_forward_q.restype = None
+        L.or_net_forward_q.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp, _dp, _dp, C.c_void_p, C.c_int]
         L.or_net_backward.restype = C.c_double
         L.or_net_backward.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp, _dp, _dp, _dp, _dp]
         L.or_adam.restype = None
@@ -429,14 +431,16 @@ def net_nparams(ch=NET_CHANNELS):
     return lib().or_net_nparams(_i32(ch))
 
 
-def net_forward(L, params, x, ch=NET_CHANNELS, want_act=False, dil=(1, 1, 1, 1)):
+def net_forward(L, params, x, ch=NET_CHANNELS, want_act=False, dil=(1, 1, 1, 1), bf16=False):
     """Raw net output [c4][P] (and the pre-activations of every layer with
-    want_act) for input x [c0][P] on an L grid; dil: per-layer dilation."""
+    want_act) for input x [c0][P] on an L grid; dil: per-layer dilation;
+    bf16: every layer's weights and inputs rounded to float and then to
+    bfloat16 (nearest even) before an FP64 convolution."""
     Lx, Ly, Lz = (int(v) for v in L)
     P = Lx * Ly * Lz
     out = np.zeros((ch[4], P))
     act = np.zeros((sum(ch[1:]), P)) if want_act else None
-    lib().or_net_forward(Lx, Ly, Lz, _i32(ch), _i32(dil), _f64(params), _f64(x), out, _ptr(act))
+    lib().or_net_forward_q(Lx, Ly, Lz, _i32(ch), _i32(dil), _f64(params), _f64(x), out, _ptr(act), int(bool(bf16)))
     return (out, act) if want_act else out
 
 

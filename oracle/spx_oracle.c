@@ -1445,6 +1445,19 @@ void or_min_iterate(int n_sub, const int *L, const int *per, const double *cell9
  */
 static int or_dil(const int *dil, int l) { return dil ? dil[l] : 1; }
 
+/* v rounded to float, then to bfloat16 (8 significant bits), each to
+   nearest even: the operands of a BF16 matrix-core convolution that reads
+   FP32 data */
+static double or_bf16(double v) {
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    u &= 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
 static void or_conv3(int Lx, int Ly, int Lz, int cin, int cout, int d, const double *W, const double *bias,
                      const double *in, double *out) {
     const long P = (long)Lx * Ly * Lz;
@@ -1478,17 +1491,29 @@ long or_net_nparams(const int *c) {
 
 /* forward: input x [c0][P] -> raw output [c4][P]; pre-activations saved in
    `act` (layer outputs before SiLU, [c1+c2+c3+c4][P]) if non-NULL */
-void or_net_forward(int Lx, int Ly, int Lz, const int *c, const int *dil, const double *params,
-                    const double *x, double *out, double *act) {
+/* quant = 1: every layer's weights and inputs rounded by or_bf16 first (the
+   emulated operands of the BF16 form); biases and sums stay FP64 */
+void or_net_forward_q(int Lx, int Ly, int Lz, const int *c, const int *dil, const double *params,
+                      const double *x, double *out, double *act, int quant) {
     const long P = (long)Lx * Ly * Lz;
     const double *cur = x;
     double *buf[4];
     const double *w = params;
+    double *qin = NULL, *qw = NULL;
     for (int l = 0; l < 4; ++l) {
         buf[l] = (double *)malloc(sizeof(double) * c[l + 1] * P);
         const double *W = w;
         const double *bias = w + (long)c[l + 1] * c[l] * 27;
-        or_conv3(Lx, Ly, Lz, c[l], c[l + 1], or_dil(dil, l), W, bias, cur, buf[l]);
+        if (quant) {
+            const long nin = (long)c[l] * P, nw = (long)c[l + 1] * c[l] * 27;
+            qin = (double *)realloc(qin, sizeof(double) * nin);
+            qw = (double *)realloc(qw, sizeof(double) * nw);
+            for (long k = 0; k < nin; ++k) qin[k] = or_bf16(cur[k]);
+            for (long k = 0; k < nw; ++k) qw[k] = or_bf16(W[k]);
+            or_conv3(Lx, Ly, Lz, c[l], c[l + 1], or_dil(dil, l), qw, bias, qin, buf[l]);
+        } else {
+            or_conv3(Lx, Ly, Lz, c[l], c[l + 1], or_dil(dil, l), W, bias, cur, buf[l]);
+        }
         w = bias + c[l + 1];
         if (act) {
             long off = 0;
@@ -1501,6 +1526,13 @@ void or_net_forward(int Lx, int Ly, int Lz, const int *c, const int *dil, const 
     }
     memcpy(out, buf[3], sizeof(double) * c[4] * P);
     for (int l = 0; l < 4; ++l) free(buf[l]);
+    free(qin);
+    free(qw);
+}
+
+void or_net_forward(int Lx, int Ly, int Lz, const int *c, const int *dil, const double *params,
+                    const double *x, double *out, double *act) {
+    or_net_forward_q(Lx, Ly, Lz, c, dil, params, x, out, act, 0);
 }
 
 /*

@@ -613,6 +613,39 @@ def test_net_dilated_backward_matches_finite_differences():
     assert abs(l1 - loss) > 1e-6
 
 
+def _bf16_by_arithmetic(a):
+    # float32 first, then the nearest number with 8 significant bits (numpy's
+    # round is half-to-even): an arithmetic rounding, not the oracle's bit form
+    f = np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+    m, e = np.frexp(f)
+    return np.ldexp(np.round(m * 256.0) / 256.0, e)
+
+
+def test_net_bf16_operands_are_rounded_to_nearest_even():
+    # the quantised oracle mode (the BF16 form's emulated operands): layer 1's
+    # pre-activation is the correlation of the rounded input with the rounded
+    # kernel, ties included (the input holds exact halfway values)
+    from scipy.ndimage import correlate
+    rng = np.random.default_rng(8)
+    L = (6, 5, 4)
+    P = L[0] * L[1] * L[2]
+    ch = (1, 1, 1, 1, 1)
+    p = np.zeros(oracle.net_nparams(ch))
+    k1 = rng.standard_normal(27)
+    p[:27] = k1
+    p[27] = 0.125
+    x = rng.standard_normal((1, P))
+    x[0, :8] = [1 + 2 ** -8, 1 + 3 * 2 ** -8, -(1 + 2 ** -8), 1 + 2 ** -9, 1.5 + 2 ** -8, 2 ** -130, 1e-3, 3.0]
+    _, act = oracle.net_forward(L, p, x, ch=ch, want_act=True, bf16=True)
+    assert _bf16_by_arithmetic(1 + 2 ** -8) == 1.0 and _bf16_by_arithmetic(1 + 3 * 2 ** -8) == 1 + 2 ** -6
+    xr = _bf16_by_arithmetic(x).reshape(L[2], L[1], L[0])
+    ref = correlate(xr, _bf16_by_arithmetic(k1).reshape(3, 3, 3), mode="constant", cval=0.0) + 0.125
+    np.testing.assert_allclose(act[0], ref.reshape(-1), atol=1e-12)
+    # without rounding the result differs
+    _, act0 = oracle.net_forward(L, p, x, ch=ch, want_act=True)
+    assert np.max(np.abs(act0[0] - act[0])) > 1e-4
+
+
 def test_net_zero_output_returns_geodesic_guess():
     L = (3, 3, 3)
     P = 27
