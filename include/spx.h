@@ -502,6 +502,13 @@ spx_status spx_net_destroy(spx_net *net);
  * to every later forward, backward and learned initial path of the net.
  * SPX_ERR_INVALID_ARG for a value out of range. */
 spx_status spx_net_set_dilation(spx_net *net, const int32_t *dil);
+/* Arithmetic of the forward pass (spx_net_forward and the learned initial
+ * path): SPX_FP32 (default, direct convolution on the vector ALUs) or
+ * SPX_BF16_MFMA (each layer a BF16 implicit GEMM on the matrix cores:
+ * activations and weights rounded to BF16 to nearest even, FP32
+ * accumulation, bias and output in FP32).  spx_net_backward always runs in
+ * FP32.  SPX_ERR_INVALID_ARG for another precision. */
+spx_status spx_net_set_precision(spx_net *net, int32_t prec);
 spx_status spx_net_forward(spx_net *net, const float *params, const int32_t *dims, int32_t batch, const double *Sg,
                            const double *SA, const double *SB, const float *t, double *Shat, void *stream);
 /* Gradient of loss = mean over batch and sites of |S_hat - S_star|^2 with
@@ -526,6 +533,10 @@ spx_status spx_stream_probe(int32_t kind, const void *src, void *dst, int64_t n_
  * D = A B for A [32][16], B [16][32], D [32][32] ([dev] row-major float),
  * operands rounded to BF16 (prec 2) or FP16 (prec 3).  Test hook. */
 spx_status spx_mfma_probe(int32_t prec, const float *A, const float *B, float *D, void *stream);
+/* The same for the 16x16x32 BF16 MFMA of the network's BF16 form: D = A B for
+ * A [16][32], B [32][16], D [16][16] ([dev] row-major float, operands rounded
+ * to BF16).  Test hook. */
+spx_status spx_mfma16_probe(const float *A, const float *B, float *D, void *stream);
 
 /* Kernel timing instrumentation (Methods, performance measurements: device
  * time of the hot kernels).  With enable = 1 every launch of the Heun

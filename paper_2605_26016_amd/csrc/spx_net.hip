@@ -22,6 +22,15 @@
 // layer runs as the same 3^3 tiles over every phase's sub-grid of
 // ceil(L / d) sites per axis: tiles stay in sub-grid coordinates and only
 // the global addressing is strided.
+//
+// Inference may instead run every layer as a BF16 implicit GEMM on the
+// matrix cores (spx_net_set_precision): for 16 output sites x 16 output
+// channels (inputs and outputs padded to 16 channels), K runs over pairs of
+// taps x 16 input channels, 14 v_mfma_f32_16x16x32_bf16 per layer with FP32
+// accumulation.  The input tile is staged in LDS as BF16 with the channels
+// innermost, so a lane's operand fragment (8 channels of one site and tap)
+// is one 16-byte read; the weight fragments of a layer are packed from the
+// FP32 parameters by a small kernel before the layer runs.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -283,6 +292,110 @@ __global__ void k_loss_final(const double *__restrict__ part, int n, double scal
     *loss = s * scale;
 }
 
+// ---------------------------------------------------------------- BF16 MFMA form
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kTapPairs = 14;  // 27 taps in pairs, the last padded
+
+// v_mfma_f32_16x16x32_bf16, one wavefront: lane l holds A[l % 16][8 (l / 16) + j]
+// and B[8 (l / 16) + j][l % 16], j = 0..7; accumulator i of lane l is
+// D[4 (l / 16) + i][l % 16].
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Weight fragments of one layer: frag[tp][lane][j] = W[co][ci][tap] with
+// co = lane % 16, tap = 2 tp + (lane / 32), ci = 8 ((lane / 16) & 1) + j
+// (zero for co >= cout, ci >= cin or tap 27), rounded to BF16.
+__global__ void k_wfrag(const float *__restrict__ W, int cin, int cout, bf16x8 *__restrict__ frag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kTapPairs * 64) return;
+    const int tp = i / 64, lane = i % 64;
+    const int co = lane % 16, tap = 2 * tp + (lane >> 5), ci0 = 8 * ((lane >> 4) & 1);
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int ci = ci0 + j;
+        const float w = (co < cout && ci < cin && tap < 27) ? W[(co * cin + ci) * 27 + tap] : 0.0f;
+        v[j] = (__bf16)w;
+    }
+    frag[i] = v;
+}
+
+// out[co] = bias[co] + sum_ci sum_k W[co][ci][k] a[ci](p + (k - 1) d), BF16
+// operands, FP32 accumulation; the block's 8 x 8 x 4 tile is 16 groups of 16
+// sites (two y rows of one z plane), four per wavefront.
+template <int CIN, int COUT, bool SILU_IN>
+__global__ __launch_bounds__(kNT) void k_conv_mfma(const float *__restrict__ in, const bf16x8 *__restrict__ frag,
+                                                   const float *__restrict__ bias, float *__restrict__ out,
+                                                   NetDims d) {
+    __shared__ __attribute__((aligned(16))) __bf16 tile[kHalo][16];
+    const NetTile tl = tile_origin(d);
+    const float *src = in + (int64_t)blockIdx.z * CIN * d.P;
+    for (int idx = threadIdx.x; idx < 16 * kHalo; idx += kNT) {
+        const int ci = idx / kHalo, r = idx - ci * kHalo;
+        const int hx = r % kHX, hy = (r / kHX) % kHY, hz = r / (kHX * kHY);
+        const int gx = tl.px + d.dil * (tl.x0 + hx - 1), gy = tl.py + d.dil * (tl.y0 + hy - 1),
+                  gz = tl.pz + d.dil * (tl.z0 + hz - 1);
+        float v = 0.0f;
+        if (ci < CIN && gx >= 0 && gy >= 0 && gz >= 0 && gx < d.Lx && gy < d.Ly && gz < d.Lz) {
+            v = src[ci * d.P + gx + (int64_t)d.Lx * (gy + (int64_t)d.Ly * gz)];
+            if (SILU_IN) v = silu(v);
+        }
+        tile[r][ci] = (__bf16)v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    f32x4 acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[m] = f32x4{};
+#pragma unroll 2
+    for (int tp = 0; tp < kTapPairs; ++tp) {
+        const bf16x8 b = frag[tp * 64 + lane];
+        const int tap = min(2 * tp + (grp >> 1), 26);  // the padded tap's weights are zero
+        const int kx = tap % 3, ky = (tap / 3) % 3, kz = tap / 9;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int mb = 4 * wave + m;  // 16-site group: z = mb / 4, y = 2 (mb % 4) + row / 8, x = row % 8
+            const int x = row & 7, y = 2 * (mb & 3) + (row >> 3), z = mb >> 2;
+            const int h = (x + kx) + kHX * ((y + ky) + kHY * (z + kz));
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&tile[h][8 * (grp & 1)]);
+            acc[m] = mfma16(a, b, acc[m]);
+        }
+    }
+    const int co = lane & 15;
+    if (co >= COUT) return;
+    const float bco = bias[co];
+    float *dst = out + (int64_t)blockIdx.z * COUT * d.P + (int64_t)co * d.P;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int mb = 4 * wave + m;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 4 * grp + i;  // the site of accumulator i
+            const int x = tl.px + d.dil * (tl.x0 + (r & 7)), y = tl.py + d.dil * (tl.y0 + 2 * (mb & 3) + (r >> 3)),
+                      z = tl.pz + d.dil * (tl.z0 + (mb >> 2));
+            if (x < d.Lx && y < d.Ly && z < d.Lz) dst[x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z)] = acc[m][i] + bco;
+        }
+    }
+}
+
+// Lane-layout check of the 16x16x32 BF16 MFMA: D = A B for A [16][32],
+// B [32][16], D [16][16] row-major FP32 (values exact in BF16).
+__global__ void k_mfma16_probe(const float *__restrict__ A, const float *__restrict__ B, float *__restrict__ D) {
+    const int l = threadIdx.x;
+    bf16x8 a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        a[j] = (__bf16)A[(l % 16) * 32 + 8 * (l / 16) + j];
+        b[j] = (__bf16)B[(8 * (l / 16) + j) * 16 + l % 16];
+    }
+    const f32x4 c = mfma16(a, b, f32x4{});
+#pragma unroll
+    for (int i = 0; i < 4; ++i) D[(4 * (l / 16) + i) * 16 + l % 16] = c[i];
+}
+
 // Adam (Kingma & Ba) on n parameters, step t >= 1.
 __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                        float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
@@ -311,6 +424,7 @@ struct NetWork {
     size_t part_cap = 0;
     double *lpart = nullptr;
     size_t lpart_cap = 0;
+    bf16x8 *frag = nullptr;     // BF16 MFMA weight fragments, [4 layers][14][64]
 };
 
 }  // namespace spx
@@ -320,6 +434,7 @@ using namespace spx;
 struct spx_net {
     NetWork w;
     int dil[4] = {1, 1, 1, 1};  // per-layer dilation
+    int prec = SPX_FP32;        // forward (inference) arithmetic: SPX_FP32 or SPX_BF16_MFMA
 };
 
 namespace {
@@ -337,7 +452,8 @@ int64_t layer_off(int l) {
 
 void net_free(NetWork &w) {
     for (void *p : {(void *)w.x, (void *)w.z[0], (void *)w.z[1], (void *)w.z[2], (void *)w.z[3], (void *)w.g[0],
-                    (void *)w.g[1], (void *)w.g[2], (void *)w.g[3], (void *)w.wt, (void *)w.part, (void *)w.lpart})
+                    (void *)w.g[1], (void *)w.g[2], (void *)w.g[3], (void *)w.wt, (void *)w.part, (void *)w.lpart,
+                    (void *)w.frag})
         if (p) (void)hipFree(p);
     w = NetWork{};
 }
@@ -382,6 +498,29 @@ dim3 conv_grid(const NetDims &d, int B) {
     return dim3((unsigned)(nbx * nby * d.dil * d.dil), (unsigned)(nbz * d.dil), (unsigned)B);
 }
 
+// forward through the four layers as BF16 implicit GEMMs (inference); z[l]
+// are pre-activations in FP32
+hipError_t net_forward_layers_mfma(NetWork &w, const float *params, const NetDims &d, const int dil[4], int B,
+                                   hipStream_t st) {
+    if (!w.frag) {
+        hipError_t e = hipMalloc((void **)&w.frag, sizeof(bf16x8) * 4 * kTapPairs * 64);
+        if (e != hipSuccess) return e;
+    }
+    const int fb = (kTapPairs * 64 + 255) / 256;
+    for (int l = 0; l < 4; ++l)
+        k_wfrag<<<fb, 256, 0, st>>>(params + layer_off(l), kC[l], kC[l + 1], w.frag + l * kTapPairs * 64);
+    const NetDims d0 = layer_dims(d, dil, 0), d1 = layer_dims(d, dil, 1), d2 = layer_dims(d, dil, 2),
+                  d3 = layer_dims(d, dil, 3);
+    const float *b0 = params + layer_off(0) + 16 * 10 * 27, *b1 = params + layer_off(1) + 16 * 16 * 27;
+    const float *b2 = params + layer_off(2) + 16 * 16 * 27, *b3 = params + layer_off(3) + 3 * 16 * 27;
+    bf16x8 *f = w.frag;
+    k_conv_mfma<10, 16, false><<<conv_grid(d0, B), kNT, 0, st>>>(w.x, f, b0, w.z[0], d0);
+    k_conv_mfma<16, 16, true><<<conv_grid(d1, B), kNT, 0, st>>>(w.z[0], f + kTapPairs * 64, b1, w.z[1], d1);
+    k_conv_mfma<16, 16, true><<<conv_grid(d2, B), kNT, 0, st>>>(w.z[1], f + 2 * kTapPairs * 64, b2, w.z[2], d2);
+    k_conv_mfma<16, 3, true><<<conv_grid(d3, B), kNT, 0, st>>>(w.z[2], f + 3 * kTapPairs * 64, b3, w.z[3], d3);
+    return hipGetLastError();
+}
+
 // forward through the four layers; z[l] are pre-activations
 hipError_t net_forward_layers(NetWork &w, const float *params, const NetDims &d, const int dil[4], int B,
                               hipStream_t st) {
@@ -424,7 +563,8 @@ spx_status net_apply(spx_net *net, const float *params, const int32_t dims[3], i
     if ((s = net_reserve(net->w, d.P, batch, false)) != SPX_OK) return s;
     const dim3 pg((unsigned)((d.P + kNT - 1) / kNT), (unsigned)batch);
     k_net_input<<<pg, kNT, 0, st>>>(Sg, SA, SB, t, net->w.x, d.P, shared_ends ? 0 : 3 * d.P);
-    hipError_t e = net_forward_layers(net->w, params, d, net->dil, batch, st);
+    hipError_t e = net->prec == SPX_BF16_MFMA ? net_forward_layers_mfma(net->w, params, d, net->dil, batch, st)
+                                              : net_forward_layers(net->w, params, d, net->dil, batch, st);
     if (e == hipSuccess) {
         k_net_head<<<pg, kNT, 0, st>>>(net->w.z[3], Sg, nullptr, Shat, nullptr, nullptr, d.P, 0.0);
         e = hipGetLastError();
@@ -459,6 +599,22 @@ spx_status spx_net_set_dilation(spx_net *net, const int32_t *dil) {
         if (dil[l] < 1 || dil[l] > kMaxDilation)
             return set_error(SPX_ERR_INVALID_ARG, "each dilation must be 1 .. 64");
     for (int l = 0; l < 4; ++l) net->dil[l] = dil[l];
+    return SPX_OK;
+}
+
+spx_status spx_net_set_precision(spx_net *net, int32_t prec) {
+    if (!handle_alive(net)) return set_error(SPX_ERR_BAD_HANDLE, "invalid spx_net handle");
+    if (prec != SPX_FP32 && prec != SPX_BF16_MFMA)
+        return set_error(SPX_ERR_INVALID_ARG, "the network runs in SPX_FP32 or SPX_BF16_MFMA");
+    net->prec = prec;
+    return SPX_OK;
+}
+
+spx_status spx_mfma16_probe(const float *A, const float *B, float *D, void *stream) {
+    if (!A || !B || !D) return set_error(SPX_ERR_INVALID_ARG, "NULL argument");
+    k_mfma16_probe<<<1, 64, 0, (hipStream_t)stream>>>(A, B, D);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(e, "spx_mfma16_probe");
     return SPX_OK;
 }
 

@@ -315,11 +315,41 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
     rp = converge(Hs, Yp, tol=1e-3, max_iter=max_iter, chunk=250, log=log, what=f"{family} test geodesic")
     rl = converge(Hs, Yl, tol=1e-3, max_iter=max_iter, chunk=250, method=1, net=net, params=p, log=log,
                   what=f"{family} test learned")
+    # the same learned initial paths with the network in BF16 on the matrix
+    # cores: the initial path's cost and distance from the FP32 one, and GNEB
+    # from it (the endpoints of the relaxed buffers are the original ones)
+    import torch
+    Yf = [y.clone() for y in Yl]
+    Yb = [y.clone() for y in Yl]
+    gf = spx.gneb_create(Hs, Yf)
+    gb = spx.gneb_create(Hs, Yb)
+    init_ms = {}
+    for prec, g in (("fp32", gf), ("bf16", gb)):
+        spx.net_set_precision(net, prec)
+        spx.gneb_init_path(g, method=1, net=net, params=p)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            spx.gneb_init_path(g, method=1, net=net, params=p)
+        e1.record()
+        torch.cuda.synchronize()
+        init_ms[prec] = e0.elapsed_time(e1) / 10
+    d_bf16 = max(float((a - b).abs().max()) for a, b in zip(Yf, Yb))
+    del gf, gb, Yf
+    rb = converge(Hs, Yb, tol=1e-3, max_iter=max_iter, chunk=250, method=1, net=net, params=p, log=log,
+                  what=f"{family} test learned bf16")
+    spx.net_set_precision(net, "fp32")
+    log(f"[path-init] {family}: initial paths of the test batch {init_ms['fp32']:.2f} ms FP32, "
+        f"{init_ms['bf16']:.2f} ms BF16 MFMA, max |dS| {d_bf16:.2e}")
     both = [k for k in range(len(Yp)) if rp.converged[k] and rl.converged[k]]
     dbar = np.abs(rl.barrier - rp.barrier)
     same = [k for k in both if dbar[k] <= 0.1]
     it_p = float(np.mean(rp.iterations[same])) if same else None
     it_l = float(np.mean(rl.iterations[same])) if same else None
+    same_b = [k for k in range(len(Yp)) if rp.converged[k] and rb.converged[k] and abs(rb.barrier[k] - rp.barrier[k]) <= 0.1]
+    it_pb = float(np.mean(rp.iterations[same_b])) if same_b else None
+    it_b = float(np.mean(rb.iterations[same_b])) if same_b else None
     log(f"[path-init] {family}: {len(same)}/{len(Yp)} test pairs in the same channel; iterations learned "
         f"{it_l} vs geodesic {it_p}")
     return {"lattices_train": [list(lat(e)) for e, _ in train_sizes], "train_share": [sh for _, sh in train_sizes],
@@ -333,4 +363,9 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
             "mean_iterations_geodesic_same_channel": it_p, "mean_iterations_learned_same_channel": it_l,
             "iteration_ratio_learned_over_geodesic": (it_l / it_p) if same else None,
             "max_barrier_difference_same_channel_meV": float(np.max(dbar[same])) if same else None,
+            "init_ms_test_batch": {"fp32": init_ms["fp32"], "bf16_mfma": init_ms["bf16"]},
+            "init_bf16_vs_fp32_max_dS": d_bf16, "iterations_learned_bf16": rb.iterations.tolist(),
+            "same_channel_bf16_within_0.1meV": len(same_b),
+            "mean_iterations_geodesic_same_channel_bf16": it_pb,
+            "mean_iterations_learned_bf16_same_channel": it_b,
             "train_loss_first_last": [hist[0], hist[-1]], "seconds": time.perf_counter() - t0}

@@ -120,6 +120,8 @@ def load(path: str = LIB_PATH):
         "spx_net_create": [vp, C.POINTER(vp)],
         "spx_net_destroy": [vp],
         "spx_net_set_dilation": [vp, C.POINTER(C.c_int32)],
+        "spx_net_set_precision": [vp, i32],
+        "spx_mfma16_probe": [vp, vp, vp, vp],
         "spx_net_forward": [vp, vp, C.POINTER(C.c_int32), i32, vp, vp, vp, vp, vp, vp],
         "spx_net_backward": [vp, vp, C.POINTER(C.c_int32), i32, vp, vp, vp, vp, vp, vp, vp, vp],
         "spx_net_adam_step": [vp, vp, vp, vp, i64, i64, dbl, dbl, dbl, dbl, vp],
@@ -604,6 +606,16 @@ def net_set_dilation(net, dil):
     d = (C.c_int32 * 4)(*[int(v) for v in dil])
     _check(load().spx_net_set_dilation(net.handle, d), "spx_net_set_dilation")
     net.dilation = tuple(int(v) for v in dil)
+
+
+def net_set_precision(net, prec):
+    """Forward arithmetic of the net: "fp32" or "bf16" (BF16 MFMA)."""
+    p = {"fp32": PREC["fp32"], "bf16": PREC["bf16"]}[prec] if isinstance(prec, str) else int(prec)
+    _check(load().spx_net_set_precision(net.handle, p), "spx_net_set_precision")
+
+
+def mfma16_probe(A, B, D, stream=None):
+    _check(load().spx_mfma16_probe(_ptr(A), _ptr(B), _ptr(D), _stream(stream)), "spx_mfma16_probe")
 
 
 def net_nparams() -> int:

@@ -170,6 +170,65 @@ def test_net_dilation_is_validated():
             spx.net_set_dilation(net, bad)
 
 
+def test_mfma16_lane_layout_probe():
+    # the 16x16x32 BF16 MFMA of the net's BF16 form, with the lane layout the
+    # kernel assumes: small integers are exact in BF16 and their products and
+    # sums exact in FP32
+    import torch
+    from paper_2605_26016_amd import spx
+    rng = np.random.default_rng(9)
+    A = rng.integers(-8, 9, (16, 32)).astype(np.float32)
+    B = rng.integers(-8, 9, (32, 16)).astype(np.float32)
+    D = torch.zeros((16, 16), dtype=torch.float32, device="cuda")
+    spx.mfma16_probe(to_dev(A), to_dev(B), D)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(D.cpu().numpy(), A @ B)
+
+
+@pytest.mark.parametrize("L,dil", [((19, 13, 11), (1, 1, 1, 1)), ((21, 17, 10), (1, 2, 4, 8))], ids=["d1", "d1248"])
+def test_net_bf16_forward_matches_emulated_oracle(L, dil):
+    # the BF16 implicit-GEMM form against the oracle with every layer's
+    # weights and inputs rounded as the kernel rounds them (FP32, then BF16)
+    # and FP64 sums; the kernel's FP32 pre-activations and SiLU can move an
+    # activation across a BF16 rounding boundary now and then (one BF16 ulp,
+    # 2^-8 relative, in one of the 432 terms of a later layer), hence 2e-3
+    # of max |u| on the corrected image.  The error against the unrounded
+    # FP64 network is printed and bounded loosely (BF16 keeps 8 bits).
+    import torch
+    from paper_2605_26016_amd import spx
+    B = 2
+    p32 = init_params(6, scale=1.0)
+    Sg, SA, SB, _, t = batch_case(L, B, 60)
+    P = L[0] * L[1] * L[2]
+    net = spx.Net(dilation=dil)
+    spx.net_set_precision(net, "bf16")
+    out = torch.zeros((B, 3, P), dtype=torch.float64, device="cuda")
+    spx.net_forward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    p64 = p32.astype(np.float64)
+    for b in range(B):
+        x = oracle_x(Sg[b], SA[b], SB[b], t[b])
+        rq = oracle.net_forward(L, p64, x, dil=dil, bf16=True)
+        refq, _ = oracle.net_predict_loss(rq, Sg[b])
+        r64 = oracle.net_forward(L, p64, x, dil=dil)
+        ref64, _ = oracle.net_predict_loss(r64, Sg[b])
+        eq = float(np.max(np.abs(got[b] - refq)))
+        mq = float(np.mean(np.abs(got[b] - refq)))
+        e64 = float(np.max(np.abs(got[b] - ref64)))
+        scale = max(1.0, float(np.max(np.abs(rq))))
+        print(f"bf16 {L} {dil} image {b}: vs emulated oracle max {eq:.2e} mean {mq:.2e}; vs FP64 net "
+              f"max {e64:.2e} (max |u| {np.max(np.abs(r64)):.2f})", flush=True)
+        assert eq <= 2e-3 * scale and mq <= 1e-5 * scale
+        assert e64 <= 5e-2 * scale
+    # FP32 again after switching back
+    spx.net_set_precision(net, "fp32")
+    spx.net_forward(net, to_dev(p32), L, B, to_dev(Sg), to_dev(SA), to_dev(SB), to_dev(t), out)
+    r64 = oracle.net_forward(L, p64, oracle_x(Sg[0], SA[0], SB[0], t[0]), dil=dil)
+    ref64, _ = oracle.net_predict_loss(r64, Sg[0])
+    assert np.max(np.abs(out[0].cpu().numpy() - ref64)) <= 1e-5 * max(1.0, float(np.max(np.abs(r64))))
+
+
 def test_adam_matches_oracle():
     import torch
     from paper_2605_26016_amd import spx
@@ -217,6 +276,22 @@ def test_learned_init_with_zero_net_is_geodesic_and_nonzero_matches_forward():
         ref, _ = oracle.net_predict_loss(raw, geo[n])
         assert np.max(np.abs(got[n] - ref)) < 1e-5
     assert np.array_equal(got[0], A) and np.array_equal(got[-1], Bv)
+    # the same initial path with the network in BF16 on the matrix cores,
+    # against the oracle that rounds the same operands to BF16 (a rounding
+    # flip moves a raw output by up to a few 1e-3)
+    spx.net_set_precision(net, "bf16")
+    Yd3 = to_dev(Y)
+    g3 = spx.gneb_create([gpu_hamiltonian(w)], [Yd3])
+    spx.gneb_init_path(g3, method=1, net=net, params=to_dev(p32))
+    torch.cuda.synchronize()
+    got = Yd3.cpu().numpy()
+    for n in range(1, n_img - 1):
+        tn = np.float32(n / (n_img - 1))
+        raw = oracle.net_forward(w.L, p64, oracle_x(geo[n], A, Bv, tn), bf16=True)
+        ref, _ = oracle.net_predict_loss(raw, geo[n])
+        assert np.max(np.abs(got[n] - ref)) < 5e-3
+        assert np.max(np.abs(np.sum(got[n] ** 2, axis=0) - 1.0)) < 1e-12
+    assert np.array_equal(got[0], A) and np.array_equal(got[-1], Bv)
 
 
 def test_trained_net_saves_gneb_iterations_at_equal_barrier():
@@ -231,7 +306,9 @@ def test_trained_net_saves_gneb_iterations_at_equal_barrier():
                                      dilation=(1, 1, 1, 1))
     print({k: r[k] for k in ("same_channel_within_0.1meV", "mean_iterations_geodesic_same_channel",
                              "mean_iterations_learned_same_channel", "iteration_ratio_learned_over_geodesic",
-                             "train_loss_first_last", "seconds")}, flush=True)
+                             "train_loss_first_last", "init_ms_test_batch", "init_bf16_vs_fp32_max_dS",
+                             "same_channel_bf16_within_0.1meV", "mean_iterations_learned_bf16_same_channel",
+                             "seconds")}, flush=True)
     assert r["test_converged_both"] == r["test_paths"]
     assert r["same_channel_within_0.1meV"] >= (2 * r["test_paths"]) // 3
     assert r["train_loss_first_last"][1] < 0.5 * r["train_loss_first_last"][0]
