@@ -267,7 +267,7 @@ def mc_workload(args):
                       "shells": [list(J) for J in MC_SHELLS], "parallelism": "single GPU"},
            "roofline": {"bound": "hbm", "achieved": rate * MC_BYTES / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": rate * MC_BYTES / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "k_mc_colour (heat-bath, one shell, 2 colours)",
+                        "kernel": "k_mc_colour_cm (heat-bath, one shell, 2 colours)",
                         "bytes_per_update_algorithmic": MC_BYTES},
            "table": table}
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_mc_baseline(args.cpu_seconds)

@@ -16,6 +16,22 @@
 // Random numbers: one Philox4x32-10 block per (site, sweep), counter
 // (i lo, i hi ^ tag, sweep lo, sweep hi), key (seed lo, seed hi), uniforms
 // (x + 1/2) 2^-32, tag kMcTag.
+//
+// Colour-major layout.  In the natural layout the sites of one colour sit
+// C apart along every row, so each launch touches every cache line of the
+// state.  A call of several sweeps therefore copies the state once into rows
+// ordered by colour class, [x mod C][x div C] with pitch C J (J =
+// ceil(Lx / C)), runs every launch there and copies it back: a colour's sites
+// of one row are then one contiguous run of J, and so are the runs of every
+// neighbour class it reads.  The neighbour through bond p of a site in class
+// x0 lies at a fixed offset from the site's slot, tabulated per (p, x0) for
+// the three cases of its x (wrapped up, inside, wrapped down); a wrap in y or
+// z shifts it by whole rows, and a bond across an open face is left out, so
+// every site of a launch takes the same path (lattices with a bond longer
+// than an extent wrap coordinates by a true modulo instead).
+// The bonds are summed in the same order with the same arithmetic, and the
+// Philox counter is the natural site index, so both layouts give the same
+// bits.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -24,6 +40,7 @@
 
 #include "spx_device.hpp"
 #include "spx_ext.hpp"
+#include "spx_mc_math.hpp"
 
 namespace spx {
 
@@ -36,6 +53,9 @@ struct MCState {
     double *d_part = nullptr;             // magnetisation block partials [kMagBlocks][3]
     int64_t *d_off = nullptr;             // linear index offset of every bond (interior sites)
     int rad[3] = {0, 0, 0};               // largest |delta| of the bonds along each axis
+    int64_t *d_coff = nullptr;            // colour-major slot offset per (bond, class x0), [n_bonds][C]
+    double *d_cm = nullptr;               // colour-major copy of the state, 3 x n_rows x C J
+    size_t cm_cap = 0;                    // doubles held by d_cm
 };
 
 void mc_destroy(MCState *m) {
@@ -43,6 +63,8 @@ void mc_destroy(MCState *m) {
     if (m->d_acc) (void)hipFree(m->d_acc);
     if (m->d_part) (void)hipFree(m->d_part);
     if (m->d_off) (void)hipFree(m->d_off);
+    if (m->d_coff) (void)hipFree(m->d_coff);
+    if (m->d_cm) (void)hipFree(m->d_cm);
     delete m;
 }
 
@@ -85,6 +107,76 @@ __device__ __forceinline__ double aniso_energy(const Onsite &os, int a, const do
     return e;
 }
 
+// The move of site i (natural index) in field b: one Philox block for (i,
+// sweep).  Heat-bath draws the new spin from exp(beta b.s) on the sphere;
+// Metropolis proposes a uniform direction and accepts it if u2 <
+// exp(-beta dH) (si: the current spin).  Returns 1 for an accepted move
+// (heat-bath: always).
+template <int METHOD>
+__device__ __forceinline__ unsigned mc_move(const Onsite &os, int a, const double b[3], const double si[3],
+                                            double beta, uint64_t seed, uint64_t sweep, int64_t i, double sn[3]) {
+    uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32) ^ kMcTag;
+    uint32_t c2 = (uint32_t)sweep, c3 = (uint32_t)(sweep >> 32);
+    philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double sc = 2.3283064365386963e-10;  // 2^-32
+    const double u0 = ((double)c0 + 0.5) * sc, u1 = ((double)c1 + 0.5) * sc;
+    if (METHOD == 0) {
+        // heat-bath: cos to b from the inverse distribution function of
+        // exp(x c) on [-1, 1], c = 1 + ln(1 + (1 - u0)(e^(-2x) - 1)) / x,
+        // azimuth 2 pi u1 in the frame around b
+        const double n2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+        double cth, e3[3] = {0.0, 0.0, 1.0};
+        if (n2 > 0.0) {
+            // |b| below 2^-511 is scaled by 2^600 first (exact), so that the
+            // squared norm is a normal number
+            const bool tiny = n2 < 0x1p-1022;
+            const double sf = tiny ? 0x1p600 : 1.0;
+            const double c[3] = {b[0] * sf, b[1] * sf, b[2] * sf};
+            const double m2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+            const double rn = rsqrt_pos(m2);
+            const double xb = beta * ((m2 * rn) * (tiny ? 0x1p-600 : 1.0));
+            for (int q = 0; q < 3; ++q) e3[q] = c[q] * rn;
+            cth = 1.0 + div_pos(log1p_neg((1.0 - u0) * expm1_nonpos(-2.0 * xb)), xb);
+        } else {
+            cth = 2.0 * u0 - 1.0;
+        }
+        cth = fmin(fmax(cth, -1.0), 1.0);
+        double e1[3], e2[3];
+        frame(e3, e1, e2);
+        const double v = 1.0 - cth * cth;
+        const double st = v > 0.0 ? sqrt_pos(v) : 0.0;
+        double sp, cp;
+        sincospi_d(2.0 * u1, sp, cp);
+        for (int q = 0; q < 3; ++q) sn[q] = cth * e3[q] + st * (cp * e1[q] + sp * e2[q]);
+        return 1u;
+    } else {
+        // Metropolis: uniform trial direction, accepted if u2 < exp(-beta dH)
+        // (always when dH <= 0, since u2 < 1)
+        const double u2 = ((double)c2 + 0.5) * sc;
+        const double zt = 2.0 * u0 - 1.0, v = 1.0 - zt * zt;
+        const double r = v > 0.0 ? sqrt_pos(v) : 0.0;
+        double sp, cp;
+        sincospi_d(2.0 * u1, sp, cp);
+        const double tr[3] = {r * cp, r * sp, zt};
+        const double dH = -((tr[0] - si[0]) * b[0] + (tr[1] - si[1]) * b[1] + (tr[2] - si[2]) * b[2]) +
+                          aniso_energy(os, a, tr) - aniso_energy(os, a, si);
+        const double y = -beta * dH;
+        const bool ok = y >= 0.0 || u2 < exp_nonpos(y);
+        for (int q = 0; q < 3; ++q) sn[q] = ok ? tr[q] : si[q];
+        return ok ? 1u : 0u;
+    }
+}
+
+// Workgroups are dealt to the 8 XCDs in turn (block b to XCD b mod 8); this
+// renumbering gives each XCD one contiguous range of blocks instead, so the
+// neighbour rows (y +- 1, z +- 1) that a block reads were mostly fetched by
+// blocks of the same XCD and come from its L2.
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t T = gridDim.x, b = blockIdx.x;
+    const int64_t q = T / 8, r = T % 8, k = b % 8;
+    return k * q + (k < r ? k : r) + b / 8;
+}
+
 // One colour of one sweep.  Thread t covers x-slot j = t % J of row (y, z, a)
 // = t / J, J = ceil(Lx / C): the row's sites of colour c are x = x0 + C j.
 // Bilinear field of an interior site (every neighbour inside the lattice):
@@ -123,7 +215,7 @@ __global__ __launch_bounds__(kMcB) void k_mc_colour(double *__restrict__ S, Bond
     const int64_t total = n_rows * J;
     const int64_t N = g.N;
     unsigned int accepted = 0;
-    for (int64_t t = (int64_t)blockIdx.x * kMcB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kMcB) {
+    for (int64_t t = xcd_block() * kMcB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kMcB) {
         // slot -> (j, y, z, a); 32-bit division when the slot count fits
         // (every lattice below 2^32 slots), which is far cheaper than the
         // 64-bit routine
@@ -158,52 +250,167 @@ __global__ __launch_bounds__(kMcB) void k_mc_colour(double *__restrict__ S, Bond
             bil_sum<double, ISO, 1>(tb, g, a, x, y, z, src, bl);
         }
         const double b[3] = {bl[0][0] + os.bz[a][0], bl[0][1] + os.bz[a][1], bl[0][2] + os.bz[a][2]};
-        uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32) ^ kMcTag;
-        uint32_t c2 = (uint32_t)sweep, c3 = (uint32_t)(sweep >> 32);
-        philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
-        const double sc = 2.3283064365386963e-10;  // 2^-32
-        const double u0 = ((double)c0 + 0.5) * sc, u1 = ((double)c1 + 0.5) * sc;
-        double sn[3];
-        if (METHOD == 0) {
-            // heat-bath: cos to b from the inverse distribution function of
-            // exp(x c) on [-1, 1], azimuth 2 pi u1 in the frame around b
-            const double bn = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-            const double xb = beta * bn;
-            double cth = xb > 0.0 ? 1.0 + log1p((1.0 - u0) * expm1(-2.0 * xb)) / xb : 2.0 * u0 - 1.0;
-            cth = fmin(fmax(cth, -1.0), 1.0);
-            double e3[3] = {0.0, 0.0, 1.0};
-            if (bn > 0.0)
-                for (int q = 0; q < 3; ++q) e3[q] = b[q] / bn;
-            double e1[3], e2[3];
-            frame(e3, e1, e2);
-            const double st = sqrt(fmax(0.0, 1.0 - cth * cth));
-            double sp, cp;
-            sincospi(2.0 * u1, &sp, &cp);
-            for (int q = 0; q < 3; ++q) sn[q] = cth * e3[q] + st * (cp * e1[q] + sp * e2[q]);
-            ++accepted;
-        } else {
-            // Metropolis: uniform trial direction, accepted if u2 < exp(-beta dH)
-            const double u2 = ((double)c2 + 0.5) * sc;
-            const double zt = 2.0 * u0 - 1.0, r = sqrt(fmax(0.0, 1.0 - zt * zt));
-            double sp, cp;
-            sincospi(2.0 * u1, &sp, &cp);
-            const double tr[3] = {r * cp, r * sp, zt};
-            double si[3];
+        double si[3] = {0.0, 0.0, 0.0};
+        if (METHOD == 1) {
             si[0] = S[i];
             si[1] = S[N + i];
             si[2] = S[2 * N + i];
-            const double dH = -((tr[0] - si[0]) * b[0] + (tr[1] - si[1]) * b[1] + (tr[2] - si[2]) * b[2]) +
-                              aniso_energy(os, a, tr) - aniso_energy(os, a, si);
-            const bool ok = u2 < exp(-beta * dH);
-            for (int q = 0; q < 3; ++q) sn[q] = ok ? tr[q] : si[q];
-            accepted += ok ? 1u : 0u;
         }
+        double sn[3];
+        accepted += mc_move<METHOD>(os, a, b, si, beta, seed, sweep, i, sn);
         S[i] = sn[0];
         S[N + i] = sn[1];
         S[2 * N + i] = sn[2];
     }
     if (acc) {
         // integer counts: the order of the atomic additions does not matter
+        unsigned int w = accepted;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_down(w, off, 64);
+        if ((threadIdx.x & 63) == 0 && w) atomicAdd(acc, (unsigned long long)w);
+    }
+}
+
+// The colour-major slot of natural site (x, row r): r C J + (x mod C) J + x div C.
+struct CmDims {
+    int C, J;
+    int64_t n_rows, NP;  // rows (y, z, a) and doubles per component
+};
+
+__device__ __forceinline__ int64_t cm_slot(const CmDims &d, int64_t r, int x) {
+    return r * ((int64_t)d.C * d.J) + (int64_t)(x % d.C) * d.J + x / d.C;
+}
+
+// Natural <-> colour-major copy (to_cm: S -> P, else P -> S), one thread per
+// colour-major slot; slots past the end of a row hold zero.
+__global__ __launch_bounds__(kMcB) void k_mc_permute(const double *__restrict__ src, double *__restrict__ dst,
+                                                     int Lx, int64_t N, CmDims d, int to_cm) {
+    const int64_t pitch = (int64_t)d.C * d.J;
+    for (int64_t q = (int64_t)blockIdx.x * kMcB + threadIdx.x; q < d.NP; q += (int64_t)gridDim.x * kMcB) {
+        const int64_t r = q / pitch;
+        const int k = (int)(q - r * pitch);
+        const int x0 = k / d.J, j = k - x0 * d.J;
+        const int x = x0 + d.C * j;
+        const int64_t i = x + (int64_t)Lx * r;  // natural index (rows are contiguous in it)
+        if (to_cm) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dst[c * d.NP + q] = x < Lx ? src[c * N + i] : 0.0;
+        } else if (x < Lx) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dst[c * N + i] = src[c * d.NP + q];
+        }
+    }
+}
+
+// One colour of one sweep on the colour-major copy P: the natural kernel's
+// site loop, draw and update, with every spin addressed by its colour-major
+// slot.
+template <bool ISO, int METHOD, int UNR>
+__global__ __launch_bounds__(kMcB) void k_mc_colour_cm(double *__restrict__ P, BondTable tb, Grid g, Onsite os,
+                                                       McColour col, int c, double beta, uint64_t seed,
+                                                       uint64_t sweep, unsigned long long *__restrict__ acc,
+                                                       const int64_t *__restrict__ coff, CmDims d) {
+    const int C = col.C;
+    const int J = d.J;
+    const int64_t total = d.n_rows * J;
+    const int64_t NP = d.NP;
+    const int64_t pitch = (int64_t)C * J;
+    const int64_t ly_rows = (int64_t)g.Ly * pitch, lz_rows = (int64_t)g.Lz * ly_rows;  // y and z wraps
+    unsigned int accepted = 0;
+    for (int64_t t = xcd_block() * kMcB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kMcB) {
+        int j, y, z, a;
+        int64_t row;
+        if (total <= (int64_t)0xffffffffll) {
+            const uint32_t tt = (uint32_t)t, uJ = (uint32_t)J, uLy = (uint32_t)g.Ly, uLz = (uint32_t)g.Lz;
+            const uint32_t rw = tt / uJ;
+            const uint32_t yz = rw / uLy;
+            j = (int)(tt - rw * uJ);
+            y = (int)(rw - yz * uLy);
+            a = (int)(yz / uLz);
+            z = (int)(yz - (uint32_t)a * uLz);
+            row = rw;
+        } else {
+            row = t / J;
+            j = (int)(t % J);
+            y = (int)(row % g.Ly);
+            z = (int)((row / g.Ly) % g.Lz);
+            a = (int)(row / ((int64_t)g.Ly * g.Lz));
+        }
+        int x0 = (c - col.ky * y - col.kz * z - col.o[a]) % C;
+        if (x0 < 0) x0 += C;
+        const int x = x0 + C * j;
+        if (x >= g.Lx) continue;
+        const int64_t i = x + (int64_t)g.Lx * row;              // natural index (the Philox counter)
+        const int64_t own = row * pitch + (int64_t)x0 * J + j;  // colour-major slot
+        double bl[3] = {0.0, 0.0, 0.0};
+        const int p0 = tb.start[a], p1 = tb.start[a + 1];
+        if (!g.wrap_general) {
+            // every site alike: a neighbour across a periodic face is one
+            // wrap away (the x-side table entry and a row shift of Ly or
+            // Ly Lz rows); across an open face the bond is left out
+#pragma unroll UNR
+            for (int p = p0; p < p1; ++p) {
+                const int4 gq = tb.geo[p];
+                const int xs = x + gq.y, ys = y + gq.z, zs = z + gq.w;
+                const int side = xs < 0 ? 0 : (xs >= g.Lx ? 2 : 1);
+                const bool ok = (side == 1 || g.per[0]) && ((unsigned)ys < (unsigned)g.Ly || g.per[1]) &&
+                                ((unsigned)zs < (unsigned)g.Lz || g.per[2]);
+                int64_t q = own + coff[(3 * p + side) * C + x0];
+                q += ys < 0 ? ly_rows : (ys >= g.Ly ? -ly_rows : 0);
+                q += zs < 0 ? lz_rows : (zs >= g.Lz ? -lz_rows : 0);
+                if (ok) {
+                    const double s0 = P[q], s1 = P[NP + q], s2 = P[2 * NP + q];
+                    if constexpr (ISO) {
+                        const double Jp = tb.Jd[p];
+                        bl[0] += Jp * s0;
+                        bl[1] += Jp * s1;
+                        bl[2] += Jp * s2;
+                    } else {
+                        const double *Jp = tb.Jd + 9 * p;
+                        bl[0] += Jp[0] * s0 + Jp[1] * s1 + Jp[2] * s2;
+                        bl[1] += Jp[3] * s0 + Jp[4] * s1 + Jp[5] * s2;
+                        bl[2] += Jp[6] * s0 + Jp[7] * s1 + Jp[8] * s2;
+                    }
+                }
+            }
+        } else {
+            // bonds longer than an extent: coordinates wrapped by a true modulo
+            for (int p = p0; p < p1; ++p) {
+                const int4 gq = tb.geo[p];
+                bool ok = true;
+                const int xx = wrap_coord(x + gq.y, g.Lx, g.per[0], g.wrap_general, ok);
+                const int yy = wrap_coord(y + gq.z, g.Ly, g.per[1], g.wrap_general, ok);
+                const int zz = wrap_coord(z + gq.w, g.Lz, g.per[2], g.wrap_general, ok);
+                if (!ok) continue;
+                const int64_t q = cm_slot(d, yy + (int64_t)g.Ly * (zz + (int64_t)g.Lz * gq.x), xx);
+                const double s0 = P[q], s1 = P[NP + q], s2 = P[2 * NP + q];
+                if constexpr (ISO) {
+                    const double Jp = tb.Jd[p];
+                    bl[0] += Jp * s0;
+                    bl[1] += Jp * s1;
+                    bl[2] += Jp * s2;
+                } else {
+                    const double *Jp = tb.Jd + 9 * p;
+                    bl[0] += Jp[0] * s0 + Jp[1] * s1 + Jp[2] * s2;
+                    bl[1] += Jp[3] * s0 + Jp[4] * s1 + Jp[5] * s2;
+                    bl[2] += Jp[6] * s0 + Jp[7] * s1 + Jp[8] * s2;
+                }
+            }
+        }
+        const double b[3] = {bl[0] + os.bz[a][0], bl[1] + os.bz[a][1], bl[2] + os.bz[a][2]};
+        double si[3] = {0.0, 0.0, 0.0};
+        if (METHOD == 1) {
+            si[0] = P[own];
+            si[1] = P[NP + own];
+            si[2] = P[2 * NP + own];
+        }
+        double sn[3];
+        accepted += mc_move<METHOD>(os, a, b, si, beta, seed, sweep, i, sn);
+        P[own] = sn[0];
+        P[NP + own] = sn[1];
+        P[2 * NP + own] = sn[2];
+    }
+    if (acc) {
         unsigned int w = accepted;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) w += __shfl_down(w, off, 64);
@@ -401,13 +608,58 @@ spx_status mc_colouring(spx_ham *h, const HamView &v, MCState *m) {
         m->rad[1] = std::max(m->rad[1], std::abs(dy));
         m->rad[2] = std::max(m->rad[2], std::abs(dz));
     }
+    // colour-major slot offset of every bond from a site of class x0, for
+    // the neighbour's x below 0 (wrapped up by Lx), inside, and at or above
+    // Lx (wrapped down): neighbour x' = cls + C (j + dv), row r + dr (rows
+    // wrapped on y and z are shifted by the kernel)
+    const int C = col.C, JC = (g.Lx + C - 1) / C;
+    const int64_t pitch = (int64_t)C * JC;
+    std::vector<int64_t> coff((size_t)std::max(info.n_bonds, 1) * 3 * C, 0);
+    for (int p = 0; p < info.n_bonds; ++p) {
+        const int dx = dli[3 * p], dy = dli[3 * p + 1], dz = dli[3 * p + 2];
+        const int64_t dr = dy + (int64_t)g.Ly * (dz + (int64_t)g.Lz * (abi[2 * p + 1] - abi[2 * p]));
+        for (int side = 0; side < 3; ++side)
+            for (int x0 = 0; x0 < C; ++x0) {
+                const int xs = x0 + dx + (side == 0 ? g.Lx : (side == 2 ? -g.Lx : 0));
+                const int cls = ((xs % C) + C) % C;
+                const int dv = (xs - cls) / C;  // exact
+                coff[((size_t)p * 3 + side) * C + x0] = dr * pitch + (int64_t)(cls - x0) * JC + dv;
+            }
+    }
     if (hipMalloc((void **)&m->d_off, sizeof(int64_t) * off.size()) != hipSuccess ||
-        hipMemcpy(m->d_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(m->d_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc((void **)&m->d_coff, sizeof(int64_t) * coff.size()) != hipSuccess ||
+        hipMemcpy(m->d_coff, coff.data(), sizeof(int64_t) * coff.size(), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipGetLastError();
+        if (m->d_off) (void)hipFree(m->d_off);
+        if (m->d_coff) (void)hipFree(m->d_coff);
+        m->d_off = nullptr;
+        m->d_coff = nullptr;
         m->C = 0;
         return set_error(SPX_ERR_OUT_OF_MEMORY, "Monte Carlo bond offsets");
     }
     return SPX_OK;
+}
+
+// Dimensions of the colour-major copy and, on first use, its buffer; false
+// if it cannot be allocated (the sweeps then run in the natural layout).
+bool mc_cm_buffer(const Grid &g, MCState *m, CmDims &d) {
+    d.C = m->C;
+    d.J = (g.Lx + m->C - 1) / m->C;
+    d.n_rows = (int64_t)g.Ly * g.Lz * g.n_sub;
+    d.NP = d.n_rows * d.C * d.J;
+    const size_t need = 3 * (size_t)d.NP;
+    if (m->cm_cap >= need) return true;
+    if (m->d_cm) (void)hipFree(m->d_cm);
+    m->d_cm = nullptr;
+    m->cm_cap = 0;
+    if (hipMalloc((void **)&m->d_cm, sizeof(double) * need) != hipSuccess) {
+        (void)hipGetLastError();
+        m->d_cm = nullptr;
+        return false;
+    }
+    m->cm_cap = need;
+    return true;
 }
 
 }  // namespace
@@ -503,9 +755,29 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
     int max_bonds = 0;
     for (int a = 0; a < v.grid.n_sub; ++a) max_bonds = std::max(max_bonds, v.tab.start[a + 1] - v.tab.start[a]);
     const bool short_list = max_bonds <= 8;
+    // calls of two sweeps or more run on the colour-major copy (two copies
+    // of the state per call against line-granular traffic of the whole
+    // lattice in every launch)
+    CmDims cd{};
+    const bool cm = p->n_sweeps >= 2 && mc_cm_buffer(v.grid, m, cd);
+    const unsigned pgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cd.NP + kMcB - 1) / kMcB, 65536));
+    if (cm) k_mc_permute<<<pgrid, kMcB, 0, st>>>(S, m->d_cm, v.grid.Lx, v.grid.N, cd, 1);
     for (int n = 0; n < p->n_sweeps; ++n) {
         const uint64_t sweep = p->sweep0 + (uint64_t)n;
         for (int c = 0; c < col.C; ++c) {
+            if (cm) {
+                double *P = m->d_cm;
+                const int64_t *co = m->d_coff;
+                if (p->method == 0) {
+                    if (iso && short_list) k_mc_colour_cm<true, 0, 2><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
+                    else if (iso) k_mc_colour_cm<true, 0, 4><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
+                    else k_mc_colour_cm<false, 0, 4><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
+                } else {
+                    if (iso) k_mc_colour_cm<true, 1, 4><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
+                    else k_mc_colour_cm<false, 1, 4><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
+                }
+                continue;
+            }
             if (p->method == 0) {
                 if (iso && short_list) k_mc_colour<true, 0, 2><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
                 else if (iso) k_mc_colour<true, 0, 4><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
@@ -516,6 +788,7 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
             }
         }
     }
+    if (cm) k_mc_permute<<<pgrid, kMcB, 0, st>>>(m->d_cm, S, v.grid.Lx, v.grid.N, cd, 0);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && accepted)
         e = hipMemcpyAsync(accepted, m->d_acc, sizeof(unsigned long long), hipMemcpyDeviceToDevice, st);

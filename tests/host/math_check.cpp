@@ -19,6 +19,7 @@ static int g_est_k = 0;
 #define SPX_EST_RSQ(x) est_perturb(1.0L / sqrtl((long double)(x)), ++g_est_k)
 #define SPX_EST_RCP(x) est_perturb(1.0L / (long double)(x), ++g_est_k)
 #include "../../paper_2605_26016_amd/csrc/spx_math.hpp"
+#include "../../paper_2605_26016_amd/csrc/spx_mc_math.hpp"
 
 static double ulp_err(double got, long double ref) {
     if (ref == 0.0L) return got == 0.0 ? 0.0 : INFINITY;
@@ -124,5 +125,45 @@ int main() {
     std::printf("div %.3f 1000000\natan2 %.3f %ld\nexpmap_cos_abs %.3f 1000000\nexpmap_sinc %.3f 1000000\n", mdiv, mang,
                 nang, mcs, msc);
     std::printf("expmap_far_cos_abs %.3f 1000000\nexpmap_far_sin_abs %.3f 1000000\n", mcs_far, msn_far);
+    // Monte Carlo moves: e^y - 1 and e^y for y <= 0 (random magnitudes from
+    // 2^-60 to 50 / 745, both sides of every reduction boundary
+    // (k + 1/2) ln 2 and the clamps), ln(1 + w) for -1 < w <= 0 (random
+    // magnitudes from 2^-60 to 1 - 2^-33, and w near -1/2 where 1 + w
+    // stops being exact)
+    double mem1 = 0, mex = 0, ml1p = 0;
+    long nem1 = 0, nex = 0, nl1p = 0;
+    auto check_y = [&](double y) {
+        mem1 = fmax(mem1, ulp_err(spx::expm1_nonpos(y), expm1l((long double)y)));
+        ++nem1;
+        if (y > -708.0) {  // normal results
+            mex = fmax(mex, ulp_err(spx::exp_nonpos(y), expl((long double)y)));
+            ++nex;
+        }
+    };
+    for (int k = 0; k < 2000000; ++k) {
+        const double m = 1.0 + ldexp((double)(rng() >> 11), -53);
+        check_y(-ldexp(m, (int)(rng() % 66) - 60));
+        check_y(-ldexp((double)(rng() >> 11), -53) * ((k & 1) ? 50.0 : 745.0));
+    }
+    const long double LN2 = 0.693147180559945309417232121458176568L;
+    for (int k = 0; k <= 1070; ++k)
+        for (int d = -8; d <= 8; ++d) {
+            const double y = (double)(-(k + 0.5L) * LN2) + d * ldexp(1.0, -40) * (k + 1);
+            if (y <= 0.0) check_y(y);
+        }
+    for (double y : {0.0, -0.0, -40.0, -39.999, -40.001, -745.0, -707.9, -1e-300, -0x1p-1074}) check_y(y);
+    auto check_w = [&](double w) {
+        ml1p = fmax(ml1p, ulp_err(spx::log1p_neg(w), log1pl((long double)w)));
+        ++nl1p;
+    };
+    for (int k = 0; k < 2000000; ++k) {
+        const double m = 1.0 + ldexp((double)(rng() >> 11), -53);
+        const double w = -ldexp(m, -(int)(rng() % 61));
+        if (w > -1.0 + 0x1p-33) check_w(w);
+        check_w(-0.5 + ldexp((double)(rng() >> 11), -53) * 0x1p-10 - 0x1p-11);
+    }
+    for (double w : {0.0, -0x1p-60, -0.5, -0.5 + 0x1p-54, -0.5 - 0x1p-53, -1.0 + 0x1p-33, -0.75}) check_w(w);
+    std::printf("expm1_nonpos %.3f %ld\nexp_nonpos %.3f %ld\nlog1p_neg %.3f %ld\n", mem1, nem1, mex, nex, ml1p,
+                nl1p);
     return 0;
 }

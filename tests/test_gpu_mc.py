@@ -41,6 +41,17 @@ CASES["sc3shell_23x17x11"] = Workload(name="s3", L=(23, 17, 11), periodic=(1, 1,
                                       B=(1.0, 0.0, 0.5), field_prec="fp64")
 CASES["bcc4_noK"] = bcc_5shell_stochastic((4, 4, 4))
 CASES["bcc4_noK"].K = 0.0
+# more sites of one colour than threads of the pipelined kernel's grid (four
+# 256-thread blocks per CU), so threads walk several sites
+CASES["sc_nn_128x96x64"] = Workload(name="big", L=(128, 96, 64), J_shell=(1.0,), B=(0.0, 0.0, 1.0),
+                                    field_prec="fp64")
+# bonds longer than an extent (the fourth shell's (0, 0, 2) on one open z
+# plane): the colour-major kernel's general coordinate wrapping
+CASES["sc4shell_6x6x1"] = Workload(name="g", L=(6, 6, 1), periodic=(1, 1, 0), J_shell=(1.0, 0.3, 0.1, 0.05),
+                                   B=(0.0, 0.5, 1.0), field_prec="fp64")
+# tensor bonds (exchange + DMI), a ragged row of 13 sites, mixed faces
+CASES["sc_dmi_13x9x7"] = Workload(name="d", L=(13, 9, 7), periodic=(1, 0, 1), J_shell=(1.0,), D_shell=(0.4,),
+                                  B=(0.2, 0.0, 0.8), field_prec="fp64")
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -56,7 +67,10 @@ def test_colouring_matches_the_oracle(name):
 @pytest.mark.parametrize("name,method,T", [("sc4", 0, 80.0), ("sc5x4x4", 0, 40.0), ("sc3shell_open", 0, 30.0),
                                            ("bcc4_noK", 0, 300.0), ("sc4", 1, 80.0), ("bcc4", 1, 600.0),
                                            ("sc_nn_37x21x13", 0, 60.0), ("sc3shell_23x17x11", 0, 40.0),
-                                           ("sc_nn_37x21x13", 1, 60.0), ("sc3shell_23x17x11", 1, 40.0)])
+                                           ("sc_nn_37x21x13", 1, 60.0), ("sc3shell_23x17x11", 1, 40.0),
+                                           ("sc_dmi_13x9x7", 0, 50.0), ("sc_dmi_13x9x7", 1, 50.0),
+                                           ("sc_nn_128x96x64", 0, 60.0), ("sc_nn_128x96x64", 1, 60.0),
+                                           ("sc4shell_6x6x1", 0, 30.0), ("sc4shell_6x6x1", 1, 30.0)])
 def test_sweeps_match_the_oracle(name, method, T):
     import torch
     from paper_2605_26016_amd import spx
@@ -73,6 +87,35 @@ def test_sweeps_match_the_oracle(name, method, T):
     assert int(acc.cpu().item()) == n_acc
     norms = np.linalg.norm(S.cpu().numpy(), axis=0)
     assert np.max(np.abs(norms - 1.0)) < 1e-13
+
+
+@pytest.mark.parametrize("name,method,T", [("sc_nn_37x21x13", 0, 60.0), ("sc_nn_37x21x13", 1, 60.0),
+                                           ("sc3shell_23x17x11", 0, 40.0), ("bcc6", 1, 600.0),
+                                           ("bcc4_noK", 0, 300.0), ("sc_dmi_13x9x7", 0, 50.0),
+                                           ("sc_dmi_13x9x7", 1, 50.0), ("chain", 0, 20.0),
+                                           ("sc_nn_128x96x64", 0, 60.0), ("sc_nn_128x96x64", 1, 60.0),
+                                           ("sc4shell_6x6x1", 0, 30.0), ("sc3shell_open", 1, 30.0)])
+def test_colour_major_sweeps_equal_natural_layout_sweeps(name, method, T):
+    # a call of several sweeps runs on the colour-major copy of the state, a
+    # call of one sweep in the natural layout: the same sweeps either way
+    # give the same bits and the same accepted-move count
+    import torch
+    from paper_2605_26016_amd import spx
+    w = CASES[name]
+    S0 = random_sphere(w.N, 41)
+    h = gpu_hamiltonian(w, field_prec="fp64")
+    Sa, Sb = to_dev(S0), to_dev(S0)
+    acc = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    spx.mc_sweep(h, Sa, T, seed=3, sweep0=10, n_sweeps=3, method=method, accepted=acc)
+    torch.cuda.synchronize()
+    n_a = int(acc.cpu().item())
+    n_b = 0
+    for k in range(3):
+        spx.mc_sweep(h, Sb, T, seed=3, sweep0=10 + k, n_sweeps=1, method=method, accepted=acc)
+        torch.cuda.synchronize()
+        n_b += int(acc.cpu().item())
+    assert torch.equal(Sa, Sb), float((Sa - Sb).abs().max())
+    assert n_a == n_b
 
 
 def test_metropolis_with_anisotropy_matches_the_oracle():

@@ -12,7 +12,12 @@ The GNEB passes' functions are checked the same way: the quotient (half an
 ulp), the angle between two unit vectors from (|a x b|, a.b) over random,
 nearly parallel and nearly opposite pairs and the reduction's octant
 boundaries (3 ulp), and cos r, sin(r)/r of the exponential map from r^2
-(1.5 ulp up to r = 1, a few 2^-53 absolute up to r = 4)."""
+(1.5 ulp up to r = 1, a few 2^-53 absolute up to r = 4).
+
+The Monte Carlo moves' functions (spx_mc_math.hpp): e^y - 1 and e^y for
+y <= 0 over random magnitudes and both sides of every reduction boundary
+(1.5 ulp), ln(1 + w) for -1 < w <= 0 over random magnitudes down to 2^-60
+and around w = -1/2 (2.5 ulp)."""
 import os
 import shutil
 import subprocess
@@ -45,3 +50,7 @@ def test_device_math_accuracy(tmp_path):
     # beyond |u| = 1 (up to 4 rad) the angle goes through u / pi in one rounding
     assert res["expmap_far_cos_abs"] <= 8.0
     assert res["expmap_far_sin_abs"] <= 8.0
+    # Monte Carlo: heat-bath inverse distribution function, Metropolis test
+    assert res["expm1_nonpos"] <= 1.5
+    assert res["exp_nonpos"] <= 1.5
+    assert res["log1p_neg"] <= 2.5
