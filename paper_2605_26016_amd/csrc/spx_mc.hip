@@ -20,19 +20,22 @@
 // Colour-major layout.  In the natural layout the sites of one colour sit
 // C apart along every row, so each launch touches every cache line of the
 // state.  A call of several sweeps therefore copies the state once into rows
-// ordered by colour class, [x mod C][x div C] with pitch C J (J =
-// ceil(Lx / C)), runs every launch there and copies it back: a colour's sites
-// of one row are then one contiguous run of J, and so are the runs of every
-// neighbour class it reads.  The neighbour through bond p of a site in class
-// x0 lies at a fixed offset from the site's slot, tabulated per (p, x0) for
-// the three cases of its x (wrapped up, inside, wrapped down); a wrap in y or
-// z shifts it by whole rows, and a bond across an open face is left out, so
-// every site of a launch takes the same path (lattices with a bond longer
-// than an extent wrap coordinates by a true modulo instead).
-// The bonds are summed in the same order with the same arithmetic, and the
-// Philox counter is the natural site index, so both layouts give the same
-// bits.
+// ordered by colour class, [x mod C][x div C], runs every launch there and
+// copies it back: a colour's sites of one row are then one contiguous run,
+// and so are the runs of every neighbour class it reads.  Each class block
+// carries ghost slots at both ends and the rows carry ghost rows in y and
+// z (copies of the wrapped sites on periodic axes, zero across open faces),
+// so the neighbour through bond p of a site in class x0 is at a fixed
+// offset from the site's slot for every site, tabulated per (p, x0), and no
+// site tests a boundary; a site whose ghost copies exist writes them with
+// its new spin (no site of the launch reads them: they share its colour).
+// The bonds are summed in the same order with the same arithmetic (a ghost
+// across an open face adds an exact zero where the natural kernel skips the
+// bond), and the Philox counter is the natural site index, so both layouts
+// give the same bits.
+
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -271,42 +274,77 @@ __global__ __launch_bounds__(kMcB) void k_mc_colour(double *__restrict__ S, Bond
     }
 }
 
-// The colour-major slot of natural site (x, row r): r C J + (x mod C) J + x div C.
+// The padded colour-major layout.  Row (y, z, a) holds C class blocks of Jp
+// = J + 2 ex slots (J = ceil(Lx / C), ex = ceil(rx / C)); slot ex + jv of
+// block k is virtual x = k + C jv, so a block covers x from k - C ex to
+// k + C (J + ex) - 1.  Rows run over virtual y in [-ry, Ly + ry) and z in
+// [-rz, Lz + rz) (rx, ry, rz: the bonds' largest offsets).  A virtual site
+// outside the lattice is a ghost: on a periodic axis a copy of its wrapped
+// site, across an open face zero (it adds nothing to a field).
 struct CmDims {
-    int C, J;
-    int64_t n_rows, NP;  // rows (y, z, a) and doubles per component
+    int C, J, Jp, ex;       // colours, real and padded slots per class block, ghost slots per end
+    int lxq, lxm;           // Lx div C, Lx mod C
+    int ry, rz, Lyp, Lzp;   // ghost rows and padded row extents
+    int64_t n_rows, NP;     // real rows (y, z, a) and padded doubles per component
+    int64_t pitch;          // C Jp
 };
 
-__device__ __forceinline__ int64_t cm_slot(const CmDims &d, int64_t r, int x) {
-    return r * ((int64_t)d.C * d.J) + (int64_t)(x % d.C) * d.J + x / d.C;
+// padded slot of virtual site (xv, yv, zv, a)
+__device__ __forceinline__ int64_t cm_slot(const CmDims &d, int xv, int yv, int zv, int a) {
+    int k = xv % d.C;
+    if (k < 0) k += d.C;
+    const int jv = (xv - k) / d.C;  // exact
+    const int64_t pr = (yv + d.ry) + (int64_t)d.Lyp * ((zv + d.rz) + (int64_t)d.Lzp * a);
+    return pr * d.pitch + (int64_t)k * d.Jp + jv + d.ex;
 }
 
-// Natural <-> colour-major copy (to_cm: S -> P, else P -> S), one thread per
-// colour-major slot; slots past the end of a row hold zero.
-__global__ __launch_bounds__(kMcB) void k_mc_permute(const double *__restrict__ src, double *__restrict__ dst,
-                                                     int Lx, int64_t N, CmDims d, int to_cm) {
-    const int64_t pitch = (int64_t)d.C * d.J;
+// the real coordinate of virtual coordinate v (-1: across an open face)
+__device__ __forceinline__ int cm_real(int v, int L, int per) {
+    if (v >= 0 && v < L) return v;
+    if (!per) return -1;
+    v %= L;
+    return v < 0 ? v + L : v;
+}
+
+// Natural -> padded colour-major copy, one thread per padded slot (ghosts
+// included), and back, one thread per site.
+__global__ __launch_bounds__(kMcB) void k_mc_to_cm(const double *__restrict__ S, double *__restrict__ P, Grid g,
+                                                   CmDims d) {
     for (int64_t q = (int64_t)blockIdx.x * kMcB + threadIdx.x; q < d.NP; q += (int64_t)gridDim.x * kMcB) {
-        const int64_t r = q / pitch;
-        const int k = (int)(q - r * pitch);
-        const int x0 = k / d.J, j = k - x0 * d.J;
-        const int x = x0 + d.C * j;
-        const int64_t i = x + (int64_t)Lx * r;  // natural index (rows are contiguous in it)
-        if (to_cm) {
+        const int64_t pr = q / d.pitch;
+        const int s = (int)(q - pr * d.pitch);
+        const int k = s / d.Jp, jv = s - k * d.Jp - d.ex;
+        const int64_t yz = pr / d.Lyp;
+        const int yv = (int)(pr - yz * d.Lyp) - d.ry;
+        const int a = (int)(yz / d.Lzp);
+        const int zv = (int)(yz - (int64_t)a * d.Lzp) - d.rz;
+        const int x = cm_real(k + d.C * jv, g.Lx, g.per[0]), y = cm_real(yv, g.Ly, g.per[1]),
+                  z = cm_real(zv, g.Lz, g.per[2]);
+        const bool live = (x | y | z) >= 0;
+        const int64_t i = live ? (int64_t)a * g.M + x + (int64_t)g.Lx * (y + (int64_t)g.Ly * z) : 0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) dst[c * d.NP + q] = x < Lx ? src[c * N + i] : 0.0;
-        } else if (x < Lx) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) dst[c * N + i] = src[c * d.NP + q];
-        }
+        for (int c = 0; c < 3; ++c) P[c * d.NP + q] = live ? S[c * g.N + i] : 0.0;
     }
 }
 
-// One colour of one sweep on the colour-major copy P: the natural kernel's
-// site loop, draw and update, with every spin addressed by its colour-major
-// slot.
+__global__ __launch_bounds__(kMcB) void k_mc_from_cm(const double *__restrict__ P, double *__restrict__ S, Grid g,
+                                                     CmDims d) {
+    for (int64_t i = (int64_t)blockIdx.x * kMcB + threadIdx.x; i < g.N; i += (int64_t)gridDim.x * kMcB) {
+        const int a = (int)(i / g.M);
+        int x, y, z;
+        site_xyz(g, (int)(i - (int64_t)a * g.M), x, y, z);
+        const int64_t q = cm_slot(d, x, y, z, a);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S[c * g.N + i] = P[c * d.NP + q];
+    }
+}
+
+// One colour of one sweep on the padded colour-major copy P: the natural
+// kernel's site loop, draw and update, every neighbour at the tabulated
+// offset of its bond and class, and the new spin also written to the
+// site's ghost copies.
 template <bool ISO, int METHOD, int UNR>
-__global__ __launch_bounds__(kMcB) void k_mc_colour_cm(double *__restrict__ P, BondTable tb, Grid g, Onsite os,
+__global__ __launch_bounds__(kMcB) __attribute__((amdgpu_waves_per_eu(4))) void k_mc_colour_cm(double *__restrict__ P, BondTable tb, Grid g, Onsite os,
                                                        McColour col, int c, double beta, uint64_t seed,
                                                        uint64_t sweep, unsigned long long *__restrict__ acc,
                                                        const int64_t *__restrict__ coff, CmDims d) {
@@ -314,12 +352,10 @@ __global__ __launch_bounds__(kMcB) void k_mc_colour_cm(double *__restrict__ P, B
     const int J = d.J;
     const int64_t total = d.n_rows * J;
     const int64_t NP = d.NP;
-    const int64_t pitch = (int64_t)C * J;
-    const int64_t ly_rows = (int64_t)g.Ly * pitch, lz_rows = (int64_t)g.Lz * ly_rows;  // y and z wraps
     unsigned int accepted = 0;
-    for (int64_t t = xcd_block() * kMcB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kMcB) {
-        int j, y, z, a;
-        int64_t row;
+    // slot t -> (j, y, z, a) of row t / J, and the site's class x0
+    auto decode = [&](int64_t t, int &j, int &y, int &z, int &a, int64_t &row, int &x0)
+                      __attribute__((always_inline)) {
         if (total <= (int64_t)0xffffffffll) {
             const uint32_t tt = (uint32_t)t, uJ = (uint32_t)J, uLy = (uint32_t)g.Ly, uLz = (uint32_t)g.Lz;
             const uint32_t rw = tt / uJ;
@@ -336,65 +372,58 @@ __global__ __launch_bounds__(kMcB) void k_mc_colour_cm(double *__restrict__ P, B
             z = (int)((row / g.Ly) % g.Lz);
             a = (int)(row / ((int64_t)g.Ly * g.Lz));
         }
-        int x0 = (c - col.ky * y - col.kz * z - col.o[a]) % C;
+        x0 = (c - col.ky * y - col.kz * z - col.o[a]) % C;
         if (x0 < 0) x0 += C;
+    };
+    // the other virtual x of the site: x - Lx in class x0 - (Lx mod C) and
+    // block slot j - (Lx div C), one less where the class folds into
+    // [0, C); x + Lx likewise (-1: outside the padded block, or open x)
+    auto x_images = [&](int x0, int j, int &sm, int &sp) __attribute__((always_inline)) {
+        sm = sp = -1;
+        if (!g.per[0]) return;
+        int km = x0 - d.lxm, jm = j - d.lxq;
+        if (km < 0) { km += C; --jm; }
+        if (jm + d.ex >= 0) sm = km * d.Jp + jm + d.ex;
+        int kp = x0 + d.lxm, jp = j + d.lxq;
+        if (kp >= C) { kp -= C; ++jp; }
+        if (jp + d.ex < d.Jp) sp = kp * d.Jp + jp + d.ex;
+    };
+    for (int64_t t = xcd_block() * kMcB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kMcB) {
+        int j, y, z, a, x0;
+        int64_t row;
+        decode(t, j, y, z, a, row, x0);
         const int x = x0 + C * j;
         if (x >= g.Lx) continue;
-        const int64_t i = x + (int64_t)g.Lx * row;              // natural index (the Philox counter)
-        const int64_t own = row * pitch + (int64_t)x0 * J + j;  // colour-major slot
+        // which ghost images the site has (bits: x - Lx, x + Lx, y - Ly,
+        // y + Ly, z - Lz, z + Lz); their slots are worked out again after
+        // the draw, only by the sites that have some
+        int ghosts;
+        {
+            int sm, sp;
+            x_images(x0, j, sm, sp);
+            ghosts = (sm >= 0 ? 1 : 0) | (sp >= 0 ? 2 : 0) | (g.per[1] && y - g.Ly >= -d.ry ? 4 : 0) |
+                     (g.per[1] && y < d.ry ? 8 : 0) | (g.per[2] && z - g.Lz >= -d.rz ? 16 : 0) |
+                     (g.per[2] && z < d.rz ? 32 : 0);
+        }
+        const int64_t i = x + (int64_t)g.Lx * row;  // natural index (the Philox counter)
+        const int64_t own = ((y + d.ry) + (int64_t)d.Lyp * ((z + d.rz) + (int64_t)d.Lzp * a)) * d.pitch +
+                            (int64_t)x0 * d.Jp + j + d.ex;
         double bl[3] = {0.0, 0.0, 0.0};
         const int p0 = tb.start[a], p1 = tb.start[a + 1];
-        if (!g.wrap_general) {
-            // every site alike: a neighbour across a periodic face is one
-            // wrap away (the x-side table entry and a row shift of Ly or
-            // Ly Lz rows); across an open face the bond is left out
 #pragma unroll UNR
-            for (int p = p0; p < p1; ++p) {
-                const int4 gq = tb.geo[p];
-                const int xs = x + gq.y, ys = y + gq.z, zs = z + gq.w;
-                const int side = xs < 0 ? 0 : (xs >= g.Lx ? 2 : 1);
-                const bool ok = (side == 1 || g.per[0]) && ((unsigned)ys < (unsigned)g.Ly || g.per[1]) &&
-                                ((unsigned)zs < (unsigned)g.Lz || g.per[2]);
-                int64_t q = own + coff[(3 * p + side) * C + x0];
-                q += ys < 0 ? ly_rows : (ys >= g.Ly ? -ly_rows : 0);
-                q += zs < 0 ? lz_rows : (zs >= g.Lz ? -lz_rows : 0);
-                if (ok) {
-                    const double s0 = P[q], s1 = P[NP + q], s2 = P[2 * NP + q];
-                    if constexpr (ISO) {
-                        const double Jp = tb.Jd[p];
-                        bl[0] += Jp * s0;
-                        bl[1] += Jp * s1;
-                        bl[2] += Jp * s2;
-                    } else {
-                        const double *Jp = tb.Jd + 9 * p;
-                        bl[0] += Jp[0] * s0 + Jp[1] * s1 + Jp[2] * s2;
-                        bl[1] += Jp[3] * s0 + Jp[4] * s1 + Jp[5] * s2;
-                        bl[2] += Jp[6] * s0 + Jp[7] * s1 + Jp[8] * s2;
-                    }
-                }
-            }
-        } else {
-            // bonds longer than an extent: coordinates wrapped by a true modulo
-            for (int p = p0; p < p1; ++p) {
-                const int4 gq = tb.geo[p];
-                bool ok = true;
-                const int xx = wrap_coord(x + gq.y, g.Lx, g.per[0], g.wrap_general, ok);
-                const int yy = wrap_coord(y + gq.z, g.Ly, g.per[1], g.wrap_general, ok);
-                const int zz = wrap_coord(z + gq.w, g.Lz, g.per[2], g.wrap_general, ok);
-                if (!ok) continue;
-                const int64_t q = cm_slot(d, yy + (int64_t)g.Ly * (zz + (int64_t)g.Lz * gq.x), xx);
-                const double s0 = P[q], s1 = P[NP + q], s2 = P[2 * NP + q];
-                if constexpr (ISO) {
-                    const double Jp = tb.Jd[p];
-                    bl[0] += Jp * s0;
-                    bl[1] += Jp * s1;
-                    bl[2] += Jp * s2;
-                } else {
-                    const double *Jp = tb.Jd + 9 * p;
-                    bl[0] += Jp[0] * s0 + Jp[1] * s1 + Jp[2] * s2;
-                    bl[1] += Jp[3] * s0 + Jp[4] * s1 + Jp[5] * s2;
-                    bl[2] += Jp[6] * s0 + Jp[7] * s1 + Jp[8] * s2;
-                }
+        for (int p = p0; p < p1; ++p) {
+            const int64_t q = own + coff[p * C + x0];
+            const double s0 = P[q], s1 = P[NP + q], s2 = P[2 * NP + q];
+            if constexpr (ISO) {
+                const double Jp = tb.Jd[p];
+                bl[0] += Jp * s0;
+                bl[1] += Jp * s1;
+                bl[2] += Jp * s2;
+            } else {
+                const double *Jp = tb.Jd + 9 * p;
+                bl[0] += Jp[0] * s0 + Jp[1] * s1 + Jp[2] * s2;
+                bl[1] += Jp[3] * s0 + Jp[4] * s1 + Jp[5] * s2;
+                bl[2] += Jp[6] * s0 + Jp[7] * s1 + Jp[8] * s2;
             }
         }
         const double b[3] = {bl[0] + os.bz[a][0], bl[1] + os.bz[a][1], bl[2] + os.bz[a][2]};
@@ -409,6 +438,34 @@ __global__ __launch_bounds__(kMcB) void k_mc_colour_cm(double *__restrict__ P, B
         P[own] = sn[0];
         P[NP + own] = sn[1];
         P[2 * NP + own] = sn[2];
+        // ghost copies: every combination of the real and the other virtual
+        // coordinates of each axis except the real site itself
+        if (ghosts) {
+            decode(t, j, y, z, a, row, x0);
+            int xs[3] = {x0 * d.Jp + j + d.ex, -1, -1};  // slots within a row (C Jp < 2^31)
+            x_images(x0, j, xs[1], xs[2]);
+            const int ym = (ghosts & 4) ? y - g.Ly : INT_MIN, yp = (ghosts & 8) ? y + g.Ly : INT_MIN;
+            const int zm = (ghosts & 16) ? z - g.Lz : INT_MIN, zp = (ghosts & 32) ? z + g.Lz : INT_MIN;
+#pragma unroll
+            for (int iz = 0; iz < 3; ++iz) {
+                const int zv = iz == 0 ? z : (iz == 1 ? zm : zp);
+                if (zv == INT_MIN) continue;
+#pragma unroll
+                for (int iy = 0; iy < 3; ++iy) {
+                    const int yv = iy == 0 ? y : (iy == 1 ? ym : yp);
+                    if (yv == INT_MIN) continue;
+                    const int64_t rb = ((yv + d.ry) + (int64_t)d.Lyp * ((zv + d.rz) + (int64_t)d.Lzp * a)) * d.pitch;
+#pragma unroll
+                    for (int ix = 0; ix < 3; ++ix) {
+                        if ((ix | iy | iz) == 0 || xs[ix] < 0) continue;
+                        const int64_t qg = rb + xs[ix];
+                        P[qg] = sn[0];
+                        P[NP + qg] = sn[1];
+                        P[2 * NP + qg] = sn[2];
+                    }
+                }
+            }
+        }
     }
     if (acc) {
         unsigned int w = accepted;
@@ -608,23 +665,22 @@ spx_status mc_colouring(spx_ham *h, const HamView &v, MCState *m) {
         m->rad[1] = std::max(m->rad[1], std::abs(dy));
         m->rad[2] = std::max(m->rad[2], std::abs(dz));
     }
-    // colour-major slot offset of every bond from a site of class x0, for
-    // the neighbour's x below 0 (wrapped up by Lx), inside, and at or above
-    // Lx (wrapped down): neighbour x' = cls + C (j + dv), row r + dr (rows
-    // wrapped on y and z are shifted by the kernel)
-    const int C = col.C, JC = (g.Lx + C - 1) / C;
-    const int64_t pitch = (int64_t)C * JC;
-    std::vector<int64_t> coff((size_t)std::max(info.n_bonds, 1) * 3 * C, 0);
+    // padded colour-major slot offset of every bond from a site of class x0:
+    // neighbour x' = x + dx in class (x0 + dx) mod C, slot j + floor((x0 +
+    // dx) / C), padded row pr + dy + Lyp (dz + Lzp (b - a))
+    const int C = col.C, JC = (g.Lx + C - 1) / C, ex = (m->rad[0] + C - 1) / C;
+    const int64_t Jp = JC + 2 * ex, pitch = C * Jp;
+    const int64_t Lyp = g.Ly + 2 * m->rad[1], Lzp = g.Lz + 2 * m->rad[2];
+    std::vector<int64_t> coff((size_t)std::max(info.n_bonds, 1) * C, 0);
     for (int p = 0; p < info.n_bonds; ++p) {
         const int dx = dli[3 * p], dy = dli[3 * p + 1], dz = dli[3 * p + 2];
-        const int64_t dr = dy + (int64_t)g.Ly * (dz + (int64_t)g.Lz * (abi[2 * p + 1] - abi[2 * p]));
-        for (int side = 0; side < 3; ++side)
-            for (int x0 = 0; x0 < C; ++x0) {
-                const int xs = x0 + dx + (side == 0 ? g.Lx : (side == 2 ? -g.Lx : 0));
-                const int cls = ((xs % C) + C) % C;
-                const int dv = (xs - cls) / C;  // exact
-                coff[((size_t)p * 3 + side) * C + x0] = dr * pitch + (int64_t)(cls - x0) * JC + dv;
-            }
+        const int64_t dr = dy + Lyp * (dz + Lzp * (abi[2 * p + 1] - abi[2 * p]));
+        for (int x0 = 0; x0 < C; ++x0) {
+            const int xs = x0 + dx;
+            const int cls = ((xs % C) + C) % C;
+            const int dv = (xs - cls) / C;  // exact
+            coff[(size_t)p * C + x0] = dr * pitch + (int64_t)(cls - x0) * Jp + dv;
+        }
     }
     if (hipMalloc((void **)&m->d_off, sizeof(int64_t) * off.size()) != hipSuccess ||
         hipMemcpy(m->d_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -641,13 +697,28 @@ spx_status mc_colouring(spx_ham *h, const HamView &v, MCState *m) {
     return SPX_OK;
 }
 
-// Dimensions of the colour-major copy and, on first use, its buffer; false
-// if it cannot be allocated (the sweeps then run in the natural layout).
+// Dimensions of the padded colour-major copy and, on first use, its buffer.
+// False (the sweeps then run in the natural layout) when a bond is longer
+// than an extent, when a ghost band of a periodic axis is wider than the
+// extent (a site would need copies two periods away), or when the buffer
+// cannot be allocated.
 bool mc_cm_buffer(const Grid &g, MCState *m, CmDims &d) {
+    if (g.wrap_general) return false;
     d.C = m->C;
     d.J = (g.Lx + m->C - 1) / m->C;
+    d.ex = (m->rad[0] + m->C - 1) / m->C;
+    d.Jp = d.J + 2 * d.ex;
+    d.lxq = g.Lx / m->C;
+    d.lxm = g.Lx % m->C;
+    d.ry = m->rad[1];
+    d.rz = m->rad[2];
+    d.Lyp = g.Ly + 2 * d.ry;
+    d.Lzp = g.Lz + 2 * d.rz;
+    d.pitch = (int64_t)d.C * d.Jp;
     d.n_rows = (int64_t)g.Ly * g.Lz * g.n_sub;
-    d.NP = d.n_rows * d.C * d.J;
+    d.NP = (int64_t)d.Lyp * d.Lzp * g.n_sub * d.pitch;
+    if (g.per[0] && ((int64_t)d.C * d.ex > g.Lx || (int64_t)d.C * (d.J + d.ex) > 2 * (int64_t)g.Lx)) return false;
+    if ((g.per[1] && d.ry > g.Ly) || (g.per[2] && d.rz > g.Lz)) return false;
     const size_t need = 3 * (size_t)d.NP;
     if (m->cm_cap >= need) return true;
     if (m->d_cm) (void)hipFree(m->d_cm);
@@ -761,7 +832,8 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
     CmDims cd{};
     const bool cm = p->n_sweeps >= 2 && mc_cm_buffer(v.grid, m, cd);
     const unsigned pgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cd.NP + kMcB - 1) / kMcB, 65536));
-    if (cm) k_mc_permute<<<pgrid, kMcB, 0, st>>>(S, m->d_cm, v.grid.Lx, v.grid.N, cd, 1);
+    const unsigned ngrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((v.grid.N + kMcB - 1) / kMcB, 65536));
+    if (cm) k_mc_to_cm<<<pgrid, kMcB, 0, st>>>(S, m->d_cm, v.grid, cd);
     for (int n = 0; n < p->n_sweeps; ++n) {
         const uint64_t sweep = p->sweep0 + (uint64_t)n;
         for (int c = 0; c < col.C; ++c) {
@@ -788,7 +860,7 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
             }
         }
     }
-    if (cm) k_mc_permute<<<pgrid, kMcB, 0, st>>>(m->d_cm, S, v.grid.Lx, v.grid.N, cd, 0);
+    if (cm) k_mc_from_cm<<<ngrid, kMcB, 0, st>>>(m->d_cm, S, v.grid, cd);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && accepted)
         e = hipMemcpyAsync(accepted, m->d_acc, sizeof(unsigned long long), hipMemcpyDeviceToDevice, st);
