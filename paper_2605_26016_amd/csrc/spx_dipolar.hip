@@ -40,6 +40,10 @@ struct DipolarPlan {
     float2 *Y = nullptr;   // [3][Lz][Py][H] after the y transform
     float2 *Z = nullptr;   // [3][Pz][Py][H] full spectrum (Pz != 512; 512 uses the fused z pass)
     float *kern = nullptr; // [6][Pz][Py][H] real dipole spectrum xx, xy, xz, yy, yz, zz
+    // Pz = 512: the spectrum in the fused z pass's order instead,
+    // [column group][kz < nkz][6][16 columns] (nkz = 257 with z parity, else 512)
+    float *kernb = nullptr;
+    int nkz = 0;
     // the third cell vector is along z and the first two have no z part: the
     // sampled tensor is even (xx, xy, yy, zz) or odd (xz, yz) under dz -> -dz,
     // so is its spectrum under kz -> Pz - kz, and the fused z pass reads only
@@ -121,24 +125,25 @@ __global__ void k_take_real(const double2 *__restrict__ in, int64_t n, float *__
 }
 
 // FP32 x rows of the occupied (y, z) lines, zero beyond x = Lx.
-__global__ void k_pad_rows(const double *__restrict__ S, int Lx, int Px, int64_t rows, int64_t N,
-                           float *__restrict__ R) {
-    const int64_t idx = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (idx >= 3 * rows * Px) return;
-    const int x = (int)(idx % Px);
-    const int64_t row = idx / Px;           // (c, z, y)
-    const int64_t c = row / rows, line = row - c * rows;  // line = y + Ly z
-    R[idx] = x < Lx ? (float)S[c * N + line * Lx + x] : 0.0f;
+// One block per padded x row (c, line = y + Ly z): the occupied Lx values
+// converted to FP32, zero up to Px.
+__global__ __launch_bounds__(kB) void k_pad_rows(const double *__restrict__ S, int Lx, int Px, int64_t rows,
+                                                 int64_t N, float *__restrict__ R) {
+    const int64_t row = blockIdx.x;
+    const int64_t c = row / rows, line = row - c * rows;
+    const double *src = S + c * N + line * Lx;
+    float *dst = R + row * Px;
+    for (int x = threadIdx.x; x < Px; x += kB) dst[x] = x < Lx ? (float)src[x] : 0.0f;
 }
 
-__global__ void k_crop_rows(const float *__restrict__ R, int Lx, int Px, int64_t rows, int64_t N,
-                            float *__restrict__ b) {
-    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= 3 * N) return;
-    const int64_t c = i / N, site = i - c * N;
-    const int64_t line = site / Lx;
-    const int x = (int)(site - line * Lx);
-    b[i] = R[(c * rows + line) * Px + x];
+// One block per row: the occupied Lx values of padded row (c, line) into b.
+__global__ __launch_bounds__(kB) void k_crop_rows(const float *__restrict__ R, int Lx, int Px, int64_t rows,
+                                                  int64_t N, float *__restrict__ b) {
+    const int64_t row = blockIdx.x;
+    const int64_t c = row / rows, line = row - c * rows;
+    const float *src = R + row * Px;
+    float *dst = b + c * N + line * Lx;
+    for (int x = threadIdx.x; x < Lx; x += kB) dst[x] = src[x];
 }
 
 // b^_a = sum_b T^_ab S^_b at every frequency (T^ real symmetric).
@@ -290,9 +295,21 @@ __global__ __launch_bounds__(kT512) void k_colfft512(const float2 *__restrict__ 
     __shared__ float2 lds[512 * kPitch];
     const int t = threadIdx.x;
     const int w = t & (kW512 - 1), q = t >> kW512Log;  // column in the tile, thread of the column
-    const int64_t j = (int64_t)blockIdx.x * kW512 + w;
+    // Rows of J complex values are not 128-byte multiples, so a block's row
+    // segments straddle lines it shares with the next column group: blocks
+    // are renumbered so that each XCD takes one contiguous range of them
+    // (workgroups are dealt to the 8 XCDs in turn) and shared lines meet in
+    // one L2.
+    int64_t bx, b;
+    {
+        const int64_t T = (int64_t)gridDim.x * gridDim.y, id = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+        const int64_t qn = T / 8, rn = T % 8, k = id % 8;
+        const int64_t v = k * qn + (k < rn ? k : rn) + id / 8;
+        bx = v % gridDim.x;
+        b = v / gridDim.x;
+    }
+    const int64_t j = bx * kW512 + w;
     const bool col = j < J;
-    const int64_t b = blockIdx.y;
     const float2 *src = in + b * in_bs + j;
     float2 *dst = out + b * out_bs + j;
     float2 v[8];
@@ -312,14 +329,30 @@ __global__ __launch_bounds__(kT512) void k_colfft512(const float2 *__restrict__ 
     }
 }
 
+// The dipole spectrum reordered for the fused z pass: block g of 16 columns
+// reads kernb[g][kz][c][0..15] for its kz, one contiguous run per kz.
+__global__ void k_kern_block(const float *__restrict__ kern, float *__restrict__ kernb, int64_t J, int64_t n_cplx,
+                             int nkz, int64_t total) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int w = (int)(q % kW512);
+    int64_t r = q / kW512;
+    const int c = (int)(r % 6);
+    r /= 6;
+    const int kz = (int)(r % nkz);
+    const int64_t g = r / nkz;
+    const int64_t j = g * kW512 + w;
+    kernb[q] = j < J ? kern[c * n_cplx + (int64_t)kz * J + j] : 0.0f;
+}
+
 // z transform, spectral product and inverse z transform fused for Pz = 512:
 // each block takes 8 (y, kx) columns of the three components (rows z < Lz of
 // Y, zero above), transforms them forward, multiplies by the dipole spectrum
 // at its 512 kz and transforms back, writing rows z < Lz in place.  The
 // forward result sits in the thread that needs it for the inverse's first
 // pass (row c + 8 g + 64 h = 64 h + qin with qin = c + 8 g).
-__global__ __launch_bounds__(kT512) void k_zconv512(float2 *__restrict__ Y, const float *__restrict__ kern, int Lz,
-                                                    int64_t J, int64_t n_cplx, const float2 *__restrict__ tw512,
+__global__ __launch_bounds__(kT512) void k_zconv512(float2 *__restrict__ Y, const float *__restrict__ kernb, int Lz,
+                                                    int64_t J, int nkz, const float2 *__restrict__ tw512,
                                                     int zsym) {
     __shared__ float2 lds[512 * kPitch];
     const int t = threadIdx.x;
@@ -345,9 +378,9 @@ __global__ __launch_bounds__(kT512) void k_zconv512(float2 *__restrict__ Y, cons
             const int kz = qq + 64 * h;
             const bool mirror = zsym && kz > 256;
             const float sgn = mirror ? -1.0f : 1.0f;
-            const int64_t k = (int64_t)(mirror ? 512 - kz : kz) * J + j;
-            const float txx = kern[k], txy = kern[n_cplx + k], txz = sgn * kern[2 * n_cplx + k];
-            const float tyy = kern[3 * n_cplx + k], tyz = sgn * kern[4 * n_cplx + k], tzz = kern[5 * n_cplx + k];
+            const float *kb = kernb + (((int64_t)blockIdx.x * nkz + (mirror ? 512 - kz : kz)) * 6) * kW512 + w;
+            const float txx = kb[0], txy = kb[kW512], txz = sgn * kb[2 * kW512];
+            const float tyy = kb[3 * kW512], tyz = sgn * kb[4 * kW512], tzz = kb[5 * kW512];
             const float2 sx = v[0][h], sy = v[1][h], sz = v[2][h];
             v[0][h] = make_float2(txx * sx.x + txy * sy.x + txz * sz.x, txx * sx.y + txy * sy.y + txz * sz.y);
             v[1][h] = make_float2(txy * sx.x + tyy * sy.x + tyz * sz.x, txy * sx.y + tyy * sy.y + tyz * sz.y);
@@ -394,7 +427,7 @@ void destroy_dipolar(DipolarPlan *p) {
     if (!p) return;
     if (p->fwd_ok) hipfftDestroy(p->fwd);
     if (p->inv_ok) hipfftDestroy(p->inv);
-    for (void *q : {(void *)p->R, (void *)p->X, (void *)p->Y, (void *)p->Z, (void *)p->kern, (void *)p->tw_y,
+    for (void *q : {(void *)p->R, (void *)p->X, (void *)p->Y, (void *)p->Z, (void *)p->kern, (void *)p->kernb, (void *)p->tw_y,
                     (void *)p->tw_z})
         if (q) (void)hipFree(q);
     delete p;
@@ -489,6 +522,27 @@ spx_status create_dipolar(const int32_t dims[3], const double cell[9], double mu
         destroy_dipolar(p);
         return s;
     }
+    if (Pz == 512) {
+        // the fused z pass's order; the [6][Pz][Py][H] spectrum is then no
+        // longer needed
+        const int64_t plane = (int64_t)Py * p->H, ngroup = (plane + kW512 - 1) / kW512;
+        p->nkz = p->zsym ? 257 : 512;
+        const int64_t total = ngroup * p->nkz * 6 * kW512;
+        if ((s = alloc((void **)&p->kernb, sizeof(float) * total, "dipole spectrum (z pass order)")) != SPX_OK) {
+            destroy_dipolar(p);
+            return s;
+        }
+        k_kern_block<<<nblocks(total), kB, 0, st>>>(p->kern, p->kernb, plane, p->n_cplx, p->nkz, total);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            destroy_dipolar(p);
+            return set_hip_error(e, "dipolar spectrum reorder");
+        }
+        (void)hipFree(p->kern);
+        p->kern = nullptr;
+        *ws_bytes -= (int64_t)(sizeof(float) * 6 * p->n_cplx);
+    }
     // batched FP32 x-row transforms of the occupied lines of the three components
     int n[1] = {Px};
     int rembed[1] = {Px}, cembed[1] = {p->H};
@@ -513,7 +567,7 @@ spx_status eval_dipolar(DipolarPlan *p, const double *S, float *bdip, hipStream_
     if (!p) return set_error(SPX_ERR_INVALID_ARG, "dipolar path not set up");
     const int Lx = p->L[0], Ly = p->L[1], Lz = p->L[2], Px = p->P[0], Py = p->P[1], Pz = p->P[2], H = p->H;
     const int64_t rows = (int64_t)Ly * Lz;
-    k_pad_rows<<<nblocks(3 * rows * Px), kB, 0, st>>>(S, Lx, Px, rows, p->N, p->R);
+    k_pad_rows<<<(unsigned)(3 * rows), kB, 0, st>>>(S, Lx, Px, rows, p->N, p->R);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_hip_error(e, "dipolar pad");
     hipfftSetStream(p->fwd, st);
@@ -525,7 +579,7 @@ spx_status eval_dipolar(DipolarPlan *p, const double *S, float *bdip, hipStream_
     if (Pz == 512) {
         // z transform, product and inverse z transform in one pass over Y
         if (e == hipSuccess) {
-            k_zconv512<<<(unsigned)((plane + kW512 - 1) / kW512), kT512, 0, st>>>(p->Y, p->kern, Lz, plane, p->n_cplx,
+            k_zconv512<<<(unsigned)((plane + kW512 - 1) / kW512), kT512, 0, st>>>(p->Y, p->kernb, Lz, plane, p->nkz,
                                                                                 p->tw_z, p->zsym ? 1 : 0);
             e = hipGetLastError();
         }
@@ -548,7 +602,7 @@ spx_status eval_dipolar(DipolarPlan *p, const double *S, float *bdip, hipStream_
     hipfftSetStream(p->inv, st);
     fr = hipfftExecC2R(p->inv, (hipfftComplex *)p->X, p->R);
     if (fr != HIPFFT_SUCCESS) return fft_fail(fr, "dipolar C2R");
-    k_crop_rows<<<nblocks(3 * p->N), kB, 0, st>>>(p->R, Lx, Px, rows, p->N, bdip);
+    k_crop_rows<<<(unsigned)(3 * rows), kB, 0, st>>>(p->R, Lx, Px, rows, p->N, bdip);
     e = hipGetLastError();
     if (e != hipSuccess) return set_hip_error(e, "dipolar crop");
     return SPX_OK;
