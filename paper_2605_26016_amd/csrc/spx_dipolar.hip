@@ -50,6 +50,7 @@ struct DipolarPlan {
     // kz <= Pz / 2 (half the spectrum traffic)
     bool zsym = false;
     float2 *tw_y = nullptr, *tw_z = nullptr;  // exp(-2 pi i k / P), k < P
+    float2 *tw_x = nullptr;                    // Px = 512: the x rows run in k_xfft512_*
     hipfftHandle fwd = 0, inv = 0;
     bool fwd_ok = false, inv_ok = false;
 };
@@ -329,6 +330,108 @@ __global__ __launch_bounds__(kT512) void k_colfft512(const float2 *__restrict__ 
     }
 }
 
+// x rows for Px = 512: two real rows (A, B) of one pair transformed as one
+// complex 512-point FFT z = a + i b, whose spectrum Z gives both halves,
+// A[k] = (Z[k] + conj Z[512 - k]) / 2 and B[k] = (Z[k] - conj Z[512 - k]) / 2i
+// for k <= 256.  Global reads and writes run along the rows (consecutive
+// lanes, consecutive x or k: thread t serves pair t / 64, position t % 64);
+// the values pass to and from fft512's column-slot layout through LDS.
+// Row r = (c, line) of the pair index holds spins S[r Lx + x] (x < Lx, zero
+// to 512) and spectrum X[r H + k] (H = 257).
+__global__ __launch_bounds__(kT512) void k_xfft512_fwd(const double *__restrict__ S, float2 *__restrict__ X, int Lx,
+                                                       int64_t nrows, const float2 *__restrict__ tw512) {
+    __shared__ float2 lds[512 * kPitch];
+    const int t = threadIdx.x;
+    const int64_t pair0 = (int64_t)blockIdx.x * kW512;
+    {
+        const int wp = t >> 6, n0 = t & 63;
+        const int64_t ra = 2 * (pair0 + wp), rb = ra + 1;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int n = 64 * a + n0;
+            const float re = (n < Lx && ra < nrows) ? (float)S[ra * Lx + n] : 0.0f;
+            const float im = (n < Lx && rb < nrows) ? (float)S[rb * Lx + n] : 0.0f;
+            lds[n * kPitch + wp] = make_float2(re, im);
+        }
+    }
+    __syncthreads();
+    const int w = t & (kW512 - 1), q = t >> kW512Log;
+    float2 v[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[a] = lds[(64 * a + q) * kPitch + w];
+    fft512<false>(v, lds, q, q, w, tw512);
+    __syncthreads();
+    const int qq = (q >> 3) + 8 * (q & 7);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) lds[(qq + 64 * h) * kPitch + w] = v[h];
+    __syncthreads();
+    {
+        const int wp = t >> 6, k0 = t & 63;
+        const int64_t ra = 2 * (pair0 + wp), rb = ra + 1;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const int k = k0 + 64 * m;
+            if (k > 256) break;
+            const float2 zk = lds[k * kPitch + wp], zm = lds[((512 - k) & 511) * kPitch + wp];
+            if (ra < nrows) X[ra * 257 + k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            if (rb < nrows) X[rb * 257 + k] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+        }
+    }
+}
+
+// The inverse: Z[n] = A[n] + i B[n] over all 512 bins from the stored half
+// (A[512 - k] = conj A[k]; the imaginary parts of bins 0 and 256 dropped, as
+// for a real inverse transform), one unnormalised inverse FFT, and rows
+// x < Lx of z = a + i b written to the field.
+__global__ __launch_bounds__(kT512) void k_xfft512_inv(const float2 *__restrict__ X, float *__restrict__ b, int Lx,
+                                                       int64_t nrows, const float2 *__restrict__ tw512) {
+    __shared__ float2 lds[512 * kPitch];
+    const int t = threadIdx.x;
+    const int64_t pair0 = (int64_t)blockIdx.x * kW512;
+    {
+        const int wp = t >> 6, n0 = t & 63;
+        const int64_t ra = 2 * (pair0 + wp), rb = ra + 1;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int n = 64 * a + n0;
+            const int k = n <= 256 ? n : 512 - n;
+            float2 A = ra < nrows ? X[ra * 257 + k] : make_float2(0.0f, 0.0f);
+            float2 B = rb < nrows ? X[rb * 257 + k] : make_float2(0.0f, 0.0f);
+            if (k == 0 || k == 256) {
+                A.y = 0.0f;
+                B.y = 0.0f;
+            } else if (n > 256) {
+                A.y = -A.y;
+                B.y = -B.y;
+            }
+            lds[n * kPitch + wp] = make_float2(A.x - B.y, A.y + B.x);
+        }
+    }
+    __syncthreads();
+    const int w = t & (kW512 - 1), q = t >> kW512Log;
+    float2 v[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[a] = lds[(64 * a + q) * kPitch + w];
+    fft512<true>(v, lds, q, q, w, tw512);
+    __syncthreads();
+    const int qq = (q >> 3) + 8 * (q & 7);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) lds[(qq + 64 * h) * kPitch + w] = v[h];
+    __syncthreads();
+    {
+        const int wp = t >> 6, n0 = t & 63;
+        const int64_t ra = 2 * (pair0 + wp), rb = ra + 1;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int n = 64 * a + n0;
+            if (n >= Lx) break;
+            const float2 z = lds[n * kPitch + wp];
+            if (ra < nrows) b[ra * Lx + n] = z.x;
+            if (rb < nrows) b[rb * Lx + n] = z.y;
+        }
+    }
+}
+
 // The dipole spectrum reordered for the fused z pass: block g of 16 columns
 // reads kernb[g][kz][c][0..15] for its kz, one contiguous run per kz.
 __global__ void k_kern_block(const float *__restrict__ kern, float *__restrict__ kernb, int64_t J, int64_t n_cplx,
@@ -428,7 +531,7 @@ void destroy_dipolar(DipolarPlan *p) {
     if (p->fwd_ok) hipfftDestroy(p->fwd);
     if (p->inv_ok) hipfftDestroy(p->inv);
     for (void *q : {(void *)p->R, (void *)p->X, (void *)p->Y, (void *)p->Z, (void *)p->kern, (void *)p->kernb, (void *)p->tw_y,
-                    (void *)p->tw_z})
+                    (void *)p->tw_z, (void *)p->tw_x})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -458,7 +561,8 @@ spx_status create_dipolar(const int32_t dims[3], const double cell[9], double mu
         return SPX_OK;
     };
     spx_status s;
-    if ((s = alloc((void **)&p->R, sizeof(float) * 3 * rows * Px, "dipolar rows")) != SPX_OK ||
+    if ((Px != 512 && (s = alloc((void **)&p->R, sizeof(float) * 3 * rows * Px, "dipolar rows")) != SPX_OK) ||
+        (Px == 512 && (s = alloc((void **)&p->tw_x, sizeof(float2) * 512, "dipolar twiddles")) != SPX_OK) ||
         (s = alloc((void **)&p->X, sizeof(float2) * 3 * rows * p->H, "dipolar x spectra")) != SPX_OK ||
         (s = alloc((void **)&p->Y, sizeof(float2) * 3 * (int64_t)Lz * Py * p->H, "dipolar xy spectra")) != SPX_OK ||
         (Pz != 512 && (s = alloc((void **)&p->Z, sizeof(float2) * 3 * p->n_cplx, "dipolar spectra")) != SPX_OK) ||
@@ -477,6 +581,11 @@ spx_status create_dipolar(const int32_t dims[3], const double cell[9], double mu
     hipError_t e = hipMemcpyAsync(p->tw_y, ty.data(), sizeof(float2) * ty.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->tw_z, tz.data(), sizeof(float2) * tz.size(), hipMemcpyHostToDevice, st);
+    std::vector<float2> tx(Px == 512 ? 512 : 0);
+    for (size_t k = 0; k < tx.size(); ++k)
+        tx[k] = make_float2((float)std::cos(2.0 * M_PI * k / 512), (float)(-std::sin(2.0 * M_PI * k / 512)));
+    if (e == hipSuccess && Px == 512)
+        e = hipMemcpyAsync(p->tw_x, tx.data(), sizeof(float2) * tx.size(), hipMemcpyHostToDevice, st);
     // kernel spectrum, one tensor component at a time in FP64
     const int64_t n_real = (int64_t)Px * Py * Pz;
     double *treal = nullptr;
@@ -543,6 +652,10 @@ spx_status create_dipolar(const int32_t dims[3], const double cell[9], double mu
         p->kern = nullptr;
         *ws_bytes -= (int64_t)(sizeof(float) * 6 * p->n_cplx);
     }
+    if (Px == 512) {  // the x rows run in k_xfft512_fwd / k_xfft512_inv
+        *out = p;
+        return SPX_OK;
+    }
     // batched FP32 x-row transforms of the occupied lines of the three components
     int n[1] = {Px};
     int rembed[1] = {Px}, cembed[1] = {p->H};
@@ -567,12 +680,21 @@ spx_status eval_dipolar(DipolarPlan *p, const double *S, float *bdip, hipStream_
     if (!p) return set_error(SPX_ERR_INVALID_ARG, "dipolar path not set up");
     const int Lx = p->L[0], Ly = p->L[1], Lz = p->L[2], Px = p->P[0], Py = p->P[1], Pz = p->P[2], H = p->H;
     const int64_t rows = (int64_t)Ly * Lz;
-    k_pad_rows<<<(unsigned)(3 * rows), kB, 0, st>>>(S, Lx, Px, rows, p->N, p->R);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return set_hip_error(e, "dipolar pad");
-    hipfftSetStream(p->fwd, st);
-    hipfftResult fr = hipfftExecR2C(p->fwd, p->R, (hipfftComplex *)p->X);
-    if (fr != HIPFFT_SUCCESS) return fft_fail(fr, "dipolar R2C");
+    // x rows: pairs of rows, 16 pairs per block
+    const unsigned xgrid = (unsigned)(((3 * rows + 1) / 2 + kW512 - 1) / kW512);
+    hipError_t e;
+    if (Px == 512) {
+        k_xfft512_fwd<<<xgrid, kT512, 0, st>>>(S, p->X, Lx, 3 * rows, p->tw_x);
+        e = hipGetLastError();
+        if (e != hipSuccess) return set_hip_error(e, "dipolar x rows");
+    } else {
+        k_pad_rows<<<(unsigned)(3 * rows), kB, 0, st>>>(S, Lx, Px, rows, p->N, p->R);
+        e = hipGetLastError();
+        if (e != hipSuccess) return set_hip_error(e, "dipolar pad");
+        hipfftSetStream(p->fwd, st);
+        hipfftResult fr = hipfftExecR2C(p->fwd, p->R, (hipfftComplex *)p->X);
+        if (fr != HIPFFT_SUCCESS) return fft_fail(fr, "dipolar R2C");
+    }
     const int64_t plane = (int64_t)Py * H;
     // y: X [3 Lz][Ly rows][H] -> Y [3 Lz][Py][H]
     e = colfft<false>(p->X, p->Y, Py, Ly, Py, H, 3 * (int64_t)Lz, (int64_t)Ly * H, plane, p->tw_y, st);
@@ -599,8 +721,14 @@ spx_status eval_dipolar(DipolarPlan *p, const double *S, float *bdip, hipStream_
     if (e == hipSuccess)
         e = colfft<true>(p->Y, p->X, Py, Py, Ly, H, 3 * (int64_t)Lz, plane, (int64_t)Ly * H, p->tw_y, st);
     if (e != hipSuccess) return set_hip_error(e, "dipolar column transforms");
+    if (Px == 512) {
+        k_xfft512_inv<<<xgrid, kT512, 0, st>>>(p->X, bdip, Lx, 3 * rows, p->tw_x);
+        e = hipGetLastError();
+        if (e != hipSuccess) return set_hip_error(e, "dipolar x rows");
+        return SPX_OK;
+    }
     hipfftSetStream(p->inv, st);
-    fr = hipfftExecC2R(p->inv, (hipfftComplex *)p->X, p->R);
+    hipfftResult fr = hipfftExecC2R(p->inv, (hipfftComplex *)p->X, p->R);
     if (fr != HIPFFT_SUCCESS) return fft_fail(fr, "dipolar C2R");
     k_crop_rows<<<(unsigned)(3 * rows), kB, 0, st>>>(p->R, Lx, Px, rows, p->N, bdip);
     e = hipGetLastError();

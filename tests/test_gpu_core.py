@@ -363,7 +363,11 @@ def dip_workload(L):
     return w
 
 
-@pytest.mark.parametrize("L", [(5, 4, 6), (8, 8, 8), (1, 3, 2), (7, 1, 9), (4, 256, 3), (3, 4, 200)])
+# x extents 200 and 130 pad to 512: the x rows run as pairs of real rows in
+# one complex transform (45 rows in the first case, so one row is unpaired),
+# the last case with the fused z pass as well
+@pytest.mark.parametrize("L", [(5, 4, 6), (8, 8, 8), (1, 3, 2), (7, 1, 9), (4, 256, 3), (3, 4, 200), (200, 3, 5),
+                               (130, 2, 140)])
 def test_dipolar_field_vs_direct_sum(L):
     from paper_2605_26016_amd import spx  # noqa: F401
     w = dip_workload(L)
