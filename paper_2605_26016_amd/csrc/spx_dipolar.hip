@@ -289,6 +289,29 @@ __device__ __forceinline__ void fft512(float2 v[8], float2 *lds, int qin, int q,
     dft8<INV>(v);
 }
 
+// The same transform with its two exchanges in two LDS buffers (A, then B):
+// each exchange is write, barrier, read, and a buffer is written again only
+// after the barrier that followed its last read, so two barriers per
+// transform suffice (against four with one buffer).
+template <bool INV>
+__device__ __forceinline__ void fft512_2buf(float2 v[8], float2 *ldsA, float2 *ldsB, int qin, int q, int w,
+                                            const float2 *__restrict__ tw) {
+    dft8<INV>(v);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) ldsA[(c * 64 + qin) * kPitch + w] = c ? cmulw<INV>(v[c], tw[(qin * c) & 511]) : v[c];
+    __syncthreads();
+    const int c2 = q >> 3, f = q & 7;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = ldsA[(c2 * 64 + 8 * e + f) * kPitch + w];
+    dft8<INV>(v);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) ldsB[(c2 * 64 + 8 * g + f) * kPitch + w] = cmulw<INV>(v[g], tw[(8 * f * g) & 511]);
+    __syncthreads();
+#pragma unroll
+    for (int ff = 0; ff < 8; ++ff) v[ff] = ldsB[(c2 * 64 + 8 * f + ff) * kPitch + w];
+    dft8<INV>(v);
+}
+
 template <bool INV>
 __global__ __launch_bounds__(kT512) void k_colfft512(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                      int nin, int nout, int64_t J, int64_t in_bs, int64_t out_bs,
@@ -457,22 +480,23 @@ __global__ void k_kern_block(const float *__restrict__ kern, float *__restrict__
 __global__ __launch_bounds__(kT512) void k_zconv512(float2 *__restrict__ Y, const float *__restrict__ kernb, int Lz,
                                                     int64_t J, int nkz, const float2 *__restrict__ tw512,
                                                     int zsym) {
-    __shared__ float2 lds[512 * kPitch];
+    __shared__ float2 ldsA[512 * kPitch], ldsB[512 * kPitch];
     const int t = threadIdx.x;
     const int w = t & (kW512 - 1), q = t >> kW512Log;
     const int64_t j = (int64_t)blockIdx.x * kW512 + w;
     const bool col = j < J;
     const int64_t cs = (int64_t)Lz * J;
+    // all three components' loads in flight before the first transform
     float2 v[3][8];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             const int r = 64 * a + q;
             v[c][a] = (col && r < Lz) ? Y[c * cs + (int64_t)r * J + j] : make_float2(0.0f, 0.0f);
         }
-        fft512<false>(v[c], lds, q, q, w, tw512);
-    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft512_2buf<false>(v[c], ldsA, ldsB, q, q, w, tw512);
     const int qq = (q >> 3) + 8 * (q & 7);
     if (col) {
 #pragma unroll
@@ -492,7 +516,7 @@ __global__ __launch_bounds__(kT512) void k_zconv512(float2 *__restrict__ Y, cons
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        fft512<true>(v[c], lds, qq, q, w, tw512);
+        fft512_2buf<true>(v[c], ldsA, ldsB, qq, q, w, tw512);
         if (col) {
 #pragma unroll
             for (int h = 0; h < 8; ++h) {
