@@ -110,7 +110,10 @@ typedef struct {
  * field_prec SPX_BF16_MFMA / SPX_FP16_MFMA run it on the matrix cores,
  * SPX_FP32 runs the direct FP32 convolution on the vector ALUs (Methods,
  * backend representations: dense convolution).  autotune: 0 off, 1 time candidate launch shapes at setup and
- * keep the fastest (cached per shape key in tune_cache_path if non-NULL).
+ * keep the fastest (cached per shape key in tune_cache_path if non-NULL, one
+ * JSON object per line: {"key": ..., "zchunk": ..., "heun_mode": ..., "us": ...,
+ * "tile_rows": ...}; plain lines "key zchunk heun_mode us [tile_rows]" are
+ * read as well; the last entry of a key wins).
  * stencil_engine: 0 auto, 1 gather kernel (any bond table), 2 z-marching LDS
  * engine (bond tables that match a built-in shell shape: simple cubic shells
  * 1, 1-3, 1-4; bcc shells 1-5).  zchunk: z planes per block of the z-march

@@ -793,18 +793,21 @@ static void heun_buffers_trim(spx_ham *h) {
 }
 
 // Autotuner of the z-march engine: times stochastic Heun steps for every
-// candidate (z planes per block, stored or recomputed corrector field) on a
-// scratch state and keeps the fastest.  Results are cached per shape key
-// (shell shape, precision, sublattices, extents, boundary flags) as lines
-// "key zchunk heun_field microseconds" in cache_path when it is given.
+// candidate (z planes per block, stored or recomputed corrector field, and
+// for the fused step the block rows) on a scratch state and keeps the
+// fastest.  Results are cached per shape key (shell shape, precision,
+// sublattices, extents, boundary flags) in cache_path when it is given, one
+// JSON object per line, {"key": ..., "zchunk": ..., "heun_mode": ...,
+// "us": ..., "tile_rows": ...}; lines of the earlier plain form
+// "key zchunk heun_mode us [tile_rows]" are read as well.
 static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z, bool tune_field, hipStream_t st) {
     const Grid &g = h->grid;
     char key[160];
     std::snprintf(key, sizeof(key), "shape%d_prec%d_sub%d_%dx%dx%d_per%d%d%d", h->zp.kind, h->field_prec, g.n_sub,
                   g.Lx, g.Ly, g.Lz, g.per[0], g.per[1], g.per[2]);
-    // cache lines: key, z chunk, Heun mode, microseconds per step, and the
-    // fused step's rows per block (0 for the other modes; lines without it
-    // read as 0)
+    // cache entries: key, z chunk, Heun mode, microseconds per step, and the
+    // fused step's rows per block (0 for the other modes; plain lines
+    // without it read as 0)
     const bool tune_rows = h->fusable && h->zp.kind == SHAPE_SC_NN && h->zp.prec == 1 && h->zp.frows == 0;
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "r")) {
@@ -816,7 +819,13 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
             double cus = 0.0;
             while (std::fgets(line, sizeof(line), f)) {
                 rows = 0;
-                const int n = std::sscanf(line, "%159s %d %d %lf %d", k2, &z, &hf, &us, &rows);
+                int n = std::sscanf(line, " {\"key\": \"%159[^\"]\", \"zchunk\": %d, \"heun_mode\": %d, \"us\": %lf, "
+                                          "\"tile_rows\": %d",
+                                    k2, &z, &hf, &us, &rows);
+                if (n != 5) {
+                    rows = 0;
+                    n = line[0] == '{' ? 0 : std::sscanf(line, "%159s %d %d %lf %d", k2, &z, &hf, &us, &rows);
+                }
                 if (n >= 4 && std::strcmp(k2, key) == 0 && z > 0 && z <= 4096 && hf >= 1 && hf <= kMaxHeunMode &&
                     (rows == 0 || rows == 8 || rows == 16)) {
                     cz = z; chf = hf; cus = us; crows = rows; hit = true;   // the last matching line wins
@@ -920,7 +929,8 @@ static spx_status autotune_heun(spx_ham *h, const char *cache_path, bool tune_z,
     heun_buffers_trim(h);
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %.3f %d\n", key, bz, bh, best, bh == kHeunFused ? fused_rows(h->zp) : 0);
+            std::fprintf(f, "{\"key\": \"%s\", \"zchunk\": %d, \"heun_mode\": %d, \"us\": %.3f, \"tile_rows\": %d}\n",
+                         key, bz, bh, best, bh == kHeunFused ? fused_rows(h->zp) : 0);
             std::fclose(f);
         }
     }

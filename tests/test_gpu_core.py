@@ -9,6 +9,8 @@ Tolerances (written per test):
   - Philox blocks and the derived uniforms: bit-exact;
   - Gaussian normals: within a few ulp (device vs host libm), checked at 1e-13.
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -445,13 +447,15 @@ def test_autotuner_picks_candidate_and_caches(tmp_path):
     info = spx.get_info(h)
     assert info.tuned == 1 and info.zchunk in (4, 8, 16) and info.heun_field in (1, 2, 3, 4, 5, 6, 7)
     assert info.tuned_step_us > 0
-    lines = open(cache).read().split("\n")
-    assert any(l.startswith("shape3_prec1_sub2_16x16x16") for l in lines)
+    # one JSON object per line
+    entries = [json.loads(l) for l in open(cache) if l.strip()]
+    assert [e["key"] for e in entries] == ["shape3_prec1_sub2_16x16x16_per111"]
+    assert (entries[0]["zchunk"], entries[0]["heun_mode"]) == (info.zchunk, info.heun_field)
     h2 = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache)
     i2 = spx.get_info(h2)
     assert (i2.zchunk, i2.heun_field) == (info.zchunk, info.heun_field)
     # the second setup read the cache instead of tuning again
-    assert sum(l.startswith("shape3_prec1_sub2_16x16x16") for l in open(cache).read().split("\n")) == 1
+    assert sum(1 for l in open(cache) if l.strip()) == 1
     assert i2.tuned == 1 and i2.tuned_step_us == pytest.approx(info.tuned_step_us, abs=1e-3)
     # the z chunk does not change results (same Heun mode, other launch shape)
     S0 = w.initial_state()

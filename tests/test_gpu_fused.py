@@ -13,6 +13,8 @@ Tolerances (as for the other Heun modes): one step from identical FP64 state
 max |S - S_ref| <= 1e-9 per component in mixed precision (FP32 field, FP64
 state) and 1e-12 in FP64, times the number of steps.
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -115,8 +117,8 @@ def test_fused_tuner_searches_block_rows(tmp_path):
     h = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache, heun_field=8)
     info = spx.get_info(h)
     assert info.tuned == 1 and info.heun_field == 8 and info.tile_rows in (8, 16)
-    line = open(cache).read().split("\n")[0].split()
-    assert int(line[2]) == 8 and int(line[4]) == info.tile_rows
+    entry = json.loads(open(cache).readline())
+    assert entry["heun_mode"] == 8 and entry["tile_rows"] == info.tile_rows
     h2 = gpu_hamiltonian(w, field_prec="fp32", autotune=1, tune_cache_path=cache, heun_field=8)
     info2 = spx.get_info(h2)
     assert (info2.zchunk, info2.heun_field, info2.tile_rows) == (info.zchunk, 8, info.tile_rows)
