@@ -343,11 +343,13 @@ __global__ __launch_bounds__(kMcB) void k_mc_from_cm(const double *__restrict__ 
 // kernel's site loop, draw and update, every neighbour at the tabulated
 // offset of its bond and class, and the new spin also written to the
 // site's ghost copies.
+// (four waves per SIMD asked of the register allocator: the heat-bath
+// instantiations otherwise take a few registers more than 128)
 template <bool ISO, int METHOD, int UNR>
-__global__ __launch_bounds__(kMcB) __attribute__((amdgpu_waves_per_eu(4))) void k_mc_colour_cm(double *__restrict__ P, BondTable tb, Grid g, Onsite os,
-                                                       McColour col, int c, double beta, uint64_t seed,
-                                                       uint64_t sweep, unsigned long long *__restrict__ acc,
-                                                       const int64_t *__restrict__ coff, CmDims d) {
+__global__ __launch_bounds__(kMcB) __attribute__((amdgpu_waves_per_eu(4)))
+void k_mc_colour_cm(double *__restrict__ P, BondTable tb, Grid g, Onsite os, McColour col, int c, double beta,
+                    uint64_t seed, uint64_t sweep, unsigned long long *__restrict__ acc,
+                    const int64_t *__restrict__ coff, CmDims d) {
     const int C = col.C;
     const int J = d.J;
     const int64_t total = d.n_rows * J;
