@@ -451,10 +451,11 @@ def learned_experiment(family, args):
                    for e in args.train_sizes.split(","))
     te = tuple(int(e) for e in args.test_sizes.split(",")) if args.test_sizes else None
     dil = tuple(int(v) for v in args.dilation.split(",")) if args.dilation else None
+    damp = tuple(float(v) for v in args.damping.split(",")) if args.damping else ()
     return pathinit.learned_vs_geodesic(family, n_train=args.n_train, n_test=args.n_test, epochs=args.epochs,
                                         lr=args.lr, max_iter=args.max_iter, train_sizes=tr, test_sizes=te,
                                         n_img_test=args.test_images, dilation=dil, endpoint_tol=args.endpoint_tol,
-                                        log=log)
+                                        damping=damp, log=log)
 
 
 def heun_workload(args, w, steps=None, warmup=None, cpu=True):
@@ -840,6 +841,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3, help="initial Adam step of the path net (cosine decay to lr/20)")
     ap.add_argument("--families", default="skyrmion,hopfion")
     ap.add_argument("--max-iter", type=int, default=30000)
+    ap.add_argument("--damping", default="",
+                    help="learned init: further factors for the network's correction, e.g. 0.6,0.3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "

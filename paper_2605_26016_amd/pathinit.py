@@ -191,7 +191,7 @@ def minimize(h, states, tol=1e-4, max_iter=20000, chunk=1000, vp_dt=0.1, vp_mass
 
 def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max_iter=30000, train_sizes=None,
                         test_sizes=None, n_img_train=16, n_img_test=32, dilation=None, endpoint_tol=2e-4,
-                        log=None):
+                        damping=(), log=None):
     """Train the path corrector on GNEB-converged paths of one family and
     compare GNEB from the learned and the geodesic initial path on held-out
     end states.
@@ -212,7 +212,11 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
     layers, and (1, 1, 1, 1) for skyrmion films).  Both GNEB runs use the same
     optimiser settings; a pair counts when both converge to max |F| < 1e-3
     meV with barriers within 0.1 meV (same channel).  End states are drawn by
-    the seeded texture generators (training seeds 1000.., test seeds 5000..)."""
+    the seeded texture generators (training seeds 1000.., test seeds 5000..).
+    damping: further factors lambda for the correction (the last layer's
+    weights and bias scaled by lambda, so the tangent update u is scaled
+    exactly); GNEB runs again from each damped learned path and the same
+    statistics are reported per lambda."""
     import time
 
     import torch
@@ -342,6 +346,29 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
     spx.net_set_precision(net, "fp32")
     log(f"[path-init] {family}: initial paths of the test batch {init_ms['fp32']:.2f} ms FP32, "
         f"{init_ms['bf16']:.2f} ms BF16 MFMA, max |dS| {d_bf16:.2e}")
+    # damped corrections: the last layer (3 x 16 x 27 weights and 3 biases,
+    # the end of the parameter vector) scaled by lambda
+    n_last = 3 * 16 * 27 + 3
+    damped = {}
+    for lam in damping:
+        pl = p.clone()
+        pl[-n_last:] *= float(lam)
+        Yd = [y.clone() for y in Yl]
+        rd = converge(Hs, Yd, tol=1e-3, max_iter=max_iter, chunk=250, method=1, net=net, params=pl, log=log,
+                      what=f"{family} test learned x{lam}")
+        sd = [k for k in range(len(Yp)) if rp.converged[k] and rd.converged[k]
+              and abs(rd.barrier[k] - rp.barrier[k]) <= 0.1]
+        ip = float(np.mean(rp.iterations[sd])) if sd else None
+        idd = float(np.mean(rd.iterations[sd])) if sd else None
+        damped[str(lam)] = {"same_channel_within_0.1meV": len(sd), "converged": int(np.sum(rd.converged)),
+                            "mean_iterations_geodesic_same_channel": ip,
+                            "mean_iterations_learned_same_channel": idd,
+                            "iteration_ratio_learned_over_geodesic": (idd / ip) if sd else None,
+                            "iterations_learned": rd.iterations.tolist(),
+                            "barrier_learned_meV": np.round(rd.barrier, 4).tolist()}
+        log(f"[path-init] {family}: correction x{lam}: {len(sd)}/{len(Yp)} test pairs in the same channel; "
+            f"iterations learned {idd} vs geodesic {ip}")
+        del Yd
     both = [k for k in range(len(Yp)) if rp.converged[k] and rl.converged[k]]
     dbar = np.abs(rl.barrier - rp.barrier)
     same = [k for k in both if dbar[k] <= 0.1]
@@ -363,6 +390,7 @@ def learned_vs_geodesic(family, n_train=200, n_test=12, epochs=150, lr=2e-3, max
             "mean_iterations_geodesic_same_channel": it_p, "mean_iterations_learned_same_channel": it_l,
             "iteration_ratio_learned_over_geodesic": (it_l / it_p) if same else None,
             "max_barrier_difference_same_channel_meV": float(np.max(dbar[same])) if same else None,
+            "damped": damped,
             "init_ms_test_batch": {"fp32": init_ms["fp32"], "bf16_mfma": init_ms["bf16"]},
             "init_bf16_vs_fp32_max_dS": d_bf16, "iterations_learned_bf16": rb.iterations.tolist(),
             "same_channel_bf16_within_0.1meV": len(same_b),
