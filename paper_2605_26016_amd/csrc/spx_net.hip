@@ -27,10 +27,12 @@
 // matrix cores (spx_net_set_precision): for 16 output sites x 16 output
 // channels (inputs and outputs padded to 16 channels), K runs over pairs of
 // taps x 16 input channels, 14 v_mfma_f32_16x16x32_bf16 per layer with FP32
-// accumulation.  The input tile is staged in LDS as BF16 with the channels
-// innermost, so a lane's operand fragment (8 channels of one site and tap)
-// is one 16-byte read; the weight fragments of a layer are packed from the
-// FP32 parameters by a small kernel before the layer runs.
+// accumulation.  The activations between layers are stored as BF16 with the
+// channels innermost (32 bytes per site), each layer's epilogue applying
+// the next layer's SiLU, so a tile is staged in LDS by 16-byte copies and a
+// lane's operand fragment (8 channels of one site and tap) is one 16-byte
+// read; the weight fragments of a layer are packed from the FP32 parameters
+// by a small kernel before the layer runs.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -322,27 +324,63 @@ __global__ void k_wfrag(const float *__restrict__ W, int cin, int cout, bf16x8 *
     frag[i] = v;
 }
 
+// The BF16 form keeps each layer's input as BF16 activations with the 16
+// channels innermost, a[b][p][16] (32 bytes per site; layer 0: the 10 input
+// channels and six zeros), so that staging a tile is a copy of 32 bytes per
+// halo site.  Each layer's epilogue writes the next layer's input,
+// BF16(SiLU(z)); the last writes its FP32 pre-activation u [b][3][p] for the
+// head.
+
+// layer-0 input: (S_g, S_A, S_B, t) rounded to float, then to BF16
+__global__ void k_net_input_bf16(const double *__restrict__ Sg, const double *__restrict__ SA,
+                                 const double *__restrict__ SB, const float *__restrict__ t,
+                                 bf16x8 *__restrict__ xa, int64_t P, int64_t ab_stride) {
+    const int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const int b = blockIdx.y;
+    if (p >= P) return;
+    const int64_t o = (int64_t)b * 3 * P, oab = (int64_t)b * ab_stride;
+    float v[16];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v[c] = (float)Sg[o + c * P + p];
+        v[3 + c] = (float)SA[oab + c * P + p];
+        v[6 + c] = (float)SB[oab + c * P + p];
+    }
+    v[9] = t[b];
+#pragma unroll
+    for (int c = 10; c < 16; ++c) v[c] = 0.0f;
+    bf16x8 lo, hi;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        lo[j] = (__bf16)v[j];
+        hi[j] = (__bf16)v[8 + j];
+    }
+    bf16x8 *dst = xa + ((int64_t)b * P + p) * 2;
+    dst[0] = lo;
+    dst[1] = hi;
+}
+
 // out[co] = bias[co] + sum_ci sum_k W[co][ci][k] a[ci](p + (k - 1) d), BF16
 // operands, FP32 accumulation; the block's 8 x 8 x 4 tile is 16 groups of 16
-// sites (two y rows of one z plane), four per wavefront.
-template <int CIN, int COUT, bool SILU_IN>
-__global__ __launch_bounds__(kNT) void k_conv_mfma(const float *__restrict__ in, const bf16x8 *__restrict__ frag,
-                                                   const float *__restrict__ bias, float *__restrict__ out,
+// sites (two y rows of one z plane), four per wavefront.  LAST: write the
+// FP32 pre-activation of the COUT channels to u [b][COUT][p]; otherwise
+// BF16(SiLU) of all 16 channels to the next activation buffer.
+template <int COUT, bool LAST>
+__global__ __launch_bounds__(kNT) void k_conv_mfma(const bf16x8 *__restrict__ in, const bf16x8 *__restrict__ frag,
+                                                   const float *__restrict__ bias, void *__restrict__ out,
                                                    NetDims d) {
     __shared__ __attribute__((aligned(16))) __bf16 tile[kHalo][16];
     const NetTile tl = tile_origin(d);
-    const float *src = in + (int64_t)blockIdx.z * CIN * d.P;
-    for (int idx = threadIdx.x; idx < 16 * kHalo; idx += kNT) {
-        const int ci = idx / kHalo, r = idx - ci * kHalo;
+    const bf16x8 *src = in + (int64_t)blockIdx.z * d.P * 2;
+    for (int e = threadIdx.x; e < 2 * kHalo; e += kNT) {
+        const int r = e >> 1, half = e & 1;
         const int hx = r % kHX, hy = (r / kHX) % kHY, hz = r / (kHX * kHY);
         const int gx = tl.px + d.dil * (tl.x0 + hx - 1), gy = tl.py + d.dil * (tl.y0 + hy - 1),
                   gz = tl.pz + d.dil * (tl.z0 + hz - 1);
-        float v = 0.0f;
-        if (ci < CIN && gx >= 0 && gy >= 0 && gz >= 0 && gx < d.Lx && gy < d.Ly && gz < d.Lz) {
-            v = src[ci * d.P + gx + (int64_t)d.Lx * (gy + (int64_t)d.Ly * gz)];
-            if (SILU_IN) v = silu(v);
-        }
-        tile[r][ci] = (__bf16)v;
+        bf16x8 v = {};
+        if (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.Lx && gy < d.Ly && gz < d.Lz)
+            v = src[(gx + (int64_t)d.Lx * (gy + (int64_t)d.Ly * gz)) * 2 + half];
+        *reinterpret_cast<bf16x8 *>(&tile[r][8 * half]) = v;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -365,9 +403,8 @@ __global__ __launch_bounds__(kNT) void k_conv_mfma(const float *__restrict__ in,
         }
     }
     const int co = lane & 15;
-    if (co >= COUT) return;
-    const float bco = bias[co];
-    float *dst = out + (int64_t)blockIdx.z * COUT * d.P + (int64_t)co * d.P;
+    if (LAST && co >= COUT) return;
+    const float bco = co < COUT ? bias[co] : 0.0f;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int mb = 4 * wave + m;
@@ -376,7 +413,16 @@ __global__ __launch_bounds__(kNT) void k_conv_mfma(const float *__restrict__ in,
             const int r = 4 * grp + i;  // the site of accumulator i
             const int x = tl.px + d.dil * (tl.x0 + (r & 7)), y = tl.py + d.dil * (tl.y0 + 2 * (mb & 3) + (r >> 3)),
                       z = tl.pz + d.dil * (tl.z0 + (mb >> 2));
-            if (x < d.Lx && y < d.Ly && z < d.Lz) dst[x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z)] = acc[m][i] + bco;
+            if (x >= d.Lx || y >= d.Ly || z >= d.Lz) continue;
+            const int64_t p = x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z);
+            const float zv = acc[m][i] + bco;
+            if constexpr (LAST) {
+                float *u = static_cast<float *>(out) + (int64_t)blockIdx.z * COUT * d.P;
+                u[(int64_t)co * d.P + p] = zv;
+            } else {
+                __bf16 *a = static_cast<__bf16 *>(out) + ((int64_t)blockIdx.z * d.P + p) * 16;
+                a[co] = (__bf16)silu(zv);
+            }
         }
     }
 }
@@ -425,6 +471,8 @@ struct NetWork {
     double *lpart = nullptr;
     size_t lpart_cap = 0;
     bf16x8 *frag = nullptr;     // BF16 MFMA weight fragments, [4 layers][14][64]
+    bf16x8 *act[2] = {nullptr, nullptr};  // BF16 activations [B][P][16] (two 8-channel halves), ping-pong
+    size_t act_cap = 0;                   // sites x images each holds
 };
 
 }  // namespace spx
@@ -453,7 +501,7 @@ int64_t layer_off(int l) {
 void net_free(NetWork &w) {
     for (void *p : {(void *)w.x, (void *)w.z[0], (void *)w.z[1], (void *)w.z[2], (void *)w.z[3], (void *)w.g[0],
                     (void *)w.g[1], (void *)w.g[2], (void *)w.g[3], (void *)w.wt, (void *)w.part, (void *)w.lpart,
-                    (void *)w.frag})
+                    (void *)w.frag, (void *)w.act[0], (void *)w.act[1]})
         if (p) (void)hipFree(p);
     w = NetWork{};
 }
@@ -498,26 +546,42 @@ dim3 conv_grid(const NetDims &d, int B) {
     return dim3((unsigned)(nbx * nby * d.dil * d.dil), (unsigned)(nbz * d.dil), (unsigned)B);
 }
 
-// forward through the four layers as BF16 implicit GEMMs (inference); z[l]
-// are pre-activations in FP32
+// forward through the four layers as BF16 implicit GEMMs (inference), from
+// the input states to the FP32 pre-activation u = z[3]
 hipError_t net_forward_layers_mfma(NetWork &w, const float *params, const NetDims &d, const int dil[4], int B,
-                                   hipStream_t st) {
+                                   const double *Sg, const double *SA, const double *SB, const float *t,
+                                   int64_t ab_stride, hipStream_t st) {
     if (!w.frag) {
         hipError_t e = hipMalloc((void **)&w.frag, sizeof(bf16x8) * 4 * kTapPairs * 64);
         if (e != hipSuccess) return e;
     }
+    const size_t need = (size_t)d.P * B;
+    if (need > w.act_cap) {
+        for (int k = 0; k < 2; ++k) {
+            if (w.act[k]) (void)hipFree(w.act[k]);
+            w.act[k] = nullptr;
+        }
+        w.act_cap = 0;
+        for (int k = 0; k < 2; ++k) {
+            hipError_t e = hipMalloc((void **)&w.act[k], sizeof(bf16x8) * 2 * need);
+            if (e != hipSuccess) return e;
+        }
+        w.act_cap = need;
+    }
     const int fb = (kTapPairs * 64 + 255) / 256;
     for (int l = 0; l < 4; ++l)
         k_wfrag<<<fb, 256, 0, st>>>(params + layer_off(l), kC[l], kC[l + 1], w.frag + l * kTapPairs * 64);
+    const dim3 pg((unsigned)((d.P + kNT - 1) / kNT), (unsigned)B);
+    k_net_input_bf16<<<pg, kNT, 0, st>>>(Sg, SA, SB, t, w.act[0], d.P, ab_stride);
     const NetDims d0 = layer_dims(d, dil, 0), d1 = layer_dims(d, dil, 1), d2 = layer_dims(d, dil, 2),
                   d3 = layer_dims(d, dil, 3);
     const float *b0 = params + layer_off(0) + 16 * 10 * 27, *b1 = params + layer_off(1) + 16 * 16 * 27;
     const float *b2 = params + layer_off(2) + 16 * 16 * 27, *b3 = params + layer_off(3) + 3 * 16 * 27;
     bf16x8 *f = w.frag;
-    k_conv_mfma<10, 16, false><<<conv_grid(d0, B), kNT, 0, st>>>(w.x, f, b0, w.z[0], d0);
-    k_conv_mfma<16, 16, true><<<conv_grid(d1, B), kNT, 0, st>>>(w.z[0], f + kTapPairs * 64, b1, w.z[1], d1);
-    k_conv_mfma<16, 16, true><<<conv_grid(d2, B), kNT, 0, st>>>(w.z[1], f + 2 * kTapPairs * 64, b2, w.z[2], d2);
-    k_conv_mfma<16, 3, true><<<conv_grid(d3, B), kNT, 0, st>>>(w.z[2], f + 3 * kTapPairs * 64, b3, w.z[3], d3);
+    k_conv_mfma<16, false><<<conv_grid(d0, B), kNT, 0, st>>>(w.act[0], f, b0, w.act[1], d0);
+    k_conv_mfma<16, false><<<conv_grid(d1, B), kNT, 0, st>>>(w.act[1], f + kTapPairs * 64, b1, w.act[0], d1);
+    k_conv_mfma<16, false><<<conv_grid(d2, B), kNT, 0, st>>>(w.act[0], f + 2 * kTapPairs * 64, b2, w.act[1], d2);
+    k_conv_mfma<3, true><<<conv_grid(d3, B), kNT, 0, st>>>(w.act[1], f + 3 * kTapPairs * 64, b3, w.z[3], d3);
     return hipGetLastError();
 }
 
@@ -562,9 +626,14 @@ spx_status net_apply(spx_net *net, const float *params, const int32_t dims[3], i
     if (s != SPX_OK) return s;
     if ((s = net_reserve(net->w, d.P, batch, false)) != SPX_OK) return s;
     const dim3 pg((unsigned)((d.P + kNT - 1) / kNT), (unsigned)batch);
-    k_net_input<<<pg, kNT, 0, st>>>(Sg, SA, SB, t, net->w.x, d.P, shared_ends ? 0 : 3 * d.P);
-    hipError_t e = net->prec == SPX_BF16_MFMA ? net_forward_layers_mfma(net->w, params, d, net->dil, batch, st)
-                                              : net_forward_layers(net->w, params, d, net->dil, batch, st);
+    const int64_t ab_stride = shared_ends ? 0 : 3 * d.P;
+    hipError_t e;
+    if (net->prec == SPX_BF16_MFMA) {
+        e = net_forward_layers_mfma(net->w, params, d, net->dil, batch, Sg, SA, SB, t, ab_stride, st);
+    } else {
+        k_net_input<<<pg, kNT, 0, st>>>(Sg, SA, SB, t, net->w.x, d.P, ab_stride);
+        e = net_forward_layers(net->w, params, d, net->dil, batch, st);
+    }
     if (e == hipSuccess) {
         k_net_head<<<pg, kNT, 0, st>>>(net->w.z[3], Sg, nullptr, Shat, nullptr, nullptr, d.P, 0.0);
         e = hipGetLastError();
