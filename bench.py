@@ -211,11 +211,62 @@ def gneb_workload(args):
     del g, hams, imgs
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_gneb_baseline(args.cpu_seconds)
     out["hbm_copy_GBps"] = copy_bandwidth()
+    out["net_forward"] = net_forward_roofline()
     if args.no_learned:
         print(json.dumps(out), flush=True)
         return
     out["learned_init"] = {fam: learned_experiment(fam, args) for fam in args.families.split(",")}
     print(json.dumps(out), flush=True)
+
+
+# useful flops of the path corrector's forward per site: four 3^3
+# convolutions 10 -> 16 -> 16 -> 16 -> 3 channels, two flops per product
+NET_FLOP_PER_SITE = 2 * 27 * (10 * 16 + 16 * 16 + 16 * 16 + 16 * 3)
+
+
+def net_forward_roofline(L=(64, 64, 64), batch=16, reps=10):
+    """The path corrector's forward (dilation 1, 2, 4, 8) on a batch of
+    64^3 images with random parameters and states, FP32 on the vector ALUs and
+    BF16 implicit GEMMs on the matrix cores, against the dense BF16 MFMA
+    peak (useful flops: the padding of channels to 16 and of the 27 taps to
+    28 is not counted)."""
+    import torch
+
+    from paper_2605_26016_amd import pathinit, spx
+    N = L[0] * L[1] * L[2]
+    gen = torch.Generator(device="cuda").manual_seed(7)
+
+    def unit():
+        v = torch.randn((batch, 3, N), dtype=torch.float64, device="cuda", generator=gen)
+        return v / v.norm(dim=1, keepdim=True)
+
+    Sg, SA, SB = unit(), unit(), unit()
+    t = torch.linspace(0.1, 0.9, batch, dtype=torch.float32, device="cuda")
+    p = torch.from_numpy(pathinit.init_params(1)).float().cuda()
+    out = torch.empty((batch, 3, N), dtype=torch.float64, device="cuda")
+    res = {"images": batch, "lattice": list(L), "dilation": [1, 2, 4, 8],
+           "flop_per_site_useful": NET_FLOP_PER_SITE}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for prec in ("fp32", "bf16"):
+        net = spx.Net(dilation=(1, 2, 4, 8))
+        spx.net_set_precision(net, prec)
+        spx.net_forward(net, p, L, batch, Sg, SA, SB, t, out)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            spx.net_forward(net, p, L, batch, Sg, SA, SB, t, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[prec + "_ms"] = ms
+        res[prec + "_TFLOPs"] = batch * N * NET_FLOP_PER_SITE / ms / 1e9
+        del net
+    res["roofline"] = {"bound": "mfma", "achieved": round(res["bf16_TFLOPs"], 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(res["bf16_TFLOPs"] / MFMA_BF16_PEAK_TFLOPS, 4),
+                       "traffic": None, "kernel": "k_conv_mfma (BF16 network forward)"}
+    log(f"[bench] network forward 64^3 x {batch}: FP32 {res['fp32_ms']:.3f} ms, BF16 MFMA {res['bf16_ms']:.3f} ms "
+        f"({res['bf16_TFLOPs']:.1f} TFLOP/s)")
+    return res
 
 
 # Monte Carlo per attempted update: the spin is read (as a neighbour) and
