@@ -317,7 +317,12 @@ spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, doub
  * SPX_ERR_UNSUPPORTED with the dipolar term or when no colouring with C <= 64
  * is found (see spx_mc_find_colouring for the search's limits); SPX_ERR_INVALID_ARG for T <= 0, n_sweeps < 0 or another method.
  * `accepted` ([dev] uint64 or NULL) receives the number of accepted moves of
- * the call (heat-bath: every draw).  Asynchronous. */
+ * the call (heat-bath: every draw).  Asynchronous.  A call of two sweeps or
+ * more copies S into a colour-major layout held by the handle (allocated on
+ * the first such call, about 3 N doubles plus ghost slots and rows, freed
+ * with the Hamiltonian; if it cannot be allocated the sweeps run in place),
+ * runs every sweep there and copies the result back; the moves and results
+ * are the same bit for bit.  Overlapping calls on one handle race. */
 typedef struct {
     double temperature_K;
     uint64_t seed;
