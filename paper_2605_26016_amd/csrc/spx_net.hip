@@ -69,19 +69,22 @@ struct NetDims {
 struct NetTile {
     int x0, y0, z0, px, py, pz;
 };
-__device__ __forceinline__ NetTile tile_origin(const NetDims &d) {
+__device__ __forceinline__ NetTile tile_origin_at(const NetDims &d, int bx, int by) {
     const int nbx = (d.Sx + kTXn - 1) / kTXn, nby = (d.Sy + kTYn - 1) / kTYn, nbz = (d.Sz + kTZn - 1) / kTZn;
     NetTile t;
-    int r = blockIdx.x;
+    int r = bx;
     t.x0 = (r % nbx) * kTXn;
     r /= nbx;
     t.y0 = (r % nby) * kTYn;
     r /= nby;
     t.px = r % d.dil;
     t.py = r / d.dil;
-    t.z0 = ((int)blockIdx.y % nbz) * kTZn;
-    t.pz = (int)blockIdx.y / nbz;
+    t.z0 = (by % nbz) * kTZn;
+    t.pz = by / nbz;
     return t;
+}
+__device__ __forceinline__ NetTile tile_origin(const NetDims &d) {
+    return tile_origin_at(d, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 // Stage CIN input channels of image blockIdx.z with a 1-cell zero halo (in
@@ -360,69 +363,145 @@ __global__ void k_net_input_bf16(const double *__restrict__ Sg, const double *__
     dst[1] = hi;
 }
 
+// Workgroups are dealt to the 8 XCDs in turn by linear id (x fastest).  This
+// renumbering gives each XCD one contiguous range of the grid instead, so the
+// d^3 phase tiles of one region, consecutive in x, run on one XCD: the
+// strided halo rows they read and the partial cache lines they write meet in
+// its L2.  The grid holds fewer than 2^31 blocks.
+struct GridBlock {
+    int x, y, z;
+};
+__device__ __forceinline__ GridBlock xcd_grid_block() {
+    const uint32_t gx = gridDim.x, gy = gridDim.y, T = gx * gy * gridDim.z;
+    const uint32_t b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const uint32_t q = T / 8, r = T % 8, k = b % 8;
+    const uint32_t l = k * q + (k < r ? k : r) + b / 8;
+    return GridBlock{(int)(l % gx), (int)((l / gx) % gy), (int)(l / (gx * gy))};
+}
+
+// The BF16 halo tile in LDS: 32 bytes per site (16 channels), x rows of 10
+// sites padded to 336 bytes.  A 16-lane pass of an A-operand read covers two
+// y rows of 8 sites; with the 16-byte pad the second row starts four banks
+// off the first, so the 16 reads of 16 bytes fall on distinct banks.
+constexpr int kRowB = kHX * 32 + 16, kPlaneB = kHY * kRowB, kTileB = kHZ * kPlaneB;
+
+// byte offset of tap (kx, ky, kz) = (tap % 3, tap / 3 % 3, tap / 9) in the
+// tile; the padded tap 27 reads offset 0 (its weights are zero)
+constexpr int tap_bytes(int tap) { return tap >= 27 ? 0 : 32 * (tap % 3) + kRowB * ((tap / 3) % 3) + kPlaneB * (tap / 9); }
+
+// SiLU with the hardware reciprocal: its result is rounded to BF16 next
+__device__ __forceinline__ float silu_bf16(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
 // out[co] = bias[co] + sum_ci sum_k W[co][ci][k] a[ci](p + (k - 1) d), BF16
 // operands, FP32 accumulation; the block's 8 x 8 x 4 tile is 16 groups of 16
 // sites (two y rows of one z plane), four per wavefront.  LAST: write the
 // FP32 pre-activation of the COUT channels to u [b][COUT][p]; otherwise
-// BF16(SiLU) of all 16 channels to the next activation buffer.
+// BF16(SiLU) of all 16 channels to the next activation buffer.  Either goes
+// through LDS first, site-major, so that each thread then writes one site.
 template <int COUT, bool LAST>
 __global__ __launch_bounds__(kNT) void k_conv_mfma(const bf16x8 *__restrict__ in, const bf16x8 *__restrict__ frag,
                                                    const float *__restrict__ bias, void *__restrict__ out,
                                                    NetDims d) {
-    __shared__ __attribute__((aligned(16))) __bf16 tile[kHalo][16];
-    const NetTile tl = tile_origin(d);
-    const bf16x8 *src = in + (int64_t)blockIdx.z * d.P * 2;
-    for (int e = threadIdx.x; e < 2 * kHalo; e += kNT) {
-        const int r = e >> 1, half = e & 1;
-        const int hx = r % kHX, hy = (r / kHX) % kHY, hz = r / (kHX * kHY);
-        const int gx = tl.px + d.dil * (tl.x0 + hx - 1), gy = tl.py + d.dil * (tl.y0 + hy - 1),
-                  gz = tl.pz + d.dil * (tl.z0 + hz - 1);
-        bf16x8 v = {};
-        if (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.Lx && gy < d.Ly && gz < d.Lz)
-            v = src[(gx + (int64_t)d.Lx * (gy + (int64_t)d.Ly * gz)) * 2 + half];
-        *reinterpret_cast<bf16x8 *>(&tile[r][8 * half]) = v;
+    static_assert(kHX == 10 && kHY * kHZ == 60 && kNT >= 240, "staging map assumes the 10 x 10 x 6 halo");
+    static_assert(kTileB >= kNT * 32, "the epilogue reuses the tile");
+    __shared__ __attribute__((aligned(16))) char lds[kTileB];
+    const GridBlock g = xcd_grid_block();
+    const NetTile tl = tile_origin_at(d, g.x, g.y);
+    const int t = threadIdx.x;
+    // staging: thread t < 240 copies the 16-byte chunk c = t % 20 (halo x =
+    // c / 2, channels 8 (c % 2) .. + 7) of halo rows t / 20 + 12 k, k = 0..4
+    // (row = hy + kHY hz); sites outside the lattice are zero
+    if (t < 240) {
+        const int c = t % 20, hx = c >> 1, half = c & 1, r0 = t / 20;
+        const int gx = tl.px + d.dil * (tl.x0 + hx - 1);
+        const bool okx = gx >= 0 && gx < d.Lx;
+        const bf16x8 *src = in + (int64_t)g.z * d.P * 2 + half;
+        bf16x8 v[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int hr = r0 + 12 * k, hy = hr % kHY, hz = hr / kHY;
+            const int gy = tl.py + d.dil * (tl.y0 + hy - 1), gz = tl.pz + d.dil * (tl.z0 + hz - 1);
+            const bool ok = okx && gy >= 0 && gy < d.Ly && gz >= 0 && gz < d.Lz;
+            const int64_t o = ok ? (gx + (int64_t)d.Lx * (gy + (int64_t)d.Ly * gz)) * 2 : 0;
+            v[k] = src[o];
+            if (!ok) v[k] = bf16x8{};
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) *reinterpret_cast<bf16x8 *>(lds + (r0 + 12 * k) * kRowB + 16 * c) = v[k];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row = lane & 15, grp = lane >> 4;
+    const int lane = t & 63, wave = t >> 6, row = lane & 15, grp = lane >> 4;
+    // lane's A operand: site (x, y, z) = (row % 8, row / 8 + 2 m, wave) of
+    // group m, channels 8 (grp % 2) .. + 7; lanes 32..63 take the pair's
+    // second tap
+    const int abase = 32 * (row & 7) + kRowB * (row >> 3) + kPlaneB * wave + 16 * (grp & 1);
+    const bool second = grp >= 2;
     f32x4 acc[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc[m] = f32x4{};
-#pragma unroll 2
+#pragma unroll
     for (int tp = 0; tp < kTapPairs; ++tp) {
         const bf16x8 b = frag[tp * 64 + lane];
-        const int tap = min(2 * tp + (grp >> 1), 26);  // the padded tap's weights are zero
-        const int kx = tap % 3, ky = (tap / 3) % 3, kz = tap / 9;
+        const int a = abase + (second ? tap_bytes(2 * tp + 1) : tap_bytes(2 * tp));
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int mb = 4 * wave + m;  // 16-site group: z = mb / 4, y = 2 (mb % 4) + row / 8, x = row % 8
-            const int x = row & 7, y = 2 * (mb & 3) + (row >> 3), z = mb >> 2;
-            const int h = (x + kx) + kHX * ((y + ky) + kHY * (z + kz));
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&tile[h][8 * (grp & 1)]);
-            acc[m] = mfma16(a, b, acc[m]);
-        }
+        for (int m = 0; m < 4; ++m)
+            acc[m] = mfma16(*reinterpret_cast<const bf16x8 *>(lds + a + 2 * kRowB * m), b, acc[m]);
     }
+    // accumulator i of lane l: site 16 mb + 4 grp + i of the tile (mb = 4
+    // wave + m), channel co = l % 16
     const int co = lane & 15;
-    if (LAST && co >= COUT) return;
-    const float bco = co < COUT ? bias[co] : 0.0f;
+    __syncthreads();  // every wavefront is done with the tile
+    // thread t then writes site t: group mb = t / 16, r = t % 16
+    const int mb = t >> 4, r = t & 15;
+    const int x = tl.px + d.dil * (tl.x0 + (r & 7)), y = tl.py + d.dil * (tl.y0 + 2 * (mb & 3) + (r >> 3)),
+              z = tl.pz + d.dil * (tl.z0 + (mb >> 2));
+    const bool inside = x < d.Lx && y < d.Ly && z < d.Lz;
+    const int64_t p = x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z);
+    if constexpr (LAST) {
+        float(*ot)[4] = reinterpret_cast<float(*)[4]>(lds);  // ot[site][co]
+        if (co < COUT) {
+            const float bco = bias[co];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int mb = 4 * wave + m;
+            for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 4 * grp + i;  // the site of accumulator i
-            const int x = tl.px + d.dil * (tl.x0 + (r & 7)), y = tl.py + d.dil * (tl.y0 + 2 * (mb & 3) + (r >> 3)),
-                      z = tl.pz + d.dil * (tl.z0 + (mb >> 2));
-            if (x >= d.Lx || y >= d.Ly || z >= d.Lz) continue;
-            const int64_t p = x + (int64_t)d.Lx * (y + (int64_t)d.Ly * z);
-            const float zv = acc[m][i] + bco;
-            if constexpr (LAST) {
-                float *u = static_cast<float *>(out) + (int64_t)blockIdx.z * COUT * d.P;
-                u[(int64_t)co * d.P + p] = zv;
-            } else {
-                __bf16 *a = static_cast<__bf16 *>(out) + ((int64_t)blockIdx.z * d.P + p) * 16;
-                a[co] = (__bf16)silu(zv);
+                for (int i = 0; i < 4; ++i) ot[16 * (4 * wave + m) + 4 * grp + i][co] = acc[m][i] + bco;
+        }
+        __syncthreads();
+        if (inside) {
+            float *u = static_cast<float *>(out) + (int64_t)g.z * COUT * d.P + p;
+#pragma unroll
+            for (int c = 0; c < COUT; ++c) u[(int64_t)c * d.P] = ot[t][c];
+        }
+    } else {
+        // ot[site][8 channel pairs]; the two 16-byte halves of site s are
+        // swapped when bit 3 of s is set, so that the 16 lanes of a pass
+        // reading one half each fall on distinct banks.  Lanes co and co ^ 1
+        // trade one value so that each writes a channel pair of one site:
+        // the even lane sites 4 grp + i, the odd lane 4 grp + i + 1.
+        bf16x2(*ot)[8] = reinterpret_cast<bf16x2(*)[8]>(lds);
+        const float bco = bias[co];
+        const bool odd = co & 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; i += 2) {
+                const float v0 = silu_bf16(acc[m][i] + bco), v1 = silu_bf16(acc[m][i + 1] + bco);
+                const float got =
+                    __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(odd ? v0 : v1), 0xB1, 0xF, 0xF, false));
+                const int st = 16 * (4 * wave + m) + 4 * grp + i + (odd ? 1 : 0);
+                const bf16x2 pr = odd ? bf16x2{(__bf16)got, (__bf16)v1} : bf16x2{(__bf16)v0, (__bf16)got};
+                ot[st][(co >> 1) ^ (st & 8 ? 4 : 0)] = pr;
             }
+        __syncthreads();
+        if (inside) {
+            const int sw = t & 8 ? 1 : 0;
+            const bf16x8 lo = *reinterpret_cast<const bf16x8 *>(lds + 32 * t + 16 * sw);
+            const bf16x8 hi = *reinterpret_cast<const bf16x8 *>(lds + 32 * t + 16 * (1 - sw));
+            bf16x8 *dst = static_cast<bf16x8 *>(out) + ((int64_t)g.z * d.P + p) * 2;
+            dst[0] = lo;
+            dst[1] = hi;
         }
     }
 }
@@ -577,6 +656,10 @@ hipError_t net_forward_layers_mfma(NetWork &w, const float *params, const NetDim
                   d3 = layer_dims(d, dil, 3);
     const float *b0 = params + layer_off(0) + 16 * 10 * 27, *b1 = params + layer_off(1) + 16 * 16 * 27;
     const float *b2 = params + layer_off(2) + 16 * 16 * 27, *b3 = params + layer_off(3) + 3 * 16 * 27;
+    for (const NetDims *e : {&d0, &d1, &d2, &d3}) {
+        const dim3 g = conv_grid(*e, B);
+        if ((uint64_t)g.x * g.y * g.z >= ((uint64_t)1 << 31)) return hipErrorInvalidConfiguration;
+    }
     bf16x8 *f = w.frag;
     k_conv_mfma<16, false><<<conv_grid(d0, B), kNT, 0, st>>>(w.act[0], f, b0, w.act[1], d0);
     k_conv_mfma<16, false><<<conv_grid(d1, B), kNT, 0, st>>>(w.act[1], f + kTapPairs * 64, b1, w.act[0], d1);
