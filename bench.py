@@ -222,14 +222,22 @@ def gneb_workload(args):
 # useful flops of the path corrector's forward per site: four 3^3
 # convolutions 10 -> 16 -> 16 -> 16 -> 3 channels, two flops per product
 NET_FLOP_PER_SITE = 2 * 27 * (10 * 16 + 16 * 16 + 16 * 16 + 16 * 3)
+# HBM bytes per site of one BF16 forward with per-image end states: the input
+# pass reads S_g, S_A, S_B (72) and writes the BF16 activations (32); each
+# hidden layer reads and writes 32; the last reads 32 and writes u (12); the
+# head reads u and S_g (36) and writes S_hat (24).  At 97 flop per byte the
+# forward sits below the MFMA ridge (2500 / 8000 = 312 flop per byte): HBM
+# bounds it.
+NET_BYTES_PER_SITE = 104 + 3 * 64 + 44 + 60
 
 
 def net_forward_roofline(L=(64, 64, 64), batch=16, reps=10):
     """The path corrector's forward (dilation 1, 2, 4, 8) on a batch of
     64^3 images with random parameters and states, FP32 on the vector ALUs and
-    BF16 implicit GEMMs on the matrix cores, against the dense BF16 MFMA
-    peak (useful flops: the padding of channels to 16 and of the 27 taps to
-    28 is not counted)."""
+    BF16 implicit GEMMs on the matrix cores.  The BF16 form's roofline is
+    HBM's (its bytes per site above); its rate of useful flops (the padding
+    of channels to 16 and of the 27 taps to 28 not counted) is also given
+    against the dense BF16 MFMA peak."""
     import torch
 
     from paper_2605_26016_amd import pathinit, spx
@@ -261,11 +269,14 @@ def net_forward_roofline(L=(64, 64, 64), batch=16, reps=10):
         res[prec + "_ms"] = ms
         res[prec + "_TFLOPs"] = batch * N * NET_FLOP_PER_SITE / ms / 1e9
         del net
-    res["roofline"] = {"bound": "mfma", "achieved": round(res["bf16_TFLOPs"], 2), "peak": MFMA_BF16_PEAK_TFLOPS,
-                       "unit": "TFLOP/s", "frac": round(res["bf16_TFLOPs"] / MFMA_BF16_PEAK_TFLOPS, 4),
-                       "traffic": None, "kernel": "k_conv_mfma (BF16 network forward)"}
+    gbs = batch * N * NET_BYTES_PER_SITE / res["bf16_ms"] / 1e6
+    res["mfma_frac"] = round(res["bf16_TFLOPs"] / MFMA_BF16_PEAK_TFLOPS, 4)
+    traffic = measured_traffic("net_forward_bf16", f"net_forward_{L[0]}x{L[1]}x{L[2]}_x{batch}", None, None)
+    res["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "bytes_per_site": NET_BYTES_PER_SITE,
+                       "kernel": "BF16 network forward (k_net_input_bf16, 4 x k_conv_mfma, k_net_head)"}
     log(f"[bench] network forward 64^3 x {batch}: FP32 {res['fp32_ms']:.3f} ms, BF16 MFMA {res['bf16_ms']:.3f} ms "
-        f"({res['bf16_TFLOPs']:.1f} TFLOP/s)")
+        f"({res['bf16_TFLOPs']:.1f} TFLOP/s, {gbs:.0f} GB/s)")
     return res
 
 
