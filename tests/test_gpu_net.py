@@ -185,7 +185,9 @@ def test_mfma16_lane_layout_probe():
     np.testing.assert_array_equal(D.cpu().numpy(), A @ B)
 
 
-@pytest.mark.parametrize("L,dil", [((19, 13, 11), (1, 1, 1, 1)), ((21, 17, 10), (1, 2, 4, 8))], ids=["d1", "d1248"])
+@pytest.mark.parametrize("L,dil", [((19, 13, 11), (1, 1, 1, 1)), ((21, 17, 10), (1, 2, 4, 8)),
+                                   ((5, 3, 2), (1, 2, 4, 8)), ((1, 1, 9), (1, 3, 1, 2))],
+                         ids=["d1", "d1248", "tiny_d1248", "line_d1312"])
 def test_net_bf16_forward_matches_emulated_oracle(L, dil):
     # the BF16 implicit-GEMM form against the oracle with every layer's
     # weights and inputs rounded as the kernel rounds them (FP32, then BF16)
