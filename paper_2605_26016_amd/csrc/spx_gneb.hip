@@ -675,6 +675,12 @@ struct spx_gneb {
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;  // library-owned capture stream (the caller's may be the null stream)
     int use_graph = 1;
+    // Parallel branches of the captured iteration: one stream per instance,
+    // a fork event and per-instance join events for each of the two passes.
+    std::vector<hipStream_t> side;
+    hipEvent_t fork_ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> join_ev[2];
+    bool branch = false;  // set while an iteration is being captured with branches
     std::vector<ZPlan> zplan;  // per instance: FP64 z-march plan (used when its Bbil or zt_per_img is set)
     std::vector<Onsite> hos;   // per instance: host copy of the on-site tables (fused first pass)
 };
@@ -696,6 +702,16 @@ void gneb_free(spx_gneb *g) {
     g->graph = nullptr;
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     g->cap_stream = nullptr;
+    for (hipStream_t s : g->side)
+        if (s) (void)hipStreamDestroy(s);
+    g->side.clear();
+    for (int p = 0; p < 2; ++p) {
+        if (g->fork_ev[p]) (void)hipEventDestroy(g->fork_ev[p]);
+        g->fork_ev[p] = nullptr;
+        for (hipEvent_t e : g->join_ev[p])
+            if (e) (void)hipEventDestroy(e);
+        g->join_ev[p].clear();
+    }
     for (void *p : g->owned) (void)hipFree(p);
     g->owned.clear();
 }
@@ -737,19 +753,44 @@ hipError_t enqueue_reparam(spx_gneb *g, int gate, hipStream_t st) {
 // Enqueue one GNEB iteration (all instances) on stream st.
 GnebPassArgs pass_args(const spx_gneb *g, int k);
 
+// Enqueue one z-march pass of every instance that has one: in turn on st,
+// or, while g->branch is set (capture), each instance on its own stream
+// between a fork from st and a join back into it, so that the graph runs
+// the instances' passes side by side and the small lattices' blocks fill
+// the chip beside the large one's.  The instances share no buffer.
+constexpr int kMaxBranches = 8;
+template <typename F>
+hipError_t per_instance(spx_gneb *g, int pass, hipStream_t st, F launch) {
+    if (!g->branch) {
+        for (int k = 0; k < g->n_inst; ++k) {
+            const hipError_t e = launch(k, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t e = hipEventRecord(g->fork_ev[pass], st);
+    for (int k = 0; k < g->n_inst && e == hipSuccess; ++k) {
+        e = hipStreamWaitEvent(g->side[k], g->fork_ev[pass], 0);
+        if (e == hipSuccess) e = launch(k, g->side[k]);
+        if (e == hipSuccess) e = hipEventRecord(g->join_ev[pass][k], g->side[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, g->join_ev[pass][k], 0);
+    }
+    return e;
+}
+
 hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
     const unsigned gi = grid_for(g->n_items);
     bool any_items = false;  // an instance that runs the item passes
-    for (int k = 0; k < g->n_inst; ++k) {
+    for (const GInst &G : g->hinst) any_items = any_items || G.zt_per_img == 0;
+    hipError_t e0 = per_instance(g, 0, st, [&](int k, hipStream_t s) {
         const GInst &G = g->hinst[k];
-        hipError_t e = hipSuccess;
-        if (G.zt_per_img > 0) e = zmarch_gneb_pass(0, g->zplan[k], G.g, g->hos[k], pass_args(g, k), st);
-        else if (G.Bbil)
-            e = zmarch_bil_images(g->zplan[k], G.g, G.n_img, G.Y[0], G.Y[1], G.st + ST_CUR, G.st + ST_DONE,
-                                  (double *)G.Bbil, st);
-        if (e != hipSuccess) return e;
-        any_items = any_items || G.zt_per_img == 0;
-    }
+        if (G.zt_per_img > 0) return zmarch_gneb_pass(0, g->zplan[k], G.g, g->hos[k], pass_args(g, k), s);
+        if (G.Bbil)
+            return zmarch_bil_images(g->zplan[k], G.g, G.n_img, G.Y[0], G.Y[1], G.st + ST_CUR, G.st + ST_DONE,
+                                     (double *)G.Bbil, s);
+        return hipSuccess;
+    });
+    if (e0 != hipSuccess) return e0;
     if (any_items) k_gneb_a<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
     k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 2, kPassA2Values, IS_E, 0, GATE_ITER,
                                              0, 0);
@@ -760,12 +801,12 @@ hipError_t enqueue_iteration(spx_gneb *g, hipStream_t st) {
     }
     k_gneb_scalars2<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
     if (any_items) k_gneb_c<<<gi, kGB, 0, st>>>(g->d_inst, g->d_items, g->n_items, g->d_partial);
-    for (int k = 0; k < g->n_inst; ++k) {
+    hipError_t e1 = per_instance(g, 1, st, [&](int k, hipStream_t s) {
         const GInst &G = g->hinst[k];
-        if (G.zt_per_img == 0) continue;
-        hipError_t e = zmarch_gneb_pass(1, g->zplan[k], G.g, g->hos[k], pass_args(g, k), st);
-        if (e != hipSuccess) return e;
-    }
+        if (G.zt_per_img == 0) return hipSuccess;
+        return zmarch_gneb_pass(1, g->zplan[k], G.g, g->hos[k], pass_args(g, k), s);
+    });
+    if (e1 != hipSuccess) return e1;
     k_gneb_reduce<<<g->n_imgs, kGB, 0, st>>>(g->d_inst, g->d_imgs, g->d_partial, 1, 1, IS_FM, 1, GATE_ITER, 1, 0);
     k_gneb_finish<<<g->n_inst, kGB, 0, st>>>(g->d_inst);
     bool any_string = false;
@@ -979,10 +1020,26 @@ spx_status spx_gneb_step(spx_gneb *g, int32_t n_iter, void *stream) {
         // launched on whatever stream the caller passes.  Capture failure
         // (graphs unsupported) leaves direct launches in place.
         if (!g->cap_stream) e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+        // with two to kMaxBranches instances, their passes become parallel
+        // branches (streams and events of default priority, made once)
+        const bool branches = g->n_inst > 1 && g->n_inst <= kMaxBranches;
+        if (e == hipSuccess && branches && g->side.empty()) {
+            g->side.assign(g->n_inst, nullptr);
+            for (int p = 0; p < 2; ++p) g->join_ev[p].assign(g->n_inst, nullptr);
+            for (int k = 0; k < g->n_inst && e == hipSuccess; ++k) {
+                e = hipStreamCreateWithFlags(&g->side[k], hipStreamNonBlocking);
+                for (int p = 0; p < 2 && e == hipSuccess; ++p)
+                    e = hipEventCreateWithFlags(&g->join_ev[p][k], hipEventDisableTiming);
+            }
+            for (int p = 0; p < 2 && e == hipSuccess; ++p)
+                e = hipEventCreateWithFlags(&g->fork_ev[p], hipEventDisableTiming);
+        }
         hipGraph_t graph;
         if (e == hipSuccess) e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
+            g->branch = branches;
             hipError_t e2 = enqueue_iteration(g, g->cap_stream);
+            g->branch = false;
             e = hipStreamEndCapture(g->cap_stream, &graph);
             if (e == hipSuccess) e = e2;
             if (e == hipSuccess) {
