@@ -101,6 +101,33 @@ def test_gneb_graph_replay_equals_single_steps():
     assert spx.gneb_get_stats(ga)["iterations"] == 9
 
 
+def test_gneb_graph_branches_equal_single_steps():
+    # several instances: the captured iteration runs their passes on
+    # parallel branches; replaying it must give the direct launches' images
+    # bit for bit
+    import torch
+    from paper_2605_26016_amd import spx
+    cases = [(frustrated((4, 4, 4)), 5, 21), (frustrated((5, 4, 3), periodic=(1, 0, 1)), 7, 22),
+             (frustrated((6, 6, 2), K=0.2), 4, 23), (frustrated((8, 8, 8)), 6, 24)]
+    ga_bufs, gb_bufs, hams_a, hams_b = [], [], [], []
+    for w, n_img, seed in cases:
+        A, B = endpoints(w, seed)
+        Y0 = oracle.geodesic_path(A, B, n_img)
+        ga_bufs.append(to_dev(Y0))
+        gb_bufs.append(to_dev(Y0))
+        hams_a.append(gpu_hamiltonian(w))
+        hams_b.append(gpu_hamiltonian(w))
+    ga = spx.gneb_create(hams_a, ga_bufs, ci_mode=1, ci_on_below=3.0)
+    gb = spx.gneb_create(hams_b, gb_bufs, ci_mode=1, ci_on_below=3.0)
+    spx.gneb_step(ga, 12)                 # captured once, replayed
+    for _ in range(12):
+        spx.gneb_step(gb, 1)              # direct launches, one instance after another
+    torch.cuda.synchronize()
+    for k in range(len(cases)):
+        assert torch.equal(ga_bufs[k], gb_bufs[k]), k
+        assert spx.gneb_get_stats(ga, k)["iterations"] == 12
+
+
 def test_gneb_batched_ragged_instances_match_oracle():
     import torch
     from paper_2605_26016_amd import spx
