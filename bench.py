@@ -442,8 +442,9 @@ def pairlist_workload(args):
             log(f"[bench] {backend} {prec}: field {N / (ms_f / 1e3):.3e}/s, Heun {N / (ms_h / 1e3):.3e} spin-steps/s")
             del h, b, S
     head = table["pairlist_fp32"]
-    # pair-list field contract bytes per site: own spin 24 B, 6 sources (4 B
-    # index + 4 B FP32 coupling), row pointer 8 B, FP32 field out 12 B
+    # pair-list field contract bytes per site: the spin array read once 24 B
+    # (each spin as some site's source), 6 sources (4 B index + 4 B FP32
+    # coupling), row pointer 8 B, FP32 field out 12 B
     pl_bytes = 24 + 6 * 8 + 8 + 12
     out = {"metric": "spin updates/s (field+Heun), pair-list backend, sc 200^3 nearest neighbours",
            "value": head["spin_steps_per_s"], "unit": "spin-steps/s", "n_gpus": 1, "steps": n, "warmup": 1,

@@ -119,7 +119,9 @@ __global__ __launch_bounds__(kPlB) void k_pl_field(PlView v, const double *__res
     for (int64_t i = (int64_t)blockIdx.x * kPlB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kPlB) {
         double bl[3], on[3];
         pl_bil<AccT, TENSOR>(v, S, i, bl);
-        const double s[3] = {S[i], S[N + i], S[2 * N + i]};
+        double s[3] = {0.0, 0.0, 0.0};  // the site's own spin: read only for the anisotropy
+        if (v.has_K)
+            for (int c = 0; c < 3; ++c) s[c] = S[c * N + i];
         pl_onsite(v, i, s, on);
         for (int c = 0; c < 3; ++c) b[c * N + i] = (OutT)(bl[c] + on[c]);
     }
