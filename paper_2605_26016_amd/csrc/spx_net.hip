@@ -441,8 +441,8 @@ __global__ __launch_bounds__(kNT) void k_conv_mfma(const bf16x8 *__restrict__ in
     const int lane = t & 63, wave = t >> 6, row = lane & 15, grp = lane >> 4;
     // lane's A operand: site (x, y, z) = (row % 8, row / 8 + 2 m, wave) of
     // group m, channels 8 (grp % 2) .. + 7; lanes 32..63 take the pair's
-    // second tap
-    // the lane's address for each kx: x row, y row, z plane, swizzled half
+    // second tap.  abx[kx]: the byte address of that half at tap offset kx
+    // in x (the y and z offsets of a tap add to it)
     int abx[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
