@@ -342,14 +342,15 @@ __global__ __launch_bounds__(kMcB) void k_mc_from_cm(const double *__restrict__ 
 // One colour of one sweep on the padded colour-major copy P: the natural
 // kernel's site loop, draw and update, every neighbour at the tabulated
 // offset of its bond and class, and the new spin also written to the
-// site's ghost copies.
-// (four waves per SIMD asked of the register allocator: the heat-bath
-// instantiations otherwise take a few registers more than 128)
+// site's ghost copies.  The register allocator is left free: asking it for
+// four waves per SIMD (at most 128 registers) kept the count of resident
+// waves where it was but made the code slower, Metropolis with 2-5 shells
+// by a third (sc 200^3).
 template <bool ISO, int METHOD, int UNR>
-__global__ __launch_bounds__(kMcB) __attribute__((amdgpu_waves_per_eu(4)))
-void k_mc_colour_cm(double *__restrict__ P, BondTable tb, Grid g, Onsite os, McColour col, int c, double beta,
-                    uint64_t seed, uint64_t sweep, unsigned long long *__restrict__ acc,
-                    const int64_t *__restrict__ coff, CmDims d) {
+__global__ __launch_bounds__(kMcB) void k_mc_colour_cm(double *__restrict__ P, BondTable tb, Grid g, Onsite os,
+                                                      McColour col, int c, double beta, uint64_t seed,
+                                                      uint64_t sweep, unsigned long long *__restrict__ acc,
+                                                      const int64_t *__restrict__ coff, CmDims d) {
     const int C = col.C;
     const int J = d.J;
     const int64_t total = d.n_rows * J;
