@@ -315,20 +315,23 @@ spx_status spx_get_bonds(spx_ham *h, int32_t *bond_ab, int32_t *bond_delta, doub
  *     2 pi u1), dH = -(S' - S_i).b_i - sum_l K_l [(S'.n_l)^2 - (S_i.n_l)^2],
  *     accepted if u2 < exp(-beta dH).
  * SPX_ERR_UNSUPPORTED with the dipolar term or when no colouring with C <= 64
- * is found (see spx_mc_find_colouring for the search's limits); SPX_ERR_INVALID_ARG for T <= 0, n_sweeps < 0 or another method.
+ * is found (see spx_mc_find_colouring for the search's limits); SPX_ERR_INVALID_ARG for T <= 0, n_sweeps < 0, another method or layout.
  * `accepted` ([dev] uint64 or NULL) receives the number of accepted moves of
  * the call (heat-bath: every draw).  Asynchronous.  A call of two sweeps or
- * more copies S into a colour-major layout held by the handle (allocated on
- * the first such call, about 3 N doubles plus ghost slots and rows, freed
- * with the Hamiltonian; if it cannot be allocated the sweeps run in place),
- * runs every sweep there and copies the result back; the moves and results
- * are the same bit for bit.  Overlapping calls on one handle race. */
+ * more, or of a colouring with more than two colours, copies S into a
+ * colour-major layout held by the handle (allocated on the first such call,
+ * about 3 N doubles plus ghost slots and rows, freed with the Hamiltonian;
+ * if it cannot be allocated the sweeps run in place), runs every sweep there
+ * and copies the result back; the moves and results are the same bit for
+ * bit (layout = 1 keeps every call in place).  Overlapping calls on one
+ * handle race. */
 typedef struct {
     double temperature_K;
     uint64_t seed;
     uint64_t sweep0;     /* counter of the first sweep */
     int32_t n_sweeps;
     int32_t method;      /* 0 heat-bath, 1 Metropolis */
+    int32_t layout;      /* 0: the library chooses (above); 1: in place, never the colour-major copy */
 } spx_mc_params;
 spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned long long *accepted, void *stream);
 /* The colouring used by spx_mc_sweep (searched on first use, synchronous):

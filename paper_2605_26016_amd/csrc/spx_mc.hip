@@ -802,6 +802,7 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
     if (!(p->temperature_K > 0.0)) return set_error(SPX_ERR_INVALID_ARG, "temperature must be > 0");
     if (p->n_sweeps < 0) return set_error(SPX_ERR_INVALID_ARG, "n_sweeps < 0");
     if (p->method != 0 && p->method != 1) return set_error(SPX_ERR_INVALID_ARG, "method must be 0 or 1");
+    if (p->layout != 0 && p->layout != 1) return set_error(SPX_ERR_INVALID_ARG, "layout must be 0 or 1");
     if (v.dip) return set_error(SPX_ERR_UNSUPPORTED, "Monte Carlo with the dipolar term is not supported");
     if (p->method == 0 && v.onsite.n_aniso > 0)
         return set_error(SPX_ERR_UNSUPPORTED, "heat-bath needs a local energy linear in the spin (no anisotropy)");
@@ -822,18 +823,20 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kMcB - 1) / kMcB, 65536));
     const bool iso = v.tab.iso != 0;
     const int3 rad = make_int3(m->rad[0], m->rad[1], m->rad[2]);
-    // heat-bath with at most 8 bonds per site (one sc shell) runs its
-    // neighbour loop two-deep: the FP64 draw then keeps more waves resident
-    // (21.3 against 18.9e9 updates/s at sc 200^3); longer lists and
+    // in place, heat-bath with at most 8 bonds per site (one sc shell) runs
+    // its neighbour loop two-deep: the FP64 draw then keeps more waves
+    // resident (21.3 against 18.9e9 updates/s at sc 200^3); longer lists and
     // Metropolis are faster four-deep
     int max_bonds = 0;
     for (int a = 0; a < v.grid.n_sub; ++a) max_bonds = std::max(max_bonds, v.tab.start[a + 1] - v.tab.start[a]);
     const bool short_list = max_bonds <= 8;
-    // calls of two sweeps or more run on the colour-major copy (two copies
-    // of the state per call against line-granular traffic of the whole
-    // lattice in every launch)
+    // The colour-major copy costs two copies of the state per call; in place,
+    // every colour launch moves the whole lattice's cache lines.  A single
+    // sweep of two colours runs faster in place (sc 200^3 one shell: 280
+    // against 403 us); two sweeps or more colours run on the copy (five
+    // shells, 20 colours, one sweep: 1.96 against 15.0 ms).
     CmDims cd{};
-    const bool cm = p->n_sweeps >= 2 && mc_cm_buffer(v.grid, m, cd);
+    const bool cm = p->layout == 0 && (p->n_sweeps >= 2 || col.C > 2) && mc_cm_buffer(v.grid, m, cd);
     const unsigned pgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cd.NP + kMcB - 1) / kMcB, 65536));
     const unsigned ngrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((v.grid.N + kMcB - 1) / kMcB, 65536));
     if (cm) k_mc_to_cm<<<pgrid, kMcB, 0, st>>>(S, m->d_cm, v.grid, cd);

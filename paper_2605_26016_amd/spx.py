@@ -63,7 +63,7 @@ class GnebParams(C.Structure):
 
 class McParams(C.Structure):
     _fields_ = [("temperature_K", C.c_double), ("seed", C.c_uint64), ("sweep0", C.c_uint64),
-                ("n_sweeps", C.c_int32), ("method", C.c_int32)]
+                ("n_sweeps", C.c_int32), ("method", C.c_int32), ("layout", C.c_int32)]
 
 
 class MinParams(C.Structure):
@@ -534,11 +534,13 @@ def min_reset(m, stream=None):
 MC_METHODS = {"heat_bath": 0, "metropolis": 1}
 
 
-def mc_sweep(h, S, temperature_K, seed, sweep0=0, n_sweeps=1, method="heat_bath", accepted=None, stream=None):
+def mc_sweep(h, S, temperature_K, seed, sweep0=0, n_sweeps=1, method="heat_bath", accepted=None, stream=None,
+             in_place=False):
     """n_sweeps heat-bath or Metropolis sweeps of the device state S in place;
-    `accepted` (device uint64 tensor of 1, optional) receives the accepted moves."""
+    `accepted` (device uint64 tensor of 1, optional) receives the accepted moves;
+    in_place keeps the sweeps in the natural layout (no colour-major copy)."""
     m = MC_METHODS[method] if isinstance(method, str) else int(method)
-    p = McParams(float(temperature_K), int(seed), int(sweep0), int(n_sweeps), m)
+    p = McParams(float(temperature_K), int(seed), int(sweep0), int(n_sweeps), m, 1 if in_place else 0)
     _check(load().spx_mc_sweep(_h(h), _ptr(S), C.byref(p), _ptr(accepted), _stream(stream)), "spx_mc_sweep")
 
 

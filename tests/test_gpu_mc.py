@@ -96,26 +96,34 @@ def test_sweeps_match_the_oracle(name, method, T):
                                            ("sc_nn_128x96x64", 0, 60.0), ("sc_nn_128x96x64", 1, 60.0),
                                            ("sc4shell_6x6x1", 0, 30.0), ("sc3shell_open", 1, 30.0)])
 def test_colour_major_sweeps_equal_natural_layout_sweeps(name, method, T):
-    # a call of several sweeps runs on the colour-major copy of the state, a
-    # call of one sweep in the natural layout: the same sweeps either way
-    # give the same bits and the same accepted-move count
+    # a call of several sweeps runs on the colour-major copy of the state;
+    # calls of one sweep kept in the natural layout (in_place), and one call
+    # of three sweeps in place, give the same bits and accepted-move count;
+    # so do calls of one sweep in the layout the library chooses
     import torch
     from paper_2605_26016_amd import spx
     w = CASES[name]
     S0 = random_sphere(w.N, 41)
     h = gpu_hamiltonian(w, field_prec="fp64")
-    Sa, Sb = to_dev(S0), to_dev(S0)
+    Sa, Sb, Sc, Sd = to_dev(S0), to_dev(S0), to_dev(S0), to_dev(S0)
     acc = torch.zeros(1, dtype=torch.uint64, device="cuda")
     spx.mc_sweep(h, Sa, T, seed=3, sweep0=10, n_sweeps=3, method=method, accepted=acc)
     torch.cuda.synchronize()
     n_a = int(acc.cpu().item())
-    n_b = 0
+    n_b = n_d = 0
     for k in range(3):
-        spx.mc_sweep(h, Sb, T, seed=3, sweep0=10 + k, n_sweeps=1, method=method, accepted=acc)
+        spx.mc_sweep(h, Sb, T, seed=3, sweep0=10 + k, n_sweeps=1, method=method, accepted=acc, in_place=True)
         torch.cuda.synchronize()
         n_b += int(acc.cpu().item())
-    assert torch.equal(Sa, Sb), float((Sa - Sb).abs().max())
-    assert n_a == n_b
+        spx.mc_sweep(h, Sd, T, seed=3, sweep0=10 + k, n_sweeps=1, method=method, accepted=acc)
+        torch.cuda.synchronize()
+        n_d += int(acc.cpu().item())
+    spx.mc_sweep(h, Sc, T, seed=3, sweep0=10, n_sweeps=3, method=method, accepted=acc, in_place=True)
+    torch.cuda.synchronize()
+    n_c = int(acc.cpu().item())
+    for X in (Sb, Sc, Sd):
+        assert torch.equal(Sa, X), float((Sa - X).abs().max())
+    assert n_a == n_b == n_c == n_d
 
 
 def test_metropolis_with_anisotropy_matches_the_oracle():
