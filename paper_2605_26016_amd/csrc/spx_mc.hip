@@ -836,7 +836,8 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
     // against 403 us); two sweeps or more colours run on the copy (five
     // shells, 20 colours, one sweep: 1.96 against 15.0 ms).
     CmDims cd{};
-    const bool cm = p->layout == 0 && (p->n_sweeps >= 2 || col.C > 2) && mc_cm_buffer(v.grid, m, cd);
+    const bool cm = p->layout == 0 && (p->n_sweeps >= 2 || (p->n_sweeps == 1 && col.C > 2)) &&
+                    mc_cm_buffer(v.grid, m, cd);
     const unsigned pgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cd.NP + kMcB - 1) / kMcB, 65536));
     const unsigned ngrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((v.grid.N + kMcB - 1) / kMcB, 65536));
     if (cm) k_mc_to_cm<<<pgrid, kMcB, 0, st>>>(S, m->d_cm, v.grid, cd);
