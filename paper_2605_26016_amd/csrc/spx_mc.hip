@@ -823,10 +823,10 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kMcB - 1) / kMcB, 65536));
     const bool iso = v.tab.iso != 0;
     const int3 rad = make_int3(m->rad[0], m->rad[1], m->rad[2]);
-    // in place, heat-bath with at most 8 bonds per site (one sc shell) runs
-    // its neighbour loop two-deep: the FP64 draw then keeps more waves
-    // resident (21.3 against 18.9e9 updates/s at sc 200^3); longer lists and
-    // Metropolis are faster four-deep
+    // in place, heat-bath runs its neighbour loop two-deep (the FP64 draw
+    // then keeps more waves resident: sc 200^3 one shell 21.3 against
+    // 18.9e9 updates/s; one sweep with two shells 0.87 against 1.01 ms, with
+    // five 11.4 against 15.1 ms); Metropolis is faster four-deep
     int max_bonds = 0;
     for (int a = 0; a < v.grid.n_sub; ++a) max_bonds = std::max(max_bonds, v.tab.start[a + 1] - v.tab.start[a]);
     const bool short_list = max_bonds <= 8;
@@ -861,8 +861,7 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
                 continue;
             }
             if (p->method == 0) {
-                if (iso && short_list) k_mc_colour<true, 0, 2><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
-                else if (iso) k_mc_colour<true, 0, 4><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
+                if (iso) k_mc_colour<true, 0, 2><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
                 else k_mc_colour<false, 0, 4><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
             } else {
                 if (iso) k_mc_colour<true, 1, 4><<<grid, kMcB, 0, st>>>(S, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, m->d_off, rad);
