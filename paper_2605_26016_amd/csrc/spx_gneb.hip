@@ -131,7 +131,8 @@ __device__ __forceinline__ double angle3(const double a[3], const double b[3]) {
     const double c0 = a[1] * b[2] - a[2] * b[1];
     const double c1 = a[2] * b[0] - a[0] * b[2];
     const double c2 = a[0] * b[1] - a[1] * b[0];
-    return atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+    const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+    return atan2_nonneg(cc > 0.0 ? sqrt_pos(cc) : 0.0, a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
 }
 
 // Point at fraction t of the great-circle arc from a to b (unit vectors):
@@ -142,9 +143,9 @@ __device__ __forceinline__ double angle3(const double a[3], const double b[3]) {
 __device__ __forceinline__ void geodesic_point(const double a[3], const double b[3], double t, double p[3]) {
     const double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
     double w[3] = {b[0] - dot * a[0], b[1] - dot * a[1], b[2] - dot * a[2]};
-    const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    const double wn2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
     double e[3], ang;
-    if (wn < 1e-10) {
+    if (wn2 < 1e-20) {  // |w| below 1e-10
         if (dot > 0) {
             for (int q = 0; q < 3; ++q) p[q] = a[q];
             return;
@@ -163,10 +164,12 @@ __device__ __forceinline__ void geodesic_point(const double a[3], const double b
         e[2] = ax[0] * a[1] - ax[1] * a[0];
         ang = M_PI;
     } else {
-        for (int q = 0; q < 3; ++q) e[q] = w[q] / wn;
-        ang = atan2(wn, dot);
+        const double rn = rsqrt_pos(wn2);
+        for (int q = 0; q < 3; ++q) e[q] = w[q] * rn;
+        ang = atan2_nonneg(wn2 * rn, dot);
     }
-    const double cs = cos(t * ang), sn = sin(t * ang);
+    double cs, sn;  // of t ang, as sin and cos of pi (t ang / pi)
+    sincospi_d(t * ang * (1.0 / M_PI), sn, cs);
     for (int q = 0; q < 3; ++q) p[q] = cs * a[q] + sn * e[q];
     normalise3(p);
 }
