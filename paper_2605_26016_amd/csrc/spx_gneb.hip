@@ -248,6 +248,25 @@ __device__ __forceinline__ bool gate_open(const GInst &G, int gate) {
     return G.st[ST_DONE] == 0.0;
 }
 
+// Work index w -> item, images fastest: within each instance (whose items
+// are stored image-major) the n_img items of one site block follow each
+// other, and blocks take their work in XCD-contiguous ranges, so the
+// neighbouring image that an item reads besides its own was mostly just read
+// by the item before it, on the same XCD, and comes from its L2.  The
+// instance of w is that of item w: both orders cover the same range per
+// instance.
+__device__ __forceinline__ int image_fastest_item(const GInst *__restrict__ inst, const GItem *__restrict__ items,
+                                                  int w) {
+    const GInst &G = inst[items[w].inst];
+    const int local = w - G.item0, tile = local / G.n_img, img = local - tile * G.n_img;
+    return G.item0 + img * G.items_per_img + tile;
+}
+__device__ __forceinline__ int xcd_block_index() {
+    const int T = (int)gridDim.x, b = (int)blockIdx.x;
+    const int q = T / 8, r = T % 8, k = b % 8;
+    return k * q + (k < r ? k : r) + b / 8;
+}
+
 // nv_items / nv_tiles: partial values per item of the item passes / per tile
 // of the two-pass instances (0: this reduction does not apply to them);
 // items_only: the pass reduced was an item pass for every instance.
@@ -551,7 +570,8 @@ __global__ __launch_bounds__(kGB) void k_gneb_geodesic(const GInst *__restrict__
 __global__ __launch_bounds__(kGB) void k_gneb_rdist(const GInst *__restrict__ inst, const GItem *__restrict__ items,
                                                     int n_items, double *__restrict__ partial, int gate) {
     __shared__ double red[kGB / 64];
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    for (int w = xcd_block_index(); w < n_items; w += gridDim.x) {
+        const int it = image_fastest_item(inst, items, w);
         const GItem itm = items[it];
         const GInst &G = inst[itm.inst];
         double d2 = 0.0;
@@ -608,8 +628,8 @@ __global__ __launch_bounds__(kGB) void k_gneb_rscalars(const GInst *__restrict__
 // them (they stay zero from set-up or the last parameter change).
 __global__ __launch_bounds__(kGB) void k_gneb_reparam(const GInst *__restrict__ inst, const GItem *__restrict__ items,
                                                       int n_items, int gate) {
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const GItem itm = items[it];
+    for (int w = xcd_block_index(); w < n_items; w += gridDim.x) {
+        const GItem itm = items[image_fastest_item(inst, items, w)];
         const GInst &G = inst[itm.inst];
         if (!gate_open(G, gate)) continue;
         const int64_t N = G.g.N;
