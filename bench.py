@@ -207,7 +207,7 @@ def gneb_workload(args):
     log(f"[bench] string method: {rate_s:.3e} spin-image-iterations/s ({ms_s / n_it:.2f} ms per iteration)")
     out["config"] = {"workload": "sc_frustrated_gneb", "lattices": [list((L, L, L)) for L in sizes], "images": 32,
                      "spin_images": spin_images, "shells_throughput": [1.0, -0.164, -0.082],
-                     "parallelism": "single GPU, ragged batch in one launch per pass"}
+                     "parallelism": "single GPU, ragged batch: one launch per instance and pass, the instances on parallel graph branches"}
     del g, hams, imgs
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_gneb_baseline(args.cpu_seconds)
     out["hbm_copy_GBps"] = copy_bandwidth()
