@@ -328,7 +328,8 @@ def mc_workload(args):
            "config": {"workload": "sc200_mc", "cells": [L, L, L], "spins": N, "T_K": T, "B_T": [0.0, 0.0, 1.0],
                       "shells": [list(J) for J in MC_SHELLS], "parallelism": "single GPU"},
            "roofline": {"bound": "hbm", "achieved": rate * MC_BYTES / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": rate * MC_BYTES / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "frac": rate * MC_BYTES / 1e9 / HBM_PEAK_GBS,
+                        "traffic": measured_traffic("mc_heat_bath_1shell", "sc200_mc", None, None),
                         "kernel": "k_mc_colour_cm (heat-bath, one shell, 2 colours)",
                         "bytes_per_update_algorithmic": MC_BYTES},
            "table": table}
@@ -454,7 +455,8 @@ def pairlist_workload(args):
                       "parallelism": "single GPU"},
            "roofline": {"bound": "hbm", "achieved": head["fields_per_s"] * pl_bytes / 1e9, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": head["fields_per_s"] * pl_bytes / 1e9 / HBM_PEAK_GBS,
-                        "traffic": None, "kernel": "k_pl_field<float> (pair-list FP32 field)",
+                        "traffic": measured_traffic("pl_field_fp32", "sc200_pairlist", None, None),
+                        "kernel": "k_pl_field<float> (pair-list FP32 field)",
                         "bytes_per_site_algorithmic": pl_bytes},
            "table": table, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
@@ -804,7 +806,8 @@ def field_workload(args, w):
     mf = dense["bf16"]
     roof = {"bound": "mfma", "achieved": round(mf["TFLOPs_algorithmic"], 2), "peak": MFMA_BF16_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(mf["TFLOPs_algorithmic"] / MFMA_BF16_PEAK_TFLOPS, 4),
-            "traffic": None, "kernel": "k_dense_mfma (BF16)",
+            "traffic": measured_traffic("dense_mfma_bf16", "sc256_chiral_dipolar_field", None, None),
+            "kernel": "k_dense_mfma (BF16)",
             "flop_per_site_algorithmic": DENSE_FLOP_PER_SITE}
     cpu = None
     if not args.no_cpu_baseline:

@@ -70,6 +70,16 @@ PlView view(const PairList *p) {
     return v;
 }
 
+// Workgroups are dealt to the 8 XCDs in turn; this renumbering gives each
+// XCD one contiguous range of the grid's blocks, so that the sites a block
+// gathers from the rows next to its own were mostly fetched into the same L2
+// by the blocks beside it.
+__device__ __forceinline__ int64_t xcd_site_block() {
+    const int64_t T = gridDim.x, b = blockIdx.x;
+    const int64_t q = T / 8, r = T % 8, k = b % 8;
+    return k * q + (k < r ? k : r) + b / 8;
+}
+
 // bilinear field of site i (AccT precision), result in FP64
 template <typename AccT, bool TENSOR>
 __device__ __forceinline__ void pl_bil(const PlView &v, const double *__restrict__ S, int64_t i, double out[3]) {
@@ -119,7 +129,7 @@ __device__ __forceinline__ void pl_onsite(const PlView &v, int64_t i, const doub
 template <typename AccT, typename OutT, bool TENSOR>
 __global__ __launch_bounds__(kPlB) void k_pl_field(PlView v, const double *__restrict__ S, OutT *__restrict__ b) {
     const int64_t N = v.N;
-    for (int64_t i = (int64_t)blockIdx.x * kPlB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kPlB) {
+    for (int64_t i = xcd_site_block() * kPlB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kPlB) {
         double bl[3], on[3];
         pl_bil<AccT, TENSOR>(v, S, i, bl);
         double s[3] = {0.0, 0.0, 0.0};  // the site's own spin: read only for the anisotropy
@@ -142,7 +152,7 @@ template <typename AccT, bool TENSOR, int STAGE>
 __global__ __launch_bounds__(kPlB) void k_pl_heun(PlView v, PlHeun hc, double *__restrict__ S,
                                                   double *__restrict__ St, double *__restrict__ f0) {
     const int64_t N = v.N;
-    for (int64_t i = (int64_t)blockIdx.x * kPlB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kPlB) {
+    for (int64_t i = xcd_site_block() * kPlB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kPlB) {
         const double *X = STAGE == 0 ? S : St;
         double x[3] = {X[i], X[N + i], X[2 * N + i]};
         double bl[3], on[3], B[3];
