@@ -386,7 +386,8 @@ def min_workload(args):
            "config": {"workload": "sc200_min", "cells": [L, L, L], "spins": N, "K_meV": 0.1, "B_T": [0.0, 0.0, 1.0],
                       "shells": [list(J) for J in MC_SHELLS], "parallelism": "single GPU"},
            "roofline": {"bound": "hbm", "achieved": rate * MIN_BYTES["vp"] / 1e9, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": rate * MIN_BYTES["vp"] / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "unit": "GB/s", "frac": rate * MIN_BYTES["vp"] / 1e9 / HBM_PEAK_GBS,
+                        "traffic": measured_traffic("min_vp_iteration", "sc200_min", None, None),
                         "kernel": "velocity-projection iteration (field, force, update)",
                         "bytes_per_spin_iteration": MIN_BYTES["vp"]},
            "table": table, "cpu_baseline": None}
