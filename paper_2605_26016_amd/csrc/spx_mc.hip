@@ -849,10 +849,12 @@ spx_status spx_mc_sweep(spx_ham *h, double *S, const spx_mc_params *p, unsigned 
                 const int64_t *co = m->d_coff;
                 // neighbour-loop unroll depths as timed on sc 200^3 with 1-5
                 // shells: heat-bath 2 throughout (a third faster than 4 with
-                // 2-5 shells), Metropolis 2 for one shell and 4 beyond
+                // 2-5 shells; with exchange + DMI tensors 342 against 365 us
+                // per sweep at one shell), Metropolis 2 for one scalar shell
+                // and 4 otherwise
                 if (p->method == 0) {
                     if (iso) k_mc_colour_cm<true, 0, 2><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
-                    else k_mc_colour_cm<false, 0, 4><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
+                    else k_mc_colour_cm<false, 0, 2><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
                 } else {
                     if (iso && short_list) k_mc_colour_cm<true, 1, 2><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
                     else if (iso) k_mc_colour_cm<true, 1, 4><<<grid, kMcB, 0, st>>>(P, v.tab, v.grid, v.onsite, col, c, beta, p->seed, sweep, acc, co, cd);
